@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark: simulated B-mode frames/s at 256 batched environments.
+
+Workload: 256 environments over 8 seeded label volumes of uneven size
+(160^3 ... 320x256x384 uint8), per-env images of 64..256 scanlines x
+128..512 depth samples at 0.5 mm, random probe poses on a spine phantom,
+stepped as one HIP-graph replay of the persistent kernel per step.  Inputs
+(volumes, poses) are resident in device memory before timing starts.
+
+Prints one JSON line (see the keys below).  Only one GPU is used; --gpus
+above 1 is refused.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz non-packed 32-bit VALU lane-ops
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def psf_radius(size: int, frac: float = 0.01) -> int:
+    return max(1, math.ceil(3.0 * frac * size))
+
+
+def ops_per_pixel(W: int, H: int) -> int:
+    """Algorithmic 32-bit VALU lane-op count of one pixel (quarter-rate ops
+    -- 32-bit integer multiplies and transcendentals -- weighted 4)."""
+    sample = 20          # Q16 position, rounding, bounds, voxel index, label gather
+    interface = 4        # boundary indicator and reflection/transmission select
+    scans = 18           # 6-step wave scans: FP32 product, FP64 sum
+    energy = 10          # exp and products
+    philox = 10 * 20     # 10 rounds: two 32x32->64 products (4 quarter-rate ops) + xors
+    scatter = 22         # Box-Muller (log, sqrt, cos) + gate + amplitude
+    psf = 2 * ((2 * psf_radius(H) + 1) + (2 * psf_radius(W) + 1))   # FMAs, two fields
+    display = 18         # compose, log10, scale, clamp
+    return sample + interface + scans + energy + philox + scatter + psf + display
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--profile-launches", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the environments shard "
+              "across GPUs without communication, see the design notes", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2507_01152_amd import sonosim as sg
+    from paper_2507_01152_amd.session import Session
+
+    wl = synth.batched_workload(seed=0)
+    n = wl.n_envs
+    offs, total = wl.out_offsets()
+    sess = Session(0)
+    vids = sess.load(wl)
+    plan = sg.sg_batch_plan_create(sess.ctx, vids, wl.probes, offs)
+    sg.sg_batch_set_poses(sess.ctx, plan, wl.poses)
+    out = torch.empty(total, dtype=torch.float32, device=sess.device)
+    if not args.no_tune:
+        sg.sg_autotune(sess.ctx, plan, os.environ.get("SG_TUNE_CACHE", "/tmp/sonosim_tune.jsonl"))
+    spw, tx, ty = sg.sg_batch_config(sess.ctx, plan)
+
+    for _ in range(args.warmup):
+        sg.sg_batch_step(sess.ctx, plan, out)
+    torch.cuda.synchronize()
+    assert sg.sg_batch_status(sess.ctx, plan) == 0
+
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for _ in range(args.steps):
+        sg.sg_batch_step(sess.ctx, plan, out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    ms_per_step = ms / args.steps
+    fps = n * args.steps / (ms / 1e3)
+    assert sg.sg_batch_status(sess.ctx, plan) == 0
+
+    # the persistent kernel alone, timed with events on its own stream
+    kms = [sg.sg_batch_step_profiled(sess.ctx, plan, out) for _ in range(args.profile_launches)]
+    kernel_ms = float(np.mean(kms))
+    pixels = sum(p.W * p.H for p in wl.probes)
+    ops = sum(ops_per_pixel(p.W, p.H) * p.W * p.H for p in wl.probes)
+    achieved_tops = ops / (kernel_ms / 1e3) / 1e12
+    alg_bytes = 5 * pixels   # 1 B label gather + 4 B FP32 frame per pixel
+    achieved_gbs = alg_bytes / (kernel_ms / 1e3) / 1e9
+
+    res = {
+        "metric": "simulated B-mode frames/sec at 256 envs (physics)",
+        "value": round(fps, 1),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched physics, 256 envs over 8 uneven label volumes 160^3..320x256x384, "
+                        "W 64-256 x H 128-512 at 0.5 mm, one persistent kernel per step in a HIP graph",
+            "n_envs": n,
+            "pixels_per_step": pixels,
+            "launch_shape": {"scanlines_per_item": spw, "tile_x": tx, "tile_y": ty},
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_persistent (ray + PSF passes)",
+            "achieved": round(achieved_tops, 3),
+            "peak": round(PEAK_VALU_TOPS, 2),
+            "unit": "Top/s",
+            "frac": round(achieved_tops / PEAK_VALU_TOPS, 4),
+            "ops_per_launch": ops,
+            "kernel_ms": round(kernel_ms, 4),
+            "traffic": None,
+            "hbm_view": {"algorithmic_bytes": alg_bytes, "achieved_GBps": round(achieved_gbs, 1),
+                         "frac_of_8TBps": round(achieved_gbs / PEAK_HBM_GBS, 4)},
+        },
+        "wall_s_timed": round(wall, 3),
+    }
+
+    if not args.no_cpu:
+        import oracle
+        t = time.perf_counter()
+        frames, used = oracle.simulate_batch(wl, n_threads=0)
+        dt = time.perf_counter() - t
+        res["cpu_baseline"] = {
+            "value": round(n / dt, 2),
+            "unit": "frames/s",
+            "cores": used,
+            "kind": "oracle",
+            "sample": f"one full step of the same workload ({n} envs, {pixels} px), FP64, "
+                      f"OpenMP over envs, {dt:.1f} s wall",
+        }
+        res["gpu_vs_cpu"] = round(fps / res["cpu_baseline"]["value"], 1)
+    sess.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

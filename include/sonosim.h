@@ -1,0 +1,220 @@
+/*
+ * sonosim.h -- C ABI of the MI355X (gfx950) batched ultrasound simulator.
+ *
+ * The problem follows SonoGym (arXiv 2507.01152), Sec. 4 "Ultrasound
+ * simulation" and App. B.2: a 3D label map (optionally with a CT volume) and a
+ * probe pose go in, a B-mode frame comes out, batched across parallel
+ * environments.  The model-based image is I = R + B with
+ *   R = PSF (x) (G * |E * cos(theta) * r|)      reflection at label boundaries,
+ *   B = E * (PSF (x) T)                          backscatter of the scattering
+ *                                                pattern T (per-voxel noise),
+ *   E = E0 * prod(t) * exp(-f * integral alpha)  remaining energy,
+ * followed by log compression to a display frame Y in [0, 1].
+ *
+ * Conventions (all entry points):
+ *  - Every call returns an sg_status; SG_OK is 0, errors are negative and a
+ *    human-readable message is available from sg_last_error() (thread-local,
+ *    valid until the next failing call on the same thread).  No C++
+ *    exception crosses this boundary.
+ *  - "device" pointers are HIP device memory of the context's device; "host"
+ *    pointers are ordinary CPU memory.  The caller owns every buffer it passes
+ *    in (volumes, outputs, offsets) and must keep device buffers alive until
+ *    the work that uses them has completed on the context's stream.  The
+ *    library owns only its workspaces, plans, graphs and plan pose buffers.
+ *  - Work is enqueued asynchronously on the context's stream unless stated.
+ *  - Contexts are not thread-safe; use one context per thread or stream.
+ *  - Image layout: a frame is [H][W] row-major FP32 (row = depth sample y,
+ *    column = scanline x); several frames are packed into one buffer at
+ *    caller-given offsets (in elements).
+ */
+#ifndef SONOSIM_H
+#define SONOSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sg_ctx sg_ctx;
+typedef int32_t sg_status;
+
+#define SG_OK 0
+#define SG_EINVAL (-1)  /* bad argument: size, id, NULL, NaN pose, label >= table size */
+#define SG_ENOMEM (-2)  /* device or host allocation failed */
+#define SG_EHIP (-3)    /* a HIP runtime call failed */
+#define SG_ESTATE (-4)  /* call not valid in the current state (e.g. no tissue table) */
+#define SG_ERANGE (-5)  /* a pose puts the image plane outside the fixed-point range */
+
+/* Limits. */
+#define SG_MAX_IMAGE 1024   /* W and H must lie in [1, SG_MAX_IMAGE] */
+#define SG_MAX_LABELS 256
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* sg_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int32_t sg_version(void);
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream` (a
+ * hipStream_t owned by the caller; NULL = the device's null stream).
+ * *out receives the context.  Errors: SG_EINVAL, SG_EHIP, SG_ENOMEM. */
+sg_status sg_create(sg_ctx** out, int32_t device, void* hip_stream);
+
+/* Destroy a context and free its workspaces, plans and graphs.  Waits for
+ * the context's stream.  NULL is accepted. */
+sg_status sg_destroy(sg_ctx* ctx);
+
+/* Change the stream later work is enqueued on. */
+sg_status sg_set_stream(sg_ctx* ctx, void* hip_stream);
+
+/* Block until all work enqueued by the context has completed. */
+sg_status sg_synchronize(sg_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Volumes (Sec. 4 "Assets": CT volumes and label maps of patients).
+ */
+typedef struct {
+    int32_t nx, ny, nz;        /* voxels; nx*ny*nz < 2^31 */
+    double spacing_mm[3];      /* voxel spacing along x, y, z (> 0) */
+    const uint8_t* labels;     /* device, [nz][ny][nx] (x fastest), caller-owned */
+    const int16_t* ct_hu;      /* device, same layout, HU; or NULL (then Z comes
+                                  from the tissue table) */
+    uint64_t noise_seed;       /* key of the fixed per-voxel noise fields
+                                  N0, N1 (App. B.2: sampled once over 3D space) */
+} sg_volume_desc;
+
+/* Register a volume; *vol_id receives its id.  Scans the label map once on
+ * the device to record its largest label (synchronises the stream).
+ * The volume memory is referenced, not copied.  Errors: SG_EINVAL. */
+sg_status sg_volume_register(sg_ctx* ctx, const sg_volume_desc* desc, int32_t* vol_id);
+
+/* Forget a registered volume (its memory stays the caller's). */
+sg_status sg_volume_release(sg_ctx* ctx, int32_t vol_id);
+
+/* ------------------------------------------------------------------------
+ * Tissue table (App. B.2: per-tissue impedance Z, attenuation alpha and the
+ * scattering parameters mu0, sigma0, mu1).  Row l describes label l.
+ *   Z_mrayl          >= 0; 0 = pressure-release, +INF = rigid (both reflect
+ *                    totally).  Ignored for volumes with a CT volume, where Z is
+ *                    proportional to max(HU + 1000, 0).
+ *   alpha_np_cm_mhz  attenuation, Np / cm / MHz (>= 0)
+ *   mu0, sigma0      scatterer amplitude: T~ = N0 * sigma0 + mu0
+ *   mu1              scatterer density: T = T~ where N1 <= mu1, else 0
+ *                    (-INF: never, +INF: always)
+ * `rows` is a host array of n_labels rows, copied.  Errors: SG_EINVAL.
+ */
+typedef struct {
+    float Z_mrayl;
+    float alpha_np_cm_mhz;
+    float mu0;
+    float sigma0;
+    float mu1;
+} sg_tissue;
+
+sg_status sg_tissue_table_set(sg_ctx* ctx, const sg_tissue* rows, int32_t n_labels);
+
+/* ------------------------------------------------------------------------
+ * Probe / image geometry of one environment (linear probe; App. C.1 uses
+ * 0.5 mm pixels).  Pixel (x, y) lies at probe-frame point
+ * (a + x*dx_mm, 0, y*dy_mm) with a = -0.5*(W-1)*dx_mm: x runs along the
+ * probe's lateral axis, y along the beam (probe z).
+ *   W, H      scanlines and depth samples, each in [1, SG_MAX_IMAGE]
+ *   f_mhz     centre frequency (attenuation scales with f)
+ *   E0        initial energy (> 0)
+ *   psf_frac  PSF standard deviation as a fraction of the image size per
+ *             axis (App. B.2: about 1 %), > 0
+ *   dr_db     display dynamic range in dB (> 0)
+ */
+typedef struct {
+    int32_t W, H;
+    double dx_mm, dy_mm, f_mhz, E0, psf_frac, dr_db;
+} sg_probe;
+
+/* Optional per-pixel outputs for checking (device pointers, each may be NULL;
+ * packed like the frames at the same offsets, philox with 4 words per pixel
+ * at 4*offset).  Writing them costs extra memory traffic. */
+typedef struct {
+    uint8_t* label;       /* nearest label (0 outside the volume) */
+    int32_t* voxel;       /* linear voxel index (z*ny + y)*nx + x, -1 outside */
+    uint32_t* philox;     /* Philox4x32-10 words of that voxel (0 outside) */
+    float* energy;        /* remaining energy E */
+    float* intensity;     /* I before log compression */
+} sg_debug_planes;
+
+/* Simulate n_envs environments (Sec. 4 "Ultrasound simulation" pipeline:
+ * pose -> image plane -> label/CT slice -> model-based image -> display).
+ *   vol_ids      host, n_envs registered volume ids
+ *   probes       host, n_envs probe descriptions
+ *   poses        host, n_envs * 12 doubles: row-major 3x4 [R | t] mapping
+ *                probe-frame mm to volume mm (volume origin at the centre of
+ *                voxel (0,0,0), axes along the array indices)
+ *   out          device, FP32 display frames Y in [0, 1]
+ *   out_offsets  host, n_envs element offsets of each [H][W] frame in out
+ *   debug        host struct of optional device planes, or NULL
+ * Errors: SG_EINVAL (ids, sizes, NaN pose, a volume label >= table size),
+ * SG_ERANGE (plane outside +-2^30 / 2^16 voxels), SG_ESTATE (no table),
+ * SG_EHIP, SG_ENOMEM.
+ */
+sg_status sg_simulate(sg_ctx* ctx, int32_t n_envs, const int32_t* vol_ids,
+                      const sg_probe* probes, const double* poses, float* out,
+                      const int64_t* out_offsets, const sg_debug_planes* debug);
+
+/* ------------------------------------------------------------------------
+ * Batched persistent path (environments stepped in batch mode, Sec. 4):
+ * a plan fixes the environments' volumes, probes and output offsets; each
+ * step replays one captured HIP graph whose persistent kernel pulls
+ * (environment, tile) work items longest-first from a device queue.  Poses
+ * live in a library-owned device buffer that the caller updates between
+ * steps (for instance from its own kernels on the same stream).
+ */
+
+/* Create a plan.  Host arrays are copied.  *plan_id receives the id. */
+sg_status sg_batch_plan_create(sg_ctx* ctx, int32_t n_envs, const int32_t* vol_ids,
+                               const sg_probe* probes, const int64_t* out_offsets,
+                               int32_t* plan_id);
+
+/* Device pointer of the plan's pose buffer (n_envs * 12 doubles, layout as in
+ * sg_simulate), owned by the library, valid until the plan is destroyed. */
+sg_status sg_batch_poses(sg_ctx* ctx, int32_t plan_id, double** dev_poses);
+
+/* Copy n_envs * 12 host doubles into the plan's pose buffer (asynchronous
+ * on the context's stream; the host array may be reused on return). */
+sg_status sg_batch_set_poses(sg_ctx* ctx, int32_t plan_id, const double* host_poses);
+
+/* Enqueue one step: geometry from the device poses, then all environments'
+ * frames into `out` (device; same offsets as the plan).  The first call (and
+ * any call with a different `out` or after sg_autotune) captures the graph.
+ * A pose whose plane leaves the fixed-point range produces a zero frame for
+ * that environment and is reported by sg_batch_status. */
+sg_status sg_batch_step(sg_ctx* ctx, int32_t plan_id, float* out);
+
+/* Synchronise and report how many environments of the last step had a pose
+ * outside the fixed-point range (or non-finite): *n_bad (host). */
+sg_status sg_batch_status(sg_ctx* ctx, int32_t plan_id, int32_t* n_bad);
+
+/* Time the candidate launch shapes for the plan on the device and keep the
+ * fastest; results are cached by (device, shape bucket) in the JSON file at
+ * `cache_path` (NULL: no file).  Synchronises; the poses currently in the
+ * plan's buffer are used.  Output-equivalent: every candidate produces
+ * bit-identical frames. */
+sg_status sg_autotune(sg_ctx* ctx, int32_t plan_id, const char* cache_path);
+
+/* Run one step without the graph, timing the persistent kernel alone with
+ * HIP events on the context's stream; synchronises.  *ms (host) receives
+ * the kernel's duration.  For measurement only; frames are identical to
+ * sg_batch_step's. */
+sg_status sg_batch_step_profiled(sg_ctx* ctx, int32_t plan_id, float* out, float* ms);
+
+/* Launch shape currently used by a plan (for reports): scanlines per ray
+ * work item, and the PSF tile (tile_x scanlines by tile_y rows). */
+sg_status sg_batch_config(sg_ctx* ctx, int32_t plan_id, int32_t* scanlines_per_item,
+                          int32_t* tile_x, int32_t* tile_y);
+
+sg_status sg_batch_plan_destroy(sg_ctx* ctx, int32_t plan_id);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SONOSIM_H */

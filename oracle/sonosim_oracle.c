@@ -18,8 +18,8 @@
  *      position is then the exact integer P0 + x*DX + y*DY.
  *   O2 nearest label: i = floor((Q + 2^15) / 2^16); outside the grid -> air.
  *   O3 impedance: per-label table Z, or with a CT volume Z = max(HU+1000, 0)
- *      from trilinear HU (outside corners -1000 HU).  Z proportional to CT
- *      intensity, App. B.2.
+ *      from trilinear HU (successive linear interpolation along x, y, z;
+ *      outside corners -1000 HU).  Z proportional to CT intensity, App. B.2.
  *   O4 interface terms of the reflection equation R (App. B.2): boundary
  *      indicator G = [label(x,y) != label(x,y+1)], amplitude reflection
  *      r = (Z2-Z1)/(Z2+Z1) and intensity transmission t = 1 - r^2 (total
@@ -260,20 +260,24 @@ int or_simulate_env(const or_volume* v, const or_tissue* table, int32_t n_labels
                 return -1;
             }
             if (v->ct) {
+                /* trilinear as successive linear interpolations along x, y, z */
                 int64_t b[3];
                 double w[3];
                 for (int c = 0; c < 3; ++c) {
                     b[c] = floordiv(q[c], 65536);
                     w[c] = (double)(q[c] - 65536 * b[c]) / 65536.0;
                 }
-                double hu = 0.0;
-                for (int dz = 0; dz < 2; ++dz)
-                    for (int dy = 0; dy < 2; ++dy)
-                        for (int dx = 0; dx < 2; ++dx) {
-                            double wt = (dz ? w[2] : 1.0 - w[2]) * (dy ? w[1] : 1.0 - w[1]) *
-                                        (dx ? w[0] : 1.0 - w[0]);
-                            hu += wt * ct_at(v, b[0] + dx, b[1] + dy, b[2] + dz);
-                        }
+                double cy[2];
+                for (int dz = 0; dz < 2; ++dz) {
+                    double cx[2];
+                    for (int dy = 0; dy < 2; ++dy) {
+                        double h0 = ct_at(v, b[0], b[1] + dy, b[2] + dz);
+                        double h1 = ct_at(v, b[0] + 1, b[1] + dy, b[2] + dz);
+                        cx[dy] = h0 + w[0] * (h1 - h0);
+                    }
+                    cy[dz] = cx[0] + w[1] * (cx[1] - cx[0]);
+                }
+                double hu = cy[0] + w[2] * (cy[1] - cy[0]);
                 double z = hu + 1000.0;
                 Z[k] = z > 0.0 ? z : 0.0;
             } else {

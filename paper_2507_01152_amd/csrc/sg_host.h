@@ -1,0 +1,103 @@
+// Host-side state of the library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "sg_internal.h"
+#include "sonosim.h"
+
+namespace sg {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    hipError_t ensure(size_t bytes);   // grow-only; synchronises the device before a regrow
+};
+
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;           // recorded after the last upload from this buffer
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+    ~PinnedBuf();
+    hipError_t acquire(size_t bytes);  // waits for the previous upload, then grows
+};
+
+struct HostVolume {
+    VolDev dev{};
+    int32_t max_label = 0;
+    bool live = false;
+};
+
+struct LaunchShape {
+    int spw = 1;      // scanlines per wave in a ray item
+    int tx = 32, ty = 32;
+};
+
+struct Plan {
+    int32_t n_envs = 0;
+    std::vector<int32_t> vol_ids;
+    std::vector<sg_probe> probes;
+    std::vector<int64_t> out_offsets;
+    std::vector<EnvDev> envs;          // static parts
+    std::vector<float> pool;
+    std::vector<int> order;            // envs, longest scanlines first
+    int64_t n_pixels = 0;
+    int max_rax = 0, max_rlat = 0;
+    LaunchShape shape;
+    int grid = 0;
+    DevBuf d_envs, d_pool, d_rays, d_tiles, d_poses, d_queue, fields;
+    int32_t n_rays = 0, n_tiles = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float* graph_out = nullptr;        // output pointer the graph was captured with
+    const void* cap_vols = nullptr;    // volume table the graph was captured with
+    int32_t cap_labels = 0;            // tissue table size the graph was captured with
+    ~Plan();
+};
+
+}  // namespace sg
+
+struct sg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 256;
+    std::string arch;
+    std::vector<sg::HostVolume> vols;
+    bool vols_dirty = true;
+    sg::DevBuf d_vols;
+    sg::DevBuf table;
+    int32_t n_labels = 0;
+    sg::DevBuf scan, params, fields;
+    sg::PinnedBuf staging;
+    std::map<int32_t, std::unique_ptr<sg::Plan>> plans;
+    int32_t next_plan = 1;
+    void* surrogates = nullptr;        // owned by the surrogate module
+};
+
+namespace sg {
+
+sg_status fail(sg_status code, const char* fmt, ...);
+sg_status hip_fail(hipError_t e, const char* what);
+int psf_taps(double sigma, std::vector<float>& pool, int32_t* offset);
+sg_status check_probe(const sg_probe& p, int idx);
+sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int64_t out_off, int64_t scr_off,
+                          std::vector<float>& pool, EnvDev& e);
+void build_items(const std::vector<EnvDev>& envs, const std::vector<int>& order, int spw, int tx, int ty,
+                 std::vector<ItemRay>& rays, std::vector<ItemPsf>& tiles);
+sg_status sync_volumes(sg_ctx* c);
+sg_status check_envs(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_probe* probes);
+void surrogate_release_all(sg_ctx* c);
+
+}  // namespace sg

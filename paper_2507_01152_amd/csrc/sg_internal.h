@@ -1,0 +1,151 @@
+// Internal structures shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+constexpr int kMaxPsfRadius = 32;   // axial / lateral PSF radius limit (pixels)
+constexpr int kWave = 64;
+constexpr int kRayWaves = 4;        // waves per ray work group (one scanline each)
+#define SG_MAX_LABELS_DEV 256
+
+struct VolDev {
+    const uint8_t* labels;
+    const int16_t* ct;   // may be null
+    double sx, sy, sz;   // voxel spacing, mm
+    int32_t nx, ny, nz;
+    uint32_t key0, key1; // noise-field key (low / high word of the seed)
+    int32_t pad;
+};
+
+struct TissueDev {
+    float Z;
+    float alpha;
+    float mu0;
+    float sigma0;
+    unsigned long long thr;   // scatter gate: word2 < thr (thr may be 2^32)
+};
+
+// Per-environment launch parameters.  The geometry part (P0, DX, DY, valid)
+// is filled either on the host (single call) or by the device geometry
+// kernel (batched plans).
+struct EnvDev {
+    int32_t P0[3], DX[3], DY[3];   // Q16 plane origin and per-pixel steps
+    int32_t valid;                 // 0: pose rejected, frame is zero
+    int32_t W, H;
+    int32_t vol;
+    int32_t rax, rlat;             // PSF radii
+    int32_t kax, klat;             // offsets of the PSF taps in the coefficient pool
+    float E0;
+    float dx, dy;                  // pixel pitch, mm (incidence angle)
+    float disp;                    // 20 / DR
+    float inv_E0;
+    double coef;                   // f * dy_cm
+    double dx64, dy64, f64;        // for device-side geometry
+    double psf64;
+    int64_t out_off;               // frame offset in the output (elements)
+    int64_t scr_off;               // offset of this env in the field scratch
+};
+
+struct ItemRay { int32_t env, x0; };          // x0: first scanline of the group
+struct ItemPsf { int32_t env, tile; };        // tile = ty << 16 | tx
+
+struct DebugDev {
+    uint8_t* label;
+    int32_t* voxel;
+    uint32_t* philox;
+    float* energy;
+    float* intensity;
+};
+
+struct PhysArgs {
+    const EnvDev* envs;
+    const VolDev* vols;
+    const TissueDev* table;
+    int32_t n_labels;
+    const float* coefs;       // PSF taps pool
+    const ItemRay* ray_items;
+    int32_t n_ray;
+    const ItemPsf* psf_items;
+    int32_t n_psf;
+    float* fR;                // scratch fields, scanline-major [x][y] per env
+    float* fT;
+    float* fE;
+    float* out;
+    DebugDev dbg;
+    int32_t scanlines_per_wave;   // ray group = kRayWaves * scanlines_per_wave
+    int32_t max_rax, max_rlat;    // sizing of the PSF tile's LDS
+};
+
+// persistent-kernel queue state (device)
+struct QueueDev {
+    int32_t next;        // next work item
+    int32_t n_bad;       // envs with rejected poses
+    int32_t timeouts;    // dependency waits that gave up
+    int32_t pad;
+    int32_t done[1];     // [n_envs] finished scanlines per env (flexible)
+};
+
+// Plane geometry: the pose [R|t] (probe mm -> volume mm) places pixel (x, y)
+// at probe point (a + x*dx, 0, y*dy), a = -0.5*(W-1)*dx.  Origin and steps
+// are converted to Q16 voxel units one rounded operation at a time
+// (no contraction) and rounded half-to-even, so host and device agree
+// bit for bit.  Returns 1 if every corner of the plane lies within
+// +-2^30 (Q16), else 0 (outputs then unspecified).
+__host__ __device__ inline int plane_geometry(const double* pose, double sx, double sy, double sz,
+                                              int32_t W, int32_t H, double dx, double dy,
+                                              int32_t P0[3], int32_t DX[3], int32_t DY[3])
+{
+#pragma clang fp contract(off)
+    const double s[3] = {sx, sy, sz};
+    double a = -0.5 * (double)(W - 1);
+    a = a * dx;
+    long long p0[3], ddx[3], ddy[3];
+    for (int c = 0; c < 3; ++c) {
+        const double r0 = pose[4 * c + 0], r2 = pose[4 * c + 2], tc = pose[4 * c + 3];
+        double u = r0 * a;
+        u = tc + u;
+        u = u / s[c];
+        u = u * 65536.0;
+        double w = r0 * dx;
+        w = w / s[c];
+        w = w * 65536.0;
+        double z = r2 * dy;
+        z = z / s[c];
+        z = z * 65536.0;
+        // non-finite or huge values fail the range test below
+        if (!(u > -1e15 && u < 1e15) || !(w > -1e15 && w < 1e15) || !(z > -1e15 && z < 1e15)) return 0;
+        p0[c] = (long long)__builtin_rint(u);
+        ddx[c] = (long long)__builtin_rint(w);
+        ddy[c] = (long long)__builtin_rint(z);
+    }
+    const long long lim = 1ll << 30;
+    for (int c = 0; c < 3; ++c) {
+        for (int k = 0; k < 4; ++k) {
+            const long long qx = (k & 1) ? (long long)(W - 1) : 0;
+            const long long qy = (k & 2) ? (long long)(H - 1) : 0;
+            const long long q = p0[c] + qx * ddx[c] + qy * ddy[c];
+            if (q > lim || q < -lim) return 0;
+        }
+        P0[c] = (int32_t)p0[c];
+        DX[c] = (int32_t)ddx[c];
+        DY[c] = (int32_t)ddy[c];
+    }
+    return 1;
+}
+
+// launchers (physics.hip)
+hipError_t launch_ray(const PhysArgs& a, hipStream_t s);
+hipError_t launch_psf(const PhysArgs& a, int tile_x, int tile_y, hipStream_t s);
+hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n_envs,
+                           QueueDev* q, hipStream_t s);
+hipError_t launch_queue_reset(QueueDev* q, int32_t n_envs, hipStream_t s);
+hipError_t launch_persistent(const PhysArgs& a, QueueDev* q, int tile_x, int tile_y, int grid,
+                             hipStream_t s);
+int persistent_blocks_per_cu(int tile_x, int tile_y, int max_rax, int max_rlat);
+size_t psf_lds_bytes(int tile_x, int tile_y, int max_rax, int max_rlat);
+hipError_t launch_max_label(const uint8_t* labels, int64_t n, int32_t* d_out, hipStream_t s);
+
+}  // namespace sg

@@ -1,0 +1,401 @@
+// Batched persistent path: plans, HIP graph capture/replay and the
+// launch-shape autotuner (C ABI in include/sonosim.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "sg_host.h"
+
+namespace sg {
+
+Plan::~Plan()
+{
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+}
+
+namespace {
+
+// Candidate launch shapes: every one yields bit-identical frames (the
+// per-pixel arithmetic and summation order do not depend on the tiling).
+const LaunchShape kShapes[] = {
+    {1, 32, 32}, {2, 32, 32}, {1, 64, 16}, {2, 64, 16}, {1, 16, 64}, {1, 64, 32}, {2, 64, 32},
+};
+
+Plan* find_plan(sg_ctx* c, int32_t id)
+{
+    auto it = c->plans.find(id);
+    return it == c->plans.end() ? nullptr : it->second.get();
+}
+
+void drop_graph(Plan* p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->graph_out = nullptr;
+}
+
+sg_status apply_shape(sg_ctx* c, Plan* p, const LaunchShape& s)
+{
+    std::vector<ItemRay> rays;
+    std::vector<ItemPsf> tiles;
+    build_items(p->envs, p->order, s.spw, s.tx, s.ty, rays, tiles);
+    const int per_cu = persistent_blocks_per_cu(s.tx, s.ty, p->max_rax, p->max_rlat);
+    if (per_cu < 1) return fail(SG_EINVAL, "launch shape %dx%d does not fit a compute unit", s.tx, s.ty);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = p->d_rays.ensure(sizeof(ItemRay) * std::max<size_t>(rays.size(), 1));
+    if (e == hipSuccess) e = p->d_tiles.ensure(sizeof(ItemPsf) * std::max<size_t>(tiles.size(), 1));
+    if (e == hipSuccess && !rays.empty())
+        e = hipMemcpy(p->d_rays.p, rays.data(), sizeof(ItemRay) * rays.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpy(p->d_tiles.p, tiles.data(), sizeof(ItemPsf) * tiles.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "work list upload");
+    p->n_rays = (int32_t)rays.size();
+    p->n_tiles = (int32_t)tiles.size();
+    p->shape = s;
+    p->grid = per_cu * c->n_cu;
+    drop_graph(p);
+    return SG_OK;
+}
+
+PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
+{
+    PhysArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.envs = (const EnvDev*)p->d_envs.p;
+    a.vols = (const VolDev*)c->d_vols.p;
+    a.table = (const TissueDev*)c->table.p;
+    a.n_labels = c->n_labels;
+    a.coefs = (const float*)p->d_pool.p;
+    a.ray_items = (const ItemRay*)p->d_rays.p;
+    a.n_ray = p->n_rays;
+    a.psf_items = (const ItemPsf*)p->d_tiles.p;
+    a.n_psf = p->n_tiles;
+    a.fR = (float*)p->fields.p;
+    a.fT = a.fR + p->n_pixels;
+    a.fE = a.fT + p->n_pixels;
+    a.out = out;
+    a.scanlines_per_wave = p->shape.spw;
+    a.max_rax = p->max_rax;
+    a.max_rlat = p->max_rlat;
+    return a;
+}
+
+// enqueue one step's kernels (reset, geometry, persistent) on stream s
+hipError_t enqueue_step(sg_ctx* c, Plan* p, float* out, hipStream_t s)
+{
+    QueueDev* q = (QueueDev*)p->d_queue.p;
+    hipError_t e = launch_queue_reset(q, p->n_envs, s);
+    if (e == hipSuccess)
+        e = launch_geometry((EnvDev*)p->d_envs.p, (const VolDev*)c->d_vols.p, (const double*)p->d_poses.p,
+                            p->n_envs, q, s);
+    if (e == hipSuccess) e = launch_persistent(plan_args(c, p, out), q, p->shape.tx, p->shape.ty, p->grid, s);
+    return e;
+}
+
+struct CaptureKey {
+    const void* vols;
+    int32_t n_labels;
+};
+
+sg_status capture(sg_ctx* c, Plan* p, float* out)
+{
+    drop_graph(p);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = enqueue_step(c, p, out, cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) {
+            p->graph = g;
+            e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        drop_graph(p);
+        return hip_fail(e, "graph capture");
+    }
+    p->graph_out = out;
+    p->cap_vols = c->d_vols.p;
+    p->cap_labels = c->n_labels;
+    return SG_OK;
+}
+
+std::string tune_key(sg_ctx* c, Plan* p)
+{
+    int maxW = 0, maxH = 0;
+    for (auto& pr : p->probes) {
+        maxW = std::max(maxW, pr.W);
+        maxH = std::max(maxH, pr.H);
+    }
+    std::ostringstream k;
+    k << c->arch << "|n" << p->n_envs << "|px" << p->n_pixels << "|W" << maxW << "|H" << maxH << "|ra"
+      << p->max_rax << "|rl" << p->max_rlat;
+    return k.str();
+}
+
+bool cache_lookup(const char* path, const std::string& key, LaunchShape* s)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const std::string tag = "\"key\": \"" + key + "\"";
+        if (line.find(tag) == std::string::npos) continue;
+        int spw = 0, tx = 0, ty = 0;
+        const char* q = std::strstr(line.c_str(), "\"spw\":");
+        const char* x = std::strstr(line.c_str(), "\"tx\":");
+        const char* y = std::strstr(line.c_str(), "\"ty\":");
+        if (q && x && y && std::sscanf(q, "\"spw\": %d", &spw) == 1 && std::sscanf(x, "\"tx\": %d", &tx) == 1 &&
+            std::sscanf(y, "\"ty\": %d", &ty) == 1) {
+            for (const LaunchShape& k : kShapes)
+                if (k.spw == spw && k.tx == tx && k.ty == ty) {
+                    *s = k;
+                    found = true;   // keep the last matching line
+                }
+        }
+    }
+    return found;
+}
+
+}  // namespace
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" sg_status sg_batch_plan_create(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
+                                          const int64_t* out_offsets, int32_t* plan_id)
+{
+    if (!c || !vol_ids || !probes || !out_offsets || !plan_id)
+        return fail(SG_EINVAL, "sg_batch_plan_create: NULL argument");
+    if (n < 1) return fail(SG_EINVAL, "sg_batch_plan_create: n_envs must be >= 1");
+    (void)hipSetDevice(c->device);
+    sg_status s = check_envs(c, n, vol_ids, probes);
+    if (s != SG_OK) return s;
+    std::unique_ptr<Plan> p(new Plan());
+    p->n_envs = n;
+    p->vol_ids.assign(vol_ids, vol_ids + n);
+    p->probes.assign(probes, probes + n);
+    p->out_offsets.assign(out_offsets, out_offsets + n);
+    p->envs.resize(n);
+    for (int i = 0; i < n; ++i) {
+        if (out_offsets[i] < 0) return fail(SG_EINVAL, "env %d: negative output offset", i);
+        s = fill_env_static(probes[i], vol_ids[i], i, out_offsets[i], p->n_pixels, p->pool, p->envs[i]);
+        if (s != SG_OK) return s;
+        p->n_pixels += (int64_t)probes[i].W * probes[i].H;
+        p->max_rax = std::max(p->max_rax, p->envs[i].rax);
+        p->max_rlat = std::max(p->max_rlat, p->envs[i].rlat);
+    }
+    // longest scanlines first (ray items cost ~H), then wider frames
+    p->order.resize(n);
+    for (int i = 0; i < n; ++i) p->order[i] = i;
+    std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) {
+        if (p->envs[a].H != p->envs[b].H) return p->envs[a].H > p->envs[b].H;
+        return p->envs[a].W > p->envs[b].W;
+    });
+    hipError_t e = p->d_envs.ensure(sizeof(EnvDev) * n);
+    if (e == hipSuccess) e = p->d_pool.ensure(sizeof(float) * p->pool.size());
+    if (e == hipSuccess) e = p->d_poses.ensure(sizeof(double) * 12 * n);
+    if (e == hipSuccess) e = p->d_queue.ensure(sizeof(QueueDev) + sizeof(int32_t) * n);
+    if (e == hipSuccess) e = p->fields.ensure(sizeof(float) * 3 * (size_t)p->n_pixels);
+    if (e != hipSuccess) return hip_fail(e, "plan allocation");
+    e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_pool.p, p->pool.data(), sizeof(float) * p->pool.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->d_poses.p, 0, sizeof(double) * 12 * n);
+    if (e != hipSuccess) return hip_fail(e, "plan upload");
+    s = apply_shape(c, p.get(), kShapes[0]);
+    if (s != SG_OK) return s;
+    const int32_t id = c->next_plan++;
+    c->plans[id] = std::move(p);
+    *plan_id = id;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_batch_poses(sg_ctx* c, int32_t id, double** dev_poses)
+{
+    Plan* p = c ? find_plan(c, id) : nullptr;
+    if (!p || !dev_poses) return fail(SG_EINVAL, "sg_batch_poses: bad plan id or NULL");
+    *dev_poses = (double*)p->d_poses.p;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_batch_set_poses(sg_ctx* c, int32_t id, const double* host_poses)
+{
+    Plan* p = c ? find_plan(c, id) : nullptr;
+    if (!p || !host_poses) return fail(SG_EINVAL, "sg_batch_set_poses: bad plan id or NULL");
+    (void)hipSetDevice(c->device);
+    const size_t bytes = sizeof(double) * 12 * (size_t)p->n_envs;
+    hipError_t e = c->staging.acquire(bytes);
+    if (e != hipSuccess) return hip_fail(e, "pinned staging");
+    std::memcpy(c->staging.p, host_poses, bytes);
+    e = hipMemcpyAsync(p->d_poses.p, c->staging.p, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->staging.ev, c->stream);
+    return e == hipSuccess ? SG_OK : hip_fail(e, "pose upload");
+}
+
+static sg_status step_checks(sg_ctx* c, Plan* p)
+{
+    if (c->n_labels < 1) return fail(SG_ESTATE, "no tissue table set");
+    for (int i = 0; i < p->n_envs; ++i) {
+        const HostVolume& v = c->vols[p->vol_ids[i]];
+        if (!v.live) return fail(SG_ESTATE, "env %d: volume %d was released", i, p->vol_ids[i]);
+        if (v.max_label >= c->n_labels) return fail(SG_EINVAL, "env %d: label outside the table", i);
+    }
+    return sync_volumes(c);
+}
+
+extern "C" sg_status sg_batch_step_profiled(sg_ctx* c, int32_t id, float* out, float* ms)
+{
+    Plan* p = c ? find_plan(c, id) : nullptr;
+    if (!p || !out || !ms) return fail(SG_EINVAL, "sg_batch_step_profiled: bad plan id or NULL");
+    (void)hipSetDevice(c->device);
+    sg_status s = step_checks(c, p);
+    if (s != SG_OK) return s;
+    QueueDev* q = (QueueDev*)p->d_queue.p;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    if (e == hipSuccess) e = launch_queue_reset(q, p->n_envs, c->stream);
+    if (e == hipSuccess)
+        e = launch_geometry((EnvDev*)p->d_envs.p, (const VolDev*)c->d_vols.p, (const double*)p->d_poses.p,
+                            p->n_envs, q, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
+    if (e == hipSuccess) e = launch_persistent(plan_args(c, p, out), q, p->shape.tx, p->shape.ty, p->grid, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, t0, t1);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    return e == hipSuccess ? SG_OK : hip_fail(e, "profiled step");
+}
+
+extern "C" sg_status sg_batch_step(sg_ctx* c, int32_t id, float* out)
+{
+    Plan* p = c ? find_plan(c, id) : nullptr;
+    if (!p || !out) return fail(SG_EINVAL, "sg_batch_step: bad plan id or NULL output");
+    (void)hipSetDevice(c->device);
+    sg_status s = step_checks(c, p);
+    if (s != SG_OK) return s;
+    if (!p->exec || p->graph_out != out || p->cap_vols != c->d_vols.p || p->cap_labels != c->n_labels) {
+        s = capture(c, p, out);
+        if (s != SG_OK) return s;
+    }
+    hipError_t e = hipGraphLaunch(p->exec, c->stream);
+    return e == hipSuccess ? SG_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+extern "C" sg_status sg_batch_status(sg_ctx* c, int32_t id, int32_t* n_bad)
+{
+    Plan* p = c ? find_plan(c, id) : nullptr;
+    if (!p || !n_bad) return fail(SG_EINVAL, "sg_batch_status: bad plan id or NULL");
+    (void)hipSetDevice(c->device);
+    QueueDev q;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(&q, p->d_queue.p, sizeof(QueueDev) - sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "status readback");
+    *n_bad = q.n_bad;
+    if (q.timeouts) return fail(SG_EHIP, "persistent kernel: %d dependency waits timed out", q.timeouts);
+    return SG_OK;
+}
+
+extern "C" sg_status sg_batch_config(sg_ctx* c, int32_t id, int32_t* spw, int32_t* tx, int32_t* ty)
+{
+    Plan* p = c ? find_plan(c, id) : nullptr;
+    if (!p || !spw || !tx || !ty) return fail(SG_EINVAL, "sg_batch_config: bad plan id or NULL");
+    *spw = p->shape.spw * kRayWaves;
+    *tx = p->shape.tx;
+    *ty = p->shape.ty;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_autotune(sg_ctx* c, int32_t id, const char* cache_path)
+{
+    Plan* p = c ? find_plan(c, id) : nullptr;
+    if (!p) return fail(SG_EINVAL, "sg_autotune: bad plan id");
+    (void)hipSetDevice(c->device);
+    if (c->n_labels < 1) return fail(SG_ESTATE, "no tissue table set");
+    sg_status s = sync_volumes(c);
+    if (s != SG_OK) return s;
+    const std::string key = tune_key(c, p);
+    LaunchShape cached;
+    if (cache_lookup(cache_path, key, &cached)) return apply_shape(c, p, cached);
+
+    DevBuf scratch_out;
+    hipError_t e = scratch_out.ensure(sizeof(float) * (size_t)p->n_pixels);
+    if (e != hipSuccess) return hip_fail(e, "autotune output");
+    // the plan's offsets may address a larger caller buffer: time into a
+    // private buffer laid out densely with the same sizes
+    std::vector<EnvDev> saved = p->envs;
+    int64_t off = 0;
+    for (int i = 0; i < p->n_envs; ++i) {
+        p->envs[i].out_off = off;
+        off += (int64_t)p->envs[i].W * p->envs[i].H;
+    }
+    e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * p->n_envs, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "autotune env upload");
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    LaunchShape best = p->shape;
+    float best_us = 1e30f;
+    for (const LaunchShape& shp : kShapes) {
+        if (apply_shape(c, p, shp) != SG_OK) continue;
+        if (capture(c, p, (float*)scratch_out.p) != SG_OK) continue;
+        for (int w = 0; w < 3; ++w) (void)hipGraphLaunch(p->exec, c->stream);
+        const int reps = 10;
+        (void)hipEventRecord(t0, c->stream);
+        for (int r = 0; r < reps; ++r) (void)hipGraphLaunch(p->exec, c->stream);
+        (void)hipEventRecord(t1, c->stream);
+        if (hipEventSynchronize(t1) != hipSuccess) continue;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        const float us = 1000.f * ms / reps;
+        if (us < best_us) {
+            best_us = us;
+            best = shp;
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    drop_graph(p);
+    p->envs = saved;
+    e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * p->n_envs, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "autotune env restore");
+    s = apply_shape(c, p, best);
+    if (s != SG_OK) return s;
+    if (cache_path && best_us < 1e29f) {
+        std::ofstream f(cache_path, std::ios::app);
+        if (f)
+            f << "{\"key\": \"" << key << "\", \"spw\": " << best.spw << ", \"tx\": " << best.tx
+              << ", \"ty\": " << best.ty << ", \"us\": " << best_us << "}\n";
+    }
+    return SG_OK;
+}
+
+extern "C" sg_status sg_batch_plan_destroy(sg_ctx* c, int32_t id)
+{
+    if (!c || !find_plan(c, id)) return fail(SG_EINVAL, "sg_batch_plan_destroy: bad plan id");
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    c->plans.erase(id);
+    return SG_OK;
+}

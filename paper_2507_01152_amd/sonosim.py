@@ -1,0 +1,250 @@
+"""Thin ctypes binding of libsonosim.so (C ABI: include/sonosim.h).
+
+Functions carry the C names and only marshal arguments: torch tensors give
+device pointers and the HIP stream, numpy/Python sequences give host arrays.
+Every step of the simulation runs in the library's HIP kernels; if the
+library is not built, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libsonosim.so")
+
+SG_OK, SG_EINVAL, SG_ENOMEM, SG_EHIP, SG_ESTATE, SG_ERANGE = 0, -1, -2, -3, -4, -5
+SG_MAX_IMAGE = 1024
+
+# every symbol include/sonosim.h declares
+SYMBOLS = (
+    "sg_last_error", "sg_version", "sg_create", "sg_destroy", "sg_set_stream", "sg_synchronize",
+    "sg_volume_register", "sg_volume_release", "sg_tissue_table_set", "sg_simulate",
+    "sg_batch_plan_create", "sg_batch_poses", "sg_batch_set_poses", "sg_batch_step",
+    "sg_batch_step_profiled", "sg_batch_status", "sg_autotune",
+    "sg_batch_config", "sg_batch_plan_destroy",
+)
+
+
+class SonosimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class sg_volume_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("spacing_mm", C.c_double * 3), ("labels", C.c_void_p), ("ct_hu", C.c_void_p),
+                ("noise_seed", C.c_uint64)]
+
+
+class sg_tissue(C.Structure):
+    _fields_ = [("Z_mrayl", C.c_float), ("alpha_np_cm_mhz", C.c_float), ("mu0", C.c_float),
+                ("sigma0", C.c_float), ("mu1", C.c_float)]
+
+
+class sg_probe(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("dx_mm", C.c_double), ("dy_mm", C.c_double),
+                ("f_mhz", C.c_double), ("E0", C.c_double), ("psf_frac", C.c_double),
+                ("dr_db", C.c_double)]
+
+
+class sg_debug_planes(C.Structure):
+    _fields_ = [("label", C.c_void_p), ("voxel", C.c_void_p), ("philox", C.c_void_p),
+                ("energy", C.c_void_p), ("intensity", C.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    P, I32, VP = C.POINTER, C.c_int32, C.c_void_p
+    L.sg_last_error.restype = C.c_char_p
+    L.sg_version.restype = I32
+    sigs = {
+        "sg_create": [P(VP), I32, VP],
+        "sg_destroy": [VP],
+        "sg_set_stream": [VP, VP],
+        "sg_synchronize": [VP],
+        "sg_volume_register": [VP, P(sg_volume_desc), P(I32)],
+        "sg_volume_release": [VP, I32],
+        "sg_tissue_table_set": [VP, VP, I32],
+        "sg_simulate": [VP, I32, VP, VP, VP, VP, VP, P(sg_debug_planes)],
+        "sg_batch_plan_create": [VP, I32, VP, VP, VP, P(I32)],
+        "sg_batch_poses": [VP, I32, P(VP)],
+        "sg_batch_set_poses": [VP, I32, VP],
+        "sg_batch_step": [VP, I32, VP],
+        "sg_batch_step_profiled": [VP, I32, VP, P(C.c_float)],
+        "sg_batch_status": [VP, I32, P(I32)],
+        "sg_autotune": [VP, I32, C.c_char_p],
+        "sg_batch_config": [VP, I32, P(I32), P(I32), P(I32)],
+        "sg_batch_plan_destroy": [VP, I32],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = I32
+    _lib = L
+    return L
+
+
+def _check(status: int, name: str):
+    if status != SG_OK:
+        msg = load().sg_last_error().decode(errors="replace")
+        raise SonosimError(status, f"{name}: {msg}")
+
+
+def _stream_of(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _dptr(t):
+    """Device pointer of a CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+
+def sg_version() -> int:
+    return int(load().sg_version())
+
+
+def sg_create(device: int = 0, stream=None):
+    ctx = C.c_void_p()
+    _check(load().sg_create(C.byref(ctx), int(device), _stream_of(stream)), "sg_create")
+    return ctx
+
+
+def sg_destroy(ctx):
+    _check(load().sg_destroy(ctx), "sg_destroy")
+
+
+def sg_set_stream(ctx, stream=None):
+    _check(load().sg_set_stream(ctx, _stream_of(stream)), "sg_set_stream")
+
+
+def sg_synchronize(ctx):
+    _check(load().sg_synchronize(ctx), "sg_synchronize")
+
+
+def sg_volume_register(ctx, labels, spacing=(1.0, 1.0, 1.0), ct=None, seed: int = 0) -> int:
+    """labels: device uint8 tensor [nz, ny, nx]; ct: device int16 tensor or None."""
+    nz, ny, nx = labels.shape
+    if ct is not None and tuple(ct.shape) != tuple(labels.shape):
+        raise ValueError("ct must have the label volume's shape")
+    d = sg_volume_desc(nx, ny, nz, (C.c_double * 3)(*[float(s) for s in spacing]), _dptr(labels),
+                       _dptr(ct), int(seed) & ((1 << 64) - 1))
+    vid = C.c_int32()
+    _check(load().sg_volume_register(ctx, C.byref(d), C.byref(vid)), "sg_volume_register")
+    return int(vid.value)
+
+
+def sg_volume_release(ctx, vol_id: int):
+    _check(load().sg_volume_release(ctx, int(vol_id)), "sg_volume_release")
+
+
+def sg_tissue_table_set(ctx, table):
+    """table: array-like [n_labels, 5] = (Z, alpha, mu0, sigma0, mu1)."""
+    t = np.ascontiguousarray(np.asarray(table, dtype=np.float32).reshape(-1, 5))
+    _check(load().sg_tissue_table_set(ctx, t.ctypes.data, t.shape[0]), "sg_tissue_table_set")
+
+
+def probes_array(probes):
+    """Host array of sg_probe from objects with W, H, dx, dy, f, E0, psf, dr."""
+    arr = (sg_probe * len(probes))()
+    for i, p in enumerate(probes):
+        arr[i] = sg_probe(int(p.W), int(p.H), float(p.dx), float(p.dy), float(p.f), float(p.E0),
+                          float(p.psf), float(p.dr))
+    return arr
+
+
+def sg_simulate(ctx, vol_ids, probes, poses, out, out_offsets, debug: dict | None = None):
+    """out: device float32 tensor; debug: dict of device tensors keyed by
+    label / voxel / philox / energy / intensity."""
+    n = len(probes)
+    vids = np.ascontiguousarray(vol_ids, dtype=np.int32)
+    pa = probes_array(probes)
+    ps = np.ascontiguousarray(poses, dtype=np.float64).reshape(n, 12)
+    offs = np.ascontiguousarray(out_offsets, dtype=np.int64)
+    if len(vids) != n or len(offs) != n:
+        raise ValueError("vol_ids, probes and out_offsets must have one entry per env")
+    dbg = None
+    if debug:
+        dbg = sg_debug_planes(*[_dptr(debug.get(k)) for k in ("label", "voxel", "philox", "energy",
+                                                               "intensity")])
+    _check(load().sg_simulate(ctx, n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data, _dptr(out),
+                              offs.ctypes.data, C.byref(dbg) if dbg is not None else None), "sg_simulate")
+
+
+def sg_batch_plan_create(ctx, vol_ids, probes, out_offsets) -> int:
+    n = len(probes)
+    vids = np.ascontiguousarray(vol_ids, dtype=np.int32)
+    offs = np.ascontiguousarray(out_offsets, dtype=np.int64)
+    pa = probes_array(probes)
+    pid = C.c_int32()
+    _check(load().sg_batch_plan_create(ctx, n, vids.ctypes.data, C.cast(pa, C.c_void_p), offs.ctypes.data,
+                                       C.byref(pid)), "sg_batch_plan_create")
+    return int(pid.value)
+
+
+def sg_batch_poses(ctx, plan_id: int) -> int:
+    """Device address of the plan's pose buffer (n_envs * 12 float64)."""
+    p = C.c_void_p()
+    _check(load().sg_batch_poses(ctx, int(plan_id), C.byref(p)), "sg_batch_poses")
+    return int(p.value)
+
+
+def sg_batch_set_poses(ctx, plan_id: int, poses):
+    """Upload host poses (n_envs x 12 float64) into the plan's buffer."""
+    ps = np.ascontiguousarray(poses, dtype=np.float64)
+    _check(load().sg_batch_set_poses(ctx, int(plan_id), ps.ctypes.data), "sg_batch_set_poses")
+
+
+def sg_batch_step_profiled(ctx, plan_id: int, out) -> float:
+    """One eager step; returns the persistent kernel's duration in ms."""
+    ms = C.c_float()
+    _check(load().sg_batch_step_profiled(ctx, int(plan_id), _dptr(out), C.byref(ms)), "sg_batch_step_profiled")
+    return float(ms.value)
+
+
+def sg_batch_step(ctx, plan_id: int, out):
+    _check(load().sg_batch_step(ctx, int(plan_id), _dptr(out)), "sg_batch_step")
+
+
+def sg_batch_status(ctx, plan_id: int) -> int:
+    n = C.c_int32()
+    _check(load().sg_batch_status(ctx, int(plan_id), C.byref(n)), "sg_batch_status")
+    return int(n.value)
+
+
+def sg_autotune(ctx, plan_id: int, cache_path: str | None = None):
+    _check(load().sg_autotune(ctx, int(plan_id), None if cache_path is None else cache_path.encode()),
+           "sg_autotune")
+
+
+def sg_batch_config(ctx, plan_id: int):
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().sg_batch_config(ctx, int(plan_id), C.byref(a), C.byref(b), C.byref(c)), "sg_batch_config")
+    return int(a.value), int(b.value), int(c.value)
+
+
+def sg_batch_plan_destroy(ctx, plan_id: int):
+    _check(load().sg_batch_plan_destroy(ctx, int(plan_id)), "sg_batch_plan_destroy")

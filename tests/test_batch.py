@@ -1,0 +1,133 @@
+"""Batched persistent path (device geometry, work queue, HIP graph replay,
+autotuner) vs the single-call path and the FP64 oracle (GPU)."""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tolerance import check_env
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sess():
+    from paper_2507_01152_amd.session import Session
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = Session(0)
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    """256 envs over 8 label volumes from 160^3 to 320x256x384, W in
+    [64, 256], H in [128, 512]."""
+    return synth.batched_workload(seed=0)
+
+
+def batch_frames(sess, wl, vids, out=None, plan=None, steps=1, poses=None):
+    from paper_2507_01152_amd import sonosim as sg
+    offs, total = wl.out_offsets()
+    if plan is None:
+        plan = sg.sg_batch_plan_create(sess.ctx, vids, wl.probes, offs)
+    sg.sg_batch_set_poses(sess.ctx, plan, wl.poses if poses is None else poses)
+    if out is None:
+        out = torch.full((total,), -7.0, dtype=torch.float32, device=sess.device)
+    for _ in range(steps):
+        sg.sg_batch_step(sess.ctx, plan, out)
+    assert sg.sg_batch_status(sess.ctx, plan) == 0
+    return out, plan
+
+
+def test_batch_equals_single_call_bit_exact(sess, uneven):
+    from paper_2507_01152_amd import sonosim as sg
+    vids = sess.load(uneven)
+    ref, _, _ = sess.simulate(uneven, vids)
+    out, plan = batch_frames(sess, uneven, vids)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, out)
+    # graph replays are deterministic
+    out2, _ = batch_frames(sess, uneven, vids, plan=plan, steps=3)
+    assert torch.equal(out, out2)
+    sg.sg_batch_plan_destroy(sess.ctx, plan)
+
+
+def test_batch_256_envs_vs_oracle(sess, uneven):
+    from paper_2507_01152_amd.session import split_frames
+    vids = sess.load(uneven)
+    out, plan = batch_frames(sess, uneven, vids)
+    Y = split_frames(out.cpu().numpy(), uneven)
+
+    def one(e):
+        o = oracle.simulate_env(uneven.volumes[uneven.vol_ids[e]], uneven.table, uneven.probes[e],
+                                uneven.poses[e], planes=("I", "A", "Y"))
+        check_env({"Y": Y[e]}, o, uneven.probes[e], f"batched env {e}")
+        return float(o["Y"].mean())
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        means = list(ex.map(one, range(uneven.n_envs)))
+    assert np.mean(means) > 0.02
+
+
+def test_env_order_invariance(sess, uneven):
+    """Permuting the environments (and their output slots) permutes frames."""
+    from paper_2507_01152_amd.session import split_frames
+    vids = sess.load(uneven)
+    out, _ = batch_frames(sess, uneven, vids)
+    perm = np.random.default_rng(1).permutation(uneven.n_envs)
+    wl2 = synth.Workload(uneven.volumes, uneven.vol_ids[perm], [uneven.probes[i] for i in perm],
+                         uneven.poses[perm], uneven.table)
+    vids2 = vids[perm]
+    out2, _ = batch_frames(sess, wl2, vids2)
+    a = split_frames(out.cpu().numpy(), uneven)
+    b = split_frames(out2.cpu().numpy(), wl2)
+    for j, i in enumerate(perm):
+        assert np.array_equal(a[i], b[j])
+
+
+def test_autotune_keeps_frames_bit_identical(sess, uneven, tmp_path):
+    from paper_2507_01152_amd import sonosim as sg
+    vids = sess.load(uneven)
+    out, plan = batch_frames(sess, uneven, vids)
+    cache = str(tmp_path / "tune.jsonl")
+    sg.sg_autotune(sess.ctx, plan, cache)
+    spw, tx, ty = sg.sg_batch_config(sess.ctx, plan)
+    assert spw in (4, 8) and (tx, ty) in [(32, 32), (64, 16), (16, 64), (64, 32)]
+    out2, _ = batch_frames(sess, uneven, vids, plan=plan)
+    assert torch.equal(out, out2)
+    text = open(cache).read()
+    assert '"spw"' in text and "|n256|" in text
+    # a second plan of the same shape reads the cache instead of timing
+    out3, plan2 = batch_frames(sess, uneven, vids)
+    sg.sg_autotune(sess.ctx, plan2, cache)
+    assert sg.sg_batch_config(sess.ctx, plan2) == (spw, tx, ty)
+    assert open(cache).read() == text
+    ms = sg.sg_batch_step_profiled(sess.ctx, plan2, out3)
+    assert ms > 0 and torch.equal(out, out3)
+
+
+def test_out_of_range_pose_gives_zero_frame_and_status(sess):
+    from paper_2507_01152_amd import sonosim as sg
+    wl = synth.ellipsoid_workload(seed=3, n_envs=3)
+    vids = sess.load(wl)
+    offs, total = wl.out_offsets()
+    plan = sg.sg_batch_plan_create(sess.ctx, vids, wl.probes, offs)
+    poses = wl.poses.copy()
+    poses[1, 7] = 1e12
+    poses[2, 0] = np.nan
+    sg.sg_batch_set_poses(sess.ctx, plan, poses)
+    out = torch.full((total,), -1.0, dtype=torch.float32, device=sess.device)
+    sg.sg_batch_step(sess.ctx, plan, out)
+    assert sg.sg_batch_status(sess.ctx, plan) == 2
+    n = wl.probes[0].W * wl.probes[0].H
+    y = out.cpu().numpy()
+    assert (y[n:] == 0).all() and (y[:n] >= 0).all() and y[:n].max() > 0
+    ref, _, _ = sess.simulate(synth.Workload(wl.volumes[:1], np.zeros(1, np.int32), wl.probes[:1],
+                                             wl.poses[:1], wl.table), vids[:1])
+    assert torch.equal(ref, out[:n])

@@ -1,0 +1,159 @@
+"""HIP physics path vs the FP64 oracle, through the C ABI (GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from cases import axis_pose, layered_volume, single_env, table_with
+from synth import Probe, Volume, Workload
+from tolerance import check_env
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sess():
+    from paper_2507_01152_amd.session import Session
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = Session(0)
+    yield s
+    s.close()
+
+
+def run_gpu(sess, wl, debug=True):
+    from paper_2507_01152_amd.session import split_frames
+    vids = sess.load(wl)
+    out, offs, dbg = sess.simulate(wl, vids, debug=debug)
+    torch.cuda.synchronize()
+    res = [dict(Y=y) for y in split_frames(out.cpu().numpy(), wl)]
+    if debug:
+        for k, t in dbg.items():
+            per = 4 if k == "philox" else 1
+            for e, a in enumerate(split_frames(t.cpu().numpy(), wl, per)):
+                res[e][k] = a
+    return res
+
+
+def check_all(sess, wl, env_ids=None, name="", debug=True):
+    g = run_gpu(sess, wl, debug=debug)
+    ids = range(wl.n_envs) if env_ids is None else env_ids
+    for e in ids:
+        o = oracle.simulate_env(wl.volumes[wl.vol_ids[e]], wl.table, wl.probes[e], wl.poses[e],
+                                planes=("label", "voxel", "philox", "E", "I", "A", "Y"))
+        check_env(g[e], o, wl.probes[e], f"{name} env {e}")
+    return g
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_ellipsoid_64_cubed_parity(sess, seed):
+    """64^3 label volume, 6 ellipsoids, 64 scanlines x 128 samples."""
+    wl = synth.ellipsoid_workload(seed=seed, n_envs=4)
+    g = check_all(sess, wl, name=f"seed{seed}")
+    assert any((x["label"] == 3).any() for x in g)   # bone is hit somewhere
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 200), (37, 101), (64, 65), (200, 1), (130, 300), (3, 700)])
+def test_ragged_and_degenerate_sizes(sess, W, H):
+    wl = synth.ellipsoid_workload(seed=7, n_envs=2, W=W, H=H, dx=0.37, dy=0.29)
+    check_all(sess, wl, name=f"{W}x{H}")
+
+
+def test_plane_entirely_outside_volume(sess):
+    vol = Volume(labels=np.ones((16, 16, 16), dtype=np.uint8), seed=4)
+    wl = single_env(vol, Probe(W=20, H=40), axis_pose((-500.0, -500.0, -500.0)))
+    g = check_all(sess, wl, name="outside")
+    assert (g[0]["voxel"] == -1).all() and (g[0]["Y"] == 0).all()
+
+
+@pytest.mark.parametrize("Zb", [np.inf, 0.0])
+def test_total_reflection_at_bone(sess, Zb):
+    table = table_with(Z_3=Zb)
+    vol = layered_volume(64, 64, 64, [(0, 1), (15, 3)])
+    wl = single_env(vol, Probe(W=15, H=120), axis_pose((32.0, 32.0, 0.0)), table)
+    g = check_all(sess, wl, name=f"Zbone={Zb}")
+    assert (g[0]["energy"][29:] == 0).all() and (g[0]["energy"][:29] > 0).all()
+
+
+def test_gate_extremes_and_energy_scale(sess):
+    table = synth.default_tissue_table().copy()
+    table[1, 4] = np.inf     # soft tissue always scatters
+    table[2, 4] = -np.inf    # fat never
+    wl = synth.ellipsoid_workload(seed=11, n_envs=3)
+    wl.table = table
+    for p in wl.probes:
+        p.E0 = 3.5
+        p.dr = 45.0
+    check_all(sess, wl, name="gate")
+
+
+def test_many_labels_and_permutation(sess):
+    rng = np.random.default_rng(5)
+    lab = rng.integers(0, 9, size=(24, 24, 24)).astype(np.uint8)
+    t = np.zeros((9, 5), dtype=np.float32)
+    t[:, 0] = rng.uniform(0.5, 8.0, 9)
+    t[0, 0] = 0.0
+    t[:, 1] = rng.uniform(0.0, 1.0, 9)
+    t[:, 2] = rng.uniform(0.0, 0.1, 9)
+    t[:, 3] = rng.uniform(0.0, 0.05, 9)
+    t[:, 4] = rng.uniform(-1, 1, 9)
+    vol = Volume(labels=lab, spacing=(0.8, 1.0, 1.2), seed=77)
+    pose = synth.pose_from(synth.random_rotation(rng), (10.0, 12.0, 11.0))
+    wl = single_env(vol, Probe(W=50, H=90, dx=0.3, dy=0.3), pose, t)
+    check_all(sess, wl, name="9 labels")
+
+
+def test_ct_impedance_parity(sess):
+    """Spine phantom with an int16 CT volume (impedance from HU)."""
+    wl = synth.spine_ct_workload(seed=3, n_envs=6, dims=(128, 128, 128), W=64, H=128)
+    g = check_all(sess, wl, name="ct")
+    assert any((x["label"] == 3).any() for x in g)
+
+
+def test_spine_ct_256_cubed_64_envs_full_size(sess):
+    """Full-size CT workload: 256^3 labels + int16 HU, 64 envs, 128 x 256."""
+    wl = synth.spine_ct_workload(seed=0)
+    assert wl.n_envs == 64 and wl.volumes[0].labels.shape == (256, 256, 256)
+    check_all(sess, wl, name="c2")
+
+
+def test_error_paths(sess):
+    from paper_2507_01152_amd import sonosim as sg
+    wl = synth.ellipsoid_workload(seed=1, n_envs=1)
+    vids = sess.load(wl)
+    out, offs = sess.frames(wl)
+
+    def sim(**kw):
+        args = dict(vol_ids=vids, probes=wl.probes, poses=wl.poses, out=out, out_offsets=offs)
+        args.update(kw)
+        sg.sg_simulate(sess.ctx, **args)
+
+    bad_pose = wl.poses.copy()
+    bad_pose[0, 3] = np.nan
+    with pytest.raises(sg.SonosimError) as e:
+        sim(poses=bad_pose)
+    assert e.value.status == sg.SG_EINVAL
+    far = wl.poses.copy()
+    far[0, 3] = 1e9
+    with pytest.raises(sg.SonosimError) as e:
+        sim(poses=far)
+    assert e.value.status == sg.SG_ERANGE
+    with pytest.raises(sg.SonosimError) as e:
+        sim(probes=[Probe(W=0, H=10)])
+    assert e.value.status == sg.SG_EINVAL
+    with pytest.raises(sg.SonosimError) as e:
+        sim(probes=[Probe(W=64, H=128, psf=0.2)])       # PSF radius > 32 px
+    assert e.value.status == sg.SG_EINVAL
+    with pytest.raises(sg.SonosimError) as e:
+        sim(vol_ids=[1234])
+    assert e.value.status == sg.SG_EINVAL
+    # a table smaller than the volume's labels
+    sg.sg_tissue_table_set(sess.ctx, wl.table[:2])
+    with pytest.raises(sg.SonosimError) as e:
+        sim()
+    assert e.value.status == sg.SG_EINVAL
+    sg.sg_tissue_table_set(sess.ctx, wl.table)
+    sim()
+    torch.cuda.synchronize()
