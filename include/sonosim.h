@@ -163,8 +163,10 @@ sg_status sg_simulate(sg_ctx* ctx, int32_t n_envs, const int32_t* vol_ids,
 /* ------------------------------------------------------------------------
  * Batched persistent path (environments stepped in batch mode, Sec. 4):
  * a plan fixes the environments' volumes, probes and output offsets; each
- * step replays one captured HIP graph whose persistent kernel pulls
- * (environment, tile) work items longest-first from a device queue.  Poses
+ * step replays one captured HIP graph: device-side plane geometry, then a
+ * persistent ray kernel pulling (environment, scanline group) items
+ * longest-first from a device queue, then a persistent PSF kernel pulling
+ * (environment, tile) items.  Poses
  * live in a library-owned device buffer that the caller updates between
  * steps (for instance from its own kernels on the same stream).
  */
@@ -200,14 +202,14 @@ sg_status sg_batch_status(sg_ctx* ctx, int32_t plan_id, int32_t* n_bad);
  * bit-identical frames. */
 sg_status sg_autotune(sg_ctx* ctx, int32_t plan_id, const char* cache_path);
 
-/* Run one step without the graph, timing the persistent kernel alone with
- * HIP events on the context's stream; synchronises.  *ms (host) receives
- * the kernel's duration.  For measurement only; frames are identical to
- * sg_batch_step's. */
-sg_status sg_batch_step_profiled(sg_ctx* ctx, int32_t plan_id, float* out, float* ms);
+/* Run one step without the graph, timing its two persistent kernels with
+ * HIP events on the context's stream; synchronises.  *ms_ray and *ms_psf
+ * (host) receive the durations of the ray kernel and of the PSF kernel.
+ * For measurement only; frames are identical to sg_batch_step's. */
+sg_status sg_batch_step_profiled(sg_ctx* ctx, int32_t plan_id, float* out, float* ms_ray, float* ms_psf);
 
 /* Launch shape currently used by a plan (for reports): scanlines per ray
- * work item, and the PSF tile (tile_x scanlines by tile_y rows). */
+ * work item, and the PSF tile (tile_x scanlines by tile_y = 64 rows). */
 sg_status sg_batch_config(sg_ctx* ctx, int32_t plan_id, int32_t* scanlines_per_item,
                           int32_t* tile_x, int32_t* tile_y);
 

@@ -1,22 +1,25 @@
 // Model-based B-mode simulation kernels for gfx950 (SonoGym, App. B.2).
 //
-// Two passes per frame:
-//  * ray pass   -- one wave64 per scanline, lanes along depth.  Each 64-row
-//                  chunk samples the plane (nearest label, optional trilinear
-//                  CT), forms the boundary/reflection/transmission terms,
-//                  runs wave-level scans for the transmission product and the
-//                  attenuation integral (remaining energy E), draws the
-//                  per-voxel scatterer (Philox4x32-10 keyed by voxel index,
-//                  Box-Muller, density gate) and writes the reflection source
-//                  R' = G*E*cos(theta)*|r|, the scattering pattern T and E to
-//                  a scanline-major scratch (coalesced along the scanline).
-//  * PSF pass   -- one workgroup per output tile: stages R' and T with the PSF
-//                  halo through LDS, applies the separable Gaussian PSF
-//                  (axial, then lateral), composes I = K(x)R' + E*K(x)T,
-//                  log-compresses and stores the frame row-major (coalesced
-//                  along image rows).
-// A persistent kernel runs both passes from one device work queue for the
-// batched path.
+// Two persistent work-queue kernels per step (the kernel boundary is the only
+// synchronisation between them):
+//  * ray kernel -- one wave64 per scanline, lanes along depth, marching down
+//                  in 64-row chunks.  Per chunk: sample the plane (nearest
+//                  label, optional FP64 trilinear CT), boundary indicator,
+//                  reflection and transmission, wave-level scans for the
+//                  transmission product and the attenuation integral
+//                  (remaining energy E), per-voxel scatterer (Philox4x32-10
+//                  keyed by voxel index, Box-Muller, density gate), the
+//                  reflection source R' = G*E*cos(theta)*|r|.  R' and T go
+//                  into a per-wave LDS ring of four chunks, and the axial
+//                  Gaussian is applied one chunk behind.  The axially filtered
+//                  fields and E are written scanline-major, coalesced along
+//                  the scanline.  The next chunk's labels are gathered one
+//                  chunk ahead.
+//  * PSF kernel -- one workgroup per tile of TX scanlines x 64 rows: stages
+//                  the axially filtered fields with the lateral halo in LDS,
+//                  applies the lateral Gaussian, composes
+//                  I = K(x)R' + E*K(x)T, log-compresses and stores the frame
+//                  row-major (coalesced along image rows).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,6 +29,11 @@ namespace sg {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+constexpr int kRing = 4 * kWave;         // rows held per wave in the axial ring (power of two)
+constexpr int kTaps = 2 * kMaxPsfRadius + 1;
+constexpr int kTileRows = 64;            // PSF tile height
+constexpr int kAS = kTileRows + 1;       // padded LDS column stride
 
 // Philox4x32-10 (Salmon et al., SC'11): multipliers and Weyl key increments.
 constexpr uint32_t kPhM0 = 0xD2511F53u;
@@ -89,7 +97,7 @@ __device__ __forceinline__ double ct_corner(const VolDev& v, int32_t ix, int32_t
 
 // impedance from CT: max(HU + 1000, 0), HU trilinear in FP64 (successive
 // linear interpolation along x, y, z; outside corners -1000 HU)
-__device__ double z_from_ct(const EnvDev& e, const VolDev& v, int x, int y)
+__device__ __forceinline__ double z_from_ct(const EnvDev& e, const VolDev& v, int x, int y)
 {
     int32_t b[3];
     double w[3];
@@ -117,7 +125,7 @@ __device__ double z_from_ct(const EnvDev& e, const VolDev& v, int x, int y)
 
 // cos(theta): Sobel (1,2,1) on [label differs from the centre label] with
 // clamped image coordinates, in physical units (only evaluated at G = 1)
-__device__ float incidence_cos(const EnvDev& e, const VolDev& v, int x, int y, int lab)
+__device__ __forceinline__ float incidence_cos(const EnvDev& e, const VolDev& v, int x, int y, int lab)
 {
     int b[3][3];
 #pragma unroll
@@ -143,12 +151,35 @@ __device__ __forceinline__ float uniform24(uint32_t w)
     return (float)((w >> 9) * 2u + 1u) * 0x1p-24f;
 }
 
-// One scanline of the ray pass, executed by one wave (lane = depth row).
-__device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v,
-                             const TissueDev* tab, int x, int lane)
+__device__ __forceinline__ void wave_sync_lds()
 {
-    const int W = e.W, H = e.H;
-    (void)W;
+    // order this wave's LDS writes before its later LDS reads (LDS executes
+    // one wave's instructions in issue order; this stops compiler reordering)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Axial filter of one chunk from the ring: lane l outputs row y0 + l.
+__device__ __forceinline__ void axial_from_ring(const float* ringR, const float* ringT, const float* kax, int ra,
+                                                int y0, int lane, float& aR, float& aT)
+{
+    float s1 = 0.f, s2 = 0.f;
+    const int base = y0 + lane - ra + kRing;   // >= kWave - ra > 0
+    for (int j = 0; j <= 2 * ra; ++j) {
+        const int slot = (base + j) & (kRing - 1);
+        s1 += kax[j] * ringR[slot];
+        s2 += kax[j] * ringT[slot];
+    }
+    aR = s1;
+    aT = s2;
+}
+
+// One scanline of the ray pass, executed by one wave (lane = depth row).
+__device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v, const TissueDev* tab,
+                             const float* kax, float* ringR, float* ringT, int x, int lane)
+{
+    const int H = e.H;
     float* fR = a.fR + e.scr_off + (int64_t)x * H;
     float* fT = a.fT + e.scr_off + (int64_t)x * H;
     float* fE = a.fE + e.scr_off + (int64_t)x * H;
@@ -161,36 +192,62 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         return;
     }
     const bool ct = v.ct != nullptr;
+    const int ra = e.rax;
+    // rows -64..-1 of the ring read as zeros (zero padding above the image)
+    ringR[kRing - kWave + lane] = 0.f;
+    ringT[kRing - kWave + lane] = 0.f;
+
     float carry_t = 1.f;     // transmission product of the rows above the chunk
     double carry_a = 0.0;    // attenuation integral (sum of alpha) above the chunk
-    for (int y0 = 0; y0 < H; y0 += kWave) {
+    float E_prev = 0.f;      // E of the previous chunk (its axial output is pending)
+
+    int32_t vox = voxel_at(e, v, x, lane);
+    int lab = label_of(v, vox);
+    double Z = ct ? z_from_ct(e, v, x, lane) : 0.0;
+
+    const int n_chunks = (H + kWave - 1) / kWave;
+    for (int k = 0; k < n_chunks; ++k) {
+        const int y0 = k * kWave;
         const int y = y0 + lane;
         const bool act = y < H;
-        const int32_t vox = voxel_at(e, v, x, y);
-        const int lab = label_of(v, vox);
-        double Z = ct ? z_from_ct(e, v, x, y) : (double)tab[lab].Z;
-        // the next row's label and impedance: neighbour lane, or row y0+64
-        int lab_n = __shfl_down(lab, 1);
-        double Z_n = __shfl_down(Z, 1);
+        // gather the next chunk's labels (and CT) ahead of use
+        const int32_t vox_n = voxel_at(e, v, x, y + kWave);
+        const int lab_n = label_of(v, vox_n);
+        const double Zct_n = ct ? z_from_ct(e, v, x, y + kWave) : 0.0;
+
+        // scatterer of this chunk's voxels (computed for every lane, selected below)
+        uint32_t w[4];
+        philox4x32_10((uint32_t)vox, v.key0, v.key1, w);
+        const TissueDev tt = tab[lab];
+        const float n0 = sqrtf(-2.f * logf(uniform24(w[0]))) * cospif(2.f * uniform24(w[1]));
+        const bool inside = act && vox >= 0;
+        const float T = (inside && (unsigned long long)w[2] < tt.thr) ? n0 * tt.sigma0 + tt.mu0 : 0.f;
+
+        // boundary with the next row
+        const double Zc = ct ? Z : (double)tt.Z;
+        int lab_nr = __shfl_down(lab, 1);
+        double Z_nr = __shfl_down(Zc, 1);
+        const int lab_first_n = __shfl(lab_n, 0);
+        const double Z_first_n = __shfl(ct ? Zct_n : (double)tab[lab_n].Z, 0);
         if (lane == kWave - 1) {
-            lab_n = label_of(v, voxel_at(e, v, x, y + 1));
-            Z_n = ct ? z_from_ct(e, v, x, y + 1) : (double)tab[lab_n].Z;
+            lab_nr = lab_first_n;
+            Z_nr = Z_first_n;
         }
-        const bool G = act && (y < H - 1) && (lab != lab_n);
+        const bool G = act && (y < H - 1) && (lab != lab_nr);
         float r = 0.f, t = 1.f;
-        if (G && Z != Z_n) {
-            if (Z == 0.0 || Z_n == 0.0 || __builtin_isinf(Z) || __builtin_isinf(Z_n)) {
-                r = Z_n > Z ? 1.f : -1.f;
+        if (G && Zc != Z_nr) {
+            if (Zc == 0.0 || Z_nr == 0.0 || __builtin_isinf(Zc) || __builtin_isinf(Z_nr)) {
+                r = Z_nr > Zc ? 1.f : -1.f;
                 t = 0.f;
             } else {
-                const double s = Z + Z_n;
-                r = (float)((Z_n - Z) / s);
-                t = (float)((2.0 * Z / s) * (2.0 * Z_n / s));
+                const double s = Zc + Z_nr;
+                r = (float)((Z_nr - Zc) / s);
+                t = (float)((2.0 * Zc / s) * (2.0 * Z_nr / s));
             }
         }
         // inclusive wave scans: transmission product (FP32), alpha sum (FP64)
         float tp = act ? t : 1.f;
-        double as = act ? (double)tab[lab].alpha : 0.0;
+        double as = act ? (double)tt.alpha : 0.0;
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) {
             const float o = __shfl_up(tp, d);
@@ -212,203 +269,148 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
 
         float cs = 1.f;
         if (G) cs = incidence_cos(e, v, x, y, lab);
-
-        float T = 0.f;
-        uint32_t w[4] = {0u, 0u, 0u, 0u};
-        if (act && vox >= 0) {
-            philox4x32_10((uint32_t)vox, v.key0, v.key1, w);
-            const TissueDev tt = tab[lab];
-            if ((unsigned long long)w[2] < tt.thr) {
-                const float n0 = sqrtf(-2.f * logf(uniform24(w[0]))) * cospif(2.f * uniform24(w[1]));
-                T = n0 * tt.sigma0 + tt.mu0;
-            }
-        }
         const float Rp = G ? E * cs * fabsf(r) : 0.f;
+
+        // ring slot of this chunk, then the axial filter of the previous chunk
+        ringR[(y0 & (kRing - 1)) + lane] = act ? Rp : 0.f;
+        ringT[(y0 & (kRing - 1)) + lane] = act ? T : 0.f;
+        wave_sync_lds();
+        if (k > 0) {
+            float aR, aT;
+            axial_from_ring(ringR, ringT, kax, ra, y0 - kWave, lane, aR, aT);
+            const int yp = y0 - kWave + lane;   // < H
+            fR[yp] = aR;
+            fT[yp] = aT;
+            fE[yp] = E_prev;
+        }
+        E_prev = E;
         if (act) {
-            fR[y] = Rp;
-            fT[y] = T;
-            fE[y] = E;
-            const int64_t k = e.out_off + (int64_t)y * e.W + x;
-            if (a.dbg.label) a.dbg.label[k] = (uint8_t)lab;
-            if (a.dbg.voxel) a.dbg.voxel[k] = vox;
-            if (a.dbg.energy) a.dbg.energy[k] = E;
+            const int64_t kk = e.out_off + (int64_t)y * e.W + x;
+            if (a.dbg.label) a.dbg.label[kk] = (uint8_t)lab;
+            if (a.dbg.voxel) a.dbg.voxel[kk] = vox;
+            if (a.dbg.energy) a.dbg.energy[kk] = E;
             if (a.dbg.philox) {
                 uint4 pw;
-                pw.x = w[0];
-                pw.y = w[1];
-                pw.z = w[2];
-                pw.w = w[3];
-                reinterpret_cast<uint4*>(a.dbg.philox)[k] = pw;
+                pw.x = inside ? w[0] : 0u;
+                pw.y = inside ? w[1] : 0u;
+                pw.z = inside ? w[2] : 0u;
+                pw.w = inside ? w[3] : 0u;
+                reinterpret_cast<uint4*>(a.dbg.philox)[kk] = pw;
             }
+        }
+        vox = vox_n;
+        lab = lab_n;
+        Z = Zct_n;
+        wave_sync_lds();
+    }
+    // flush: rows below the image read as zeros
+    const int y_last = (n_chunks - 1) * kWave;
+    ringR[((y_last + kWave) & (kRing - 1)) + lane] = 0.f;
+    ringT[((y_last + kWave) & (kRing - 1)) + lane] = 0.f;
+    wave_sync_lds();
+    float aR, aT;
+    axial_from_ring(ringR, ringT, kax, ra, y_last, lane, aR, aT);
+    if (y_last + lane < H) {
+        fR[y_last + lane] = aR;
+        fT[y_last + lane] = aT;
+        fE[y_last + lane] = E_prev;
+    }
+    wave_sync_lds();
+}
+
+__device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    return *s_item;
+}
+
+// Ray kernel: items (env, group of kWaves * spw scanlines), longest first.
+__global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a, QueueDev* q)
+{
+    __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
+    __shared__ float s_kax[kTaps];
+    __shared__ float s_ring[kWaves][2][kRing];
+    __shared__ int s_item;
+    for (int i = threadIdx.x; i < a.n_labels; i += kThreads) s_tab[i] = a.table[i];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    for (;;) {
+        const int item = next_item(&q->next_ray, &s_item);
+        if (item >= a.n_ray) break;
+        const ItemRay it = a.ray_items[item];
+        const EnvDev e = a.envs[it.env];
+        const VolDev v = a.vols[e.vol];
+        for (int i = threadIdx.x; i <= 2 * e.rax; i += kThreads) s_kax[i] = a.coefs[e.kax + i];
+        __syncthreads();
+        for (int s = 0; s < a.scanlines_per_wave; ++s) {
+            const int x = it.x0 + s * kWaves + wave;
+            if (x < e.W) ray_scanline(a, e, v, s_tab, s_kax, s_ring[wave][0], s_ring[wave][1], x, lane);
         }
     }
 }
 
-// tissue table staged in LDS for the ray pass
-__device__ void stage_table(const PhysArgs& a, TissueDev* s_tab)
+// PSF kernel: items (env, tile of TX scanlines x 64 rows).
+template <int TX>
+__global__ __launch_bounds__(kThreads) void k_psf(PhysArgs a, QueueDev* q)
 {
-    for (int i = threadIdx.x; i < a.n_labels; i += blockDim.x) s_tab[i] = a.table[i];
-}
-
-// one ray work item: kRayWaves waves x scanlines_per_wave scanlines from x0
-__device__ int ray_item(const PhysArgs& a, const ItemRay it, const TissueDev* s_tab)
-{
-    const EnvDev e = a.envs[it.env];
-    const VolDev v = a.vols[e.vol];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    const int spw = a.scanlines_per_wave;
-    for (int s = 0; s < spw; ++s) {
-        const int x = it.x0 + s * kRayWaves + wave;
-        if (x < e.W) ray_scanline(a, e, v, s_tab, x, lane);
-    }
-    return min(e.W - it.x0, kRayWaves * spw);
-}
-
-// one PSF tile (TX scanlines x TY rows); lds sized by psf_lds_bytes
-template <int TX, int TY>
-__device__ void psf_tile(const PhysArgs& a, const ItemPsf it, float* lds)
-{
-    const EnvDev e = a.envs[it.env];
-    const int W = e.W, H = e.H, ra = e.rax, rl = e.rlat;
-    const int x0 = (it.tile & 0xFFFF) * TX;
-    const int y0 = (it.tile >> 16) * TY;
-    const int CW = TX + 2 * rl;          // staged scanlines (with lateral halo)
-    const int CH = TY + 2 * ra;          // staged rows (with axial halo)
-    const int AS = TY + 1;               // padded column stride of the axial result
-    float* sR = lds;
-    float* sT = sR + CW * CH;
-    float* aR = sT + CW * CH;
-    float* aT = aR + CW * AS;
-    float* sE = aT + CW * AS;
-    float* kax = sE + TX * AS;
-    float* klat = kax + 2 * kMaxPsfRadius + 1;
+    extern __shared__ float lds[];
+    __shared__ float s_klat[kTaps];
+    __shared__ int s_item;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    constexpr int kWaves = kThreads / kWave;
-
-    for (int i = tid; i <= 2 * ra; i += kThreads) kax[i] = a.coefs[e.kax + i];
-    for (int i = tid; i <= 2 * rl; i += kThreads) klat[i] = a.coefs[e.klat + i];
-    const float* gR = a.fR + e.scr_off;
-    const float* gT = a.fT + e.scr_off;
-    const float* gE = a.fE + e.scr_off;
-    for (int c = wave; c < CW; c += kWaves) {
-        const int gx = x0 - rl + c;
-        const bool xin = gx >= 0 && gx < W;
-        for (int r = lane; r < CH; r += kWave) {
-            const int gy = y0 - ra + r;
-            const bool in = xin && gy >= 0 && gy < H;
-            const int64_t off = (int64_t)gx * H + gy;
-            sR[c * CH + r] = in ? gR[off] : 0.f;
-            sT[c * CH + r] = in ? gT[off] : 0.f;
-        }
-    }
-    for (int c = wave; c < TX; c += kWaves) {
-        const int gx = x0 + c;
-        for (int r = lane; r < TY; r += kWave) {
-            const int gy = y0 + r;
-            sE[c * AS + r] = (gx < W && gy < H) ? gE[(int64_t)gx * H + gy] : 0.f;
-        }
-    }
-    __syncthreads();
-    // axial pass over every staged scanline
-    for (int c = wave; c < CW; c += kWaves) {
-        for (int r = lane; r < TY; r += kWave) {
-            const float* pr = sR + c * CH + r;
-            const float* pt = sT + c * CH + r;
-            float s1 = 0.f, s2 = 0.f;
-            for (int j = 0; j <= 2 * ra; ++j) {
-                s1 += kax[j] * pr[j];
-                s2 += kax[j] * pt[j];
-            }
-            aR[c * AS + r] = s1;
-            aT[c * AS + r] = s2;
-        }
-    }
-    __syncthreads();
-    // lateral pass, composition, log compression, row-major store
-    for (int idx = tid; idx < TX * TY; idx += kThreads) {
-        const int cx = idx % TX;
-        const int r = idx / TX;
-        const int x = x0 + cx, y = y0 + r;
-        if (x < W && y < H) {
-            float s1 = 0.f, s2 = 0.f;
-            for (int i = 0; i <= 2 * rl; ++i) {
-                s1 += klat[i] * aR[(cx + i) * AS + r];
-                s2 += klat[i] * aT[(cx + i) * AS + r];
-            }
-            const float I = s1 + sE[cx * AS + r] * s2;
-            float Y = 0.f;
-            if (I > 0.f) {
-                Y = 1.f + e.disp * log10f(I / e.E0);
-                Y = fminf(fmaxf(Y, 0.f), 1.f);
-            }
-            const int64_t k = e.out_off + (int64_t)y * W + x;
-            a.out[k] = Y;
-            if (a.dbg.intensity) a.dbg.intensity[k] = I;
-        }
-    }
-    __syncthreads();   // LDS is reused by the caller's next item
-}
-
-__global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a)
-{
-    __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
-    stage_table(a, s_tab);
-    __syncthreads();
-    if ((int)blockIdx.x < a.n_ray) ray_item(a, a.ray_items[blockIdx.x], s_tab);
-}
-
-template <int TX, int TY>
-__global__ __launch_bounds__(kThreads) void k_psf(PhysArgs a)
-{
-    extern __shared__ float lds[];
-    if ((int)blockIdx.x < a.n_psf) psf_tile<TX, TY>(a, a.psf_items[blockIdx.x], lds);
-}
-
-// Persistent batched kernel: ray items first, then PSF tiles.  A tile waits
-// until every scanline of its environment is finished; ray items never wait
-// and are all dequeued before any tile, so every wait ends.
-constexpr long long kSpinLimit = 1ll << 24;
-
-template <int TX, int TY>
-__global__ __launch_bounds__(kThreads) void k_persistent(PhysArgs a, QueueDev* q)
-{
-    extern __shared__ float lds[];
-    __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
-    __shared__ int s_item;
-    stage_table(a, s_tab);
-    const int total = a.n_ray + a.n_psf;
     for (;;) {
+        const int item = next_item(&q->next_psf, &s_item);
+        if (item >= a.n_psf) break;
+        const ItemPsf it = a.psf_items[item];
+        const EnvDev e = a.envs[it.env];
+        const int W = e.W, H = e.H, rl = e.rlat;
+        const int x0 = (it.tile & 0xFFFF) * TX;
+        const int y0 = (it.tile >> 16) * kTileRows;
+        const int CW = TX + 2 * rl;
+        float* sR = lds;
+        float* sT = sR + CW * kAS;
+        float* sE = sT + CW * kAS;
+        for (int i = tid; i <= 2 * rl; i += kThreads) s_klat[i] = a.coefs[e.klat + i];
+        const float* gR = a.fR + e.scr_off;
+        const float* gT = a.fT + e.scr_off;
+        const float* gE = a.fE + e.scr_off;
+        const int gy = y0 + lane;
+        const bool yin = gy < H;
+        for (int c = wave; c < CW; c += kWaves) {
+            const int gx = x0 - rl + c;
+            const bool in = yin && gx >= 0 && gx < W;
+            const int64_t off = (int64_t)gx * H + gy;
+            sR[c * kAS + lane] = in ? gR[off] : 0.f;
+            sT[c * kAS + lane] = in ? gT[off] : 0.f;
+        }
+        for (int c = wave; c < TX; c += kWaves) {
+            const int gx = x0 + c;
+            sE[c * kAS + lane] = (yin && gx < W) ? gE[(int64_t)gx * H + gy] : 0.f;
+        }
         __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(&q->next, 1);
-        __syncthreads();
-        const int item = s_item;
-        if (item >= total) break;
-        if (item < a.n_ray) {
-            const ItemRay it = a.ray_items[item];
-            const int n = ray_item(a, it, s_tab);
-            __threadfence();          // publish this wave's fields at device scope
-            __syncthreads();
-            if (threadIdx.x == 0) atomicAdd(&q->done[it.env], n);
-        } else {
-            const ItemPsf it = a.psf_items[item - a.n_ray];
-            if (threadIdx.x == 0) {
-                const int need = a.envs[it.env].W;
-                long long spins = 0;
-                while (__hip_atomic_load(&q->done[it.env], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                       need) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > kSpinLimit) {
-                        atomicAdd(&q->timeouts, 1);
-                        break;
-                    }
+        for (int idx = tid; idx < TX * kTileRows; idx += kThreads) {
+            const int cx = idx % TX;
+            const int r = idx / TX;
+            const int x = x0 + cx, y = y0 + r;
+            if (x < W && y < H) {
+                float s1 = 0.f, s2 = 0.f;
+                for (int i = 0; i <= 2 * rl; ++i) {
+                    s1 += s_klat[i] * sR[(cx + i) * kAS + r];
+                    s2 += s_klat[i] * sT[(cx + i) * kAS + r];
                 }
+                const float I = s1 + sE[cx * kAS + r] * s2;
+                float Y = 0.f;
+                if (I > 0.f) {
+                    Y = 1.f + e.disp * log10f(I / e.E0);
+                    Y = fminf(fmaxf(Y, 0.f), 1.f);
+                }
+                const int64_t k = e.out_off + (int64_t)y * W + x;
+                a.out[k] = Y;
+                if (a.dbg.intensity) a.dbg.intensity[k] = I;
             }
-            __syncthreads();
-            __threadfence();          // see other workgroups' fields
-            psf_tile<TX, TY>(a, it, lds);
         }
     }
 }
@@ -430,16 +432,14 @@ __global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses
     if (!ok) atomicAdd(&q->n_bad, 1);
 }
 
-__global__ void k_queue_reset(QueueDev* q, int n_envs)
+__global__ void k_queue_reset(QueueDev* q)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        q->next = 0;
+    if (threadIdx.x == 0) {
+        q->next_ray = 0;
+        q->next_psf = 0;
         q->n_bad = 0;
-        q->timeouts = 0;
         q->pad = 0;
     }
-    if (i < n_envs) q->done[i] = 0;
 }
 
 __global__ void k_max_label(const uint8_t* labels, int64_t n, int32_t* out)
@@ -451,67 +451,64 @@ __global__ void k_max_label(const uint8_t* labels, int64_t n, int32_t* out)
     if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
 }
 
-template <int TX, int TY>
-const void* persistent_fn()
+const void* psf_fn(int tx)
 {
-    return reinterpret_cast<const void*>(&k_persistent<TX, TY>);
+    if (tx == 16) return reinterpret_cast<const void*>(&k_psf<16>);
+    if (tx == 32) return reinterpret_cast<const void*>(&k_psf<32>);
+    if (tx == 64) return reinterpret_cast<const void*>(&k_psf<64>);
+    return nullptr;
+}
+
+int blocks_per_cu(const void* fn, size_t lds)
+{
+    int n = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kThreads, lds) != hipSuccess) return 0;
+    return n;
 }
 
 }  // namespace
 
-size_t psf_lds_bytes(int tx, int ty, int max_rax, int max_rlat)
+size_t psf_lds_bytes(int tx, int max_rlat)
 {
-    const size_t CW = tx + 2 * max_rlat, CH = ty + 2 * max_rax, AS = ty + 1;
-    return sizeof(float) * (2 * CW * CH + 2 * CW * AS + tx * AS + 2 * (2 * kMaxPsfRadius + 1));
+    return sizeof(float) * (size_t)kAS * (2 * (tx + 2 * max_rlat) + tx);
 }
 
-#define SG_TILE_SWITCH(TX_, TY_, CALL)                                        \
-    if (TX_ == 32 && TY_ == 32) { CALL(32, 32); }                             \
-    else if (TX_ == 64 && TY_ == 16) { CALL(64, 16); }                        \
-    else if (TX_ == 16 && TY_ == 64) { CALL(16, 64); }                        \
-    else if (TX_ == 64 && TY_ == 32) { CALL(64, 32); }                        \
-    else { return hipErrorInvalidValue; }
+bool psf_tile_supported(int tx) { return psf_fn(tx) != nullptr; }
 
-hipError_t launch_ray(const PhysArgs& a, hipStream_t s)
+int ray_grid(int n_cu)
+{
+    return blocks_per_cu(reinterpret_cast<const void*>(&k_ray), 0) * n_cu;
+}
+
+int psf_grid(int tx, int max_rlat, int n_cu)
+{
+    return blocks_per_cu(psf_fn(tx), psf_lds_bytes(tx, max_rlat)) * n_cu;
+}
+
+hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s)
 {
     if (a.n_ray <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ray, dim3(a.n_ray), dim3(kThreads), 0, s, a);
+    if (grid > a.n_ray) grid = a.n_ray;
+    if (grid < 1) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_ray, dim3(grid), dim3(kThreads), 0, s, a, q);
     return hipGetLastError();
 }
 
-hipError_t launch_psf(const PhysArgs& a, int tx, int ty, hipStream_t s)
+hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tx, int grid, hipStream_t s)
 {
     if (a.n_psf <= 0) return hipSuccess;
-    const size_t lds = psf_lds_bytes(tx, ty, a.max_rax, a.max_rlat);
-#define SG_LAUNCH_PSF(X, Y) hipLaunchKernelGGL((k_psf<X, Y>), dim3(a.n_psf), dim3(kThreads), lds, s, a)
-    SG_TILE_SWITCH(tx, ty, SG_LAUNCH_PSF)
-#undef SG_LAUNCH_PSF
+    if (grid > a.n_psf) grid = a.n_psf;
+    if (grid < 1) return hipErrorInvalidConfiguration;
+    const size_t lds = psf_lds_bytes(tx, a.max_rlat);
+    if (tx == 16)
+        hipLaunchKernelGGL(k_psf<16>, dim3(grid), dim3(kThreads), lds, s, a, q);
+    else if (tx == 32)
+        hipLaunchKernelGGL(k_psf<32>, dim3(grid), dim3(kThreads), lds, s, a, q);
+    else if (tx == 64)
+        hipLaunchKernelGGL(k_psf<64>, dim3(grid), dim3(kThreads), lds, s, a, q);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
-}
-
-hipError_t launch_persistent(const PhysArgs& a, QueueDev* q, int tx, int ty, int grid, hipStream_t s)
-{
-    const size_t lds = psf_lds_bytes(tx, ty, a.max_rax, a.max_rlat);
-#define SG_LAUNCH_PERS(X, Y) hipLaunchKernelGGL((k_persistent<X, Y>), dim3(grid), dim3(kThreads), lds, s, a, q)
-    SG_TILE_SWITCH(tx, ty, SG_LAUNCH_PERS)
-#undef SG_LAUNCH_PERS
-    return hipGetLastError();
-}
-
-int persistent_blocks_per_cu(int tx, int ty, int max_rax, int max_rlat)
-{
-    const size_t lds = psf_lds_bytes(tx, ty, max_rax, max_rlat);
-    int n = 0;
-    const void* fn = nullptr;
-#define SG_FN(X, Y) fn = persistent_fn<X, Y>()
-    if (tx == 32 && ty == 32) SG_FN(32, 32);
-    else if (tx == 64 && ty == 16) SG_FN(64, 16);
-    else if (tx == 16 && ty == 64) SG_FN(16, 64);
-    else if (tx == 64 && ty == 32) SG_FN(64, 32);
-    else return 0;
-#undef SG_FN
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kThreads, lds) != hipSuccess) return 0;
-    return n;
 }
 
 hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n, QueueDev* q,
@@ -522,10 +519,9 @@ hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses
     return hipGetLastError();
 }
 
-hipError_t launch_queue_reset(QueueDev* q, int32_t n_envs, hipStream_t s)
+hipError_t launch_queue_reset(QueueDev* q, hipStream_t s)
 {
-    const int n = n_envs > 1 ? n_envs : 1;
-    hipLaunchKernelGGL(k_queue_reset, dim3((n + 255) / 256), dim3(256), 0, s, q, n_envs);
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q);
     return hipGetLastError();
 }
 

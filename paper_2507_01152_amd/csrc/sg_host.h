@@ -42,7 +42,7 @@ struct HostVolume {
 
 struct LaunchShape {
     int spw = 1;      // scanlines per wave in a ray item
-    int tx = 32, ty = 32;
+    int tx = 32;      // PSF tile width (scanlines); tiles are 64 rows high
 };
 
 struct Plan {
@@ -56,7 +56,7 @@ struct Plan {
     int64_t n_pixels = 0;
     int max_rax = 0, max_rlat = 0;
     LaunchShape shape;
-    int grid = 0;
+    int grid_ray = 0, grid_psf = 0;
     DevBuf d_envs, d_pool, d_rays, d_tiles, d_poses, d_queue, fields;
     int32_t n_rays = 0, n_tiles = 0;
     hipGraph_t graph = nullptr;
@@ -79,7 +79,7 @@ struct sg_ctx {
     sg::DevBuf d_vols;
     sg::DevBuf table;
     int32_t n_labels = 0;
-    sg::DevBuf scan, params, fields;
+    sg::DevBuf scan, params, fields, queue;
     sg::PinnedBuf staging;
     std::map<int32_t, std::unique_ptr<sg::Plan>> plans;
     int32_t next_plan = 1;
@@ -94,7 +94,7 @@ int psf_taps(double sigma, std::vector<float>& pool, int32_t* offset);
 sg_status check_probe(const sg_probe& p, int idx);
 sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int64_t out_off, int64_t scr_off,
                           std::vector<float>& pool, EnvDev& e);
-void build_items(const std::vector<EnvDev>& envs, const std::vector<int>& order, int spw, int tx, int ty,
+void build_items(const std::vector<EnvDev>& envs, const std::vector<int>& order, int spw, int tx,
                  std::vector<ItemRay>& rays, std::vector<ItemPsf>& tiles);
 sg_status sync_volumes(sg_ctx* c);
 sg_status check_envs(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_probe* probes);

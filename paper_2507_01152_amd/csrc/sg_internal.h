@@ -76,16 +76,15 @@ struct PhysArgs {
     float* out;
     DebugDev dbg;
     int32_t scanlines_per_wave;   // ray group = kRayWaves * scanlines_per_wave
-    int32_t max_rax, max_rlat;    // sizing of the PSF tile's LDS
+    int32_t max_rlat;             // sizing of the PSF tile's LDS
 };
 
-// persistent-kernel queue state (device)
+// work-queue state of the two persistent kernels (device)
 struct QueueDev {
-    int32_t next;        // next work item
-    int32_t n_bad;       // envs with rejected poses
-    int32_t timeouts;    // dependency waits that gave up
+    int32_t next_ray;    // next ray work item
+    int32_t next_psf;    // next PSF tile
+    int32_t n_bad;       // envs with rejected poses (device geometry)
     int32_t pad;
-    int32_t done[1];     // [n_envs] finished scanlines per env (flexible)
 };
 
 // Plane geometry: the pose [R|t] (probe mm -> volume mm) places pixel (x, y)
@@ -137,15 +136,15 @@ __host__ __device__ inline int plane_geometry(const double* pose, double sx, dou
 }
 
 // launchers (physics.hip)
-hipError_t launch_ray(const PhysArgs& a, hipStream_t s);
-hipError_t launch_psf(const PhysArgs& a, int tile_x, int tile_y, hipStream_t s);
+hipError_t launch_queue_reset(QueueDev* q, hipStream_t s);
 hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n_envs,
                            QueueDev* q, hipStream_t s);
-hipError_t launch_queue_reset(QueueDev* q, int32_t n_envs, hipStream_t s);
-hipError_t launch_persistent(const PhysArgs& a, QueueDev* q, int tile_x, int tile_y, int grid,
-                             hipStream_t s);
-int persistent_blocks_per_cu(int tile_x, int tile_y, int max_rax, int max_rlat);
-size_t psf_lds_bytes(int tile_x, int tile_y, int max_rax, int max_rlat);
+hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s);
+hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tile_x, int grid, hipStream_t s);
 hipError_t launch_max_label(const uint8_t* labels, int64_t n, int32_t* d_out, hipStream_t s);
+size_t psf_lds_bytes(int tile_x, int max_rlat);
+bool psf_tile_supported(int tile_x);
+int ray_grid(int n_cu);                              // resident ray workgroups
+int psf_grid(int tile_x, int max_rlat, int n_cu);    // resident PSF workgroups
 
 }  // namespace sg

@@ -163,7 +163,7 @@ sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int64_t out_o
     return SG_OK;
 }
 
-void build_items(const std::vector<EnvDev>& envs, const std::vector<int>& order, int spw, int tx, int ty,
+void build_items(const std::vector<EnvDev>& envs, const std::vector<int>& order, int spw, int tx,
                  std::vector<ItemRay>& rays, std::vector<ItemPsf>& tiles)
 {
     rays.clear();
@@ -173,7 +173,7 @@ void build_items(const std::vector<EnvDev>& envs, const std::vector<int>& order,
         for (int x0 = 0; x0 < envs[e].W; x0 += group) rays.push_back(ItemRay{e, x0});
     }
     for (int e : order) {
-        const int nx = (envs[e].W + tx - 1) / tx, ny = (envs[e].H + ty - 1) / ty;
+        const int nx = (envs[e].W + tx - 1) / tx, ny = (envs[e].H + 63) / 64;
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) tiles.push_back(ItemPsf{e, (j << 16) | i});
     }
@@ -361,7 +361,7 @@ extern "C" sg_status sg_simulate(sg_ctx* c, int32_t n, const int32_t* vol_ids, c
     std::vector<EnvDev> envs(n);
     std::vector<float> pool;
     int64_t scr = 0;
-    int max_rax = 0, max_rlat = 0;
+    int max_rlat = 0;
     for (int i = 0; i < n; ++i) {
         for (int k = 0; k < 12; ++k)
             if (!std::isfinite(poses[12 * i + k])) return fail(SG_EINVAL, "env %d: pose is not finite", i);
@@ -374,17 +374,21 @@ extern "C" sg_status sg_simulate(sg_ctx* c, int32_t n, const int32_t* vol_ids, c
         if (!envs[i].valid)
             return fail(SG_ERANGE, "env %d: image plane outside the fixed-point range (|Q16| > 2^30)", i);
         scr += (int64_t)probes[i].W * probes[i].H;
-        max_rax = std::max(max_rax, envs[i].rax);
         max_rlat = std::max(max_rlat, envs[i].rlat);
     }
     s = sync_volumes(c);
     if (s != SG_OK) return s;
+    // longest scanlines first (ray items cost ~H), then wider frames
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (envs[a].H != envs[b].H) return envs[a].H > envs[b].H;
+        return envs[a].W > envs[b].W;
+    });
     std::vector<ItemRay> rays;
     std::vector<ItemPsf> tiles;
-    const int spw = 1, tx = 32, ty = 32;
-    build_items(envs, order, spw, tx, ty, rays, tiles);
+    const int spw = 1, tx = 32;
+    build_items(envs, order, spw, tx, rays, tiles);
 
     // one staging block: envs | taps | ray items | psf items
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -402,6 +406,7 @@ extern "C" sg_status sg_simulate(sg_ctx* c, int32_t n, const int32_t* vol_ids, c
     std::memcpy(h + o_psf, tiles.data(), sizeof(ItemPsf) * tiles.size());
     if ((e = c->params.ensure(total)) != hipSuccess) return hip_fail(e, "hipMalloc params");
     if ((e = c->fields.ensure(sizeof(float) * 3 * (size_t)scr)) != hipSuccess) return hip_fail(e, "hipMalloc scratch");
+    if ((e = c->queue.ensure(sizeof(QueueDev))) != hipSuccess) return hip_fail(e, "hipMalloc queue");
     e = hipMemcpyAsync(c->params.p, h, total, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->staging.ev, c->stream);
     if (e != hipSuccess) return hip_fail(e, "parameter upload");
@@ -430,9 +435,11 @@ extern "C" sg_status sg_simulate(sg_ctx* c, int32_t n, const int32_t* vol_ids, c
         a.dbg.intensity = dbg->intensity;
     }
     a.scanlines_per_wave = spw;
-    a.max_rax = max_rax;
     a.max_rlat = max_rlat;
-    if ((e = launch_ray(a, c->stream)) != hipSuccess) return hip_fail(e, "ray kernel launch");
-    if ((e = launch_psf(a, tx, ty, c->stream)) != hipSuccess) return hip_fail(e, "PSF kernel launch");
+    QueueDev* q = (QueueDev*)c->queue.p;
+    if ((e = launch_queue_reset(q, c->stream)) != hipSuccess) return hip_fail(e, "queue reset");
+    if ((e = launch_ray(a, q, ray_grid(c->n_cu), c->stream)) != hipSuccess) return hip_fail(e, "ray kernel launch");
+    if ((e = launch_psf(a, q, tx, psf_grid(tx, max_rlat, c->n_cu), c->stream)) != hipSuccess)
+        return hip_fail(e, "PSF kernel launch");
     return SG_OK;
 }

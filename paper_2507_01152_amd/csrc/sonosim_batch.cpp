@@ -26,7 +26,7 @@ namespace {
 // Candidate launch shapes: every one yields bit-identical frames (the
 // per-pixel arithmetic and summation order do not depend on the tiling).
 const LaunchShape kShapes[] = {
-    {1, 32, 32}, {2, 32, 32}, {1, 64, 16}, {2, 64, 16}, {1, 16, 64}, {1, 64, 32}, {2, 64, 32},
+    {1, 32}, {2, 32}, {1, 64}, {2, 64}, {1, 16}, {4, 32},
 };
 
 Plan* find_plan(sg_ctx* c, int32_t id)
@@ -48,9 +48,9 @@ sg_status apply_shape(sg_ctx* c, Plan* p, const LaunchShape& s)
 {
     std::vector<ItemRay> rays;
     std::vector<ItemPsf> tiles;
-    build_items(p->envs, p->order, s.spw, s.tx, s.ty, rays, tiles);
-    const int per_cu = persistent_blocks_per_cu(s.tx, s.ty, p->max_rax, p->max_rlat);
-    if (per_cu < 1) return fail(SG_EINVAL, "launch shape %dx%d does not fit a compute unit", s.tx, s.ty);
+    build_items(p->envs, p->order, s.spw, s.tx, rays, tiles);
+    const int gr = ray_grid(c->n_cu), gp = psf_grid(s.tx, p->max_rlat, c->n_cu);
+    if (gr < 1 || gp < 1) return fail(SG_EINVAL, "launch shape (tile %d) does not fit a compute unit", s.tx);
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = p->d_rays.ensure(sizeof(ItemRay) * std::max<size_t>(rays.size(), 1));
     if (e == hipSuccess) e = p->d_tiles.ensure(sizeof(ItemPsf) * std::max<size_t>(tiles.size(), 1));
@@ -62,7 +62,8 @@ sg_status apply_shape(sg_ctx* c, Plan* p, const LaunchShape& s)
     p->n_rays = (int32_t)rays.size();
     p->n_tiles = (int32_t)tiles.size();
     p->shape = s;
-    p->grid = per_cu * c->n_cu;
+    p->grid_ray = gr;
+    p->grid_psf = gp;
     drop_graph(p);
     return SG_OK;
 }
@@ -85,27 +86,28 @@ PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
     a.fE = a.fT + p->n_pixels;
     a.out = out;
     a.scanlines_per_wave = p->shape.spw;
-    a.max_rax = p->max_rax;
     a.max_rlat = p->max_rlat;
     return a;
 }
 
-// enqueue one step's kernels (reset, geometry, persistent) on stream s
-hipError_t enqueue_step(sg_ctx* c, Plan* p, float* out, hipStream_t s)
+// enqueue one step's kernels (queue reset, device geometry, persistent ray
+// kernel, persistent PSF kernel) on stream s; optional events around the
+// ray and PSF kernels
+hipError_t enqueue_step(sg_ctx* c, Plan* p, float* out, hipStream_t s, hipEvent_t* ev = nullptr)
 {
     QueueDev* q = (QueueDev*)p->d_queue.p;
-    hipError_t e = launch_queue_reset(q, p->n_envs, s);
+    const PhysArgs a = plan_args(c, p, out);
+    hipError_t e = launch_queue_reset(q, s);
     if (e == hipSuccess)
         e = launch_geometry((EnvDev*)p->d_envs.p, (const VolDev*)c->d_vols.p, (const double*)p->d_poses.p,
                             p->n_envs, q, s);
-    if (e == hipSuccess) e = launch_persistent(plan_args(c, p, out), q, p->shape.tx, p->shape.ty, p->grid, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = launch_ray(a, q, p->grid_ray, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = launch_psf(a, q, p->shape.tx, p->grid_psf, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
     return e;
 }
-
-struct CaptureKey {
-    const void* vols;
-    int32_t n_labels;
-};
 
 sg_status capture(sg_ctx* c, Plan* p, float* out)
 {
@@ -167,7 +169,7 @@ bool cache_lookup(const char* path, const std::string& key, LaunchShape* s)
         if (q && x && y && std::sscanf(q, "\"spw\": %d", &spw) == 1 && std::sscanf(x, "\"tx\": %d", &tx) == 1 &&
             std::sscanf(y, "\"ty\": %d", &ty) == 1) {
             for (const LaunchShape& k : kShapes)
-                if (k.spw == spw && k.tx == tx && k.ty == ty) {
+                if (k.spw == spw && k.tx == tx && ty == 64) {
                     *s = k;
                     found = true;   // keep the last matching line
                 }
@@ -214,7 +216,7 @@ extern "C" sg_status sg_batch_plan_create(sg_ctx* c, int32_t n, const int32_t* v
     hipError_t e = p->d_envs.ensure(sizeof(EnvDev) * n);
     if (e == hipSuccess) e = p->d_pool.ensure(sizeof(float) * p->pool.size());
     if (e == hipSuccess) e = p->d_poses.ensure(sizeof(double) * 12 * n);
-    if (e == hipSuccess) e = p->d_queue.ensure(sizeof(QueueDev) + sizeof(int32_t) * n);
+    if (e == hipSuccess) e = p->d_queue.ensure(sizeof(QueueDev));
     if (e == hipSuccess) e = p->fields.ensure(sizeof(float) * 3 * (size_t)p->n_pixels);
     if (e != hipSuccess) return hip_fail(e, "plan allocation");
     e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice);
@@ -263,28 +265,22 @@ static sg_status step_checks(sg_ctx* c, Plan* p)
     return sync_volumes(c);
 }
 
-extern "C" sg_status sg_batch_step_profiled(sg_ctx* c, int32_t id, float* out, float* ms)
+extern "C" sg_status sg_batch_step_profiled(sg_ctx* c, int32_t id, float* out, float* ms_ray, float* ms_psf)
 {
     Plan* p = c ? find_plan(c, id) : nullptr;
-    if (!p || !out || !ms) return fail(SG_EINVAL, "sg_batch_step_profiled: bad plan id or NULL");
+    if (!p || !out || !ms_ray || !ms_psf) return fail(SG_EINVAL, "sg_batch_step_profiled: bad plan id or NULL");
     (void)hipSetDevice(c->device);
     sg_status s = step_checks(c, p);
     if (s != SG_OK) return s;
-    QueueDev* q = (QueueDev*)p->d_queue.p;
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    hipError_t e = hipEventCreate(&t0);
-    if (e == hipSuccess) e = hipEventCreate(&t1);
-    if (e == hipSuccess) e = launch_queue_reset(q, p->n_envs, c->stream);
-    if (e == hipSuccess)
-        e = launch_geometry((EnvDev*)p->d_envs.p, (const VolDev*)c->d_vols.p, (const double*)p->d_poses.p,
-                            p->n_envs, q, c->stream);
-    if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
-    if (e == hipSuccess) e = launch_persistent(plan_args(c, p, out), q, p->shape.tx, p->shape.ty, p->grid, c->stream);
-    if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(t1);
-    if (e == hipSuccess) e = hipEventElapsedTime(ms, t0, t1);
-    if (t0) (void)hipEventDestroy(t0);
-    if (t1) (void)hipEventDestroy(t1);
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    if (e == hipSuccess) e = enqueue_step(c, p, out, c->stream, ev);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms_ray, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms_psf, ev[1], ev[2]);
+    for (int i = 0; i < 3; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
     return e == hipSuccess ? SG_OK : hip_fail(e, "profiled step");
 }
 
@@ -310,10 +306,9 @@ extern "C" sg_status sg_batch_status(sg_ctx* c, int32_t id, int32_t* n_bad)
     (void)hipSetDevice(c->device);
     QueueDev q;
     hipError_t e = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess) e = hipMemcpy(&q, p->d_queue.p, sizeof(QueueDev) - sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&q, p->d_queue.p, sizeof(QueueDev), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "status readback");
     *n_bad = q.n_bad;
-    if (q.timeouts) return fail(SG_EHIP, "persistent kernel: %d dependency waits timed out", q.timeouts);
     return SG_OK;
 }
 
@@ -323,7 +318,7 @@ extern "C" sg_status sg_batch_config(sg_ctx* c, int32_t id, int32_t* spw, int32_
     if (!p || !spw || !tx || !ty) return fail(SG_EINVAL, "sg_batch_config: bad plan id or NULL");
     *spw = p->shape.spw * kRayWaves;
     *tx = p->shape.tx;
-    *ty = p->shape.ty;
+    *ty = 64;
     return SG_OK;
 }
 
@@ -386,7 +381,7 @@ extern "C" sg_status sg_autotune(sg_ctx* c, int32_t id, const char* cache_path)
         std::ofstream f(cache_path, std::ios::app);
         if (f)
             f << "{\"key\": \"" << key << "\", \"spw\": " << best.spw << ", \"tx\": " << best.tx
-              << ", \"ty\": " << best.ty << ", \"us\": " << best_us << "}\n";
+              << ", \"ty\": 64, \"us\": " << best_us << "}\n";
     }
     return SG_OK;
 }

@@ -83,7 +83,7 @@ def load():
         "sg_batch_poses": [VP, I32, P(VP)],
         "sg_batch_set_poses": [VP, I32, VP],
         "sg_batch_step": [VP, I32, VP],
-        "sg_batch_step_profiled": [VP, I32, VP, P(C.c_float)],
+        "sg_batch_step_profiled": [VP, I32, VP, P(C.c_float), P(C.c_float)],
         "sg_batch_status": [VP, I32, P(I32)],
         "sg_autotune": [VP, I32, C.c_char_p],
         "sg_batch_config": [VP, I32, P(I32), P(I32), P(I32)],
@@ -218,11 +218,12 @@ def sg_batch_set_poses(ctx, plan_id: int, poses):
     _check(load().sg_batch_set_poses(ctx, int(plan_id), ps.ctypes.data), "sg_batch_set_poses")
 
 
-def sg_batch_step_profiled(ctx, plan_id: int, out) -> float:
-    """One eager step; returns the persistent kernel's duration in ms."""
-    ms = C.c_float()
-    _check(load().sg_batch_step_profiled(ctx, int(plan_id), _dptr(out), C.byref(ms)), "sg_batch_step_profiled")
-    return float(ms.value)
+def sg_batch_step_profiled(ctx, plan_id: int, out):
+    """One eager step; returns (ray kernel ms, PSF kernel ms)."""
+    a, b = C.c_float(), C.c_float()
+    _check(load().sg_batch_step_profiled(ctx, int(plan_id), _dptr(out), C.byref(a), C.byref(b)),
+           "sg_batch_step_profiled")
+    return float(a.value), float(b.value)
 
 
 def sg_batch_step(ctx, plan_id: int, out):

@@ -98,7 +98,7 @@ def test_autotune_keeps_frames_bit_identical(sess, uneven, tmp_path):
     cache = str(tmp_path / "tune.jsonl")
     sg.sg_autotune(sess.ctx, plan, cache)
     spw, tx, ty = sg.sg_batch_config(sess.ctx, plan)
-    assert spw in (4, 8) and (tx, ty) in [(32, 32), (64, 16), (16, 64), (64, 32)]
+    assert spw in (4, 8, 16) and tx in (16, 32, 64) and ty == 64
     out2, _ = batch_frames(sess, uneven, vids, plan=plan)
     assert torch.equal(out, out2)
     text = open(cache).read()
@@ -108,8 +108,8 @@ def test_autotune_keeps_frames_bit_identical(sess, uneven, tmp_path):
     sg.sg_autotune(sess.ctx, plan2, cache)
     assert sg.sg_batch_config(sess.ctx, plan2) == (spw, tx, ty)
     assert open(cache).read() == text
-    ms = sg.sg_batch_step_profiled(sess.ctx, plan2, out3)
-    assert ms > 0 and torch.equal(out, out3)
+    ms_ray, ms_psf = sg.sg_batch_step_profiled(sess.ctx, plan2, out3)
+    assert ms_ray > 0 and ms_psf > 0 and torch.equal(out, out3)
 
 
 def test_out_of_range_pose_gives_zero_frame_and_status(sess):
