@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--profile-launches", type=int, default=20)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the environments shard "
@@ -167,6 +169,13 @@ def main():
                       f"OpenMP over envs, {dt:.1f} s wall",
         }
         res["gpu_vs_cpu"] = round(fps / res["cpu_baseline"]["value"], 1)
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=sess.device)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = src.numel() * 4
     sess.close()
     print(json.dumps(res))
 

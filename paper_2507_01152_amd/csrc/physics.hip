@@ -10,7 +10,8 @@
 //                  (remaining energy E), per-voxel scatterer (Philox4x32-10
 //                  keyed by voxel index, Box-Muller, density gate), the
 //                  reflection source R' = G*E*cos(theta)*|r|.  R' and T go
-//                  into a per-wave LDS ring of four chunks, and the axial
+//                  into a per-wave LDS ring of four chunks (the first two
+//                  mirrored past its end so filter windows never wrap), and the axial
 //                  Gaussian is applied one chunk behind.  The axially filtered
 //                  fields and E are written scanline-major, coalesced along
 //                  the scanline.  The next chunk's labels are gathered one
@@ -31,6 +32,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kRing = 4 * kWave;         // rows held per wave in the axial ring (power of two)
+constexpr int kRingAlloc = kRing + 2 * kWave;   // + mirror of the first two chunks: windows never wrap
 constexpr int kTaps = 2 * kMaxPsfRadius + 1;
 constexpr int kTileRows = 64;            // PSF tile height
 constexpr int kAS = kTileRows + 1;       // padded LDS column stride
@@ -46,16 +48,15 @@ __device__ __forceinline__ void philox4x32_10(uint32_t n_lo, uint32_t k0, uint32
     uint32_t c0 = n_lo, c1 = 0u, c2 = 0u, c3 = 0u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(kPhM0, c0);
-        const uint32_t lo0 = kPhM0 * c0;
-        const uint32_t hi1 = __umulhi(kPhM1, c2);
-        const uint32_t lo1 = kPhM1 * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // one 32x32->64 multiply-add instruction per product
+        const uint64_t p0 = (uint64_t)kPhM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhM1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (uint32_t)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (uint32_t)p0;
         k0 += kPhW0;
         k1 += kPhW1;
     }
@@ -123,20 +124,54 @@ __device__ __forceinline__ double z_from_ct(const EnvDev& e, const VolDev& v, in
     return z > 0.0 ? z : 0.0;
 }
 
-// cos(theta): Sobel (1,2,1) on [label differs from the centre label] with
-// clamped image coordinates, in physical units (only evaluated at G = 1)
-__device__ __forceinline__ float incidence_cos(const EnvDev& e, const VolDev& v, int x, int y, int lab)
+// nearest voxel index at Q16 position q, -1 outside the grid
+__device__ __forceinline__ int32_t voxel_at_q(const VolDev& v, const int32_t q[3])
 {
+    const int32_t ix = (int32_t)((uint32_t)q[0] + 32768u) >> 16;
+    const int32_t iy = (int32_t)((uint32_t)q[1] + 32768u) >> 16;
+    const int32_t iz = (int32_t)((uint32_t)q[2] + 32768u) >> 16;
+    const bool in = (uint32_t)ix < (uint32_t)v.nx && (uint32_t)iy < (uint32_t)v.ny &&
+                    (uint32_t)iz < (uint32_t)v.nz;
+    return in ? (iz * v.ny + iy) * v.nx + ix : -1;
+}
+
+// label at Q16 position q (nearest voxel, air outside)
+__device__ __forceinline__ int label_at_q(const VolDev& v, int32_t q0, int32_t q1, int32_t q2)
+{
+    const int32_t ix = (int32_t)((uint32_t)q0 + 32768u) >> 16;
+    const int32_t iy = (int32_t)((uint32_t)q1 + 32768u) >> 16;
+    const int32_t iz = (int32_t)((uint32_t)q2 + 32768u) >> 16;
+    const bool in = (uint32_t)ix < (uint32_t)v.nx && (uint32_t)iy < (uint32_t)v.ny &&
+                    (uint32_t)iz < (uint32_t)v.nz;
+    return in ? (int)v.labels[(iz * v.ny + iy) * v.nx + ix] : 0;
+}
+
+// cos(theta): Sobel (1,2,1) on [label differs from the centre label] with
+// clamped image coordinates, in physical units (only evaluated at G = 1).
+// q: Q16 position of (x, y); lab_up / lab_dn: labels of (x, y-1) / (x, y+1)
+// (already clamped); side columns are stepped from q by +-DX, +-DY.
+__device__ __forceinline__ float incidence_cos(const EnvDev& e, const VolDev& v, const int32_t q[3], int x, int y,
+                                              int lab, int lab_up, int lab_dn)
+{
+    const int xl = x > 0 ? -1 : 0, xr = x < e.W - 1 ? 1 : 0;
+    const int yu = y > 0 ? -1 : 0, yd = y < e.H - 1 ? 1 : 0;
     int b[3][3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
+        const int yo = j == 0 ? yu : (j == 1 ? 0 : yd);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const int xx = min(max(x + i - 1, 0), e.W - 1);
-            const int yy = min(max(y + j - 1, 0), e.H - 1);
-            b[j][i] = label_of(v, voxel_at(e, v, xx, yy)) != lab;
+        for (int i = 0; i < 3; i += 2) {
+            const int xo = i == 0 ? xl : xr;
+            int32_t p[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                p[c] = (int32_t)((uint32_t)q[c] + (uint32_t)(xo * e.DX[c]) + (uint32_t)(yo * e.DY[c]));
+            b[j][i] = label_at_q(v, p[0], p[1], p[2]) != lab;
         }
     }
+    b[0][1] = lab_up != lab;
+    b[1][1] = 0;
+    b[2][1] = lab_dn != lab;
     float gx = (float)((b[0][2] - b[0][0]) + 2 * (b[1][2] - b[1][0]) + (b[2][2] - b[2][0]));
     float gy = (float)((b[2][0] - b[0][0]) + 2 * (b[2][1] - b[0][1]) + (b[2][2] - b[0][2]));
     gx = gx / e.dx;
@@ -151,6 +186,78 @@ __device__ __forceinline__ float uniform24(uint32_t w)
     return (float)((w >> 9) * 2u + 1u) * 0x1p-24f;
 }
 
+// ---- wave64 data movement on DPP (GFX9 controls) -----------------------
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+constexpr int kWaveShl1 = 0x130;   // lane i reads lane i + 1
+constexpr int kWaveShr1 = 0x138;   // lane i reads lane i - 1
+
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_f(float old, float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ int dpp_i(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_d(double old, double v)
+{
+    const uint64_t o = __double_as_longlong(old), x = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)x, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(x >> 32), CTRL,
+                                                              ROWS, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// inclusive scans over the 64 lanes (rows of 16 by row shifts, then the
+// row totals by row broadcasts)
+__device__ __forceinline__ float wave_scan_mul(float v)
+{
+    v *= dpp_f<kRowShr1>(1.f, v);
+    v *= dpp_f<kRowShr2>(1.f, v);
+    v *= dpp_f<kRowShr4>(1.f, v);
+    v *= dpp_f<kRowShr8>(1.f, v);
+    v *= dpp_f<kRowBcast15, 0xa>(1.f, v);
+    v *= dpp_f<kRowBcast31, 0xc>(1.f, v);
+    return v;
+}
+
+__device__ __forceinline__ double wave_scan_add(double v)
+{
+    v += dpp_d<kRowShr1>(0.0, v);
+    v += dpp_d<kRowShr2>(0.0, v);
+    v += dpp_d<kRowShr4>(0.0, v);
+    v += dpp_d<kRowShr8>(0.0, v);
+    v += dpp_d<kRowBcast15, 0xa>(0.0, v);
+    v += dpp_d<kRowBcast31, 0xc>(0.0, v);
+    return v;
+}
+
+__device__ __forceinline__ float lane_f(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ double lane_d(double v, int lane)
+{
+    const uint64_t x = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// store the pair for ring slot `slot` (< kRing) and its mirror
+__device__ __forceinline__ void ring_put(float2* ring, int slot, float2 f)
+{
+    ring[slot] = f;
+    if (slot < kRingAlloc - kRing) ring[slot + kRing] = f;
+}
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     // order this wave's LDS writes before its later LDS reads (LDS executes
@@ -160,16 +267,19 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Axial filter of one chunk from the ring: lane l outputs row y0 + l.
-__device__ __forceinline__ void axial_from_ring(const float* ringR, const float* ringT, const float* kax, int ra,
-                                                int y0, int lane, float& aR, float& aT)
+// Axial filter of one chunk from the ring of (R', T) pairs: lane l outputs
+// row y0 + l.
+__device__ __forceinline__ void axial_from_ring(const float2* ring, const float* kax, int ra, int y0, int lane,
+                                                float& aR, float& aT)
 {
     float s1 = 0.f, s2 = 0.f;
-    const int base = y0 + lane - ra + kRing;   // >= kWave - ra > 0
+    // rows y0 + lane - ra + j live at slot ((y0 - ra) mod kRing) + lane + j < kRingAlloc
+    const float2* p = ring + ((y0 - ra + kRing) & (kRing - 1)) + lane;
+#pragma unroll 8
     for (int j = 0; j <= 2 * ra; ++j) {
-        const int slot = (base + j) & (kRing - 1);
-        s1 += kax[j] * ringR[slot];
-        s2 += kax[j] * ringT[slot];
+        const float2 f = p[j];
+        s1 += kax[j] * f.x;
+        s2 += kax[j] * f.y;
     }
     aR = s1;
     aT = s2;
@@ -177,7 +287,7 @@ __device__ __forceinline__ void axial_from_ring(const float* ringR, const float*
 
 // One scanline of the ray pass, executed by one wave (lane = depth row).
 __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v, const TissueDev* tab,
-                             const float* kax, float* ringR, float* ringT, int x, int lane)
+                             const float* kax, float2* ring, int x, int lane)
 {
     const int H = e.H;
     float* fR = a.fR + e.scr_off + (int64_t)x * H;
@@ -194,8 +304,7 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
     const bool ct = v.ct != nullptr;
     const int ra = e.rax;
     // rows -64..-1 of the ring read as zeros (zero padding above the image)
-    ringR[kRing - kWave + lane] = 0.f;
-    ringT[kRing - kWave + lane] = 0.f;
+    ring_put(ring, kRing - kWave + lane, make_float2(0.f, 0.f));
 
     float carry_t = 1.f;     // transmission product of the rows above the chunk
     double carry_a = 0.0;    // attenuation integral (sum of alpha) above the chunk
@@ -204,6 +313,10 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
     int32_t vox = voxel_at(e, v, x, lane);
     int lab = label_of(v, vox);
     double Z = ct ? z_from_ct(e, v, x, lane) : 0.0;
+    int32_t q[3];    // Q16 position of (x, y0 + lane)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[c] = q16(e.P0[c], e.DX[c], e.DY[c], x, lane);
+    int lab_last_prev = 0;   // label of row y0 - 1 (previous chunk's last row)
 
     const int n_chunks = (H + kWave - 1) / kWave;
     for (int k = 0; k < n_chunks; ++k) {
@@ -211,28 +324,30 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         const int y = y0 + lane;
         const bool act = y < H;
         // gather the next chunk's labels (and CT) ahead of use
-        const int32_t vox_n = voxel_at(e, v, x, y + kWave);
+        int32_t qn[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) qn[c] = (int32_t)((uint32_t)q[c] + (uint32_t)e.DY[c] * (uint32_t)kWave);
+        const int32_t vox_n = voxel_at_q(v, qn);
         const int lab_n = label_of(v, vox_n);
         const double Zct_n = ct ? z_from_ct(e, v, x, y + kWave) : 0.0;
 
-        // scatterer of this chunk's voxels (computed for every lane, selected below)
+        // scatterer of this chunk's voxels (computed for every lane, selected below):
+        // N0 = sqrt(-2 ln u0) cos(2 pi u1) with hardware log2 / sqrt / cos(2 pi x)
         uint32_t w[4];
         philox4x32_10((uint32_t)vox, v.key0, v.key1, w);
         const TissueDev tt = tab[lab];
-        const float n0 = sqrtf(-2.f * logf(uniform24(w[0]))) * cospif(2.f * uniform24(w[1]));
+        const float m2ln = __builtin_amdgcn_logf(uniform24(w[0])) * -1.3862943611198906f;   // -2 ln 2
+        const float n0 = __builtin_amdgcn_sqrtf(m2ln) * __builtin_amdgcn_cosf(uniform24(w[1]));
         const bool inside = act && vox >= 0;
         const float T = (inside && (unsigned long long)w[2] < tt.thr) ? n0 * tt.sigma0 + tt.mu0 : 0.f;
 
-        // boundary with the next row
+        // boundary with the next row: lane i + 1, or the next chunk's first row
         const double Zc = ct ? Z : (double)tt.Z;
-        int lab_nr = __shfl_down(lab, 1);
-        double Z_nr = __shfl_down(Zc, 1);
-        const int lab_first_n = __shfl(lab_n, 0);
-        const double Z_first_n = __shfl(ct ? Zct_n : (double)tab[lab_n].Z, 0);
-        if (lane == kWave - 1) {
-            lab_nr = lab_first_n;
-            Z_nr = Z_first_n;
-        }
+        const int lab_first_n = __builtin_amdgcn_readlane(lab_n, 0);
+        const double Z_first_n = ct ? lane_d(Zct_n, 0) : (double)tab[lab_first_n].Z;
+        const int lab_nr = dpp_i<kWaveShl1>(lab_first_n, lab);
+        const int lab_pr = dpp_i<kWaveShr1>(y0 > 0 ? lab_last_prev : lab, lab);   // row y - 1 (clamped)
+        const double Z_nr = dpp_d<kWaveShl1>(Z_first_n, Zc);
         const bool G = act && (y < H - 1) && (lab != lab_nr);
         float r = 0.f, t = 1.f;
         if (G && Zc != Z_nr) {
@@ -245,39 +360,27 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
                 t = (float)((2.0 * Zc / s) * (2.0 * Z_nr / s));
             }
         }
-        // inclusive wave scans: transmission product (FP32), alpha sum (FP64)
-        float tp = act ? t : 1.f;
-        double as = act ? (double)tt.alpha : 0.0;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const float o = __shfl_up(tp, d);
-            const double oa = __shfl_up(as, d);
-            if (lane >= d) {
-                tp *= o;
-                as += oa;
-            }
-        }
-        float t_ex = __shfl_up(tp, 1);
-        double a_ex = __shfl_up(as, 1);
-        if (lane == 0) {
-            t_ex = 1.f;
-            a_ex = 0.0;
-        }
-        const float E = e.E0 * (carry_t * t_ex) * expf((float)(-e.coef * (carry_a + a_ex)));
-        carry_t *= __shfl(tp, kWave - 1);
-        carry_a += __shfl(as, kWave - 1);
+        // inclusive wave scans (FP32 transmission product, FP64 alpha sum),
+        // shifted by one lane for the exclusive prefix
+        const float tp = wave_scan_mul(act ? t : 1.f);
+        const double as = wave_scan_add(act ? (double)tt.alpha : 0.0);
+        const float t_ex = dpp_f<kWaveShr1>(1.f, tp);
+        const double a_ex = dpp_d<kWaveShr1>(0.0, as);
+        // E = E0 * prod(t) * exp(-f dy alpha-integral), as 2^(-coef2 * sum)
+        const float E = e.E0 * (carry_t * t_ex) * __builtin_amdgcn_exp2f((float)(-e.coef2 * (carry_a + a_ex)));
+        carry_t *= lane_f(tp, kWave - 1);
+        carry_a += lane_d(as, kWave - 1);
 
         float cs = 1.f;
-        if (G) cs = incidence_cos(e, v, x, y, lab);
+        if (G) cs = incidence_cos(e, v, q, x, y, lab, y > 0 ? lab_pr : lab, lab_nr);
         const float Rp = G ? E * cs * fabsf(r) : 0.f;
 
         // ring slot of this chunk, then the axial filter of the previous chunk
-        ringR[(y0 & (kRing - 1)) + lane] = act ? Rp : 0.f;
-        ringT[(y0 & (kRing - 1)) + lane] = act ? T : 0.f;
+        ring_put(ring, (y0 & (kRing - 1)) + lane, act ? make_float2(Rp, T) : make_float2(0.f, 0.f));
         wave_sync_lds();
         if (k > 0) {
             float aR, aT;
-            axial_from_ring(ringR, ringT, kax, ra, y0 - kWave, lane, aR, aT);
+            axial_from_ring(ring, kax, ra, y0 - kWave, lane, aR, aT);
             const int yp = y0 - kWave + lane;   // < H
             fR[yp] = aR;
             fT[yp] = aT;
@@ -298,18 +401,20 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
                 reinterpret_cast<uint4*>(a.dbg.philox)[kk] = pw;
             }
         }
+        lab_last_prev = __builtin_amdgcn_readlane(lab, kWave - 1);
         vox = vox_n;
         lab = lab_n;
         Z = Zct_n;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) q[c] = qn[c];
         wave_sync_lds();
     }
     // flush: rows below the image read as zeros
     const int y_last = (n_chunks - 1) * kWave;
-    ringR[((y_last + kWave) & (kRing - 1)) + lane] = 0.f;
-    ringT[((y_last + kWave) & (kRing - 1)) + lane] = 0.f;
+    ring_put(ring, ((y_last + kWave) & (kRing - 1)) + lane, make_float2(0.f, 0.f));
     wave_sync_lds();
     float aR, aT;
-    axial_from_ring(ringR, ringT, kax, ra, y_last, lane, aR, aT);
+    axial_from_ring(ring, kax, ra, y_last, lane, aR, aT);
     if (y_last + lane < H) {
         fR[y_last + lane] = aR;
         fT[y_last + lane] = aT;
@@ -331,7 +436,7 @@ __global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a, QueueDev* q)
 {
     __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
     __shared__ float s_kax[kTaps];
-    __shared__ float s_ring[kWaves][2][kRing];
+    __shared__ float2 s_ring[kWaves][kRingAlloc];
     __shared__ int s_item;
     for (int i = threadIdx.x; i < a.n_labels; i += kThreads) s_tab[i] = a.table[i];
     const int lane = threadIdx.x & (kWave - 1);
@@ -346,7 +451,7 @@ __global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a, QueueDev* q)
         __syncthreads();
         for (int s = 0; s < a.scanlines_per_wave; ++s) {
             const int x = it.x0 + s * kWaves + wave;
-            if (x < e.W) ray_scanline(a, e, v, s_tab, s_kax, s_ring[wave][0], s_ring[wave][1], x, lane);
+            if (x < e.W) ray_scanline(a, e, v, s_tab, s_kax, s_ring[wave], x, lane);
         }
     }
 }
@@ -379,16 +484,38 @@ __global__ __launch_bounds__(kThreads) void k_psf(PhysArgs a, QueueDev* q)
         const float* gE = a.fE + e.scr_off;
         const int gy = y0 + lane;
         const bool yin = gy < H;
-        for (int c = wave; c < CW; c += kWaves) {
-            const int gx = x0 - rl + c;
-            const bool in = yin && gx >= 0 && gx < W;
-            const int64_t off = (int64_t)gx * H + gy;
-            sR[c * kAS + lane] = in ? gR[off] : 0.f;
-            sT[c * kAS + lane] = in ? gT[off] : 0.f;
+        constexpr int kU = 4;   // columns in flight per wave
+        for (int c0 = wave; c0 < CW; c0 += kWaves * kU) {
+            float vr[kU], vt[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int c = c0 + u * kWaves;
+                const int gx = x0 - rl + c;
+                const bool in = yin && c < CW && gx >= 0 && gx < W;
+                const int64_t off = in ? (int64_t)gx * H + gy : 0;
+                vr[u] = in ? gR[off] : 0.f;
+                vt[u] = in ? gT[off] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int c = c0 + u * kWaves;
+                if (c < CW) {
+                    sR[c * kAS + lane] = vr[u];
+                    sT[c * kAS + lane] = vt[u];
+                }
+            }
         }
-        for (int c = wave; c < TX; c += kWaves) {
-            const int gx = x0 + c;
-            sE[c * kAS + lane] = (yin && gx < W) ? gE[(int64_t)gx * H + gy] : 0.f;
+        for (int c0 = wave; c0 < TX; c0 += kWaves * kU) {
+            float ve[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int gx = x0 + c0 + u * kWaves;
+                const bool in = yin && c0 + u * kWaves < TX && gx < W;
+                ve[u] = in ? gE[(int64_t)gx * H + gy] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (c0 + u * kWaves < TX) sE[(c0 + u * kWaves) * kAS + lane] = ve[u];
         }
         __syncthreads();
         for (int idx = tid; idx < TX * kTileRows; idx += kThreads) {
@@ -404,7 +531,8 @@ __global__ __launch_bounds__(kThreads) void k_psf(PhysArgs a, QueueDev* q)
                 const float I = s1 + sE[cx * kAS + r] * s2;
                 float Y = 0.f;
                 if (I > 0.f) {
-                    Y = 1.f + e.disp * log10f(I / e.E0);
+                    // (20 / DR) log10(I / E0) as disp2 * log2(I * (1 / E0))
+                    Y = 1.f + e.disp2 * __builtin_amdgcn_logf(I * e.inv_E0);
                     Y = fminf(fmaxf(Y, 0.f), 1.f);
                 }
                 const int64_t k = e.out_off + (int64_t)y * W + x;

@@ -41,8 +41,10 @@ struct EnvDev {
     float E0;
     float dx, dy;                  // pixel pitch, mm (incidence angle)
     float disp;                    // 20 / DR
+    float disp2;                   // (20 / DR) * log10(2): display slope per octave
     float inv_E0;
     double coef;                   // f * dy_cm
+    double coef2;                  // f * dy_cm * log2(e): attenuation in octaves
     double dx64, dy64, f64;        // for device-side geometry
     double psf64;
     int64_t out_off;               // frame offset in the output (elements)

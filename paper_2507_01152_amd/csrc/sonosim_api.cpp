@@ -153,7 +153,9 @@ sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int64_t out_o
     e.dx = (float)p.dx_mm;
     e.dy = (float)p.dy_mm;
     e.disp = (float)(20.0 / p.dr_db);
+    e.disp2 = (float)((20.0 / p.dr_db) * 0.30102999566398119521);    // log10(2)
     e.coef = p.f_mhz * (p.dy_mm / 10.0);
+    e.coef2 = e.coef * 1.44269504088896340736;                        // log2(e)
     e.dx64 = p.dx_mm;
     e.dy64 = p.dy_mm;
     e.f64 = p.f_mhz;
