@@ -215,6 +215,102 @@ sg_status sg_batch_config(sg_ctx* ctx, int32_t plan_id, int32_t* scanlines_per_i
 
 sg_status sg_batch_plan_destroy(sg_ctx* ctx, int32_t plan_id);
 
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate (a label-slice -> B-mode convolutional network trained on
+ * frames of the physics path; the paper's learning-based simulator, Sec. 4
+ * and App. B.2 "Learning-based approach", is a pix2pix U-Net trained with an
+ * L1 term).  BF16 weights and activations, FP32 accumulation; all
+ * convolutions run on MFMA implicit-GEMM kernels.
+ *
+ * Tensors are NHWC bf16 (uint16_t storage, round-to-nearest-even) with the
+ * channel count a multiple of 8; conv weights are [Co][k][k][C] bf16.
+ */
+typedef struct {
+    int32_t N, H, W, C;       /* input: N x H x W x C (stored size) */
+    int32_t Co;               /* output channels (multiple of 8) */
+    int32_t kernel, stride, pad;
+    int32_t upsample;         /* 1: the conv reads its input nearest-upsampled x2,
+                                 i.e. at (h / 2, w / 2) of a 2H x 2W grid */
+} sg_conv_desc;
+/* Output size: Ho = (H' + 2 pad - kernel) / stride + 1 with H' = H (x2 if upsample). */
+
+/* y = act(conv(x, w) + bias), bf16 (device buffers, N x Ho x Wo x Co).
+ * bias (FP32, Co) may be NULL; relu 0/1; if skip (bf16, like y) is given,
+ * y_skip = bf16(y + skip) is written too; y_f32 (optional) receives act(acc +
+ * bias) before rounding.  Errors: SG_EINVAL. */
+sg_status sg_conv_forward(sg_ctx* ctx, const sg_conv_desc* d, const uint16_t* x, const uint16_t* w,
+                          const float* bias, int32_t relu, const uint16_t* skip, uint16_t* y, uint16_t* y_skip,
+                          float* y_f32);
+
+/* dx = d(sum dy * y) / dx for the conv above without activation: dy is the
+ * gradient at the conv output (bf16, N x Ho x Wo x Co), dx FP32 (N x H x W x C,
+ * the stored input; with upsample the four fine positions are summed).
+ * accumulate 0: write, 1: add into dx. */
+sg_status sg_conv_backward_data(sg_ctx* ctx, const sg_conv_desc* d, const uint16_t* dy, const uint16_t* w,
+                                float* dx, int32_t accumulate);
+
+/* dw[Co][k][k][C] = sum over output pixels of dy * shifted x (FP32), and
+ * db[Co] = sum of dy (FP32, may be NULL).  Deterministic (fixed-order
+ * split-K reduction). */
+sg_status sg_conv_backward_weight(sg_ctx* ctx, const sg_conv_desc* d, const uint16_t* x, const uint16_t* dy,
+                                  float* dw, float* db);
+
+/* Create a surrogate for H x W frames (multiples of 16): a five-level
+ * encoder-decoder (16/32/64/128/256 channels, two 3x3 convs per level,
+ * stride-2 downsampling, nearest x2 upsampling + 3x3 conv, additive skips,
+ * 1x1 head), He-initialised from `seed`.  Input per pixel: one-hot label
+ * (labels 0..3) and the gated scatterer sample of the volume's noise field.
+ * *surr_id receives the id. */
+sg_status sg_surr_create(sg_ctx* ctx, int32_t H, int32_t W, uint64_t seed, int32_t* surr_id);
+sg_status sg_surr_destroy(sg_ctx* ctx, int32_t surr_id);
+
+/* Number of parameters (FP32 masters: weights then bias, layer by layer). */
+sg_status sg_surr_num_params(sg_ctx* ctx, int32_t surr_id, int64_t* n);
+
+/* One training step on n_envs pairs generated on the fly: the physics path
+ * renders the targets, the encoder builds the inputs, then forward, L1 loss
+ * (mean |Yhat - Y|), backward and one Adam step (beta1 0.5, beta2 0.999,
+ * eps 1e-8) with learning rate lr.  Every probe must be H x W.  *loss (host)
+ * receives the batch loss before the update (synchronises). */
+sg_status sg_surr_train_step(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, const int32_t* vol_ids,
+                             const sg_probe* probes, const double* poses, float lr, float* loss);
+
+/* Inference with an audit (the physics path judges the network on a subset
+ * and replaces failing frames).  out: device FP32, n_envs frames of H x W,
+ * clamp(Yhat, 0, 1).  audit_envs (host, n_audit distinct env indices, chosen
+ * by the caller) are also rendered by physics; their PSNR (peak 1) is written
+ * to psnr_out (host, n_audit).  A frame whose PSNR is below psnr_min is
+ * replaced by its physics frame; if more than max_fail_frac of the audited
+ * frames fail, every frame is rendered by physics.  *n_fallback (host)
+ * receives the number of frames that came from physics.  Synchronises. */
+sg_status sg_surr_infer(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, const int32_t* vol_ids,
+                        const sg_probe* probes, const double* poses, float* out, const int32_t* audit_envs,
+                        int32_t n_audit, float psnr_min, float max_fail_frac, float* psnr_out,
+                        int32_t* n_fallback);
+
+/* Decision rule of sg_surr_infer on host data (no device work): fallback[i]
+ * (host, n_audit) = psnr[i] < psnr_min (NaN counts as failing); *whole = 1
+ * if the failing fraction exceeds max_fail_frac. */
+sg_status sg_audit_decide(int32_t n_audit, const float* psnr, float psnr_min, float max_fail_frac,
+                          int32_t* fallback, int32_t* whole);
+
+/* Checkpoint: FP32 masters, Adam moments, step count and frame size in one
+ * file.  Loading restores them bit for bit (same frame size required). */
+sg_status sg_surr_save(sg_ctx* ctx, int32_t surr_id, const char* path);
+sg_status sg_surr_load(sg_ctx* ctx, int32_t surr_id, const char* path);
+
+/* Host copies of the FP32 parameters, of the gradient of the last training
+ * step, and setting the parameters (also refreshes the bf16 copies);
+ * `host` holds sg_surr_num_params floats. */
+sg_status sg_surr_get_params(sg_ctx* ctx, int32_t surr_id, float* host);
+sg_status sg_surr_get_grads(sg_ctx* ctx, int32_t surr_id, float* host);
+sg_status sg_surr_set_params(sg_ctx* ctx, int32_t surr_id, const float* host);
+
+/* Host copies of the last training step's encoded input (bf16, n x H x W x 8)
+ * and physics target (FP32, n x H x W). */
+sg_status sg_surr_get_batch(sg_ctx* ctx, int32_t surr_id, uint16_t* input, float* target);
+
 #ifdef __cplusplus
 }
 #endif

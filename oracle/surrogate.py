@@ -1,0 +1,223 @@
+"""FP64 oracle of the learned surrogate (test infrastructure only).
+
+Only the tests, the package's smoke check and the benchmark's CPU-baseline
+leg may import this module.  It shares no code with the GPU path.
+
+The surrogate follows the paper's learning-based simulator in spirit
+(Sec. 4 and App. B.2: a pix2pix-style encoder-decoder with skip connections
+trained with an L1 term): a five-level encoder-decoder on one-hot label
+slices plus one scatterer channel.  Numbers are bf16 where the GPU stores
+bf16 (weights, activations, the masked output gradients), with every sum
+carried out in FP64 here instead of FP32.
+
+Conventions:
+  tensors NHWC; conv weights [Co][k][k][Ci]; parameters flattened layer by
+  layer as (weights, bias), then the 1x1 head (16 weights, 1 bias).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# bf16 rounding
+
+
+def bf16_round(x) -> np.ndarray:
+    """Nearest bfloat16 value (ties to even) of each element, as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_bits_to_f64(b) -> np.ndarray:
+    return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def f64_to_bf16_bits(x) -> np.ndarray:
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+# ---------------------------------------------------------------------------
+# convolution and its two gradients, from the definition
+# out[n, ho, wo, co] = sum_{r, s, ci} xpad[n, ho*stride + r, wo*stride + s, ci] * w[co, r, s, ci]
+
+
+def upsample2(x: np.ndarray) -> np.ndarray:
+    """Nearest-neighbour x2 upsampling of NHWC."""
+    return x.repeat(2, axis=1).repeat(2, axis=2)
+
+
+def _out_size(n, k, stride, pad):
+    return (n + 2 * pad - k) // stride + 1
+
+
+def conv_forward(x, w, b=None, stride=1, pad=1, up=False, relu=False):
+    x = upsample2(x) if up else x
+    N, H, W, C = x.shape
+    Co, k = w.shape[0], w.shape[1]
+    Ho, Wo = _out_size(H, k, stride, pad), _out_size(W, k, stride, pad)
+    xp = np.pad(x, ((0, 0), (pad, pad), (pad, pad), (0, 0)))
+    out = np.zeros((N, Ho, Wo, Co))
+    for r in range(k):
+        for s in range(k):
+            patch = xp[:, r:r + stride * (Ho - 1) + 1:stride, s:s + stride * (Wo - 1) + 1:stride, :]
+            out += patch @ w[:, r, s, :].T
+    if b is not None:
+        out += b
+    if relu:
+        out = np.maximum(out, 0.0)
+    return out
+
+
+def conv_backward_data(dy, w, in_shape, stride=1, pad=1, up=False):
+    """Gradient w.r.t. the stored input (N, H, W, C) of conv_forward (no
+    activation); with up the four fine positions of each input are summed."""
+    N, H, W, C = in_shape
+    Hin, Win = (2 * H, 2 * W) if up else (H, W)
+    Co, k = w.shape[0], w.shape[1]
+    Ho, Wo = dy.shape[1], dy.shape[2]
+    dxp = np.zeros((N, Hin + 2 * pad, Win + 2 * pad, C))
+    for r in range(k):
+        for s in range(k):
+            dxp[:, r:r + stride * (Ho - 1) + 1:stride, s:s + stride * (Wo - 1) + 1:stride, :] += dy @ w[:, r, s, :]
+    dx = dxp[:, pad:pad + Hin, pad:pad + Win, :]
+    if up:
+        dx = dx.reshape(N, H, 2, W, 2, C).sum(axis=(2, 4))
+    return dx
+
+
+def conv_backward_weight(x, dy, k=3, stride=1, pad=1, up=False):
+    """(dw [Co][k][k][C], db [Co]) of conv_forward for output gradient dy."""
+    x = upsample2(x) if up else x
+    N, H, W, C = x.shape
+    Co = dy.shape[3]
+    Ho, Wo = dy.shape[1], dy.shape[2]
+    xp = np.pad(x, ((0, 0), (pad, pad), (pad, pad), (0, 0)))
+    g = dy.reshape(-1, Co)
+    dw = np.zeros((Co, k, k, C))
+    for r in range(k):
+        for s in range(k):
+            patch = xp[:, r:r + stride * (Ho - 1) + 1:stride, s:s + stride * (Wo - 1) + 1:stride, :]
+            dw[:, r, s, :] = g.T @ patch.reshape(-1, C)
+    return dw, dy.sum(axis=(0, 1, 2))
+
+
+# ---------------------------------------------------------------------------
+# the network
+
+# tensor name -> (channels, pyramid level)
+TENSORS = {
+    "X": (8, 0), "T1": (16, 0), "E0": (16, 0), "T2": (32, 1), "E1": (32, 1), "T3": (64, 2), "E2": (64, 2),
+    "T4": (128, 3), "E3": (128, 3), "T5": (256, 4), "B4": (256, 4),
+    "U3": (128, 3), "S3": (128, 3), "D3": (128, 3), "U2": (64, 2), "S2": (64, 2), "D2": (64, 2),
+    "U1": (32, 1), "S1": (32, 1), "D1": (32, 1), "U0": (16, 0), "S0": (16, 0), "D0": (16, 0),
+}
+
+# (input, output, stride, upsample, skip tensor, skip-added output); all 3x3, pad 1, ReLU
+LAYERS = [
+    ("X", "T1", 1, False, None, None), ("T1", "E0", 1, False, None, None),
+    ("E0", "T2", 2, False, None, None), ("T2", "E1", 1, False, None, None),
+    ("E1", "T3", 2, False, None, None), ("T3", "E2", 1, False, None, None),
+    ("E2", "T4", 2, False, None, None), ("T4", "E3", 1, False, None, None),
+    ("E3", "T5", 2, False, None, None), ("T5", "B4", 1, False, None, None),
+    ("B4", "U3", 1, True, "E3", "S3"), ("S3", "D3", 1, False, None, None),
+    ("D3", "U2", 1, True, "E2", "S2"), ("S2", "D2", 1, False, None, None),
+    ("D2", "U1", 1, True, "E1", "S1"), ("S1", "D1", 1, False, None, None),
+    ("D1", "U0", 1, True, "E0", "S0"), ("S0", "D0", 1, False, None, None),
+]
+HEAD_C = 16
+
+
+def param_layout():
+    """[(name, offset, shape)] of the flat parameter vector."""
+    out, off = [], 0
+    for i, (src, dst, *_rest) in enumerate(LAYERS):
+        ci, co = TENSORS[src][0], TENSORS[dst][0]
+        out.append((f"w{i}", off, (co, 3, 3, ci)))
+        off += co * 9 * ci
+        out.append((f"b{i}", off, (co,)))
+        off += co
+    out.append(("head_w", off, (HEAD_C,)))
+    off += HEAD_C
+    out.append(("head_b", off, (1,)))
+    off += 1
+    return out, off
+
+
+def unflatten(flat):
+    layout, n = param_layout()
+    assert flat.size == n, (flat.size, n)
+    return {name: np.asarray(flat[o:o + int(np.prod(shape))], dtype=np.float64).reshape(shape)
+            for name, o, shape in layout}
+
+
+def flatten(d):
+    layout, n = param_layout()
+    out = np.zeros(n)
+    for name, o, shape in layout:
+        out[o:o + int(np.prod(shape))] = d[name].ravel()
+    return out
+
+
+def forward(params, x, rounding=True):
+    """params: dict (FP32 masters); x: NHWC input (8 channels).  Returns
+    (activations dict, yhat [N,H,W])."""
+    q = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
+    act = {"X": q(x)}
+    for i, (src, dst, stride, up, skip, dst2) in enumerate(LAYERS):
+        y = conv_forward(act[src], q(params[f"w{i}"]), params[f"b{i}"], stride=stride, pad=1, up=up, relu=True)
+        act[dst] = q(y)
+        if skip is not None:
+            act[dst2] = q(act[dst] + act[skip])
+    yhat = act["D0"] @ q(params["head_w"]) + params["head_b"][0]
+    return act, yhat
+
+
+def l1_loss(yhat, y):
+    return float(np.abs(yhat - y).mean())
+
+
+def backward(params, act, yhat, y, rounding=True):
+    """Gradients of the L1 loss (mean |yhat - y|) w.r.t. every parameter."""
+    q = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
+    P = yhat.size
+    gy = np.sign(yhat - y) / P
+    grads = {"head_w": np.einsum("nhwc,nhw->c", act["D0"], gy), "head_b": np.array([gy.sum()])}
+    g = {"D0": gy[..., None] * q(params["head_w"])[None, None, None, :]}
+    for i in range(len(LAYERS) - 1, -1, -1):
+        src, dst, stride, up, skip, dst2 = LAYERS[i]
+        gout = g[dst2] if dst2 is not None else g[dst]
+        dpre = q(gout * (act[dst] > 0))
+        if skip is not None:
+            g[skip] = gout.copy()
+        dw, db = conv_backward_weight(act[src], dpre, k=3, stride=stride, pad=1, up=up)
+        grads[f"w{i}"], grads[f"b{i}"] = dw, db
+        if i > 0:
+            dx = conv_backward_data(dpre, q(params[f"w{i}"]), act[src].shape, stride=stride, pad=1, up=up)
+            g[src] = g[src] + dx if src in g else dx
+    return grads
+
+
+def loss_and_grads(flat_params, x, y, rounding=True):
+    params = unflatten(flat_params)
+    act, yhat = forward(params, x, rounding)
+    return l1_loss(yhat, y), flatten(backward(params, act, yhat, y, rounding)), yhat
+
+
+def psnr(yhat, y):
+    """PSNR (peak 1) of clamp(yhat, 0, 1) against y."""
+    mse = float(np.mean((np.clip(yhat, 0.0, 1.0) - y) ** 2))
+    return 200.0 if mse == 0 else -10.0 * np.log10(mse)
+
+
+def adam_update(w, g, m, v, step, lr, b1=0.5, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba 2015) on FP64 copies; returns (w, m, v)."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return w - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -1,0 +1,642 @@
+// BF16 MFMA implicit-GEMM convolutions (forward, data gradient, weight
+// gradient) with FP32 accumulation for gfx950, plus the element-wise kernels
+// of the surrogate network.
+//
+// Tensors are NHWC bf16 with C a multiple of 8; weights are [Co][kh][kw][Ci]
+// (K = kh*kw*Ci contiguous per output channel).  One GEMM kernel template
+// serves the three products:
+//   forward   C[pixel][co]       = sum_k im2col(x)[pixel][k] * W[co][k]
+//   data grad C[in pixel][ci]    = sum_k gather(dy)[in pixel][k] * WT[ci][k]
+//                                  (k = (r, s, co); WT = [Ci][kh][kw][Co])
+//   weight gr C[co][(r, s, ci)]  = sum_pixels dy[pixel][co] * x(shifted)[pixel][ci]
+// A block tile (BM x BN) is built from 4 waves, each owning FM x FN tiles of
+// v_mfma_f32_16x16x32_bf16; operands are staged through double-buffered LDS
+// (rows padded to 80 bytes).  The forward / data-gradient operands are
+// contiguous along K and are written to LDS with 16-byte stores; the
+// weight-gradient operands are contiguous along the channel (M / N) axis and
+// are transposed into LDS.  The weight gradient splits K (pixels) over
+// blocks and sums the partial tiles in a fixed order (deterministic).
+// A conv may read its input through a nearest-neighbour x2 upsampling
+// (decoder layers): the gather maps (h, w) to (h / 2, w / 2).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "surrogate_internal.h"
+
+namespace sg {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kBK = 32;           // K per MFMA step
+constexpr int kBKP = kBK + 8;     // padded LDS row (bf16)
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b)
+{
+    return __uint_as_float((uint32_t)b << 16);
+}
+
+enum Mode { kFwd = 0, kDgrad = 1, kWgrad = 2 };
+
+struct Pix {
+    int n, h, w;
+};
+
+__device__ __forceinline__ Pix split_pixel(int64_t m, int H, int W)
+{
+    Pix p;
+    const int hw = H * W;
+    p.n = (int)(m / hw);
+    const int rem = (int)(m - (int64_t)p.n * hw);
+    p.h = rem / W;
+    p.w = rem - p.h * W;
+    return p;
+}
+
+// 8 input channels of x at conv-input position (n, hi, wi), or zeros
+__device__ __forceinline__ uint4 load_x8(const ConvGeom& g, const uint16_t* x, int n, int hi, int wi, int ci0)
+{
+    const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
+    if (hi < 0 || wi < 0 || hi >= Hin || wi >= Win) return make_uint4(0u, 0u, 0u, 0u);
+    if (g.up) {
+        hi >>= 1;
+        wi >>= 1;
+    }
+    return *reinterpret_cast<const uint4*>(x + (((int64_t)n * g.H + hi) * g.W + wi) * g.C + ci0);
+}
+
+// A operand chunk (8 consecutive k of row m) for the K-contiguous modes
+template <int MODE>
+__device__ __forceinline__ uint4 load_a_k(const ConvGeom& g, const uint16_t* src, int64_t m, int k)
+{
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    if (MODE == kFwd) {
+        if (m >= g.M || k >= g.K) return z;
+        const Pix p = split_pixel(m, g.Ho, g.Wo);
+        const int t = k / g.C, ci0 = k - t * g.C;
+        const int r = t / g.kw, s = t - r * g.kw;
+        return load_x8(g, src, p.n, p.h * g.stride - g.pad + r, p.w * g.stride - g.pad + s, ci0);
+    } else {
+        // data gradient: row = conv-input pixel, k = (r, s, co)
+        if (m >= g.M || k >= g.K) return z;
+        const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
+        const Pix p = split_pixel(m, Hin, Win);
+        const int t = k / g.Co, co0 = k - t * g.Co;
+        const int r = t / g.kw, s = t - r * g.kw;
+        const int hh = p.h + g.pad - r, ww = p.w + g.pad - s;
+        if (hh < 0 || ww < 0) return z;
+        const int ho = hh / g.stride, wo = ww / g.stride;
+        if (ho * g.stride != hh || wo * g.stride != ww || ho >= g.Ho || wo >= g.Wo) return z;
+        return *reinterpret_cast<const uint4*>(src + (((int64_t)p.n * g.Ho + ho) * g.Wo + wo) * g.Co + co0);
+    }
+}
+
+// B operand chunk (8 consecutive k of column col) for the K-contiguous modes:
+// weights row-major [col][K]
+__device__ __forceinline__ uint4 load_b_k(const ConvGeom& g, const uint16_t* w, int col, int k)
+{
+    if (col >= g.N || k >= g.K) return make_uint4(0u, 0u, 0u, 0u);
+    return *reinterpret_cast<const uint4*>(w + (int64_t)col * g.K + k);
+}
+
+// weight gradient operands, contiguous along M (co) or N ((r, s, ci))
+__device__ __forceinline__ uint4 load_wg_a(const ConvGeom& g, const uint16_t* dy, int m0, int64_t k)
+{
+    if (m0 >= g.M || k >= g.Kw) return make_uint4(0u, 0u, 0u, 0u);
+    return *reinterpret_cast<const uint4*>(dy + k * g.Co + m0);
+}
+
+__device__ __forceinline__ uint4 load_wg_b(const ConvGeom& g, const uint16_t* x, int n0, int64_t k)
+{
+    if (n0 >= g.N || k >= g.Kw) return make_uint4(0u, 0u, 0u, 0u);
+    const Pix p = split_pixel(k, g.Ho, g.Wo);
+    const int t = n0 / g.C, ci0 = n0 - t * g.C;
+    const int r = t / g.kw, s = t - r * g.kw;
+    return load_x8(g, x, p.n, p.h * g.stride - g.pad + r, p.w * g.stride - g.pad + s, ci0);
+}
+
+template <int MODE, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
+{
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int FM = TM / 16, FN = TN / 16;
+    static_assert(WM * WN == 4, "four waves");
+    static_assert(FM >= 1 && FN >= 1, "tile");
+    // per-thread staged chunks per K step
+    constexpr int CA = (MODE == kWgrad) ? (BM / 8) * kBK : BM * (kBK / 8);
+    constexpr int CB = (MODE == kWgrad) ? (BN / 8) * kBK : BN * (kBK / 8);
+    constexpr int PA = (CA + kThreads - 1) / kThreads;
+    constexpr int PB = (CB + kThreads - 1) / kThreads;
+
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * kBKP];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * kBKP];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int64_t m_base = (int64_t)blockIdx.x * BM;
+    const int n_base = blockIdx.y * BN;
+
+    // K range of this block (split-K for the weight gradient)
+    int64_t k_begin = 0, k_end = (MODE == kWgrad) ? g.Kw : g.K;
+    if (MODE == kWgrad) {
+        k_begin = (int64_t)blockIdx.z * a.k_chunk;
+        k_end = min(k_end, k_begin + a.k_chunk);
+    }
+    const int nk = (int)((k_end - k_begin + kBK - 1) / kBK);
+
+    uint4 ra[PA], rb[PB];
+
+    auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int c = tid + i * kThreads;
+            ra[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (c < CA) {
+                if (MODE == kWgrad) {
+                    const int m8 = c % (BM / 8), kk = c / (BM / 8);
+                    const int64_t k = k0 + kk;
+                    if (k < k_end) ra[i] = load_wg_a(g, a.a, (int)m_base + m8 * 8, k);
+                } else {
+                    const int row = c / (kBK / 8), k8 = c % (kBK / 8);
+                    ra[i] = load_a_k<MODE>(g, a.a, m_base + row, (int)k0 + k8 * 8);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int c = tid + i * kThreads;
+            rb[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (c < CB) {
+                if (MODE == kWgrad) {
+                    const int n8 = c % (BN / 8), kk = c / (BN / 8);
+                    const int64_t k = k0 + kk;
+                    if (k < k_end) rb[i] = load_wg_b(g, a.b, n_base + n8 * 8, k);
+                } else {
+                    const int col = c / (kBK / 8), k8 = c % (kBK / 8);
+                    rb[i] = load_b_k(g, a.b, n_base + col, (int)k0 + k8 * 8);
+                }
+            }
+        }
+    };
+    auto store_tiles = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            const int c = tid + i * kThreads;
+            if (c < CA) {
+                if (MODE == kWgrad) {
+                    const int m8 = c % (BM / 8), kk = c / (BM / 8);
+                    const uint16_t* v = reinterpret_cast<const uint16_t*>(&ra[i]);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) sA[buf][(m8 * 8 + j) * kBKP + kk] = v[j];
+                } else {
+                    const int row = c / (kBK / 8), k8 = c % (kBK / 8);
+                    *reinterpret_cast<uint4*>(&sA[buf][row * kBKP + k8 * 8]) = ra[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int c = tid + i * kThreads;
+            if (c < CB) {
+                if (MODE == kWgrad) {
+                    const int n8 = c % (BN / 8), kk = c / (BN / 8);
+                    const uint16_t* v = reinterpret_cast<const uint16_t*>(&rb[i]);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) sB[buf][(n8 * 8 + j) * kBKP + kk] = v[j];
+                } else {
+                    const int col = c / (kBK / 8), k8 = c % (kBK / 8);
+                    *reinterpret_cast<uint4*>(&sB[buf][col * kBKP + k8 * 8]) = rb[i];
+                }
+            }
+        }
+    };
+
+    f32x4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    if (nk > 0) {
+        load_tiles(k_begin);
+        store_tiles(0);
+    }
+    __syncthreads();
+    const int frow = lane & 15, fk = (lane >> 4) * 8;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load_tiles(k_begin + (int64_t)(kt + 1) * kBK);
+        bf16x8 fa[FM], fb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            fa[i] = *reinterpret_cast<const bf16x8*>(&sA[buf][(wm * TM + i * 16 + frow) * kBKP + fk]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            fb[j] = *reinterpret_cast<const bf16x8*>(&sB[buf][(wn * TN + j * 16 + frow) * kBKP + fk]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        if (kt + 1 < nk) store_tiles(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each tile
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = n_base + wn * TN + j * 16 + (lane & 15);
+            if (col >= g.N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = m_base + wm * TM + i * 16 + (lane >> 4) * 4 + r;
+                if (row >= g.M) continue;
+                const float v = acc[i][j][r];
+                if (MODE == kFwd) {
+                    float y = v + (a.bias ? a.bias[col] : 0.f);
+                    if (a.relu) y = fmaxf(y, 0.f);
+                    const int64_t o = row * g.Co + col;
+                    const uint16_t yb = f2bf(y);
+                    if (a.out_bf16) a.out_bf16[o] = yb;
+                    if (a.out_f32) a.out_f32[o] = y;
+                    if (a.skip && a.out2_bf16) a.out2_bf16[o] = f2bf(bf2f(yb) + bf2f(a.skip[o]));
+                } else if (MODE == kDgrad) {
+                    const int64_t o = row * g.C + col;
+                    a.out_f32[o] = a.accumulate ? a.out_f32[o] + v : v;
+                } else {
+                    a.out_f32[(int64_t)blockIdx.z * g.M * g.N + row * g.N + col] = v;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element-wise / reduction kernels
+
+// dPre = bf16(g * [y > 0]) (ReLU) or bf16(g) (no activation)
+__global__ void k_mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = (y == nullptr || bf2f(y[i]) > 0.f) ? g[i] : 0.f;
+        out[i] = f2bf(v);
+    }
+}
+
+// coarse[n][h][w][c] (+)= sum of the 2x2 fine block (backward of the x2 upsample)
+__global__ void k_pool2x2_sum(const float* fine, float* coarse, int N, int H, int W, int C, int accumulate)
+{
+    const int64_t total = (int64_t)N * H * W * C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const int64_t p = i / C;
+        const int w = (int)(p % W);
+        const int64_t q = p / W;
+        const int h = (int)(q % H);
+        const int n = (int)(q / H);
+        const int64_t base = (((int64_t)n * 2 * H + 2 * h) * 2 * W + 2 * w) * C + c;
+        const int64_t rs = (int64_t)2 * W * C;
+        const float s = (fine[base] + fine[base + C]) + (fine[base + rs] + fine[base + rs + C]);
+        coarse[i] = accumulate ? coarse[i] + s : s;
+    }
+}
+
+// column partial sums of a [rows][cols] bf16 matrix over row blocks: part[b][c]
+__global__ void k_colsum_bf16(const uint16_t* x, int64_t rows, int cols, int64_t rows_per_block, float* part)
+{
+    const int c = blockIdx.y * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(rows, r0 + rows_per_block);
+    float s = 0.f;
+    for (int64_t r = r0; r < r1; ++r) s += bf2f(x[r * cols + c]);
+    part[(int64_t)blockIdx.x * cols + c] = s;
+}
+
+// out[i] = sum_s part[s][i] in fixed order
+__global__ void k_sum_parts(const float* part, int64_t n, int splits, float* out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int z = 0; z < splits; ++z) s += part[(int64_t)z * n + i];
+        out[i] = s;
+    }
+}
+
+// 1x1 head with one output channel: y[p] = sum_c w[c] x[p][c] + b
+__global__ void k_head_fwd(const uint16_t* x, const uint16_t* w, const float* b, float* y, int64_t P, int C)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int c = 0; c < C; ++c) s += bf2f(w[c]) * bf2f(x[p * C + c]);
+        y[p] = s + b[0];
+    }
+}
+
+// head backward: dx[p][c] = w[c] g[p]; per-block partials of dw[c] = sum x g
+// and db = sum g (part row layout: C + 1 values per block)
+__global__ void k_head_bwd(const uint16_t* x, const uint16_t* w, const float* g, float* dx, int64_t P, int C,
+                           int64_t rows_per_block, float* part)
+{
+    const int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t p1 = min(P, p0 + rows_per_block);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x)
+        for (int c = 0; c < C; ++c) dx[p * C + c] = bf2f(w[c]) * g[p];
+    if (threadIdx.x <= C) {
+        float s = 0.f;
+        for (int64_t p = p0; p < p1; ++p) s += (threadIdx.x < C) ? bf2f(x[p * C + threadIdx.x]) * g[p] : g[p];
+        part[(int64_t)blockIdx.x * (C + 1) + threadIdx.x] = s;
+    }
+}
+
+// L1 loss: per-block partial sums of |yhat - y| * scale (scale = 1 / n);
+// grad = sign(yhat - y) * scale
+__global__ void k_l1(const float* yhat, const float* y, int64_t n, float scale, float* grad, int64_t per_block,
+                     float* part)
+{
+    __shared__ float red[256];
+    const int64_t i0 = (int64_t)blockIdx.x * per_block;
+    const int64_t i1 = min(n, i0 + per_block);
+    float s = 0.f;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const float d = yhat[i] - y[i];
+        s += fabsf(d);
+        grad[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] * scale;   // mean over all n
+}
+
+// Adam on FP32 masters; writes the bf16 weights [Co][K] and their transpose
+// WT [Ci][taps][Co] (data gradient operand)
+__global__ void k_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[i] = wi;
+        if (wb) {
+            const uint16_t b = f2bf(wi);
+            wb[i] = b;
+            if (wt) {
+                // i = (co * taps + t) * Ci + ci  ->  (ci * taps + t) * Co + co
+                const int ci = (int)(i % Ci);
+                const int64_t q = i / Ci;
+                const int t = (int)(q % taps);
+                const int co = (int)(q / taps);
+                wt[((int64_t)ci * taps + t) * Co + co] = b;
+            }
+        }
+    }
+}
+
+// bf16 copies of FP32 weights and the transpose (initialisation / load)
+__global__ void k_weights_to_bf16(const float* w, int64_t n, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint16_t b = f2bf(w[i]);
+        wb[i] = b;
+        if (wt) {
+            const int ci = (int)(i % Ci);
+            const int64_t q = i / Ci;
+            const int t = (int)(q % taps);
+            const int co = (int)(q / taps);
+            wt[((int64_t)ci * taps + t) * Co + co] = b;
+        }
+    }
+}
+
+// per-frame PSNR of clamp(yhat, 0, 1) against y (peak 1): one block per frame
+__global__ void k_psnr(const float* yhat, const float* y, int64_t frame, float* psnr)
+{
+    __shared__ float red[256];
+    const float* a = yhat + (int64_t)blockIdx.x * frame;
+    const float* b = y + (int64_t)blockIdx.x * frame;
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < frame; i += blockDim.x) {
+        const float d = fminf(fmaxf(a[i], 0.f), 1.f) - b[i];
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float mse = red[0] / (float)frame;
+        psnr[blockIdx.x] = mse > 0.f ? -10.f * log10f(mse) : 200.f;
+    }
+}
+
+// wt[ci][t][co] = w[co][t][ci] (bf16)
+__global__ void k_transpose_w(const uint16_t* w, uint16_t* wt, int Co, int taps, int Ci)
+{
+    const int64_t n = (int64_t)Co * taps * Ci;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int ci = (int)(i % Ci);
+        const int64_t q = i / Ci;
+        const int t = (int)(q % taps);
+        const int co = (int)(q / taps);
+        wt[((int64_t)ci * taps + t) * Co + co] = w[i];
+    }
+}
+
+// PSNR of clamp(yhat frame idx[b], 0, 1) against target frame b (peak 1)
+__global__ void k_psnr_idx(const float* yhat, const float* y, const int32_t* idx, int64_t frame, float* psnr)
+{
+    __shared__ float red[256];
+    const float* a = yhat + (int64_t)idx[blockIdx.x] * frame;
+    const float* b = y + (int64_t)blockIdx.x * frame;
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < frame; i += blockDim.x) {
+        const float d = fminf(fmaxf(a[i], 0.f), 1.f) - b[i];
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float mse = red[0] / (float)frame;
+        psnr[blockIdx.x] = mse > 0.f ? -10.f * log10f(mse) : 200.f;
+    }
+}
+
+__global__ void k_clamp01(const float* x, float* y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = fminf(fmaxf(x[i], 0.f), 1.f);
+}
+
+int64_t grid_for(int64_t n, int64_t per = 256)
+{
+    int64_t b = (n + per - 1) / per;
+    if (b > 8192) b = 8192;
+    return b < 1 ? 1 : b;
+}
+
+template <int MODE, int BM, int BN, int WM, int WN>
+hipError_t launch_gemm(const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s)
+{
+    const int64_t gm = (g.M + BM - 1) / BM;
+    const int gn = (g.N + BN - 1) / BN;
+    hipLaunchKernelGGL((k_conv_gemm<MODE, BM, BN, WM, WN>), dim3((unsigned)gm, gn, splits), dim3(kThreads), 0, s,
+                       g, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s)
+{
+    if (mode == kWgrad) {
+        if (g.M <= 16) return launch_gemm<kWgrad, 16, 128, 1, 4>(g, a, splits, s);
+        if (g.M <= 32) return launch_gemm<kWgrad, 32, 128, 1, 4>(g, a, splits, s);
+        return launch_gemm<kWgrad, 64, 128, 2, 2>(g, a, splits, s);
+    }
+    if (mode == kFwd) {
+        if (g.N <= 16) return launch_gemm<kFwd, 256, 16, 4, 1>(g, a, 1, s);
+        if (g.N <= 32) return launch_gemm<kFwd, 128, 32, 4, 1>(g, a, 1, s);
+        if (g.N <= 64) return launch_gemm<kFwd, 128, 64, 2, 2>(g, a, 1, s);
+        return launch_gemm<kFwd, 128, 128, 2, 2>(g, a, 1, s);
+    }
+    if (g.N <= 16) return launch_gemm<kDgrad, 256, 16, 4, 1>(g, a, 1, s);
+    if (g.N <= 32) return launch_gemm<kDgrad, 128, 32, 4, 1>(g, a, 1, s);
+    if (g.N <= 64) return launch_gemm<kDgrad, 128, 64, 2, 2>(g, a, 1, s);
+    return launch_gemm<kDgrad, 128, 128, 2, 2>(g, a, 1, s);
+}
+
+int wgrad_tile_m(int M) { return M <= 16 ? 16 : (M <= 32 ? 32 : 64); }
+
+hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mask_to_bf16, dim3((unsigned)grid_for(n)), dim3(256), 0, s, g, y, out, n);
+    return hipGetLastError();
+}
+
+hipError_t pool2x2_sum(const float* fine, float* coarse, int N, int H, int W, int C, int accumulate, hipStream_t s)
+{
+    const int64_t n = (int64_t)N * H * W * C;
+    hipLaunchKernelGGL(k_pool2x2_sum, dim3((unsigned)grid_for(n)), dim3(256), 0, s, fine, coarse, N, H, W, C,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t colsum_bf16(const uint16_t* x, int64_t rows, int cols, float* part, int blocks, float* out,
+                       hipStream_t s)
+{
+    const int64_t per = (rows + blocks - 1) / blocks;
+    hipLaunchKernelGGL(k_colsum_bf16, dim3(blocks, (cols + 255) / 256), dim3(256), 0, s, x, rows, cols, per, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(cols)), dim3(256), 0, s, part, (int64_t)cols, blocks, out);
+    return hipGetLastError();
+}
+
+hipError_t sum_parts(const float* part, int64_t n, int splits, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(n)), dim3(256), 0, s, part, n, splits, out);
+    return hipGetLastError();
+}
+
+hipError_t head_fwd(const uint16_t* x, const uint16_t* w, const float* b, float* y, int64_t P, int C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_head_fwd, dim3((unsigned)grid_for(P)), dim3(256), 0, s, x, w, b, y, P, C);
+    return hipGetLastError();
+}
+
+hipError_t head_bwd(const uint16_t* x, const uint16_t* w, const float* g, float* dx, int64_t P, int C, float* part,
+                    int blocks, float* dwb, hipStream_t s)
+{
+    const int64_t per = (P + blocks - 1) / blocks;
+    hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, x, w, g, dx, P, C, per, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int64_t)(C + 1), blocks, dwb);
+    return hipGetLastError();
+}
+
+hipError_t l1_loss(const float* yhat, const float* y, int64_t n, float* grad, float* part, int blocks, float* loss,
+                   hipStream_t s)
+{
+    const int64_t per = (n + blocks - 1) / blocks;
+    hipLaunchKernelGGL(k_l1, dim3(blocks), dim3(256), 0, s, yhat, y, n, 1.f / (float)n, grad, per, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int64_t)1, blocks, loss);
+    return hipGetLastError();
+}
+
+hipError_t adam_step(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                     float c1, float c2, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)grid_for(n)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, c1, c2,
+                       wb, wt, Co, taps, Ci);
+    return hipGetLastError();
+}
+
+hipError_t weights_to_bf16(const float* w, int64_t n, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_weights_to_bf16, dim3((unsigned)grid_for(n)), dim3(256), 0, s, w, n, wb, wt, Co, taps, Ci);
+    return hipGetLastError();
+}
+
+hipError_t transpose_w(const uint16_t* w, uint16_t* wt, int Co, int taps, int Ci, hipStream_t s)
+{
+    const int64_t n = (int64_t)Co * taps * Ci;
+    hipLaunchKernelGGL(k_transpose_w, dim3((unsigned)grid_for(n)), dim3(256), 0, s, w, wt, Co, taps, Ci);
+    return hipGetLastError();
+}
+
+hipError_t psnr_indexed(const float* yhat, const float* y, const int32_t* idx, int n_frames, int64_t frame,
+                        float* psnr, hipStream_t s)
+{
+    if (n_frames <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_psnr_idx, dim3(n_frames), dim3(256), 0, s, yhat, y, idx, frame, psnr);
+    return hipGetLastError();
+}
+
+hipError_t clamp01(const float* x, float* y, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clamp01, dim3((unsigned)grid_for(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t psnr_frames(const float* yhat, const float* y, int n_frames, int64_t frame, float* psnr, hipStream_t s)
+{
+    if (n_frames <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_psnr, dim3(n_frames), dim3(256), 0, s, yhat, y, frame, psnr);
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -543,6 +543,50 @@ __global__ __launch_bounds__(kThreads) void k_psf(PhysArgs a, QueueDev* q)
     }
 }
 
+// Surrogate input of each pixel: one-hot label (channels 0..3) and the
+// scatterer sample of the same fixed noise field the ray pass uses (channel 4:
+// N0 where the density gate passes, else 0), bf16, 8 channels per pixel,
+// frames packed [env][y][x][8] at 8 * out_off.
+__device__ __forceinline__ uint16_t f2bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(kThreads) void k_encode(PhysArgs a, uint16_t* enc)
+{
+    const int env = blockIdx.y;
+    const EnvDev e = a.envs[env];
+    const VolDev v = a.vols[e.vol];
+    const int npx = e.W * e.H;
+    for (int p = blockIdx.x * kThreads + threadIdx.x; p < npx; p += gridDim.x * kThreads) {
+        const int y = p / e.W, x = p - y * e.W;
+        int lab = 0;
+        float sc = 0.f;
+        if (e.valid) {
+            const int32_t vox = voxel_at(e, v, x, y);
+            lab = label_of(v, vox);
+            if (vox >= 0) {
+                uint32_t w[4];
+                philox4x32_10((uint32_t)vox, v.key0, v.key1, w);
+                const TissueDev tt = a.table[lab];
+                if ((unsigned long long)w[2] < tt.thr) {
+                    const float m2ln = __builtin_amdgcn_logf(uniform24(w[0])) * -1.3862943611198906f;
+                    sc = __builtin_amdgcn_sqrtf(m2ln) * __builtin_amdgcn_cosf(uniform24(w[1]));
+                }
+            }
+        }
+        uint4 o;
+        const uint32_t one = 0x3F80u;   // bf16 1.0
+        o.x = (lab == 0 ? one : 0u) | ((lab == 1 ? one : 0u) << 16);
+        o.y = (lab == 2 ? one : 0u) | ((lab == 3 ? one : 0u) << 16);
+        o.z = (uint32_t)f2bf16(sc);
+        o.w = 0u;
+        reinterpret_cast<uint4*>(enc)[e.out_off + p] = o;
+    }
+}
+
 __global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int n, QueueDev* q)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -636,6 +680,15 @@ hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tx, int grid, hipStrea
         hipLaunchKernelGGL(k_psf<64>, dim3(grid), dim3(kThreads), lds, s, a, q);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, uint16_t* enc, hipStream_t s)
+{
+    if (n_envs <= 0) return hipSuccess;
+    int bx = (max_pixels + kThreads - 1) / kThreads;
+    if (bx > 64) bx = 64;
+    hipLaunchKernelGGL(k_encode, dim3(bx, n_envs), dim3(kThreads), 0, s, a, enc);
     return hipGetLastError();
 }
 

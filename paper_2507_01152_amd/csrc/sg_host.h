@@ -69,6 +69,13 @@ struct Plan {
 
 }  // namespace sg
 
+namespace sg {
+struct Surrogate;   // surrogate.cpp
+struct SurrogateDeleter {
+    void operator()(Surrogate* p) const;
+};
+}  // namespace sg
+
 struct sg_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -83,7 +90,9 @@ struct sg_ctx {
     sg::PinnedBuf staging;
     std::map<int32_t, std::unique_ptr<sg::Plan>> plans;
     int32_t next_plan = 1;
-    void* surrogates = nullptr;        // owned by the surrogate module
+    std::map<int32_t, std::unique_ptr<sg::Surrogate, sg::SurrogateDeleter>> surrogates;
+    int32_t next_surr = 1;
+    sg::DevBuf op_wt, op_fine, op_parts;   // workspaces of the conv op entry points
 };
 
 namespace sg {
@@ -97,6 +106,15 @@ sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int64_t out_o
 void build_items(const std::vector<EnvDev>& envs, const std::vector<int>& order, int spw, int tx,
                  std::vector<ItemRay>& rays, std::vector<ItemPsf>& tiles);
 sg_status sync_volumes(sg_ctx* c);
+
+struct StageInfo {
+    int tile_x = 32;
+    int max_pixels = 0;
+};
+sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_probe* probes, const double* poses,
+                        float* out, const int64_t* out_offsets, const sg_debug_planes* dbg, PhysArgs& a,
+                        StageInfo& info);
+sg_status launch_physics(sg_ctx* c, const PhysArgs& a, const StageInfo& info);
 sg_status check_envs(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_probe* probes);
 void surrogate_release_all(sg_ctx* c);
 

@@ -144,6 +144,8 @@ hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses
 hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s);
 hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tile_x, int grid, hipStream_t s);
 hipError_t launch_max_label(const uint8_t* labels, int64_t n, int32_t* d_out, hipStream_t s);
+// surrogate input encoding of every pixel of n_envs frames (8 bf16 per pixel)
+hipError_t launch_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, uint16_t* enc, hipStream_t s);
 size_t psf_lds_bytes(int tile_x, int max_rlat);
 bool psf_tile_supported(int tile_x);
 int ray_grid(int n_cu);                              // resident ray workgroups

@@ -348,22 +348,21 @@ sg_status check_envs(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_prob
 
 }  // namespace sg
 
-extern "C" sg_status sg_simulate(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
-                                 const double* poses, float* out, const int64_t* out_offsets,
-                                 const sg_debug_planes* dbg)
+namespace sg {
+
+// Validate a call's environments, compute their geometry on the host and
+// upload the parameters and work lists; fills `a` (fields scratch, queue and
+// work lists of the context).  Nothing is launched.
+sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_probe* probes, const double* poses,
+                        float* out, const int64_t* out_offsets, const sg_debug_planes* dbg, PhysArgs& a,
+                        StageInfo& info)
 {
-    if (!c) return fail(SG_EINVAL, "sg_simulate: NULL context");
-    if (n < 0) return fail(SG_EINVAL, "sg_simulate: n_envs < 0");
-    if (n == 0) return SG_OK;
-    if (!vol_ids || !probes || !poses || !out || !out_offsets)
-        return fail(SG_EINVAL, "sg_simulate: NULL argument");
-    (void)hipSetDevice(c->device);
     sg_status s = check_envs(c, n, vol_ids, probes);
     if (s != SG_OK) return s;
     std::vector<EnvDev> envs(n);
     std::vector<float> pool;
     int64_t scr = 0;
-    int max_rlat = 0;
+    int max_rlat = 0, max_px = 0;
     for (int i = 0; i < n; ++i) {
         for (int k = 0; k < 12; ++k)
             if (!std::isfinite(poses[12 * i + k])) return fail(SG_EINVAL, "env %d: pose is not finite", i);
@@ -377,15 +376,16 @@ extern "C" sg_status sg_simulate(sg_ctx* c, int32_t n, const int32_t* vol_ids, c
             return fail(SG_ERANGE, "env %d: image plane outside the fixed-point range (|Q16| > 2^30)", i);
         scr += (int64_t)probes[i].W * probes[i].H;
         max_rlat = std::max(max_rlat, envs[i].rlat);
+        max_px = std::max(max_px, probes[i].W * probes[i].H);
     }
     s = sync_volumes(c);
     if (s != SG_OK) return s;
     // longest scanlines first (ray items cost ~H), then wider frames
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (envs[a].H != envs[b].H) return envs[a].H > envs[b].H;
-        return envs[a].W > envs[b].W;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (envs[x].H != envs[y].H) return envs[x].H > envs[y].H;
+        return envs[x].W > envs[y].W;
     });
     std::vector<ItemRay> rays;
     std::vector<ItemPsf> tiles;
@@ -414,7 +414,6 @@ extern "C" sg_status sg_simulate(sg_ctx* c, int32_t n, const int32_t* vol_ids, c
     if (e != hipSuccess) return hip_fail(e, "parameter upload");
 
     char* d = (char*)c->params.p;
-    PhysArgs a;
     std::memset(&a, 0, sizeof(a));
     a.envs = (const EnvDev*)(d + o_env);
     a.vols = (const VolDev*)c->d_vols.p;
@@ -438,10 +437,38 @@ extern "C" sg_status sg_simulate(sg_ctx* c, int32_t n, const int32_t* vol_ids, c
     }
     a.scanlines_per_wave = spw;
     a.max_rlat = max_rlat;
+    info.tile_x = tx;
+    info.max_pixels = max_px;
+    return SG_OK;
+}
+
+// enqueue the two physics kernels of a staged call
+sg_status launch_physics(sg_ctx* c, const PhysArgs& a, const StageInfo& info)
+{
     QueueDev* q = (QueueDev*)c->queue.p;
+    hipError_t e;
     if ((e = launch_queue_reset(q, c->stream)) != hipSuccess) return hip_fail(e, "queue reset");
     if ((e = launch_ray(a, q, ray_grid(c->n_cu), c->stream)) != hipSuccess) return hip_fail(e, "ray kernel launch");
-    if ((e = launch_psf(a, q, tx, psf_grid(tx, max_rlat, c->n_cu), c->stream)) != hipSuccess)
+    if ((e = launch_psf(a, q, info.tile_x, psf_grid(info.tile_x, a.max_rlat, c->n_cu), c->stream)) != hipSuccess)
         return hip_fail(e, "PSF kernel launch");
     return SG_OK;
+}
+
+}  // namespace sg
+
+extern "C" sg_status sg_simulate(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
+                                 const double* poses, float* out, const int64_t* out_offsets,
+                                 const sg_debug_planes* dbg)
+{
+    if (!c) return fail(SG_EINVAL, "sg_simulate: NULL context");
+    if (n < 0) return fail(SG_EINVAL, "sg_simulate: n_envs < 0");
+    if (n == 0) return SG_OK;
+    if (!vol_ids || !probes || !poses || !out || !out_offsets)
+        return fail(SG_EINVAL, "sg_simulate: NULL argument");
+    (void)hipSetDevice(c->device);
+    PhysArgs a;
+    StageInfo info;
+    sg_status s = stage_physics(c, n, vol_ids, probes, poses, out, out_offsets, dbg, a, info);
+    if (s != SG_OK) return s;
+    return launch_physics(c, a, info);
 }

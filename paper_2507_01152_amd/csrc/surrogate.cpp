@@ -1,0 +1,665 @@
+// Learned surrogate of the physics simulator (C ABI in include/sonosim.h):
+// conv op entry points, the encoder-decoder network, training on pairs the
+// physics path renders, inference with a physics audit and fallback, and
+// checkpoints.  All arithmetic runs in the kernels of conv_mfma.hip and
+// physics.hip; this file only orchestrates.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "sg_host.h"
+#include "surrogate_internal.h"
+
+namespace sg {
+namespace {
+
+// tensors of the network (per frame: channels and pyramid level)
+enum { X = 0, T1, E0, T2, E1, T3, E2, T4, E3, T5, B4, U3, S3, D3, U2, S2, D2, U1, S1, D1, U0, S0, D0, kNumT };
+const int kTC[kNumT] = {8, 16, 16, 32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 128, 64, 64, 64, 32, 32, 32, 16, 16, 16};
+const int kTL[kNumT] = {0, 0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 3, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0};
+
+struct LayerDef {
+    int in, out, skip, out2, Ci, Co, stride, up;
+};
+// 3x3 convs with ReLU; decoder "U" layers read their input upsampled x2 and
+// add the encoder tensor of the same level (out2 = out + skip).
+const LayerDef kLayers[] = {
+    {X, T1, -1, -1, 8, 16, 1, 0},       {T1, E0, -1, -1, 16, 16, 1, 0},
+    {E0, T2, -1, -1, 16, 32, 2, 0},     {T2, E1, -1, -1, 32, 32, 1, 0},
+    {E1, T3, -1, -1, 32, 64, 2, 0},     {T3, E2, -1, -1, 64, 64, 1, 0},
+    {E2, T4, -1, -1, 64, 128, 2, 0},    {T4, E3, -1, -1, 128, 128, 1, 0},
+    {E3, T5, -1, -1, 128, 256, 2, 0},   {T5, B4, -1, -1, 256, 256, 1, 0},
+    {B4, U3, E3, S3, 256, 128, 1, 1},   {S3, D3, -1, -1, 128, 128, 1, 0},
+    {D3, U2, E2, S2, 128, 64, 1, 1},    {S2, D2, -1, -1, 64, 64, 1, 0},
+    {D2, U1, E1, S1, 64, 32, 1, 1},     {S1, D1, -1, -1, 32, 32, 1, 0},
+    {D1, U0, E0, S0, 32, 16, 1, 1},     {S0, D0, -1, -1, 16, 16, 1, 0},
+};
+constexpr int kNumL = sizeof(kLayers) / sizeof(kLayers[0]);
+constexpr int kHeadC = 16;
+constexpr float kBeta1 = 0.5f, kBeta2 = 0.999f, kEps = 1e-8f;
+
+}  // namespace
+
+struct Surrogate {
+    int H = 0, W = 0;
+    int64_t n_params = 0;
+    int64_t w_off[kNumL], b_off[kNumL], w_n[kNumL];
+    int64_t head_w = 0, head_b = 0;
+    DevBuf master, mom1, mom2, grad, wb, wt;
+    int64_t step = 0;
+    int cap = 0, cap_grad = 0, last_n = 0;
+    DevBuf act[kNumT], gact[kNumT];
+    DevBuf dpre, fine, parts, yhat, target, gy, loss, psnr, idx;
+};
+
+void SurrogateDeleter::operator()(Surrogate* p) const { delete p; }
+
+void surrogate_release_all(sg_ctx* c) { c->surrogates.clear(); }
+
+namespace {
+
+Surrogate* find_surr(sg_ctx* c, int32_t id)
+{
+    if (!c) return nullptr;
+    auto it = c->surrogates.find(id);
+    return it == c->surrogates.end() ? nullptr : it->second.get();
+}
+
+ConvShape layer_shape(const Surrogate& s, int L, int n)
+{
+    const LayerDef& d = kLayers[L];
+    const int lv = kTL[d.in];
+    ConvShape sh;
+    sh.N = n;
+    sh.H = s.H >> lv;
+    sh.W = s.W >> lv;
+    sh.C = d.Ci;
+    sh.Co = d.Co;
+    sh.k = 3;
+    sh.stride = d.stride;
+    sh.pad = 1;
+    sh.up = d.up;
+    return sh;
+}
+
+int64_t tensor_elems(const Surrogate& s, int t, int n)
+{
+    const int lv = kTL[t];
+    return (int64_t)n * (s.H >> lv) * (s.W >> lv) * kTC[t];
+}
+
+int blocks_for(int64_t n, int cap = 1024)
+{
+    int64_t b = (n + 4095) / 4096;
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+sg_status check(hipError_t e, const char* what) { return e == hipSuccess ? SG_OK : hip_fail(e, what); }
+
+#define SG_TRY(x)                             \
+    do {                                      \
+        sg_status _s = (x);                   \
+        if (_s != SG_OK) return _s;           \
+    } while (0)
+
+// weight gradient of one conv: dw (FP32) and optional bias gradient db
+sg_status wgrad(sg_ctx* c, const ConvShape& sh, const uint16_t* x, const uint16_t* dy, float* dw, float* db,
+                DevBuf& parts)
+{
+    ConvGeom g = geom_of(sh, 2);
+    const int bm = wgrad_tile_m((int)g.M);
+    const int64_t tiles = ((g.M + bm - 1) / bm) * ((g.N + 127) / 128);
+    const int64_t nkt = (g.Kw + 31) / 32;
+    int64_t splits = 2048 / tiles;
+    if (splits < 1) splits = 1;
+    if (splits > 512) splits = 512;
+    if (splits > nkt) splits = nkt;
+    const int64_t k_chunk = ((nkt + splits - 1) / splits) * 32;
+    splits = (g.Kw + k_chunk - 1) / k_chunk;
+    const int cs_blocks = blocks_for(g.Kw, 512);
+    const size_t need = sizeof(float) * std::max<int64_t>(splits * g.M * g.N, (int64_t)cs_blocks * sh.Co);
+    SG_TRY(check(parts.ensure(need), "wgrad workspace"));
+    ConvArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.a = dy;
+    a.b = x;
+    a.out_f32 = (float*)parts.p;
+    a.k_chunk = k_chunk;
+    SG_TRY(check(conv_gemm(2, g, a, (int)splits, c->stream), "wgrad launch"));
+    SG_TRY(check(sum_parts((float*)parts.p, g.M * g.N, (int)splits, dw, c->stream), "wgrad reduce"));
+    if (db) SG_TRY(check(colsum_bf16(dy, g.Kw, sh.Co, (float*)parts.p, cs_blocks, db, c->stream), "bias grad"));
+    return SG_OK;
+}
+
+// data gradient of one conv into dx (stored input resolution)
+sg_status dgrad(sg_ctx* c, const ConvShape& sh, const uint16_t* dy, const uint16_t* wt, float* dx, int accumulate,
+                DevBuf& fine)
+{
+    ConvGeom g = geom_of(sh, 1);
+    ConvArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.a = dy;
+    a.b = wt;
+    if (sh.up) {
+        SG_TRY(check(fine.ensure(sizeof(float) * (size_t)g.M * sh.C), "dgrad workspace"));
+        a.out_f32 = (float*)fine.p;
+        a.accumulate = 0;
+        SG_TRY(check(conv_gemm(1, g, a, 1, c->stream), "dgrad launch"));
+        return check(pool2x2_sum((float*)fine.p, dx, sh.N, sh.H, sh.W, sh.C, accumulate, c->stream), "upsample grad");
+    }
+    a.out_f32 = dx;
+    a.accumulate = accumulate;
+    return check(conv_gemm(1, g, a, 1, c->stream), "dgrad launch");
+}
+
+sg_status check_desc(const sg_conv_desc* d)
+{
+    if (!d) return fail(SG_EINVAL, "conv: NULL descriptor");
+    if (d->N < 1 || d->H < 1 || d->W < 1 || d->C < 8 || d->C % 8 || d->Co < 8 || d->Co % 8 || d->kernel < 1 ||
+        d->stride < 1 || d->pad < 0 || (d->upsample != 0 && d->upsample != 1))
+        return fail(SG_EINVAL, "conv: bad descriptor (C and Co multiples of 8, sizes >= 1)");
+    ConvShape sh{d->N, d->H, d->W, d->C, d->Co, d->kernel, d->stride, d->pad, d->upsample};
+    if (sh.Hin() + 2 * sh.pad < sh.k || sh.Win() + 2 * sh.pad < sh.k) return fail(SG_EINVAL, "conv: empty output");
+    const int64_t px = (int64_t)sh.N * sh.Hin() * sh.Win();
+    if (px * std::max(sh.C, sh.Co) >= (1ll << 40)) return fail(SG_EINVAL, "conv: tensor too large");
+    if ((int64_t)sh.k * sh.k * std::max(sh.C, sh.Co) >= (1ll << 30)) return fail(SG_EINVAL, "conv: K too large");
+    return SG_OK;
+}
+
+ConvShape shape_of(const sg_conv_desc* d)
+{
+    return ConvShape{d->N, d->H, d->W, d->C, d->Co, d->kernel, d->stride, d->pad, d->upsample};
+}
+
+// capacity for n frames; grads: also the backward buffers
+sg_status ensure_capacity(Surrogate& s, int n, bool grads)
+{
+    if (n > s.cap) {
+        for (int t = 0; t < kNumT; ++t)
+            SG_TRY(check(s.act[t].ensure(sizeof(uint16_t) * tensor_elems(s, t, n)), "activation buffers"));
+        const int64_t P = (int64_t)n * s.H * s.W;
+        SG_TRY(check(s.yhat.ensure(sizeof(float) * P), "output buffer"));
+        SG_TRY(check(s.target.ensure(sizeof(float) * P), "target buffer"));
+        s.cap = n;
+    }
+    if (grads && n > s.cap_grad) {
+        for (int t = 1; t < kNumT; ++t)
+            SG_TRY(check(s.gact[t].ensure(sizeof(float) * tensor_elems(s, t, n)), "gradient buffers"));
+        int64_t mx = 0;
+        for (int t = 1; t < kNumT; ++t) mx = std::max(mx, tensor_elems(s, t, n));
+        SG_TRY(check(s.dpre.ensure(sizeof(uint16_t) * mx), "dpre buffer"));
+        SG_TRY(check(s.gy.ensure(sizeof(float) * (int64_t)n * s.H * s.W), "output grad"));
+        s.cap_grad = n;
+    }
+    SG_TRY(check(s.loss.ensure(sizeof(float) * 8), "loss"));
+    return SG_OK;
+}
+
+sg_status refresh_bf16(sg_ctx* c, Surrogate& s)
+{
+    for (int L = 0; L < kNumL; ++L) {
+        const LayerDef& d = kLayers[L];
+        SG_TRY(check(weights_to_bf16((float*)s.master.p + s.w_off[L], s.w_n[L], (uint16_t*)s.wb.p + s.w_off[L],
+                                     (uint16_t*)s.wt.p + s.w_off[L], d.Co, 9, d.Ci, c->stream),
+                     "bf16 weights"));
+    }
+    return check(weights_to_bf16((float*)s.master.p + s.head_w, kHeadC, (uint16_t*)s.wb.p + s.head_w, nullptr, 1, 1,
+                                 kHeadC, c->stream),
+                 "bf16 head");
+}
+
+sg_status forward(sg_ctx* c, Surrogate& s, int n)
+{
+    for (int L = 0; L < kNumL; ++L) {
+        const LayerDef& d = kLayers[L];
+        const ConvShape sh = layer_shape(s, L, n);
+        ConvArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.a = (const uint16_t*)s.act[d.in].p;
+        a.b = (const uint16_t*)s.wb.p + s.w_off[L];
+        a.bias = (const float*)s.master.p + s.b_off[L];
+        a.relu = 1;
+        a.out_bf16 = (uint16_t*)s.act[d.out].p;
+        if (d.skip >= 0) {
+            a.skip = (const uint16_t*)s.act[d.skip].p;
+            a.out2_bf16 = (uint16_t*)s.act[d.out2].p;
+        }
+        SG_TRY(check(conv_gemm(0, geom_of(sh, 0), a, 1, c->stream), "forward conv"));
+    }
+    return check(head_fwd((const uint16_t*)s.act[D0].p, (const uint16_t*)s.wb.p + s.head_w,
+                          (const float*)s.master.p + s.head_b, (float*)s.yhat.p, (int64_t)n * s.H * s.W, kHeadC,
+                          c->stream),
+                 "head forward");
+}
+
+sg_status backward(sg_ctx* c, Surrogate& s, int n)
+{
+    bool written[kNumT] = {};
+    const int64_t P = (int64_t)n * s.H * s.W;
+    float* grad = (float*)s.grad.p;
+    const int hb = blocks_for(P);
+    SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)hb * (kHeadC + 1)), "head workspace"));
+    SG_TRY(check(head_bwd((const uint16_t*)s.act[D0].p, (const uint16_t*)s.wb.p + s.head_w, (const float*)s.gy.p,
+                          (float*)s.gact[D0].p, P, kHeadC, (float*)s.parts.p, hb, grad + s.head_w, c->stream),
+                 "head backward"));
+    written[D0] = true;
+    for (int L = kNumL - 1; L >= 0; --L) {
+        const LayerDef& d = kLayers[L];
+        const ConvShape sh = layer_shape(s, L, n);
+        const int go = d.out2 >= 0 ? d.out2 : d.out;   // gradient at the layer's (skip-added) output
+        const int64_t n_out = tensor_elems(s, d.out, n);
+        SG_TRY(check(mask_to_bf16((const float*)s.gact[go].p, (const uint16_t*)s.act[d.out].p, (uint16_t*)s.dpre.p,
+                                  n_out, c->stream),
+                     "relu mask"));
+        if (d.skip >= 0) {
+            // out2 = out + skip: the skip tensor receives the same gradient
+            SG_TRY(check(hipMemcpyAsync(s.gact[d.skip].p, s.gact[go].p, sizeof(float) * n_out,
+                                        hipMemcpyDeviceToDevice, c->stream),
+                         "skip gradient"));
+            written[d.skip] = true;
+        }
+        SG_TRY(wgrad(c, sh, (const uint16_t*)s.act[d.in].p, (const uint16_t*)s.dpre.p, grad + s.w_off[L],
+                     grad + s.b_off[L], s.parts));
+        if (L > 0) {
+            SG_TRY(dgrad(c, sh, (const uint16_t*)s.dpre.p, (const uint16_t*)s.wt.p + s.w_off[L],
+                         (float*)s.gact[d.in].p, written[d.in] ? 1 : 0, s.fine));
+            written[d.in] = true;
+        }
+    }
+    return SG_OK;
+}
+
+sg_status adam(sg_ctx* c, Surrogate& s, float lr)
+{
+    s.step += 1;
+    const float c1 = 1.f - std::pow(kBeta1, (float)s.step);
+    const float c2 = 1.f - std::pow(kBeta2, (float)s.step);
+    float* w = (float*)s.master.p;
+    float* m = (float*)s.mom1.p;
+    float* v = (float*)s.mom2.p;
+    const float* g = (const float*)s.grad.p;
+    for (int L = 0; L < kNumL; ++L) {
+        const LayerDef& d = kLayers[L];
+        const int64_t o = s.w_off[L];
+        SG_TRY(check(adam_step(w + o, m + o, v + o, g + o, s.w_n[L], lr, kBeta1, kBeta2, kEps, c1, c2,
+                               (uint16_t*)s.wb.p + o, (uint16_t*)s.wt.p + o, d.Co, 9, d.Ci, c->stream),
+                     "adam"));
+        const int64_t b = s.b_off[L];
+        SG_TRY(check(adam_step(w + b, m + b, v + b, g + b, d.Co, lr, kBeta1, kBeta2, kEps, c1, c2, nullptr, nullptr,
+                               1, 1, 1, c->stream),
+                     "adam bias"));
+    }
+    SG_TRY(check(adam_step(w + s.head_w, m + s.head_w, v + s.head_w, g + s.head_w, kHeadC, lr, kBeta1, kBeta2, kEps, c1,
+                           c2, (uint16_t*)s.wb.p + s.head_w, nullptr, 1, 1, kHeadC, c->stream),
+                 "adam head"));
+    return check(adam_step(w + s.head_b, m + s.head_b, v + s.head_b, g + s.head_b, 1, lr, kBeta1, kBeta2, kEps, c1, c2,
+                           nullptr, nullptr, 1, 1, 1, c->stream),
+                 "adam head bias");
+}
+
+sg_status check_frames(const Surrogate& s, int32_t n, const sg_probe* probes)
+{
+    for (int i = 0; i < n; ++i)
+        if (probes[i].W != s.W || probes[i].H != s.H)
+            return fail(SG_EINVAL, "env %d: probe %dx%d, the surrogate renders %dx%d", i, probes[i].W, probes[i].H,
+                        s.W, s.H);
+    if (n > 65535) return fail(SG_EINVAL, "at most 65535 envs per call");
+    return SG_OK;
+}
+
+// encode inputs of n envs into act[X] (and optionally render their targets)
+sg_status encode_and_render(sg_ctx* c, Surrogate& s, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
+                            const double* poses, float* target)
+{
+    std::vector<int64_t> offs(n);
+    for (int i = 0; i < n; ++i) offs[i] = (int64_t)i * s.H * s.W;
+    PhysArgs a;
+    StageInfo info;
+    SG_TRY(stage_physics(c, n, vol_ids, probes, poses, target ? target : (float*)s.yhat.p, offs.data(), nullptr, a,
+                         info));
+    SG_TRY(check(launch_encode(a, n, s.H * s.W, (uint16_t*)s.act[X].p, c->stream), "encode"));
+    if (target) SG_TRY(launch_physics(c, a, info));
+    return SG_OK;
+}
+
+}  // namespace
+}  // namespace sg
+
+using namespace sg;
+
+// ---------------------------------------------------------------------------
+// conv op entry points
+
+extern "C" sg_status sg_conv_forward(sg_ctx* c, const sg_conv_desc* d, const uint16_t* x, const uint16_t* w,
+                                     const float* bias, int32_t relu, const uint16_t* skip, uint16_t* y,
+                                     uint16_t* y_skip, float* y_f32)
+{
+    if (!c || !x || !w || (!y && !y_f32)) return fail(SG_EINVAL, "sg_conv_forward: NULL argument");
+    SG_TRY(check_desc(d));
+    if (skip && !y_skip) return fail(SG_EINVAL, "sg_conv_forward: skip given without y_skip");
+    (void)hipSetDevice(c->device);
+    const ConvShape sh = shape_of(d);
+    ConvArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.a = x;
+    a.b = w;
+    a.bias = bias;
+    a.relu = relu ? 1 : 0;
+    a.skip = skip;
+    a.out2_bf16 = y_skip;
+    a.out_bf16 = y;
+    a.out_f32 = y_f32;
+    return check(conv_gemm(0, geom_of(sh, 0), a, 1, c->stream), "conv forward");
+}
+
+extern "C" sg_status sg_conv_backward_data(sg_ctx* c, const sg_conv_desc* d, const uint16_t* dy, const uint16_t* w,
+                                           float* dx, int32_t accumulate)
+{
+    if (!c || !dy || !w || !dx) return fail(SG_EINVAL, "sg_conv_backward_data: NULL argument");
+    SG_TRY(check_desc(d));
+    (void)hipSetDevice(c->device);
+    const ConvShape sh = shape_of(d);
+    const int taps = sh.k * sh.k;
+    SG_TRY(check(c->op_wt.ensure(sizeof(uint16_t) * (size_t)sh.Co * taps * sh.C), "weight workspace"));
+    SG_TRY(check(transpose_w(w, (uint16_t*)c->op_wt.p, sh.Co, taps, sh.C, c->stream), "weight transpose"));
+    return dgrad(c, sh, dy, (const uint16_t*)c->op_wt.p, dx, accumulate ? 1 : 0, c->op_fine);
+}
+
+extern "C" sg_status sg_conv_backward_weight(sg_ctx* c, const sg_conv_desc* d, const uint16_t* x, const uint16_t* dy,
+                                             float* dw, float* db)
+{
+    if (!c || !x || !dy || !dw) return fail(SG_EINVAL, "sg_conv_backward_weight: NULL argument");
+    SG_TRY(check_desc(d));
+    (void)hipSetDevice(c->device);
+    return wgrad(c, shape_of(d), x, dy, dw, db, c->op_parts);
+}
+
+// ---------------------------------------------------------------------------
+// surrogate model
+
+extern "C" sg_status sg_surr_create(sg_ctx* c, int32_t H, int32_t W, uint64_t seed, int32_t* id)
+{
+    if (!c || !id) return fail(SG_EINVAL, "sg_surr_create: NULL argument");
+    if (H < 16 || W < 16 || H % 16 || W % 16 || H > SG_MAX_IMAGE || W > SG_MAX_IMAGE)
+        return fail(SG_EINVAL, "surrogate frame %dx%d: H and W must be multiples of 16 in [16, %d]", W, H,
+                    SG_MAX_IMAGE);
+    (void)hipSetDevice(c->device);
+    std::unique_ptr<Surrogate, SurrogateDeleter> s(new Surrogate());
+    s->H = H;
+    s->W = W;
+    int64_t off = 0;
+    for (int L = 0; L < kNumL; ++L) {
+        s->w_off[L] = off;
+        s->w_n[L] = (int64_t)kLayers[L].Co * 9 * kLayers[L].Ci;
+        off += s->w_n[L];
+        s->b_off[L] = off;
+        off += kLayers[L].Co;
+    }
+    s->head_w = off;
+    off += kHeadC;
+    s->head_b = off;
+    off += 1;
+    s->n_params = off;
+    // He-normal weights, zero biases; head bias at a mid-grey level
+    std::vector<float> h(off, 0.f);
+    std::mt19937_64 rng(seed);
+    for (int L = 0; L < kNumL; ++L) {
+        std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (9.f * kLayers[L].Ci)));
+        for (int64_t i = 0; i < s->w_n[L]; ++i) h[s->w_off[L] + i] = nd(rng);
+    }
+    std::normal_distribution<float> nh(0.f, std::sqrt(1.f / kHeadC));
+    for (int i = 0; i < kHeadC; ++i) h[s->head_w + i] = nh(rng);
+    h[s->head_b] = 0.2f;
+    const size_t bytes = sizeof(float) * off;
+    hipError_t e = s->master.ensure(bytes);
+    if (e == hipSuccess) e = s->mom1.ensure(bytes);
+    if (e == hipSuccess) e = s->mom2.ensure(bytes);
+    if (e == hipSuccess) e = s->grad.ensure(bytes);
+    if (e == hipSuccess) e = s->wb.ensure(sizeof(uint16_t) * off);
+    if (e == hipSuccess) e = s->wt.ensure(sizeof(uint16_t) * off);
+    if (e == hipSuccess) e = hipMemcpy(s->master.p, h.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(s->mom1.p, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(s->mom2.p, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(s->grad.p, 0, bytes);
+    if (e != hipSuccess) return hip_fail(e, "surrogate allocation");
+    SG_TRY(refresh_bf16(c, *s));
+    const int32_t sid = c->next_surr++;
+    c->surrogates[sid] = std::move(s);
+    *id = sid;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_destroy(sg_ctx* c, int32_t id)
+{
+    if (!find_surr(c, id)) return fail(SG_EINVAL, "sg_surr_destroy: bad surrogate id");
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    c->surrogates.erase(id);
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_num_params(sg_ctx* c, int32_t id, int64_t* n)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !n) return fail(SG_EINVAL, "sg_surr_num_params: bad surrogate id or NULL");
+    *n = s->n_params;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_train_step(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids,
+                                        const sg_probe* probes, const double* poses, float lr, float* loss)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !vol_ids || !probes || !poses || !loss) return fail(SG_EINVAL, "sg_surr_train_step: bad id or NULL");
+    if (n < 1) return fail(SG_EINVAL, "sg_surr_train_step: n_envs must be >= 1");
+    if (!(lr >= 0.f) || !std::isfinite(lr)) return fail(SG_EINVAL, "sg_surr_train_step: bad learning rate");
+    (void)hipSetDevice(c->device);
+    SG_TRY(check_frames(*s, n, probes));
+    SG_TRY(ensure_capacity(*s, n, true));
+    SG_TRY(encode_and_render(c, *s, n, vol_ids, probes, poses, (float*)s->target.p));
+    SG_TRY(forward(c, *s, n));
+    const int64_t P = (int64_t)n * s->H * s->W;
+    const int lb = blocks_for(P);
+    SG_TRY(check(s->parts.ensure(sizeof(float) * (size_t)lb), "loss workspace"));
+    SG_TRY(check(l1_loss((const float*)s->yhat.p, (const float*)s->target.p, P, (float*)s->gy.p, (float*)s->parts.p,
+                         lb, (float*)s->loss.p, c->stream),
+                 "loss"));
+    SG_TRY(backward(c, *s, n));
+    SG_TRY(adam(c, *s, lr));
+    s->last_n = n;
+    hipError_t e = hipMemcpyAsync(loss, s->loss.p, sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return check(e, "loss readback");
+}
+
+extern "C" sg_status sg_audit_decide(int32_t n_audit, const float* psnr, float psnr_min, float max_fail_frac,
+                                     int32_t* fallback, int32_t* whole)
+{
+    if (n_audit < 0 || (n_audit > 0 && (!psnr || !fallback)) || !whole)
+        return fail(SG_EINVAL, "sg_audit_decide: bad arguments");
+    int fails = 0;
+    for (int i = 0; i < n_audit; ++i) {
+        const bool bad = !(psnr[i] >= psnr_min);   // NaN fails
+        fallback[i] = bad ? 1 : 0;
+        fails += bad;
+    }
+    *whole = (n_audit > 0 && (double)fails > (double)max_fail_frac * (double)n_audit) ? 1 : 0;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_infer(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
+                                   const double* poses, float* out, const int32_t* audit_envs, int32_t n_audit,
+                                   float psnr_min, float max_fail_frac, float* psnr_out, int32_t* n_fallback)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !vol_ids || !probes || !poses || !out || !n_fallback)
+        return fail(SG_EINVAL, "sg_surr_infer: bad id or NULL");
+    if (n < 1 || n_audit < 0 || n_audit > n || (n_audit > 0 && (!audit_envs || !psnr_out)))
+        return fail(SG_EINVAL, "sg_surr_infer: bad sizes");
+    std::vector<char> seen(n, 0);
+    for (int i = 0; i < n_audit; ++i) {
+        const int e = audit_envs[i];
+        if (e < 0 || e >= n || seen[e]) return fail(SG_EINVAL, "sg_surr_infer: audit env %d out of range or repeated", e);
+        seen[e] = 1;
+    }
+    (void)hipSetDevice(c->device);
+    SG_TRY(check_frames(*s, n, probes));
+    SG_TRY(ensure_capacity(*s, n, false));
+    const int64_t HW = (int64_t)s->H * s->W;
+    SG_TRY(encode_and_render(c, *s, n, vol_ids, probes, poses, nullptr));
+    SG_TRY(forward(c, *s, n));
+    SG_TRY(check(clamp01((const float*)s->yhat.p, out, (int64_t)n * HW, c->stream), "clamp"));
+    *n_fallback = 0;
+    if (n_audit == 0) return check(hipStreamSynchronize(c->stream), "infer");
+    // render the audited envs with the physics path
+    std::vector<int32_t> av(audit_envs, audit_envs + n_audit);
+    std::vector<int32_t> a_vol(n_audit);
+    std::vector<sg_probe> a_probe(n_audit);
+    std::vector<double> a_pose(12 * (size_t)n_audit);
+    std::vector<int64_t> a_off(n_audit);
+    for (int i = 0; i < n_audit; ++i) {
+        a_vol[i] = vol_ids[av[i]];
+        a_probe[i] = probes[av[i]];
+        std::memcpy(&a_pose[12 * (size_t)i], poses + 12 * (size_t)av[i], 12 * sizeof(double));
+        a_off[i] = (int64_t)i * HW;
+    }
+    PhysArgs a;
+    StageInfo info;
+    SG_TRY(stage_physics(c, n_audit, a_vol.data(), a_probe.data(), a_pose.data(), (float*)s->target.p, a_off.data(),
+                         nullptr, a, info));
+    SG_TRY(launch_physics(c, a, info));
+    SG_TRY(check(s->idx.ensure(sizeof(int32_t) * n_audit), "audit index"));
+    SG_TRY(check(s->psnr.ensure(sizeof(float) * n_audit), "audit psnr"));
+    SG_TRY(check(hipMemcpyAsync(s->idx.p, av.data(), sizeof(int32_t) * n_audit, hipMemcpyHostToDevice, c->stream),
+                 "audit index upload"));
+    SG_TRY(check(psnr_indexed(out, (const float*)s->target.p, (const int32_t*)s->idx.p, n_audit, HW,
+                              (float*)s->psnr.p, c->stream),
+                 "audit psnr"));
+    SG_TRY(check(hipMemcpyAsync(psnr_out, s->psnr.p, sizeof(float) * n_audit, hipMemcpyDeviceToHost, c->stream),
+                 "psnr readback"));
+    SG_TRY(check(hipStreamSynchronize(c->stream), "audit"));
+    std::vector<int32_t> fb(n_audit);
+    int32_t whole = 0;
+    SG_TRY(sg_audit_decide(n_audit, psnr_out, psnr_min, max_fail_frac, fb.data(), &whole));
+    if (whole) {
+        std::vector<int64_t> offs(n);
+        for (int i = 0; i < n; ++i) offs[i] = (int64_t)i * HW;
+        SG_TRY(stage_physics(c, n, vol_ids, probes, poses, out, offs.data(), nullptr, a, info));
+        SG_TRY(launch_physics(c, a, info));
+        *n_fallback = n;
+    } else {
+        int nf = 0;
+        for (int i = 0; i < n_audit; ++i) {
+            if (!fb[i]) continue;
+            SG_TRY(check(hipMemcpyAsync(out + (int64_t)av[i] * HW, (const float*)s->target.p + (int64_t)i * HW,
+                                        sizeof(float) * HW, hipMemcpyDeviceToDevice, c->stream),
+                         "fallback copy"));
+            ++nf;
+        }
+        *n_fallback = nf;
+    }
+    return check(hipStreamSynchronize(c->stream), "infer");
+}
+
+namespace {
+const char kMagic[8] = {'S', 'G', 'S', 'U', 'R', 'R', '0', '1'};
+}
+
+extern "C" sg_status sg_surr_save(sg_ctx* c, int32_t id, const char* path)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !path) return fail(SG_EINVAL, "sg_surr_save: bad id or NULL path");
+    (void)hipSetDevice(c->device);
+    const size_t n = (size_t)s->n_params;
+    std::vector<float> buf(3 * n);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(buf.data(), s->master.p, sizeof(float) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(buf.data() + n, s->mom1.p, sizeof(float) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(buf.data() + 2 * n, s->mom2.p, sizeof(float) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint readback");
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(SG_EINVAL, "cannot open %s for writing", path);
+    const int32_t hw[2] = {s->H, s->W};
+    const int64_t meta[2] = {s->n_params, s->step};
+    bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(hw, sizeof(hw), 1, f) == 1 &&
+              std::fwrite(meta, sizeof(meta), 1, f) == 1 && std::fwrite(buf.data(), sizeof(float), 3 * n, f) == 3 * n;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? SG_OK : fail(SG_EINVAL, "write to %s failed", path);
+}
+
+extern "C" sg_status sg_surr_load(sg_ctx* c, int32_t id, const char* path)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !path) return fail(SG_EINVAL, "sg_surr_load: bad id or NULL path");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(SG_EINVAL, "cannot open %s", path);
+    char magic[8];
+    int32_t hw[2];
+    int64_t meta[2];
+    const size_t n = (size_t)s->n_params;
+    std::vector<float> buf(3 * n);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+              std::fread(hw, sizeof(hw), 1, f) == 1 && std::fread(meta, sizeof(meta), 1, f) == 1 &&
+              hw[0] == s->H && hw[1] == s->W && meta[0] == s->n_params &&
+              std::fread(buf.data(), sizeof(float), 3 * n, f) == 3 * n;
+    std::fclose(f);
+    if (!ok) return fail(SG_EINVAL, "%s is not a checkpoint of this surrogate (%dx%d, %lld params)", path, s->W,
+                         s->H, (long long)s->n_params);
+    (void)hipSetDevice(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(s->master.p, buf.data(), sizeof(float) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->mom1.p, buf.data() + n, sizeof(float) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->mom2.p, buf.data() + 2 * n, sizeof(float) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint upload");
+    s->step = meta[1];
+    return refresh_bf16(c, *s);
+}
+
+extern "C" sg_status sg_surr_get_params(sg_ctx* c, int32_t id, float* host)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !host) return fail(SG_EINVAL, "sg_surr_get_params: bad id or NULL");
+    (void)hipSetDevice(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(host, s->master.p, sizeof(float) * s->n_params, hipMemcpyDeviceToHost);
+    return check(e, "parameter readback");
+}
+
+extern "C" sg_status sg_surr_get_grads(sg_ctx* c, int32_t id, float* host)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !host) return fail(SG_EINVAL, "sg_surr_get_grads: bad id or NULL");
+    (void)hipSetDevice(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(host, s->grad.p, sizeof(float) * s->n_params, hipMemcpyDeviceToHost);
+    return check(e, "gradient readback");
+}
+
+extern "C" sg_status sg_surr_set_params(sg_ctx* c, int32_t id, const float* host)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !host) return fail(SG_EINVAL, "sg_surr_set_params: bad id or NULL");
+    (void)hipSetDevice(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(s->master.p, host, sizeof(float) * s->n_params, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "parameter upload");
+    return refresh_bf16(c, *s);
+}
+
+extern "C" sg_status sg_surr_get_batch(sg_ctx* c, int32_t id, uint16_t* input, float* target)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || (!input && !target)) return fail(SG_EINVAL, "sg_surr_get_batch: bad id or NULL");
+    if (s->last_n < 1) return fail(SG_ESTATE, "sg_surr_get_batch: no training step yet");
+    (void)hipSetDevice(c->device);
+    const int64_t P = (int64_t)s->last_n * s->H * s->W;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && input) e = hipMemcpy(input, s->act[X].p, sizeof(uint16_t) * 8 * P, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && target) e = hipMemcpy(target, s->target.p, sizeof(float) * P, hipMemcpyDeviceToHost);
+    return check(e, "batch readback");
+}

@@ -1,0 +1,95 @@
+// Internal declarations of the surrogate network's kernels (conv_mfma.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+// GEMM view of one convolution product (see conv_mfma.hip).
+struct ConvGeom {
+    int64_t M;      // GEMM rows
+    int32_t N;      // GEMM columns
+    int32_t K;      // reduction length (forward / data gradient)
+    int64_t Kw;     // reduction length of the weight gradient (pixels)
+    int32_t C, Co;  // input / output channels
+    int32_t H, W;   // stored input size (before the optional x2 upsampling)
+    int32_t Ho, Wo; // output size
+    int32_t kh, kw, stride, pad, up;
+};
+
+struct ConvArgs {
+    const uint16_t* a;       // forward: x; data gradient: dy; weight gradient: dy
+    const uint16_t* b;       // forward: W [Co][K]; data gradient: WT [Ci][K]; weight gradient: x
+    const float* bias;       // forward, may be null
+    int32_t relu;            // forward
+    const uint16_t* skip;    // forward: second output = out + skip (may be null)
+    uint16_t* out2_bf16;
+    uint16_t* out_bf16;      // forward
+    float* out_f32;          // forward (optional), data gradient, weight gradient partials
+    int32_t accumulate;      // data gradient: add into out_f32
+    int64_t k_chunk;         // weight gradient: pixels per split (multiple of 32)
+};
+
+// convolution shape of one layer (per batch)
+struct ConvShape {
+    int N, H, W, C, Co, k, stride, pad, up;
+    int Hin() const { return up ? 2 * H : H; }
+    int Win() const { return up ? 2 * W : W; }
+    int Ho() const { return (Hin() + 2 * pad - k) / stride + 1; }
+    int Wo() const { return (Win() + 2 * pad - k) / stride + 1; }
+};
+
+inline ConvGeom geom_of(const ConvShape& s, int mode)
+{
+    ConvGeom g;
+    g.C = s.C;
+    g.Co = s.Co;
+    g.H = s.H;
+    g.W = s.W;
+    g.Ho = s.Ho();
+    g.Wo = s.Wo();
+    g.kh = g.kw = s.k;
+    g.stride = s.stride;
+    g.pad = s.pad;
+    g.up = s.up;
+    g.Kw = (int64_t)s.N * g.Ho * g.Wo;
+    if (mode == 0) {
+        g.M = (int64_t)s.N * g.Ho * g.Wo;
+        g.N = s.Co;
+        g.K = s.k * s.k * s.C;
+    } else if (mode == 1) {
+        g.M = (int64_t)s.N * s.Hin() * s.Win();
+        g.N = s.C;
+        g.K = s.k * s.k * s.Co;
+    } else {
+        g.M = s.Co;
+        g.N = s.k * s.k * s.C;
+        g.K = 0;
+    }
+    return g;
+}
+
+hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s);
+int wgrad_tile_m(int M);
+hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s);
+hipError_t pool2x2_sum(const float* fine, float* coarse, int N, int H, int W, int C, int accumulate, hipStream_t s);
+hipError_t colsum_bf16(const uint16_t* x, int64_t rows, int cols, float* part, int blocks, float* out,
+                       hipStream_t s);
+hipError_t sum_parts(const float* part, int64_t n, int splits, float* out, hipStream_t s);
+hipError_t head_fwd(const uint16_t* x, const uint16_t* w, const float* b, float* y, int64_t P, int C, hipStream_t s);
+hipError_t head_bwd(const uint16_t* x, const uint16_t* w, const float* g, float* dx, int64_t P, int C, float* part,
+                    int blocks, float* dwb, hipStream_t s);
+hipError_t l1_loss(const float* yhat, const float* y, int64_t n, float* grad, float* part, int blocks, float* loss,
+                   hipStream_t s);
+hipError_t adam_step(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                     float c1, float c2, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci, hipStream_t s);
+hipError_t weights_to_bf16(const float* w, int64_t n, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci,
+                           hipStream_t s);
+hipError_t psnr_frames(const float* yhat, const float* y, int n_frames, int64_t frame, float* psnr, hipStream_t s);
+hipError_t psnr_indexed(const float* yhat, const float* y, const int32_t* idx, int n_frames, int64_t frame,
+                        float* psnr, hipStream_t s);
+hipError_t transpose_w(const uint16_t* w, uint16_t* wt, int Co, int taps, int Ci, hipStream_t s);
+hipError_t clamp01(const float* x, float* y, int64_t n, hipStream_t s);
+
+}  // namespace sg

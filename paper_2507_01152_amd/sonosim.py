@@ -25,6 +25,10 @@ SYMBOLS = (
     "sg_batch_plan_create", "sg_batch_poses", "sg_batch_set_poses", "sg_batch_step",
     "sg_batch_step_profiled", "sg_batch_status", "sg_autotune",
     "sg_batch_config", "sg_batch_plan_destroy",
+    "sg_conv_forward", "sg_conv_backward_data", "sg_conv_backward_weight",
+    "sg_surr_create", "sg_surr_destroy", "sg_surr_num_params", "sg_surr_train_step", "sg_surr_infer",
+    "sg_audit_decide", "sg_surr_save", "sg_surr_load", "sg_surr_get_params", "sg_surr_get_grads",
+    "sg_surr_set_params", "sg_surr_get_batch",
 )
 
 
@@ -49,6 +53,11 @@ class sg_probe(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("dx_mm", C.c_double), ("dy_mm", C.c_double),
                 ("f_mhz", C.c_double), ("E0", C.c_double), ("psf_frac", C.c_double),
                 ("dr_db", C.c_double)]
+
+
+class sg_conv_desc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("H", C.c_int32), ("W", C.c_int32), ("C", C.c_int32), ("Co", C.c_int32),
+                ("kernel", C.c_int32), ("stride", C.c_int32), ("pad", C.c_int32), ("upsample", C.c_int32)]
 
 
 class sg_debug_planes(C.Structure):
@@ -88,6 +97,21 @@ def load():
         "sg_autotune": [VP, I32, C.c_char_p],
         "sg_batch_config": [VP, I32, P(I32), P(I32), P(I32)],
         "sg_batch_plan_destroy": [VP, I32],
+        "sg_conv_forward": [VP, P(sg_conv_desc), VP, VP, VP, I32, VP, VP, VP, VP],
+        "sg_conv_backward_data": [VP, P(sg_conv_desc), VP, VP, VP, I32],
+        "sg_conv_backward_weight": [VP, P(sg_conv_desc), VP, VP, VP, VP],
+        "sg_surr_create": [VP, I32, I32, C.c_uint64, P(I32)],
+        "sg_surr_destroy": [VP, I32],
+        "sg_surr_num_params": [VP, I32, P(C.c_int64)],
+        "sg_surr_train_step": [VP, I32, I32, VP, VP, VP, C.c_float, P(C.c_float)],
+        "sg_surr_infer": [VP, I32, I32, VP, VP, VP, VP, VP, I32, C.c_float, C.c_float, VP, P(I32)],
+        "sg_audit_decide": [I32, VP, C.c_float, C.c_float, VP, P(I32)],
+        "sg_surr_save": [VP, I32, C.c_char_p],
+        "sg_surr_load": [VP, I32, C.c_char_p],
+        "sg_surr_get_params": [VP, I32, VP],
+        "sg_surr_get_grads": [VP, I32, VP],
+        "sg_surr_set_params": [VP, I32, VP],
+        "sg_surr_get_batch": [VP, I32, VP, VP],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -249,3 +273,113 @@ def sg_batch_config(ctx, plan_id: int):
 
 def sg_batch_plan_destroy(ctx, plan_id: int):
     _check(load().sg_batch_plan_destroy(ctx, int(plan_id)), "sg_batch_plan_destroy")
+
+
+# ---------------------------------------------------------------------------
+# convolution ops and the surrogate
+
+def conv_desc(N, H, W, C_, Co, kernel=3, stride=1, pad=1, upsample=0):
+    return sg_conv_desc(N, H, W, C_, Co, kernel, stride, pad, upsample)
+
+
+def sg_conv_forward(ctx, desc, x, w, bias=None, relu=False, skip=None, y=None, y_skip=None, y_f32=None):
+    """x, w, skip, y, y_skip: device bf16 tensors (torch.int16/uint16 storage or bfloat16);
+    bias, y_f32: device float32."""
+    _check(load().sg_conv_forward(ctx, C.byref(desc), _dptr(x), _dptr(w), _dptr(bias), int(bool(relu)), _dptr(skip),
+                                  _dptr(y), _dptr(y_skip), _dptr(y_f32)), "sg_conv_forward")
+
+
+def sg_conv_backward_data(ctx, desc, dy, w, dx, accumulate=False):
+    _check(load().sg_conv_backward_data(ctx, C.byref(desc), _dptr(dy), _dptr(w), _dptr(dx), int(bool(accumulate))),
+           "sg_conv_backward_data")
+
+
+def sg_conv_backward_weight(ctx, desc, x, dy, dw, db=None):
+    _check(load().sg_conv_backward_weight(ctx, C.byref(desc), _dptr(x), _dptr(dy), _dptr(dw), _dptr(db)),
+           "sg_conv_backward_weight")
+
+
+def sg_surr_create(ctx, H=256, W=128, seed=0) -> int:
+    sid = C.c_int32()
+    _check(load().sg_surr_create(ctx, int(H), int(W), int(seed) & ((1 << 64) - 1), C.byref(sid)), "sg_surr_create")
+    return int(sid.value)
+
+
+def sg_surr_destroy(ctx, sid):
+    _check(load().sg_surr_destroy(ctx, int(sid)), "sg_surr_destroy")
+
+
+def sg_surr_num_params(ctx, sid) -> int:
+    n = C.c_int64()
+    _check(load().sg_surr_num_params(ctx, int(sid), C.byref(n)), "sg_surr_num_params")
+    return int(n.value)
+
+
+def sg_surr_train_step(ctx, sid, vol_ids, probes, poses, lr) -> float:
+    n = len(probes)
+    vids = np.ascontiguousarray(vol_ids, dtype=np.int32)
+    pa = probes_array(probes)
+    ps = np.ascontiguousarray(poses, dtype=np.float64).reshape(n, 12)
+    loss = C.c_float()
+    _check(load().sg_surr_train_step(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data,
+                                     float(lr), C.byref(loss)), "sg_surr_train_step")
+    return float(loss.value)
+
+
+def sg_surr_infer(ctx, sid, vol_ids, probes, poses, out, audit_envs=(), psnr_min=30.0, max_fail_frac=0.25):
+    """Returns (psnr of the audited envs, number of frames rendered by physics)."""
+    n = len(probes)
+    vids = np.ascontiguousarray(vol_ids, dtype=np.int32)
+    pa = probes_array(probes)
+    ps = np.ascontiguousarray(poses, dtype=np.float64).reshape(n, 12)
+    au = np.ascontiguousarray(audit_envs, dtype=np.int32)
+    psnr = np.zeros(max(1, len(au)), dtype=np.float32)
+    nf = C.c_int32()
+    _check(load().sg_surr_infer(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data, _dptr(out),
+                                au.ctypes.data if len(au) else None, len(au), float(psnr_min), float(max_fail_frac),
+                                psnr.ctypes.data if len(au) else None, C.byref(nf)), "sg_surr_infer")
+    return psnr[:len(au)], int(nf.value)
+
+
+def sg_audit_decide(psnr, psnr_min, max_fail_frac):
+    p = np.ascontiguousarray(psnr, dtype=np.float32)
+    fb = np.zeros(max(1, len(p)), dtype=np.int32)
+    whole = C.c_int32()
+    _check(load().sg_audit_decide(len(p), p.ctypes.data if len(p) else None, float(psnr_min), float(max_fail_frac),
+                                  fb.ctypes.data, C.byref(whole)), "sg_audit_decide")
+    return fb[:len(p)].astype(bool), bool(whole.value)
+
+
+def sg_surr_save(ctx, sid, path):
+    _check(load().sg_surr_save(ctx, int(sid), str(path).encode()), "sg_surr_save")
+
+
+def sg_surr_load(ctx, sid, path):
+    _check(load().sg_surr_load(ctx, int(sid), str(path).encode()), "sg_surr_load")
+
+
+def sg_surr_get_params(ctx, sid) -> np.ndarray:
+    h = np.zeros(sg_surr_num_params(ctx, sid), dtype=np.float32)
+    _check(load().sg_surr_get_params(ctx, int(sid), h.ctypes.data), "sg_surr_get_params")
+    return h
+
+
+def sg_surr_get_grads(ctx, sid) -> np.ndarray:
+    h = np.zeros(sg_surr_num_params(ctx, sid), dtype=np.float32)
+    _check(load().sg_surr_get_grads(ctx, int(sid), h.ctypes.data), "sg_surr_get_grads")
+    return h
+
+
+def sg_surr_set_params(ctx, sid, params):
+    h = np.ascontiguousarray(params, dtype=np.float32)
+    if h.size != sg_surr_num_params(ctx, sid):
+        raise ValueError("wrong parameter count")
+    _check(load().sg_surr_set_params(ctx, int(sid), h.ctypes.data), "sg_surr_set_params")
+
+
+def sg_surr_get_batch(ctx, sid, n, H, W):
+    """(input bf16 bits uint16 [n,H,W,8], target float32 [n,H,W]) of the last training step."""
+    x = np.zeros((n, H, W, 8), dtype=np.uint16)
+    y = np.zeros((n, H, W), dtype=np.float32)
+    _check(load().sg_surr_get_batch(ctx, int(sid), x.ctypes.data, y.ctypes.data), "sg_surr_get_batch")
+    return x, y

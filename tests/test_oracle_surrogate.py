@@ -1,0 +1,120 @@
+"""Pins of the surrogate oracle: torch's bfloat16 conversion, torch FP64
+conv2d and its autograd (library routines), central finite differences of
+the whole network, and the closed form of a first Adam step.  CPU only."""
+import numpy as np
+import pytest
+
+from oracle import surrogate as so
+
+torch = pytest.importorskip("torch")
+F = torch.nn.functional
+
+
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000),
+                        np.array([0.0, -0.0, 1.0, 1.00390625, 1.01171875, 65504.0, 3.0e38])])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(so.bf16_round(x), ref)
+    bits = so.f64_to_bf16_bits(x)
+    assert np.array_equal(so.bf16_bits_to_f64(bits), ref)
+
+
+def _torch_conv(x, w, b, stride, pad, up):
+    xt = torch.tensor(x).permute(0, 3, 1, 2)
+    if up:
+        xt = F.interpolate(xt, scale_factor=2, mode="nearest")
+    wt = torch.tensor(w).permute(0, 3, 1, 2)
+    return F.conv2d(xt, wt, None if b is None else torch.tensor(b), stride=stride, padding=pad)
+
+
+@pytest.mark.parametrize("k,stride,pad,up", [(3, 1, 1, False), (3, 2, 1, False), (3, 1, 1, True), (1, 1, 0, False),
+                                             (3, 2, 0, False)])
+def test_conv_ops_match_torch_autograd(k, stride, pad, up):
+    rng = np.random.default_rng(1)
+    N, H, W, C, Co = 2, 6, 10, 8, 16
+    x = rng.standard_normal((N, H, W, C))
+    w = rng.standard_normal((Co, k, k, C))
+    b = rng.standard_normal(Co)
+    y = so.conv_forward(x, w, b, stride=stride, pad=pad, up=up)
+    xt = torch.tensor(x, requires_grad=True)
+    wt = torch.tensor(w, requires_grad=True)
+    bt = torch.tensor(b, requires_grad=True)
+    xin = xt.permute(0, 3, 1, 2)
+    if up:
+        xin = F.interpolate(xin, scale_factor=2, mode="nearest")
+    yt = F.conv2d(xin, wt.permute(0, 3, 1, 2), bt, stride=stride, padding=pad).permute(0, 2, 3, 1)
+    assert y.shape == tuple(yt.shape)
+    assert np.allclose(y, yt.detach().numpy(), rtol=1e-12, atol=1e-12)
+    dy = rng.standard_normal(y.shape)
+    (yt * torch.tensor(dy)).sum().backward()
+    dx = so.conv_backward_data(dy, w, x.shape, stride=stride, pad=pad, up=up)
+    dw, db = so.conv_backward_weight(x, dy, k=k, stride=stride, pad=pad, up=up)
+    assert np.allclose(dx, xt.grad.numpy(), rtol=1e-12, atol=1e-11)
+    assert np.allclose(dw, wt.grad.numpy(), rtol=1e-12, atol=1e-11)
+    assert np.allclose(db, bt.grad.numpy(), rtol=1e-12, atol=1e-11)
+
+
+def _small_problem(seed=3, H=16, W=16):
+    rng = np.random.default_rng(seed)
+    layout, n = so.param_layout()
+    flat = np.zeros(n)
+    for name, o, shape in layout:
+        fan = int(np.prod(shape[1:])) if name.startswith("w") else 1
+        scale = np.sqrt(2.0 / fan) if name.startswith("w") else 0.05
+        flat[o:o + int(np.prod(shape))] = rng.standard_normal(int(np.prod(shape))) * scale
+    x = np.zeros((1, H, W, 8))
+    lab = rng.integers(0, 4, size=(H, W))
+    x[0, np.arange(H)[:, None], np.arange(W)[None, :], lab] = 1.0
+    x[0, :, :, 4] = rng.standard_normal((H, W))
+    y = rng.uniform(0, 1, size=(1, H, W))
+    return flat, x, y
+
+
+def test_network_parameter_count():
+    _, n = so.param_layout()
+    assert 1_700_000 < n < 2_100_000     # about 2M parameters
+
+
+def test_network_gradient_matches_finite_differences():
+    """Without bf16 rounding the network is piecewise linear; central
+    differences on random parameters of every layer pin the backward pass
+    (skip copies, upsampling adjoint, strides, head)."""
+    flat, x, y = _small_problem()
+    loss, g, _ = so.loss_and_grads(flat, x, y, rounding=False)
+    layout, _ = so.param_layout()
+    rng = np.random.default_rng(7)
+    eps = 1e-6
+    checked = 0
+    for name, o, shape in layout:
+        size = int(np.prod(shape))
+        for idx in rng.choice(size, size=min(3, size), replace=False):
+            i = o + int(idx)
+            fp, fm = flat.copy(), flat.copy()
+            fp[i] += eps
+            fm[i] -= eps
+            lp = so.loss_and_grads(fp, x, y, rounding=False)[0]
+            lm = so.loss_and_grads(fm, x, y, rounding=False)[0]
+            fd = (lp - lm) / (2 * eps)
+            assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-9, (name, idx, fd, g[i])
+            checked += 1
+    assert checked > 50
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(4)
+    w = rng.standard_normal(100)
+    g = rng.standard_normal(100)
+    w1, m, v = so.adam_update(w, g, np.zeros(100), np.zeros(100), step=1, lr=1e-3)
+    # with zero moments the first bias-corrected step is lr * g / (|g| + eps)
+    assert np.allclose(w1, w - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+    assert np.allclose(m, 0.5 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_forward_shapes_and_psnr():
+    flat, x, y = _small_problem(H=32, W=16)
+    act, yhat = so.forward(so.unflatten(flat), x)
+    assert yhat.shape == (1, 32, 16)
+    assert act["B4"].shape == (1, 2, 1, 256) and act["S0"].shape == (1, 32, 16, 16)
+    assert so.psnr(y, y) == 200.0
+    assert abs(so.psnr(np.full_like(y, 0.5), np.full_like(y, 0.6)) - 20.0) < 1e-9

@@ -1,0 +1,243 @@
+"""Surrogate kernels and model through the C ABI vs the FP64 oracle (GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import surrogate as so
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+U = 2.0 ** -24   # FP32 unit roundoff: products of bf16 are exact in FP32
+
+
+@pytest.fixture(scope="module")
+def sess():
+    from paper_2507_01152_amd.session import Session
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = Session(0)
+    yield s
+    s.close()
+
+
+def dev_bf16(a):
+    return torch.from_numpy(so.f64_to_bf16_bits(a).view(np.int16)).cuda()
+
+
+def host_bf16(t):
+    return so.bf16_bits_to_f64(t.cpu().numpy().view(np.uint16))
+
+
+CONV_CASES = [
+    # N, H, W, C, Co, k, stride, pad, up
+    (2, 16, 12, 8, 16, 3, 1, 1, 0),
+    (1, 13, 17, 16, 32, 3, 2, 1, 0),     # ragged output tiles
+    (2, 8, 6, 32, 64, 3, 1, 1, 1),       # upsampled input
+    (1, 9, 7, 64, 128, 3, 2, 1, 0),
+    (1, 5, 4, 256, 256, 3, 1, 1, 0),
+    (1, 4, 3, 128, 64, 3, 1, 1, 1),
+    (3, 11, 5, 24, 40, 1, 1, 0, 0),      # 1x1, channel counts not powers of two
+]
+
+
+@pytest.mark.parametrize("case", CONV_CASES)
+def test_conv_forward_parity(sess, case):
+    from paper_2507_01152_amd import sonosim as sg
+    N, H, W, C, Co, k, st, pad, up = case
+    rng = np.random.default_rng(sum(case))
+    x = so.bf16_round(rng.standard_normal((N, H, W, C)))
+    w = so.bf16_round(rng.standard_normal((Co, k, k, C)) * 0.2)
+    b = rng.standard_normal(Co).astype(np.float32).astype(np.float64)
+    ref = so.conv_forward(x, w, b, stride=st, pad=pad, up=up, relu=True)
+    mag = so.conv_forward(np.abs(x), np.abs(w), np.abs(b), stride=st, pad=pad, up=up)
+    skip = so.bf16_round(rng.standard_normal(ref.shape))
+    y = torch.empty(ref.shape, dtype=torch.int16, device="cuda")
+    ys = torch.empty_like(y)
+    yf = torch.empty(ref.shape, dtype=torch.float32, device="cuda")
+    d = sg.conv_desc(N, H, W, C, Co, k, st, pad, up)
+    sg.sg_conv_forward(sess.ctx, d, dev_bf16(x), dev_bf16(w), torch.tensor(b, dtype=torch.float32, device="cuda"),
+                       True, dev_bf16(skip), y, ys, yf)
+    torch.cuda.synchronize()
+    K = k * k * C
+    tol = (K + 2) * U * mag + 1e-30
+    got = yf.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= tol)
+    # the bf16 output is the FP32 value rounded; the skip output adds in bf16
+    assert np.array_equal(host_bf16(y), so.bf16_round(got))
+    assert np.array_equal(host_bf16(ys), so.bf16_round(so.bf16_round(got) + skip))
+
+
+@pytest.mark.parametrize("case", CONV_CASES)
+def test_conv_backward_parity(sess, case):
+    from paper_2507_01152_amd import sonosim as sg
+    N, H, W, C, Co, k, st, pad, up = case
+    rng = np.random.default_rng(100 + sum(case))
+    x = so.bf16_round(rng.standard_normal((N, H, W, C)))
+    w = so.bf16_round(rng.standard_normal((Co, k, k, C)) * 0.2)
+    y_shape = so.conv_forward(x, w, stride=st, pad=pad, up=up).shape
+    dy = so.bf16_round(rng.standard_normal(y_shape))
+    d = sg.conv_desc(N, H, W, C, Co, k, st, pad, up)
+    # data gradient, written then accumulated
+    dx_ref = so.conv_backward_data(dy, w, x.shape, stride=st, pad=pad, up=up)
+    dx_mag = so.conv_backward_data(np.abs(dy), np.abs(w), x.shape, stride=st, pad=pad, up=up)
+    dx = torch.empty(x.shape, dtype=torch.float32, device="cuda")
+    sg.sg_conv_backward_data(sess.ctx, d, dev_bf16(dy), dev_bf16(w), dx, False)
+    torch.cuda.synchronize()
+    Kd = k * k * Co * (4 if up else 1)
+    got = dx.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - dx_ref) <= (Kd + 2) * U * dx_mag + 1e-30)
+    sg.sg_conv_backward_data(sess.ctx, d, dev_bf16(dy), dev_bf16(w), dx, True)
+    torch.cuda.synchronize()
+    got2 = dx.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got2 - 2 * dx_ref) <= 2 * (Kd + 3) * U * dx_mag + 1e-30)
+    # weight and bias gradients
+    dw_ref, db_ref = so.conv_backward_weight(x, dy, k=k, stride=st, pad=pad, up=up)
+    dw_mag, db_mag = so.conv_backward_weight(np.abs(x), np.abs(dy), k=k, stride=st, pad=pad, up=up)
+    dw = torch.empty(w.shape, dtype=torch.float32, device="cuda")
+    db = torch.empty(Co, dtype=torch.float32, device="cuda")
+    sg.sg_conv_backward_weight(sess.ctx, d, dev_bf16(x), dev_bf16(dy), dw, db)
+    torch.cuda.synchronize()
+    Kw = int(np.prod(y_shape[:3]))
+    assert np.all(np.abs(dw.cpu().numpy() - dw_ref) <= (Kw + 2) * U * dw_mag + 1e-30)
+    assert np.all(np.abs(db.cpu().numpy() - db_ref) <= (Kw + 2) * U * db_mag + 1e-30)
+    # deterministic: a second run is bit-identical
+    dw2 = torch.empty_like(dw)
+    sg.sg_conv_backward_weight(sess.ctx, d, dev_bf16(x), dev_bf16(dy), dw2, None)
+    torch.cuda.synchronize()
+    assert torch.equal(dw, dw2)
+
+
+def _pairs(n, H, W, seed):
+    """n envs on 64^3 ellipsoid phantoms imaged at H x W (0.25 mm pixels)."""
+    return synth.ellipsoid_workload(seed=seed, n_envs=n, W=W, H=H, dx=0.25, dy=0.25)
+
+
+def test_encoder_channels_match_oracle(sess):
+    from paper_2507_01152_amd import sonosim as sg
+    H, W = 48, 32
+    wl = _pairs(2, H, W, seed=21)
+    vids = sess.load(wl)
+    sid = sg.sg_surr_create(sess.ctx, H, W, seed=1)
+    sg.sg_surr_train_step(sess.ctx, sid, vids, wl.probes, wl.poses, 0.0)
+    xin, _ = sg.sg_surr_get_batch(sess.ctx, sid, 2, H, W)
+    x = so.bf16_bits_to_f64(xin)
+    t1 = wl.table.copy()
+    t1[:, 2] = 0.0   # mu0 = 0, sigma0 = 1: the oracle's T is the gated N0
+    t1[:, 3] = 1.0
+    for e in range(2):
+        o = oracle.simulate_env(wl.volumes[e], t1, wl.probes[e], wl.poses[e], planes=("label", "T"))
+        onehot = np.eye(4)[o["label"]]
+        assert np.array_equal(x[e, :, :, :4], onehot)
+        assert np.all(x[e, :, :, 5:] == 0)
+        ref = o["T"]
+        assert np.array_equal(x[e, :, :, 4] != 0, ref != 0)
+        # within one bf16 step of the FP64 value
+        assert np.all(np.abs(x[e, :, :, 4] - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-6)
+    sg.sg_surr_destroy(sess.ctx, sid)
+
+
+def test_training_gradients_match_oracle(sess):
+    """Every layer's gradient of one training step against the FP64 network
+    oracle on the same bf16 input and target.  bf16 rounding flips of single
+    activations (FP32 vs FP64 sums) make the layers differ by about 1e-3 to
+    1e-2 in norm.  The flips matter most in the deepest levels, which have
+    the fewest pixels, so the frames are 128 x 64 (8 x 4 at the bottleneck)."""
+    from paper_2507_01152_amd import sonosim as sg
+    H, W, n = 128, 64, 2
+    wl = _pairs(n, H, W, seed=5)
+    vids = sess.load(wl)
+    sid = sg.sg_surr_create(sess.ctx, H, W, seed=11)
+    p0 = sg.sg_surr_get_params(sess.ctx, sid)
+    loss = sg.sg_surr_train_step(sess.ctx, sid, vids, wl.probes, wl.poses, 0.0)
+    g = sg.sg_surr_get_grads(sess.ctx, sid).astype(np.float64)
+    xin, tgt = sg.sg_surr_get_batch(sess.ctx, sid, n, H, W)
+    ref_loss, ref_g, _ = so.loss_and_grads(p0.astype(np.float64), so.bf16_bits_to_f64(xin), tgt.astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+    layout, _ = so.param_layout()
+    for name, o, shape in layout:
+        sz = int(np.prod(shape))
+        a, b = g[o:o + sz], ref_g[o:o + sz]
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        cos = float(a @ b) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
+        assert err <= 2e-2 and cos >= 0.999, (name, err, cos)
+    # one Adam step from zero moments moves each weight by lr * g / (|g| + eps)
+    lr = 1e-3
+    sid2 = sg.sg_surr_create(sess.ctx, H, W, seed=11)
+    sg.sg_surr_train_step(sess.ctx, sid2, vids, wl.probes, wl.poses, lr)
+    g2 = sg.sg_surr_get_grads(sess.ctx, sid2).astype(np.float64)
+    p1 = sg.sg_surr_get_params(sess.ctx, sid2).astype(np.float64)
+    expect = p0 - lr * g2 / (np.abs(g2) + 1e-8)
+    # FP32 bias corrections (0.999 is not exact in FP32) allow ~1e-5 relative
+    assert np.allclose(p1, expect, rtol=1e-4, atol=1e-6 * lr)
+    sg.sg_surr_destroy(sess.ctx, sid)
+    sg.sg_surr_destroy(sess.ctx, sid2)
+
+
+def test_checkpoint_resume_is_bit_exact(sess, tmp_path):
+    from paper_2507_01152_amd import sonosim as sg
+    H, W = 32, 48
+    wl = _pairs(3, H, W, seed=8)
+    vids = sess.load(wl)
+    sid = sg.sg_surr_create(sess.ctx, H, W, seed=3)
+    for _ in range(2):
+        sg.sg_surr_train_step(sess.ctx, sid, vids, wl.probes, wl.poses, 1e-3)
+    path = str(tmp_path / "ck.bin")
+    sg.sg_surr_save(sess.ctx, sid, path)
+    la = [sg.sg_surr_train_step(sess.ctx, sid, vids, wl.probes, wl.poses, 1e-3) for _ in range(2)]
+    pa = sg.sg_surr_get_params(sess.ctx, sid)
+    sid2 = sg.sg_surr_create(sess.ctx, H, W, seed=99)
+    sg.sg_surr_load(sess.ctx, sid2, path)
+    lb = [sg.sg_surr_train_step(sess.ctx, sid2, vids, wl.probes, wl.poses, 1e-3) for _ in range(2)]
+    pb = sg.sg_surr_get_params(sess.ctx, sid2)
+    assert la == lb and np.array_equal(pa, pb)
+    bad = sg.sg_surr_create(sess.ctx, 48, 48, seed=1)
+    with pytest.raises(sg.SonosimError):
+        sg.sg_surr_load(sess.ctx, bad, path)
+
+
+def test_training_reduces_loss(sess):
+    from paper_2507_01152_amd import sonosim as sg
+    H, W = 64, 32
+    wl = _pairs(8, H, W, seed=13)
+    vids = sess.load(wl)
+    sid = sg.sg_surr_create(sess.ctx, H, W, seed=5)
+    losses = [sg.sg_surr_train_step(sess.ctx, sid, vids, wl.probes, wl.poses, 2e-3) for _ in range(60)]
+    assert np.mean(losses[-5:]) < 0.7 * np.mean(losses[:3])
+
+
+def test_infer_audit_and_fallback(sess):
+    from paper_2507_01152_amd import sonosim as sg
+    H, W, n = 64, 32, 12
+    wl = _pairs(n, H, W, seed=17)
+    vids = sess.load(wl)
+    sid = sg.sg_surr_create(sess.ctx, H, W, seed=2)
+    for _ in range(20):
+        sg.sg_surr_train_step(sess.ctx, sid, vids, wl.probes, wl.poses, 2e-3)
+    phys, offs, _ = sess.simulate(wl, vids)
+    phys = phys.cpu().numpy().reshape(n, H, W)
+    out = torch.empty(n * H * W, dtype=torch.float32, device="cuda")
+    audit = [1, 4, 7, 10]
+    # no audit: pure network output, clamped
+    _, nf = sg.sg_surr_infer(sess.ctx, sid, vids, wl.probes, wl.poses, out, [], 30.0)
+    net = out.cpu().numpy().reshape(n, H, W)
+    assert nf == 0 and net.min() >= 0 and net.max() <= 1
+    # audit that never fails: frames unchanged, PSNR as computed on the host
+    psnr, nf = sg.sg_surr_infer(sess.ctx, sid, vids, wl.probes, wl.poses, out, audit, -np.inf, 0.25)
+    assert nf == 0 and np.array_equal(out.cpu().numpy().reshape(n, H, W), net)
+    for i, e in enumerate(audit):
+        assert abs(psnr[i] - so.psnr(net[e], phys[e])) < 1e-3
+    # a threshold between the audited PSNRs: failing frames come from physics
+    thr = float(np.median(psnr))
+    psnr2, nf = sg.sg_surr_infer(sess.ctx, sid, vids, wl.probes, wl.poses, out, audit, thr, 1.0)
+    got = out.cpu().numpy().reshape(n, H, W)
+    fails = [e for p, e in zip(psnr2, audit) if not p >= thr]
+    assert nf == len(fails) and 0 < nf < len(audit)
+    for e in range(n):
+        assert np.array_equal(got[e], phys[e] if e in fails else net[e])
+    # every audited frame failing beyond the allowed fraction: whole step from physics
+    _, nf = sg.sg_surr_infer(sess.ctx, sid, vids, wl.probes, wl.poses, out, audit, np.inf, 0.25)
+    assert nf == n and np.array_equal(out.cpu().numpy().reshape(n, H, W), phys)
+    with pytest.raises(sg.SonosimError):
+        sg.sg_surr_infer(sess.ctx, sid, vids, wl.probes, wl.poses, out, [1, 1], 30.0)
