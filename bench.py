@@ -50,6 +50,87 @@ def psf_ops_per_pixel(W: int, H: int) -> int:
     return 2 * (2 * psf_radius(W) + 1) + 18
 
 
+# surrogate network: (Ci, Co, level, stride) of each 3x3 conv (output level for
+# the FLOP count) -- five levels 16/32/64/128/256, decoders read x2 upsampled
+SURR_CONVS = [(8, 16, 0), (16, 16, 0), (16, 32, 1), (32, 32, 1), (32, 64, 2), (64, 64, 2), (64, 128, 3),
+              (128, 128, 3), (128, 256, 4), (256, 256, 4), (256, 128, 3), (128, 128, 3), (128, 64, 2),
+              (64, 64, 2), (64, 32, 1), (32, 32, 1), (32, 16, 0), (16, 16, 0)]
+
+
+def surrogate_flops_per_frame(H: int, W: int) -> float:
+    """Forward FLOPs (2 per multiply-add) of the convolutions and head."""
+    f = sum(2.0 * 9 * ci * co * (H >> lv) * (W >> lv) for ci, co, lv in SURR_CONVS)
+    return f + 2.0 * 16 * H * W
+
+
+def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, psnr_min: float = 30.0):
+    """Train the surrogate on physics pairs for a fixed budget, then time
+    audited inference of n_envs 128 x 256 frames beside the physics path on
+    the same workload."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2507_01152_amd import sonosim as sg
+    from paper_2507_01152_amd.train_surrogate import FRAME_H, FRAME_W, PairSource, train
+
+    t0 = time.perf_counter()
+    sess, sid, _train_src, _ev, hist = train(train_steps, 64, 5e-4, seed=0, eval_every=max(1, train_steps),
+                                             log=lambda s: None)
+    train_s = time.perf_counter() - t0
+    test_src = PairSource(sess, 64, seed0=200000)     # held-out phantoms
+    rng = np.random.default_rng(2024)
+    vids, probes, poses = test_src.batch(n_envs, rng)
+    audit = np.sort(np.random.Generator(np.random.Philox(key=7)).choice(n_envs, n_envs // audit_frac,
+                                                                         replace=False)).astype(np.int32)
+    HW = FRAME_W * FRAME_H
+    out = torch.empty(n_envs * HW, dtype=torch.float32, device=sess.device)
+    sg.sg_surr_infer(sess.ctx, sid, vids, probes, poses, out, audit, psnr_min, 0.25)   # warm-up
+    reps = 5
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        psnr, n_fb = sg.sg_surr_infer(sess.ctx, sid, vids, probes, poses, out, audit, psnr_min, 0.25)
+    surr_s = (time.perf_counter() - t) / reps
+    # network alone (no audit), for the MFMA roofline
+    t = time.perf_counter()
+    for _ in range(reps):
+        sg.sg_surr_infer(sess.ctx, sid, vids, probes, poses, out, [], psnr_min, 0.25)
+    net_s = (time.perf_counter() - t) / reps
+    # physics on the same workload: batched plan, graph replays
+    offs = np.arange(n_envs, dtype=np.int64) * HW
+    plan = sg.sg_batch_plan_create(sess.ctx, vids, probes, offs)
+    sg.sg_batch_set_poses(sess.ctx, plan, poses)
+    for _ in range(3):
+        sg.sg_batch_step(sess.ctx, plan, out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(20):
+        sg.sg_batch_step(sess.ctx, plan, out)
+    torch.cuda.synchronize()
+    phys_s = (time.perf_counter() - t) / 20
+    mse = 10.0 ** (-np.asarray(psnr, dtype=np.float64) / 10.0)
+    flops = surrogate_flops_per_frame(FRAME_H, FRAME_W) * n_envs
+    res = {
+        "workload": f"{n_envs} envs, {FRAME_W}x{FRAME_H} frames on held-out 64^3 ellipsoid phantoms, "
+                    f"1/{audit_frac} seeded physics audit at PSNR >= {psnr_min} dB",
+        "frames_per_s": round(n_envs / surr_s, 1),
+        "physics_frames_per_s_same_workload": round(n_envs / phys_s, 1),
+        "surrogate_vs_physics": round(phys_s / surr_s, 4),
+        "psnr_audit_mean_db": round(float(np.mean(psnr)), 2),
+        "psnr_audit_pooled_db": round(float(-10 * np.log10(mse.mean())), 2),
+        "frames_from_physics": int(n_fb),
+        "train": {"steps": train_steps, "pairs": train_steps * 64, "seconds": round(train_s, 1),
+                  "last_eval": hist[-1] if hist else None},
+        "roofline": {"bound": "mfma", "kernel": "network forward (encode + 18 convs + head)",
+                     "achieved": round(flops / net_s / 1e12, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(flops / net_s / 1e12 / 2500.0, 4), "flops_per_launch": flops,
+                     "ms": round(net_s * 1e3, 3)},
+    }
+    sess.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +139,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--profile-launches", type=int, default=20)
+    ap.add_argument("--surrogate-steps", type=int, default=2500,
+                    help="training steps (batch 64) before timing surrogate inference; 0 skips the surrogate")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -118,7 +201,7 @@ def main():
     achieved_gbs = alg_bytes / (ms_per_step / 1e3) / 1e9
 
     res = {
-        "metric": "simulated B-mode frames/sec at 256 envs (physics)",
+        "metric": "simulated B-mode frames/sec at 256 envs (physics vs surrogate @ stated PSNR)",
         "value": round(fps, 1),
         "unit": "frames/s",
         "n_gpus": 1,
@@ -169,6 +252,9 @@ def main():
                       f"OpenMP over envs, {dt:.1f} s wall",
         }
         res["gpu_vs_cpu"] = round(fps / res["cpu_baseline"]["value"], 1)
+    if args.surrogate_steps > 0:
+        sess.close()
+        res["surrogate"] = surrogate_leg(args.surrogate_steps)
     if args.copy_probe:
         src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=sess.device)
         dst = torch.empty_like(src)
@@ -176,7 +262,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         res["copy_probe_bytes"] = src.numel() * 4
-    sess.close()
+    if sess.ctx is not None:
+        sess.close()
     print(json.dumps(res))
 
 

@@ -251,8 +251,9 @@ sg_status sg_conv_backward_data(sg_ctx* ctx, const sg_conv_desc* d, const uint16
                                 float* dx, int32_t accumulate);
 
 /* dw[Co][k][k][C] = sum over output pixels of dy * shifted x (FP32), and
- * db[Co] = sum of dy (FP32, may be NULL).  Deterministic (fixed-order
- * split-K reduction). */
+ * db[Co] = sum of dy (FP32, may be NULL; needs Co <= 256).  Deterministic
+ * (fixed-order split-K reduction).  Limits for all three conv calls: C and Co
+ * multiples of 8 up to 4096, fewer than 2^31 input and output pixels. */
 sg_status sg_conv_backward_weight(sg_ctx* ctx, const sg_conv_desc* d, const uint16_t* x, const uint16_t* dy,
                                   float* dw, float* db);
 
@@ -260,7 +261,8 @@ sg_status sg_conv_backward_weight(sg_ctx* ctx, const sg_conv_desc* d, const uint
  * encoder-decoder (16/32/64/128/256 channels, two 3x3 convs per level,
  * stride-2 downsampling, nearest x2 upsampling + 3x3 conv, additive skips,
  * 1x1 head), He-initialised from `seed`.  Input per pixel: one-hot label
- * (labels 0..3) and the gated scatterer sample of the volume's noise field.
+ * (labels 0..3), the gated scatterer sample of the volume's noise field and
+ * the normalised depth (y + 0.5) / H.
  * *surr_id receives the id. */
 sg_status sg_surr_create(sg_ctx* ctx, int32_t H, int32_t W, uint64_t seed, int32_t* surr_id);
 sg_status sg_surr_destroy(sg_ctx* ctx, int32_t surr_id);
@@ -270,7 +272,7 @@ sg_status sg_surr_num_params(sg_ctx* ctx, int32_t surr_id, int64_t* n);
 
 /* One training step on n_envs pairs generated on the fly: the physics path
  * renders the targets, the encoder builds the inputs, then forward, L1 loss
- * (mean |Yhat - Y|), backward and one Adam step (beta1 0.5, beta2 0.999,
+ * (mean |Yhat - Y|), backward and one Adam step (beta1 0.9, beta2 0.999,
  * eps 1e-8) with learning rate lr.  Every probe must be H x W.  *loss (host)
  * receives the batch loss before the update (synchronises). */
 sg_status sg_surr_train_step(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, const int32_t* vol_ids,

@@ -214,7 +214,7 @@ def psnr(yhat, y):
     return 200.0 if mse == 0 else -10.0 * np.log10(mse)
 
 
-def adam_update(w, g, m, v, step, lr, b1=0.5, b2=0.999, eps=1e-8):
+def adam_update(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam step (Kingma & Ba 2015) on FP64 copies; returns (w, m, v)."""
     m = b1 * m + (1 - b1) * g
     v = b2 * v + (1 - b2) * g * g

@@ -28,6 +28,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte staging chunk
 
 constexpr int kThreads = 256;
 constexpr int kBK = 32;           // K per MFMA step
@@ -48,83 +49,6 @@ __device__ __forceinline__ float bf2f(uint16_t b)
 
 enum Mode { kFwd = 0, kDgrad = 1, kWgrad = 2 };
 
-struct Pix {
-    int n, h, w;
-};
-
-__device__ __forceinline__ Pix split_pixel(int64_t m, int H, int W)
-{
-    Pix p;
-    const int hw = H * W;
-    p.n = (int)(m / hw);
-    const int rem = (int)(m - (int64_t)p.n * hw);
-    p.h = rem / W;
-    p.w = rem - p.h * W;
-    return p;
-}
-
-// 8 input channels of x at conv-input position (n, hi, wi), or zeros
-__device__ __forceinline__ uint4 load_x8(const ConvGeom& g, const uint16_t* x, int n, int hi, int wi, int ci0)
-{
-    const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
-    if (hi < 0 || wi < 0 || hi >= Hin || wi >= Win) return make_uint4(0u, 0u, 0u, 0u);
-    if (g.up) {
-        hi >>= 1;
-        wi >>= 1;
-    }
-    return *reinterpret_cast<const uint4*>(x + (((int64_t)n * g.H + hi) * g.W + wi) * g.C + ci0);
-}
-
-// A operand chunk (8 consecutive k of row m) for the K-contiguous modes
-template <int MODE>
-__device__ __forceinline__ uint4 load_a_k(const ConvGeom& g, const uint16_t* src, int64_t m, int k)
-{
-    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-    if (MODE == kFwd) {
-        if (m >= g.M || k >= g.K) return z;
-        const Pix p = split_pixel(m, g.Ho, g.Wo);
-        const int t = k / g.C, ci0 = k - t * g.C;
-        const int r = t / g.kw, s = t - r * g.kw;
-        return load_x8(g, src, p.n, p.h * g.stride - g.pad + r, p.w * g.stride - g.pad + s, ci0);
-    } else {
-        // data gradient: row = conv-input pixel, k = (r, s, co)
-        if (m >= g.M || k >= g.K) return z;
-        const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
-        const Pix p = split_pixel(m, Hin, Win);
-        const int t = k / g.Co, co0 = k - t * g.Co;
-        const int r = t / g.kw, s = t - r * g.kw;
-        const int hh = p.h + g.pad - r, ww = p.w + g.pad - s;
-        if (hh < 0 || ww < 0) return z;
-        const int ho = hh / g.stride, wo = ww / g.stride;
-        if (ho * g.stride != hh || wo * g.stride != ww || ho >= g.Ho || wo >= g.Wo) return z;
-        return *reinterpret_cast<const uint4*>(src + (((int64_t)p.n * g.Ho + ho) * g.Wo + wo) * g.Co + co0);
-    }
-}
-
-// B operand chunk (8 consecutive k of column col) for the K-contiguous modes:
-// weights row-major [col][K]
-__device__ __forceinline__ uint4 load_b_k(const ConvGeom& g, const uint16_t* w, int col, int k)
-{
-    if (col >= g.N || k >= g.K) return make_uint4(0u, 0u, 0u, 0u);
-    return *reinterpret_cast<const uint4*>(w + (int64_t)col * g.K + k);
-}
-
-// weight gradient operands, contiguous along M (co) or N ((r, s, ci))
-__device__ __forceinline__ uint4 load_wg_a(const ConvGeom& g, const uint16_t* dy, int m0, int64_t k)
-{
-    if (m0 >= g.M || k >= g.Kw) return make_uint4(0u, 0u, 0u, 0u);
-    return *reinterpret_cast<const uint4*>(dy + k * g.Co + m0);
-}
-
-__device__ __forceinline__ uint4 load_wg_b(const ConvGeom& g, const uint16_t* x, int n0, int64_t k)
-{
-    if (n0 >= g.N || k >= g.Kw) return make_uint4(0u, 0u, 0u, 0u);
-    const Pix p = split_pixel(k, g.Ho, g.Wo);
-    const int t = n0 / g.C, ci0 = n0 - t * g.C;
-    const int r = t / g.kw, s = t - r * g.kw;
-    return load_x8(g, x, p.n, p.h * g.stride - g.pad + r, p.w * g.stride - g.pad + s, ci0);
-}
-
 template <int MODE, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
 {
@@ -132,11 +56,13 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
     constexpr int FM = TM / 16, FN = TN / 16;
     static_assert(WM * WN == 4, "four waves");
     static_assert(FM >= 1 && FN >= 1, "tile");
-    // per-thread staged chunks per K step
+    // staged 16-byte chunks per K step: K-contiguous operands are (row, 8 k)
+    // chunks, the weight gradient's are (8 rows, k) chunks
     constexpr int CA = (MODE == kWgrad) ? (BM / 8) * kBK : BM * (kBK / 8);
     constexpr int CB = (MODE == kWgrad) ? (BN / 8) * kBK : BN * (kBK / 8);
     constexpr int PA = (CA + kThreads - 1) / kThreads;
     constexpr int PB = (CB + kThreads - 1) / kThreads;
+    constexpr int AM8 = BM / 8, BN8 = BN / 8;   // weight-gradient row groups
 
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * kBKP];
     __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * kBKP];
@@ -145,80 +71,168 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
-    const int64_t m_base = (int64_t)blockIdx.x * BM;
+    const int m_base = (int)blockIdx.x * BM;    // M < 2^31
     const int n_base = blockIdx.y * BN;
+    const uint16_t* __restrict__ A = a.a;
+    const uint16_t* __restrict__ B = a.b;
+    const u32x4 zero = {0u, 0u, 0u, 0u};
 
     // K range of this block (split-K for the weight gradient)
     int64_t k_begin = 0, k_end = (MODE == kWgrad) ? g.Kw : g.K;
-    if (MODE == kWgrad) {
+    if constexpr (MODE == kWgrad) {
         k_begin = (int64_t)blockIdx.z * a.k_chunk;
         k_end = min(k_end, k_begin + a.k_chunk);
     }
     const int nk = (int)((k_end - k_begin + kBK - 1) / kBK);
+    const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
 
-    uint4 ra[PA], rb[PB];
-
-    auto load_tiles = [&](int64_t k0) {
+    // ---- per-thread chunk bookkeeping, fixed over the K loop ----
+    // K-contiguous modes: chunk c = tid + i * 256 -> (row c / 4, k8 = tid % 4)
+    const int k8 = tid & 3;
+    int a_hb[PA], a_wb[PA];       // forward: ho*s - pad, wo*s - pad; data grad: h + pad, w + pad
+    int64_t a_base[PA];           // element offset of the row's image (or -1: row outside M)
+    // weight gradient: fixed channel group of A (dy) and of B (x)
+    const int wg_m0 = m_base + (tid % AM8) * 8;
+    const int wg_n0 = n_base + (tid % BN8) * 8;
+    int wg_r = 0, wg_s = 0, wg_ci0 = 0;
+    if constexpr (MODE == kWgrad) {
+        if (wg_n0 < g.N) {
+            const int t = (int)fdiv((uint32_t)wg_n0, g.f_c);
+            wg_ci0 = wg_n0 - t * g.C;
+            wg_r = (int)fdiv((uint32_t)t, g.f_kw);
+            wg_s = t - wg_r * g.kw;
+        }
+    } else {
 #pragma unroll
         for (int i = 0; i < PA; ++i) {
-            const int c = tid + i * kThreads;
-            ra[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < CA) {
-                if (MODE == kWgrad) {
-                    const int m8 = c % (BM / 8), kk = c / (BM / 8);
-                    const int64_t k = k0 + kk;
-                    if (k < k_end) ra[i] = load_wg_a(g, a.a, (int)m_base + m8 * 8, k);
+            const int row = (tid >> 2) + i * (kThreads / 4);
+            const int m = m_base + row;
+            a_base[i] = -1;
+            a_hb[i] = a_wb[i] = 0;
+            if (row < BM && m < g.M) {
+                if constexpr (MODE == kFwd) {
+                    const int n = (int)fdiv((uint32_t)m, g.f_howo);
+                    const int rem = m - n * g.Ho * g.Wo;
+                    const int ho = (int)fdiv((uint32_t)rem, g.f_wo);
+                    const int wo = rem - ho * g.Wo;
+                    a_hb[i] = ho * g.stride - g.pad;
+                    a_wb[i] = wo * g.stride - g.pad;
+                    a_base[i] = (int64_t)n * g.H * g.W * g.C;
                 } else {
-                    const int row = c / (kBK / 8), k8 = c % (kBK / 8);
-                    ra[i] = load_a_k<MODE>(g, a.a, m_base + row, (int)k0 + k8 * 8);
+                    const int n = (int)fdiv((uint32_t)m, g.f_hinwin);
+                    const int rem = m - n * Hin * Win;
+                    const int h = (int)fdiv((uint32_t)rem, g.f_win);
+                    const int w = rem - h * Win;
+                    a_hb[i] = h + g.pad;
+                    a_wb[i] = w + g.pad;
+                    a_base[i] = (int64_t)n * g.Ho * g.Wo * g.Co;
                 }
+            }
+        }
+    }
+
+    u32x4 ra[PA], rb[PB];
+
+    auto load_tiles = [&](int64_t k0) __attribute__((always_inline)) {
+        if constexpr (MODE == kWgrad) {
+#pragma unroll
+            for (int i = 0; i < PA; ++i) {
+                const int c = tid + i * kThreads;
+                const int64_t k = k0 + c / AM8;
+                ra[i] = (c < CA && wg_m0 < g.M && k < k_end)
+                            ? *reinterpret_cast<const u32x4*>(A + k * g.Co + wg_m0)
+                            : zero;
+            }
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                const int c = tid + i * kThreads;
+                const int64_t k = k0 + c / BN8;
+                rb[i] = zero;
+                if (c < CB && wg_n0 < g.N && k < k_end) {
+                    const int p = (int)k;
+                    const int n = (int)fdiv((uint32_t)p, g.f_howo);
+                    const int rem = p - n * g.Ho * g.Wo;
+                    const int ho = (int)fdiv((uint32_t)rem, g.f_wo);
+                    const int wo = rem - ho * g.Wo;
+                    int hi = ho * g.stride - g.pad + wg_r, wi = wo * g.stride - g.pad + wg_s;
+                    if (hi >= 0 && wi >= 0 && hi < Hin && wi < Win) {
+                        if (g.up) {
+                            hi >>= 1;
+                            wi >>= 1;
+                        }
+                        rb[i] = *reinterpret_cast<const u32x4*>(B + (((int64_t)n * g.H + hi) * g.W + wi) * g.C + wg_ci0);
+                    }
+                }
+            }
+            return;
+        }
+        // K-contiguous: one tap / channel split per K step (k8 fixed per thread)
+        const int k = (int)k0 + k8 * 8;
+        const bool kin = k < g.K;
+        int r = 0, s = 0, c0 = 0;
+        if (kin) {
+            const FastDiv fc = (MODE == kFwd) ? g.f_c : g.f_co;
+            const int cc = (MODE == kFwd) ? g.C : g.Co;
+            const int t = (int)fdiv((uint32_t)k, fc);
+            c0 = k - t * cc;
+            r = (int)fdiv((uint32_t)t, g.f_kw);
+            s = t - r * g.kw;
+        }
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            ra[i] = zero;
+            if (!kin || a_base[i] < 0) continue;
+            if constexpr (MODE == kFwd) {
+                int hi = a_hb[i] + r, wi = a_wb[i] + s;
+                if (hi < 0 || wi < 0 || hi >= Hin || wi >= Win) continue;
+                if (g.up) {
+                    hi >>= 1;
+                    wi >>= 1;
+                }
+                ra[i] = *reinterpret_cast<const u32x4*>(A + a_base[i] + ((int64_t)hi * g.W + wi) * g.C + c0);
+            } else {
+                const int hh = a_hb[i] - r, ww = a_wb[i] - s;
+                if (hh < 0 || ww < 0) continue;
+                const int ho = (int)fdiv((uint32_t)hh, g.f_stride), wo = (int)fdiv((uint32_t)ww, g.f_stride);
+                if (ho * g.stride != hh || wo * g.stride != ww || ho >= g.Ho || wo >= g.Wo) continue;
+                ra[i] = *reinterpret_cast<const u32x4*>(A + a_base[i] + ((int64_t)ho * g.Wo + wo) * g.Co + c0);
             }
         }
 #pragma unroll
         for (int i = 0; i < PB; ++i) {
-            const int c = tid + i * kThreads;
-            rb[i] = make_uint4(0u, 0u, 0u, 0u);
-            if (c < CB) {
-                if (MODE == kWgrad) {
-                    const int n8 = c % (BN / 8), kk = c / (BN / 8);
-                    const int64_t k = k0 + kk;
-                    if (k < k_end) rb[i] = load_wg_b(g, a.b, n_base + n8 * 8, k);
-                } else {
-                    const int col = c / (kBK / 8), k8 = c % (kBK / 8);
-                    rb[i] = load_b_k(g, a.b, n_base + col, (int)k0 + k8 * 8);
-                }
-            }
+            const int col = n_base + (tid >> 2) + i * (kThreads / 4);
+            rb[i] = (kin && (tid >> 2) + i * (kThreads / 4) < BN && col < g.N)
+                        ? *reinterpret_cast<const u32x4*>(B + (int64_t)col * g.K + k)
+                        : zero;
         }
     };
-    auto store_tiles = [&](int buf) {
+    auto store_tiles = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < PA; ++i) {
             const int c = tid + i * kThreads;
-            if (c < CA) {
-                if (MODE == kWgrad) {
-                    const int m8 = c % (BM / 8), kk = c / (BM / 8);
-                    const uint16_t* v = reinterpret_cast<const uint16_t*>(&ra[i]);
+            if (c >= CA) continue;
+            if constexpr (MODE == kWgrad) {
+                const int m8 = c % AM8, kk = c / AM8;
+                const u32x4 w4 = ra[i];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) sA[buf][(m8 * 8 + j) * kBKP + kk] = v[j];
-                } else {
-                    const int row = c / (kBK / 8), k8 = c % (kBK / 8);
-                    *reinterpret_cast<uint4*>(&sA[buf][row * kBKP + k8 * 8]) = ra[i];
-                }
+                for (int j = 0; j < 8; ++j)
+                    sA[buf][(m8 * 8 + j) * kBKP + kk] = (uint16_t)(w4[j >> 1] >> ((j & 1) * 16));
+            } else {
+                *reinterpret_cast<u32x4*>(&sA[buf][(c >> 2) * kBKP + k8 * 8]) = ra[i];
             }
         }
 #pragma unroll
         for (int i = 0; i < PB; ++i) {
             const int c = tid + i * kThreads;
-            if (c < CB) {
-                if (MODE == kWgrad) {
-                    const int n8 = c % (BN / 8), kk = c / (BN / 8);
-                    const uint16_t* v = reinterpret_cast<const uint16_t*>(&rb[i]);
+            if (c >= CB) continue;
+            if constexpr (MODE == kWgrad) {
+                const int n8 = c % BN8, kk = c / BN8;
+                const u32x4 w4 = rb[i];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) sB[buf][(n8 * 8 + j) * kBKP + kk] = v[j];
-                } else {
-                    const int col = c / (kBK / 8), k8 = c % (kBK / 8);
-                    *reinterpret_cast<uint4*>(&sB[buf][col * kBKP + k8 * 8]) = rb[i];
-                }
+                for (int j = 0; j < 8; ++j)
+                    sB[buf][(n8 * 8 + j) * kBKP + kk] = (uint16_t)(w4[j >> 1] >> ((j & 1) * 16));
+            } else {
+                *reinterpret_cast<u32x4*>(&sB[buf][(c >> 2) * kBKP + k8 * 8]) = rb[i];
             }
         }
     };
@@ -263,10 +277,10 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
             if (col >= g.N) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = m_base + wm * TM + i * 16 + (lane >> 4) * 4 + r;
+                const int64_t row = (int64_t)m_base + wm * TM + i * 16 + (lane >> 4) * 4 + r;
                 if (row >= g.M) continue;
                 const float v = acc[i][j][r];
-                if (MODE == kFwd) {
+                if constexpr (MODE == kFwd) {
                     float y = v + (a.bias ? a.bias[col] : 0.f);
                     if (a.relu) y = fmaxf(y, 0.f);
                     const int64_t o = row * g.Co + col;
@@ -274,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
                     if (a.out_bf16) a.out_bf16[o] = yb;
                     if (a.out_f32) a.out_f32[o] = y;
                     if (a.skip && a.out2_bf16) a.out2_bf16[o] = f2bf(bf2f(yb) + bf2f(a.skip[o]));
-                } else if (MODE == kDgrad) {
+                } else if constexpr (MODE == kDgrad) {
                     const int64_t o = row * g.C + col;
                     a.out_f32[o] = a.accumulate ? a.out_f32[o] + v : v;
                 } else {
@@ -315,16 +329,42 @@ __global__ void k_pool2x2_sum(const float* fine, float* coarse, int N, int H, in
     }
 }
 
-// column partial sums of a [rows][cols] bf16 matrix over row blocks: part[b][c]
-__global__ void k_colsum_bf16(const uint16_t* x, int64_t rows, int cols, int64_t rows_per_block, float* part)
+// Masked output gradient and bias-gradient partials in one pass over a
+// [rows][C] matrix: out = bf16(g * [y > 0]) (y may be null: no mask; out may
+// be null: g is already bf16 in gb), part[block][c] = sum of the block's rows
+// of out.  Thread t owns column t % C for every (256 / C)-th row; the threads
+// of a column are summed in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_mask_colsum(const float* g, const uint16_t* gb, const uint16_t* y,
+                                                     uint16_t* out, int64_t rows, int C, int64_t rows_per_block,
+                                                     float* part)
 {
-    const int c = blockIdx.y * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+    __shared__ float red[256];
+    const int lanes = 256 / C;
+    const int c = threadIdx.x % C;
+    const int r_off = threadIdx.x / C;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = min(rows, r0 + rows_per_block);
     float s = 0.f;
-    for (int64_t r = r0; r < r1; ++r) s += bf2f(x[r * cols + c]);
-    part[(int64_t)blockIdx.x * cols + c] = s;
+    if (r_off < lanes) {
+        for (int64_t r = r0 + r_off; r < r1; r += lanes) {
+            const int64_t i = r * C + c;
+            uint16_t b;
+            if (gb) {
+                b = gb[i];
+            } else {
+                b = f2bf((y == nullptr || bf2f(y[i]) > 0.f) ? g[i] : 0.f);
+                if (out) out[i] = b;
+            }
+            s += bf2f(b);
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (r_off == 0) {
+        float t = 0.f;
+        for (int j = 0; j < lanes; ++j) t += red[j * C + c];
+        part[(int64_t)blockIdx.x * C + c] = t;
+    }
 }
 
 // out[i] = sum_s part[s][i] in fixed order
@@ -337,30 +377,66 @@ __global__ void k_sum_parts(const float* part, int64_t n, int splits, float* out
     }
 }
 
-// 1x1 head with one output channel: y[p] = sum_c w[c] x[p][c] + b
-__global__ void k_head_fwd(const uint16_t* x, const uint16_t* w, const float* b, float* y, int64_t P, int C)
+// 1x1 head with one output channel: y[p] = sum_c w[c] x[p][c] + b (C = 16)
+__global__ __launch_bounds__(256) void k_head_fwd(const uint16_t* x, const uint16_t* w, const float* b, float* y,
+                                                  int64_t P, int C)
 {
+    float wf[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) wf[c] = c < C ? bf2f(w[c]) : 0.f;
+    const float bias = b[0];
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 v0 = *reinterpret_cast<const uint4*>(x + p * 16);
+        const uint4 v1 = *reinterpret_cast<const uint4*>(x + p * 16 + 8);
+        const uint16_t* h0 = reinterpret_cast<const uint16_t*>(&v0);
+        const uint16_t* h1 = reinterpret_cast<const uint16_t*>(&v1);
         float s = 0.f;
-        for (int c = 0; c < C; ++c) s += bf2f(w[c]) * bf2f(x[p * C + c]);
-        y[p] = s + b[0];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s += wf[c] * bf2f(h0[c]);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s += wf[8 + c] * bf2f(h1[c]);
+        y[p] = s + bias;
     }
 }
 
-// head backward: dx[p][c] = w[c] g[p]; per-block partials of dw[c] = sum x g
-// and db = sum g (part row layout: C + 1 values per block)
-__global__ void k_head_bwd(const uint16_t* x, const uint16_t* w, const float* g, float* dx, int64_t P, int C,
-                           int64_t rows_per_block, float* part)
+// head backward (C = 16): dx[p][c] = w[c] g[p]; per-block partials of
+// dw[c] = sum_p x[p][c] g[p] (c < 16) and db = sum_p g[p] (entry 16)
+__global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* x, const uint16_t* w, const float* g, float* dx,
+                                                  int64_t P, int C, int64_t rows_per_block, float* part)
 {
+    __shared__ float red[17][256];
+    float wf[16], acc[17];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) wf[c] = bf2f(w[c]);
+#pragma unroll
+    for (int c = 0; c < 17; ++c) acc[c] = 0.f;
     const int64_t p0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t p1 = min(P, p0 + rows_per_block);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x)
-        for (int c = 0; c < C; ++c) dx[p * C + c] = bf2f(w[c]) * g[p];
-    if (threadIdx.x <= C) {
-        float s = 0.f;
-        for (int64_t p = p0; p < p1; ++p) s += (threadIdx.x < C) ? bf2f(x[p * C + threadIdx.x]) * g[p] : g[p];
-        part[(int64_t)blockIdx.x * (C + 1) + threadIdx.x] = s;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const float gp = g[p];
+        const uint4 v0 = *reinterpret_cast<const uint4*>(x + p * 16);
+        const uint4 v1 = *reinterpret_cast<const uint4*>(x + p * 16 + 8);
+        const uint16_t* h0 = reinterpret_cast<const uint16_t*>(&v0);
+        const uint16_t* h1 = reinterpret_cast<const uint16_t*>(&v1);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] += bf2f(h0[c]) * gp;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[8 + c] += bf2f(h1[c]) * gp;
+        acc[16] += gp;
+        float4* d = reinterpret_cast<float4*>(dx + p * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            d[q] = make_float4(wf[4 * q] * gp, wf[4 * q + 1] * gp, wf[4 * q + 2] * gp, wf[4 * q + 3] * gp);
     }
+#pragma unroll
+    for (int c = 0; c < 17; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < 17) {
+        float t = 0.f;
+        for (int j = 0; j < 256; ++j) t += red[threadIdx.x][j];
+        part[(int64_t)blockIdx.x * 17 + threadIdx.x] = t;
+    }
+    (void)C;
 }
 
 // L1 loss: per-block partial sums of |yhat - y| * scale (scale = 1 / n);
@@ -537,6 +613,18 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
 
 int wgrad_tile_m(int M) { return M <= 16 ? 16 : (M <= 32 ? 32 : 64); }
 
+hipError_t mask_colsum(const float* g, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
+                       int blocks, float* bias_grad, hipStream_t s)
+{
+    if (C > 256) return hipErrorInvalidValue;
+    const int64_t per = (rows + blocks - 1) / blocks;
+    hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, g, nullptr, y, out, rows, C, per, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(C)), dim3(256), 0, s, part, (int64_t)C, blocks, bias_grad);
+    return hipGetLastError();
+}
+
 hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mask_to_bf16, dim3((unsigned)grid_for(n)), dim3(256), 0, s, g, y, out, n);
@@ -554,8 +642,10 @@ hipError_t pool2x2_sum(const float* fine, float* coarse, int N, int H, int W, in
 hipError_t colsum_bf16(const uint16_t* x, int64_t rows, int cols, float* part, int blocks, float* out,
                        hipStream_t s)
 {
+    if (cols > 256) return hipErrorInvalidValue;
     const int64_t per = (rows + blocks - 1) / blocks;
-    hipLaunchKernelGGL(k_colsum_bf16, dim3(blocks, (cols + 255) / 256), dim3(256), 0, s, x, rows, cols, per, part);
+    hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, nullptr, x, nullptr, nullptr, rows, cols, per,
+                       part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(cols)), dim3(256), 0, s, part, (int64_t)cols, blocks, out);
@@ -581,7 +671,7 @@ hipError_t head_bwd(const uint16_t* x, const uint16_t* w, const float* g, float*
     hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, x, w, g, dx, P, C, per, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int64_t)(C + 1), blocks, dwb);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int64_t)17, blocks, dwb);
     return hipGetLastError();
 }
 

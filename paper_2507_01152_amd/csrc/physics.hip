@@ -543,10 +543,11 @@ __global__ __launch_bounds__(kThreads) void k_psf(PhysArgs a, QueueDev* q)
     }
 }
 
-// Surrogate input of each pixel: one-hot label (channels 0..3) and the
+// Surrogate input of each pixel: one-hot label (channels 0..3), the
 // scatterer sample of the same fixed noise field the ray pass uses (channel 4:
-// N0 where the density gate passes, else 0), bf16, 8 channels per pixel,
-// frames packed [env][y][x][8] at 8 * out_off.
+// N0 where the density gate passes, else 0) and the normalised depth
+// (y + 0.5) / H (channel 5); bf16, 8 channels per pixel, frames packed
+// [env][y][x][8] at 8 * out_off.
 __device__ __forceinline__ uint16_t f2bf16(float f)
 {
     uint32_t u = __float_as_uint(f);
@@ -581,7 +582,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(PhysArgs a, uint16_t* enc)
         const uint32_t one = 0x3F80u;   // bf16 1.0
         o.x = (lab == 0 ? one : 0u) | ((lab == 1 ? one : 0u) << 16);
         o.y = (lab == 2 ? one : 0u) | ((lab == 3 ? one : 0u) << 16);
-        o.z = (uint32_t)f2bf16(sc);
+        o.z = (uint32_t)f2bf16(sc) | ((uint32_t)f2bf16(((float)y + 0.5f) / (float)e.H) << 16);
         o.w = 0u;
         reinterpret_cast<uint4*>(enc)[e.out_off + p] = o;
     }

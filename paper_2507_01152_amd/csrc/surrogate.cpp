@@ -40,7 +40,7 @@ const LayerDef kLayers[] = {
 };
 constexpr int kNumL = sizeof(kLayers) / sizeof(kLayers[0]);
 constexpr int kHeadC = 16;
-constexpr float kBeta1 = 0.5f, kBeta2 = 0.999f, kEps = 1e-8f;
+constexpr float kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
 
 }  // namespace
 
@@ -161,11 +161,13 @@ sg_status check_desc(const sg_conv_desc* d)
 {
     if (!d) return fail(SG_EINVAL, "conv: NULL descriptor");
     if (d->N < 1 || d->H < 1 || d->W < 1 || d->C < 8 || d->C % 8 || d->Co < 8 || d->Co % 8 || d->kernel < 1 ||
-        d->stride < 1 || d->pad < 0 || (d->upsample != 0 && d->upsample != 1))
-        return fail(SG_EINVAL, "conv: bad descriptor (C and Co multiples of 8, sizes >= 1)");
+        d->stride < 1 || d->pad < 0 || (d->upsample != 0 && d->upsample != 1) || d->C > 4096 || d->Co > 4096)
+        return fail(SG_EINVAL, "conv: bad descriptor (C and Co multiples of 8 in [8, 4096], sizes >= 1)");
     ConvShape sh{d->N, d->H, d->W, d->C, d->Co, d->kernel, d->stride, d->pad, d->upsample};
     if (sh.Hin() + 2 * sh.pad < sh.k || sh.Win() + 2 * sh.pad < sh.k) return fail(SG_EINVAL, "conv: empty output");
     const int64_t px = (int64_t)sh.N * sh.Hin() * sh.Win();
+    if (px >= (1ll << 31) || (int64_t)sh.N * sh.Ho() * sh.Wo() >= (1ll << 31))
+        return fail(SG_EINVAL, "conv: more than 2^31 - 1 pixels");
     if (px * std::max(sh.C, sh.Co) >= (1ll << 40)) return fail(SG_EINVAL, "conv: tensor too large");
     if ((int64_t)sh.k * sh.k * std::max(sh.C, sh.Co) >= (1ll << 30)) return fail(SG_EINVAL, "conv: K too large");
     return SG_OK;
@@ -253,9 +255,12 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
         const ConvShape sh = layer_shape(s, L, n);
         const int go = d.out2 >= 0 ? d.out2 : d.out;   // gradient at the layer's (skip-added) output
         const int64_t n_out = tensor_elems(s, d.out, n);
-        SG_TRY(check(mask_to_bf16((const float*)s.gact[go].p, (const uint16_t*)s.act[d.out].p, (uint16_t*)s.dpre.p,
-                                  n_out, c->stream),
-                     "relu mask"));
+        const int64_t rows = n_out / d.Co;
+        const int mb = blocks_for(rows * 16, 1024);
+        SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)mb * d.Co), "bias workspace"));
+        SG_TRY(check(mask_colsum((const float*)s.gact[go].p, (const uint16_t*)s.act[d.out].p, (uint16_t*)s.dpre.p,
+                                 rows, d.Co, (float*)s.parts.p, mb, grad + s.b_off[L], c->stream),
+                     "relu mask and bias gradient"));
         if (d.skip >= 0) {
             // out2 = out + skip: the skip tensor receives the same gradient
             SG_TRY(check(hipMemcpyAsync(s.gact[d.skip].p, s.gact[go].p, sizeof(float) * n_out,
@@ -263,8 +268,8 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
                          "skip gradient"));
             written[d.skip] = true;
         }
-        SG_TRY(wgrad(c, sh, (const uint16_t*)s.act[d.in].p, (const uint16_t*)s.dpre.p, grad + s.w_off[L],
-                     grad + s.b_off[L], s.parts));
+        SG_TRY(wgrad(c, sh, (const uint16_t*)s.act[d.in].p, (const uint16_t*)s.dpre.p, grad + s.w_off[L], nullptr,
+                     s.parts));
         if (L > 0) {
             SG_TRY(dgrad(c, sh, (const uint16_t*)s.dpre.p, (const uint16_t*)s.wt.p + s.w_off[L],
                          (float*)s.gact[d.in].p, written[d.in] ? 1 : 0, s.fine));
@@ -375,6 +380,7 @@ extern "C" sg_status sg_conv_backward_weight(sg_ctx* c, const sg_conv_desc* d, c
 {
     if (!c || !x || !dy || !dw) return fail(SG_EINVAL, "sg_conv_backward_weight: NULL argument");
     SG_TRY(check_desc(d));
+    if (db && d->Co > 256) return fail(SG_EINVAL, "sg_conv_backward_weight: bias gradient needs Co <= 256");
     (void)hipSetDevice(c->device);
     return wgrad(c, shape_of(d), x, dy, dw, db, c->op_parts);
 }

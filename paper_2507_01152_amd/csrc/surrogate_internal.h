@@ -6,6 +6,27 @@
 
 namespace sg {
 
+// Division by a fixed divisor d (1 <= d < 2^31) for dividends n < 2^31 by one
+// multiply-high and a shift (Granlund & Montgomery, "Division by invariant
+// integers using multiplication", PLDI 1994): q = (mulhi(n, m) + n) >> s with
+// s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    const uint64_t m = ((1ull << 32) * ((1ull << s) - d)) / d + 1;
+    return FastDiv{d, (uint32_t)m, s};
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f)
+{
+    return (uint32_t)(((uint64_t)__umulhi(n, f.m) + n) >> f.s);
+}
+
 // GEMM view of one convolution product (see conv_mfma.hip).
 struct ConvGeom {
     int64_t M;      // GEMM rows
@@ -16,6 +37,7 @@ struct ConvGeom {
     int32_t H, W;   // stored input size (before the optional x2 upsampling)
     int32_t Ho, Wo; // output size
     int32_t kh, kw, stride, pad, up;
+    FastDiv f_c, f_co, f_kw, f_stride, f_howo, f_wo, f_hinwin, f_win;
 };
 
 struct ConvArgs {
@@ -54,6 +76,14 @@ inline ConvGeom geom_of(const ConvShape& s, int mode)
     g.pad = s.pad;
     g.up = s.up;
     g.Kw = (int64_t)s.N * g.Ho * g.Wo;
+    g.f_c = make_fastdiv((uint32_t)s.C);
+    g.f_co = make_fastdiv((uint32_t)s.Co);
+    g.f_kw = make_fastdiv((uint32_t)s.k);
+    g.f_stride = make_fastdiv((uint32_t)s.stride);
+    g.f_howo = make_fastdiv((uint32_t)(g.Ho * g.Wo));
+    g.f_wo = make_fastdiv((uint32_t)g.Wo);
+    g.f_hinwin = make_fastdiv((uint32_t)(s.Hin() * s.Win()));
+    g.f_win = make_fastdiv((uint32_t)s.Win());
     if (mode == 0) {
         g.M = (int64_t)s.N * g.Ho * g.Wo;
         g.N = s.Co;
@@ -73,6 +103,9 @@ inline ConvGeom geom_of(const ConvShape& s, int mode)
 hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s);
 int wgrad_tile_m(int M);
 hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s);
+// out = bf16(g * [y > 0]) over [rows][C] and bias_grad[c] = sum of out's column c (C <= 256)
+hipError_t mask_colsum(const float* g, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
+                       int blocks, float* bias_grad, hipStream_t s);
 hipError_t pool2x2_sum(const float* fine, float* coarse, int N, int H, int W, int C, int accumulate, hipStream_t s);
 hipError_t colsum_bf16(const uint16_t* x, int64_t rows, int cols, float* part, int blocks, float* out,
                        hipStream_t s);

@@ -108,7 +108,7 @@ def test_adam_first_step_closed_form():
     w1, m, v = so.adam_update(w, g, np.zeros(100), np.zeros(100), step=1, lr=1e-3)
     # with zero moments the first bias-corrected step is lr * g / (|g| + eps)
     assert np.allclose(w1, w - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
-    assert np.allclose(m, 0.5 * g) and np.allclose(v, 0.001 * g * g)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
 
 
 def test_forward_shapes_and_psnr():
