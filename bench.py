@@ -54,13 +54,14 @@ def psf_ops_per_pixel(W: int, H: int) -> int:
 # the FLOP count) -- five levels 16/32/64/128/256, decoders read x2 upsampled
 SURR_CONVS = [(8, 16, 0), (16, 16, 0), (16, 32, 1), (32, 32, 1), (32, 64, 2), (64, 64, 2), (64, 128, 3),
               (128, 128, 3), (128, 256, 4), (256, 256, 4), (256, 128, 3), (128, 128, 3), (128, 64, 2),
-              (64, 64, 2), (64, 32, 1), (32, 32, 1), (32, 16, 0), (16, 16, 0)]
+              (64, 64, 2), (64, 32, 1), (32, 32, 1), (32, 16, 0), (24, 16, 0)]
 
 
 def surrogate_flops_per_frame(H: int, W: int) -> float:
-    """Forward FLOPs (2 per multiply-add) of the convolutions and head."""
+    """Forward FLOPs (2 per multiply-add) of the convolutions, the 1x1 depth
+    map (16 -> 8) with its running sum, and the head."""
     f = sum(2.0 * 9 * ci * co * (H >> lv) * (W >> lv) for ci, co, lv in SURR_CONVS)
-    return f + 2.0 * 16 * H * W
+    return f + (2.0 * 16 * 8 + 8) * H * W + 2.0 * 16 * H * W
 
 
 def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, psnr_min: float = 30.0):
@@ -122,7 +123,7 @@ def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, ps
         "frames_from_physics": int(n_fb),
         "train": {"steps": train_steps, "pairs": train_steps * 64, "seconds": round(train_s, 1),
                   "last_eval": hist[-1] if hist else None},
-        "roofline": {"bound": "mfma", "kernel": "network forward (encode + 18 convs + head)",
+        "roofline": {"bound": "mfma", "kernel": "network forward (encode + 18 convs + depth integral + head)",
                      "achieved": round(flops / net_s / 1e12, 2), "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(flops / net_s / 1e12 / 2500.0, 4), "flops_per_launch": flops,
                      "ms": round(net_s * 1e3, 3)},

@@ -10,9 +10,16 @@ slices plus one scatterer channel.  Numbers are bf16 where the GPU stores
 bf16 (weights, activations, the masked output gradients), with every sum
 carried out in FP64 here instead of FP32.
 
+The decoder's last 3x3 conv also reads a beam-axis integral: a 1x1 map of
+the full-resolution encoder tensor E0 to 8 channels, summed down each
+scanline over the rows above the pixel (scaled by 1/16) and appended to S0.
+This mirrors the exclusive depth integral of the energy equation (App. B.2),
+which a plain encoder-decoder reproduces only coarsely.
+
 Conventions:
-  tensors NHWC; conv weights [Co][k][k][Ci]; parameters flattened layer by
-  layer as (weights, bias), then the 1x1 head (16 weights, 1 bias).
+  tensors NHWC, rows = depth; conv weights [Co][k][k][Ci]; parameters
+  flattened layer by layer as (weights, bias), then the depth-integral map
+  (8 x 16 weights, 8 biases), then the 1x1 head (16 weights, 1 bias).
 """
 from __future__ import annotations
 
@@ -114,7 +121,7 @@ TENSORS = {
     "X": (8, 0), "T1": (16, 0), "E0": (16, 0), "T2": (32, 1), "E1": (32, 1), "T3": (64, 2), "E2": (64, 2),
     "T4": (128, 3), "E3": (128, 3), "T5": (256, 4), "B4": (256, 4),
     "U3": (128, 3), "S3": (128, 3), "D3": (128, 3), "U2": (64, 2), "S2": (64, 2), "D2": (64, 2),
-    "U1": (32, 1), "S1": (32, 1), "D1": (32, 1), "U0": (16, 0), "S0": (16, 0), "D0": (16, 0),
+    "U1": (32, 1), "S1": (32, 1), "D1": (32, 1), "U0": (16, 0), "S0": (24, 0), "D0": (16, 0),
 }
 
 # (input, output, stride, upsample, skip tensor, skip-added output); all 3x3, pad 1, ReLU
@@ -130,6 +137,22 @@ LAYERS = [
     ("D1", "U0", 1, True, "E0", "S0"), ("S0", "D0", 1, False, None, None),
 ]
 HEAD_C = 16
+# depth integral: source tensor, tensor it is appended to, channels, scale
+SCAN_SRC, SCAN_DST, SCAN_C, SCAN_SCALE = "E0", "S0", 8, 1.0 / 16.0
+
+
+def depth_sum_above(p):
+    """Exclusive running sum over rows (axis 1): out[:, y] = sum_{v < y} p[:, v]."""
+    out = np.zeros_like(p)
+    out[:, 1:] = np.cumsum(p, axis=1)[:, :-1]
+    return out
+
+
+def depth_sum_below(g):
+    """Adjoint of depth_sum_above: out[:, v] = sum_{y > v} g[:, y]."""
+    out = np.zeros_like(g)
+    out[:, :-1] = np.cumsum(g[:, ::-1], axis=1)[:, ::-1][:, 1:]
+    return out
 
 
 def param_layout():
@@ -141,6 +164,11 @@ def param_layout():
         off += co * 9 * ci
         out.append((f"b{i}", off, (co,)))
         off += co
+    cs = TENSORS[SCAN_SRC][0]
+    out.append(("wp", off, (SCAN_C, cs)))
+    off += SCAN_C * cs
+    out.append(("bp", off, (SCAN_C,)))
+    off += SCAN_C
     out.append(("head_w", off, (HEAD_C,)))
     off += HEAD_C
     out.append(("head_b", off, (1,)))
@@ -173,6 +201,9 @@ def forward(params, x, rounding=True):
         act[dst] = q(y)
         if skip is not None:
             act[dst2] = q(act[dst] + act[skip])
+            if dst2 == SCAN_DST:
+                p = act[SCAN_SRC] @ q(params["wp"]).T + params["bp"]
+                act[dst2] = np.concatenate([act[dst2], q(SCAN_SCALE * depth_sum_above(p))], axis=-1)
     yhat = act["D0"] @ q(params["head_w"]) + params["head_b"][0]
     return act, yhat
 
@@ -191,9 +222,17 @@ def backward(params, act, yhat, y, rounding=True):
     for i in range(len(LAYERS) - 1, -1, -1):
         src, dst, stride, up, skip, dst2 = LAYERS[i]
         gout = g[dst2] if dst2 is not None else g[dst]
+        if dst2 == SCAN_DST:
+            # split the appended depth-integral channels off and back-propagate them
+            gout, ga = gout[..., :-SCAN_C], gout[..., -SCAN_C:]
+            dp = q(SCAN_SCALE * depth_sum_below(ga))
+            grads["wp"] = np.einsum("nhwk,nhwc->kc", dp, act[SCAN_SRC])
+            grads["bp"] = dp.sum(axis=(0, 1, 2))
+            gs = dp @ q(params["wp"])
+            g[SCAN_SRC] = g[SCAN_SRC] + gs if SCAN_SRC in g else gs
         dpre = q(gout * (act[dst] > 0))
         if skip is not None:
-            g[skip] = gout.copy()
+            g[skip] = g[skip] + gout if skip in g else gout.copy()
         dw, db = conv_backward_weight(act[src], dpre, k=3, stride=stride, pad=1, up=up)
         grads[f"w{i}"], grads[f"b{i}"] = dw, db
         if i > 0:

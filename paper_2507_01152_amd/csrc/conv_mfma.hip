@@ -287,7 +287,8 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
                     const uint16_t yb = f2bf(y);
                     if (a.out_bf16) a.out_bf16[o] = yb;
                     if (a.out_f32) a.out_f32[o] = y;
-                    if (a.skip && a.out2_bf16) a.out2_bf16[o] = f2bf(bf2f(yb) + bf2f(a.skip[o]));
+                    if (a.skip && a.out2_bf16)
+                        a.out2_bf16[row * (a.ld_out2 ? a.ld_out2 : g.Co) + col] = f2bf(bf2f(yb) + bf2f(a.skip[o]));
                 } else if constexpr (MODE == kDgrad) {
                     const int64_t o = row * g.C + col;
                     a.out_f32[o] = a.accumulate ? a.out_f32[o] + v : v;
@@ -334,7 +335,7 @@ __global__ void k_pool2x2_sum(const float* fine, float* coarse, int N, int H, in
 // be null: g is already bf16 in gb), part[block][c] = sum of the block's rows
 // of out.  Thread t owns column t % C for every (256 / C)-th row; the threads
 // of a column are summed in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_mask_colsum(const float* g, const uint16_t* gb, const uint16_t* y,
+__global__ __launch_bounds__(256) void k_mask_colsum(const float* g, int ldg, const uint16_t* gb, const uint16_t* y,
                                                      uint16_t* out, int64_t rows, int C, int64_t rows_per_block,
                                                      float* part)
 {
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(256) void k_mask_colsum(const float* g, const uint1
             if (gb) {
                 b = gb[i];
             } else {
-                b = f2bf((y == nullptr || bf2f(y[i]) > 0.f) ? g[i] : 0.f);
+                b = f2bf((y == nullptr || bf2f(y[i]) > 0.f) ? g[r * ldg + c] : 0.f);
                 if (out) out[i] = b;
             }
             s += bf2f(b);
@@ -368,6 +369,147 @@ __global__ __launch_bounds__(256) void k_mask_colsum(const float* g, const uint1
 }
 
 // out[i] = sum_s part[s][i] in fixed order
+// Depth integral along the beam.  One wave per (frame, column), grid-stride
+// over columns; lanes run along depth in chunks of 64 rows.  Each chunk is a
+// Hillis-Steele scan over the wave (lane shuffles) plus the running total of
+// the chunks already done.  Eight channels per pixel (kScanC).
+constexpr int kScanC = 8;
+
+__device__ __forceinline__ float lane_get(float v, int src) { return __shfl(v, src, 64); }
+
+// out[n][y][x][c_off + k] = bf16(scale * sum_{v < y} p[n][v][x][k])
+__global__ __launch_bounds__(256) void k_depth_scan_fwd(const float* __restrict__ p, uint16_t* __restrict__ out,
+                                                        int N, int H, int W, float scale, int ld, int c_off)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t n_cols = (int64_t)N * W;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t col = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); col < n_cols; col += waves) {
+        const int64_t n = col / W;
+        const int x = (int)(col - n * W);
+        float carry[kScanC];
+#pragma unroll
+        for (int k = 0; k < kScanC; ++k) carry[k] = 0.f;
+        for (int y0 = 0; y0 < H; y0 += 64) {
+            const int y = y0 + lane;
+            const int64_t px = (n * H + y) * W + x;
+            float v[kScanC];
+            if (y < H) {
+                const float4 a = *reinterpret_cast<const float4*>(p + px * kScanC);
+                const float4 b = *reinterpret_cast<const float4*>(p + px * kScanC + 4);
+                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+                v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < kScanC; ++k) v[k] = 0.f;
+            }
+            // exclusive: shift down by one lane, then an inclusive scan
+#pragma unroll
+            for (int k = 0; k < kScanC; ++k) {
+                float e = lane_get(v[k], lane - 1);
+                e = lane > 0 ? e : 0.f;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const float t = lane_get(e, lane - d);
+                    if (lane >= d) e += t;
+                }
+                const float tot = lane_get(e + v[k], 63);
+                v[k] = carry[k] + e;
+                carry[k] += tot;
+            }
+            if (y < H) {
+                u32x4 o;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    o[j] = (uint32_t)f2bf(scale * v[2 * j]) | ((uint32_t)f2bf(scale * v[2 * j + 1]) << 16);
+                *reinterpret_cast<u32x4*>(out + px * ld + c_off) = o;
+            }
+        }
+    }
+}
+
+// Backward of k_depth_scan_fwd through a tensor g [pixel][ld] (FP32) whose
+// channels [c_off, c_off + 8) are the integral's gradient:
+//   dp[n][v][x][k] = bf16(scale * sum_{y > v} g[n][y][x][c_off + k]),
+// channels [0, c_off) copied to g_skip [pixel][c_off], and per-block column
+// sums of the bf16 dp (bias gradient partials) in part[block][8].
+__global__ __launch_bounds__(256) void k_depth_scan_bwd(const float* __restrict__ g, int ld, int c_off,
+                                                        float* __restrict__ g_skip, uint16_t* __restrict__ dp,
+                                                        float* __restrict__ part, int N, int H, int W, float scale)
+{
+    __shared__ float red[4][kScanC];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t n_cols = (int64_t)N * W;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    float bsum[kScanC];
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) bsum[k] = 0.f;
+    for (int64_t col = (int64_t)blockIdx.x * 4 + wave; col < n_cols; col += waves) {
+        const int64_t n = col / W;
+        const int x = (int)(col - n * W);
+        float carry[kScanC];
+#pragma unroll
+        for (int k = 0; k < kScanC; ++k) carry[k] = 0.f;
+        const int n_chunks = (H + 63) / 64;
+        for (int ch = n_chunks - 1; ch >= 0; --ch) {
+            const int y = ch * 64 + lane;
+            const int64_t px = (n * H + y) * W + x;
+            float v[kScanC];
+            if (y < H) {
+                const float* src = g + px * ld;
+                for (int c = 0; c < c_off; c += 4)
+                    *reinterpret_cast<float4*>(g_skip + px * c_off + c) = *reinterpret_cast<const float4*>(src + c);
+                const float4 a = *reinterpret_cast<const float4*>(src + c_off);
+                const float4 b = *reinterpret_cast<const float4*>(src + c_off + 4);
+                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+                v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < kScanC; ++k) v[k] = 0.f;
+            }
+            // exclusive suffix: shift up by one lane, then an inclusive suffix scan
+#pragma unroll
+            for (int k = 0; k < kScanC; ++k) {
+                float e = lane_get(v[k], lane + 1);
+                e = lane < 63 ? e : 0.f;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const float t = lane_get(e, lane + d);
+                    if (lane + d < 64) e += t;
+                }
+                const float tot = lane_get(e + v[k], 0);
+                v[k] = carry[k] + e;
+                carry[k] += tot;
+            }
+            if (y < H) {
+                u32x4 o;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint16_t lo = f2bf(scale * v[2 * j]), hi = f2bf(scale * v[2 * j + 1]);
+                    bsum[2 * j] += bf2f(lo);
+                    bsum[2 * j + 1] += bf2f(hi);
+                    o[j] = (uint32_t)lo | ((uint32_t)hi << 16);
+                }
+                *reinterpret_cast<u32x4*>(dp + px * kScanC) = o;
+            }
+        }
+    }
+    // fixed-order reduction: wave butterfly, then the block's four waves
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) {
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) bsum[k] += lane_get(bsum[k], lane ^ d);
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < kScanC; ++k) red[wave][k] = bsum[k];
+    __syncthreads();
+    if (threadIdx.x < kScanC)
+        part[(int64_t)blockIdx.x * kScanC + threadIdx.x] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
 __global__ void k_sum_parts(const float* part, int64_t n, int splits, float* out)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -613,15 +755,44 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
 
 int wgrad_tile_m(int M) { return M <= 16 ? 16 : (M <= 32 ? 32 : 64); }
 
-hipError_t mask_colsum(const float* g, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
+hipError_t mask_colsum(const float* g, int ldg, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
                        int blocks, float* bias_grad, hipStream_t s)
 {
-    if (C > 256) return hipErrorInvalidValue;
+    if (C > 256 || (ldg != 0 && ldg < C)) return hipErrorInvalidValue;
     const int64_t per = (rows + blocks - 1) / blocks;
-    hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, g, nullptr, y, out, rows, C, per, part);
+    hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, g, ldg ? ldg : C, nullptr, y, out, rows, C, per,
+                       part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(C)), dim3(256), 0, s, part, (int64_t)C, blocks, bias_grad);
+    return hipGetLastError();
+}
+
+int depth_scan_blocks(int N, int W)
+{
+    const int64_t b = ((int64_t)N * W + 3) / 4;
+    return (int)(b > 1024 ? 1024 : (b < 1 ? 1 : b));
+}
+
+hipError_t depth_scan_fwd(const float* p, uint16_t* out, int N, int H, int W, float scale, int ld, int c_off,
+                          hipStream_t s)
+{
+    if (ld % 8 || c_off % 8 || c_off + kScanC > ld) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_depth_scan_fwd, dim3((unsigned)depth_scan_blocks(N, W)), dim3(256), 0, s, p, out, N, H, W,
+                       scale, ld, c_off);
+    return hipGetLastError();
+}
+
+hipError_t depth_scan_bwd(const float* g, int ld, int c_off, float* g_skip, uint16_t* dp, float* part,
+                          float* bias_grad, int N, int H, int W, float scale, hipStream_t s)
+{
+    if (ld % 4 || c_off % 4 || c_off + kScanC > ld) return hipErrorInvalidValue;
+    const int blocks = depth_scan_blocks(N, W);
+    hipLaunchKernelGGL(k_depth_scan_bwd, dim3((unsigned)blocks), dim3(256), 0, s, g, ld, c_off, g_skip, dp, part, N,
+                       H, W, scale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int64_t)kScanC, blocks, bias_grad);
     return hipGetLastError();
 }
 
@@ -644,8 +815,8 @@ hipError_t colsum_bf16(const uint16_t* x, int64_t rows, int cols, float* part, i
 {
     if (cols > 256) return hipErrorInvalidValue;
     const int64_t per = (rows + blocks - 1) / blocks;
-    hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, nullptr, x, nullptr, nullptr, rows, cols, per,
-                       part);
+    hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, nullptr, cols, x, nullptr, nullptr, rows, cols,
+                       per, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(cols)), dim3(256), 0, s, part, (int64_t)cols, blocks, out);

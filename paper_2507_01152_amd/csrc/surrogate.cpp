@@ -19,14 +19,15 @@ namespace {
 
 // tensors of the network (per frame: channels and pyramid level)
 enum { X = 0, T1, E0, T2, E1, T3, E2, T4, E3, T5, B4, U3, S3, D3, U2, S2, D2, U1, S1, D1, U0, S0, D0, kNumT };
-const int kTC[kNumT] = {8, 16, 16, 32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 128, 64, 64, 64, 32, 32, 32, 16, 16, 16};
+const int kTC[kNumT] = {8, 16, 16, 32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 128, 64, 64, 64, 32, 32, 32, 16, 24, 16};
 const int kTL[kNumT] = {0, 0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 3, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0};
 
 struct LayerDef {
     int in, out, skip, out2, Ci, Co, stride, up;
 };
 // 3x3 convs with ReLU; decoder "U" layers read their input upsampled x2 and
-// add the encoder tensor of the same level (out2 = out + skip).
+// add the encoder tensor of the same level (out2 = out + skip).  S0 has 8
+// more channels: the depth integral of a 1x1 map of E0 (kScan*).
 const LayerDef kLayers[] = {
     {X, T1, -1, -1, 8, 16, 1, 0},       {T1, E0, -1, -1, 16, 16, 1, 0},
     {E0, T2, -1, -1, 16, 32, 2, 0},     {T2, E1, -1, -1, 32, 32, 1, 0},
@@ -36,10 +37,15 @@ const LayerDef kLayers[] = {
     {B4, U3, E3, S3, 256, 128, 1, 1},   {S3, D3, -1, -1, 128, 128, 1, 0},
     {D3, U2, E2, S2, 128, 64, 1, 1},    {S2, D2, -1, -1, 64, 64, 1, 0},
     {D2, U1, E1, S1, 64, 32, 1, 1},     {S1, D1, -1, -1, 32, 32, 1, 0},
-    {D1, U0, E0, S0, 32, 16, 1, 1},     {S0, D0, -1, -1, 16, 16, 1, 0},
+    {D1, U0, E0, S0, 32, 16, 1, 1},     {S0, D0, -1, -1, 24, 16, 1, 0},
 };
 constexpr int kNumL = sizeof(kLayers) / sizeof(kLayers[0]);
 constexpr int kHeadC = 16;
+// depth integral along the beam (the exclusive sum over rows above a pixel,
+// as in the energy equation of App. B.2): p = W_p E0 + b_p (1x1, 16 -> 8),
+// S0[..., 16 + k] = bf16(kScanScale * sum_{v < y} p_k(v))
+constexpr int kScanSrc = E0, kScanDst = S0, kScanC = 8, kScanOff = 16;
+constexpr float kScanScale = 1.f / 16.f;
 constexpr float kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
 
 }  // namespace
@@ -48,12 +54,13 @@ struct Surrogate {
     int H = 0, W = 0;
     int64_t n_params = 0;
     int64_t w_off[kNumL], b_off[kNumL], w_n[kNumL];
+    int64_t proj_w = 0, proj_b = 0;
     int64_t head_w = 0, head_b = 0;
     DevBuf master, mom1, mom2, grad, wb, wt;
     int64_t step = 0;
     int cap = 0, cap_grad = 0, last_n = 0;
     DevBuf act[kNumT], gact[kNumT];
-    DevBuf dpre, fine, parts, yhat, target, gy, loss, psnr, idx;
+    DevBuf dpre, fine, parts, proj, yhat, target, gy, loss, psnr, idx;
 };
 
 void SurrogateDeleter::operator()(Surrogate* p) const { delete p; }
@@ -185,6 +192,7 @@ sg_status ensure_capacity(Surrogate& s, int n, bool grads)
         for (int t = 0; t < kNumT; ++t)
             SG_TRY(check(s.act[t].ensure(sizeof(uint16_t) * tensor_elems(s, t, n)), "activation buffers"));
         const int64_t P = (int64_t)n * s.H * s.W;
+        SG_TRY(check(s.proj.ensure(sizeof(float) * P * kScanC), "depth integral buffer"));
         SG_TRY(check(s.yhat.ensure(sizeof(float) * P), "output buffer"));
         SG_TRY(check(s.target.ensure(sizeof(float) * P), "target buffer"));
         s.cap = n;
@@ -210,9 +218,27 @@ sg_status refresh_bf16(sg_ctx* c, Surrogate& s)
                                      (uint16_t*)s.wt.p + s.w_off[L], d.Co, 9, d.Ci, c->stream),
                      "bf16 weights"));
     }
+    SG_TRY(check(weights_to_bf16((float*)s.master.p + s.proj_w, kScanC * kTC[kScanSrc], (uint16_t*)s.wb.p + s.proj_w,
+                                 (uint16_t*)s.wt.p + s.proj_w, kScanC, 1, kTC[kScanSrc], c->stream),
+                 "bf16 depth map"));
     return check(weights_to_bf16((float*)s.master.p + s.head_w, kHeadC, (uint16_t*)s.wb.p + s.head_w, nullptr, 1, 1,
                                  kHeadC, c->stream),
                  "bf16 head");
+}
+
+ConvShape proj_shape(const Surrogate& s, int n)
+{
+    ConvShape sh;
+    sh.N = n;
+    sh.H = s.H;
+    sh.W = s.W;
+    sh.C = kTC[kScanSrc];
+    sh.Co = kScanC;
+    sh.k = 1;
+    sh.stride = 1;
+    sh.pad = 0;
+    sh.up = 0;
+    return sh;
 }
 
 sg_status forward(sg_ctx* c, Surrogate& s, int n)
@@ -230,8 +256,22 @@ sg_status forward(sg_ctx* c, Surrogate& s, int n)
         if (d.skip >= 0) {
             a.skip = (const uint16_t*)s.act[d.skip].p;
             a.out2_bf16 = (uint16_t*)s.act[d.out2].p;
+            a.ld_out2 = kTC[d.out2];
         }
         SG_TRY(check(conv_gemm(0, geom_of(sh, 0), a, 1, c->stream), "forward conv"));
+        if (d.out2 == kScanDst) {
+            // 1x1 map of E0 to FP32, then its depth integral into S0's last channels
+            ConvArgs p;
+            std::memset(&p, 0, sizeof(p));
+            p.a = (const uint16_t*)s.act[kScanSrc].p;
+            p.b = (const uint16_t*)s.wb.p + s.proj_w;
+            p.bias = (const float*)s.master.p + s.proj_b;
+            p.out_f32 = (float*)s.proj.p;
+            SG_TRY(check(conv_gemm(0, geom_of(proj_shape(s, n), 0), p, 1, c->stream), "depth map"));
+            SG_TRY(check(depth_scan_fwd((const float*)s.proj.p, (uint16_t*)s.act[kScanDst].p, n, s.H, s.W, kScanScale,
+                                        kTC[kScanDst], kScanOff, c->stream),
+                         "depth integral"));
+        }
     }
     return check(head_fwd((const uint16_t*)s.act[D0].p, (const uint16_t*)s.wb.p + s.head_w,
                           (const float*)s.master.p + s.head_b, (float*)s.yhat.p, (int64_t)n * s.H * s.W, kHeadC,
@@ -256,12 +296,28 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
         const int go = d.out2 >= 0 ? d.out2 : d.out;   // gradient at the layer's (skip-added) output
         const int64_t n_out = tensor_elems(s, d.out, n);
         const int64_t rows = n_out / d.Co;
+        if (go == kScanDst) {
+            // depth integral: dp (bf16, in dpre), its bias gradient, and the skip copy of
+            // S0's first channels into E0's gradient; then the 1x1 map's two products
+            const int sb = depth_scan_blocks(n, s.W);
+            SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)sb * kScanC), "depth integral workspace"));
+            SG_TRY(check(depth_scan_bwd((const float*)s.gact[kScanDst].p, kTC[kScanDst], kScanOff,
+                                        (float*)s.gact[kScanSrc].p, (uint16_t*)s.dpre.p, (float*)s.parts.p,
+                                        grad + s.proj_b, n, s.H, s.W, kScanScale, c->stream),
+                         "depth integral backward"));
+            const ConvShape ps = proj_shape(s, n);
+            SG_TRY(wgrad(c, ps, (const uint16_t*)s.act[kScanSrc].p, (const uint16_t*)s.dpre.p, grad + s.proj_w,
+                         nullptr, s.parts));
+            SG_TRY(dgrad(c, ps, (const uint16_t*)s.dpre.p, (const uint16_t*)s.wt.p + s.proj_w,
+                         (float*)s.gact[kScanSrc].p, 1, s.fine));
+            written[kScanSrc] = true;
+        }
         const int mb = blocks_for(rows * 16, 1024);
         SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)mb * d.Co), "bias workspace"));
-        SG_TRY(check(mask_colsum((const float*)s.gact[go].p, (const uint16_t*)s.act[d.out].p, (uint16_t*)s.dpre.p,
-                                 rows, d.Co, (float*)s.parts.p, mb, grad + s.b_off[L], c->stream),
+        SG_TRY(check(mask_colsum((const float*)s.gact[go].p, kTC[go], (const uint16_t*)s.act[d.out].p,
+                                 (uint16_t*)s.dpre.p, rows, d.Co, (float*)s.parts.p, mb, grad + s.b_off[L], c->stream),
                      "relu mask and bias gradient"));
-        if (d.skip >= 0) {
+        if (d.skip >= 0 && go != kScanDst) {   // (S0's skip copy is done by the depth integral's backward)
             // out2 = out + skip: the skip tensor receives the same gradient
             SG_TRY(check(hipMemcpyAsync(s.gact[d.skip].p, s.gact[go].p, sizeof(float) * n_out,
                                         hipMemcpyDeviceToDevice, c->stream),
@@ -299,6 +355,13 @@ sg_status adam(sg_ctx* c, Surrogate& s, float lr)
                                1, 1, 1, c->stream),
                      "adam bias"));
     }
+    const int cs = kTC[kScanSrc];
+    SG_TRY(check(adam_step(w + s.proj_w, m + s.proj_w, v + s.proj_w, g + s.proj_w, kScanC * cs, lr, kBeta1, kBeta2, kEps,
+                           c1, c2, (uint16_t*)s.wb.p + s.proj_w, (uint16_t*)s.wt.p + s.proj_w, kScanC, 1, cs, c->stream),
+                 "adam depth map"));
+    SG_TRY(check(adam_step(w + s.proj_b, m + s.proj_b, v + s.proj_b, g + s.proj_b, kScanC, lr, kBeta1, kBeta2, kEps, c1,
+                           c2, nullptr, nullptr, 1, 1, 1, c->stream),
+                 "adam depth map bias"));
     SG_TRY(check(adam_step(w + s.head_w, m + s.head_w, v + s.head_w, g + s.head_w, kHeadC, lr, kBeta1, kBeta2, kEps, c1,
                            c2, (uint16_t*)s.wb.p + s.head_w, nullptr, 1, 1, kHeadC, c->stream),
                  "adam head"));
@@ -406,6 +469,10 @@ extern "C" sg_status sg_surr_create(sg_ctx* c, int32_t H, int32_t W, uint64_t se
         s->b_off[L] = off;
         off += kLayers[L].Co;
     }
+    s->proj_w = off;
+    off += kScanC * kTC[kScanSrc];
+    s->proj_b = off;
+    off += kScanC;
     s->head_w = off;
     off += kHeadC;
     s->head_b = off;
@@ -418,6 +485,8 @@ extern "C" sg_status sg_surr_create(sg_ctx* c, int32_t H, int32_t W, uint64_t se
         std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (9.f * kLayers[L].Ci)));
         for (int64_t i = 0; i < s->w_n[L]; ++i) h[s->w_off[L] + i] = nd(rng);
     }
+    std::normal_distribution<float> np_(0.f, std::sqrt(1.f / kTC[kScanSrc]));
+    for (int i = 0; i < kScanC * kTC[kScanSrc]; ++i) h[s->proj_w + i] = np_(rng);
     std::normal_distribution<float> nh(0.f, std::sqrt(1.f / kHeadC));
     for (int i = 0; i < kHeadC; ++i) h[s->head_w + i] = nh(rng);
     h[s->head_b] = 0.2f;

@@ -47,6 +47,7 @@ struct ConvArgs {
     int32_t relu;            // forward
     const uint16_t* skip;    // forward: second output = out + skip (may be null)
     uint16_t* out2_bf16;
+    int32_t ld_out2;         // channels per pixel of out2 (0: Co); out2 may be wider than the conv's output
     uint16_t* out_bf16;      // forward
     float* out_f32;          // forward (optional), data gradient, weight gradient partials
     int32_t accumulate;      // data gradient: add into out_f32
@@ -103,9 +104,19 @@ inline ConvGeom geom_of(const ConvShape& s, int mode)
 hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s);
 int wgrad_tile_m(int M);
 hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s);
-// out = bf16(g * [y > 0]) over [rows][C] and bias_grad[c] = sum of out's column c (C <= 256)
-hipError_t mask_colsum(const float* g, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
+// out = bf16(g * [y > 0]) over [rows][C] and bias_grad[c] = sum of out's column c (C <= 256);
+// g has ldg floats per row (0: C)
+hipError_t mask_colsum(const float* g, int ldg, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
                        int blocks, float* bias_grad, hipStream_t s);
+// depth integral of 8 FP32 channels p [N][H][W][8] down each column (rows above only), times scale, into
+// channels [c_off, c_off + 8) of the bf16 tensor out [N][H][W][ld]
+hipError_t depth_scan_fwd(const float* p, uint16_t* out, int N, int H, int W, float scale, int ld, int c_off,
+                          hipStream_t s);
+// its backward from g [N][H][W][ld] (FP32): dp (bf16, [N][H][W][8]), the channels [0, c_off) copied to
+// g_skip [N][H][W][c_off], bias_grad[8] = column sums of dp; part holds depth_scan_blocks(N, W) * 8 floats
+int depth_scan_blocks(int N, int W);
+hipError_t depth_scan_bwd(const float* g, int ld, int c_off, float* g_skip, uint16_t* dp, float* part,
+                          float* bias_grad, int N, int H, int W, float scale, hipStream_t s);
 hipError_t pool2x2_sum(const float* fine, float* coarse, int N, int H, int W, int C, int accumulate, hipStream_t s);
 hipError_t colsum_bf16(const uint16_t* x, int64_t rows, int cols, float* part, int blocks, float* out,
                        hipStream_t s);

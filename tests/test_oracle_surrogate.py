@@ -115,6 +115,37 @@ def test_forward_shapes_and_psnr():
     flat, x, y = _small_problem(H=32, W=16)
     act, yhat = so.forward(so.unflatten(flat), x)
     assert yhat.shape == (1, 32, 16)
-    assert act["B4"].shape == (1, 2, 1, 256) and act["S0"].shape == (1, 32, 16, 16)
+    assert act["B4"].shape == (1, 2, 1, 256) and act["S0"].shape == (1, 32, 16, 24)
     assert so.psnr(y, y) == 200.0
     assert abs(so.psnr(np.full_like(y, 0.5), np.full_like(y, 0.6)) - 20.0) < 1e-9
+
+
+def test_depth_integral_definition_and_adjoint():
+    """The depth integral is the running sum over the rows strictly above a
+    pixel (brute force), and the backward helper is its exact adjoint."""
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal((2, 7, 3, 4))
+    a = so.depth_sum_above(p)
+    for y in range(7):
+        assert np.allclose(a[:, y], p[:, :y].sum(axis=1), rtol=0, atol=1e-12)
+    g = rng.standard_normal(p.shape)
+    b = so.depth_sum_below(g)
+    for v in range(7):
+        assert np.allclose(b[:, v], g[:, v + 1:].sum(axis=1), rtol=0, atol=1e-12)
+    assert abs(np.sum(a * g) - np.sum(p * b)) < 1e-10
+
+
+def test_depth_integral_reaches_the_output_from_above_only():
+    """A change of E0 features at one row can move the decoder's appended
+    integral channels only in rows below it (causality along the beam)."""
+    flat, x, _ = _small_problem(H=32, W=16)
+    params = so.unflatten(flat)
+    act, _ = so.forward(params, x, rounding=False)
+    p = act["E0"] @ params["wp"].T + params["bp"]
+    a = so.SCAN_SCALE * so.depth_sum_above(p)
+    assert np.allclose(act["S0"][..., -so.SCAN_C:], a)
+    p2 = p.copy()
+    p2[:, 20] += 1.0
+    a2 = so.SCAN_SCALE * so.depth_sum_above(p2)
+    assert np.array_equal(a2[:, :21], a[:, :21])
+    assert np.allclose(a2[:, 21:] - a[:, 21:], so.SCAN_SCALE)

@@ -39,6 +39,8 @@ CONV_CASES = [
     (1, 5, 4, 256, 256, 3, 1, 1, 0),
     (1, 4, 3, 128, 64, 3, 1, 1, 1),
     (3, 11, 5, 24, 40, 1, 1, 0, 0),      # 1x1, channel counts not powers of two
+    (2, 9, 70, 16, 8, 1, 1, 0, 0),       # 1x1 to 8 channels (the depth map), K below one MFMA step
+    (1, 12, 10, 24, 16, 3, 1, 1, 0),     # 24 input channels (the last decoder conv)
 ]
 
 
@@ -145,9 +147,10 @@ def test_training_gradients_match_oracle(sess):
     oracle on the same bf16 input and target.  bf16 rounding flips of single
     activations (FP32 vs FP64 sums) make the layers differ by about 1e-3 to
     1e-2 in norm.  The flips matter most in the deepest levels, which have
-    the fewest pixels, so the frames are 128 x 64 (8 x 4 at the bottleneck)."""
+    the fewest pixels, so the batch is 4 frames of 128 x 64 (8 x 4 at the
+    bottleneck); the noise falls as one over the root of the pixel count."""
     from paper_2507_01152_amd import sonosim as sg
-    H, W, n = 128, 64, 2
+    H, W, n = 128, 64, 4
     wl = _pairs(n, H, W, seed=5)
     vids = sess.load(wl)
     sid = sg.sg_surr_create(sess.ctx, H, W, seed=11)
@@ -158,12 +161,16 @@ def test_training_gradients_match_oracle(sess):
     ref_loss, ref_g, _ = so.loss_and_grads(p0.astype(np.float64), so.bf16_bits_to_f64(xin), tgt.astype(np.float64))
     assert abs(loss - ref_loss) <= 1e-3 * ref_loss
     layout, _ = so.param_layout()
+    report = []
     for name, o, shape in layout:
         sz = int(np.prod(shape))
         a, b = g[o:o + sz], ref_g[o:o + sz]
         err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
         cos = float(a @ b) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
-        assert err <= 2e-2 and cos >= 0.999, (name, err, cos)
+        report.append((name, round(float(err), 5), round(cos, 6)))
+    print(report)
+    bad = [r for r in report if not (r[1] <= 2e-2 and r[2] >= 0.999)]
+    assert not bad, bad
     # one Adam step from zero moments moves each weight by lr * g / (|g| + eps)
     lr = 1e-3
     sid2 = sg.sg_surr_create(sess.ctx, H, W, seed=11)
