@@ -13,9 +13,11 @@ above 1 is refused.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -64,6 +66,34 @@ def surrogate_flops_per_frame(H: int, W: int) -> float:
     return f + (2.0 * 16 * 8 + 8) * H * W + 2.0 * 16 * H * W
 
 
+RAY_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_ray_hbm_traffic_256env.md")
+RAY_SOURCES = [os.path.join(ROOT, "paper_2507_01152_amd", "csrc", f) for f in ("physics.hip", "sg_internal.h")]
+
+
+def ray_kernel_digest() -> str:
+    h = hashlib.sha256()
+    for f in RAY_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def ray_traffic_bytes():
+    """HBM bytes per ray-kernel launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or None when
+    the summary is missing or was taken on other kernel sources."""
+    try:
+        with open(RAY_TRAFFIC_SUMMARY) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    b = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
+    d = re.search(r"^kernel_sources_sha256:\s*([0-9a-f]{64})", text, re.M)
+    if not b or not d or d.group(1) != ray_kernel_digest():
+        return None
+    return int(b.group(1))
+
+
 def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, psnr_min: float = 30.0):
     """Train the surrogate on physics pairs for a fixed budget, then time
     audited inference of n_envs 128 x 256 frames beside the physics path on
@@ -76,7 +106,7 @@ def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, ps
     from paper_2507_01152_amd.train_surrogate import FRAME_H, FRAME_W, PairSource, train
 
     t0 = time.perf_counter()
-    sess, sid, _train_src, _ev, hist = train(train_steps, 64, 5e-4, seed=0, eval_every=max(1, train_steps),
+    sess, sid, _train_src, _ev, hist = train(train_steps, 64, 1e-3, seed=0, eval_every=max(1, train_steps),
                                              log=lambda s: None)
     train_s = time.perf_counter() - t0
     test_src = PairSource(sess, 64, seed0=200000)     # held-out phantoms
@@ -140,8 +170,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--profile-launches", type=int, default=20)
-    ap.add_argument("--surrogate-steps", type=int, default=2500,
-                    help="training steps (batch 64) before timing surrogate inference; 0 skips the surrogate")
+    ap.add_argument("--surrogate-steps", type=int, default=3125,
+                    help="training steps (batch 64; 3125 = 200k pairs) before timing surrogate inference; "
+                         "0 skips the surrogate")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU time of the oracle baseline sample (whole steps, at most 20)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -230,7 +263,7 @@ def main():
             "frac": round(achieved_tops / PEAK_VALU_TOPS, 4),
             "ops_per_launch": ray_ops,
             "kernel_ms": round(ray_ms, 4),
-            "traffic": None,
+            "traffic": ray_traffic_bytes(),
             "psf_kernel": {"kernel_ms": round(psf_ms, 4), "ops_per_launch": psf_ops,
                            "achieved_Tops": round(psf_ops / (psf_ms / 1e3) / 1e12, 3)},
             "hbm_view_whole_step": {"algorithmic_bytes": alg_bytes, "achieved_GBps": round(achieved_gbs, 1),
@@ -241,15 +274,18 @@ def main():
 
     if not args.no_cpu:
         import oracle
-        t = time.perf_counter()
-        frames, used = oracle.simulate_batch(wl, n_threads=0)
-        dt = time.perf_counter() - t
+        reps, dt = 0, 0.0
+        while reps < 20 and (reps == 0 or dt < args.cpu_seconds):
+            t = time.perf_counter()
+            _frames, used = oracle.simulate_batch(wl, n_threads=0)
+            dt += time.perf_counter() - t
+            reps += 1
         res["cpu_baseline"] = {
-            "value": round(n / dt, 2),
+            "value": round(reps * n / dt, 2),
             "unit": "frames/s",
             "cores": used,
             "kind": "oracle",
-            "sample": f"one full step of the same workload ({n} envs, {pixels} px), FP64, "
+            "sample": f"{reps} full steps of the same workload ({n} envs, {pixels} px each), FP64, "
                       f"OpenMP over envs, {dt:.1f} s wall",
         }
         res["gpu_vs_cpu"] = round(fps / res["cpu_baseline"]["value"], 1)

@@ -301,6 +301,164 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Direct 3x3 convolution (stride 1, pad 1) for few channels.  A block computes
+// an 8 x 32 pixel output tile of one image for all CO output channels.  The
+// input tile with its one-pixel halo (10 x 34 pixels, zero outside the image;
+// with upsampling, fine pixel (h, w) reads stored pixel (h / 2, w / 2)) and
+// all weights are staged in LDS once, and the MFMA operands are read from
+// there, so each input pixel leaves global memory once per tile instead of
+// once per tap.  LDS pixel and weight rows are odd multiples of 16 bytes, so
+// the 16-byte operand reads of a wave are free of bank conflicts.  The output
+// tile is staged through LDS for 16-byte stores; the skip sum and a 1x1 head
+// with one output can be fused.
+constexpr int kTileH = 8, kTileW = 32;
+
+template <int C, int CO>
+__global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
+{
+    constexpr int HP = kTileH + 2, WP = kTileW + 2;
+    constexpr int C8 = C / 8;
+    constexpr int PS = (C8 % 2 == 0) ? C + 8 : C;   // LDS pixel stride (bf16)
+    constexpr int K8 = 9 * C8;                       // 8-wide K groups
+    constexpr int NKS = (K8 + 3) / 4;                // MFMA K steps of 32
+    constexpr int KP = NKS * 32 + 8;                 // LDS weight row (bf16), zero beyond K
+    constexpr int FN = CO / 16;
+    constexpr int CO8 = CO / 8;
+    constexpr int XS = HP * WP * PS, OS = kTileH * kTileW * CO;
+    __shared__ __attribute__((aligned(16))) uint16_t sX[XS > OS ? XS : OS];
+    __shared__ __attribute__((aligned(16))) uint16_t sW[CO * KP];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int tiles_x = (g.Wo + kTileW - 1) / kTileW, tiles_y = (g.Ho + kTileH - 1) / kTileH;
+    // neighbouring tiles on the same XCD (blocks are dealt round-robin over 8)
+    int64_t b = blockIdx.x;
+    const int64_t nb = gridDim.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int64_t per_img = (int64_t)tiles_x * tiles_y;
+    const int64_t n = b / per_img;
+    const int t_in = (int)(b - n * per_img);
+    const int ty = t_in / tiles_x, tx = t_in - ty * tiles_x;
+    const int ho0 = ty * kTileH, wo0 = tx * kTileW;
+    const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+
+    for (int i = tid; i < HP * WP * C8; i += 256) {
+        const int c8 = i % C8, pix = i / C8;
+        const int hy = pix / WP, wx = pix - hy * WP;
+        int hi = ho0 - 1 + hy, wi = wo0 - 1 + wx;
+        u32x4 v = zero;
+        if (hi >= 0 && wi >= 0 && hi < Hin && wi < Win) {
+            if (g.up) {
+                hi >>= 1;
+                wi >>= 1;
+            }
+            v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + hi) * g.W + wi) * C + c8 * 8);
+        }
+        *reinterpret_cast<u32x4*>(&sX[pix * PS + c8 * 8]) = v;
+    }
+    for (int i = tid; i < CO * NKS * 4; i += 256) {
+        const int co = i / (NKS * 4), k8 = i - co * (NKS * 4);
+        const u32x4 v = k8 < K8 ? *reinterpret_cast<const u32x4*>(a.b + (int64_t)co * (9 * C) + k8 * 8) : zero;
+        *reinterpret_cast<u32x4*>(&sW[co * KP + k8 * 8]) = v;
+    }
+    __syncthreads();
+
+    f32x4 acc[4][FN];
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[gi][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
+    for (int ks = 0; ks < NKS; ++ks) {
+        const int k8 = ks * 4 + lk;
+        int r = 0, s = 0, c0 = 0;
+        if (k8 < K8) {   // beyond K the weights are zero; read tap 0
+            const int tap = k8 / C8;
+            c0 = (k8 - tap * C8) * 8;
+            r = tap / 3;
+            s = tap - r * 3;
+        }
+        bf16x8 fb[FN];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) fb[j] = *reinterpret_cast<const bf16x8*>(&sW[(16 * j + lr) * KP + k8 * 8]);
+#pragma unroll
+        for (int gi = 0; gi < 4; ++gi) {
+            const int rr = 2 * wave + (gi >> 1), cc = (gi & 1) * 16 + lr;
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sX[((rr + r) * WP + cc + s) * PS + c0]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[gi][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[gi][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();   // sX is reused for the output tile
+
+    uint16_t* sO = sX;   // [kTileH * kTileW][CO]
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi) {
+        const int rr = 2 * wave + (gi >> 1);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int co = 16 * j + lr;
+            const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int cc = (gi & 1) * 16 + 4 * lk + q;
+                float y = acc[gi][j][q] + bias;
+                if (a.relu) y = fmaxf(y, 0.f);
+                sO[(rr * kTileW + cc) * CO + co] = f2bf(y);
+                const int ho = ho0 + rr, wo = wo0 + cc;
+                if (a.out_f32 && ho < g.Ho && wo < g.Wo) a.out_f32[((n * g.Ho + ho) * g.Wo + wo) * CO + co] = y;
+            }
+        }
+    }
+    __syncthreads();
+    const int ld2 = a.ld_out2 ? a.ld_out2 : CO;
+    for (int i = tid; i < kTileH * kTileW * CO8; i += 256) {
+        const int c8 = i % CO8, pix = i / CO8;
+        const int rr = pix / kTileW, cc = pix - rr * kTileW;
+        const int ho = ho0 + rr, wo = wo0 + cc;
+        if (ho >= g.Ho || wo >= g.Wo) continue;
+        const int64_t op = (n * g.Ho + ho) * g.Wo + wo;
+        const u32x4 v = *reinterpret_cast<const u32x4*>(&sO[pix * CO + c8 * 8]);
+        if (a.out_bf16) *reinterpret_cast<u32x4*>(a.out_bf16 + op * CO + c8 * 8) = v;
+        if (a.skip && a.out2_bf16) {
+            const u32x4 k = *reinterpret_cast<const u32x4*>(a.skip + op * CO + c8 * 8);
+            u32x4 o;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint16_t lo = f2bf(bf2f((uint16_t)(v[j] & 0xFFFFu)) + bf2f((uint16_t)(k[j] & 0xFFFFu)));
+                const uint16_t hi = f2bf(bf2f((uint16_t)(v[j] >> 16)) + bf2f((uint16_t)(k[j] >> 16)));
+                o[j] = (uint32_t)lo | ((uint32_t)hi << 16);
+            }
+            *reinterpret_cast<u32x4*>(a.out2_bf16 + op * ld2 + c8 * 8) = o;
+        }
+    }
+    if (a.extra && a.out2_bf16) {
+        const int E8 = a.extra_c / 8;
+        for (int i = tid; i < kTileH * kTileW * E8; i += 256) {
+            const int e8 = i % E8, pix = i / E8;
+            const int rr = pix / kTileW, cc = pix - rr * kTileW;
+            const int ho = ho0 + rr, wo = wo0 + cc;
+            if (ho >= g.Ho || wo >= g.Wo) continue;
+            const int64_t op = (n * g.Ho + ho) * g.Wo + wo;
+            *reinterpret_cast<u32x4*>(a.out2_bf16 + op * ld2 + CO + e8 * 8) =
+                *reinterpret_cast<const u32x4*>(a.extra + op * a.extra_c + e8 * 8);
+        }
+    }
+    if (a.head_out && tid < kTileH * kTileW) {
+        const int rr = tid / kTileW, cc = tid - rr * kTileW;
+        const int ho = ho0 + rr, wo = wo0 + cc;
+        if (ho < g.Ho && wo < g.Wo) {
+            float sum = 0.f;
+#pragma unroll
+            for (int co = 0; co < CO; ++co) sum += bf2f(a.head_w[co]) * bf2f(sO[tid * CO + co]);
+            a.head_out[(n * g.Ho + ho) * g.Wo + wo] = sum + a.head_b[0];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // element-wise / reduction kernels
 
 // dPre = bf16(g * [y > 0]) (ReLU) or bf16(g) (no activation)
@@ -339,183 +497,301 @@ __global__ __launch_bounds__(256) void k_mask_colsum(const float* g, int ldg, co
                                                      uint16_t* out, int64_t rows, int C, int64_t rows_per_block,
                                                      float* part)
 {
-    __shared__ float red[256];
-    const int lanes = 256 / C;
-    const int c = threadIdx.x % C;
-    const int r_off = threadIdx.x / C;
+    // a thread owns one 8-channel chunk of rows r_off, r_off + RP, ... (C multiple of 8, <= 256)
+    __shared__ float red[256 * 8];
+    const int C8 = C / 8;
+    const int RP = 256 / C8;
+    const int c8 = threadIdx.x % C8;
+    const int r_off = threadIdx.x / C8;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r1 = min(rows, r0 + rows_per_block);
-    float s = 0.f;
-    if (r_off < lanes) {
-        for (int64_t r = r0 + r_off; r < r1; r += lanes) {
-            const int64_t i = r * C + c;
-            uint16_t b;
+    float sum[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sum[j] = 0.f;
+    if (r_off < RP) {
+        for (int64_t r = r0 + r_off; r < r1; r += RP) {
+            const int64_t i = r * C + c8 * 8;
+            u32x4 b;
             if (gb) {
-                b = gb[i];
+                b = *reinterpret_cast<const u32x4*>(gb + i);
             } else {
-                b = f2bf((y == nullptr || bf2f(y[i]) > 0.f) ? g[r * ldg + c] : 0.f);
-                if (out) out[i] = b;
+                const float4 g0 = *reinterpret_cast<const float4*>(g + r * ldg + c8 * 8);
+                const float4 g1 = *reinterpret_cast<const float4*>(g + r * ldg + c8 * 8 + 4);
+                const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+                u32x4 yv = {0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u};   // no mask: bf16 1.0
+                if (y) yv = *reinterpret_cast<const u32x4*>(y + i);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint16_t lo = f2bf(__uint_as_float(yv[j] << 16) > 0.f ? gv[2 * j] : 0.f);
+                    const uint16_t hi = f2bf(__uint_as_float(yv[j] & 0xFFFF0000u) > 0.f ? gv[2 * j + 1] : 0.f);
+                    b[j] = (uint32_t)lo | ((uint32_t)hi << 16);
+                }
+                if (out) *reinterpret_cast<u32x4*>(out + i) = b;
             }
-            s += bf2f(b);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                sum[2 * j] += __uint_as_float(b[j] << 16);
+                sum[2 * j + 1] += __uint_as_float(b[j] & 0xFFFF0000u);
+            }
         }
     }
-    red[threadIdx.x] = s;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) red[threadIdx.x * 8 + j] = sum[j];
     __syncthreads();
-    if (r_off == 0) {
+    if ((int)threadIdx.x < C) {
+        const int k8 = threadIdx.x / 8, j = threadIdx.x % 8;
         float t = 0.f;
-        for (int j = 0; j < lanes; ++j) t += red[j * C + c];
-        part[(int64_t)blockIdx.x * C + c] = t;
+        for (int q = 0; q < RP; ++q) t += red[(q * C8 + k8) * 8 + j];
+        part[(int64_t)blockIdx.x * C + threadIdx.x] = t;
     }
 }
 
 // out[i] = sum_s part[s][i] in fixed order
-// Depth integral along the beam.  One wave per (frame, column), grid-stride
-// over columns; lanes run along depth in chunks of 64 rows.  Each chunk is a
-// Hillis-Steele scan over the wave (lane shuffles) plus the running total of
-// the chunks already done.  Eight channels per pixel (kScanC).
+// Depth integral along the beam.  A block owns 32 neighbouring columns (in
+// frame-major order) and splits their rows into 8 segments, one thread per
+// (segment, column): each thread first sums its segment, the segment totals
+// meet in LDS, and a second pass over the segment writes the running sums
+// from the totals of the segments above (below, for the backward).  A wave
+// covers 32 columns of two segments, so each row access is contiguous.
+// Eight channels per pixel (kScanC).
 constexpr int kScanC = 8;
+constexpr int kScanCols = 32, kScanSeg = 8;
+constexpr int kScanRows = 4;   // rows whose loads are issued together
 
-__device__ __forceinline__ float lane_get(float v, int src) { return __shfl(v, src, 64); }
-
-// out[n][y][x][c_off + k] = bf16(scale * sum_{v < y} p[n][v][x][k])
-__global__ __launch_bounds__(256) void k_depth_scan_fwd(const float* __restrict__ p, uint16_t* __restrict__ out,
-                                                        int N, int H, int W, float scale, int ld, int c_off)
+// the 1x1 map p = b + w e of one pixel (e: 16 bf16 channels as two 16-byte chunks); w, b in LDS
+__device__ __forceinline__ void depth_map(const u32x4& a0, const u32x4& a1, const float* wf, const float* bf,
+                                          float* p)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t n_cols = (int64_t)N * W;
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t col = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); col < n_cols; col += waves) {
-        const int64_t n = col / W;
-        const int x = (int)(col - n * W);
-        float carry[kScanC];
+    asm volatile("" ::: "memory");   // weights stay in LDS (broadcast reads), not in registers
+    float xc[16];
 #pragma unroll
-        for (int k = 0; k < kScanC; ++k) carry[k] = 0.f;
-        for (int y0 = 0; y0 < H; y0 += 64) {
-            const int y = y0 + lane;
-            const int64_t px = (n * H + y) * W + x;
-            float v[kScanC];
-            if (y < H) {
-                const float4 a = *reinterpret_cast<const float4*>(p + px * kScanC);
-                const float4 b = *reinterpret_cast<const float4*>(p + px * kScanC + 4);
-                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-                v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-            } else {
+    for (int j = 0; j < 4; ++j) {
+        xc[2 * j] = __uint_as_float(a0[j] << 16);
+        xc[2 * j + 1] = __uint_as_float(a0[j] & 0xFFFF0000u);
+        xc[8 + 2 * j] = __uint_as_float(a1[j] << 16);
+        xc[8 + 2 * j + 1] = __uint_as_float(a1[j] & 0xFFFF0000u);
+    }
 #pragma unroll
-                for (int k = 0; k < kScanC; ++k) v[k] = 0.f;
-            }
-            // exclusive: shift down by one lane, then an inclusive scan
+    for (int k = 0; k < kScanC; ++k) {
+        float acc = bf[k];
 #pragma unroll
-            for (int k = 0; k < kScanC; ++k) {
-                float e = lane_get(v[k], lane - 1);
-                e = lane > 0 ? e : 0.f;
+        for (int c = 0; c < 16; ++c) acc = fmaf(wf[k * 16 + c], xc[c], acc);
+        p[k] = acc;
+    }
+}
+
+// out[n][y][x][c_off + k] = bf16(scale * sum_{v < y} p_k(n, v, x)) with the
+// 1x1 map p_k = b[k] + sum_c w[k][c] e[n][v][x][c] of the bf16 tensor e
+// [N][H][W][16] (w bf16 [8][16], b FP32), evaluated in FP32 per pixel.
+__global__ __launch_bounds__(256) void k_depth_map_scan_fwd(const uint16_t* __restrict__ e,
+                                                            const uint16_t* __restrict__ w,
+                                                            const float* __restrict__ b, uint16_t* __restrict__ out,
+                                                            int N, int H, int W, float scale, int ld, int c_off)
+{
+    __shared__ float sw[kScanC * 16];
+    __shared__ float sb[kScanC];
+    __shared__ float tot[kScanSeg][kScanC][kScanCols + 1];
+    if (threadIdx.x < kScanC * 16) sw[threadIdx.x] = bf2f(w[threadIdx.x]);
+    if (threadIdx.x < kScanC) sb[threadIdx.x] = b[threadIdx.x];
+    __syncthreads();
+    const int c = threadIdx.x % kScanCols, sg = threadIdx.x / kScanCols;
+    const int64_t col = (int64_t)blockIdx.x * kScanCols + c;
+    const bool live = col < (int64_t)N * W;
+    const int64_t n = live ? col / W : 0;
+    const int x = live ? (int)(col - n * W) : 0;
+    const int seg = (H + kScanSeg - 1) / kScanSeg;
+    const int ya = live ? min(sg * seg, H) : 0, yb = live ? min(ya + seg, H) : 0;
+    const float* wf = sw;
+    const float* bf = sb;
+    float sum[kScanC], p[kScanC];
 #pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const float t = lane_get(e, lane - d);
-                    if (lane >= d) e += t;
-                }
-                const float tot = lane_get(e + v[k], 63);
-                v[k] = carry[k] + e;
-                carry[k] += tot;
-            }
-            if (y < H) {
-                u32x4 o;
+    for (int k = 0; k < kScanC; ++k) sum[k] = 0.f;
+    const uint16_t* ec = e + (n * H * W + x) * 16;   // column base; row stride W * 16
+    for (int y0 = ya; y0 < yb; y0 += kScanRows) {
+        u32x4 a0[kScanRows], a1[kScanRows];
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    o[j] = (uint32_t)f2bf(scale * v[2 * j]) | ((uint32_t)f2bf(scale * v[2 * j + 1]) << 16);
-                *reinterpret_cast<u32x4*>(out + px * ld + c_off) = o;
-            }
+        for (int q = 0; q < kScanRows; ++q) {
+            const int64_t o = (int64_t)min(y0 + q, yb - 1) * W * 16;
+            a0[q] = *reinterpret_cast<const u32x4*>(ec + o);
+            a1[q] = *reinterpret_cast<const u32x4*>(ec + o + 8);
+        }
+#pragma unroll
+        for (int q = 0; q < kScanRows; ++q) {
+            if (y0 + q >= yb) break;
+            depth_map(a0[q], a1[q], wf, bf, p);
+#pragma unroll
+            for (int k = 0; k < kScanC; ++k) sum[k] += p[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) tot[sg][k][c] = sum[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) {
+        float o = 0.f;
+        for (int q = 0; q < sg; ++q) o += tot[q][k][c];
+        sum[k] = o;   // running sum over the rows above this segment
+    }
+    uint16_t* oc = out + (n * H * W + x) * ld + c_off;
+    for (int y0 = ya; y0 < yb; y0 += kScanRows) {
+        u32x4 a0[kScanRows], a1[kScanRows];
+#pragma unroll
+        for (int q = 0; q < kScanRows; ++q) {
+            const int64_t o = (int64_t)min(y0 + q, yb - 1) * W * 16;
+            a0[q] = *reinterpret_cast<const u32x4*>(ec + o);
+            a1[q] = *reinterpret_cast<const u32x4*>(ec + o + 8);
+        }
+#pragma unroll
+        for (int q = 0; q < kScanRows; ++q) {
+            const int y = y0 + q;
+            if (y >= yb) break;
+            u32x4 ov;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                ov[j] = (uint32_t)f2bf(scale * sum[2 * j]) | ((uint32_t)f2bf(scale * sum[2 * j + 1]) << 16);
+            *reinterpret_cast<u32x4*>(oc + (int64_t)y * W * ld) = ov;
+            depth_map(a0[q], a1[q], wf, bf, p);
+#pragma unroll
+            for (int k = 0; k < kScanC; ++k) sum[k] += p[k];
         }
     }
 }
 
-// Backward of k_depth_scan_fwd through a tensor g [pixel][ld] (FP32) whose
-// channels [c_off, c_off + 8) are the integral's gradient:
-//   dp[n][v][x][k] = bf16(scale * sum_{y > v} g[n][y][x][c_off + k]),
-// channels [0, c_off) copied to g_skip [pixel][c_off], and per-block column
-// sums of the bf16 dp (bias gradient partials) in part[block][8].
+// Backward of k_depth_map_scan_fwd after the 1x1 map, through a tensor g
+// [pixel][ld] (FP32) whose channels [c_off, c_off + 8) are the integral's
+// gradient:  dp[n][v][x][k] = bf16(scale * sum_{y > v} g[n][y][x][c_off + k]),
+// channels [0, c_off) copied to g_skip [pixel][c_off] (c_off multiple of 4),
+// and per-block column sums of the bf16 dp (bias gradient partials) in
+// part[block][8].
 __global__ __launch_bounds__(256) void k_depth_scan_bwd(const float* __restrict__ g, int ld, int c_off,
                                                         float* __restrict__ g_skip, uint16_t* __restrict__ dp,
                                                         float* __restrict__ part, int N, int H, int W, float scale)
 {
-    __shared__ float red[4][kScanC];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t n_cols = (int64_t)N * W;
-    const int64_t waves = (int64_t)gridDim.x * 4;
-    float bsum[kScanC];
-#pragma unroll
-    for (int k = 0; k < kScanC; ++k) bsum[k] = 0.f;
-    for (int64_t col = (int64_t)blockIdx.x * 4 + wave; col < n_cols; col += waves) {
-        const int64_t n = col / W;
-        const int x = (int)(col - n * W);
-        float carry[kScanC];
-#pragma unroll
-        for (int k = 0; k < kScanC; ++k) carry[k] = 0.f;
-        const int n_chunks = (H + 63) / 64;
-        for (int ch = n_chunks - 1; ch >= 0; --ch) {
-            const int y = ch * 64 + lane;
-            const int64_t px = (n * H + y) * W + x;
-            float v[kScanC];
-            if (y < H) {
-                const float* src = g + px * ld;
-                for (int c = 0; c < c_off; c += 4)
-                    *reinterpret_cast<float4*>(g_skip + px * c_off + c) = *reinterpret_cast<const float4*>(src + c);
-                const float4 a = *reinterpret_cast<const float4*>(src + c_off);
-                const float4 b = *reinterpret_cast<const float4*>(src + c_off + 4);
-                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-                v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-            } else {
-#pragma unroll
-                for (int k = 0; k < kScanC; ++k) v[k] = 0.f;
-            }
-            // exclusive suffix: shift up by one lane, then an inclusive suffix scan
-#pragma unroll
-            for (int k = 0; k < kScanC; ++k) {
-                float e = lane_get(v[k], lane + 1);
-                e = lane < 63 ? e : 0.f;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const float t = lane_get(e, lane + d);
-                    if (lane + d < 64) e += t;
-                }
-                const float tot = lane_get(e + v[k], 0);
-                v[k] = carry[k] + e;
-                carry[k] += tot;
-            }
-            if (y < H) {
-                u32x4 o;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint16_t lo = f2bf(scale * v[2 * j]), hi = f2bf(scale * v[2 * j + 1]);
-                    bsum[2 * j] += bf2f(lo);
-                    bsum[2 * j + 1] += bf2f(hi);
-                    o[j] = (uint32_t)lo | ((uint32_t)hi << 16);
-                }
-                *reinterpret_cast<u32x4*>(dp + px * kScanC) = o;
-            }
-        }
-    }
-    // fixed-order reduction: wave butterfly, then the block's four waves
+    __shared__ float tot[kScanSeg][kScanC][kScanCols + 1];
+    __shared__ float red[kScanC][256];
+    const int c = threadIdx.x % kScanCols, sg = threadIdx.x / kScanCols;
+    const int64_t col = (int64_t)blockIdx.x * kScanCols + c;
+    const bool live = col < (int64_t)N * W;
+    const int64_t n = live ? col / W : 0;
+    const int x = live ? (int)(col - n * W) : 0;
+    const int seg = (H + kScanSeg - 1) / kScanSeg;
+    const int ya = live ? min(sg * seg, H) : 0, yb = live ? min(ya + seg, H) : 0;
+    const int64_t pc = n * H * W + x;   // column's pixel index at row 0; row stride W
+    float sum[kScanC], bsum[kScanC];
 #pragma unroll
     for (int k = 0; k < kScanC; ++k) {
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) bsum[k] += lane_get(bsum[k], lane ^ d);
+        sum[k] = 0.f;
+        bsum[k] = 0.f;
     }
-    if (lane == 0)
+    for (int y0 = ya; y0 < yb; y0 += kScanRows) {
+        float4 ga[kScanRows][2];
 #pragma unroll
-        for (int k = 0; k < kScanC; ++k) red[wave][k] = bsum[k];
+        for (int q = 0; q < kScanRows; ++q) {
+            const int64_t px = pc + (int64_t)min(y0 + q, yb - 1) * W;
+            ga[q][0] = *reinterpret_cast<const float4*>(g + px * ld + c_off);
+            ga[q][1] = *reinterpret_cast<const float4*>(g + px * ld + c_off + 4);
+        }
+#pragma unroll
+        for (int q = 0; q < kScanRows; ++q) {
+            if (y0 + q >= yb) break;
+            sum[0] += ga[q][0].x; sum[1] += ga[q][0].y; sum[2] += ga[q][0].z; sum[3] += ga[q][0].w;
+            sum[4] += ga[q][1].x; sum[5] += ga[q][1].y; sum[6] += ga[q][1].z; sum[7] += ga[q][1].w;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) tot[sg][k][c] = sum[k];
     __syncthreads();
-    if (threadIdx.x < kScanC)
-        part[(int64_t)blockIdx.x * kScanC + threadIdx.x] =
-            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) {
+        float o = 0.f;
+        for (int q = kScanSeg - 1; q > sg; --q) o += tot[q][k][c];
+        sum[k] = o;   // running sum over the rows below this segment
+    }
+    for (int y0 = yb - 1; y0 >= ya; y0 -= kScanRows) {
+        float4 ga[kScanRows][2];
+#pragma unroll
+        for (int q = 0; q < kScanRows; ++q) {
+            const int64_t px = pc + (int64_t)max(y0 - q, ya) * W;
+            ga[q][0] = *reinterpret_cast<const float4*>(g + px * ld + c_off);
+            ga[q][1] = *reinterpret_cast<const float4*>(g + px * ld + c_off + 4);
+        }
+#pragma unroll
+        for (int q = 0; q < kScanRows; ++q) {
+            const int y = y0 - q;
+            if (y < ya) break;
+            const int64_t px = pc + (int64_t)y * W;
+            for (int cc = 0; cc < c_off; cc += 4)
+                *reinterpret_cast<float4*>(g_skip + px * c_off + cc) = *reinterpret_cast<const float4*>(g + px * ld + cc);
+            u32x4 o;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint16_t lo = f2bf(scale * sum[2 * j]), hi = f2bf(scale * sum[2 * j + 1]);
+                bsum[2 * j] += bf2f(lo);
+                bsum[2 * j + 1] += bf2f(hi);
+                o[j] = (uint32_t)lo | ((uint32_t)hi << 16);
+            }
+            *reinterpret_cast<u32x4*>(dp + px * kScanC) = o;
+            sum[0] += ga[q][0].x; sum[1] += ga[q][0].y; sum[2] += ga[q][0].z; sum[3] += ga[q][0].w;
+            sum[4] += ga[q][1].x; sum[5] += ga[q][1].y; sum[6] += ga[q][1].z; sum[7] += ga[q][1].w;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) red[k][threadIdx.x] = bsum[k];
+    __syncthreads();
+    if (threadIdx.x < kScanC) {   // fixed order over the block's threads
+        float t = 0.f;
+        for (int i = 0; i < 256; ++i) t += red[threadIdx.x][i];
+        part[(int64_t)blockIdx.x * kScanC + threadIdx.x] = t;
+    }
 }
 
+// out[i] = sum over z of part[z][i]; one thread per output, rows in order
+// (for many outputs and few rows)
 __global__ void k_sum_parts(const float* part, int64_t n, int splits, float* out)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         float s = 0.f;
-        for (int z = 0; z < splits; ++z) s += part[(int64_t)z * n + i];
+        int z = 0;
+        for (; z + 8 <= splits; z += 8) {   // eight loads in flight, added in order
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(z + j) * n + i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += v[j];
+        }
+        for (; z < splits; ++z) s += part[(int64_t)z * n + i];
         out[i] = s;
+    }
+}
+
+// the same sum for few outputs and many rows: thread (ty, tx) of a block sums
+// rows ty, ty + G, ... of output blockIdx.x * ob + tx (G = 256 / ob), then
+// the G partial sums are added in order (fixed order, deterministic)
+__global__ __launch_bounds__(256) void k_sum_parts_grouped(const float* part, int64_t n, int splits, float* out,
+                                                           int ob)
+{
+    __shared__ float red[256];
+    const int tx = threadIdx.x % ob, ty = threadIdx.x / ob;
+    const int G = 256 / ob;
+    const int64_t i = (int64_t)blockIdx.x * ob + tx;
+    float s = 0.f;
+    if (i < n) {
+        int z = ty;
+        for (; z + 7 * G < splits; z += 8 * G) {   // eight loads in flight, added in order
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(z + j * G) * n + i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += v[j];
+        }
+        for (; z < splits; z += G) s += part[(int64_t)z * n + i];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (ty == 0 && i < n) {
+        float t = 0.f;
+        for (int j = 0; j < G; ++j) t += red[j * ob + tx];
+        out[i] = t;
     }
 }
 
@@ -720,6 +996,20 @@ int64_t grid_for(int64_t n, int64_t per = 256)
     return b < 1 ? 1 : b;
 }
 
+// sum of `splits` rows of n partial results into out, in a fixed order
+hipError_t reduce_parts(const float* part, int64_t n, int splits, float* out, hipStream_t s)
+{
+    if (splits <= 16 || n >= 65536) {
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(n)), dim3(256), 0, s, part, n, splits, out);
+        return hipGetLastError();
+    }
+    int ob = 64;   // outputs per block; fewer when that leaves under 256 blocks
+    while (ob > 1 && (n + ob - 1) / ob < 256) ob >>= 1;
+    hipLaunchKernelGGL(k_sum_parts_grouped, dim3((unsigned)((n + ob - 1) / ob)), dim3(256), 0, s, part, n, splits,
+                       out, ob);
+    return hipGetLastError();
+}
+
 template <int MODE, int BM, int BN, int WM, int WN>
 hipError_t launch_gemm(const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s)
 {
@@ -734,8 +1024,42 @@ hipError_t launch_gemm(const ConvGeom& g, const ConvArgs& a, int splits, hipStre
 
 // ---------------------------------------------------------------------------
 
+bool conv_tile_supported(const ConvGeom& g)
+{
+    return g.kh == 3 && g.kw == 3 && g.stride == 1 && g.pad == 1 && (g.C == 8 || g.C == 16 || g.C == 24 || g.C == 32) &&
+           (g.Co == 16 || g.Co == 32) && g.Ho == (g.up ? 2 * g.H : g.H) && g.Wo == (g.up ? 2 * g.W : g.W);
+}
+
+template <int C, int CO>
+hipError_t launch_tile(const ConvGeom& g, const ConvArgs& a, hipStream_t s)
+{
+    const int64_t tiles = (int64_t)((g.Ho + kTileH - 1) / kTileH) * ((g.Wo + kTileW - 1) / kTileW);
+    const int64_t blocks = tiles * (g.Kw / ((int64_t)g.Ho * g.Wo));   // Kw = N * Ho * Wo
+    if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_conv3x3_tile<C, CO>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
+    return hipGetLastError();
+}
+
+template <int CO>
+hipError_t launch_tile_co(const ConvGeom& g, const ConvArgs& a, hipStream_t s)
+{
+    switch (g.C) {
+    case 8: return launch_tile<8, CO>(g, a, s);
+    case 16: return launch_tile<16, CO>(g, a, s);
+    case 24: return launch_tile<24, CO>(g, a, s);
+    default: return launch_tile<32, CO>(g, a, s);
+    }
+}
+
 hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s)
 {
+    if (a.head_out && (mode != kFwd || !conv_tile_supported(g) || g.Co != 16 || !a.head_w || !a.head_b))
+        return hipErrorInvalidValue;
+    if (a.extra && (mode != kFwd || !conv_tile_supported(g) || !a.out2_bf16 || a.extra_c < 8 || a.extra_c % 8 ||
+                    g.Co + a.extra_c > a.ld_out2))
+        return hipErrorInvalidValue;
+    if (mode == kFwd && conv_tile_supported(g))
+        return g.Co == 16 ? launch_tile_co<16>(g, a, s) : launch_tile_co<32>(g, a, s);
     if (mode == kWgrad) {
         if (g.M <= 16) return launch_gemm<kWgrad, 16, 128, 1, 4>(g, a, splits, s);
         if (g.M <= 32) return launch_gemm<kWgrad, 32, 128, 1, 4>(g, a, splits, s);
@@ -758,28 +1082,26 @@ int wgrad_tile_m(int M) { return M <= 16 ? 16 : (M <= 32 ? 32 : 64); }
 hipError_t mask_colsum(const float* g, int ldg, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
                        int blocks, float* bias_grad, hipStream_t s)
 {
-    if (C > 256 || (ldg != 0 && ldg < C)) return hipErrorInvalidValue;
+    if (C > 256 || C % 8 || (ldg != 0 && (ldg < C || ldg % 4))) return hipErrorInvalidValue;
     const int64_t per = (rows + blocks - 1) / blocks;
     hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, g, ldg ? ldg : C, nullptr, y, out, rows, C, per,
                        part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(C)), dim3(256), 0, s, part, (int64_t)C, blocks, bias_grad);
-    return hipGetLastError();
+    return reduce_parts(part, C, blocks, bias_grad, s);
 }
 
 int depth_scan_blocks(int N, int W)
 {
-    const int64_t b = ((int64_t)N * W + 3) / 4;
-    return (int)(b > 1024 ? 1024 : (b < 1 ? 1 : b));
+    return (int)(((int64_t)N * W + kScanCols - 1) / kScanCols);
 }
 
-hipError_t depth_scan_fwd(const float* p, uint16_t* out, int N, int H, int W, float scale, int ld, int c_off,
-                          hipStream_t s)
+hipError_t depth_map_scan_fwd(const uint16_t* e, const uint16_t* w, const float* b, uint16_t* out, int N, int H,
+                              int W, float scale, int ld, int c_off, hipStream_t s)
 {
     if (ld % 8 || c_off % 8 || c_off + kScanC > ld) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_depth_scan_fwd, dim3((unsigned)depth_scan_blocks(N, W)), dim3(256), 0, s, p, out, N, H, W,
-                       scale, ld, c_off);
+    hipLaunchKernelGGL(k_depth_map_scan_fwd, dim3((unsigned)depth_scan_blocks(N, W)), dim3(256), 0, s, e, w, b, out, N,
+                       H, W, scale, ld, c_off);
     return hipGetLastError();
 }
 
@@ -792,8 +1114,7 @@ hipError_t depth_scan_bwd(const float* g, int ld, int c_off, float* g_skip, uint
                        H, W, scale);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int64_t)kScanC, blocks, bias_grad);
-    return hipGetLastError();
+    return reduce_parts(part, kScanC, blocks, bias_grad, s);
 }
 
 hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s)
@@ -813,20 +1134,18 @@ hipError_t pool2x2_sum(const float* fine, float* coarse, int N, int H, int W, in
 hipError_t colsum_bf16(const uint16_t* x, int64_t rows, int cols, float* part, int blocks, float* out,
                        hipStream_t s)
 {
-    if (cols > 256) return hipErrorInvalidValue;
+    if (cols > 256 || cols % 8) return hipErrorInvalidValue;
     const int64_t per = (rows + blocks - 1) / blocks;
     hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, nullptr, cols, x, nullptr, nullptr, rows, cols,
                        per, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(cols)), dim3(256), 0, s, part, (int64_t)cols, blocks, out);
-    return hipGetLastError();
+    return reduce_parts(part, cols, blocks, out, s);
 }
 
 hipError_t sum_parts(const float* part, int64_t n, int splits, float* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)grid_for(n)), dim3(256), 0, s, part, n, splits, out);
-    return hipGetLastError();
+    return reduce_parts(part, n, splits, out, s);
 }
 
 hipError_t head_fwd(const uint16_t* x, const uint16_t* w, const float* b, float* y, int64_t P, int C, hipStream_t s)
@@ -842,8 +1161,7 @@ hipError_t head_bwd(const uint16_t* x, const uint16_t* w, const float* g, float*
     hipLaunchKernelGGL(k_head_bwd, dim3(blocks), dim3(256), 0, s, x, w, g, dx, P, C, per, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int64_t)17, blocks, dwb);
-    return hipGetLastError();
+    return reduce_parts(part, 17, blocks, dwb, s);
 }
 
 hipError_t l1_loss(const float* yhat, const float* y, int64_t n, float* grad, float* part, int blocks, float* loss,
@@ -853,8 +1171,7 @@ hipError_t l1_loss(const float* yhat, const float* y, int64_t n, float* grad, fl
     hipLaunchKernelGGL(k_l1, dim3(blocks), dim3(256), 0, s, yhat, y, n, 1.f / (float)n, grad, per, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, (int64_t)1, blocks, loss);
-    return hipGetLastError();
+    return reduce_parts(part, 1, blocks, loss, s);
 }
 
 hipError_t adam_step(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,

@@ -18,9 +18,10 @@ namespace sg {
 namespace {
 
 // tensors of the network (per frame: channels and pyramid level)
-enum { X = 0, T1, E0, T2, E1, T3, E2, T4, E3, T5, B4, U3, S3, D3, U2, S2, D2, U1, S1, D1, U0, S0, D0, kNumT };
-const int kTC[kNumT] = {8, 16, 16, 32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 128, 64, 64, 64, 32, 32, 32, 16, 24, 16};
-const int kTL[kNumT] = {0, 0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 3, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0};
+// (A0: the depth integral, stored densely before it is copied into S0's last channels)
+enum { X = 0, T1, E0, T2, E1, T3, E2, T4, E3, T5, B4, U3, S3, D3, U2, S2, D2, U1, S1, D1, U0, S0, D0, A0, kNumT };
+const int kTC[kNumT] = {8, 16, 16, 32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 128, 64, 64, 64, 32, 32, 32, 16, 24, 16, 8};
+const int kTL[kNumT] = {0, 0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 3, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0, 0};
 
 struct LayerDef {
     int in, out, skip, out2, Ci, Co, stride, up;
@@ -44,7 +45,7 @@ constexpr int kHeadC = 16;
 // depth integral along the beam (the exclusive sum over rows above a pixel,
 // as in the energy equation of App. B.2): p = W_p E0 + b_p (1x1, 16 -> 8),
 // S0[..., 16 + k] = bf16(kScanScale * sum_{v < y} p_k(v))
-constexpr int kScanSrc = E0, kScanDst = S0, kScanC = 8, kScanOff = 16;
+constexpr int kScanSrc = E0, kScanDst = S0, kScanTmp = A0, kScanC = 8, kScanOff = 16;
 constexpr float kScanScale = 1.f / 16.f;
 constexpr float kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
 
@@ -60,7 +61,7 @@ struct Surrogate {
     int64_t step = 0;
     int cap = 0, cap_grad = 0, last_n = 0;
     DevBuf act[kNumT], gact[kNumT];
-    DevBuf dpre, fine, parts, proj, yhat, target, gy, loss, psnr, idx;
+    DevBuf dpre, fine, parts, yhat, target, gy, loss, psnr, idx;
 };
 
 void SurrogateDeleter::operator()(Surrogate* p) const { delete p; }
@@ -192,7 +193,6 @@ sg_status ensure_capacity(Surrogate& s, int n, bool grads)
         for (int t = 0; t < kNumT; ++t)
             SG_TRY(check(s.act[t].ensure(sizeof(uint16_t) * tensor_elems(s, t, n)), "activation buffers"));
         const int64_t P = (int64_t)n * s.H * s.W;
-        SG_TRY(check(s.proj.ensure(sizeof(float) * P * kScanC), "depth integral buffer"));
         SG_TRY(check(s.yhat.ensure(sizeof(float) * P), "output buffer"));
         SG_TRY(check(s.target.ensure(sizeof(float) * P), "target buffer"));
         s.cap = n;
@@ -241,8 +241,10 @@ ConvShape proj_shape(const Surrogate& s, int n)
     return sh;
 }
 
-sg_status forward(sg_ctx* c, Surrogate& s, int n)
+// train: also keep the pre-skip outputs of the decoder layers (ReLU masks of the backward)
+sg_status forward(sg_ctx* c, Surrogate& s, int n, bool train)
 {
+    bool head_fused = false;
     for (int L = 0; L < kNumL; ++L) {
         const LayerDef& d = kLayers[L];
         const ConvShape sh = layer_shape(s, L, n);
@@ -252,27 +254,39 @@ sg_status forward(sg_ctx* c, Surrogate& s, int n)
         a.b = (const uint16_t*)s.wb.p + s.w_off[L];
         a.bias = (const float*)s.master.p + s.b_off[L];
         a.relu = 1;
-        a.out_bf16 = (uint16_t*)s.act[d.out].p;
+        a.out_bf16 = (d.skip >= 0 && !train) ? nullptr : (uint16_t*)s.act[d.out].p;
+        if (L == kNumL - 1 && d.Co == kHeadC && conv_tile_supported(geom_of(sh, 0))) {
+            // the 1x1 head in the last conv's epilogue; its input is kept for the backward only
+            a.head_w = (const uint16_t*)s.wb.p + s.head_w;
+            a.head_b = (const float*)s.master.p + s.head_b;
+            a.head_out = (float*)s.yhat.p;
+            if (!train) a.out_bf16 = nullptr;
+            head_fused = true;
+        }
         if (d.skip >= 0) {
             a.skip = (const uint16_t*)s.act[d.skip].p;
             a.out2_bf16 = (uint16_t*)s.act[d.out2].p;
             a.ld_out2 = kTC[d.out2];
         }
-        SG_TRY(check(conv_gemm(0, geom_of(sh, 0), a, 1, c->stream), "forward conv"));
-        if (d.out2 == kScanDst) {
-            // 1x1 map of E0 to FP32, then its depth integral into S0's last channels
-            ConvArgs p;
-            std::memset(&p, 0, sizeof(p));
-            p.a = (const uint16_t*)s.act[kScanSrc].p;
-            p.b = (const uint16_t*)s.wb.p + s.proj_w;
-            p.bias = (const float*)s.master.p + s.proj_b;
-            p.out_f32 = (float*)s.proj.p;
-            SG_TRY(check(conv_gemm(0, geom_of(proj_shape(s, n), 0), p, 1, c->stream), "depth map"));
-            SG_TRY(check(depth_scan_fwd((const float*)s.proj.p, (uint16_t*)s.act[kScanDst].p, n, s.H, s.W, kScanScale,
-                                        kTC[kScanDst], kScanOff, c->stream),
-                         "depth integral"));
+        const bool scan_here = d.out2 == kScanDst;
+        const bool scan_fused = scan_here && conv_tile_supported(geom_of(sh, 0));
+        if (scan_fused) {   // S0 = [U0 + E0, integral]: the conv writes whole pixels
+            a.extra = (const uint16_t*)s.act[kScanTmp].p;
+            a.extra_c = kScanC;
         }
+        SG_TRY(check(conv_gemm(0, geom_of(sh, 0), a, 1, c->stream), "forward conv"));
+        if (scan_here && !scan_fused)
+            SG_TRY(check(hipMemcpy2DAsync((uint16_t*)s.act[kScanDst].p + kScanOff, sizeof(uint16_t) * kTC[kScanDst],
+                                          s.act[kScanTmp].p, sizeof(uint16_t) * kScanC, sizeof(uint16_t) * kScanC,
+                                          (size_t)n * s.H * s.W, hipMemcpyDeviceToDevice, c->stream),
+                         "depth integral copy"));
+        if (d.out == kScanSrc)   // 1x1 map of E0 and its depth integral (dense, copied into S0 later)
+            SG_TRY(check(depth_map_scan_fwd((const uint16_t*)s.act[kScanSrc].p, (const uint16_t*)s.wb.p + s.proj_w,
+                                            (const float*)s.master.p + s.proj_b, (uint16_t*)s.act[kScanTmp].p, n, s.H,
+                                            s.W, kScanScale, kScanC, 0, c->stream),
+                         "depth integral"));
     }
+    if (head_fused) return SG_OK;
     return check(head_fwd((const uint16_t*)s.act[D0].p, (const uint16_t*)s.wb.p + s.head_w,
                           (const float*)s.master.p + s.head_b, (float*)s.yhat.p, (int64_t)n * s.H * s.W, kHeadC,
                           c->stream),
@@ -537,7 +551,7 @@ extern "C" sg_status sg_surr_train_step(sg_ctx* c, int32_t id, int32_t n, const 
     SG_TRY(check_frames(*s, n, probes));
     SG_TRY(ensure_capacity(*s, n, true));
     SG_TRY(encode_and_render(c, *s, n, vol_ids, probes, poses, (float*)s->target.p));
-    SG_TRY(forward(c, *s, n));
+    SG_TRY(forward(c, *s, n, true));
     const int64_t P = (int64_t)n * s->H * s->W;
     const int lb = blocks_for(P);
     SG_TRY(check(s->parts.ensure(sizeof(float) * (size_t)lb), "loss workspace"));
@@ -587,7 +601,7 @@ extern "C" sg_status sg_surr_infer(sg_ctx* c, int32_t id, int32_t n, const int32
     SG_TRY(ensure_capacity(*s, n, false));
     const int64_t HW = (int64_t)s->H * s->W;
     SG_TRY(encode_and_render(c, *s, n, vol_ids, probes, poses, nullptr));
-    SG_TRY(forward(c, *s, n));
+    SG_TRY(forward(c, *s, n, false));
     SG_TRY(check(clamp01((const float*)s->yhat.p, out, (int64_t)n * HW, c->stream), "clamp"));
     *n_fallback = 0;
     if (n_audit == 0) return check(hipStreamSynchronize(c->stream), "infer");

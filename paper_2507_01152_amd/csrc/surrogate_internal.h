@@ -52,6 +52,15 @@ struct ConvArgs {
     float* out_f32;          // forward (optional), data gradient, weight gradient partials
     int32_t accumulate;      // data gradient: add into out_f32
     int64_t k_chunk;         // weight gradient: pixels per split (multiple of 32)
+    // forward, tiled 3x3 path only (conv_tile_supported): fused 1x1 head with one output,
+    // head_out[pixel] = head_b[0] + sum_co head_w[co] * bf16(out[pixel][co])
+    const uint16_t* head_w;
+    const float* head_b;
+    float* head_out;
+    // forward, tiled 3x3 path only: out2's channels [Co, Co + extra_c) are copied from extra
+    // [pixel][extra_c] (extra_c multiple of 8, Co + extra_c <= ld_out2), so out2 is written whole
+    const uint16_t* extra;
+    int32_t extra_c;
 };
 
 // convolution shape of one layer (per batch)
@@ -102,16 +111,20 @@ inline ConvGeom geom_of(const ConvShape& s, int mode)
 }
 
 hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s);
+// forward shapes served by the LDS-tiled direct 3x3 kernel (stride 1, pad 1, C in {8, 16, 24, 32},
+// Co in {16, 32}); the fused head needs Co = 16
+bool conv_tile_supported(const ConvGeom& g);
 int wgrad_tile_m(int M);
 hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s);
 // out = bf16(g * [y > 0]) over [rows][C] and bias_grad[c] = sum of out's column c (C <= 256);
 // g has ldg floats per row (0: C)
 hipError_t mask_colsum(const float* g, int ldg, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
                        int blocks, float* bias_grad, hipStream_t s);
-// depth integral of 8 FP32 channels p [N][H][W][8] down each column (rows above only), times scale, into
-// channels [c_off, c_off + 8) of the bf16 tensor out [N][H][W][ld]
-hipError_t depth_scan_fwd(const float* p, uint16_t* out, int N, int H, int W, float scale, int ld, int c_off,
-                          hipStream_t s);
+// depth integral down each column (rows above only), times scale, of the 1x1 map p = w e + b of the bf16
+// tensor e [N][H][W][16] (w bf16 [8][16], b FP32 [8]), into channels [c_off, c_off + 8) of the bf16 tensor
+// out [N][H][W][ld]
+hipError_t depth_map_scan_fwd(const uint16_t* e, const uint16_t* w, const float* b, uint16_t* out, int N, int H,
+                              int W, float scale, int ld, int c_off, hipStream_t s);
 // its backward from g [N][H][W][ld] (FP32): dp (bf16, [N][H][W][8]), the channels [0, c_off) copied to
 // g_skip [N][H][W][c_off], bias_grad[8] = column sums of dp; part holds depth_scan_blocks(N, W) * 8 floats
 int depth_scan_blocks(int N, int W);

@@ -41,6 +41,11 @@ CONV_CASES = [
     (3, 11, 5, 24, 40, 1, 1, 0, 0),      # 1x1, channel counts not powers of two
     (2, 9, 70, 16, 8, 1, 1, 0, 0),       # 1x1 to 8 channels (the depth map), K below one MFMA step
     (1, 12, 10, 24, 16, 3, 1, 1, 0),     # 24 input channels (the last decoder conv)
+    # LDS-tiled direct 3x3 path (stride 1, pad 1, C <= 32, Co 16 or 32): 8 x 32 tiles
+    (2, 19, 70, 16, 16, 3, 1, 1, 0),     # ragged tiles in both directions
+    (1, 7, 11, 32, 16, 3, 1, 1, 1),      # upsampled to 14 x 22
+    (2, 10, 33, 16, 32, 3, 1, 1, 0),     # 32 output channels
+    (1, 9, 40, 32, 32, 3, 1, 1, 1),      # upsampled, 32 -> 32
 ]
 
 
