@@ -174,7 +174,7 @@ def main():
                     help="training steps (batch 64; 3125 = 200k pairs) before timing surrogate inference; "
                          "0 skips the surrogate")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="minimum CPU time of the oracle baseline sample (whole steps, at most 20)")
+                    help="minimum CPU time of the oracle baseline sample (whole steps, at most 200)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -275,7 +275,7 @@ def main():
     if not args.no_cpu:
         import oracle
         reps, dt = 0, 0.0
-        while reps < 20 and (reps == 0 or dt < args.cpu_seconds):
+        while reps < 200 and (reps == 0 or dt < args.cpu_seconds):
             t = time.perf_counter()
             _frames, used = oracle.simulate_batch(wl, n_threads=0)
             dt += time.perf_counter() - t
