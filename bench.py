@@ -200,7 +200,7 @@ def main():
     out = torch.empty(total, dtype=torch.float32, device=sess.device)
     if not args.no_tune:
         sg.sg_autotune(sess.ctx, plan, os.environ.get("SG_TUNE_CACHE", "/tmp/sonosim_tune.jsonl"))
-    spw, tx, ty = sg.sg_batch_config(sess.ctx, plan)
+    spw, tx, ty, chunks = sg.sg_batch_config(sess.ctx, plan)
 
     for _ in range(args.warmup):
         sg.sg_batch_step(sess.ctx, plan, out)
@@ -252,7 +252,7 @@ def main():
                         "W 64-256 x H 128-512 at 0.5 mm, one persistent kernel per step in a HIP graph",
             "n_envs": n,
             "pixels_per_step": pixels,
-            "launch_shape": {"scanlines_per_item": spw, "tile_x": tx, "tile_y": ty},
+            "launch_shape": {"scanlines_per_item": spw, "tile_x": tx, "tile_y": ty, "chunks": chunks},
         },
         "roofline": {
             "bound": "alu",

@@ -202,16 +202,29 @@ sg_status sg_batch_status(sg_ctx* ctx, int32_t plan_id, int32_t* n_bad);
  * bit-identical frames. */
 sg_status sg_autotune(sg_ctx* ctx, int32_t plan_id, const char* cache_path);
 
-/* Run one step without the graph, timing its two persistent kernels with
- * HIP events on the context's stream; synchronises.  *ms_ray and *ms_psf
- * (host) receive the durations of the ray kernel and of the PSF kernel.
- * For measurement only; frames are identical to sg_batch_step's. */
+/* Run one step without the graph, timing its persistent kernels with HIP
+ * events on the context's stream; synchronises.  *ms_ray (host) receives the
+ * time from the first ray kernel's start to the last one's end (with one
+ * chunk: the ray kernel's duration); *ms_psf the time after that until the
+ * step ends (with one chunk: the PSF kernel's duration; with more, the PSF
+ * work not overlapped with ray kernels).  For measurement only; frames are
+ * identical to sg_batch_step's. */
 sg_status sg_batch_step_profiled(sg_ctx* ctx, int32_t plan_id, float* out, float* ms_ray, float* ms_psf);
 
 /* Launch shape currently used by a plan (for reports): scanlines per ray
- * work item, and the PSF tile (tile_x scanlines by tile_y = 64 rows). */
+ * work item, the PSF tile (tile_x scanlines by tile_y = 64 rows) and the
+ * number of env chunks (the PSF kernel of chunk k runs beside the ray kernel
+ * of chunk k + 1 on a second stream).  Any pointer may be NULL. */
 sg_status sg_batch_config(sg_ctx* ctx, int32_t plan_id, int32_t* scanlines_per_item,
-                          int32_t* tile_x, int32_t* tile_y);
+                          int32_t* tile_x, int32_t* tile_y, int32_t* chunks);
+
+/* Set a plan's launch shape explicitly (instead of sg_autotune):
+ * scanlines_per_item in {4, 8, 16} (four waves of 1, 2 or 4 scanlines),
+ * tile_x in {16, 32, 64}, chunks in [1, 4] (clamped to the env count).
+ * Every shape gives bit-identical frames.  SG_EINVAL for other values;
+ * synchronises the context's stream. */
+sg_status sg_batch_set_config(sg_ctx* ctx, int32_t plan_id, int32_t scanlines_per_item, int32_t tile_x,
+                              int32_t chunks);
 
 sg_status sg_batch_plan_destroy(sg_ctx* ctx, int32_t plan_id);
 

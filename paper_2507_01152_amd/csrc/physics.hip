@@ -457,9 +457,19 @@ __global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a, QueueDev* q)
 }
 
 // PSF kernel: items (env, tile of TX scanlines x 64 rows).
+// Lateral radii up to kRB take the register-window path: the kernel is
+// zero-padded to 2 kRB + 1 taps and a lane keeps the kSx + 2 kRB values of its
+// row that an 8-column output strip needs, so each LDS value is read once per
+// strip instead of once per tap.  Larger radii use a per-pixel tap loop.
+constexpr int kRB = 8;
+constexpr int kSx = 8;
+
 template <int TX>
-__global__ __launch_bounds__(kThreads) void k_psf(PhysArgs a, QueueDev* q)
+__global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* q)
 {
+    static_assert(TX % kSx == 0, "strips");
+    constexpr int kPW = TX / kSx;        // waves: one 8-column output strip each
+    constexpr int kPT = kPW * kWave;     // threads
     extern __shared__ float lds[];
     __shared__ float s_klat[kTaps];
     __shared__ int s_item;
@@ -472,25 +482,65 @@ __global__ __launch_bounds__(kThreads) void k_psf(PhysArgs a, QueueDev* q)
         const ItemPsf it = a.psf_items[item];
         const EnvDev e = a.envs[it.env];
         const int W = e.W, H = e.H, rl = e.rlat;
+        const int R = rl <= kRB ? kRB : rl;   // halo of the staged tile
         const int x0 = (it.tile & 0xFFFF) * TX;
         const int y0 = (it.tile >> 16) * kTileRows;
-        const int CW = TX + 2 * rl;
+        const int CW = TX + 2 * R;
         float* sR = lds;
         float* sT = sR + CW * kAS;
         float* sE = sT + CW * kAS;
-        for (int i = tid; i <= 2 * rl; i += kThreads) s_klat[i] = a.coefs[e.klat + i];
+        // taps centred in a window of 2 R + 1 (zero outside the env's 2 rl + 1)
+        for (int i = tid; i <= 2 * R; i += kPT) {
+            const int k = i - (R - rl);
+            s_klat[i] = (k >= 0 && k <= 2 * rl) ? a.coefs[e.klat + k] : 0.f;
+        }
         const float* gR = a.fR + e.scr_off;
         const float* gT = a.fT + e.scr_off;
         const float* gE = a.fE + e.scr_off;
         const int gy = y0 + lane;
         const bool yin = gy < H;
+        if (R == kRB) {
+            // every column load of the tile in flight before the LDS stores
+            constexpr int CWF = TX + 2 * kRB;
+            constexpr int NCR = (CWF + kPW - 1) / kPW, NCE = (TX + kPW - 1) / kPW;
+            float vr[NCR], vt[NCR], ve[NCE];
+#pragma unroll
+            for (int u = 0; u < NCR; ++u) {
+                const int c = wave + u * kPW;
+                const int gx = x0 - kRB + c;
+                const bool in = yin && c < CWF && gx >= 0 && gx < W;
+                const int64_t off = in ? (int64_t)gx * H + gy : 0;
+                vr[u] = in ? gR[off] : 0.f;
+                vt[u] = in ? gT[off] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < NCE; ++u) {
+                const int c = wave + u * kPW;
+                const int gx = x0 + c;
+                const bool in = yin && c < TX && gx < W;
+                ve[u] = in ? gE[(int64_t)gx * H + gy] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < NCR; ++u) {
+                const int c = wave + u * kPW;
+                if (c < CWF) {
+                    sR[c * kAS + lane] = vr[u];
+                    sT[c * kAS + lane] = vt[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NCE; ++u) {
+                const int c = wave + u * kPW;
+                if (c < TX) sE[c * kAS + lane] = ve[u];
+            }
+        } else {
         constexpr int kU = 4;   // columns in flight per wave
-        for (int c0 = wave; c0 < CW; c0 += kWaves * kU) {
+        for (int c0 = wave; c0 < CW; c0 += kPW * kU) {
             float vr[kU], vt[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int c = c0 + u * kWaves;
-                const int gx = x0 - rl + c;
+                const int c = c0 + u * kPW;
+                const int gx = x0 - R + c;
                 const bool in = yin && c < CW && gx >= 0 && gx < W;
                 const int64_t off = in ? (int64_t)gx * H + gy : 0;
                 vr[u] = in ? gR[off] : 0.f;
@@ -498,47 +548,99 @@ __global__ __launch_bounds__(kThreads) void k_psf(PhysArgs a, QueueDev* q)
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int c = c0 + u * kWaves;
+                const int c = c0 + u * kPW;
                 if (c < CW) {
                     sR[c * kAS + lane] = vr[u];
                     sT[c * kAS + lane] = vt[u];
                 }
             }
         }
-        for (int c0 = wave; c0 < TX; c0 += kWaves * kU) {
+        for (int c0 = wave; c0 < TX; c0 += kPW * kU) {
             float ve[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int gx = x0 + c0 + u * kWaves;
-                const bool in = yin && c0 + u * kWaves < TX && gx < W;
+                const int gx = x0 + c0 + u * kPW;
+                const bool in = yin && c0 + u * kPW < TX && gx < W;
                 ve[u] = in ? gE[(int64_t)gx * H + gy] : 0.f;
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u)
-                if (c0 + u * kWaves < TX) sE[(c0 + u * kWaves) * kAS + lane] = ve[u];
+                if (c0 + u * kPW < TX) sE[(c0 + u * kPW) * kAS + lane] = ve[u];
+        }
         }
         __syncthreads();
-        for (int idx = tid; idx < TX * kTileRows; idx += kThreads) {
-            const int cx = idx % TX;
-            const int r = idx / TX;
-            const int x = x0 + cx, y = y0 + r;
-            if (x < W && y < H) {
-                float s1 = 0.f, s2 = 0.f;
-                for (int i = 0; i <= 2 * rl; ++i) {
-                    s1 += s_klat[i] * sR[(cx + i) * kAS + r];
-                    s2 += s_klat[i] * sT[(cx + i) * kAS + r];
+        // lane = tile row; Y of each strip goes to registers, then through LDS to row-major stores
+        constexpr int kStrips = TX / kSx;
+        constexpr int kSPW = (kStrips + kPW - 1) / kPW;   // strips per wave
+        float yv[kSPW][kSx];
+        const int r = lane, y = y0 + r;
+        if (R == kRB) {
+            float kp[2 * kRB + 1];
+#pragma unroll
+            for (int i = 0; i <= 2 * kRB; ++i) kp[i] = s_klat[i];
+#pragma unroll
+            for (int q = 0; q < kSPW; ++q) {
+                const int sx = wave + q * kPW;
+                if (sx >= kStrips) break;
+                const int cx0 = sx * kSx;
+                float wr[kSx + 2 * kRB], wt[kSx + 2 * kRB];
+#pragma unroll
+                for (int j = 0; j < kSx + 2 * kRB; ++j) {
+                    wr[j] = sR[(cx0 + j) * kAS + r];
+                    wt[j] = sT[(cx0 + j) * kAS + r];
                 }
-                const float I = s1 + sE[cx * kAS + r] * s2;
+#pragma unroll
+                for (int o = 0; o < kSx; ++o) {
+                    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+                    for (int i = 0; i <= 2 * kRB; ++i) {
+                        s1 = fmaf(kp[i], wr[o + i], s1);
+                        s2 = fmaf(kp[i], wt[o + i], s2);
+                    }
+                    yv[q][o] = s1 + sE[(cx0 + o) * kAS + r] * s2;   // I
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kSPW; ++q) {
+                const int sx = wave + q * kPW;
+                if (sx >= kStrips) break;
+                for (int o = 0; o < kSx; ++o) {
+                    const int cx = sx * kSx + o;
+                    float s1 = 0.f, s2 = 0.f;
+                    for (int i = 0; i <= 2 * R; ++i) {
+                        s1 = fmaf(s_klat[i], sR[(cx + i) * kAS + r], s1);
+                        s2 = fmaf(s_klat[i], sT[(cx + i) * kAS + r], s2);
+                    }
+                    yv[q][o] = s1 + sE[cx * kAS + r] * s2;
+                }
+            }
+        }
+        __syncthreads();   // sR is reused for the output tile
+        float* sY = lds;   // [kTileRows][TX + 1]
+#pragma unroll
+        for (int q = 0; q < kSPW; ++q) {
+            const int sx = wave + q * kPW;
+            if (sx >= kStrips) break;
+#pragma unroll
+            for (int o = 0; o < kSx; ++o) {
+                const int x = x0 + sx * kSx + o;
+                const float I = yv[q][o];
                 float Y = 0.f;
                 if (I > 0.f) {
                     // (20 / DR) log10(I / E0) as disp2 * log2(I * (1 / E0))
                     Y = 1.f + e.disp2 * __builtin_amdgcn_logf(I * e.inv_E0);
                     Y = fminf(fmaxf(Y, 0.f), 1.f);
                 }
-                const int64_t k = e.out_off + (int64_t)y * W + x;
-                a.out[k] = Y;
-                if (a.dbg.intensity) a.dbg.intensity[k] = I;
+                sY[r * (TX + 1) + sx * kSx + o] = Y;
+                if (a.dbg.intensity && y < H && x < W) a.dbg.intensity[e.out_off + (int64_t)y * W + x] = I;
             }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < TX * kTileRows; idx += kPT) {
+            const int cx = idx % TX, rr = idx / TX;
+            const int x = x0 + cx, yy = y0 + rr;
+            if (x < W && yy < H) a.out[e.out_off + (int64_t)yy * W + x] = sY[rr * (TX + 1) + cx];
         }
     }
 }
@@ -605,13 +707,13 @@ __global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses
     if (!ok) atomicAdd(&q->n_bad, 1);
 }
 
-__global__ void k_queue_reset(QueueDev* q)
+__global__ void k_queue_reset(QueueDev* q, int n)
 {
-    if (threadIdx.x == 0) {
-        q->next_ray = 0;
-        q->next_psf = 0;
-        q->n_bad = 0;
-        q->pad = 0;
+    if ((int)threadIdx.x < n) {
+        q[threadIdx.x].next_ray = 0;
+        q[threadIdx.x].next_psf = 0;
+        q[threadIdx.x].n_bad = 0;
+        q[threadIdx.x].pad = 0;
     }
 }
 
@@ -632,30 +734,34 @@ const void* psf_fn(int tx)
     return nullptr;
 }
 
-int blocks_per_cu(const void* fn, size_t lds)
+int blocks_per_cu(const void* fn, int threads, size_t lds)
 {
     int n = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kThreads, lds) != hipSuccess) return 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, lds) != hipSuccess) return 0;
     return n;
 }
+
+// PSF block size: one wave per 8-column strip of the tile
+constexpr int psf_threads(int tx) { return tx / kSx * kWave; }
 
 }  // namespace
 
 size_t psf_lds_bytes(int tx, int max_rlat)
 {
-    return sizeof(float) * (size_t)kAS * (2 * (tx + 2 * max_rlat) + tx);
+    const int R = max_rlat < kRB ? kRB : max_rlat;
+    return sizeof(float) * (size_t)kAS * (2 * (tx + 2 * R) + tx);
 }
 
 bool psf_tile_supported(int tx) { return psf_fn(tx) != nullptr; }
 
 int ray_grid(int n_cu)
 {
-    return blocks_per_cu(reinterpret_cast<const void*>(&k_ray), 0) * n_cu;
+    return blocks_per_cu(reinterpret_cast<const void*>(&k_ray), kThreads, 0) * n_cu;
 }
 
 int psf_grid(int tx, int max_rlat, int n_cu)
 {
-    return blocks_per_cu(psf_fn(tx), psf_lds_bytes(tx, max_rlat)) * n_cu;
+    return blocks_per_cu(psf_fn(tx), psf_threads(tx), psf_lds_bytes(tx, max_rlat)) * n_cu;
 }
 
 hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s)
@@ -674,11 +780,11 @@ hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tx, int grid, hipStrea
     if (grid < 1) return hipErrorInvalidConfiguration;
     const size_t lds = psf_lds_bytes(tx, a.max_rlat);
     if (tx == 16)
-        hipLaunchKernelGGL(k_psf<16>, dim3(grid), dim3(kThreads), lds, s, a, q);
+        hipLaunchKernelGGL(k_psf<16>, dim3(grid), dim3(psf_threads(16)), lds, s, a, q);
     else if (tx == 32)
-        hipLaunchKernelGGL(k_psf<32>, dim3(grid), dim3(kThreads), lds, s, a, q);
+        hipLaunchKernelGGL(k_psf<32>, dim3(grid), dim3(psf_threads(32)), lds, s, a, q);
     else if (tx == 64)
-        hipLaunchKernelGGL(k_psf<64>, dim3(grid), dim3(kThreads), lds, s, a, q);
+        hipLaunchKernelGGL(k_psf<64>, dim3(grid), dim3(psf_threads(64)), lds, s, a, q);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -701,9 +807,10 @@ hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses
     return hipGetLastError();
 }
 
-hipError_t launch_queue_reset(QueueDev* q, hipStream_t s)
+hipError_t launch_queue_reset(QueueDev* q, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q);
+    if (n < 1 || n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q, n);
     return hipGetLastError();
 }
 

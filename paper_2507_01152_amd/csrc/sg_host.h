@@ -43,7 +43,9 @@ struct HostVolume {
 struct LaunchShape {
     int spw = 1;      // scanlines per wave in a ray item
     int tx = 32;      // PSF tile width (scanlines); tiles are 64 rows high
+    int chunks = 1;   // env chunks: the PSF kernel of chunk k runs beside the ray kernel of chunk k + 1
 };
+constexpr int kMaxChunks = 4;
 
 struct Plan {
     int32_t n_envs = 0;
@@ -56,9 +58,13 @@ struct Plan {
     int64_t n_pixels = 0;
     int max_rax = 0, max_rlat = 0;
     LaunchShape shape;
-    int grid_ray = 0, grid_psf = 0;
+    int grid_ray = 0, grid_psf = 0, grid_psf_last = 0;   // (last: the last chunk's PSF kernel runs alone)
     DevBuf d_envs, d_pool, d_rays, d_tiles, d_poses, d_queue, fields;
     int32_t n_rays = 0, n_tiles = 0;
+    // per chunk: ranges of the ray and PSF work lists (one queue each)
+    int32_t ray_off[kMaxChunks] = {}, ray_cnt[kMaxChunks] = {}, tile_off[kMaxChunks] = {}, tile_cnt[kMaxChunks] = {};
+    hipStream_t aux = nullptr;                      // second stream of the chunked pipeline
+    hipEvent_t ev_ray[kMaxChunks] = {}, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float* graph_out = nullptr;        // output pointer the graph was captured with

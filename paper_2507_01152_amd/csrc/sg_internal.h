@@ -138,7 +138,7 @@ __host__ __device__ inline int plane_geometry(const double* pose, double sx, dou
 }
 
 // launchers (physics.hip)
-hipError_t launch_queue_reset(QueueDev* q, hipStream_t s);
+hipError_t launch_queue_reset(QueueDev* q, int n_queues, hipStream_t s);   // resets q[0 .. n_queues)
 hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n_envs,
                            QueueDev* q, hipStream_t s);
 hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s);

@@ -19,14 +19,23 @@ Plan::~Plan()
 {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t& ev : ev_ray)
+        if (ev) (void)hipEventDestroy(ev);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
 }
 
 namespace {
 
 // Candidate launch shapes: every one yields bit-identical frames (the
-// per-pixel arithmetic and summation order do not depend on the tiling).
+// per-pixel arithmetic and summation order do not depend on the tiling or on
+// the chunking).  With chunks > 1 the envs are split into that many groups of
+// about equal pixel count; the PSF kernel of a group runs on a second stream
+// beside the ray kernel of the next group (the ray kernel is bound by the
+// VALU, the PSF kernel by memory), each kernel on part of the GPU.
 const LaunchShape kShapes[] = {
-    {1, 32}, {2, 32}, {1, 64}, {2, 64}, {1, 16}, {4, 32},
+    {1, 32, 1}, {2, 32, 1}, {1, 64, 1}, {2, 64, 1}, {1, 16, 1}, {4, 32, 1},
+    {2, 32, 2}, {2, 64, 2}, {2, 32, 4}, {2, 64, 4},
 };
 
 Plan* find_plan(sg_ctx* c, int32_t id)
@@ -46,12 +55,47 @@ void drop_graph(Plan* p)
 
 sg_status apply_shape(sg_ctx* c, Plan* p, const LaunchShape& s)
 {
+    if (s.chunks < 1 || s.chunks > kMaxChunks) return fail(SG_EINVAL, "launch shape: %d chunks", s.chunks);
+    // contiguous groups of the longest-first order with about equal pixel counts
     std::vector<ItemRay> rays;
     std::vector<ItemPsf> tiles;
-    build_items(p->envs, p->order, s.spw, s.tx, rays, tiles);
-    const int gr = ray_grid(c->n_cu), gp = psf_grid(s.tx, p->max_rlat, c->n_cu);
+    const int K = std::min<int>(s.chunks, p->n_envs);
+    size_t gi = 0;
+    int64_t acc = 0;
+    for (int k = 0; k < kMaxChunks; ++k) p->ray_off[k] = p->ray_cnt[k] = p->tile_off[k] = p->tile_cnt[k] = 0;
+    for (int k = 0; k < K; ++k) {
+        std::vector<int> part;
+        const int64_t goal = p->n_pixels * (k + 1) / K;
+        while (gi < p->order.size() && (k == K - 1 || acc < goal || part.empty()) &&
+               (int)(p->order.size() - gi) > K - 1 - k) {
+            const EnvDev& e = p->envs[p->order[gi]];
+            acc += (int64_t)e.W * e.H;
+            part.push_back(p->order[gi++]);
+            if (k < K - 1 && acc >= goal) break;
+        }
+        std::vector<ItemRay> r;
+        std::vector<ItemPsf> t;
+        build_items(p->envs, part, s.spw, s.tx, r, t);
+        p->ray_off[k] = (int32_t)rays.size();
+        p->ray_cnt[k] = (int32_t)r.size();
+        p->tile_off[k] = (int32_t)tiles.size();
+        p->tile_cnt[k] = (int32_t)t.size();
+        rays.insert(rays.end(), r.begin(), r.end());
+        tiles.insert(tiles.end(), t.begin(), t.end());
+    }
+    int gr = ray_grid(c->n_cu), gp = psf_grid(s.tx, p->max_rlat, c->n_cu);
     if (gr < 1 || gp < 1) return fail(SG_EINVAL, "launch shape (tile %d) does not fit a compute unit", s.tx);
+    p->grid_psf_last = gp;
+    if (K > 1) {   // leave room on every CU for one PSF block beside the ray blocks
+        const int rb = gr / c->n_cu;
+        gr = std::max(1, rb - 1) * c->n_cu;
+        gp = c->n_cu;
+    }
     hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && K > 1 && !p->aux) e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking);
+    for (int k = 0; k < K && e == hipSuccess; ++k)
+        if (!p->ev_ray[k]) e = hipEventCreateWithFlags(&p->ev_ray[k], hipEventDisableTiming);
+    if (e == hipSuccess && K > 1 && !p->ev_join) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = p->d_rays.ensure(sizeof(ItemRay) * std::max<size_t>(rays.size(), 1));
     if (e == hipSuccess) e = p->d_tiles.ensure(sizeof(ItemPsf) * std::max<size_t>(tiles.size(), 1));
     if (e == hipSuccess && !rays.empty())
@@ -62,6 +106,7 @@ sg_status apply_shape(sg_ctx* c, Plan* p, const LaunchShape& s)
     p->n_rays = (int32_t)rays.size();
     p->n_tiles = (int32_t)tiles.size();
     p->shape = s;
+    p->shape.chunks = K;
     p->grid_ray = gr;
     p->grid_psf = gp;
     drop_graph(p);
@@ -91,20 +136,41 @@ PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
 }
 
 // enqueue one step's kernels (queue reset, device geometry, persistent ray
-// kernel, persistent PSF kernel) on stream s; optional events around the
-// ray and PSF kernels
+// kernel, persistent PSF kernel) on stream s; optional events: before the
+// first ray kernel, after the last ray kernel, at the end of the step.  With
+// chunks, chunk k's PSF kernel waits for its ray kernel on the plan's second
+// stream, which the step joins at the end (the same code is captured).
 hipError_t enqueue_step(sg_ctx* c, Plan* p, float* out, hipStream_t s, hipEvent_t* ev = nullptr)
 {
     QueueDev* q = (QueueDev*)p->d_queue.p;
-    const PhysArgs a = plan_args(c, p, out);
-    hipError_t e = launch_queue_reset(q, s);
+    const int K = p->shape.chunks;
+    hipError_t e = launch_queue_reset(q, K, s);
     if (e == hipSuccess)
         e = launch_geometry((EnvDev*)p->d_envs.p, (const VolDev*)c->d_vols.p, (const double*)p->d_poses.p,
                             p->n_envs, q, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[0], s);
-    if (e == hipSuccess) e = launch_ray(a, q, p->grid_ray, s);
+    if (K == 1) {
+        const PhysArgs a = plan_args(c, p, out);
+        if (e == hipSuccess) e = launch_ray(a, q, p->grid_ray, s);
+        if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess) e = launch_psf(a, q, p->shape.tx, p->grid_psf, s);
+        if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
+        return e;
+    }
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+        PhysArgs a = plan_args(c, p, out);
+        a.ray_items += p->ray_off[k];
+        a.n_ray = p->ray_cnt[k];
+        a.psf_items += p->tile_off[k];
+        a.n_psf = p->tile_cnt[k];
+        e = launch_ray(a, q + k, p->grid_ray, s);
+        if (e == hipSuccess) e = hipEventRecord(p->ev_ray[k], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->aux, p->ev_ray[k], 0);
+        if (e == hipSuccess) e = launch_psf(a, q + k, p->shape.tx, k == K - 1 ? p->grid_psf_last : p->grid_psf, p->aux);
+    }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
-    if (e == hipSuccess) e = launch_psf(a, q, p->shape.tx, p->grid_psf, s);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join, 0);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
     return e;
 }
@@ -162,14 +228,15 @@ bool cache_lookup(const char* path, const std::string& key, LaunchShape* s)
     while (std::getline(f, line)) {
         const std::string tag = "\"key\": \"" + key + "\"";
         if (line.find(tag) == std::string::npos) continue;
-        int spw = 0, tx = 0, ty = 0;
+        int spw = 0, tx = 0, ty = 0, ch = 0;
         const char* q = std::strstr(line.c_str(), "\"spw\":");
         const char* x = std::strstr(line.c_str(), "\"tx\":");
         const char* y = std::strstr(line.c_str(), "\"ty\":");
-        if (q && x && y && std::sscanf(q, "\"spw\": %d", &spw) == 1 && std::sscanf(x, "\"tx\": %d", &tx) == 1 &&
-            std::sscanf(y, "\"ty\": %d", &ty) == 1) {
+        const char* z = std::strstr(line.c_str(), "\"chunks\":");
+        if (q && x && y && z && std::sscanf(q, "\"spw\": %d", &spw) == 1 && std::sscanf(x, "\"tx\": %d", &tx) == 1 &&
+            std::sscanf(y, "\"ty\": %d", &ty) == 1 && std::sscanf(z, "\"chunks\": %d", &ch) == 1) {
             for (const LaunchShape& k : kShapes)
-                if (k.spw == spw && k.tx == tx && ty == 64) {
+                if (k.spw == spw && k.tx == tx && k.chunks == ch && ty == 64) {
                     *s = k;
                     found = true;   // keep the last matching line
                 }
@@ -216,7 +283,7 @@ extern "C" sg_status sg_batch_plan_create(sg_ctx* c, int32_t n, const int32_t* v
     hipError_t e = p->d_envs.ensure(sizeof(EnvDev) * n);
     if (e == hipSuccess) e = p->d_pool.ensure(sizeof(float) * p->pool.size());
     if (e == hipSuccess) e = p->d_poses.ensure(sizeof(double) * 12 * n);
-    if (e == hipSuccess) e = p->d_queue.ensure(sizeof(QueueDev));
+    if (e == hipSuccess) e = p->d_queue.ensure(sizeof(QueueDev) * kMaxChunks);
     if (e == hipSuccess) e = p->fields.ensure(sizeof(float) * 3 * (size_t)p->n_pixels);
     if (e != hipSuccess) return hip_fail(e, "plan allocation");
     e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice);
@@ -312,14 +379,32 @@ extern "C" sg_status sg_batch_status(sg_ctx* c, int32_t id, int32_t* n_bad)
     return SG_OK;
 }
 
-extern "C" sg_status sg_batch_config(sg_ctx* c, int32_t id, int32_t* spw, int32_t* tx, int32_t* ty)
+extern "C" sg_status sg_batch_config(sg_ctx* c, int32_t id, int32_t* spw, int32_t* tx, int32_t* ty, int32_t* chunks)
 {
     Plan* p = c ? find_plan(c, id) : nullptr;
-    if (!p || !spw || !tx || !ty) return fail(SG_EINVAL, "sg_batch_config: bad plan id or NULL");
-    *spw = p->shape.spw * kRayWaves;
-    *tx = p->shape.tx;
-    *ty = 64;
+    if (!p) return fail(SG_EINVAL, "sg_batch_config: bad plan id");
+    if (spw) *spw = p->shape.spw * kRayWaves;
+    if (tx) *tx = p->shape.tx;
+    if (ty) *ty = 64;
+    if (chunks) *chunks = p->shape.chunks;
     return SG_OK;
+}
+
+extern "C" sg_status sg_batch_set_config(sg_ctx* c, int32_t id, int32_t scanlines_per_item, int32_t tile_x,
+                                         int32_t chunks)
+{
+    Plan* p = c ? find_plan(c, id) : nullptr;
+    if (!p) return fail(SG_EINVAL, "sg_batch_set_config: bad plan id");
+    if ((scanlines_per_item != 4 && scanlines_per_item != 8 && scanlines_per_item != 16) ||
+        (tile_x != 16 && tile_x != 32 && tile_x != 64) || chunks < 1 || chunks > kMaxChunks)
+        return fail(SG_EINVAL, "sg_batch_set_config: scanlines_per_item in {4, 8, 16}, tile_x in {16, 32, 64}, "
+                               "chunks in [1, %d]", kMaxChunks);
+    (void)hipSetDevice(c->device);
+    LaunchShape s;
+    s.spw = scanlines_per_item / kRayWaves;
+    s.tx = tile_x;
+    s.chunks = chunks;
+    return apply_shape(c, p, s);
 }
 
 extern "C" sg_status sg_autotune(sg_ctx* c, int32_t id, const char* cache_path)
@@ -381,7 +466,7 @@ extern "C" sg_status sg_autotune(sg_ctx* c, int32_t id, const char* cache_path)
         std::ofstream f(cache_path, std::ios::app);
         if (f)
             f << "{\"key\": \"" << key << "\", \"spw\": " << best.spw << ", \"tx\": " << best.tx
-              << ", \"ty\": 64, \"us\": " << best_us << "}\n";
+              << ", \"ty\": 64, \"chunks\": " << best.chunks << ", \"us\": " << best_us << "}\n";
     }
     return SG_OK;
 }

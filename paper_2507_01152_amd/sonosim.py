@@ -24,7 +24,7 @@ SYMBOLS = (
     "sg_volume_register", "sg_volume_release", "sg_tissue_table_set", "sg_simulate",
     "sg_batch_plan_create", "sg_batch_poses", "sg_batch_set_poses", "sg_batch_step",
     "sg_batch_step_profiled", "sg_batch_status", "sg_autotune",
-    "sg_batch_config", "sg_batch_plan_destroy",
+    "sg_batch_config", "sg_batch_set_config", "sg_batch_plan_destroy",
     "sg_conv_forward", "sg_conv_backward_data", "sg_conv_backward_weight",
     "sg_surr_create", "sg_surr_destroy", "sg_surr_num_params", "sg_surr_train_step", "sg_surr_infer",
     "sg_audit_decide", "sg_surr_save", "sg_surr_load", "sg_surr_get_params", "sg_surr_get_grads",
@@ -95,7 +95,8 @@ def load():
         "sg_batch_step_profiled": [VP, I32, VP, P(C.c_float), P(C.c_float)],
         "sg_batch_status": [VP, I32, P(I32)],
         "sg_autotune": [VP, I32, C.c_char_p],
-        "sg_batch_config": [VP, I32, P(I32), P(I32), P(I32)],
+        "sg_batch_config": [VP, I32, P(I32), P(I32), P(I32), P(I32)],
+        "sg_batch_set_config": [VP, I32, I32, I32, I32],
         "sg_batch_plan_destroy": [VP, I32],
         "sg_conv_forward": [VP, P(sg_conv_desc), VP, VP, VP, I32, VP, VP, VP, VP],
         "sg_conv_backward_data": [VP, P(sg_conv_desc), VP, VP, VP, I32],
@@ -266,9 +267,16 @@ def sg_autotune(ctx, plan_id: int, cache_path: str | None = None):
 
 
 def sg_batch_config(ctx, plan_id: int):
-    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-    _check(load().sg_batch_config(ctx, int(plan_id), C.byref(a), C.byref(b), C.byref(c)), "sg_batch_config")
-    return int(a.value), int(b.value), int(c.value)
+    """(scanlines_per_item, tile_x, tile_y, chunks) of a plan."""
+    a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().sg_batch_config(ctx, int(plan_id), C.byref(a), C.byref(b), C.byref(c), C.byref(d)),
+           "sg_batch_config")
+    return int(a.value), int(b.value), int(c.value), int(d.value)
+
+
+def sg_batch_set_config(ctx, plan_id: int, scanlines_per_item: int, tile_x: int, chunks: int = 1):
+    _check(load().sg_batch_set_config(ctx, int(plan_id), int(scanlines_per_item), int(tile_x), int(chunks)),
+           "sg_batch_set_config")
 
 
 def sg_batch_plan_destroy(ctx, plan_id: int):

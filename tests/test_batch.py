@@ -97,8 +97,8 @@ def test_autotune_keeps_frames_bit_identical(sess, uneven, tmp_path):
     out, plan = batch_frames(sess, uneven, vids)
     cache = str(tmp_path / "tune.jsonl")
     sg.sg_autotune(sess.ctx, plan, cache)
-    spw, tx, ty = sg.sg_batch_config(sess.ctx, plan)
-    assert spw in (4, 8, 16) and tx in (16, 32, 64) and ty == 64
+    spw, tx, ty, chunks = sg.sg_batch_config(sess.ctx, plan)
+    assert spw in (4, 8, 16) and tx in (16, 32, 64) and ty == 64 and 1 <= chunks <= 4
     out2, _ = batch_frames(sess, uneven, vids, plan=plan)
     assert torch.equal(out, out2)
     text = open(cache).read()
@@ -106,10 +106,41 @@ def test_autotune_keeps_frames_bit_identical(sess, uneven, tmp_path):
     # a second plan of the same shape reads the cache instead of timing
     out3, plan2 = batch_frames(sess, uneven, vids)
     sg.sg_autotune(sess.ctx, plan2, cache)
-    assert sg.sg_batch_config(sess.ctx, plan2) == (spw, tx, ty)
+    assert sg.sg_batch_config(sess.ctx, plan2) == (spw, tx, ty, chunks)
     assert open(cache).read() == text
     ms_ray, ms_psf = sg.sg_batch_step_profiled(sess.ctx, plan2, out3)
     assert ms_ray > 0 and ms_psf > 0 and torch.equal(out, out3)
+
+
+@pytest.mark.parametrize("spw,tx,chunks", [(4, 16, 1), (16, 64, 1), (8, 32, 2), (8, 64, 3), (4, 32, 4)])
+def test_every_launch_shape_gives_identical_frames(sess, uneven, spw, tx, chunks):
+    """Explicit launch shapes, including the chunked pipeline (PSF kernel of
+    one env group beside the ray kernel of the next on a second stream), give
+    the default shape's frames bit for bit, eagerly and through the graph."""
+    from paper_2507_01152_amd import sonosim as sg
+    vids = sess.load(uneven)
+    ref, _ = batch_frames(sess, uneven, vids)
+    out, plan = batch_frames(sess, uneven, vids)
+    sg.sg_batch_set_config(sess.ctx, plan, spw, tx, chunks)
+    assert sg.sg_batch_config(sess.ctx, plan) == (spw, tx, 64, chunks)
+    for _ in range(3):   # graph replays
+        out.fill_(-1.0)
+        sg.sg_batch_step(sess.ctx, plan, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+    out.fill_(-1.0)
+    ms_ray, ms_psf = sg.sg_batch_step_profiled(sess.ctx, plan, out)
+    assert ms_ray > 0 and ms_psf > 0 and torch.equal(out, ref)
+    assert sg.sg_batch_status(sess.ctx, plan) == 0
+
+
+def test_set_config_rejects_bad_shapes(sess, uneven):
+    from paper_2507_01152_amd import sonosim as sg
+    vids = sess.load(uneven)
+    _, plan = batch_frames(sess, uneven, vids)
+    for bad in [(5, 32, 1), (8, 48, 1), (8, 32, 0), (8, 32, 5)]:
+        with pytest.raises(sg.SonosimError):
+            sg.sg_batch_set_config(sess.ctx, plan, *bad)
 
 
 def test_out_of_range_pose_gives_zero_frame_and_status(sess):
