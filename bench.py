@@ -39,7 +39,7 @@ def ray_ops_per_pixel(W: int, H: int) -> int:
     (quarter-rate ops -- 32-bit integer multiplies, transcendentals -- count 4)."""
     sample = 20          # Q16 position, rounding, bounds, voxel index, label gather
     interface = 4        # boundary indicator and reflection/transmission select
-    scans = 18           # 6-step wave scans: FP32 product, FP64 sum
+    scans = 18           # 6-step wave scans: FP32 product and sum
     energy = 10          # exp and products
     philox = 10 * 20     # 10 rounds: two 32x32->64 products (4 quarter-rate ops) + xors
     scatter = 22         # Box-Muller (log, sqrt, cos) + gate + amplitude

@@ -227,14 +227,14 @@ __device__ __forceinline__ float wave_scan_mul(float v)
     return v;
 }
 
-__device__ __forceinline__ double wave_scan_add(double v)
+__device__ __forceinline__ float wave_scan_add(float v)
 {
-    v += dpp_d<kRowShr1>(0.0, v);
-    v += dpp_d<kRowShr2>(0.0, v);
-    v += dpp_d<kRowShr4>(0.0, v);
-    v += dpp_d<kRowShr8>(0.0, v);
-    v += dpp_d<kRowBcast15, 0xa>(0.0, v);
-    v += dpp_d<kRowBcast31, 0xc>(0.0, v);
+    v += dpp_f<kRowShr1>(0.f, v);
+    v += dpp_f<kRowShr2>(0.f, v);
+    v += dpp_f<kRowShr4>(0.f, v);
+    v += dpp_f<kRowShr8>(0.f, v);
+    v += dpp_f<kRowBcast15, 0xa>(0.f, v);
+    v += dpp_f<kRowBcast31, 0xc>(0.f, v);
     return v;
 }
 
@@ -287,7 +287,7 @@ __device__ __forceinline__ void axial_from_ring(const float2* ring, const float*
 
 // One scanline of the ray pass, executed by one wave (lane = depth row).
 __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v, const TissueDev* tab,
-                             const float* kax, float2* ring, int x, int lane)
+                             const float2* pair_rt, const float* kax, float2* ring, int x, int lane)
 {
     const int H = e.H;
     float* fR = a.fR + e.scr_off + (int64_t)x * H;
@@ -307,7 +307,11 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
     ring_put(ring, kRing - kWave + lane, make_float2(0.f, 0.f));
 
     float carry_t = 1.f;     // transmission product of the rows above the chunk
-    double carry_a = 0.0;    // attenuation integral (sum of alpha) above the chunk
+    float carry_a = 0.f;     // attenuation integral (sum of alpha) above the chunk,
+    float carry_c = 0.f;     // with its Kahan compensation (integral = carry_a - carry_c)
+    const float coef2 = (float)e.coef2;
+    const bool pairs = !ct && pair_rt != nullptr;
+    const int n_lab = a.n_labels;
     float E_prev = 0.f;      // E of the previous chunk (its axial output is pending)
 
     int32_t vox = voxel_at(e, v, x, lane);
@@ -342,34 +346,50 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         const float T = (inside && (unsigned long long)w[2] < tt.thr) ? n0 * tt.sigma0 + tt.mu0 : 0.f;
 
         // boundary with the next row: lane i + 1, or the next chunk's first row
-        const double Zc = ct ? Z : (double)tt.Z;
         const int lab_first_n = __builtin_amdgcn_readlane(lab_n, 0);
-        const double Z_first_n = ct ? lane_d(Zct_n, 0) : (double)tab[lab_first_n].Z;
         const int lab_nr = dpp_i<kWaveShl1>(lab_first_n, lab);
         const int lab_pr = dpp_i<kWaveShr1>(y0 > 0 ? lab_last_prev : lab, lab);   // row y - 1 (clamped)
-        const double Z_nr = dpp_d<kWaveShl1>(Z_first_n, Zc);
         const bool G = act && (y < H - 1) && (lab != lab_nr);
         float r = 0.f, t = 1.f;
-        if (G && Zc != Z_nr) {
-            if (Zc == 0.0 || Z_nr == 0.0 || __builtin_isinf(Zc) || __builtin_isinf(Z_nr)) {
-                r = Z_nr > Zc ? 1.f : -1.f;
-                t = 0.f;
-            } else {
-                const double s = Zc + Z_nr;
-                r = (float)((Z_nr - Zc) / s);
-                t = (float)((2.0 * Zc / s) * (2.0 * Z_nr / s));
+        if (pairs) {
+            // label volume: the pair table holds the FP64 expressions below, evaluated per label pair
+            if (G) {
+                const float2 p = pair_rt[lab * n_lab + lab_nr];
+                r = p.x;
+                t = p.y;
+            }
+        } else {
+            const double Zc = ct ? Z : (double)tt.Z;
+            const double Z_first_n = ct ? lane_d(Zct_n, 0) : (double)tab[lab_first_n].Z;
+            const double Z_nr = dpp_d<kWaveShl1>(Z_first_n, Zc);
+            if (G && Zc != Z_nr) {
+                if (Zc == 0.0 || Z_nr == 0.0 || __builtin_isinf(Zc) || __builtin_isinf(Z_nr)) {
+                    r = Z_nr > Zc ? 1.f : -1.f;
+                    t = 0.f;
+                } else {
+                    const double s = Zc + Z_nr;
+                    r = (float)((Z_nr - Zc) / s);
+                    t = (float)((2.0 * Zc / s) * (2.0 * Z_nr / s));
+                }
             }
         }
-        // inclusive wave scans (FP32 transmission product, FP64 alpha sum),
-        // shifted by one lane for the exclusive prefix
+        // inclusive wave scans (FP32 transmission product and alpha sum; tree
+        // order within the chunk and a compensated sum of the chunk totals, so
+        // the integral's relative error stays near 9 u), shifted by one lane
+        // for the exclusive prefix
         const float tp = wave_scan_mul(act ? t : 1.f);
-        const double as = wave_scan_add(act ? (double)tt.alpha : 0.0);
+        const float as = wave_scan_add(act ? tt.alpha : 0.f);
         const float t_ex = dpp_f<kWaveShr1>(1.f, tp);
-        const double a_ex = dpp_d<kWaveShr1>(0.0, as);
+        const float a_ex = dpp_f<kWaveShr1>(0.f, as);
         // E = E0 * prod(t) * exp(-f dy alpha-integral), as 2^(-coef2 * sum)
-        const float E = e.E0 * (carry_t * t_ex) * __builtin_amdgcn_exp2f((float)(-e.coef2 * (carry_a + a_ex)));
+        const float E = e.E0 * (carry_t * t_ex) * __builtin_amdgcn_exp2f(-coef2 * ((carry_a + a_ex) - carry_c));
         carry_t *= lane_f(tp, kWave - 1);
-        carry_a += lane_d(as, kWave - 1);
+        {   // compensated running sum of the chunk totals
+            const float yk = lane_f(as, kWave - 1) - carry_c;
+            const float tk = carry_a + yk;
+            carry_c = (tk - carry_a) - yk;
+            carry_a = tk;
+        }
 
         float cs = 1.f;
         if (G) cs = incidence_cos(e, v, q, x, y, lab, y > 0 ? lab_pr : lab, lab_nr);
@@ -435,10 +455,13 @@ __device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
 __global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a, QueueDev* q)
 {
     __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
+    __shared__ float2 s_pair[kPairLabels * kPairLabels];
     __shared__ float s_kax[kTaps];
     __shared__ float2 s_ring[kWaves][kRingAlloc];
     __shared__ int s_item;
     for (int i = threadIdx.x; i < a.n_labels; i += kThreads) s_tab[i] = a.table[i];
+    if (a.pair_rt)
+        for (int i = threadIdx.x; i < a.n_labels * a.n_labels; i += kThreads) s_pair[i] = a.pair_rt[i];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     for (;;) {
@@ -451,7 +474,7 @@ __global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a, QueueDev* q)
         __syncthreads();
         for (int s = 0; s < a.scanlines_per_wave; ++s) {
             const int x = it.x0 + s * kWaves + wave;
-            if (x < e.W) ray_scanline(a, e, v, s_tab, s_kax, s_ring[wave], x, lane);
+            if (x < e.W) ray_scanline(a, e, v, s_tab, a.pair_rt ? s_pair : nullptr, s_kax, s_ring[wave], x, lane);
         }
     }
 }

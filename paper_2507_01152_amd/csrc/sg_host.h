@@ -91,6 +91,7 @@ struct sg_ctx {
     bool vols_dirty = true;
     sg::DevBuf d_vols;
     sg::DevBuf table;
+    sg::DevBuf pair_rt;   // (r, t) per label pair, when n_labels <= kPairLabels
     int32_t n_labels = 0;
     sg::DevBuf scan, params, fields, queue;
     sg::PinnedBuf staging;

@@ -62,11 +62,15 @@ struct DebugDev {
     float* intensity;
 };
 
+// label volumes with at most this many labels take r and t from a pair table
+constexpr int kPairLabels = 16;
+
 struct PhysArgs {
     const EnvDev* envs;
     const VolDev* vols;
     const TissueDev* table;
     int32_t n_labels;
+    const float2* pair_rt;    // [n_labels][n_labels] (r, t) of a boundary between two labels, or null
     const float* coefs;       // PSF taps pool
     const ItemRay* ray_items;
     int32_t n_ray;

@@ -304,11 +304,35 @@ extern "C" sg_status sg_tissue_table_set(sg_ctx* c, const sg_tissue* rows, int32
         t[i].sigma0 = r.sigma0;
         t[i].thr = gate_threshold(r.mu1);
     }
+    // reflection and transmission of a boundary between labels i (above) and j
+    // (below), for label volumes: the ray kernel's FP64 expressions, evaluated
+    // here once per pair (IEEE double on both sides, so the same bits)
+    std::vector<float2> rt((size_t)kPairLabels * kPairLabels, make_float2(0.f, 1.f));
+    if (n <= kPairLabels) {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double Zc = (double)t[i].Z, Zn = (double)t[j].Z;
+                float r = 0.f, tt = 1.f;
+                if (i != j && Zc != Zn) {
+                    if (Zc == 0.0 || Zn == 0.0 || std::isinf(Zc) || std::isinf(Zn)) {
+                        r = Zn > Zc ? 1.f : -1.f;
+                        tt = 0.f;
+                    } else {
+                        const double s = Zc + Zn;
+                        r = (float)((Zn - Zc) / s);
+                        tt = (float)((2.0 * Zc / s) * (2.0 * Zn / s));
+                    }
+                }
+                rt[(size_t)i * n + j] = make_float2(r, tt);
+            }
+    }
     (void)hipSetDevice(c->device);
     // the previous table may still be read by enqueued work: wait for it
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = c->table.ensure(sizeof(TissueDev) * SG_MAX_LABELS_DEV);
+    if (e == hipSuccess) e = c->pair_rt.ensure(sizeof(float2) * rt.size());
     if (e == hipSuccess) e = hipMemcpy(c->table.p, t.data(), sizeof(TissueDev) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->pair_rt.p, rt.data(), sizeof(float2) * rt.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "tissue table upload");
     c->n_labels = n;
     return SG_OK;
@@ -419,6 +443,7 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
     a.vols = (const VolDev*)c->d_vols.p;
     a.table = (const TissueDev*)c->table.p;
     a.n_labels = c->n_labels;
+    a.pair_rt = c->n_labels <= kPairLabels ? (const float2*)c->pair_rt.p : nullptr;
     a.coefs = (const float*)(d + o_pool);
     a.ray_items = (const ItemRay*)(d + o_ray);
     a.n_ray = (int32_t)rays.size();

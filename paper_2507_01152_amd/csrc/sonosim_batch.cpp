@@ -121,6 +121,7 @@ PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
     a.vols = (const VolDev*)c->d_vols.p;
     a.table = (const TissueDev*)c->table.p;
     a.n_labels = c->n_labels;
+    a.pair_rt = c->n_labels <= kPairLabels ? (const float2*)c->pair_rt.p : nullptr;
     a.coefs = (const float*)p->d_pool.p;
     a.ray_items = (const ItemRay*)p->d_rays.p;
     a.n_ray = p->n_rays;

@@ -77,6 +77,19 @@ def test_total_reflection_at_bone(sess, Zb):
     assert (g[0]["energy"][29:] == 0).all() and (g[0]["energy"][:29] > 0).all()
 
 
+def test_deep_attenuation_down_to_the_energy_floor(sess):
+    """1024 rows through strongly attenuating tissue: E falls to about
+    2^-81 E0 at the bottom (3e-25 E0, above the 1e-30 E0 floor of the
+    tolerance); the GPU's FP32 running sum of alpha (tree order within a
+    chunk, compensated across 16 chunks) must keep E within 1e-4 E."""
+    table = table_with(alpha_1=2.0, alpha_2=1.0)
+    vol = layered_volume(16, 16, 80, [(0, 1), (30, 2), (45, 1)])
+    wl = single_env(vol, Probe(W=3, H=1024, dx=1.0, dy=0.0625), axis_pose((8.0, 8.0, 0.0)), table)
+    g = check_all(sess, wl, name="deep")
+    E = g[0]["energy"]
+    assert (E[-1] > 1e-26).all() and (E[-1] < 1e-24).all()
+
+
 def test_gate_extremes_and_energy_scale(sess):
     table = synth.default_tissue_table().copy()
     table[1, 4] = np.inf     # soft tissue always scatters
