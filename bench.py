@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--surrogate-steps", type=int, default=3125,
                     help="training steps (batch 64; 3125 = 200k pairs) before timing surrogate inference; "
                          "0 skips the surrogate")
+    ap.add_argument("--noise-scales", type=int, default=3,
+                    help="also time the workload with this many noise scales (<= 1 skips it)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline sample (whole steps, at most 200)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -272,6 +274,28 @@ def main():
         "wall_s_timed": round(wall, 3),
     }
 
+    if args.noise_scales > 1:
+        # the same workload with a multi-scale noise field (coarser N0 / N1 scales)
+        import dataclasses
+        ms = dataclasses.replace(wl, volumes=[dataclasses.replace(v, noise_scales=args.noise_scales)
+                                              for v in wl.volumes])
+        vids_ms = sess.load(ms)
+        plan_ms = sg.sg_batch_plan_create(sess.ctx, vids_ms, ms.probes, offs)
+        sg.sg_batch_set_poses(sess.ctx, plan_ms, ms.poses)
+        sg.sg_batch_set_config(sess.ctx, plan_ms, spw, tx, chunks)
+        for _ in range(args.warmup):
+            sg.sg_batch_step(sess.ctx, plan_ms, out)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(args.steps):
+            sg.sg_batch_step(sess.ctx, plan_ms, out)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_ms = t0.elapsed_time(t1) / args.steps
+        assert sg.sg_batch_status(sess.ctx, plan_ms) == 0
+        res["multiscale_noise"] = {"noise_scales": args.noise_scales, "ms_per_step": round(ms_ms, 4),
+                                   "frames_per_s": round(n / (ms_ms / 1e3), 1),
+                                   "vs_one_scale": round(ms_per_step / ms_ms, 3)}
     if not args.no_cpu:
         import oracle
         reps, dt = 0, 0.0

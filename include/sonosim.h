@@ -82,6 +82,14 @@ typedef struct {
                                   from the tissue table) */
     uint64_t noise_seed;       /* key of the fixed per-voxel noise fields
                                   N0, N1 (App. B.2: sampled once over 3D space) */
+    int32_t noise_scales;      /* S in [0, 4]; 0 or 1: one sample per voxel.
+                                  S > 1 adds coarser scales (App. B.2, multi-scale
+                                  N0 and N1): scale s draws on cells of 2^s voxels
+                                  per axis (Philox counter (cell, 0, s, 0)),
+                                  N0 = sum_s N0_s / sqrt(S), and the density gate
+                                  tests sum_s Q[w2_s >> 20] <= fl32(sqrt(S) mu1)
+                                  in FP32, Q = the quantised normal of
+                                  sg_noise_quantiles. */
 } sg_volume_desc;
 
 /* Register a volume; *vol_id receives its id.  Scans the label map once on
@@ -91,6 +99,11 @@ sg_status sg_volume_register(sg_ctx* ctx, const sg_volume_desc* desc, int32_t* v
 
 /* Forget a registered volume (its memory stays the caller's). */
 sg_status sg_volume_release(sg_ctx* ctx, int32_t vol_id);
+
+/* The quantised standard normal of the multi-scale density gate (host, no
+ * context): out[k] = fl32(Phi^-1((k + 1/2) / 4096)) for k < 4096, with
+ * Phi^-1 solved to FP64 precision from erfc.  out: host, 4096 floats. */
+sg_status sg_noise_quantiles(float* out);
 
 /* ------------------------------------------------------------------------
  * Tissue table (App. B.2: per-tissue impedance Z, attenuation alpha and the
@@ -140,6 +153,7 @@ typedef struct {
     uint32_t* philox;     /* Philox4x32-10 words of that voxel (0 outside) */
     float* energy;        /* remaining energy E */
     float* intensity;     /* I before log compression */
+    float* scatter;       /* scattering pattern T (0 where the gate fails) */
 } sg_debug_planes;
 
 /* Simulate n_envs environments (Sec. 4 "Ultrasound simulation" pipeline:

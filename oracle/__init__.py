@@ -35,7 +35,8 @@ def build(force: bool = True) -> str:
 class _Volume(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("sx", C.c_double), ("sy", C.c_double), ("sz", C.c_double),
-                ("labels", C.c_void_p), ("ct", C.c_void_p), ("seed", C.c_uint64)]
+                ("labels", C.c_void_p), ("ct", C.c_void_p), ("seed", C.c_uint64),
+                ("scales", C.c_int32), ("q_lut", C.c_void_p)]
 
 
 class _Tissue(C.Structure):
@@ -81,6 +82,10 @@ def lib():
         L.or_simulate_env.argtypes = [C.POINTER(_Volume), C.c_void_p, C.c_int32, C.POINTER(_Probe),
                                       C.c_void_p, C.POINTER(_Planes)]
         L.or_simulate_env.restype = C.c_int
+        L.or_scatter_voxel.argtypes = [C.POINTER(_Volume), C.c_float, C.c_int64, C.c_int64, C.c_int64,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_float), C.c_void_p]
+        L.or_scatter_voxel.restype = C.c_int
+        L.or_scatter_grid.argtypes = [C.POINTER(_Volume), C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_simulate_batch.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                         C.POINTER(C.c_int32)]
@@ -93,14 +98,29 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
+_Q_LUT = None
+
+
+def quantised_normal_table() -> np.ndarray:
+    """Q[k] = fl32(Phi^-1((k + 1/2) / 4096)), k < 4096: the quantised standard
+    normal of the multi-scale gate (scipy's ndtri in FP64, rounded once)."""
+    global _Q_LUT
+    if _Q_LUT is None:
+        from scipy.special import ndtri
+        _Q_LUT = np.ascontiguousarray(ndtri((np.arange(4096) + 0.5) / 4096.0).astype(np.float32))
+    return _Q_LUT
+
+
 def _volume_struct(vol):
     labels = np.ascontiguousarray(vol.labels, dtype=np.uint8)
     ct = None if vol.ct is None else np.ascontiguousarray(vol.ct, dtype=np.int16)
     nz, ny, nx = labels.shape
     sx, sy, sz = vol.spacing
+    q = quantised_normal_table()
     s = _Volume(nx, ny, nz, sx, sy, sz, labels.ctypes.data,
-                None if ct is None else ct.ctypes.data, int(vol.seed) & ((1 << 64) - 1))
-    return s, (labels, ct)
+                None if ct is None else ct.ctypes.data, int(vol.seed) & ((1 << 64) - 1),
+                int(getattr(vol, "noise_scales", 1)), q.ctypes.data)
+    return s, (labels, ct, q)
 
 
 def _table(table):
@@ -114,6 +134,28 @@ def _probe_struct(p):
 
 
 # ---------------------------------------------------------------------------
+
+def scatter_voxel(vol, mu1: float, ix: int, iy: int, iz: int):
+    """Scattering draw of one voxel: (N0 (FP64), N1 (FP32 sum of quantised
+    normals, 0 with one scale), gate (bool), scale-0 Philox words)."""
+    vs, keep = _volume_struct(vol)
+    n0, n1 = C.c_double(), C.c_float()
+    w = np.zeros(4, dtype=np.uint32)
+    g = lib().or_scatter_voxel(C.byref(vs), float(mu1), int(ix), int(iy), int(iz), C.byref(n0), C.byref(n1),
+                               w.ctypes.data)
+    return float(n0.value), float(n1.value), bool(g), w
+
+
+def scatter_grid(vol, mu1: float):
+    """(N0, N1, gate) of every voxel of vol, each [nz][ny][nx]."""
+    vs, keep = _volume_struct(vol)
+    shape = np.asarray(vol.labels).shape
+    n0 = np.zeros(shape, dtype=np.float64)
+    n1 = np.zeros(shape, dtype=np.float32)
+    g = np.zeros(shape, dtype=np.uint8)
+    lib().or_scatter_grid(C.byref(vs), float(mu1), n0.ctypes.data, n1.ctypes.data, g.ctypes.data)
+    return n0, n1, g.astype(bool)
+
 
 def philox4x32(ctr, key, rounds: int = 10) -> np.ndarray:
     """Philox4x32-R of one counter (4 x u32) under one key (2 x u32)."""

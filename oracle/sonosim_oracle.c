@@ -31,6 +31,15 @@
  *   O7 scattering pattern T (App. B.2, scattering equations): per voxel
  *      Philox4x32-10 words (key = volume seed, counter = voxel index),
  *      N0 by Box-Muller, gate N1 <= mu1 as the integer test w2 < Phi(mu1)*2^32.
+ *      Multi-scale noise (App. B.2, last sentence on the scattering pattern;
+ *      reading): with S > 1 scales, scale s draws the same generator on cells
+ *      of 2^s voxels per axis (counter = (cell index, 0, s, 0); s = 0 is the
+ *      voxel stream above) and
+ *        N0 = (1/sqrt(S)) * sum_s BoxMuller(w0_s, w1_s)       (FP64),
+ *        N1 = sum_s Q[w2_s >> 20] <= fl32(sqrt(S) * mu1)      (FP32 sum, s ascending),
+ *      with Q[k] = fl32(Phi^-1((k + 1/2) / 4096)), a quantised standard
+ *      normal: the gate is decided in FP32 from exactly representable steps,
+ *      as the GPU decides it.
  *   O8 R' = G * E * cos(theta) * |r|.
  *   O9 separable Gaussian PSF with std c_psf * (image size) per axis, radius
  *      max(1, ceil(3 sigma)), normalised, zero padding (App. B.2).
@@ -57,6 +66,8 @@ typedef struct {
     const uint8_t* labels;    /* [nz][ny][nx] */
     const int16_t* ct;        /* [nz][ny][nx] or NULL */
     uint64_t seed;            /* noise-field key */
+    int32_t scales;           /* noise scales S (<= 1: one) */
+    const float* q_lut;       /* [4096] quantised normal Q (used when S > 1) */
 } or_volume;
 
 typedef struct {
@@ -199,6 +210,55 @@ int32_t or_psf_kernel(double sigma, double* K, int32_t cap)
     }
     for (int32_t k = 0; k < 2 * r + 1; ++k) K[k] /= sum;
     return r;
+}
+
+/* O7 for one voxel (ix, iy, iz) inside the grid: N0 and, with S > 1, the
+ * FP32 sum N1 of the quantised normals and its threshold test; words of
+ * scale 0 in w[4].  Returns the gate (1: scatter). */
+int or_scatter_voxel(const or_volume* v, float mu1, int64_t ix, int64_t iy, int64_t iz, double* n0, float* n1,
+                     uint32_t w[4])
+{
+    const uint32_t key[2] = {(uint32_t)v->seed, (uint32_t)(v->seed >> 32)};
+    const int S = v->scales > 1 ? v->scales : 1;
+    double sum0 = 0.0;
+    float sum1 = 0.0f;
+    int gate = 0;
+    for (int s = 0; s < S; ++s) {
+        const int64_t mx = ((int64_t)v->nx + ((int64_t)1 << s) - 1) >> s;
+        const int64_t my = ((int64_t)v->ny + ((int64_t)1 << s) - 1) >> s;
+        const int64_t cell = (((iz >> s) * my) + (iy >> s)) * mx + (ix >> s);
+        const uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), (uint32_t)s, 0u};
+        uint32_t ws[4];
+        or_philox4x32_10(ctr, key, ws);
+        if (s == 0) memcpy(w, ws, sizeof(ws));
+        double u0 = (2.0 * (double)(ws[0] >> 9) + 1.0) / 16777216.0;
+        double u1 = (2.0 * (double)(ws[1] >> 9) + 1.0) / 16777216.0;
+        sum0 += sqrt(-2.0 * log(u0)) * cos(2.0 * M_PI * u1);
+        if (S > 1) sum1 = sum1 + v->q_lut[ws[2] >> 20];
+    }
+    if (S == 1) {
+        *n0 = sum0;
+        *n1 = 0.0f;
+        gate = (uint64_t)w[2] < or_gate_threshold(mu1);
+    } else {
+        *n0 = sum0 / sqrt((double)S);
+        *n1 = sum1;
+        const float thr = (float)(sqrt((double)S) * (double)mu1);
+        gate = sum1 <= thr;
+    }
+    return gate;
+}
+
+/* O7 over the whole grid: N0, N1 and the gate of every voxel, [nz][ny][nx]. */
+void or_scatter_grid(const or_volume* v, float mu1, double* n0, float* n1, uint8_t* gate)
+{
+    const int64_t n = (int64_t)v->nx * v->ny * v->nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t w[4];
+        const int64_t ix = k % v->nx, iy = (k / v->nx) % v->ny, iz = k / ((int64_t)v->nx * v->ny);
+        gate[k] = (uint8_t)or_scatter_voxel(v, mu1, ix, iy, iz, &n0[k], &n1[k], w);
+    }
 }
 
 static double ct_at(const or_volume* v, int64_t ix, int64_t iy, int64_t iz)
@@ -348,20 +408,16 @@ int or_simulate_env(const or_volume* v, const or_tissue* table, int32_t n_labels
     }
 
     /* O7, O8 */
-    const uint32_t key[2] = {(uint32_t)v->seed, (uint32_t)(v->seed >> 32)};
     for (int64_t k = 0; k < NP; ++k) {
         T[k] = 0.0;
         ph[4 * k + 0] = ph[4 * k + 1] = ph[4 * k + 2] = ph[4 * k + 3] = 0;
         if (vox[k] >= 0) {
-            uint64_t n = (uint64_t)vox[k];
-            const uint32_t ctr[4] = {(uint32_t)n, (uint32_t)(n >> 32), 0u, 0u};
-            or_philox4x32_10(ctr, key, &ph[4 * k]);
-            double u0 = (2.0 * (double)(ph[4 * k + 0] >> 9) + 1.0) / 16777216.0;
-            double u1 = (2.0 * (double)(ph[4 * k + 1] >> 9) + 1.0) / 16777216.0;
-            double n0 = sqrt(-2.0 * log(u0)) * cos(2.0 * M_PI * u1);
+            const int64_t ix = vox[k] % v->nx, iy = (vox[k] / v->nx) % v->ny, iz = vox[k] / ((int64_t)v->nx * v->ny);
             const or_tissue* tt = &table[lab[k]];
-            uint64_t thr = or_gate_threshold(tt->mu1);
-            if ((uint64_t)ph[4 * k + 2] < thr) T[k] = n0 * (double)tt->sigma0 + (double)tt->mu0;
+            double n0;
+            float n1;
+            if (or_scatter_voxel(v, tt->mu1, ix, iy, iz, &n0, &n1, &ph[4 * k]))
+                T[k] = n0 * (double)tt->sigma0 + (double)tt->mu0;
         }
         Tabs[k] = fabs(T[k]);
         Rp[k] = G[k] ? E[k] * cs[k] * fabs(r[k]) : 0.0;

@@ -43,9 +43,11 @@ constexpr uint32_t kPhM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhW0 = 0x9E3779B9u;
 constexpr uint32_t kPhW1 = 0xBB67AE85u;
 
-__device__ __forceinline__ void philox4x32_10(uint32_t n_lo, uint32_t k0, uint32_t k1, uint32_t w[4])
+// counter (n_lo, 0, c2_in, 0): n_lo = voxel or cell index, c2_in = noise scale
+__device__ __forceinline__ void philox4x32_10(uint32_t n_lo, uint32_t k0, uint32_t k1, uint32_t w[4],
+                                              uint32_t c2_in = 0u)
 {
-    uint32_t c0 = n_lo, c1 = 0u, c2 = 0u, c3 = 0u;
+    uint32_t c0 = n_lo, c1 = 0u, c2 = c2_in, c3 = 0u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         // one 32x32->64 multiply-add instruction per product
@@ -186,6 +188,38 @@ __device__ __forceinline__ float uniform24(uint32_t w)
     return (float)((w >> 9) * 2u + 1u) * 0x1p-24f;
 }
 
+// Box-Muller N0 = sqrt(-2 ln u0) cos(2 pi u1) with hardware log2 / sqrt / cos(2 pi x)
+__device__ __forceinline__ float box_muller(uint32_t w0, uint32_t w1)
+{
+    const float m2ln = __builtin_amdgcn_logf(uniform24(w0)) * -1.3862943611198906f;   // -2 ln 2
+    return __builtin_amdgcn_sqrtf(m2ln) * __builtin_amdgcn_cosf(uniform24(w1));
+}
+
+// Scatterer draw of voxel (ix, iy, iz) -- index vox, scale-0 words in w --
+// for a volume with S > 1 noise scales: scale s draws on cells of 2^s voxels
+// (counter (cell, 0, s, 0)); n0 = sum_s N0_s / sqrt(S); the gate sums the
+// quantised normals Q[w2_s >> 20] in FP32 (s ascending) against
+// fl32(sqrt(S) mu1), exactly as the oracle decides it.
+__device__ __forceinline__ void scatter_multiscale(const VolDev& v, const float* __restrict__ q_lut, float mu1,
+                                                int32_t ix, int32_t iy, int32_t iz, const uint32_t w[4],
+                                                float& n0, bool& gate)
+{
+    float s0 = box_muller(w[0], w[1]);
+    float s1 = q_lut[w[2] >> 20];
+    for (int s = 1; s < v.scales; ++s) {
+        const uint32_t mx = ((uint32_t)v.nx + (1u << s) - 1u) >> s;
+        const uint32_t my = ((uint32_t)v.ny + (1u << s) - 1u) >> s;
+        const uint32_t cell = (((uint32_t)iz >> s) * my + ((uint32_t)iy >> s)) * mx + ((uint32_t)ix >> s);
+        uint32_t ws[4];
+        philox4x32_10(cell, v.key0, v.key1, ws, (uint32_t)s);
+        s0 += box_muller(ws[0], ws[1]);
+        s1 = s1 + q_lut[ws[2] >> 20];
+    }
+    const double rs = sqrt((double)v.scales);
+    n0 = s0 * (float)(1.0 / rs);
+    gate = s1 <= (float)(rs * (double)mu1);
+}
+
 // ---- wave64 data movement on DPP (GFX9 controls) -----------------------
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
 constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
@@ -286,6 +320,9 @@ __device__ __forceinline__ void axial_from_ring(const float2* ring, const float*
 }
 
 // One scanline of the ray pass, executed by one wave (lane = depth row).
+// MS: the volume may have several noise scales (a separate instantiation, so
+// the single-scale code keeps its registers)
+template <bool MS>
 __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v, const TissueDev* tab,
                              const float2* pair_rt, const float* kax, float2* ring, int x, int lane)
 {
@@ -335,15 +372,23 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         const int lab_n = label_of(v, vox_n);
         const double Zct_n = ct ? z_from_ct(e, v, x, y + kWave) : 0.0;
 
-        // scatterer of this chunk's voxels (computed for every lane, selected below):
-        // N0 = sqrt(-2 ln u0) cos(2 pi u1) with hardware log2 / sqrt / cos(2 pi x)
+        // scatterer of this chunk's voxels (computed for every lane, selected below)
         uint32_t w[4];
         philox4x32_10((uint32_t)vox, v.key0, v.key1, w);
         const TissueDev tt = tab[lab];
-        const float m2ln = __builtin_amdgcn_logf(uniform24(w[0])) * -1.3862943611198906f;   // -2 ln 2
-        const float n0 = __builtin_amdgcn_sqrtf(m2ln) * __builtin_amdgcn_cosf(uniform24(w[1]));
         const bool inside = act && vox >= 0;
-        const float T = (inside && (unsigned long long)w[2] < tt.thr) ? n0 * tt.sigma0 + tt.mu0 : 0.f;
+        float T;
+        if (!MS || v.scales <= 1) {
+            const float n0 = box_muller(w[0], w[1]);
+            T = (inside && (unsigned long long)w[2] < tt.thr) ? n0 * tt.sigma0 + tt.mu0 : 0.f;
+        } else {
+            float n0;
+            bool gate;
+            scatter_multiscale(v, a.q_lut, tt.mu1, (int32_t)((uint32_t)q[0] + 32768u) >> 16,
+                               (int32_t)((uint32_t)q[1] + 32768u) >> 16, (int32_t)((uint32_t)q[2] + 32768u) >> 16, w,
+                               n0, gate);
+            T = (inside && gate) ? n0 * tt.sigma0 + tt.mu0 : 0.f;
+        }
 
         // boundary with the next row: lane i + 1, or the next chunk's first row
         const int lab_first_n = __builtin_amdgcn_readlane(lab_n, 0);
@@ -412,6 +457,7 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
             if (a.dbg.label) a.dbg.label[kk] = (uint8_t)lab;
             if (a.dbg.voxel) a.dbg.voxel[kk] = vox;
             if (a.dbg.energy) a.dbg.energy[kk] = E;
+            if (a.dbg.scatter) a.dbg.scatter[kk] = T;
             if (a.dbg.philox) {
                 uint4 pw;
                 pw.x = inside ? w[0] : 0u;
@@ -452,6 +498,7 @@ __device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
 }
 
 // Ray kernel: items (env, group of kWaves * spw scanlines), longest first.
+template <bool MS>
 __global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a, QueueDev* q)
 {
     __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
@@ -474,7 +521,7 @@ __global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a, QueueDev* q)
         __syncthreads();
         for (int s = 0; s < a.scanlines_per_wave; ++s) {
             const int x = it.x0 + s * kWaves + wave;
-            if (x < e.W) ray_scanline(a, e, v, s_tab, a.pair_rt ? s_pair : nullptr, s_kax, s_ring[wave], x, lane);
+            if (x < e.W) ray_scanline<MS>(a, e, v, s_tab, a.pair_rt ? s_pair : nullptr, s_kax, s_ring[wave], x, lane);
         }
     }
 }
@@ -680,6 +727,7 @@ __device__ __forceinline__ uint16_t f2bf16(float f)
     return (uint16_t)(u >> 16);
 }
 
+template <bool MS>
 __global__ __launch_bounds__(kThreads) void k_encode(PhysArgs a, uint16_t* enc)
 {
     const int env = blockIdx.y;
@@ -697,9 +745,14 @@ __global__ __launch_bounds__(kThreads) void k_encode(PhysArgs a, uint16_t* enc)
                 uint32_t w[4];
                 philox4x32_10((uint32_t)vox, v.key0, v.key1, w);
                 const TissueDev tt = a.table[lab];
-                if ((unsigned long long)w[2] < tt.thr) {
-                    const float m2ln = __builtin_amdgcn_logf(uniform24(w[0])) * -1.3862943611198906f;
-                    sc = __builtin_amdgcn_sqrtf(m2ln) * __builtin_amdgcn_cosf(uniform24(w[1]));
+                if (!MS || v.scales <= 1) {
+                    if ((unsigned long long)w[2] < tt.thr) sc = box_muller(w[0], w[1]);
+                } else {
+                    const int32_t ix = vox % v.nx, iy = (vox / v.nx) % v.ny, iz = vox / (v.nx * v.ny);
+                    float n0;
+                    bool gate;
+                    scatter_multiscale(v, a.q_lut, tt.mu1, ix, iy, iz, w, n0, gate);
+                    if (gate) sc = n0;
                 }
             }
         }
@@ -777,9 +830,11 @@ size_t psf_lds_bytes(int tx, int max_rlat)
 
 bool psf_tile_supported(int tx) { return psf_fn(tx) != nullptr; }
 
-int ray_grid(int n_cu)
+int ray_grid(int n_cu, bool multiscale)
 {
-    return blocks_per_cu(reinterpret_cast<const void*>(&k_ray), kThreads, 0) * n_cu;
+    const void* fn = multiscale ? reinterpret_cast<const void*>(&k_ray<true>)
+                                : reinterpret_cast<const void*>(&k_ray<false>);
+    return blocks_per_cu(fn, kThreads, 0) * n_cu;
 }
 
 int psf_grid(int tx, int max_rlat, int n_cu)
@@ -792,7 +847,10 @@ hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s)
     if (a.n_ray <= 0) return hipSuccess;
     if (grid > a.n_ray) grid = a.n_ray;
     if (grid < 1) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_ray, dim3(grid), dim3(kThreads), 0, s, a, q);
+    if (a.multiscale)
+        hipLaunchKernelGGL(k_ray<true>, dim3(grid), dim3(kThreads), 0, s, a, q);
+    else
+        hipLaunchKernelGGL(k_ray<false>, dim3(grid), dim3(kThreads), 0, s, a, q);
     return hipGetLastError();
 }
 
@@ -818,7 +876,10 @@ hipError_t launch_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, 
     if (n_envs <= 0) return hipSuccess;
     int bx = (max_pixels + kThreads - 1) / kThreads;
     if (bx > 64) bx = 64;
-    hipLaunchKernelGGL(k_encode, dim3(bx, n_envs), dim3(kThreads), 0, s, a, enc);
+    if (a.multiscale)
+        hipLaunchKernelGGL(k_encode<true>, dim3(bx, n_envs), dim3(kThreads), 0, s, a, enc);
+    else
+        hipLaunchKernelGGL(k_encode<false>, dim3(bx, n_envs), dim3(kThreads), 0, s, a, enc);
     return hipGetLastError();
 }
 

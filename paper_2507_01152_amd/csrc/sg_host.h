@@ -57,6 +57,7 @@ struct Plan {
     std::vector<int> order;            // envs, longest scanlines first
     int64_t n_pixels = 0;
     int max_rax = 0, max_rlat = 0;
+    int multiscale = 0;                // some env's volume has several noise scales
     LaunchShape shape;
     int grid_ray = 0, grid_psf = 0, grid_psf_last = 0;   // (last: the last chunk's PSF kernel runs alone)
     DevBuf d_envs, d_pool, d_rays, d_tiles, d_poses, d_queue, fields;
@@ -92,6 +93,7 @@ struct sg_ctx {
     sg::DevBuf d_vols;
     sg::DevBuf table;
     sg::DevBuf pair_rt;   // (r, t) per label pair, when n_labels <= kPairLabels
+    sg::DevBuf q_lut;     // quantised normal of the multi-scale gate (kNoiseQ floats)
     int32_t n_labels = 0;
     sg::DevBuf scan, params, fields, queue;
     sg::PinnedBuf staging;

@@ -17,14 +17,18 @@ struct VolDev {
     double sx, sy, sz;   // voxel spacing, mm
     int32_t nx, ny, nz;
     uint32_t key0, key1; // noise-field key (low / high word of the seed)
-    int32_t pad;
+    int32_t scales;      // noise scales S >= 1
 };
+
+constexpr int kNoiseQ = 4096;   // entries of the quantised normal (w2 >> 20)
+constexpr int kMaxNoiseScales = 4;
 
 struct TissueDev {
     float Z;
     float alpha;
     float mu0;
     float sigma0;
+    float mu1;                // density parameter (multi-scale gate)
     unsigned long long thr;   // scatter gate: word2 < thr (thr may be 2^32)
 };
 
@@ -60,6 +64,7 @@ struct DebugDev {
     uint32_t* philox;
     float* energy;
     float* intensity;
+    float* scatter;
 };
 
 // label volumes with at most this many labels take r and t from a pair table
@@ -71,6 +76,8 @@ struct PhysArgs {
     const TissueDev* table;
     int32_t n_labels;
     const float2* pair_rt;    // [n_labels][n_labels] (r, t) of a boundary between two labels, or null
+    const float* q_lut;       // [kNoiseQ] quantised normal of the multi-scale gate
+    int32_t multiscale;       // some env's volume has more than one noise scale
     const float* coefs;       // PSF taps pool
     const ItemRay* ray_items;
     int32_t n_ray;
@@ -152,7 +159,7 @@ hipError_t launch_max_label(const uint8_t* labels, int64_t n, int32_t* d_out, hi
 hipError_t launch_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, uint16_t* enc, hipStream_t s);
 size_t psf_lds_bytes(int tile_x, int max_rlat);
 bool psf_tile_supported(int tile_x);
-int ray_grid(int n_cu);                              // resident ray workgroups
+int ray_grid(int n_cu, bool multiscale);                              // resident ray workgroups
 int psf_grid(int tile_x, int max_rlat, int n_cu);    // resident PSF workgroups
 
 }  // namespace sg

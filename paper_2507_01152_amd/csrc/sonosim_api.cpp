@@ -191,6 +191,29 @@ extern "C" const char* sg_last_error(void) { return g_err.c_str(); }
 
 extern "C" int32_t sg_version(void) { return 100; }
 
+extern "C" sg_status sg_noise_quantiles(float* out)
+{
+    if (!out) return fail(SG_EINVAL, "sg_noise_quantiles: NULL argument");
+    // Phi(x) = erfc(-x / sqrt 2) / 2 is increasing: bisect to adjacent doubles
+    for (int k = 0; k < kNoiseQ; ++k) {
+        const double p = ((double)k + 0.5) / (double)kNoiseQ;
+        double lo = -40.0, hi = 40.0;
+        for (int it = 0; it < 2000; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (0.5 * std::erfc(-mid / std::sqrt(2.0)) < p)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        // the double nearer the root of the computed Phi
+        const double flo = std::fabs(0.5 * std::erfc(-lo / std::sqrt(2.0)) - p);
+        const double fhi = std::fabs(0.5 * std::erfc(-hi / std::sqrt(2.0)) - p);
+        out[k] = (float)(flo < fhi ? lo : hi);
+    }
+    return SG_OK;
+}
+
 extern "C" sg_status sg_create(sg_ctx** out, int32_t device, void* stream)
 {
     if (!out) return fail(SG_EINVAL, "sg_create: out is NULL");
@@ -209,6 +232,14 @@ extern "C" sg_status sg_create(sg_ctx** out, int32_t device, void* stream)
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
         c->n_cu = prop.multiProcessorCount;
         c->arch = prop.gcnArchName;
+    }
+    std::vector<float> q(kNoiseQ);
+    (void)sg_noise_quantiles(q.data());
+    e = c->q_lut.ensure(sizeof(float) * kNoiseQ);
+    if (e == hipSuccess) e = hipMemcpy(c->q_lut.p, q.data(), sizeof(float) * kNoiseQ, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "noise table upload");
     }
     *out = c;
     return SG_OK;
@@ -250,6 +281,8 @@ extern "C" sg_status sg_volume_register(sg_ctx* c, const sg_volume_desc* d, int3
         if (!(std::isfinite(d->spacing_mm[i]) && d->spacing_mm[i] > 0.0))
             return fail(SG_EINVAL, "voxel spacing must be finite and positive");
     if (!d->labels) return fail(SG_EINVAL, "labels pointer is NULL");
+    if (d->noise_scales < 0 || d->noise_scales > kMaxNoiseScales)
+        return fail(SG_EINVAL, "noise_scales %d outside [0, %d]", d->noise_scales, kMaxNoiseScales);
     (void)hipSetDevice(c->device);
     hipError_t e = c->scan.ensure(sizeof(int32_t));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
@@ -272,6 +305,7 @@ extern "C" sg_status sg_volume_register(sg_ctx* c, const sg_volume_desc* d, int3
     v.dev.nz = d->nz;
     v.dev.key0 = (uint32_t)d->noise_seed;
     v.dev.key1 = (uint32_t)(d->noise_seed >> 32);
+    v.dev.scales = d->noise_scales < 1 ? 1 : d->noise_scales;
     v.max_label = mx;
     v.live = true;
     c->vols.push_back(v);
@@ -302,6 +336,7 @@ extern "C" sg_status sg_tissue_table_set(sg_ctx* c, const sg_tissue* rows, int32
         t[i].alpha = r.alpha_np_cm_mhz;
         t[i].mu0 = r.mu0;
         t[i].sigma0 = r.sigma0;
+        t[i].mu1 = r.mu1;
         t[i].thr = gate_threshold(r.mu1);
     }
     // reflection and transmission of a boundary between labels i (above) and j
@@ -386,7 +421,7 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
     std::vector<EnvDev> envs(n);
     std::vector<float> pool;
     int64_t scr = 0;
-    int max_rlat = 0, max_px = 0;
+    int max_rlat = 0, max_px = 0, multiscale = 0;
     for (int i = 0; i < n; ++i) {
         for (int k = 0; k < 12; ++k)
             if (!std::isfinite(poses[12 * i + k])) return fail(SG_EINVAL, "env %d: pose is not finite", i);
@@ -394,6 +429,7 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
         s = fill_env_static(probes[i], vol_ids[i], i, out_offsets[i], scr, pool, envs[i]);
         if (s != SG_OK) return s;
         const VolDev& v = c->vols[vol_ids[i]].dev;
+        multiscale |= v.scales > 1;
         envs[i].valid = plane_geometry(poses + 12 * i, v.sx, v.sy, v.sz, probes[i].W, probes[i].H,
                                        probes[i].dx_mm, probes[i].dy_mm, envs[i].P0, envs[i].DX, envs[i].DY);
         if (!envs[i].valid)
@@ -444,6 +480,7 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
     a.table = (const TissueDev*)c->table.p;
     a.n_labels = c->n_labels;
     a.pair_rt = c->n_labels <= kPairLabels ? (const float2*)c->pair_rt.p : nullptr;
+    a.q_lut = (const float*)c->q_lut.p;
     a.coefs = (const float*)(d + o_pool);
     a.ray_items = (const ItemRay*)(d + o_ray);
     a.n_ray = (int32_t)rays.size();
@@ -459,9 +496,11 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
         a.dbg.philox = dbg->philox;
         a.dbg.energy = dbg->energy;
         a.dbg.intensity = dbg->intensity;
+        a.dbg.scatter = dbg->scatter;
     }
     a.scanlines_per_wave = spw;
     a.max_rlat = max_rlat;
+    a.multiscale = multiscale;
     info.tile_x = tx;
     info.max_pixels = max_px;
     return SG_OK;
@@ -473,7 +512,8 @@ sg_status launch_physics(sg_ctx* c, const PhysArgs& a, const StageInfo& info)
     QueueDev* q = (QueueDev*)c->queue.p;
     hipError_t e;
     if ((e = launch_queue_reset(q, 1, c->stream)) != hipSuccess) return hip_fail(e, "queue reset");
-    if ((e = launch_ray(a, q, ray_grid(c->n_cu), c->stream)) != hipSuccess) return hip_fail(e, "ray kernel launch");
+    if ((e = launch_ray(a, q, ray_grid(c->n_cu, a.multiscale != 0), c->stream)) != hipSuccess)
+        return hip_fail(e, "ray kernel launch");
     if ((e = launch_psf(a, q, info.tile_x, psf_grid(info.tile_x, a.max_rlat, c->n_cu), c->stream)) != hipSuccess)
         return hip_fail(e, "PSF kernel launch");
     return SG_OK;

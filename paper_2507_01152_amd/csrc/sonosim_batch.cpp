@@ -83,7 +83,7 @@ sg_status apply_shape(sg_ctx* c, Plan* p, const LaunchShape& s)
         rays.insert(rays.end(), r.begin(), r.end());
         tiles.insert(tiles.end(), t.begin(), t.end());
     }
-    int gr = ray_grid(c->n_cu), gp = psf_grid(s.tx, p->max_rlat, c->n_cu);
+    int gr = ray_grid(c->n_cu, p->multiscale != 0), gp = psf_grid(s.tx, p->max_rlat, c->n_cu);
     if (gr < 1 || gp < 1) return fail(SG_EINVAL, "launch shape (tile %d) does not fit a compute unit", s.tx);
     p->grid_psf_last = gp;
     if (K > 1) {   // leave room on every CU for one PSF block beside the ray blocks
@@ -122,6 +122,7 @@ PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
     a.table = (const TissueDev*)c->table.p;
     a.n_labels = c->n_labels;
     a.pair_rt = c->n_labels <= kPairLabels ? (const float2*)c->pair_rt.p : nullptr;
+    a.q_lut = (const float*)c->q_lut.p;
     a.coefs = (const float*)p->d_pool.p;
     a.ray_items = (const ItemRay*)p->d_rays.p;
     a.n_ray = p->n_rays;
@@ -133,6 +134,7 @@ PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
     a.out = out;
     a.scanlines_per_wave = p->shape.spw;
     a.max_rlat = p->max_rlat;
+    a.multiscale = p->multiscale;
     return a;
 }
 
@@ -273,6 +275,7 @@ extern "C" sg_status sg_batch_plan_create(sg_ctx* c, int32_t n, const int32_t* v
         p->n_pixels += (int64_t)probes[i].W * probes[i].H;
         p->max_rax = std::max(p->max_rax, p->envs[i].rax);
         p->max_rlat = std::max(p->max_rlat, p->envs[i].rlat);
+        p->multiscale |= c->vols[vol_ids[i]].dev.scales > 1;
     }
     // longest scanlines first (ray items cost ~H), then wider frames
     p->order.resize(n);

@@ -32,7 +32,8 @@ class Session:
         if volume.ct is not None:
             ct = torch.from_numpy(np.ascontiguousarray(volume.ct)).to(self.device)
         self._keep.append((lab, ct))
-        return sg.sg_volume_register(self.ctx, lab, volume.spacing, ct, volume.seed)
+        return sg.sg_volume_register(self.ctx, lab, volume.spacing, ct, volume.seed,
+                                     getattr(volume, "noise_scales", 1))
 
     def load(self, workload):
         """Register the workload's volumes and tissue table; returns env vol ids."""
@@ -52,6 +53,7 @@ class Session:
             "philox": torch.empty(4 * total, dtype=torch.int32, device=d),
             "energy": torch.empty(total, dtype=torch.float32, device=d),
             "intensity": torch.empty(total, dtype=torch.float32, device=d),
+            "scatter": torch.empty(total, dtype=torch.float32, device=d),
         }
 
     def simulate(self, workload, vol_ids, debug: bool = False):

@@ -21,7 +21,7 @@ SG_MAX_IMAGE = 1024
 # every symbol include/sonosim.h declares
 SYMBOLS = (
     "sg_last_error", "sg_version", "sg_create", "sg_destroy", "sg_set_stream", "sg_synchronize",
-    "sg_volume_register", "sg_volume_release", "sg_tissue_table_set", "sg_simulate",
+    "sg_volume_register", "sg_volume_release", "sg_noise_quantiles", "sg_tissue_table_set", "sg_simulate",
     "sg_batch_plan_create", "sg_batch_poses", "sg_batch_set_poses", "sg_batch_step",
     "sg_batch_step_profiled", "sg_batch_status", "sg_autotune",
     "sg_batch_config", "sg_batch_set_config", "sg_batch_plan_destroy",
@@ -41,7 +41,7 @@ class SonosimError(RuntimeError):
 class sg_volume_desc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("spacing_mm", C.c_double * 3), ("labels", C.c_void_p), ("ct_hu", C.c_void_p),
-                ("noise_seed", C.c_uint64)]
+                ("noise_seed", C.c_uint64), ("noise_scales", C.c_int32)]
 
 
 class sg_tissue(C.Structure):
@@ -62,7 +62,7 @@ class sg_conv_desc(C.Structure):
 
 class sg_debug_planes(C.Structure):
     _fields_ = [("label", C.c_void_p), ("voxel", C.c_void_p), ("philox", C.c_void_p),
-                ("energy", C.c_void_p), ("intensity", C.c_void_p)]
+                ("energy", C.c_void_p), ("intensity", C.c_void_p), ("scatter", C.c_void_p)]
 
 
 _lib = None
@@ -86,6 +86,7 @@ def load():
         "sg_synchronize": [VP],
         "sg_volume_register": [VP, P(sg_volume_desc), P(I32)],
         "sg_volume_release": [VP, I32],
+        "sg_noise_quantiles": [VP],
         "sg_tissue_table_set": [VP, VP, I32],
         "sg_simulate": [VP, I32, VP, VP, VP, VP, VP, P(sg_debug_planes)],
         "sg_batch_plan_create": [VP, I32, VP, VP, VP, P(I32)],
@@ -170,13 +171,13 @@ def sg_synchronize(ctx):
     _check(load().sg_synchronize(ctx), "sg_synchronize")
 
 
-def sg_volume_register(ctx, labels, spacing=(1.0, 1.0, 1.0), ct=None, seed: int = 0) -> int:
+def sg_volume_register(ctx, labels, spacing=(1.0, 1.0, 1.0), ct=None, seed: int = 0, noise_scales: int = 1) -> int:
     """labels: device uint8 tensor [nz, ny, nx]; ct: device int16 tensor or None."""
     nz, ny, nx = labels.shape
     if ct is not None and tuple(ct.shape) != tuple(labels.shape):
         raise ValueError("ct must have the label volume's shape")
     d = sg_volume_desc(nx, ny, nz, (C.c_double * 3)(*[float(s) for s in spacing]), _dptr(labels),
-                       _dptr(ct), int(seed) & ((1 << 64) - 1))
+                       _dptr(ct), int(seed) & ((1 << 64) - 1), int(noise_scales))
     vid = C.c_int32()
     _check(load().sg_volume_register(ctx, C.byref(d), C.byref(vid)), "sg_volume_register")
     return int(vid.value)
@@ -184,6 +185,13 @@ def sg_volume_register(ctx, labels, spacing=(1.0, 1.0, 1.0), ct=None, seed: int 
 
 def sg_volume_release(ctx, vol_id: int):
     _check(load().sg_volume_release(ctx, int(vol_id)), "sg_volume_release")
+
+
+def sg_noise_quantiles() -> np.ndarray:
+    """The quantised standard normal of the multi-scale gate (4096 floats, host)."""
+    out = np.zeros(4096, dtype=np.float32)
+    _check(load().sg_noise_quantiles(out.ctypes.data), "sg_noise_quantiles")
+    return out
 
 
 def sg_tissue_table_set(ctx, table):
@@ -214,7 +222,7 @@ def sg_simulate(ctx, vol_ids, probes, poses, out, out_offsets, debug: dict | Non
     dbg = None
     if debug:
         dbg = sg_debug_planes(*[_dptr(debug.get(k)) for k in ("label", "voxel", "philox", "energy",
-                                                               "intensity")])
+                                                               "intensity", "scatter")])
     _check(load().sg_simulate(ctx, n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data, _dptr(out),
                               offs.ctypes.data, C.byref(dbg) if dbg is not None else None), "sg_simulate")
 

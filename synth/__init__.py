@@ -76,6 +76,7 @@ class Volume:
     ct: np.ndarray | None = None  # int16 [nz][ny][nx] or None
     spacing: tuple = (1.0, 1.0, 1.0)  # mm along (x, y, z)
     seed: int = 0                 # noise-field key
+    noise_scales: int = 1         # scales of the noise field (1: one sample per voxel)
 
     @property
     def dims(self):

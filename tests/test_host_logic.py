@@ -1,5 +1,6 @@
 """Host-side logic of the library that runs without a device: the audit
-decision rule of surrogate inference."""
+decision rule of surrogate inference and the quantised normal of the
+multi-scale density gate."""
 import numpy as np
 import pytest
 
@@ -30,3 +31,12 @@ def test_audit_rule_rejects_bad_arguments(sg):
     whole = ctypes.c_int32()
     assert lib.sg_audit_decide(-1, None, 30.0, 0.5, None, ctypes.byref(whole)) == sg.SG_EINVAL
     assert lib.sg_audit_decide(3, None, 30.0, 0.5, None, ctypes.byref(whole)) == sg.SG_EINVAL
+
+
+def test_noise_quantiles_of_the_library_match_the_oracle():
+    """The library's host-side quantised normal of the multi-scale gate
+    (bisection on erfc, C++) equals the oracle's (scipy's ndtri), entry for
+    entry: both sides then decide the gate on identical FP32 steps."""
+    import oracle
+    from paper_2507_01152_amd import sonosim as sg
+    assert np.array_equal(sg.sg_noise_quantiles(), oracle.quantised_normal_table())

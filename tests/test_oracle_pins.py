@@ -446,3 +446,61 @@ def test_rejects_label_outside_table():
     with pytest.raises(ValueError):
         oracle.simulate_env(vol, synth.default_tissue_table(), Probe(W=3, H=3),
                             axis_pose((2.0, 2.0, 1.0)))
+
+
+# ---------------------------------------------------------------------------
+# multi-scale noise (reading of the last sentence on the scattering pattern)
+
+def test_quantised_normal_table_inverts_the_normal_cdf():
+    """Q[k] is the FP32 quantile of (k + 1/2)/4096: pinned by the forward CDF
+    (a different library routine), odd symmetry and monotonicity."""
+    from scipy.stats import norm
+    q = oracle.quantised_normal_table()
+    p = (np.arange(4096) + 0.5) / 4096.0
+    back = norm.cdf(q.astype(np.float64))
+    # one FP32 rounding of the quantile moves the CDF by at most pdf(Q) * ulp(Q) / 2
+    bound = norm.pdf(q) * np.spacing(np.abs(q).astype(np.float32)).astype(np.float64) + 1e-15
+    assert np.all(np.abs(back - p) <= bound)
+    assert np.array_equal(q, -q[::-1]) and np.all(np.diff(q) > 0)
+
+
+def _ms_volume(n, scales, seed=41):
+    return synth.Volume(labels=np.ones((n, n, n), np.uint8), seed=seed, noise_scales=scales)
+
+
+def test_multiscale_scale_zero_is_the_voxel_stream():
+    """Scale 0 of a multi-scale field draws the single-scale counters, and one
+    scale is exactly the single-scale model."""
+    v1, v3 = _ms_volume(16, 1), _ms_volume(16, 3)
+    for ix, iy, iz in [(0, 0, 0), (5, 9, 13), (15, 15, 15)]:
+        a = oracle.scatter_voxel(v1, 0.3, ix, iy, iz)
+        b = oracle.scatter_voxel(v3, 0.3, ix, iy, iz)
+        vox = (iz * 16 + iy) * 16 + ix
+        assert np.array_equal(a[3], oracle.philox4x32([vox, 0, 0, 0], [41, 0]))
+        assert np.array_equal(a[3], b[3])
+        assert a[1] == 0.0 and a[2] == (int(a[3][2]) < oracle.gate_threshold(0.3))
+
+
+@pytest.mark.parametrize("scales", [2, 3])
+def test_multiscale_noise_statistics(scales):
+    """N0 stays standard normal, the gate passes with probability Phi(mu1),
+    and two voxels are correlated by the fraction of scales whose cell they
+    share (1/S per shared scale): pins of the sum, its 1/sqrt(S) weight, the
+    sqrt(S) threshold and the cell indexing."""
+    from scipy.stats import norm
+    vol = _ms_volume(64, scales)
+    n0, n1, g = oracle.scatter_grid(vol, 0.5)
+    assert abs(n0.mean()) < 0.03 and abs(n0.var() - 1.0) < 0.03
+    assert abs(g.mean() - norm.cdf(0.5)) < 0.02
+    for mu1 in (-0.5, 0.0):
+        _, _, gm = oracle.scatter_grid(vol, mu1)
+        assert abs(gm.mean() - norm.cdf(mu1)) < 0.02
+    # neighbours along x: x = 4i + j and x + 1 share the cells of scales s
+    # with (x >> s) == ((x + 1) >> s)
+    for j in range(3):
+        a = n0[:, :, j::4].ravel()
+        b = n0[:, :, j + 1::4].ravel()
+        shared = sum(1 for s in range(scales) if (j >> s) == ((j + 1) >> s))
+        assert abs(np.corrcoef(a, b)[0, 1] - shared / scales) < 0.03, (j, shared)
+    # N1 sums S unit-variance quantised normals: mean 0, variance S
+    assert abs(n1.mean()) < 0.05 * np.sqrt(scales) and abs(n1.var() / scales - 1.0) < 0.05

@@ -42,7 +42,7 @@ def check_all(sess, wl, env_ids=None, name="", debug=True):
     ids = range(wl.n_envs) if env_ids is None else env_ids
     for e in ids:
         o = oracle.simulate_env(wl.volumes[wl.vol_ids[e]], wl.table, wl.probes[e], wl.poses[e],
-                                planes=("label", "voxel", "philox", "E", "I", "A", "Y"))
+                                planes=("label", "voxel", "philox", "E", "T", "I", "A", "Y"))
         check_env(g[e], o, wl.probes[e], f"{name} env {e}")
     return g
 
@@ -88,6 +88,24 @@ def test_deep_attenuation_down_to_the_energy_floor(sess):
     g = check_all(sess, wl, name="deep")
     E = g[0]["energy"]
     assert (E[-1] > 1e-26).all() and (E[-1] < 1e-24).all()
+
+
+@pytest.mark.parametrize("scales", [2, 3, 4])
+def test_multiscale_noise_parity(sess, scales):
+    """Multi-scale N0 and N1: the gate pattern bit for bit (FP32 sums of the
+    quantised normal on both sides), T, E, I and Y within the bars; odd
+    volume sizes exercise the coarse cells' partial edges."""
+    wl = synth.ellipsoid_workload(seed=20 + scales, n_envs=2)
+    for v in wl.volumes:
+        v.noise_scales = scales
+    check_all(sess, wl, name=f"S={scales}")
+    lab = np.zeros((37, 29, 41), dtype=np.uint8)
+    lab[:, :, :] = 1
+    lab[20:, :, :] = 3
+    vol = Volume(labels=lab, seed=99, noise_scales=scales)
+    t = table_with(mu1_1=0.3, mu1_3=-0.2)
+    wl2 = single_env(vol, Probe(W=45, H=70, dx=0.7, dy=0.45), axis_pose((20.0, 14.0, 1.0)), t)
+    check_all(sess, wl2, name=f"S={scales} odd")
 
 
 def test_gate_extremes_and_energy_scale(sess):

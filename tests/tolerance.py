@@ -27,6 +27,14 @@ def check_env(gpu: dict, ora: dict, probe, name: str = ""):
         dE = np.abs(gpu["energy"].astype(np.float64) - ora["E"])
         bad = dE > REL * ora["E"] + FLOOR * E0
         assert not bad.any(), f"{name}: E off at {np.argwhere(bad)[:5].tolist()} max rel {(dE / np.maximum(ora['E'], 1e-300)).max():.3g}"
+    if "scatter" in gpu and "T" in ora:
+        # the density gate is decided identically (integer test, or the FP32
+        # sum of quantised normals); the amplitude within FP32 + 1e-5 relative
+        Tg = gpu["scatter"].astype(np.float64)
+        assert np.array_equal(Tg != 0, ora["T"] != 0), f"{name}: scatter gate mismatch"
+        dT = np.abs(Tg - ora["T"])
+        bad = dT > 1e-5 * (np.abs(ora["T"]) + 1e-3)
+        assert not bad.any(), f"{name}: T off at {np.argwhere(bad)[:5].tolist()}"
     A = ora["A"]
     tolI = REL * A + FLOOR * E0
     if "intensity" in gpu:
