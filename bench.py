@@ -175,6 +175,8 @@ def main():
                          "0 skips the surrogate")
     ap.add_argument("--noise-scales", type=int, default=3,
                     help="also time the workload with this many noise scales (<= 1 skips it)")
+    ap.add_argument("--no-volumetric", dest="volumetric", action="store_false",
+                    help="skip the volumetric-probe leg")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline sample (whole steps, at most 200)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -296,6 +298,29 @@ def main():
         res["multiscale_noise"] = {"noise_scales": args.noise_scales, "ms_per_step": round(ms_ms, 4),
                                    "frames_per_s": round(n / (ms_ms / 1e3), 1),
                                    "vs_one_scale": round(ms_per_step / ms_ms, 3)}
+    if args.volumetric:
+        # the surgery task's volumetric probe (50 x 37 x 5 at 2 x 2 x 10 mm) on the same volumes and poses
+        vw = synth.volumetric_workload(seed=0)
+        voffs, vtotal = vw.out_offsets()
+        vout = torch.empty(vtotal, dtype=torch.float32, device=sess.device)
+        plan_v = sg.sg_batch_plan_create(sess.ctx, vids, vw.probes, voffs)
+        sg.sg_batch_set_poses(sess.ctx, plan_v, vw.poses)
+        if not args.no_tune:
+            sg.sg_autotune(sess.ctx, plan_v, os.environ.get("SG_TUNE_CACHE", "/tmp/sonosim_tune.jsonl"))
+        for _ in range(args.warmup):
+            sg.sg_batch_step(sess.ctx, plan_v, vout)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(args.steps):
+            sg.sg_batch_step(sess.ctx, plan_v, vout)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        v_ms = t0.elapsed_time(t1) / args.steps
+        assert sg.sg_batch_status(sess.ctx, plan_v) == 0
+        res["volumetric_probe"] = {"workload": "256 envs, 50 x 37 x 5 volumes at 2 x 2 x 10 mm, same volumes/poses",
+                                   "ms_per_step": round(v_ms, 4), "volumes_per_s": round(n / (v_ms / 1e3), 1),
+                                   "planes_per_s": round(5 * n / (v_ms / 1e3), 1),
+                                   "launch_shape": list(sg.sg_batch_config(sess.ctx, plan_v))}
     if not args.no_cpu:
         import oracle
         reps, dt = 0, 0.0

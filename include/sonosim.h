@@ -130,18 +130,29 @@ sg_status sg_tissue_table_set(sg_ctx* ctx, const sg_tissue* rows, int32_t n_labe
 /* ------------------------------------------------------------------------
  * Probe / image geometry of one environment (linear probe; App. C.1 uses
  * 0.5 mm pixels).  Pixel (x, y) lies at probe-frame point
- * (a + x*dx_mm, 0, y*dy_mm) with a = -0.5*(W-1)*dx_mm: x runs along the
- * probe's lateral axis, y along the beam (probe z).
+ * (a + x*dx_mm, b, y*dy_mm) with a = -0.5*(W-1)*dx_mm: x runs along the
+ * probe's lateral axis, y along the beam (probe z), b along the elevation
+ * (probe y).
  *   W, H      scanlines and depth samples, each in [1, SG_MAX_IMAGE]
  *   f_mhz     centre frequency (attenuation scales with f)
  *   E0        initial energy (> 0)
  *   psf_frac  PSF standard deviation as a fraction of the image size per
  *             axis (App. B.2: about 1 %), > 0
  *   dr_db     display dynamic range in dB (> 0)
+ *   n_elev    planes of a volumetric probe (Sec. 4, surgery task: H x W x E
+ *             images, App. C: 50 x 37 x 5 at 2 x 2 x 10 mm); 0 or 1: one
+ *             plane, at most SG_MAX_ELEV.  Plane j lies at
+ *             b = (j - (n_elev - 1) / 2) * elev_mm and is simulated as its own
+ *             2D image; the env's output is [n_elev][H][W] at its offset.
+ *   elev_mm   plane spacing (> 0 when n_elev > 1)
  */
+#define SG_MAX_ELEV 64
+
 typedef struct {
     int32_t W, H;
     double dx_mm, dy_mm, f_mhz, E0, psf_frac, dr_db;
+    int32_t n_elev;
+    double elev_mm;
 } sg_probe;
 
 /* Optional per-pixel outputs for checking (device pointers, each may be NULL;

@@ -46,7 +46,8 @@ class _Tissue(C.Structure):
 
 class _Probe(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
-                ("f", C.c_double), ("E0", C.c_double), ("psf", C.c_double), ("dr", C.c_double)]
+                ("f", C.c_double), ("E0", C.c_double), ("psf", C.c_double), ("dr", C.c_double),
+                ("elev", C.c_double)]
 
 
 _PLANES = [("q", np.int64, 3), ("label", np.uint8, 1), ("voxel", np.int64, 1),
@@ -128,9 +129,21 @@ def _table(table):
     return t, t.shape[0]
 
 
-def _probe_struct(p):
+def n_planes(p) -> int:
+    """Image planes of a probe (volumetric probes have n_elev > 1)."""
+    return max(1, int(getattr(p, "n_elev", 1)))
+
+
+def plane_elevation(p, j: int) -> float:
+    """Elevation b of plane j, mm: (j - (E - 1) / 2) * spacing, centred."""
+    if n_planes(p) == 1:
+        return 0.0
+    return (float(j) - 0.5 * float(p.n_elev - 1)) * float(p.elev)
+
+
+def _probe_struct(p, plane: int = 0):
     return _Probe(int(p.W), int(p.H), float(p.dx), float(p.dy), float(p.f), float(p.E0),
-                  float(p.psf), float(p.dr))
+                  float(p.psf), float(p.dr), plane_elevation(p, plane))
 
 
 # ---------------------------------------------------------------------------
@@ -201,10 +214,18 @@ def psf_kernel(sigma: float) -> np.ndarray:
 def simulate_env(vol, table, probe, pose, planes=("label", "voxel", "philox", "E", "T", "Rp",
                                                   "I", "A", "Y")) -> dict:
     """Simulate one environment; returns the requested per-pixel planes
-    shaped [H][W] (philox [H][W][4], q [H][W][3])."""
+    shaped [H][W] (philox [H][W][4], q [H][W][3]); a volumetric probe's
+    planes are stacked in front: [E][H][W]."""
+    if n_planes(probe) > 1:
+        per = [_simulate_plane(vol, table, probe, pose, planes, j) for j in range(n_planes(probe))]
+        return {k: np.stack([d[k] for d in per]) for k in per[0]}
+    return _simulate_plane(vol, table, probe, pose, planes, 0)
+
+
+def _simulate_plane(vol, table, probe, pose, planes, j):
     vs, keep = _volume_struct(vol)
     t, n_labels = _table(table)
-    ps = _probe_struct(probe)
+    ps = _probe_struct(probe, j)
     pose = np.ascontiguousarray(pose, dtype=np.float64)
     out, pl = {}, _Planes()
     want = set(planes)
@@ -232,18 +253,25 @@ def simulate_batch(workload, env_ids=None, n_threads: int = 0):
         keep.append(k)
     vols = (_Volume * len(vol_structs))(*vol_structs)
     t, n_labels = _table(workload.table)
-    probes = (_Probe * len(env_ids))(*[_probe_struct(workload.probes[e]) for e in env_ids])
-    vol_ids = np.ascontiguousarray([workload.vol_ids[e] for e in env_ids], dtype=np.int32)
-    poses = np.ascontiguousarray(workload.poses[env_ids], dtype=np.float64)
-    sizes = np.array([workload.probes[e].W * workload.probes[e].H for e in env_ids], dtype=np.int64)
+    # one oracle env per image plane
+    pl = [(e, j) for e in env_ids for j in range(n_planes(workload.probes[e]))]
+    probes = (_Probe * len(pl))(*[_probe_struct(workload.probes[e], j) for e, j in pl])
+    vol_ids = np.ascontiguousarray([workload.vol_ids[e] for e, _ in pl], dtype=np.int32)
+    poses = np.ascontiguousarray(workload.poses[[e for e, _ in pl]], dtype=np.float64)
+    sizes = np.array([workload.probes[e].W * workload.probes[e].H for e, _ in pl], dtype=np.int64)
     offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
     Y = np.zeros(int(sizes.sum()), dtype=np.float64)
     used = C.c_int32(0)
-    rc = lib().or_simulate_batch(len(env_ids), C.cast(vols, C.c_void_p), vol_ids.ctypes.data,
+    rc = lib().or_simulate_batch(len(pl), C.cast(vols, C.c_void_p), vol_ids.ctypes.data,
                                  t.ctypes.data, n_labels, C.cast(probes, C.c_void_p), poses.ctypes.data,
                                  Y.ctypes.data, offs.ctypes.data, int(n_threads), C.byref(used))
     if rc != 0:
         raise ValueError("oracle rejected the inputs")
-    frames = [Y[o:o + s].reshape(workload.probes[e].H, workload.probes[e].W)
-              for o, s, e in zip(offs, sizes, env_ids)]
+    frames, k = [], 0
+    for e in env_ids:
+        p = workload.probes[e]
+        E = n_planes(p)
+        f = Y[offs[k]:offs[k] + E * p.W * p.H].reshape(E, p.H, p.W)
+        frames.append(f if E > 1 else f[0])
+        k += E
     return frames, int(used.value)

@@ -12,7 +12,9 @@
  *
  *   O1 plane geometry (App. B.2 / Sec. 4 "Ultrasound simulation": the image
  *      plane comes from the end-effector pose): pixel (x,y) sits at probe
- *      point (a + x*dx, 0, y*dy), a = -0.5*(W-1)*dx, mapped by the pose into
+ *      point (a + x*dx, b, y*dy), a = -0.5*(W-1)*dx, b = the plane's
+ *      elevation (0 for a linear probe; a volumetric probe, Sec. 4 surgery
+ *      task, is a stack of such planes), mapped by the pose into
  *      volume mm, divided by the voxel spacing and rounded to Q16 fixed point
  *      (rint, half-even) as an origin and two per-pixel steps; every pixel
  *      position is then the exact integer P0 + x*DX + y*DY.
@@ -77,6 +79,7 @@ typedef struct {
 typedef struct {
     int32_t W, H;
     double dx, dy, f, E0, psf, dr;
+    double elev;              /* elevation b of this image plane, mm (0: single plane) */
 } or_probe;
 
 /* Per-pixel planes, each [H][W] row-major (philox [H][W][4], q [H][W][3]).
@@ -167,10 +170,13 @@ void or_geometry(const or_volume* v, const or_probe* p, const double pose[12],
     a = a * p->dx;
     for (int c = 0; c < 3; ++c) {
         double Rc0 = pose[4 * c + 0];
+        double Rc1 = pose[4 * c + 1];
         double Rc2 = pose[4 * c + 2];
         double tc = pose[4 * c + 3];
         double u = Rc0 * a;
         u = tc + u;
+        double v = Rc1 * p->elev;
+        u = u + v;
         u = u / s[c];
         u = u * 65536.0;
         P0[c] = (int64_t)rint(u);

@@ -773,14 +773,15 @@ __global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses
     EnvDev& d = envs[e];
     const VolDev v = vols[d.vol];
     int32_t P0[3], DX[3], DY[3];
-    const int ok = plane_geometry(poses + 12 * e, v.sx, v.sy, v.sz, d.W, d.H, d.dx64, d.dy64, P0, DX, DY);
+    const int ok = plane_geometry(poses + 12 * d.pose_env, v.sx, v.sy, v.sz, d.W, d.H, d.dx64, d.dy64, d.elev64, P0,
+                                  DX, DY);
     for (int c = 0; c < 3; ++c) {
         d.P0[c] = ok ? P0[c] : 0;
         d.DX[c] = ok ? DX[c] : 0;
         d.DY[c] = ok ? DY[c] : 0;
     }
     d.valid = ok;
-    if (!ok) atomicAdd(&q->n_bad, 1);
+    if (!ok && d.plane == 0) atomicAdd(&q->n_bad, 1);   // counted once per caller env
 }
 
 __global__ void k_queue_reset(QueueDev* q, int n)

@@ -48,7 +48,8 @@ struct LaunchShape {
 constexpr int kMaxChunks = 4;
 
 struct Plan {
-    int32_t n_envs = 0;
+    int32_t n_envs = 0;                // internal envs: one per image plane
+    int32_t n_user = 0;                // caller envs (poses, volumes, probes, offsets)
     std::vector<int32_t> vol_ids;
     std::vector<sg_probe> probes;
     std::vector<int64_t> out_offsets;
@@ -110,8 +111,11 @@ sg_status fail(sg_status code, const char* fmt, ...);
 sg_status hip_fail(hipError_t e, const char* what);
 int psf_taps(double sigma, std::vector<float>& pool, int32_t* offset);
 sg_status check_probe(const sg_probe& p, int idx);
-sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int64_t out_off, int64_t scr_off,
+// static parameters of plane `plane` of caller env idx (frame at out_off + plane * W * H)
+sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int plane, int64_t out_off, int64_t scr_off,
                           std::vector<float>& pool, EnvDev& e);
+int probe_planes(const sg_probe& p);                 // image planes of a probe (>= 1)
+double plane_elevation(const sg_probe& p, int j);   // elevation b of plane j, mm
 void build_items(const std::vector<EnvDev>& envs, const std::vector<int>& order, int spw, int tx,
                  std::vector<ItemRay>& rays, std::vector<ItemPsf>& tiles);
 sg_status sync_volumes(sg_ctx* c);

@@ -51,6 +51,9 @@ struct EnvDev {
     double coef2;                  // f * dy_cm * log2(e): attenuation in octaves
     double dx64, dy64, f64;        // for device-side geometry
     double psf64;
+    double elev64;                 // elevation b of this plane, mm (volumetric probes)
+    int32_t pose_env;              // caller's env whose pose this plane uses
+    int32_t plane;                 // plane index within that env
     int64_t out_off;               // frame offset in the output (elements)
     int64_t scr_off;               // offset of this env in the field scratch
 };
@@ -107,7 +110,7 @@ struct QueueDev {
 // bit for bit.  Returns 1 if every corner of the plane lies within
 // +-2^30 (Q16), else 0 (outputs then unspecified).
 __host__ __device__ inline int plane_geometry(const double* pose, double sx, double sy, double sz,
-                                              int32_t W, int32_t H, double dx, double dy,
+                                              int32_t W, int32_t H, double dx, double dy, double elev,
                                               int32_t P0[3], int32_t DX[3], int32_t DY[3])
 {
 #pragma clang fp contract(off)
@@ -116,9 +119,11 @@ __host__ __device__ inline int plane_geometry(const double* pose, double sx, dou
     a = a * dx;
     long long p0[3], ddx[3], ddy[3];
     for (int c = 0; c < 3; ++c) {
-        const double r0 = pose[4 * c + 0], r2 = pose[4 * c + 2], tc = pose[4 * c + 3];
+        const double r0 = pose[4 * c + 0], r1 = pose[4 * c + 1], r2 = pose[4 * c + 2], tc = pose[4 * c + 3];
         double u = r0 * a;
         u = tc + u;
+        const double v = r1 * elev;   // elevation offset (exactly 0 for a single plane)
+        u = u + v;
         u = u / s[c];
         u = u * 65536.0;
         double w = r0 * dx;

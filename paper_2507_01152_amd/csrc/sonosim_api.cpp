@@ -133,14 +133,27 @@ sg_status check_probe(const sg_probe& p, int idx)
     if (!pos(p.dx_mm) || !pos(p.dy_mm) || !pos(p.E0) || !pos(p.psf_frac) || !pos(p.dr_db) ||
         !std::isfinite(p.f_mhz) || p.f_mhz < 0.0)
         return fail(SG_EINVAL, "env %d: probe parameters must be finite and positive", idx);
+    if (p.n_elev < 0 || p.n_elev > SG_MAX_ELEV || (p.n_elev > 1 && !pos(p.elev_mm)))
+        return fail(SG_EINVAL, "env %d: n_elev in [0, %d] with elev_mm > 0 for several planes", idx, SG_MAX_ELEV);
     return SG_OK;
 }
 
+int probe_planes(const sg_probe& p) { return p.n_elev > 1 ? p.n_elev : 1; }
+
+double plane_elevation(const sg_probe& p, int j)
+{
+    if (probe_planes(p) == 1) return 0.0;
+    return ((double)j - 0.5 * (double)(p.n_elev - 1)) * p.elev_mm;
+}
+
 // Static (pose-independent) part of an environment's parameters.
-sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int64_t out_off, int64_t scr_off,
+sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int plane, int64_t out_off, int64_t scr_off,
                           std::vector<float>& pool, EnvDev& e)
 {
     std::memset(&e, 0, sizeof(e));
+    e.pose_env = idx;
+    e.plane = plane;
+    e.elev64 = plane_elevation(p, plane);
     e.W = p.W;
     e.H = p.H;
     e.vol = vol;
@@ -160,7 +173,7 @@ sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int64_t out_o
     e.dy64 = p.dy_mm;
     e.f64 = p.f_mhz;
     e.psf64 = p.psf_frac;
-    e.out_off = out_off;
+    e.out_off = out_off + (int64_t)plane * p.W * p.H;
     e.scr_off = scr_off;
     return SG_OK;
 }
@@ -418,7 +431,8 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
 {
     sg_status s = check_envs(c, n, vol_ids, probes);
     if (s != SG_OK) return s;
-    std::vector<EnvDev> envs(n);
+    // one internal env per image plane (volumetric probes have several)
+    std::vector<EnvDev> envs;
     std::vector<float> pool;
     int64_t scr = 0;
     int max_rlat = 0, max_px = 0, multiscale = 0;
@@ -426,23 +440,29 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
         for (int k = 0; k < 12; ++k)
             if (!std::isfinite(poses[12 * i + k])) return fail(SG_EINVAL, "env %d: pose is not finite", i);
         if (out_offsets[i] < 0) return fail(SG_EINVAL, "env %d: negative output offset", i);
-        s = fill_env_static(probes[i], vol_ids[i], i, out_offsets[i], scr, pool, envs[i]);
-        if (s != SG_OK) return s;
         const VolDev& v = c->vols[vol_ids[i]].dev;
         multiscale |= v.scales > 1;
-        envs[i].valid = plane_geometry(poses + 12 * i, v.sx, v.sy, v.sz, probes[i].W, probes[i].H,
-                                       probes[i].dx_mm, probes[i].dy_mm, envs[i].P0, envs[i].DX, envs[i].DY);
-        if (!envs[i].valid)
-            return fail(SG_ERANGE, "env %d: image plane outside the fixed-point range (|Q16| > 2^30)", i);
-        scr += (int64_t)probes[i].W * probes[i].H;
-        max_rlat = std::max(max_rlat, envs[i].rlat);
-        max_px = std::max(max_px, probes[i].W * probes[i].H);
+        for (int j = 0; j < probe_planes(probes[i]); ++j) {
+            EnvDev ed;
+            s = fill_env_static(probes[i], vol_ids[i], i, j, out_offsets[i], scr, pool, ed);
+            if (s != SG_OK) return s;
+            ed.valid = plane_geometry(poses + 12 * i, v.sx, v.sy, v.sz, probes[i].W, probes[i].H, probes[i].dx_mm,
+                                      probes[i].dy_mm, ed.elev64, ed.P0, ed.DX, ed.DY);
+            if (!ed.valid)
+                return fail(SG_ERANGE, "env %d plane %d: image plane outside the fixed-point range (|Q16| > 2^30)",
+                            i, j);
+            scr += (int64_t)probes[i].W * probes[i].H;
+            max_rlat = std::max(max_rlat, ed.rlat);
+            max_px = std::max(max_px, probes[i].W * probes[i].H);
+            envs.push_back(ed);
+        }
     }
+    const int n_int = (int)envs.size();
     s = sync_volumes(c);
     if (s != SG_OK) return s;
     // longest scanlines first (ray items cost ~H), then wider frames
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
+    std::vector<int> order(n_int);
+    for (int i = 0; i < n_int; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         if (envs[x].H != envs[y].H) return envs[x].H > envs[y].H;
         return envs[x].W > envs[y].W;

@@ -263,34 +263,39 @@ extern "C" sg_status sg_batch_plan_create(sg_ctx* c, int32_t n, const int32_t* v
     sg_status s = check_envs(c, n, vol_ids, probes);
     if (s != SG_OK) return s;
     std::unique_ptr<Plan> p(new Plan());
-    p->n_envs = n;
+    p->n_user = n;
     p->vol_ids.assign(vol_ids, vol_ids + n);
     p->probes.assign(probes, probes + n);
     p->out_offsets.assign(out_offsets, out_offsets + n);
-    p->envs.resize(n);
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n; ++i) {   // one internal env per image plane
         if (out_offsets[i] < 0) return fail(SG_EINVAL, "env %d: negative output offset", i);
-        s = fill_env_static(probes[i], vol_ids[i], i, out_offsets[i], p->n_pixels, p->pool, p->envs[i]);
-        if (s != SG_OK) return s;
-        p->n_pixels += (int64_t)probes[i].W * probes[i].H;
-        p->max_rax = std::max(p->max_rax, p->envs[i].rax);
-        p->max_rlat = std::max(p->max_rlat, p->envs[i].rlat);
+        for (int j = 0; j < probe_planes(probes[i]); ++j) {
+            EnvDev ed;
+            s = fill_env_static(probes[i], vol_ids[i], i, j, out_offsets[i], p->n_pixels, p->pool, ed);
+            if (s != SG_OK) return s;
+            p->n_pixels += (int64_t)probes[i].W * probes[i].H;
+            p->max_rax = std::max(p->max_rax, ed.rax);
+            p->max_rlat = std::max(p->max_rlat, ed.rlat);
+            p->envs.push_back(ed);
+        }
         p->multiscale |= c->vols[vol_ids[i]].dev.scales > 1;
     }
+    p->n_envs = (int32_t)p->envs.size();
+    const int ni = p->n_envs;
     // longest scanlines first (ray items cost ~H), then wider frames
-    p->order.resize(n);
-    for (int i = 0; i < n; ++i) p->order[i] = i;
+    p->order.resize(ni);
+    for (int i = 0; i < ni; ++i) p->order[i] = i;
     std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) {
         if (p->envs[a].H != p->envs[b].H) return p->envs[a].H > p->envs[b].H;
         return p->envs[a].W > p->envs[b].W;
     });
-    hipError_t e = p->d_envs.ensure(sizeof(EnvDev) * n);
+    hipError_t e = p->d_envs.ensure(sizeof(EnvDev) * ni);
     if (e == hipSuccess) e = p->d_pool.ensure(sizeof(float) * p->pool.size());
     if (e == hipSuccess) e = p->d_poses.ensure(sizeof(double) * 12 * n);
     if (e == hipSuccess) e = p->d_queue.ensure(sizeof(QueueDev) * kMaxChunks);
     if (e == hipSuccess) e = p->fields.ensure(sizeof(float) * 3 * (size_t)p->n_pixels);
     if (e != hipSuccess) return hip_fail(e, "plan allocation");
-    e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * n, hipMemcpyHostToDevice);
+    e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * ni, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_pool.p, p->pool.data(), sizeof(float) * p->pool.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->d_poses.p, 0, sizeof(double) * 12 * n);
@@ -316,7 +321,7 @@ extern "C" sg_status sg_batch_set_poses(sg_ctx* c, int32_t id, const double* hos
     Plan* p = c ? find_plan(c, id) : nullptr;
     if (!p || !host_poses) return fail(SG_EINVAL, "sg_batch_set_poses: bad plan id or NULL");
     (void)hipSetDevice(c->device);
-    const size_t bytes = sizeof(double) * 12 * (size_t)p->n_envs;
+    const size_t bytes = sizeof(double) * 12 * (size_t)p->n_user;
     hipError_t e = c->staging.acquire(bytes);
     if (e != hipSuccess) return hip_fail(e, "pinned staging");
     std::memcpy(c->staging.p, host_poses, bytes);
@@ -328,7 +333,7 @@ extern "C" sg_status sg_batch_set_poses(sg_ctx* c, int32_t id, const double* hos
 static sg_status step_checks(sg_ctx* c, Plan* p)
 {
     if (c->n_labels < 1) return fail(SG_ESTATE, "no tissue table set");
-    for (int i = 0; i < p->n_envs; ++i) {
+    for (int i = 0; i < p->n_user; ++i) {
         const HostVolume& v = c->vols[p->vol_ids[i]];
         if (!v.live) return fail(SG_ESTATE, "env %d: volume %d was released", i, p->vol_ids[i]);
         if (v.max_label >= c->n_labels) return fail(SG_EINVAL, "env %d: label outside the table", i);

@@ -387,9 +387,9 @@ sg_status adam(sg_ctx* c, Surrogate& s, float lr)
 sg_status check_frames(const Surrogate& s, int32_t n, const sg_probe* probes)
 {
     for (int i = 0; i < n; ++i)
-        if (probes[i].W != s.W || probes[i].H != s.H)
-            return fail(SG_EINVAL, "env %d: probe %dx%d, the surrogate renders %dx%d", i, probes[i].W, probes[i].H,
-                        s.W, s.H);
+        if (probes[i].W != s.W || probes[i].H != s.H || probes[i].n_elev > 1)
+            return fail(SG_EINVAL, "env %d: probe %dx%d (x%d planes), the surrogate renders one %dx%d plane", i,
+                        probes[i].W, probes[i].H, probes[i].n_elev, s.W, s.H);
     if (n > 65535) return fail(SG_EINVAL, "at most 65535 envs per call");
     return SG_OK;
 }

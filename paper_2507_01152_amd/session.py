@@ -64,11 +64,14 @@ class Session:
 
 
 def split_frames(flat: np.ndarray, workload, per_pixel: int = 1):
-    """Unpack a packed buffer into per-env [H][W] (or [H][W][k]) arrays."""
+    """Unpack a packed buffer into per-env [H][W] (or [H][W][k]) arrays;
+    volumetric probes give [E][H][W] (or [E][H][W][k])."""
     offs, _ = workload.out_offsets()
     res = []
     for o, p in zip(offs, workload.probes):
-        n = p.W * p.H
+        E = max(1, int(getattr(p, "n_elev", 1)))
+        n = p.W * p.H * E
         a = flat[per_pixel * o: per_pixel * (o + n)]
-        res.append(a.reshape((p.H, p.W) if per_pixel == 1 else (p.H, p.W, per_pixel)))
+        shape = (p.H, p.W) if per_pixel == 1 else (p.H, p.W, per_pixel)
+        res.append(a.reshape(((E,) if E > 1 else ()) + shape))
     return res

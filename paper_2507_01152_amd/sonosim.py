@@ -52,7 +52,7 @@ class sg_tissue(C.Structure):
 class sg_probe(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("dx_mm", C.c_double), ("dy_mm", C.c_double),
                 ("f_mhz", C.c_double), ("E0", C.c_double), ("psf_frac", C.c_double),
-                ("dr_db", C.c_double)]
+                ("dr_db", C.c_double), ("n_elev", C.c_int32), ("elev_mm", C.c_double)]
 
 
 class sg_conv_desc(C.Structure):
@@ -205,7 +205,7 @@ def probes_array(probes):
     arr = (sg_probe * len(probes))()
     for i, p in enumerate(probes):
         arr[i] = sg_probe(int(p.W), int(p.H), float(p.dx), float(p.dy), float(p.f), float(p.E0),
-                          float(p.psf), float(p.dr))
+                          float(p.psf), float(p.dr), int(getattr(p, "n_elev", 1)), float(getattr(p, "elev", 0.0)))
     return arr
 
 

@@ -65,6 +65,12 @@ class Probe:
     E0: float = 1.0  # initial energy
     psf: float = 0.01  # PSF std as a fraction of the image size
     dr: float = 60.0   # display dynamic range, dB
+    n_elev: int = 1    # planes of a volumetric probe
+    elev: float = 0.0  # plane spacing along the elevation, mm
+
+    @property
+    def planes(self) -> int:
+        return max(1, int(self.n_elev))
 
     def astuple(self):
         return (self.W, self.H, self.dx, self.dy, self.f, self.E0, self.psf, self.dr)
@@ -97,7 +103,7 @@ class Workload:
         return len(self.probes)
 
     def out_offsets(self):
-        sizes = np.array([p.W * p.H for p in self.probes], dtype=np.int64)
+        sizes = np.array([p.W * p.H * p.planes for p in self.probes], dtype=np.int64)
         offs = np.zeros(len(sizes), dtype=np.int64)
         if len(sizes) > 1:
             offs[1:] = np.cumsum(sizes)[:-1]
@@ -296,3 +302,12 @@ def batched_workload(seed: int = 0, n_envs: int = 256, n_vols: int = 8,
         probes.append(Probe(W=W, H=H))
         poses.append(spine_pose(g, d[1], rng))
     return Workload(vols, vol_ids, probes, np.stack(poses))
+
+
+def volumetric_workload(seed: int = 0, n_envs: int = 256, n_vols: int = 8) -> Workload:
+    """The uneven batch's volumes and probe poses with the surgery task's
+    volumetric probe: 37 scanlines x 50 depth samples at 2 mm, 5 elevation
+    planes 10 mm apart (H x W x E = 50 x 37 x 5 at 2 x 2 x 10 mm)."""
+    wl = batched_workload(seed=seed, n_envs=n_envs, n_vols=n_vols)
+    wl.probes = [Probe(W=37, H=50, dx=2.0, dy=2.0, n_elev=5, elev=10.0) for _ in range(n_envs)]
+    return wl

@@ -143,6 +143,29 @@ def test_set_config_rejects_bad_shapes(sess, uneven):
             sg.sg_batch_set_config(sess.ctx, plan, *bad)
 
 
+def test_volumetric_batch_equals_single_call_and_counts_envs(sess):
+    """A plan of volumetric probes (5 planes each) gives the single-call
+    frames bit for bit; a rejected pose zeroes all of its env's planes and
+    counts once."""
+    from paper_2507_01152_amd import sonosim as sg
+    from paper_2507_01152_amd.session import split_frames
+    wl = synth.volumetric_workload(seed=1, n_envs=6, n_vols=2)
+    vids = sess.load(wl)
+    one, offs, _ = sess.simulate(wl, vids)
+    out, plan = batch_frames(sess, wl, vids)
+    assert torch.equal(one, out)
+    poses = wl.poses.copy()
+    poses[4, 3] = 1e12
+    sg.sg_batch_set_poses(sess.ctx, plan, poses)
+    sg.sg_batch_step(sess.ctx, plan, out)
+    assert sg.sg_batch_status(sess.ctx, plan) == 1
+    frames = split_frames(out.cpu().numpy(), wl)
+    assert frames[4].shape == (5, 50, 37) and not frames[4].any()
+    ref = split_frames(one.cpu().numpy(), wl)
+    for e in (0, 1, 2, 3, 5):
+        assert np.array_equal(frames[e], ref[e])
+
+
 def test_out_of_range_pose_gives_zero_frame_and_status(sess):
     from paper_2507_01152_amd import sonosim as sg
     wl = synth.ellipsoid_workload(seed=3, n_envs=3)

@@ -504,3 +504,47 @@ def test_multiscale_noise_statistics(scales):
         assert abs(np.corrcoef(a, b)[0, 1] - shared / scales) < 0.03, (j, shared)
     # N1 sums S unit-variance quantised normals: mean 0, variance S
     assert abs(n1.mean()) < 0.05 * np.sqrt(scales) and abs(n1.var() / scales - 1.0) < 0.05
+
+
+# ---------------------------------------------------------------------------
+# volumetric probe: a stack of elevation planes (Sec. 4, surgery task)
+
+def test_volumetric_planes_are_numpy_slices_at_their_elevation():
+    """Axis-aligned probe with 5 planes 2 mm apart: plane j samples volume row
+    y = 3 + (j - 2) * 2 (probe y -> volume y), each a numpy slice."""
+    lab = _rand_labels((20, 13, 24), 8)
+    vol = Volume(labels=lab, seed=1)
+    probe = Probe(W=9, H=30, dx=1.0, dy=1.0, n_elev=5, elev=2.0)
+    o = oracle.simulate_env(vol, synth.default_tissue_table(), probe, axis_pose((10.0, 7.0, -2.0)),
+                            planes=("label", "voxel"))
+    assert o["label"].shape == (5, 30, 9)
+    for j in range(5):
+        iy = 7 + (j - 2) * 2
+        for y in range(30):
+            iz = -2 + y
+            for x in range(9):
+                ix = 6 + x
+                if 0 <= iz < 20:
+                    assert o["label"][j, y, x] == lab[iz, iy, ix]
+                    assert o["voxel"][j, y, x] == (iz * 13 + iy) * 24 + ix
+                else:
+                    assert o["label"][j, y, x] == 0
+
+
+def test_volumetric_centre_plane_is_the_linear_probe():
+    """An odd stack's centre plane has elevation 0 and is the linear probe's
+    image bit for bit; the other planes follow the rotated elevation axis."""
+    rng = np.random.default_rng(4)
+    vol = Volume(labels=synth.ellipsoid_volume(3), seed=9)
+    pose = synth.pose_from(synth.random_rotation(rng), (32.0, 30.0, 28.0))
+    lin = Probe(W=20, H=40)
+    vol3 = Probe(W=20, H=40, n_elev=3, elev=4.0)
+    a = oracle.simulate_env(vol, synth.default_tissue_table(), lin, pose, planes=("q", "label", "Y"))
+    b = oracle.simulate_env(vol, synth.default_tissue_table(), vol3, pose, planes=("q", "label", "Y"))
+    assert np.array_equal(b["q"][1], a["q"]) and np.array_equal(b["Y"][1], a["Y"])
+    # plane origins step by R (0, 4, 0) mm (in voxel Q16 units, within rounding)
+    R = pose.reshape(3, 4)[:, :3]
+    step = R @ np.array([0.0, 4.0, 0.0]) * 65536.0
+    for j in (0, 2):
+        d = (b["q"][j, 0, 0] - b["q"][1, 0, 0]).astype(np.float64)
+        assert np.all(np.abs(d - (j - 1) * step) <= 1.0)

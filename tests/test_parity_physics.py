@@ -108,6 +108,18 @@ def test_multiscale_noise_parity(sess, scales):
     check_all(sess, wl2, name=f"S={scales} odd")
 
 
+def test_volumetric_probe_parity(sess):
+    """Volumetric probe of the surgery task (50 x 37 x 5 at 2 x 2 x 10 mm):
+    every elevation plane against the oracle, on the spine phantom and on a
+    small volume where outer planes leave the grid."""
+    wl = synth.volumetric_workload(seed=2, n_envs=3, n_vols=1)
+    g = check_all(sess, wl, name="volumetric")
+    assert g[0]["Y"].shape == (5, 50, 37)
+    vol = Volume(labels=synth.ellipsoid_volume(5), seed=3)
+    wl2 = single_env(vol, Probe(W=30, H=60, n_elev=7, elev=9.0), axis_pose((32.0, 32.0, 2.0)))
+    check_all(sess, wl2, name="volumetric small")
+
+
 def test_gate_extremes_and_energy_scale(sess):
     table = synth.default_tissue_table().copy()
     table[1, 4] = np.inf     # soft tissue always scatters
