@@ -177,6 +177,8 @@ def main():
                     help="also time the workload with this many noise scales (<= 1 skips it)")
     ap.add_argument("--no-volumetric", dest="volumetric", action="store_false",
                     help="skip the volumetric-probe leg")
+    ap.add_argument("--no-recon", dest="recon", action="store_false",
+                    help="skip the reconstruction-observation leg")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle baseline sample (whole steps, at most 200)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -298,6 +300,28 @@ def main():
         res["multiscale_noise"] = {"noise_scales": args.noise_scales, "ms_per_step": round(ms_ms, 4),
                                    "frames_per_s": round(n / (ms_ms / 1e3), 1),
                                    "vs_one_scale": round(ms_per_step / ms_ms, 3)}
+    if args.recon:
+        # bone-surface reconstruction observation after each physics step (256 envs)
+        rid = sg.sg_recon_create(sess.ctx, plan, 65536, None, 0.2, seed=1)
+        grids = torch.zeros(n * 40 ** 3, dtype=torch.uint8, device=sess.device)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        upd, obs = [], []
+        for st in range(20):
+            ev[0].record(stream)
+            sg.sg_recon_update(sess.ctx, rid, st)
+            ev[1].record(stream)
+            sg.sg_recon_observe(sess.ctx, rid, grids)
+            ev[2].record(stream)
+            torch.cuda.synchronize()
+            upd.append(ev[0].elapsed_time(ev[1]))
+            obs.append(ev[1].elapsed_time(ev[2]))
+        stored, over = sg.sg_recon_counts(sess.ctx, rid, n)
+        res["recon_observation"] = {
+            "workload": "256 envs of the benchmark batch, 20 updates at one pose each, 40^3 grids at 3 mm",
+            "update_ms": round(float(np.median(upd)), 4), "observe_ms": round(float(np.median(obs)), 4),
+            "points_stored": int(stored.sum()), "points_overflow": int(over.sum()),
+            "occupied_cells": int(grids.sum().item())}
+        sg.sg_recon_destroy(sess.ctx, rid)
     if args.volumetric:
         # the surgery task's volumetric probe (50 x 37 x 5 at 2 x 2 x 10 mm) on the same volumes and poses
         vw = synth.volumetric_workload(seed=0)

@@ -253,6 +253,55 @@ sg_status sg_batch_set_config(sg_ctx* ctx, int32_t plan_id, int32_t scanlines_pe
 
 sg_status sg_batch_plan_destroy(sg_ctx* ctx, int32_t plan_id);
 
+/* ------------------------------------------------------------------------
+ * Reconstruction observation of the bone-surface task (Sec. 4, task 2:
+ * bone surface segmented from each frame with misses, accumulated into a
+ * reconstruction M and voxelised in the current probe frame; App. C: 40^3
+ * voxels of 3 mm, 20 % missing points).  Bound to a batch plan: it reads the
+ * plan's device geometry and poses of the step last enqueued, so its calls
+ * go on the same stream after sg_batch_step.
+ *   surface point   per scanline of each image plane, the first pixel whose
+ *                   nearest label is a bone label (the rest of the scanline is
+ *                   in the acoustic shadow)
+ *   miss            Philox4x32-10 (key = seed, counter = (x | plane << 16,
+ *                   env, step, 0x5245434F)): kept when word 0 <
+ *                   floor((1 - p_miss) * 2^32)
+ *   stored point    the pixel's probe point (a + x*dx, b, y*dy) mapped by the
+ *                   step's pose into volume mm, FP64
+ *   observation     each stored point u = R^T (p - t) in the current probe
+ *                   frame occupies cell (floor(u_z / 3), floor((u_x + 60) / 3),
+ *                   floor((u_y + 60) / 3)) of a [40][40][40] uint8 grid
+ *                   (depth, lateral, elevation), 1 = occupied.
+ */
+
+/* Create a reconstruction for the plan's envs.  capacity: stored points per
+ * env (further points are counted as overflow); bone_labels: host bitmap of
+ * 256 bytes (nonzero = bone), or NULL for label 3 only; p_miss in [0, 1].
+ * The plan must outlive the reconstruction's use.  Errors: SG_EINVAL. */
+sg_status sg_recon_create(sg_ctx* ctx, int32_t plan_id, int32_t capacity, const uint8_t* bone_labels,
+                          double p_miss, uint64_t seed, int32_t* recon_id);
+
+/* Add the surface points of the plan's current frames (step index `step`
+ * keys the misses).  Asynchronous on the context's stream. */
+sg_status sg_recon_update(sg_ctx* ctx, int32_t recon_id, int32_t step);
+
+/* Voxelise every env's stored points at the plan's current pose into grids:
+ * device, n_envs * 40^3 uint8, env-major.  Asynchronous. */
+sg_status sg_recon_observe(sg_ctx* ctx, int32_t recon_id, uint8_t* grids);
+
+/* Host copies (synchronising): per-env stored point counts and overflow
+ * (points beyond capacity); either pointer may be NULL. */
+sg_status sg_recon_counts(sg_ctx* ctx, int32_t recon_id, int64_t* stored, int64_t* overflow);
+
+/* Host copy (synchronising) of env `env`'s stored points, xyz doubles, at
+ * most max_points; *n receives the number copied.  Order is unspecified. */
+sg_status sg_recon_points(sg_ctx* ctx, int32_t recon_id, int32_t env, double* xyz, int64_t max_points, int64_t* n);
+
+/* Forget the stored points of all envs (env < 0) or of one env. */
+sg_status sg_recon_reset(sg_ctx* ctx, int32_t recon_id, int32_t env);
+
+sg_status sg_recon_destroy(sg_ctx* ctx, int32_t recon_id);
+
 
 /* ------------------------------------------------------------------------
  * Learned surrogate (a label-slice -> B-mode convolutional network trained on

@@ -87,6 +87,10 @@ def lib():
                                        C.POINTER(C.c_double), C.POINTER(C.c_float), C.c_void_p]
         L.or_scatter_voxel.restype = C.c_int
         L.or_scatter_grid.argtypes = [C.POINTER(_Volume), C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_recon_points.argtypes = [C.POINTER(_Volume), C.c_void_p, C.POINTER(_Probe), C.c_void_p, C.c_int32,
+                                      C.c_int32, C.c_int32, C.c_uint64, C.c_double, C.c_void_p]
+        L.or_recon_points.restype = C.c_int64
+        L.or_recon_observe.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.or_simulate_batch.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                         C.POINTER(C.c_int32)]
@@ -275,3 +279,31 @@ def simulate_batch(workload, env_ids=None, n_threads: int = 0):
         frames.append(f if E > 1 else f[0])
         k += E
     return frames, int(used.value)
+
+
+# ---------------------------------------------------------------------------
+# reconstruction observation (bone-surface task)
+
+def recon_points(vol, probe, pose, env: int, step: int, seed: int, p_drop: float = 0.2, bone_labels=(3,)):
+    """Kept bone-surface points of one frame (all planes), float64 [n, 3] in volume mm."""
+    vs, keep = _volume_struct(vol)
+    bone = np.zeros(256, dtype=np.uint8)
+    bone[list(bone_labels)] = 1
+    pose = np.ascontiguousarray(pose, dtype=np.float64)
+    out = []
+    for j in range(n_planes(probe)):
+        ps = _probe_struct(probe, j)
+        buf = np.zeros((probe.W, 3), dtype=np.float64)
+        n = lib().or_recon_points(C.byref(vs), bone.ctypes.data, C.byref(ps), pose.ctypes.data, j, int(env),
+                                  int(step), int(seed) & ((1 << 64) - 1), float(p_drop), buf.ctypes.data)
+        out.append(buf[:n])
+    return np.concatenate(out) if out else np.zeros((0, 3))
+
+
+def recon_observe(points, pose) -> np.ndarray:
+    """40^3 occupancy grid (depth, lateral, elevation) of points at a pose."""
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    pose = np.ascontiguousarray(pose, dtype=np.float64)
+    grid = np.zeros((40, 40, 40), dtype=np.uint8)
+    lib().or_recon_observe(pts.ctypes.data, pts.shape[0], pose.ctypes.data, grid.ctypes.data)
+    return grid

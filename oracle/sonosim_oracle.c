@@ -527,3 +527,91 @@ int or_simulate_batch(int32_t n_envs, const or_volume* vols, const int32_t* vol_
     if (threads_used) *threads_used = used;
     return err;
 }
+
+/* ------------------------------------------------------------------------
+ * Reconstruction observation (Sec. 4 task 2 "Bone surface reconstruction";
+ * App. C environment settings; readings):
+ *   R1 surface points of a frame: per scanline x of image plane j, the first
+ *      pixel (smallest depth y) whose nearest label is a bone label; pixels
+ *      below it lie in the acoustic shadow.
+ *   R2 segmentation misses each ground-truth point independently with
+ *      probability p: Philox4x32-10, key = reconstruction seed, counter =
+ *      (x | j << 16, env, step, 0x5245434F); the point is kept when word 0 <
+ *      floor((1 - p) * 2^32).
+ *   R3 a kept point is stored in volume mm: the pixel's probe point
+ *      (a + x*dx, b_j, y*dy) mapped by that step's pose, in FP64 with the
+ *      operation order written below (no contraction).
+ *   R4 observation at a pose: every stored point, moved into that pose's
+ *      probe frame (u = R^T (p - t)), falls in the 40^3 grid of 3 mm cells
+ *      indexed (depth floor(u_z / 3), lateral floor((u_x + 60) / 3),
+ *      elevation floor((u_y + 60) / 3)); occupied cells read 1.
+ */
+#define OR_RECON_TAG 0x5245434Fu
+
+/* R1-R3 for one plane; appends kept points (xyz triples) to pts, returns
+ * their number, -1 on bad labels. */
+int64_t or_recon_points(const or_volume* v, const uint8_t* bone, const or_probe* p, const double pose[12],
+                        int32_t plane, int32_t env, int32_t step, uint64_t seed, double p_drop, double* pts)
+{
+    int64_t P0[3], DX[3], DY[3];
+    or_geometry(v, p, pose, P0, DX, DY);
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    double keep = floor((1.0 - p_drop) * 4294967296.0);
+    int64_t n = 0;
+    for (int32_t x = 0; x < p->W; ++x) {
+        int32_t yb = -1;
+        for (int32_t y = 0; y < p->H && yb < 0; ++y) {
+            int64_t ix = floordiv(P0[0] + (int64_t)x * DX[0] + (int64_t)y * DY[0] + 32768, 65536);
+            int64_t iy = floordiv(P0[1] + (int64_t)x * DX[1] + (int64_t)y * DY[1] + 32768, 65536);
+            int64_t iz = floordiv(P0[2] + (int64_t)x * DX[2] + (int64_t)y * DY[2] + 32768, 65536);
+            int lab = 0;
+            if (ix >= 0 && iy >= 0 && iz >= 0 && ix < v->nx && iy < v->ny && iz < v->nz)
+                lab = v->labels[(iz * v->ny + iy) * v->nx + ix];
+            if (bone[lab]) yb = y;
+        }
+        if (yb < 0) continue;
+        const uint32_t ctr[4] = {(uint32_t)x | ((uint32_t)plane << 16), (uint32_t)env, (uint32_t)step, OR_RECON_TAG};
+        uint32_t w[4];
+        or_philox4x32_10(ctr, key, w);
+        if (!((double)w[0] < keep)) continue;
+        double a = -0.5 * (double)(p->W - 1);
+        a = a * p->dx;
+        double px = (double)x * p->dx;
+        px = a + px;
+        double pz = (double)yb * p->dy;
+        for (int c = 0; c < 3; ++c) {
+            double s = pose[4 * c + 0] * px;
+            double e = pose[4 * c + 1] * p->elev;
+            s = s + e;
+            double z = pose[4 * c + 2] * pz;
+            s = s + z;
+            s = s + pose[4 * c + 3];
+            pts[3 * n + c] = s;
+        }
+        ++n;
+    }
+    return n;
+}
+
+/* R4: occupancy grid [40][40][40] (depth, lateral, elevation) of n points. */
+void or_recon_observe(const double* pts, int64_t n, const double pose[12], uint8_t* grid)
+{
+    memset(grid, 0, 40 * 40 * 40);
+    for (int64_t k = 0; k < n; ++k) {
+        double d[3], u[3];
+        for (int c = 0; c < 3; ++c) d[c] = pts[3 * k + c] - pose[4 * c + 3];
+        for (int a = 0; a < 3; ++a) {   /* u_a = column a of R dotted with d */
+            double s = pose[0 * 4 + a] * d[0];
+            double s1 = pose[1 * 4 + a] * d[1];
+            s = s + s1;
+            double s2 = pose[2 * 4 + a] * d[2];
+            s = s + s2;
+            u[a] = s;
+        }
+        double fh = floor(u[2] / 3.0);
+        double fw = floor((u[0] + 60.0) / 3.0);
+        double fe = floor((u[1] + 60.0) / 3.0);
+        if (fh >= 0.0 && fh < 40.0 && fw >= 0.0 && fw < 40.0 && fe >= 0.0 && fe < 40.0)
+            grid[((int)fh * 40 + (int)fw) * 40 + (int)fe] = 1;
+    }
+}

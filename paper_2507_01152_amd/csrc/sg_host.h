@@ -82,6 +82,10 @@ struct Surrogate;   // surrogate.cpp
 struct SurrogateDeleter {
     void operator()(Surrogate* p) const;
 };
+struct Recon;       // recon.hip
+struct ReconDeleter {
+    void operator()(Recon* p) const;
+};
 }  // namespace sg
 
 struct sg_ctx {
@@ -102,6 +106,8 @@ struct sg_ctx {
     int32_t next_plan = 1;
     std::map<int32_t, std::unique_ptr<sg::Surrogate, sg::SurrogateDeleter>> surrogates;
     int32_t next_surr = 1;
+    std::map<int32_t, std::unique_ptr<sg::Recon, sg::ReconDeleter>> recons;
+    int32_t next_recon = 1;
     sg::DevBuf op_wt, op_fine, op_parts;   // workspaces of the conv op entry points
 };
 
@@ -130,5 +136,6 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
 sg_status launch_physics(sg_ctx* c, const PhysArgs& a, const StageInfo& info);
 sg_status check_envs(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_probe* probes);
 void surrogate_release_all(sg_ctx* c);
+void recon_release_all(sg_ctx* c);
 
 }  // namespace sg

@@ -264,6 +264,7 @@ extern "C" sg_status sg_destroy(sg_ctx* c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     surrogate_release_all(c);
+    recon_release_all(c);
     delete c;
     return SG_OK;
 }

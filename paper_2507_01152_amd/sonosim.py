@@ -25,6 +25,8 @@ SYMBOLS = (
     "sg_batch_plan_create", "sg_batch_poses", "sg_batch_set_poses", "sg_batch_step",
     "sg_batch_step_profiled", "sg_batch_status", "sg_autotune",
     "sg_batch_config", "sg_batch_set_config", "sg_batch_plan_destroy",
+    "sg_recon_create", "sg_recon_update", "sg_recon_observe", "sg_recon_counts", "sg_recon_points",
+    "sg_recon_reset", "sg_recon_destroy",
     "sg_conv_forward", "sg_conv_backward_data", "sg_conv_backward_weight",
     "sg_surr_create", "sg_surr_destroy", "sg_surr_num_params", "sg_surr_train_step", "sg_surr_infer",
     "sg_audit_decide", "sg_surr_save", "sg_surr_load", "sg_surr_get_params", "sg_surr_get_grads",
@@ -98,6 +100,13 @@ def load():
         "sg_autotune": [VP, I32, C.c_char_p],
         "sg_batch_config": [VP, I32, P(I32), P(I32), P(I32), P(I32)],
         "sg_batch_set_config": [VP, I32, I32, I32, I32],
+        "sg_recon_create": [VP, I32, I32, VP, C.c_double, C.c_uint64, P(I32)],
+        "sg_recon_update": [VP, I32, I32],
+        "sg_recon_observe": [VP, I32, VP],
+        "sg_recon_counts": [VP, I32, VP, VP],
+        "sg_recon_points": [VP, I32, I32, VP, C.c_int64, P(C.c_int64)],
+        "sg_recon_reset": [VP, I32, I32],
+        "sg_recon_destroy": [VP, I32],
         "sg_batch_plan_destroy": [VP, I32],
         "sg_conv_forward": [VP, P(sg_conv_desc), VP, VP, VP, I32, VP, VP, VP, VP],
         "sg_conv_backward_data": [VP, P(sg_conv_desc), VP, VP, VP, I32],
@@ -399,3 +408,50 @@ def sg_surr_get_batch(ctx, sid, n, H, W):
     y = np.zeros((n, H, W), dtype=np.float32)
     _check(load().sg_surr_get_batch(ctx, int(sid), x.ctypes.data, y.ctypes.data), "sg_surr_get_batch")
     return x, y
+
+
+# ---------------------------------------------------------------------------
+# reconstruction observation (bone-surface task)
+
+def sg_recon_create(ctx, plan_id: int, capacity: int, bone_labels=None, p_miss: float = 0.2, seed: int = 0) -> int:
+    """bone_labels: iterable of label values (None: label 3)."""
+    bone = None
+    if bone_labels is not None:
+        bone = np.zeros(256, dtype=np.uint8)
+        bone[list(bone_labels)] = 1
+    rid = C.c_int32()
+    _check(load().sg_recon_create(ctx, int(plan_id), int(capacity), None if bone is None else bone.ctypes.data,
+                                  float(p_miss), int(seed) & ((1 << 64) - 1), C.byref(rid)), "sg_recon_create")
+    return int(rid.value)
+
+
+def sg_recon_update(ctx, recon_id: int, step: int):
+    _check(load().sg_recon_update(ctx, int(recon_id), int(step)), "sg_recon_update")
+
+
+def sg_recon_observe(ctx, recon_id: int, grids):
+    """grids: device uint8 tensor of n_envs * 40^3 elements."""
+    _check(load().sg_recon_observe(ctx, int(recon_id), _dptr(grids)), "sg_recon_observe")
+
+
+def sg_recon_counts(ctx, recon_id: int, n_envs: int):
+    stored = np.zeros(n_envs, dtype=np.int64)
+    over = np.zeros(n_envs, dtype=np.int64)
+    _check(load().sg_recon_counts(ctx, int(recon_id), stored.ctypes.data, over.ctypes.data), "sg_recon_counts")
+    return stored, over
+
+
+def sg_recon_points(ctx, recon_id: int, env: int, max_points: int) -> np.ndarray:
+    buf = np.zeros((max(1, max_points), 3), dtype=np.float64)
+    n = C.c_int64()
+    _check(load().sg_recon_points(ctx, int(recon_id), int(env), buf.ctypes.data, int(max_points), C.byref(n)),
+           "sg_recon_points")
+    return buf[:n.value].copy()
+
+
+def sg_recon_reset(ctx, recon_id: int, env: int = -1):
+    _check(load().sg_recon_reset(ctx, int(recon_id), int(env)), "sg_recon_reset")
+
+
+def sg_recon_destroy(ctx, recon_id: int):
+    _check(load().sg_recon_destroy(ctx, int(recon_id)), "sg_recon_destroy")

@@ -548,3 +548,67 @@ def test_volumetric_centre_plane_is_the_linear_probe():
     for j in (0, 2):
         d = (b["q"][j, 0, 0] - b["q"][1, 0, 0]).astype(np.float64)
         assert np.all(np.abs(d - (j - 1) * step) <= 1.0)
+
+
+# ---------------------------------------------------------------------------
+# reconstruction observation (bone-surface task)
+
+def test_recon_surface_points_of_a_bone_slab_closed_form():
+    """Bone (label 3) below z = 20 mm under soft tissue: every scanline's
+    first bone pixel is row 20 (1 mm pixels from z = 0), so without misses the
+    points lie at (x0 + a + x, y0, 20) mm."""
+    vol = layered_volume(64, 64, 64, [(0, 1), (20, 3), (40, 1)])
+    probe = Probe(W=31, H=50, dx=1.0, dy=1.0)
+    pts = oracle.recon_points(vol, probe, axis_pose((32.0, 30.0, 0.0)), env=0, step=0, seed=5, p_drop=0.0)
+    assert pts.shape == (31, 3)
+    a = -0.5 * 30
+    assert np.array_equal(pts[:, 0], 32.0 + a + np.arange(31.0))
+    assert np.all(pts[:, 1] == 30.0) and np.all(pts[:, 2] == 20.0)
+    # no bone in the image: no points
+    assert oracle.recon_points(vol, Probe(W=8, H=15), axis_pose((32.0, 30.0, 0.0)), 0, 0, 5, 0.0).shape == (0, 3)
+
+
+def test_recon_misses_points_with_the_stated_probability():
+    vol = layered_volume(64, 64, 64, [(0, 1), (10, 3)])
+    probe = Probe(W=1024, H=30, dx=0.05, dy=1.0)
+    kept = [oracle.recon_points(vol, probe, axis_pose((32.0, 32.0, 0.0)), env=e, step=s, seed=9).shape[0]
+            for e in range(4) for s in range(5)]
+    frac = np.sum(kept) / (1024.0 * 20)
+    assert abs(frac - 0.8) < 4 * np.sqrt(0.16 / (1024 * 20))
+    a = oracle.recon_points(vol, probe, axis_pose((32.0, 32.0, 0.0)), env=1, step=2, seed=9)
+    b = oracle.recon_points(vol, probe, axis_pose((32.0, 32.0, 0.0)), env=1, step=2, seed=9)
+    c = oracle.recon_points(vol, probe, axis_pose((32.0, 32.0, 0.0)), env=1, step=3, seed=9)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_recon_observation_cells_closed_form():
+    """Probe frame = volume frame shifted by t: a point at probe-frame (u_x,
+    u_y, u_z) occupies cell (floor(u_z/3), floor((u_x+60)/3), floor((u_y+60)/3));
+    points outside the 120 mm cube leave the grid empty."""
+    t = np.array([10.0, -4.0, 7.0])
+    pose = axis_pose(tuple(t))
+    u = np.array([[0.0, 0.0, 0.0], [-59.9, 59.9, 119.9], [1.5, -1.5, 4.5], [0.0, 0.0, 120.0], [-60.1, 0.0, 3.0],
+                  [0.0, 0.0, -0.1]])
+    g = oracle.recon_observe(u + t, pose)
+    expect = np.zeros((40, 40, 40), dtype=np.uint8)
+    for ux, uy, uz in u[:3]:
+        expect[int(np.floor(uz / 3)), int(np.floor((ux + 60) / 3)), int(np.floor((uy + 60) / 3))] = 1
+    assert np.array_equal(g, expect) and g.sum() == 3
+    # a rotated probe: points acquired and observed at the same pose land at
+    # their pixel's depth and lateral cells; the image plane (elevation 0 up
+    # to rounding) lies on the boundary of elevation cells 19 and 20
+    rng = np.random.default_rng(2)
+    vol = layered_volume(64, 64, 64, [(0, 1), (20, 3)])
+    R = synth.random_rotation(rng)
+    pose = synth.pose_from(R, (32.0, 32.0, 0.0))
+    probe = Probe(W=40, H=60, dx=1.0, dy=1.0)
+    pts = oracle.recon_points(vol, probe, pose, 0, 0, 1, p_drop=0.0)
+    g = oracle.recon_observe(pts, pose)
+    uu = (pts - pose.reshape(3, 4)[:, 3]) @ R     # rows: R^T (p - t)
+    assert np.allclose(uu[:, 1], 0.0, atol=1e-9)
+
+    def cells(v):   # cells a coordinate may fall in (both neighbours on a boundary)
+        return sorted({int(np.floor(v - 1e-9)), int(np.floor(v + 1e-9))})
+    for ux, uy, uz in uu:
+        assert any(g[h, w, e] for h in cells(uz / 3) for w in cells((ux + 60) / 3) for e in cells((uy + 60) / 3))
+    assert g[:, :, :19].sum() == 0 and g[:, :, 21:].sum() == 0
