@@ -260,3 +260,74 @@ def adam_update(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# CT-conditioned input (the learning-based simulator translates CT slices,
+# Sec. 4 "Ultrasound simulation"; readings):
+#   channel 0  nearest-voxel HU of the pixel (air, -1000 HU, outside the
+#              volume) after histogram matching to a reference: the frame's
+#              bins b = clip(HU + 1024, 0, 4095) map to the smallest reference
+#              bin r with refC[r] * n_src >= srcC[b] * n_ref (C: inclusive
+#              cumulative counts; exact integers), value (r - 1024) / 1000
+#   channel 1  N0 of the voxel's noise draw (Box-Muller of its Philox words,
+#              not gated); 0 outside
+#   channel 2  N1 as the quantised normal Q[w2 >> 20]; 0 outside
+#   channel 3  depth (y + 0.5) / H
+# all bf16; channels 4..7 zero.
+
+CT_BINS = 4096
+
+
+def ct_bins(vol, probe, pose):
+    """Histogram bins of the frame's nearest-voxel HU, [H][W] int64."""
+    import oracle as _or
+    o = _or.simulate_env(vol, _unit_table(vol), probe, pose, planes=("voxel",))
+    vox = o["voxel"]
+    hu = np.full(vox.shape, -1000, dtype=np.int64)
+    inside = vox >= 0
+    hu[inside] = np.asarray(vol.ct).ravel()[vox[inside]].astype(np.int64)
+    return np.clip(hu + 1024, 0, CT_BINS - 1)
+
+
+def _unit_table(vol):
+    n = int(np.asarray(vol.labels).max()) + 1
+    t = np.zeros((max(n, 1), 5), dtype=np.float32)
+    t[:, 0] = 1.0
+    return t
+
+
+def ct_histogram(bins) -> np.ndarray:
+    return np.bincount(np.asarray(bins).ravel(), minlength=CT_BINS).astype(np.int64)
+
+
+def histogram_match_lut(src_hist, ref_hist) -> np.ndarray:
+    """Bin map of histogram specification: lut[b] = smallest r with
+    refC[r] * n_src >= srcC[b] * n_ref (exact in int64)."""
+    sc = np.cumsum(np.asarray(src_hist, dtype=np.int64))
+    rc = np.cumsum(np.asarray(ref_hist, dtype=np.int64))
+    ns, nr = int(sc[-1]), int(rc[-1])
+    return np.searchsorted(rc * ns, sc * nr, side="left").astype(np.int64)
+
+
+def ct_input(vol, probe, pose, ref_hist) -> np.ndarray:
+    """The 8-channel bf16 input of one frame (values as float64), [H][W][8]."""
+    import oracle as _or
+    o = _or.simulate_env(vol, _unit_table(vol), probe, pose, planes=("voxel", "philox"))
+    vox, w = o["voxel"], o["philox"].astype(np.uint64)
+    bins = ct_bins(vol, probe, pose)
+    lut = histogram_match_lut(ct_histogram(bins), ref_hist)
+    x = np.zeros(vox.shape + (8,))
+    ct = (lut[bins] - 1024).astype(np.float32) / np.float32(1000.0)
+    x[..., 0] = bf16_round(ct)
+    inside = vox >= 0
+    u0 = (2.0 * (w[..., 0] >> 9).astype(np.float64) + 1.0) / 16777216.0
+    u1 = (2.0 * (w[..., 1] >> 9).astype(np.float64) + 1.0) / 16777216.0
+    n0 = np.sqrt(-2.0 * np.log(u0)) * np.cos(2.0 * np.pi * u1)
+    q = _or.quantised_normal_table()
+    n1 = q[(w[..., 2] >> 20).astype(np.int64)].astype(np.float64)
+    x[..., 1] = np.where(inside, bf16_round(n0), 0.0)
+    x[..., 2] = np.where(inside, bf16_round(n1), 0.0)
+    H = probe.H
+    x[..., 3] = bf16_round(((np.arange(H) + 0.5) / H)[:, None] * np.ones(vox.shape[1]))
+    return x

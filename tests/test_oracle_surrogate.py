@@ -149,3 +149,51 @@ def test_depth_integral_reaches_the_output_from_above_only():
     a2 = so.SCAN_SCALE * so.depth_sum_above(p2)
     assert np.array_equal(a2[:, :21], a[:, :21])
     assert np.allclose(a2[:, 21:] - a[:, 21:], so.SCAN_SCALE)
+
+
+def test_histogram_matching_lut_pins():
+    """Histogram specification: identical histograms map every occupied bin to
+    itself; a shifted histogram maps back by the shift; the matched frame's
+    cumulative counts never fall below the reference's at the mapped bins."""
+    rng = np.random.default_rng(8)
+    h = np.bincount(rng.integers(100, 900, 5000), minlength=so.CT_BINS)
+    lut = so.histogram_match_lut(h, h)
+    occ = np.nonzero(h)[0]
+    assert np.array_equal(lut[occ], occ)
+    shifted = np.roll(h, 37)
+    lut2 = so.histogram_match_lut(shifted, h)
+    assert np.array_equal(lut2[occ + 37], occ)
+    # monotone, and exact in integers for arbitrary totals
+    src = np.bincount(rng.integers(0, 4096, 777), minlength=so.CT_BINS)
+    lut3 = so.histogram_match_lut(src, h)
+    assert np.all(np.diff(lut3) >= 0)
+    sc, rc = np.cumsum(src), np.cumsum(h)
+    for b in range(0, 4096, 97):
+        r = lut3[b]
+        assert rc[r] * sc[-1] >= sc[b] * rc[-1]
+        assert r == 0 or rc[r - 1] * sc[-1] < sc[b] * rc[-1]
+
+
+def test_ct_input_channels():
+    """CT input of an axis-aligned frame over a CT volume: channel 0 equals the
+    matched nearest HU / 1000 (here matched to the frame's own histogram, so
+    unchanged), channels 1-2 the voxel's noise draws, channel 3 the depth."""
+    import synth
+    from cases import axis_pose
+    rng = np.random.default_rng(3)
+    lab = np.ones((30, 20, 25), dtype=np.uint8)
+    lab[15:] = 3
+    ct = synth.ct_from_labels(lab, 5)
+    vol = synth.Volume(labels=lab, ct=ct, seed=11)
+    probe = synth.Probe(W=12, H=40, dx=1.0, dy=1.0)
+    pose = axis_pose((12.0, 9.0, 0.0))
+    bins = so.ct_bins(vol, probe, pose)
+    x = so.ct_input(vol, probe, pose, so.ct_histogram(bins))
+    # pixel (x, y) lies at volume mm (6.5 + x, 9, y): nearest voxel (7 + x, 9, y), rounding half up
+    hu = np.full((40, 12), -1000, dtype=np.int64)
+    hu[:30] = ct[:30, 9, 7:19]
+    expect0 = so.bf16_round((np.clip(hu + 1024, 0, 4095) - 1024).astype(np.float32) / np.float32(1000.0))
+    assert np.array_equal(x[..., 0], expect0)
+    assert np.all(x[30:, :, 1:3] == 0) and np.all(x[..., 4:] == 0)
+    assert abs(x[:30, :, 1].std() - 1.0) < 0.3 and abs(x[:30, :, 2].std() - 1.0) < 0.3
+    assert np.array_equal(x[:, 0, 3], so.bf16_round((np.arange(40) + 0.5) / 40))
