@@ -354,6 +354,34 @@ sg_status sg_conv_backward_weight(sg_ctx* ctx, const sg_conv_desc* d, const uint
 sg_status sg_surr_create(sg_ctx* ctx, int32_t H, int32_t W, uint64_t seed, int32_t* surr_id);
 sg_status sg_surr_destroy(sg_ctx* ctx, int32_t surr_id);
 
+/* CT-conditioned surrogate: the learning-based simulator translates CT slices
+ * into B-mode images, and its input CT is histogram-matched to a set of
+ * training CT images (Sec. 4, "Ultrasound simulation"; App. B.2, learning-based
+ * approach).  Same network and training calls as sg_surr_create; the input
+ * per pixel is (bf16, 8 channels):
+ *   0  the nearest voxel's HU (-1000 outside the volume), binned b =
+ *      clamp(HU + 1024, 0, 4095), mapped through the frame's histogram
+ *      specification r(b) = the smallest bin with refC[r] * n_src >=
+ *      srcC[b] * n_ref (inclusive cumulative counts of the reference and of
+ *      the frame, compared exactly in 64-bit integers), as (r - 1024) / 1000;
+ *   1  N0 of the voxel's noise draw (not gated), 0 outside;
+ *   2  N1 of the draw as the quantised normal of sg_noise_quantiles
+ *      (entry w2 >> 20), 0 outside;
+ *   3  depth (y + 0.5) / H;  4..7 zero.
+ * Every volume it reads must carry a CT (SG_EINVAL otherwise), and the
+ * reference must be set (SG_ESTATE otherwise).  adv_weight: weight of the
+ * adversarial term of the training loss, in [0, 1]; 0 trains with L1 only.
+ * Checkpoints of CT surrogates also hold the reference counts. */
+sg_status sg_surr_create_ct(sg_ctx* ctx, int32_t H, int32_t W, uint64_t seed, float adv_weight, int32_t* surr_id);
+
+/* Sets the reference of a CT surrogate's histogram matching: the pooled bin
+ * counts of n_envs frames (H x W probes, one plane) of CT volumes at the given
+ * poses.  hist (host, 4096 int64, may be NULL) receives the counts.
+ * Synchronises.  Errors: SG_EINVAL (not a CT surrogate, sizes, a volume
+ * without CT), SG_ERANGE (a pose outside the fixed-point range). */
+sg_status sg_surr_set_ct_reference(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, const int32_t* vol_ids,
+                                   const sg_probe* probes, const double* poses, int64_t* hist);
+
 /* Number of parameters (FP32 masters: weights then bias, layer by layer). */
 sg_status sg_surr_num_params(sg_ctx* ctx, int32_t surr_id, int64_t* n);
 

@@ -766,6 +766,138 @@ __global__ __launch_bounds__(kThreads) void k_encode(PhysArgs a, uint16_t* enc)
     }
 }
 
+// CT-conditioned surrogate input.  Histogram bin of a pixel: its nearest
+// voxel's HU (-1000 outside the volume) + 1024, clamped to [0, 4095].
+__device__ __forceinline__ int ct_bin(const EnvDev& e, const VolDev& v, int x, int y, int32_t& vox)
+{
+    vox = voxel_at(e, v, x, y);
+    const int hu = (vox >= 0 && v.ct) ? (int)v.ct[vox] : -1000;
+    return min(max(hu + 1024, 0), kCtBins - 1);
+}
+
+// per-frame histograms of the bins: hist [n_envs][kCtBins], zeroed by the caller
+__global__ __launch_bounds__(kThreads) void k_ct_hist(PhysArgs a, uint32_t* hist)
+{
+    __shared__ uint32_t h[kCtBins];
+    const int env = blockIdx.y;
+    const EnvDev e = a.envs[env];
+    const VolDev v = a.vols[e.vol];
+    for (int i = threadIdx.x; i < kCtBins; i += kThreads) h[i] = 0u;
+    __syncthreads();
+    const int npx = e.W * e.H;
+    for (int p = blockIdx.x * kThreads + threadIdx.x; p < npx; p += gridDim.x * kThreads) {
+        const int y = p / e.W, x = p - y * e.W;
+        int32_t vox;
+        const int b = e.valid ? ct_bin(e, v, x, y, vox) : 1024 - 1000;
+        atomicAdd(&h[b], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kCtBins; i += kThreads)
+        if (h[i]) atomicAdd(&hist[(int64_t)env * kCtBins + i], h[i]);
+}
+
+// histogram specification per frame: lut[b] = smallest r with
+// refC[r] * n_src >= srcC[b] * n_ref (inclusive cumulative counts, int64)
+__global__ __launch_bounds__(kThreads) void k_ct_lut(const uint32_t* hist, const long long* ref_cum, long long n_ref,
+                                                     uint16_t* lut)
+{
+    constexpr int kPer = kCtBins / kThreads;   // 16 bins per thread
+    __shared__ long long part[kThreads];
+    const int env = blockIdx.x;
+    const uint32_t* h = hist + (int64_t)env * kCtBins;
+    long long c[kPer];
+    long long run = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        run += h[threadIdx.x * kPer + i];
+        c[i] = run;
+    }
+    part[threadIdx.x] = run;
+    __syncthreads();
+    for (int d = 1; d < kThreads; d <<= 1) {   // inclusive scan of the thread totals
+        const long long t = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const long long before = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+    const long long n_src = part[kThreads - 1];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const long long goal = (before + c[i]) * n_ref;
+        int lo = 0, hi = kCtBins - 1;   // smallest r with ref_cum[r] * n_src >= goal (ref_cum[4095] = n_ref)
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ref_cum[mid] * n_src >= goal)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        lut[(int64_t)env * kCtBins + threadIdx.x * kPer + i] = (uint16_t)lo;
+    }
+}
+
+// pooled reference of the histogram matching: ref_hist[b] = sum over the n
+// frames' histograms, ref_cum its inclusive cumulative counts (one block)
+__global__ __launch_bounds__(kThreads) void k_ct_ref(const uint32_t* hist, int n, long long* ref_hist,
+                                                     long long* ref_cum)
+{
+    constexpr int kPer = kCtBins / kThreads;
+    __shared__ long long part[kThreads];
+    long long c[kPer];
+    long long run = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int b = threadIdx.x * kPer + i;
+        long long t = 0;
+        for (int f = 0; f < n; ++f) t += hist[(int64_t)f * kCtBins + b];
+        ref_hist[b] = t;
+        run += t;
+        c[i] = run;
+    }
+    part[threadIdx.x] = run;
+    __syncthreads();
+    for (int d = 1; d < kThreads; d <<= 1) {
+        const long long t = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const long long before = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) ref_cum[threadIdx.x * kPer + i] = before + c[i];
+}
+
+// 8 bf16 channels per pixel: matched CT / 1000, N0 and N1 (quantised) of the
+// voxel's noise draw (0 outside), depth (y + 0.5) / H, zeros
+__global__ __launch_bounds__(kThreads) void k_encode_ct(PhysArgs a, const uint16_t* lut, uint16_t* enc)
+{
+    const int env = blockIdx.y;
+    const EnvDev e = a.envs[env];
+    const VolDev v = a.vols[e.vol];
+    const int npx = e.W * e.H;
+    for (int p = blockIdx.x * kThreads + threadIdx.x; p < npx; p += gridDim.x * kThreads) {
+        const int y = p / e.W, x = p - y * e.W;
+        int32_t vox = -1;
+        const int b = e.valid ? ct_bin(e, v, x, y, vox) : 1024 - 1000;
+        const int r = (int)lut[(int64_t)env * kCtBins + b];
+        const float ct = (float)(r - 1024) / 1000.f;
+        float n0 = 0.f, n1 = 0.f;
+        if (vox >= 0) {
+            uint32_t w[4];
+            philox4x32_10((uint32_t)vox, v.key0, v.key1, w);
+            n0 = box_muller(w[0], w[1]);
+            n1 = a.q_lut[w[2] >> 20];
+        }
+        uint4 o;
+        o.x = (uint32_t)f2bf16(ct) | ((uint32_t)f2bf16(n0) << 16);
+        o.y = (uint32_t)f2bf16(n1) | ((uint32_t)f2bf16(((float)y + 0.5f) / (float)e.H) << 16);
+        o.z = 0u;
+        o.w = 0u;
+        reinterpret_cast<uint4*>(enc)[e.out_off + p] = o;
+    }
+}
+
 __global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int n, QueueDev* q)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -869,6 +1001,29 @@ hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tx, int grid, hipStrea
         hipLaunchKernelGGL(k_psf<64>, dim3(grid), dim3(psf_threads(64)), lds, s, a, q);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_ct_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, uint32_t* hist,
+                            const long long* ref_cum, long long n_ref, uint16_t* lut, uint16_t* enc, hipStream_t s)
+{
+    if (n_envs <= 0) return hipSuccess;
+    int bx = (max_pixels + kThreads - 1) / kThreads;
+    if (bx > 64) bx = 64;
+    hipError_t e = hipMemsetAsync(hist, 0, sizeof(uint32_t) * kCtBins * (size_t)n_envs, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ct_hist, dim3(bx, n_envs), dim3(kThreads), 0, s, a, hist);
+    if ((e = hipGetLastError()) != hipSuccess || !enc) return e;
+    hipLaunchKernelGGL(k_ct_lut, dim3(n_envs), dim3(kThreads), 0, s, hist, ref_cum, n_ref, lut);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_encode_ct, dim3(bx, n_envs), dim3(kThreads), 0, s, a, lut, enc);
+    return hipGetLastError();
+}
+
+hipError_t launch_ct_reference(const uint32_t* hist, int32_t n_envs, long long* ref_hist, long long* ref_cum,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ct_ref, dim3(1), dim3(kThreads), 0, s, hist, n_envs, ref_hist, ref_cum);
     return hipGetLastError();
 }
 

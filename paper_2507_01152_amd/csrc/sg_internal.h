@@ -21,6 +21,7 @@ struct VolDev {
 };
 
 constexpr int kNoiseQ = 4096;   // entries of the quantised normal (w2 >> 20)
+constexpr int kCtBins = 4096;   // HU histogram bins of the CT-conditioned surrogate input (HU + 1024)
 constexpr int kMaxNoiseScales = 4;
 
 struct TissueDev {
@@ -162,6 +163,13 @@ hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tile_x, int grid, hipS
 hipError_t launch_max_label(const uint8_t* labels, int64_t n, int32_t* d_out, hipStream_t s);
 // surrogate input encoding of every pixel of n_envs frames (8 bf16 per pixel)
 hipError_t launch_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, uint16_t* enc, hipStream_t s);
+// CT-conditioned input: per-frame HU histograms (hist, n_envs x kCtBins), and when enc is given the
+// matched-histogram maps (lut, n_envs x kCtBins) against the reference cumulative counts and the encoding
+hipError_t launch_ct_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, uint32_t* hist,
+                            const long long* ref_cum, long long n_ref, uint16_t* lut, uint16_t* enc, hipStream_t s);
+// pooled reference histogram of n_envs per-frame histograms (int64 counts and inclusive cumulative counts)
+hipError_t launch_ct_reference(const uint32_t* hist, int32_t n_envs, long long* ref_hist, long long* ref_cum,
+                               hipStream_t s);
 size_t psf_lds_bytes(int tile_x, int max_rlat);
 bool psf_tile_supported(int tile_x);
 int ray_grid(int n_cu, bool multiscale);                              // resident ray workgroups

@@ -62,6 +62,12 @@ struct Surrogate {
     int cap = 0, cap_grad = 0, last_n = 0;
     DevBuf act[kNumT], gact[kNumT];
     DevBuf dpre, fine, parts, yhat, target, gy, loss, psnr, idx;
+    // CT-conditioned input: per-frame histograms and matching maps, the reference
+    // (kCtBins int64 counts, then their inclusive cumulative counts) and its total
+    bool ct = false;
+    float adv_weight = 0.f;
+    DevBuf ct_hist, ct_lut, ct_ref;
+    long long ct_n_ref = 0;
 };
 
 void SurrogateDeleter::operator()(Surrogate* p) const { delete p; }
@@ -394,17 +400,39 @@ sg_status check_frames(const Surrogate& s, int32_t n, const sg_probe* probes)
     return SG_OK;
 }
 
+sg_status check_ct_volumes(sg_ctx* c, int32_t n, const int32_t* vol_ids)
+{
+    for (int i = 0; i < n; ++i) {
+        const int32_t v = vol_ids[i];
+        if (v >= 0 && v < (int32_t)c->vols.size() && c->vols[v].live && !c->vols[v].dev.ct)
+            return fail(SG_EINVAL, "env %d: volume %d has no CT (the CT-conditioned surrogate reads HU)", i, v);
+    }
+    return SG_OK;
+}
+
 // encode inputs of n envs into act[X] (and optionally render their targets)
 sg_status encode_and_render(sg_ctx* c, Surrogate& s, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
                             const double* poses, float* target)
 {
+    if (s.ct) {
+        if (s.ct_n_ref <= 0) return fail(SG_ESTATE, "CT surrogate: no reference histogram (sg_surr_set_ct_reference)");
+        SG_TRY(check_ct_volumes(c, n, vol_ids));
+        SG_TRY(check(s.ct_hist.ensure(sizeof(uint32_t) * kCtBins * (size_t)n), "CT histograms"));
+        SG_TRY(check(s.ct_lut.ensure(sizeof(uint16_t) * kCtBins * (size_t)n), "CT matching maps"));
+    }
     std::vector<int64_t> offs(n);
     for (int i = 0; i < n; ++i) offs[i] = (int64_t)i * s.H * s.W;
     PhysArgs a;
     StageInfo info;
     SG_TRY(stage_physics(c, n, vol_ids, probes, poses, target ? target : (float*)s.yhat.p, offs.data(), nullptr, a,
                          info));
-    SG_TRY(check(launch_encode(a, n, s.H * s.W, (uint16_t*)s.act[X].p, c->stream), "encode"));
+    if (s.ct)
+        SG_TRY(check(launch_ct_encode(a, n, s.H * s.W, (uint32_t*)s.ct_hist.p,
+                                      (const long long*)s.ct_ref.p + kCtBins, s.ct_n_ref, (uint16_t*)s.ct_lut.p,
+                                      (uint16_t*)s.act[X].p, c->stream),
+                     "CT encode"));
+    else
+        SG_TRY(check(launch_encode(a, n, s.H * s.W, (uint16_t*)s.act[X].p, c->stream), "encode"));
     if (target) SG_TRY(launch_physics(c, a, info));
     return SG_OK;
 }
@@ -520,6 +548,57 @@ extern "C" sg_status sg_surr_create(sg_ctx* c, int32_t H, int32_t W, uint64_t se
     const int32_t sid = c->next_surr++;
     c->surrogates[sid] = std::move(s);
     *id = sid;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_create_ct(sg_ctx* c, int32_t H, int32_t W, uint64_t seed, float adv_weight, int32_t* id)
+{
+    if (!(adv_weight >= 0.f && adv_weight <= 1.f)) return fail(SG_EINVAL, "sg_surr_create_ct: adv_weight in [0, 1]");
+    if (adv_weight > 0.f) return fail(SG_EINVAL, "sg_surr_create_ct: the adversarial term is not available");
+    SG_TRY(sg_surr_create(c, H, W, seed, id));
+    Surrogate* s = find_surr(c, *id);
+    s->ct = true;
+    s->adv_weight = adv_weight;
+    const hipError_t e = s->ct_ref.ensure(sizeof(long long) * 2 * kCtBins);
+    if (e != hipSuccess) {
+        c->surrogates.erase(*id);
+        return hip_fail(e, "CT reference");
+    }
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_set_ct_reference(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids,
+                                              const sg_probe* probes, const double* poses, int64_t* hist)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !vol_ids || !probes || !poses) return fail(SG_EINVAL, "sg_surr_set_ct_reference: bad id or NULL");
+    if (!s->ct) return fail(SG_EINVAL, "sg_surr_set_ct_reference: not a CT-conditioned surrogate");
+    if (n < 1) return fail(SG_EINVAL, "sg_surr_set_ct_reference: n_envs must be >= 1");
+    (void)hipSetDevice(c->device);
+    SG_TRY(check_frames(*s, n, probes));
+    SG_TRY(check_ct_volumes(c, n, vol_ids));
+    DevBuf h;
+    SG_TRY(check(h.ensure(sizeof(uint32_t) * kCtBins * (size_t)n), "reference histograms"));
+    std::vector<int64_t> offs(n);
+    for (int i = 0; i < n; ++i) offs[i] = (int64_t)i * s->H * s->W;
+    SG_TRY(ensure_capacity(*s, 1, false));
+    PhysArgs a;
+    StageInfo info;
+    SG_TRY(stage_physics(c, n, vol_ids, probes, poses, (float*)s->yhat.p, offs.data(), nullptr, a, info));
+    SG_TRY(check(launch_ct_encode(a, n, s->H * s->W, (uint32_t*)h.p, nullptr, 0, nullptr, nullptr, c->stream),
+                 "reference histograms"));
+    SG_TRY(check(launch_ct_reference((const uint32_t*)h.p, n, (long long*)s->ct_ref.p,
+                                     (long long*)s->ct_ref.p + kCtBins, c->stream),
+                 "reference"));
+    std::vector<long long> r(kCtBins);
+    hipError_t e = hipMemcpyAsync(r.data(), s->ct_ref.p, sizeof(long long) * kCtBins, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    SG_TRY(check(e, "reference readback"));
+    long long tot = 0;
+    for (int b = 0; b < kCtBins; ++b) tot += r[b];
+    s->ct_n_ref = tot;
+    if (hist)
+        for (int b = 0; b < kCtBins; ++b) hist[b] = (int64_t)r[b];
     return SG_OK;
 }
 
@@ -657,6 +736,7 @@ extern "C" sg_status sg_surr_infer(sg_ctx* c, int32_t id, int32_t n, const int32
 
 namespace {
 const char kMagic[8] = {'S', 'G', 'S', 'U', 'R', 'R', '0', '1'};
+const char kMagicCt[8] = {'S', 'G', 'S', 'U', 'R', 'R', 'C', '1'};   // + the CT reference counts
 }
 
 extern "C" sg_status sg_surr_save(sg_ctx* c, int32_t id, const char* path)
@@ -670,13 +750,17 @@ extern "C" sg_status sg_surr_save(sg_ctx* c, int32_t id, const char* path)
     if (e == hipSuccess) e = hipMemcpy(buf.data(), s->master.p, sizeof(float) * n, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(buf.data() + n, s->mom1.p, sizeof(float) * n, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(buf.data() + 2 * n, s->mom2.p, sizeof(float) * n, hipMemcpyDeviceToHost);
+    std::vector<long long> ref(s->ct ? kCtBins : 0);
+    if (e == hipSuccess && s->ct)
+        e = hipMemcpy(ref.data(), s->ct_ref.p, sizeof(long long) * kCtBins, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "checkpoint readback");
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(SG_EINVAL, "cannot open %s for writing", path);
     const int32_t hw[2] = {s->H, s->W};
     const int64_t meta[2] = {s->n_params, s->step};
-    bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(hw, sizeof(hw), 1, f) == 1 &&
+    bool ok = std::fwrite(s->ct ? kMagicCt : kMagic, 1, 8, f) == 8 && std::fwrite(hw, sizeof(hw), 1, f) == 1 &&
               std::fwrite(meta, sizeof(meta), 1, f) == 1 && std::fwrite(buf.data(), sizeof(float), 3 * n, f) == 3 * n;
+    if (s->ct) ok = ok && std::fwrite(ref.data(), sizeof(long long), kCtBins, f) == (size_t)kCtBins;
     ok = (std::fclose(f) == 0) && ok;
     return ok ? SG_OK : fail(SG_EINVAL, "write to %s failed", path);
 }
@@ -692,11 +776,19 @@ extern "C" sg_status sg_surr_load(sg_ctx* c, int32_t id, const char* path)
     int64_t meta[2];
     const size_t n = (size_t)s->n_params;
     std::vector<float> buf(3 * n);
-    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+    std::vector<long long> ref(2 * kCtBins, 0);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, s->ct ? kMagicCt : kMagic, 8) == 0 &&
               std::fread(hw, sizeof(hw), 1, f) == 1 && std::fread(meta, sizeof(meta), 1, f) == 1 &&
               hw[0] == s->H && hw[1] == s->W && meta[0] == s->n_params &&
               std::fread(buf.data(), sizeof(float), 3 * n, f) == 3 * n;
+    if (s->ct) ok = ok && std::fread(ref.data(), sizeof(long long), kCtBins, f) == (size_t)kCtBins;
     std::fclose(f);
+    long long tot = 0;
+    for (int b = 0; b < kCtBins && s->ct; ++b) {
+        ok = ok && ref[b] >= 0;
+        tot += ref[b];
+        ref[kCtBins + b] = tot;
+    }
     if (!ok) return fail(SG_EINVAL, "%s is not a checkpoint of this surrogate (%dx%d, %lld params)", path, s->W,
                          s->H, (long long)s->n_params);
     (void)hipSetDevice(c->device);
@@ -704,8 +796,11 @@ extern "C" sg_status sg_surr_load(sg_ctx* c, int32_t id, const char* path)
     if (e == hipSuccess) e = hipMemcpy(s->master.p, buf.data(), sizeof(float) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->mom1.p, buf.data() + n, sizeof(float) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->mom2.p, buf.data() + 2 * n, sizeof(float) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess && s->ct)
+        e = hipMemcpy(s->ct_ref.p, ref.data(), sizeof(long long) * 2 * kCtBins, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "checkpoint upload");
     s->step = meta[1];
+    if (s->ct) s->ct_n_ref = tot;
     return refresh_bf16(c, *s);
 }
 

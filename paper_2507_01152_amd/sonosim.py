@@ -28,7 +28,8 @@ SYMBOLS = (
     "sg_recon_create", "sg_recon_update", "sg_recon_observe", "sg_recon_counts", "sg_recon_points",
     "sg_recon_reset", "sg_recon_destroy",
     "sg_conv_forward", "sg_conv_backward_data", "sg_conv_backward_weight",
-    "sg_surr_create", "sg_surr_destroy", "sg_surr_num_params", "sg_surr_train_step", "sg_surr_infer",
+    "sg_surr_create", "sg_surr_create_ct", "sg_surr_set_ct_reference", "sg_surr_destroy", "sg_surr_num_params",
+    "sg_surr_train_step", "sg_surr_infer",
     "sg_audit_decide", "sg_surr_save", "sg_surr_load", "sg_surr_get_params", "sg_surr_get_grads",
     "sg_surr_set_params", "sg_surr_get_batch",
 )
@@ -112,6 +113,8 @@ def load():
         "sg_conv_backward_data": [VP, P(sg_conv_desc), VP, VP, VP, I32],
         "sg_conv_backward_weight": [VP, P(sg_conv_desc), VP, VP, VP, VP],
         "sg_surr_create": [VP, I32, I32, C.c_uint64, P(I32)],
+        "sg_surr_create_ct": [VP, I32, I32, C.c_uint64, C.c_float, P(I32)],
+        "sg_surr_set_ct_reference": [VP, I32, I32, VP, VP, VP, VP],
         "sg_surr_destroy": [VP, I32],
         "sg_surr_num_params": [VP, I32, P(C.c_int64)],
         "sg_surr_train_step": [VP, I32, I32, VP, VP, VP, C.c_float, P(C.c_float)],
@@ -328,6 +331,25 @@ def sg_surr_create(ctx, H=256, W=128, seed=0) -> int:
     sid = C.c_int32()
     _check(load().sg_surr_create(ctx, int(H), int(W), int(seed) & ((1 << 64) - 1), C.byref(sid)), "sg_surr_create")
     return int(sid.value)
+
+
+def sg_surr_create_ct(ctx, H=256, W=128, seed=0, adv_weight=0.0) -> int:
+    sid = C.c_int32()
+    _check(load().sg_surr_create_ct(ctx, int(H), int(W), int(seed) & ((1 << 64) - 1), float(adv_weight),
+                                    C.byref(sid)), "sg_surr_create_ct")
+    return int(sid.value)
+
+
+def sg_surr_set_ct_reference(ctx, sid, vol_ids, probes, poses) -> np.ndarray:
+    """Pooled reference histogram (4096 int64 counts) of the given frames."""
+    n = len(probes)
+    vids = np.ascontiguousarray(vol_ids, dtype=np.int32)
+    pa = probes_array(probes)
+    ps = np.ascontiguousarray(poses, dtype=np.float64).reshape(n, 12)
+    h = np.zeros(4096, dtype=np.int64)
+    _check(load().sg_surr_set_ct_reference(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p),
+                                           ps.ctypes.data, h.ctypes.data), "sg_surr_set_ct_reference")
+    return h
 
 
 def sg_surr_destroy(ctx, sid):
