@@ -212,11 +212,15 @@ def l1_loss(yhat, y):
     return float(np.abs(yhat - y).mean())
 
 
-def backward(params, act, yhat, y, rounding=True):
-    """Gradients of the L1 loss (mean |yhat - y|) w.r.t. every parameter."""
+def backward(params, act, yhat, y, rounding=True, extra_gy=None):
+    """Gradients of the L1 loss (mean |yhat - y|) w.r.t. every parameter;
+    extra_gy (optional, like yhat) is a further loss term's gradient at yhat
+    (the adversarial term of the CT surrogate)."""
     q = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
     P = yhat.size
     gy = np.sign(yhat - y) / P
+    if extra_gy is not None:
+        gy = gy + extra_gy
     grads = {"head_w": np.einsum("nhwc,nhw->c", act["D0"], gy), "head_b": np.array([gy.sum()])}
     g = {"D0": gy[..., None] * q(params["head_w"])[None, None, None, :]}
     for i in range(len(LAYERS) - 1, -1, -1):
@@ -331,3 +335,141 @@ def ct_input(vol, probe, pose, ref_hist) -> np.ndarray:
     H = probe.H
     x[..., 3] = bf16_round(((np.arange(H) + 0.5) / H)[:, None] * np.ones(vox.shape[1]))
     return x
+
+
+# ---------------------------------------------------------------------------
+# Adversarial term of the CT-conditioned surrogate (App. B.2: the pix2pix
+# objective, L1 with weight 1 plus a GAN term with weight 0.01; pix2pix's
+# discriminator judges patches of the image together with its input).
+# Readings: a conditional patch discriminator of five 3x3 convs (pad 1),
+#   8 -> 32 (stride 2), 32 -> 64 (2), 64 -> 128 (2), 128 -> 128 (1), 128 -> 8 (1),
+# leaky ReLU (slope 0.2 in FP32) after the first four, no normalisation; the
+# patch logit is channel 0 of the last conv (its other channels start at zero
+# and receive no gradient).  Its input is the generator's input with channel
+# 4 replaced by the image (bf16) and channels 5..7 zero.  Losses are the
+# binary cross-entropy on logits l, softplus(-l) for "real" and softplus(l)
+# for "fake", averaged over patches:
+#   discriminator  L_D   = (mean_real softplus(-l) + mean_fake softplus(l)) / 2
+#   generator      L_adv = mean softplus(-l(x, yhat))  (the non-saturating form)
+# and one step runs in pix2pix's order: G forward, D update on the real pair
+# (x, y) and the fake pair (x, yhat), then the G update on L1 + w L_adv with
+# the updated D.
+
+DISC_LAYERS = [(8, 32, 2), (32, 64, 2), (64, 128, 2), (128, 128, 1), (128, 8, 1)]   # (Ci, Co, stride)
+LEAKY_SLOPE = float(np.float32(0.2))
+DISC_IMAGE_C = 4
+
+
+def disc_layout():
+    """[(name, offset, shape)] of the discriminator's flat parameter vector."""
+    out, off = [], 0
+    for i, (ci, co, _st) in enumerate(DISC_LAYERS):
+        out.append((f"dw{i}", off, (co, 3, 3, ci)))
+        off += co * 9 * ci
+        out.append((f"db{i}", off, (co,)))
+        off += co
+    return out, off
+
+
+def disc_unflatten(flat):
+    layout, n = disc_layout()
+    assert flat.size == n, (flat.size, n)
+    return {name: np.asarray(flat[o:o + int(np.prod(shape))], dtype=np.float64).reshape(shape)
+            for name, o, shape in layout}
+
+
+def disc_flatten(d):
+    layout, n = disc_layout()
+    out = np.zeros(n)
+    for name, o, shape in layout:
+        out[o:o + int(np.prod(shape))] = d[name].ravel()
+    return out
+
+
+def leaky_relu(a):
+    a = np.asarray(a, dtype=np.float64)
+    return np.where(a > 0, a, LEAKY_SLOPE * a)
+
+
+def disc_input(x, img, rounding=True):
+    """Discriminator input: x's channels 0..3, the image (bf16) in channel 4."""
+    z = np.zeros(x.shape[:3] + (8,))
+    z[..., :DISC_IMAGE_C] = x[..., :DISC_IMAGE_C]
+    z[..., DISC_IMAGE_C] = bf16_round(img) if rounding else img
+    return z
+
+
+def disc_forward(dp, z, rounding=True):
+    """Returns (activations [z, a1, .., a4], logits [N, H/8, W/8])."""
+    q = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
+    act = [q(z)]
+    last = len(DISC_LAYERS) - 1
+    for i, (_ci, _co, st) in enumerate(DISC_LAYERS):
+        y = conv_forward(act[-1], q(dp[f"dw{i}"]), dp[f"db{i}"], stride=st, pad=1)
+        if i < last:
+            act.append(q(leaky_relu(y)))
+        else:
+            logits = y[..., 0]
+    return act, logits
+
+
+def disc_backward(dp, act, dlogits, rounding=True, weights=True):
+    """Back-propagates dlogits (gradient at the logits) through the
+    discriminator: (parameter gradients or None, gradient at its input z)."""
+    q = bf16_round if rounding else (lambda a: np.asarray(a, dtype=np.float64))
+    last = len(DISC_LAYERS) - 1
+    g = np.zeros(dlogits.shape + (DISC_LAYERS[last][1],))
+    g[..., 0] = dlogits
+    grads = {} if weights else None
+    for i in range(last, -1, -1):
+        _ci, _co, st = DISC_LAYERS[i]
+        dpre = q(g) if i == last else q(g * np.where(act[i + 1] > 0, 1.0, LEAKY_SLOPE))
+        if weights:
+            grads[f"dw{i}"], grads[f"db{i}"] = conv_backward_weight(act[i], dpre, k=3, stride=st, pad=1)
+        g = conv_backward_data(dpre, q(dp[f"dw{i}"]), act[i].shape, stride=st, pad=1)
+    return grads, g
+
+
+def softplus(a):
+    """log(1 + exp(a)), stable for large |a|."""
+    a = np.asarray(a, dtype=np.float64)
+    return np.maximum(a, 0.0) + np.log1p(np.exp(-np.abs(a)))
+
+
+def sigmoid(a):
+    a = np.asarray(a, dtype=np.float64)
+    e = np.exp(-np.abs(a))
+    return np.where(a >= 0, 1.0 / (1.0 + e), e / (1.0 + e))
+
+
+def bce_logits(l, label):
+    """Per-patch binary cross-entropy of logits l against label 1 or 0, and its
+    derivative sigmoid(l) - label."""
+    return (softplus(-l) if label else softplus(l)), sigmoid(l) - float(label)
+
+
+def gan_train_step(gflat, dflat, x, y, adv_weight, lr, d_m=None, d_v=None, d_step=1, rounding=True):
+    """One step of the CT surrogate with the adversarial term (order above).
+    Returns a dict: yhat, l1, loss_d, loss_adv, d_grads and g_grads (flat),
+    d_new (flat discriminator after its Adam step)."""
+    gp, dp = unflatten(gflat), disc_unflatten(dflat)
+    act, yhat = forward(gp, x, rounding)
+    # discriminator step on the real and the fake pair
+    act_r, l_r = disc_forward(dp, disc_input(x, y, rounding), rounding)
+    act_f, l_f = disc_forward(dp, disc_input(x, yhat, rounding), rounding)
+    (sr, gr), (sf, gf) = bce_logits(l_r, 1), bce_logits(l_f, 0)
+    loss_d = 0.5 * (sr.mean() + sf.mean())
+    dg_r, _ = disc_backward(dp, act_r, 0.5 * gr / l_r.size, rounding)
+    dg_f, _ = disc_backward(dp, act_f, 0.5 * gf / l_f.size, rounding)
+    d_grads = disc_flatten({k: dg_r[k] + dg_f[k] for k in dg_r})
+    d_m = np.zeros_like(d_grads) if d_m is None else d_m
+    d_v = np.zeros_like(d_grads) if d_v is None else d_v
+    d_new, _m, _v = adam_update(np.asarray(dflat, dtype=np.float64), d_grads, d_m, d_v, d_step, lr)
+    # generator's adversarial gradient through the updated discriminator
+    dp2 = disc_unflatten(d_new)
+    act_g, l_g = disc_forward(dp2, disc_input(x, yhat, rounding), rounding)
+    sg, gg = bce_logits(l_g, 1)
+    _, dz = disc_backward(dp2, act_g, adv_weight * gg / l_g.size, rounding, weights=False)
+    g_grads = flatten(backward(gp, act, yhat, y, rounding, extra_gy=dz[..., DISC_IMAGE_C]))
+    return dict(yhat=yhat, l1=l1_loss(yhat, y), loss_d=float(loss_d), loss_adv=float(sg.mean()),
+                d_grads=d_grads, g_grads=g_grads, d_new=d_new)

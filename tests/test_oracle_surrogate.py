@@ -197,3 +197,176 @@ def test_ct_input_channels():
     assert np.all(x[30:, :, 1:3] == 0) and np.all(x[..., 4:] == 0)
     assert abs(x[:30, :, 1].std() - 1.0) < 0.3 and abs(x[:30, :, 2].std() - 1.0) < 0.3
     assert np.array_equal(x[:, 0, 3], so.bf16_round((np.arange(40) + 0.5) / 40))
+
+
+# ---------------------------------------------------------------------------
+# adversarial term (conditional patch discriminator, binary cross-entropy)
+
+
+def _disc_params(seed=4, scale=1.0):
+    rng = np.random.default_rng(seed)
+    layout, n = so.disc_layout()
+    flat = np.zeros(n)
+    for name, o, shape in layout:
+        sz = int(np.prod(shape))
+        if name.startswith("dw"):
+            flat[o:o + sz] = rng.standard_normal(sz) * scale * np.sqrt(2.0 / np.prod(shape[1:]))
+        else:
+            flat[o:o + sz] = rng.standard_normal(sz) * 0.05
+    return flat
+
+
+def test_softplus_sigmoid_and_bce_closed_forms():
+    l = np.array([-1000.0, -30.0, -1.5, 0.0, 0.25, 7.0, 1000.0])
+    assert so.softplus(np.array([0.0]))[0] == np.log(2.0)
+    # softplus(-l) - softplus(l) = -l, and no overflow at |l| = 1000
+    assert np.allclose(so.softplus(-l) - so.softplus(l), -l, rtol=0, atol=1e-12)
+    assert so.softplus(np.array([1000.0]))[0] == 1000.0 and so.softplus(np.array([-1000.0]))[0] == 0.0
+    assert so.sigmoid(np.array([0.0]))[0] == 0.5
+    assert np.allclose(so.sigmoid(l) + so.sigmoid(-l), 1.0, atol=1e-15)
+    # d softplus / dl = sigmoid, by central differences
+    h = 1e-6
+    m = np.abs(l) < 100
+    fd = (so.softplus(l[m] + h) - so.softplus(l[m] - h)) / (2 * h)
+    assert np.allclose(fd, so.sigmoid(l[m]), atol=1e-8)
+    for label in (0, 1):
+        v, g = so.bce_logits(l, label)
+        assert np.allclose(g, so.sigmoid(l) - label, atol=0)
+        assert np.all(v >= 0)
+    # label 1 at logit 0 costs log 2; a confident right answer costs ~0
+    assert so.bce_logits(np.array([0.0]), 1)[0][0] == np.log(2.0)
+    assert so.bce_logits(np.array([50.0]), 1)[0][0] < 1e-20
+
+
+def test_leaky_relu_values():
+    a = np.array([-2.0, -0.0, 0.0, 3.0])
+    assert np.array_equal(so.leaky_relu(a), [-2.0 * float(np.float32(0.2)), 0.0, 0.0, 3.0])
+    assert so.LEAKY_SLOPE == float(np.float32(0.2))
+
+
+@pytest.mark.parametrize("chan", [0, so.DISC_IMAGE_C])
+def test_disc_forward_center_tap_pin(chan):
+    """Each layer passes the centre tap of one channel to channel 0 (weight 1,
+    no bias): the logit at patch (i, j) is input pixel (8i, 8j) of that
+    channel after four leaky ReLUs, i.e. v for v > 0 and slope^4 v else.
+    With chan = 4 the value comes from the image placed by disc_input."""
+    layout, n = so.disc_layout()
+    dp = so.disc_unflatten(np.zeros(n))
+    dp["dw0"][0, 1, 1, chan] = 1.0
+    for i in range(1, len(so.DISC_LAYERS)):
+        dp[f"dw{i}"][0, 1, 1, 0] = 1.0
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((2, 32, 48, 8))
+    img = rng.standard_normal((2, 32, 48))
+    z = so.disc_input(x, img, rounding=False)
+    assert np.array_equal(z[..., :4], x[..., :4]) and np.array_equal(z[..., 4], img) and not z[..., 5:].any()
+    _, logits = so.disc_forward(dp, z, rounding=False)
+    v = z[:, ::8, ::8, chan]
+    assert logits.shape == (2, 4, 6)
+    assert np.allclose(logits, np.where(v > 0, v, so.LEAKY_SLOPE ** 4 * v), rtol=1e-15, atol=0)
+
+
+def test_disc_backward_matches_finite_differences():
+    """Without rounding the discriminator is piecewise linear: central
+    differences of sum(c * logits) w.r.t. parameters of every layer and
+    input pixels pin the backward (strides, leaky mask, channel-0 logit)."""
+    flat = _disc_params(seed=5)
+    rng = np.random.default_rng(6)
+    z = rng.standard_normal((1, 16, 24, 8))
+    c = rng.standard_normal((1, 2, 3))
+
+    def f(fl, zz):
+        return float((c * so.disc_forward(so.disc_unflatten(fl), zz, rounding=False)[1]).sum())
+
+    dp = so.disc_unflatten(flat)
+    act, _ = so.disc_forward(dp, z, rounding=False)
+    grads, dz = so.disc_backward(dp, act, c, rounding=False)
+    g = so.disc_flatten(grads)
+    eps = 1e-6
+    layout, _ = so.disc_layout()
+    checked = 0
+    for name, o, shape in layout:
+        size = int(np.prod(shape))
+        for idx in rng.choice(size, size=min(4, size), replace=False):
+            i = o + int(idx)
+            fp, fm = flat.copy(), flat.copy()
+            fp[i] += eps
+            fm[i] -= eps
+            fd = (f(fp, z) - f(fm, z)) / (2 * eps)
+            assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-9, (name, idx, fd, g[i])
+            checked += 1
+    # the last conv's channels 1..7 carry no gradient
+    o = dict((nm, off) for nm, off, _ in layout)["dw4"]
+    assert not g[o + 9 * 128:o + 8 * 9 * 128].any()
+    for _ in range(8):
+        p = tuple(int(rng.integers(0, s)) for s in z.shape)
+        zp, zm = z.copy(), z.copy()
+        zp[p] += eps
+        zm[p] -= eps
+        fd = (f(flat, zp) - f(flat, zm)) / (2 * eps)
+        assert abs(fd - dz[p]) <= 1e-6 * max(1.0, abs(dz[p])) + 1e-9, (p, fd, dz[p])
+        checked += 1
+    assert checked >= 28
+
+
+def test_gan_step_gradients_match_finite_differences():
+    """The step's three gradients against central differences of the losses
+    they belong to (no rounding, learning rate 0 so the discriminator that
+    judges the generator is the one that was differentiated):
+    d_grads of L_D at fixed yhat, g_grads of L1 + w L_adv through G and D."""
+    gflat, x, y = _small_problem(seed=9)
+    x[..., 5:] = 0.0
+    dflat = _disc_params(seed=10)
+    w = 0.7
+    r = so.gan_train_step(gflat, dflat, x, y, w, 0.0, rounding=False)
+    assert np.array_equal(r["d_new"], dflat)
+    yhat = r["yhat"]
+
+    def loss_d(df):
+        dp = so.disc_unflatten(df)
+        lr_ = so.disc_forward(dp, so.disc_input(x, y, False), False)[1]
+        lf_ = so.disc_forward(dp, so.disc_input(x, yhat, False), False)[1]
+        return 0.5 * (so.bce_logits(lr_, 1)[0].mean() + so.bce_logits(lf_, 0)[0].mean())
+
+    def loss_g(gf):
+        _, yh = so.forward(so.unflatten(gf), x, rounding=False)
+        lg = so.disc_forward(so.disc_unflatten(dflat), so.disc_input(x, yh, False), False)[1]
+        return so.l1_loss(yh, y) + w * so.bce_logits(lg, 1)[0].mean()
+
+    assert abs(loss_d(dflat) - r["loss_d"]) <= 1e-12
+    rng = np.random.default_rng(11)
+    eps = 1e-6
+    for i in rng.choice(dflat.size, size=12, replace=False):
+        fp, fm = dflat.copy(), dflat.copy()
+        fp[i] += eps
+        fm[i] -= eps
+        fd = (loss_d(fp) - loss_d(fm)) / (2 * eps)
+        assert abs(fd - r["d_grads"][i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, r["d_grads"][i])
+    layout, _ = so.param_layout()
+    adv_seen = 0.0
+    for name, o, shape in layout:
+        size = int(np.prod(shape))
+        for idx in rng.choice(size, size=min(2, size), replace=False):
+            i = o + int(idx)
+            fp, fm = gflat.copy(), gflat.copy()
+            fp[i] += eps
+            fm[i] -= eps
+            fd = (loss_g(fp) - loss_g(fm)) / (2 * eps)
+            assert abs(fd - r["g_grads"][i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (name, idx, fd, r["g_grads"][i])
+    # the adversarial term changes the generator's gradient
+    g_l1 = so.loss_and_grads(gflat, x, y, rounding=False)[1]
+    assert np.linalg.norm(r["g_grads"] - g_l1) > 1e-3 * np.linalg.norm(g_l1)
+
+
+def test_gan_step_discriminator_update_is_adam():
+    gflat, x, y = _small_problem(seed=12)
+    x[..., 5:] = 0.0
+    dflat = _disc_params(seed=13)
+    r = so.gan_train_step(gflat, dflat, x, y, 0.01, 1e-3)
+    g = r["d_grads"]
+    assert np.allclose(r["d_new"], dflat - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-12)
+    # pix2pix's order: the generator is judged by the updated discriminator
+    r2 = so.gan_train_step(gflat, r["d_new"], x, y, 0.01, 0.0)
+    assert np.array_equal(r2["g_grads"], r["g_grads"])
+    r3 = so.gan_train_step(gflat, dflat, x, y, 0.01, 0.0)
+    assert not np.array_equal(r3["g_grads"], r["g_grads"])
