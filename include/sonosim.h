@@ -369,9 +369,21 @@ sg_status sg_surr_destroy(sg_ctx* ctx, int32_t surr_id);
  *      (entry w2 >> 20), 0 outside;
  *   3  depth (y + 0.5) / H;  4..7 zero.
  * Every volume it reads must carry a CT (SG_EINVAL otherwise), and the
- * reference must be set (SG_ESTATE otherwise).  adv_weight: weight of the
- * adversarial term of the training loss, in [0, 1]; 0 trains with L1 only.
- * Checkpoints of CT surrogates also hold the reference counts. */
+ * reference must be set (SG_ESTATE otherwise).
+ * adv_weight in [0, 1]: weight of the adversarial term (the paper trains with
+ * L1 weight 1 and GAN weight 0.01); 0 trains with L1 only.  With
+ * adv_weight > 0 the surrogate owns a conditional patch discriminator: five
+ * 3x3 convs (pad 1) 8->32 (stride 2), 32->64 (2), 64->128 (2), 128->128,
+ * 128->8, leaky ReLU (slope 0.2) after the first four, channel 0 of the last
+ * one the logit of an (H/8 x W/8) patch; its input is the encoded input's
+ * channels 0..3 with the image (bf16) in channel 4.  Each training step then
+ * runs in pix2pix's order: generator forward; discriminator step (Adam, same
+ * rate) on L_D = (mean softplus(-l_real) + mean softplus(l_fake)) / 2 with
+ * (input, physics frame) as real and (input, Yhat) as fake; the generator's
+ * step on L1 + adv_weight * L_adv, L_adv = mean softplus(-l) of the updated
+ * discriminator on (input, Yhat).
+ * Checkpoints of CT surrogates also hold the reference counts and the
+ * discriminator (parameters, moments, step). */
 sg_status sg_surr_create_ct(sg_ctx* ctx, int32_t H, int32_t W, uint64_t seed, float adv_weight, int32_t* surr_id);
 
 /* Sets the reference of a CT surrogate's histogram matching: the pooled bin
@@ -411,6 +423,29 @@ sg_status sg_surr_infer(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, const int3
  * if the failing fraction exceeds max_fail_frac. */
 sg_status sg_audit_decide(int32_t n_audit, const float* psnr, float psnr_min, float max_fail_frac,
                           int32_t* fallback, int32_t* whole);
+
+/* One training step on caller-supplied pairs: input (device, bf16, n_envs x
+ * H x W x 8, the layout the encoder writes) and target (device, FP32, n_envs
+ * x H x W); H and W state the buffers' frame size and must equal the
+ * surrogate's (SG_EINVAL otherwise).  Otherwise as sg_surr_train_step (both
+ * buffers are copied before the step).  For a CT surrogate with an
+ * adversarial term the discriminator reads input channels 0..3.
+ * Synchronises. */
+sg_status sg_surr_train_pairs(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, int32_t H, int32_t W,
+                              const uint16_t* input, const float* target, float lr, float* loss);
+
+/* Adversarial losses of the last training step (host): L_D before the
+ * discriminator's update and L_adv (without its weight) after it.
+ * SG_EINVAL without an adversarial term, SG_ESTATE before the first step. */
+sg_status sg_surr_gan_losses(sg_ctx* ctx, int32_t surr_id, float* loss_d, float* loss_adv);
+
+/* The discriminator's FP32 parameters (per layer: weights [Co][3][3][Ci],
+ * then Co biases), their gradient of the last step (host copies), and
+ * setting them.  SG_EINVAL without an adversarial term. */
+sg_status sg_surr_disc_num_params(sg_ctx* ctx, int32_t surr_id, int64_t* n);
+sg_status sg_surr_disc_get_params(sg_ctx* ctx, int32_t surr_id, float* host);
+sg_status sg_surr_disc_get_grads(sg_ctx* ctx, int32_t surr_id, float* host);
+sg_status sg_surr_disc_set_params(sg_ctx* ctx, int32_t surr_id, const float* host);
 
 /* Checkpoint: FP32 masters, Adam moments, step count and frame size in one
  * file.  Loading restores them bit for bit (same frame size required). */

@@ -31,6 +31,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte staging chunk
 
 constexpr int kThreads = 256;
+
+// conv epilogue activation: 0 none, 1 ReLU, 2 leaky ReLU (slope kLeakySlope)
+__device__ __forceinline__ float activate(float y, int act)
+{
+    if (act == 1) return fmaxf(y, 0.f);
+    if (act == 2) return y > 0.f ? y : kLeakySlope * y;
+    return y;
+}
 constexpr int kBK = 32;           // K per MFMA step
 constexpr int kBKP = kBK + 8;     // padded LDS row (bf16)
 
@@ -281,8 +289,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
                 if (row >= g.M) continue;
                 const float v = acc[i][j][r];
                 if constexpr (MODE == kFwd) {
-                    float y = v + (a.bias ? a.bias[col] : 0.f);
-                    if (a.relu) y = fmaxf(y, 0.f);
+                    float y = activate(v + (a.bias ? a.bias[col] : 0.f), a.relu);
                     const int64_t o = row * g.Co + col;
                     const uint16_t yb = f2bf(y);
                     if (a.out_bf16) a.out_bf16[o] = yb;
@@ -404,8 +411,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int cc = (gi & 1) * 16 + 4 * lk + q;
-                float y = acc[gi][j][q] + bias;
-                if (a.relu) y = fmaxf(y, 0.f);
+                const float y = activate(acc[gi][j][q] + bias, a.relu);
                 sO[(rr * kTileW + cc) * CO + co] = f2bf(y);
                 const int ho = ho0 + rr, wo = wo0 + cc;
                 if (a.out_f32 && ho < g.Ho && wo < g.Wo) a.out_f32[((n * g.Ho + ho) * g.Wo + wo) * CO + co] = y;
@@ -495,7 +501,7 @@ __global__ void k_pool2x2_sum(const float* fine, float* coarse, int N, int H, in
 // of a column are summed in a fixed order (deterministic).
 __global__ __launch_bounds__(256) void k_mask_colsum(const float* g, int ldg, const uint16_t* gb, const uint16_t* y,
                                                      uint16_t* out, int64_t rows, int C, int64_t rows_per_block,
-                                                     float* part)
+                                                     float* part, float slope)
 {
     // a thread owns one 8-channel chunk of rows r_off, r_off + RP, ... (C multiple of 8, <= 256)
     __shared__ float red[256 * 8];
@@ -522,8 +528,10 @@ __global__ __launch_bounds__(256) void k_mask_colsum(const float* g, int ldg, co
                 if (y) yv = *reinterpret_cast<const u32x4*>(y + i);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const uint16_t lo = f2bf(__uint_as_float(yv[j] << 16) > 0.f ? gv[2 * j] : 0.f);
-                    const uint16_t hi = f2bf(__uint_as_float(yv[j] & 0xFFFF0000u) > 0.f ? gv[2 * j + 1] : 0.f);
+                    const float ylo = __uint_as_float(yv[j] << 16), yhi = __uint_as_float(yv[j] & 0xFFFF0000u);
+                    const uint16_t lo = f2bf(ylo > 0.f ? gv[2 * j] : (slope != 0.f ? slope * gv[2 * j] : 0.f));
+                    const uint16_t hi =
+                        f2bf(yhi > 0.f ? gv[2 * j + 1] : (slope != 0.f ? slope * gv[2 * j + 1] : 0.f));
                     b[j] = (uint32_t)lo | ((uint32_t)hi << 16);
                 }
                 if (out) *reinterpret_cast<u32x4*>(out + i) = b;
@@ -857,6 +865,66 @@ __global__ __launch_bounds__(256) void k_head_bwd(const uint16_t* x, const uint1
     (void)C;
 }
 
+// Discriminator input of two sets of P pixels: z[i] = (x[p] channels 0..3,
+// bf16(img), 0, 0, 0) with img = y_real[p] for i = p < P and y_fake[p] for
+// i = P + p (the same encoded input x[p] in both sets)
+__global__ void k_disc_input(const uint16_t* x, const float* y_real, const float* y_fake, uint16_t* z, int64_t P)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * P; i += (int64_t)gridDim.x * blockDim.x) {
+        const bool fake = i >= P;
+        const int64_t p = fake ? i - P : i;
+        const uint2 xv = *reinterpret_cast<const uint2*>(x + p * 8);
+        const float img = fake ? y_fake[p] : y_real[p];
+        uint4 o;
+        o.x = xv.x;
+        o.y = xv.y;
+        o.z = (uint32_t)f2bf(img);
+        o.w = 0u;
+        *reinterpret_cast<uint4*>(z + i * 8) = o;
+    }
+}
+
+// Binary cross-entropy on the logits l = logits[r * ld] of rows r < P_total:
+// rows r < P_real have label 1 (loss w_real softplus(-l), gradient
+// gscale w_real (sigmoid(l) - 1)), the rest label 0 (w_fake softplus(l),
+// gscale w_fake sigmoid(l)).  grad rows hold ld floats (channel 0 the
+// gradient, the others 0); part[block] = the block's loss sum.
+__device__ __forceinline__ float softplus_f(float a) { return fmaxf(a, 0.f) + log1pf(expf(-fabsf(a))); }
+
+__global__ __launch_bounds__(256) void k_bce_logits(const float* logits, int ld, int64_t P_real, int64_t P_total,
+                                                    float w_real, float w_fake, float gscale, float* grad,
+                                                    int64_t per_block, float* part)
+{
+    __shared__ float red[256];
+    const int64_t r0 = (int64_t)blockIdx.x * per_block;
+    const int64_t r1 = min(P_total, r0 + per_block);
+    float acc = 0.f;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const float l = logits[r * ld];
+        const float e = expf(-fabsf(l));
+        const float sig = l >= 0.f ? 1.f / (1.f + e) : e / (1.f + e);
+        const bool real = r < P_real;
+        const float w = real ? w_real : w_fake;
+        acc += w * softplus_f(real ? -l : l);
+        grad[r * ld] = gscale * w * (real ? sig - 1.f : sig);
+        for (int c = 1; c < ld; ++c) grad[r * ld + c] = 0.f;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// gy[p] += dz[p * ld + c]
+__global__ void k_add_channel(float* gy, const float* dz, int ld, int c, int64_t P)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x)
+        gy[p] += dz[p * ld + c];
+}
+
 // L1 loss: per-block partial sums of |yhat - y| * scale (scale = 1 / n);
 // grad = sign(yhat - y) * scale
 __global__ void k_l1(const float* yhat, const float* y, int64_t n, float scale, float* grad, int64_t per_block,
@@ -1080,12 +1148,12 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
 int wgrad_tile_m(int M) { return M <= 16 ? 16 : (M <= 32 ? 32 : 64); }
 
 hipError_t mask_colsum(const float* g, int ldg, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
-                       int blocks, float* bias_grad, hipStream_t s)
+                       int blocks, float* bias_grad, hipStream_t s, float slope)
 {
     if (C > 256 || C % 8 || (ldg != 0 && (ldg < C || ldg % 4))) return hipErrorInvalidValue;
     const int64_t per = (rows + blocks - 1) / blocks;
     hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, g, ldg ? ldg : C, nullptr, y, out, rows, C, per,
-                       part);
+                       part, slope);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return reduce_parts(part, C, blocks, bias_grad, s);
@@ -1137,7 +1205,7 @@ hipError_t colsum_bf16(const uint16_t* x, int64_t rows, int cols, float* part, i
     if (cols > 256 || cols % 8) return hipErrorInvalidValue;
     const int64_t per = (rows + blocks - 1) / blocks;
     hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, nullptr, cols, x, nullptr, nullptr, rows, cols,
-                       per, part);
+                       per, part, 0.f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return reduce_parts(part, cols, blocks, out, s);
@@ -1172,6 +1240,30 @@ hipError_t l1_loss(const float* yhat, const float* y, int64_t n, float* grad, fl
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return reduce_parts(part, 1, blocks, loss, s);
+}
+
+hipError_t disc_input(const uint16_t* x, const float* y_real, const float* y_fake, uint16_t* z, int64_t P,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_disc_input, dim3((unsigned)grid_for(2 * P)), dim3(256), 0, s, x, y_real, y_fake, z, P);
+    return hipGetLastError();
+}
+
+hipError_t bce_logits(const float* logits, int ld, int64_t P_real, int64_t P_total, float w_real, float w_fake,
+                      float gscale, float* grad, float* part, int blocks, float* loss, hipStream_t s)
+{
+    const int64_t per = (P_total + blocks - 1) / blocks;
+    hipLaunchKernelGGL(k_bce_logits, dim3(blocks), dim3(256), 0, s, logits, ld, P_real, P_total, w_real, w_fake,
+                       gscale, grad, per, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_parts(part, 1, blocks, loss, s);
+}
+
+hipError_t add_channel(float* gy, const float* dz, int ld, int c, int64_t P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_channel, dim3((unsigned)grid_for(P)), dim3(256), 0, s, gy, dz, ld, c, P);
+    return hipGetLastError();
 }
 
 hipError_t adam_step(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,

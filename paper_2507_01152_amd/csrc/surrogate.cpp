@@ -49,6 +49,22 @@ constexpr int kScanSrc = E0, kScanDst = S0, kScanTmp = A0, kScanC = 8, kScanOff 
 constexpr float kScanScale = 1.f / 16.f;
 constexpr float kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
 
+// conditional patch discriminator of the adversarial term (pix2pix: the
+// discriminator judges patches of an image together with the network's
+// input): 3x3 convs, pad 1, leaky ReLU after all but the last, whose channel
+// 0 is the patch logit (its other channels stay zero).  Input: the encoded
+// input's channels 0..3 and the image in channel kDiscImageC.
+struct DiscDef {
+    int Ci, Co, stride;
+};
+const DiscDef kDisc[] = {{8, 32, 2}, {32, 64, 2}, {64, 128, 2}, {128, 128, 1}, {128, 8, 1}};
+constexpr int kNumD = sizeof(kDisc) / sizeof(kDisc[0]);
+constexpr int kDiscImageC = 4;
+constexpr int kDiscLogitC = 8;   // channels of the last conv (channel 0: the logit)
+// pyramid level of the discriminator's tensor k (k = 0: input, k = L + 1: output of layer L)
+constexpr int kDiscLevel[kNumD + 1] = {0, 1, 2, 3, 3, 3};
+constexpr int kDiscTC[kNumD + 1] = {8, 32, 64, 128, 128, kDiscLogitC};
+
 }  // namespace
 
 struct Surrogate {
@@ -68,6 +84,15 @@ struct Surrogate {
     float adv_weight = 0.f;
     DevBuf ct_hist, ct_lut, ct_ref;
     long long ct_n_ref = 0;
+    // discriminator (adv_weight > 0): FP32 masters, Adam moments, gradient, bf16 copies; tensors for up to
+    // d_cap frames (d_act[k]: bf16, tensor k; d_g[k]: FP32 gradient at tensor k; logits FP32)
+    int64_t dn_params = 0;
+    int64_t dw_off[kNumD] = {}, db_off[kNumD] = {}, dw_n[kNumD] = {};
+    DevBuf d_master, d_mom1, d_mom2, d_grad, d_wb, d_wt;
+    int64_t d_step = 0;
+    int d_cap = 0;
+    DevBuf d_act[kNumD], d_g[kNumD], d_logits, d_glog, d_dpre, d_bias_scratch;
+    float last_loss[3] = {0.f, 0.f, 0.f};   // L1, L_D, L_adv of the last training step
 };
 
 void SurrogateDeleter::operator()(Surrogate* p) const { delete p; }
@@ -390,6 +415,191 @@ sg_status adam(sg_ctx* c, Surrogate& s, float lr)
                  "adam head bias");
 }
 
+// ---------------------------------------------------------------------------
+// discriminator of the adversarial term
+
+ConvShape disc_shape(const Surrogate& s, int L, int frames)
+{
+    const int lv = kDiscLevel[L];
+    ConvShape sh;
+    sh.N = frames;
+    sh.H = s.H >> lv;
+    sh.W = s.W >> lv;
+    sh.C = kDisc[L].Ci;
+    sh.Co = kDisc[L].Co;
+    sh.k = 3;
+    sh.stride = kDisc[L].stride;
+    sh.pad = 1;
+    sh.up = 0;
+    return sh;
+}
+
+int64_t disc_elems(const Surrogate& s, int k, int frames)
+{
+    return (int64_t)frames * (s.H >> kDiscLevel[k]) * (s.W >> kDiscLevel[k]) * kDiscTC[k];
+}
+
+sg_status disc_capacity(Surrogate& s, int frames)
+{
+    if (frames <= s.d_cap) return SG_OK;
+    int64_t mx = 0;
+    for (int k = 0; k < kNumD; ++k) {
+        SG_TRY(check(s.d_act[k].ensure(sizeof(uint16_t) * disc_elems(s, k, frames)), "discriminator activations"));
+        SG_TRY(check(s.d_g[k].ensure(sizeof(float) * disc_elems(s, k, frames)), "discriminator gradients"));
+        mx = std::max(mx, disc_elems(s, k + 1, frames));
+    }
+    SG_TRY(check(s.d_logits.ensure(sizeof(float) * disc_elems(s, kNumD, frames)), "discriminator logits"));
+    SG_TRY(check(s.d_glog.ensure(sizeof(float) * disc_elems(s, kNumD, frames)), "logit gradient"));
+    SG_TRY(check(s.d_dpre.ensure(sizeof(uint16_t) * mx), "discriminator dpre"));
+    SG_TRY(check(s.d_bias_scratch.ensure(sizeof(float) * 256), "discriminator bias scratch"));
+    s.d_cap = frames;
+    return SG_OK;
+}
+
+sg_status disc_refresh_bf16(sg_ctx* c, Surrogate& s)
+{
+    for (int L = 0; L < kNumD; ++L)
+        SG_TRY(check(weights_to_bf16((float*)s.d_master.p + s.dw_off[L], s.dw_n[L], (uint16_t*)s.d_wb.p + s.dw_off[L],
+                                     (uint16_t*)s.d_wt.p + s.dw_off[L], kDisc[L].Co, 9, kDisc[L].Ci, c->stream),
+                     "discriminator bf16 weights"));
+    return SG_OK;
+}
+
+// parameters, He-normal (last layer: channel 0 only), zero biases
+sg_status disc_create(sg_ctx* c, Surrogate& s, uint64_t seed)
+{
+    int64_t off = 0;
+    for (int L = 0; L < kNumD; ++L) {
+        s.dw_off[L] = off;
+        s.dw_n[L] = (int64_t)kDisc[L].Co * 9 * kDisc[L].Ci;
+        off += s.dw_n[L];
+        s.db_off[L] = off;
+        off += kDisc[L].Co;
+    }
+    s.dn_params = off;
+    std::vector<float> h(off, 0.f);
+    std::mt19937_64 rng(seed ^ 0x9E3779B97F4A7C15ull);
+    for (int L = 0; L < kNumD; ++L) {
+        const bool last = L == kNumD - 1;
+        std::normal_distribution<float> nd(0.f, std::sqrt((last ? 1.f : 2.f) / (9.f * kDisc[L].Ci)));
+        const int64_t n = last ? 9 * kDisc[L].Ci : s.dw_n[L];   // [Co][3][3][Ci]: channel 0 first
+        for (int64_t i = 0; i < n; ++i) h[s.dw_off[L] + i] = nd(rng);
+    }
+    const size_t bytes = sizeof(float) * off;
+    hipError_t e = s.d_master.ensure(bytes);
+    if (e == hipSuccess) e = s.d_mom1.ensure(bytes);
+    if (e == hipSuccess) e = s.d_mom2.ensure(bytes);
+    if (e == hipSuccess) e = s.d_grad.ensure(bytes);
+    if (e == hipSuccess) e = s.d_wb.ensure(sizeof(uint16_t) * off);
+    if (e == hipSuccess) e = s.d_wt.ensure(sizeof(uint16_t) * off);
+    if (e == hipSuccess) e = hipMemcpy(s.d_master.p, h.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(s.d_mom1.p, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(s.d_mom2.p, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(s.d_grad.p, 0, bytes);
+    if (e != hipSuccess) return hip_fail(e, "discriminator allocation");
+    return disc_refresh_bf16(c, s);
+}
+
+// forward over `frames` frames of input z (bf16, [frames][H][W][8]): d_act[1..], logits
+sg_status disc_forward(sg_ctx* c, Surrogate& s, const uint16_t* z, int frames)
+{
+    for (int L = 0; L < kNumD; ++L) {
+        const bool last = L == kNumD - 1;
+        ConvArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.a = L == 0 ? z : (const uint16_t*)s.d_act[L].p;
+        a.b = (const uint16_t*)s.d_wb.p + s.dw_off[L];
+        a.bias = (const float*)s.d_master.p + s.db_off[L];
+        a.relu = last ? 0 : 2;
+        if (last)
+            a.out_f32 = (float*)s.d_logits.p;
+        else
+            a.out_bf16 = (uint16_t*)s.d_act[L + 1].p;
+        SG_TRY(check(conv_gemm(0, geom_of(disc_shape(s, L, frames), 0), a, 1, c->stream), "discriminator conv"));
+    }
+    return SG_OK;
+}
+
+// backward from the logit gradient in d_glog: parameter gradients into d_grad (weights) and the input
+// gradient into d_g[0] (input_grad)
+sg_status disc_backward(sg_ctx* c, Surrogate& s, const uint16_t* z, int frames, bool weights, bool input_grad)
+{
+    float* grad = (float*)s.d_grad.p;
+    for (int L = kNumD - 1; L >= 0; --L) {
+        const bool last = L == kNumD - 1;
+        const ConvShape sh = disc_shape(s, L, frames);
+        const int64_t rows = disc_elems(s, L + 1, frames) / kDisc[L].Co;
+        const float* g_out = last ? (const float*)s.d_glog.p : (const float*)s.d_g[L + 1].p;
+        const int mb = blocks_for(rows * 16, 1024);
+        SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)mb * kDisc[L].Co), "bias workspace"));
+        SG_TRY(check(mask_colsum(g_out, 0, last ? nullptr : (const uint16_t*)s.d_act[L + 1].p, (uint16_t*)s.d_dpre.p,
+                                 rows, kDisc[L].Co, (float*)s.parts.p, mb,
+                                 weights ? grad + s.db_off[L] : (float*)s.d_bias_scratch.p, c->stream,
+                                 last ? 0.f : kLeakySlope),
+                     "discriminator mask"));
+        const uint16_t* x = L == 0 ? z : (const uint16_t*)s.d_act[L].p;
+        if (weights)
+            SG_TRY(wgrad(c, sh, x, (const uint16_t*)s.d_dpre.p, grad + s.dw_off[L], nullptr, s.parts));
+        if (L > 0 || input_grad)
+            SG_TRY(dgrad(c, sh, (const uint16_t*)s.d_dpre.p, (const uint16_t*)s.d_wt.p + s.dw_off[L],
+                         (float*)s.d_g[L].p, 0, s.fine));
+    }
+    return SG_OK;
+}
+
+sg_status disc_adam(sg_ctx* c, Surrogate& s, float lr)
+{
+    s.d_step += 1;
+    const float c1 = 1.f - std::pow(kBeta1, (float)s.d_step);
+    const float c2 = 1.f - std::pow(kBeta2, (float)s.d_step);
+    float* w = (float*)s.d_master.p;
+    float* m = (float*)s.d_mom1.p;
+    float* v = (float*)s.d_mom2.p;
+    const float* g = (const float*)s.d_grad.p;
+    for (int L = 0; L < kNumD; ++L) {
+        const int64_t o = s.dw_off[L], b = s.db_off[L];
+        SG_TRY(check(adam_step(w + o, m + o, v + o, g + o, s.dw_n[L], lr, kBeta1, kBeta2, kEps, c1, c2,
+                               (uint16_t*)s.d_wb.p + o, (uint16_t*)s.d_wt.p + o, kDisc[L].Co, 9, kDisc[L].Ci,
+                               c->stream),
+                     "discriminator adam"));
+        SG_TRY(check(adam_step(w + b, m + b, v + b, g + b, kDisc[L].Co, lr, kBeta1, kBeta2, kEps, c1, c2, nullptr,
+                               nullptr, 1, 1, 1, c->stream),
+                     "discriminator adam bias"));
+    }
+    return SG_OK;
+}
+
+// The adversarial part of one training step (pix2pix order), after the generator's forward and L1 loss:
+// discriminator step on (x, target) as real and (x, yhat) as fake, then the generator's adversarial
+// gradient through the updated discriminator, added into gy.  Losses: loss[1] = L_D, loss[2] = L_adv.
+sg_status adversarial_step(sg_ctx* c, Surrogate& s, int n, float lr)
+{
+    SG_TRY(disc_capacity(s, 2 * n));
+    const int64_t P = (int64_t)n * s.H * s.W;
+    const int64_t Pp = (int64_t)n * (s.H >> 3) * (s.W >> 3);   // patches per set
+    uint16_t* z = (uint16_t*)s.d_act[0].p;
+    SG_TRY(check(disc_input((const uint16_t*)s.act[X].p, (const float*)s.target.p, (const float*)s.yhat.p, z, P,
+                            c->stream),
+                 "discriminator input"));
+    SG_TRY(disc_forward(c, s, z, 2 * n));
+    const int bb = blocks_for(2 * Pp, 256);
+    SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)bb), "bce workspace"));
+    const float wd = 0.5f / (float)Pp;
+    SG_TRY(check(bce_logits((const float*)s.d_logits.p, kDiscLogitC, Pp, 2 * Pp, wd, wd, 1.f, (float*)s.d_glog.p,
+                            (float*)s.parts.p, bb, (float*)s.loss.p + 1, c->stream),
+                 "discriminator loss"));
+    SG_TRY(disc_backward(c, s, z, 2 * n, true, false));
+    SG_TRY(disc_adam(c, s, lr));
+    const uint16_t* zf = z + P * 8;   // the fake half
+    SG_TRY(disc_forward(c, s, zf, n));
+    SG_TRY(check(bce_logits((const float*)s.d_logits.p, kDiscLogitC, Pp, Pp, 1.f / (float)Pp, 0.f, s.adv_weight,
+                            (float*)s.d_glog.p, (float*)s.parts.p, bb, (float*)s.loss.p + 2, c->stream),
+                 "adversarial loss"));
+    SG_TRY(disc_backward(c, s, zf, n, false, true));
+    return check(add_channel((float*)s.gy.p, (const float*)s.d_g[0].p, 8, kDiscImageC, P, c->stream),
+                 "adversarial gradient");
+}
+
 sg_status check_frames(const Surrogate& s, int32_t n, const sg_probe* probes)
 {
     for (int i = 0; i < n; ++i)
@@ -554,17 +764,16 @@ extern "C" sg_status sg_surr_create(sg_ctx* c, int32_t H, int32_t W, uint64_t se
 extern "C" sg_status sg_surr_create_ct(sg_ctx* c, int32_t H, int32_t W, uint64_t seed, float adv_weight, int32_t* id)
 {
     if (!(adv_weight >= 0.f && adv_weight <= 1.f)) return fail(SG_EINVAL, "sg_surr_create_ct: adv_weight in [0, 1]");
-    if (adv_weight > 0.f) return fail(SG_EINVAL, "sg_surr_create_ct: the adversarial term is not available");
     SG_TRY(sg_surr_create(c, H, W, seed, id));
     Surrogate* s = find_surr(c, *id);
     s->ct = true;
     s->adv_weight = adv_weight;
-    const hipError_t e = s->ct_ref.ensure(sizeof(long long) * 2 * kCtBins);
-    if (e != hipSuccess) {
-        c->surrogates.erase(*id);
-        return hip_fail(e, "CT reference");
-    }
-    return SG_OK;
+    hipError_t e = s->ct_ref.ensure(sizeof(long long) * 2 * kCtBins);
+    if (e == hipSuccess) e = hipMemset(s->ct_ref.p, 0, sizeof(long long) * 2 * kCtBins);   // no reference yet
+    sg_status st = e == hipSuccess ? SG_OK : hip_fail(e, "CT reference");
+    if (st == SG_OK && adv_weight > 0.f) st = disc_create(c, *s, seed);
+    if (st != SG_OK) c->surrogates.erase(*id);
+    return st;
 }
 
 extern "C" sg_status sg_surr_set_ct_reference(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids,
@@ -619,6 +828,30 @@ extern "C" sg_status sg_surr_num_params(sg_ctx* c, int32_t id, int64_t* n)
     return SG_OK;
 }
 
+namespace sg {
+namespace {
+// forward, L1 (and adversarial) loss, backward and Adam on the batch in act[X] / target
+sg_status train_on_batch(sg_ctx* c, Surrogate& s, int32_t n, float lr, float* loss)
+{
+    SG_TRY(forward(c, s, n, true));
+    const int64_t P = (int64_t)n * s.H * s.W;
+    const int lb = blocks_for(P);
+    SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)lb), "loss workspace"));
+    SG_TRY(check(l1_loss((const float*)s.yhat.p, (const float*)s.target.p, P, (float*)s.gy.p, (float*)s.parts.p, lb,
+                         (float*)s.loss.p, c->stream),
+                 "loss"));
+    if (s.adv_weight > 0.f) SG_TRY(adversarial_step(c, s, n, lr));
+    SG_TRY(backward(c, s, n));
+    SG_TRY(adam(c, s, lr));
+    s.last_n = n;
+    hipError_t e = hipMemcpyAsync(s.last_loss, s.loss.p, sizeof(float) * 3, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    *loss = s.last_loss[0];
+    return check(e, "loss readback");
+}
+}  // namespace
+}  // namespace sg
+
 extern "C" sg_status sg_surr_train_step(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids,
                                         const sg_probe* probes, const double* poses, float lr, float* loss)
 {
@@ -630,19 +863,26 @@ extern "C" sg_status sg_surr_train_step(sg_ctx* c, int32_t id, int32_t n, const 
     SG_TRY(check_frames(*s, n, probes));
     SG_TRY(ensure_capacity(*s, n, true));
     SG_TRY(encode_and_render(c, *s, n, vol_ids, probes, poses, (float*)s->target.p));
-    SG_TRY(forward(c, *s, n, true));
+    return train_on_batch(c, *s, n, lr, loss);
+}
+
+extern "C" sg_status sg_surr_train_pairs(sg_ctx* c, int32_t id, int32_t n, int32_t H, int32_t W,
+                                         const uint16_t* input, const float* target, float lr, float* loss)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !input || !target || !loss) return fail(SG_EINVAL, "sg_surr_train_pairs: bad id or NULL");
+    if (n < 1 || n > 65535) return fail(SG_EINVAL, "sg_surr_train_pairs: n in [1, 65535]");
+    if (H != s->H || W != s->W)
+        return fail(SG_EINVAL, "sg_surr_train_pairs: %dx%d frames, the surrogate takes %dx%d", W, H, s->W, s->H);
+    if (!(lr >= 0.f) || !std::isfinite(lr)) return fail(SG_EINVAL, "sg_surr_train_pairs: bad learning rate");
+    (void)hipSetDevice(c->device);
+    SG_TRY(ensure_capacity(*s, n, true));
     const int64_t P = (int64_t)n * s->H * s->W;
-    const int lb = blocks_for(P);
-    SG_TRY(check(s->parts.ensure(sizeof(float) * (size_t)lb), "loss workspace"));
-    SG_TRY(check(l1_loss((const float*)s->yhat.p, (const float*)s->target.p, P, (float*)s->gy.p, (float*)s->parts.p,
-                         lb, (float*)s->loss.p, c->stream),
-                 "loss"));
-    SG_TRY(backward(c, *s, n));
-    SG_TRY(adam(c, *s, lr));
-    s->last_n = n;
-    hipError_t e = hipMemcpyAsync(loss, s->loss.p, sizeof(float), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    return check(e, "loss readback");
+    SG_TRY(check(hipMemcpyAsync(s->act[X].p, input, sizeof(uint16_t) * 8 * P, hipMemcpyDeviceToDevice, c->stream),
+                 "input copy"));
+    SG_TRY(check(hipMemcpyAsync(s->target.p, target, sizeof(float) * P, hipMemcpyDeviceToDevice, c->stream),
+                 "target copy"));
+    return train_on_batch(c, *s, n, lr, loss);
 }
 
 extern "C" sg_status sg_audit_decide(int32_t n_audit, const float* psnr, float psnr_min, float max_fail_frac,
@@ -736,7 +976,10 @@ extern "C" sg_status sg_surr_infer(sg_ctx* c, int32_t id, int32_t n, const int32
 
 namespace {
 const char kMagic[8] = {'S', 'G', 'S', 'U', 'R', 'R', '0', '1'};
-const char kMagicCt[8] = {'S', 'G', 'S', 'U', 'R', 'R', 'C', '1'};   // + the CT reference counts
+const char kMagicCt[8] = {'S', 'G', 'S', 'U', 'R', 'R', 'C', '1'};    // + the CT reference counts
+const char kMagicGan[8] = {'S', 'G', 'S', 'U', 'R', 'R', 'G', '1'};   // + the CT reference and the discriminator
+
+const char* magic_of(const Surrogate& s) { return s.adv_weight > 0.f ? kMagicGan : (s.ct ? kMagicCt : kMagic); }
 }
 
 extern "C" sg_status sg_surr_save(sg_ctx* c, int32_t id, const char* path)
@@ -753,14 +996,25 @@ extern "C" sg_status sg_surr_save(sg_ctx* c, int32_t id, const char* path)
     std::vector<long long> ref(s->ct ? kCtBins : 0);
     if (e == hipSuccess && s->ct)
         e = hipMemcpy(ref.data(), s->ct_ref.p, sizeof(long long) * kCtBins, hipMemcpyDeviceToHost);
+    const size_t dn = (size_t)s->dn_params;
+    std::vector<float> dbuf(3 * dn);
+    if (e == hipSuccess && dn) e = hipMemcpy(dbuf.data(), s->d_master.p, sizeof(float) * dn, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && dn) e = hipMemcpy(dbuf.data() + dn, s->d_mom1.p, sizeof(float) * dn, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && dn)
+        e = hipMemcpy(dbuf.data() + 2 * dn, s->d_mom2.p, sizeof(float) * dn, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "checkpoint readback");
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(SG_EINVAL, "cannot open %s for writing", path);
     const int32_t hw[2] = {s->H, s->W};
     const int64_t meta[2] = {s->n_params, s->step};
-    bool ok = std::fwrite(s->ct ? kMagicCt : kMagic, 1, 8, f) == 8 && std::fwrite(hw, sizeof(hw), 1, f) == 1 &&
+    bool ok = std::fwrite(magic_of(*s), 1, 8, f) == 8 && std::fwrite(hw, sizeof(hw), 1, f) == 1 &&
               std::fwrite(meta, sizeof(meta), 1, f) == 1 && std::fwrite(buf.data(), sizeof(float), 3 * n, f) == 3 * n;
     if (s->ct) ok = ok && std::fwrite(ref.data(), sizeof(long long), kCtBins, f) == (size_t)kCtBins;
+    if (dn) {
+        const int64_t dmeta[2] = {s->dn_params, s->d_step};
+        ok = ok && std::fwrite(dmeta, sizeof(dmeta), 1, f) == 1 &&
+             std::fwrite(dbuf.data(), sizeof(float), 3 * dn, f) == 3 * dn;
+    }
     ok = (std::fclose(f) == 0) && ok;
     return ok ? SG_OK : fail(SG_EINVAL, "write to %s failed", path);
 }
@@ -777,11 +1031,17 @@ extern "C" sg_status sg_surr_load(sg_ctx* c, int32_t id, const char* path)
     const size_t n = (size_t)s->n_params;
     std::vector<float> buf(3 * n);
     std::vector<long long> ref(2 * kCtBins, 0);
-    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, s->ct ? kMagicCt : kMagic, 8) == 0 &&
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, magic_of(*s), 8) == 0 &&
               std::fread(hw, sizeof(hw), 1, f) == 1 && std::fread(meta, sizeof(meta), 1, f) == 1 &&
               hw[0] == s->H && hw[1] == s->W && meta[0] == s->n_params &&
               std::fread(buf.data(), sizeof(float), 3 * n, f) == 3 * n;
     if (s->ct) ok = ok && std::fread(ref.data(), sizeof(long long), kCtBins, f) == (size_t)kCtBins;
+    const size_t dn = (size_t)s->dn_params;
+    std::vector<float> dbuf(3 * dn);
+    int64_t dmeta[2] = {0, 0};
+    if (dn)
+        ok = ok && std::fread(dmeta, sizeof(dmeta), 1, f) == 1 && dmeta[0] == s->dn_params &&
+             std::fread(dbuf.data(), sizeof(float), 3 * dn, f) == 3 * dn;
     std::fclose(f);
     long long tot = 0;
     for (int b = 0; b < kCtBins && s->ct; ++b) {
@@ -798,9 +1058,17 @@ extern "C" sg_status sg_surr_load(sg_ctx* c, int32_t id, const char* path)
     if (e == hipSuccess) e = hipMemcpy(s->mom2.p, buf.data() + 2 * n, sizeof(float) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess && s->ct)
         e = hipMemcpy(s->ct_ref.p, ref.data(), sizeof(long long) * 2 * kCtBins, hipMemcpyHostToDevice);
+    if (e == hipSuccess && dn) e = hipMemcpy(s->d_master.p, dbuf.data(), sizeof(float) * dn, hipMemcpyHostToDevice);
+    if (e == hipSuccess && dn) e = hipMemcpy(s->d_mom1.p, dbuf.data() + dn, sizeof(float) * dn, hipMemcpyHostToDevice);
+    if (e == hipSuccess && dn)
+        e = hipMemcpy(s->d_mom2.p, dbuf.data() + 2 * dn, sizeof(float) * dn, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "checkpoint upload");
     s->step = meta[1];
     if (s->ct) s->ct_n_ref = tot;
+    if (dn) {
+        s->d_step = dmeta[1];
+        SG_TRY(disc_refresh_bf16(c, *s));
+    }
     return refresh_bf16(c, *s);
 }
 
@@ -846,4 +1114,58 @@ extern "C" sg_status sg_surr_get_batch(sg_ctx* c, int32_t id, uint16_t* input, f
     if (e == hipSuccess && input) e = hipMemcpy(input, s->act[X].p, sizeof(uint16_t) * 8 * P, hipMemcpyDeviceToHost);
     if (e == hipSuccess && target) e = hipMemcpy(target, s->target.p, sizeof(float) * P, hipMemcpyDeviceToHost);
     return check(e, "batch readback");
+}
+
+extern "C" sg_status sg_surr_gan_losses(sg_ctx* c, int32_t id, float* loss_d, float* loss_adv)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !loss_d || !loss_adv) return fail(SG_EINVAL, "sg_surr_gan_losses: bad id or NULL");
+    if (s->adv_weight <= 0.f) return fail(SG_EINVAL, "sg_surr_gan_losses: the surrogate has no adversarial term");
+    if (s->last_n < 1) return fail(SG_ESTATE, "sg_surr_gan_losses: no training step yet");
+    *loss_d = s->last_loss[1];
+    *loss_adv = s->last_loss[2];
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_disc_num_params(sg_ctx* c, int32_t id, int64_t* n)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !n) return fail(SG_EINVAL, "sg_surr_disc_num_params: bad id or NULL");
+    if (s->adv_weight <= 0.f) return fail(SG_EINVAL, "sg_surr_disc_num_params: the surrogate has no discriminator");
+    *n = s->dn_params;
+    return SG_OK;
+}
+
+namespace {
+sg_status disc_copy(sg_ctx* c, int32_t id, float* host, int what, const char* name)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !host) return fail(SG_EINVAL, "%s: bad id or NULL", name);
+    if (s->adv_weight <= 0.f) return fail(SG_EINVAL, "%s: the surrogate has no discriminator", name);
+    (void)hipSetDevice(c->device);
+    const size_t bytes = sizeof(float) * s->dn_params;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) {
+        if (what == 0) e = hipMemcpy(host, s->d_master.p, bytes, hipMemcpyDeviceToHost);
+        if (what == 1) e = hipMemcpy(host, s->d_grad.p, bytes, hipMemcpyDeviceToHost);
+        if (what == 2) e = hipMemcpy(s->d_master.p, host, bytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_fail(e, name);
+    return what == 2 ? disc_refresh_bf16(c, *s) : SG_OK;
+}
+}  // namespace
+
+extern "C" sg_status sg_surr_disc_get_params(sg_ctx* c, int32_t id, float* host)
+{
+    return disc_copy(c, id, host, 0, "sg_surr_disc_get_params");
+}
+
+extern "C" sg_status sg_surr_disc_get_grads(sg_ctx* c, int32_t id, float* host)
+{
+    return disc_copy(c, id, host, 1, "sg_surr_disc_get_grads");
+}
+
+extern "C" sg_status sg_surr_disc_set_params(sg_ctx* c, int32_t id, const float* host)
+{
+    return disc_copy(c, id, const_cast<float*>(host), 2, "sg_surr_disc_set_params");
 }

@@ -40,11 +40,13 @@ struct ConvGeom {
     FastDiv f_c, f_co, f_kw, f_stride, f_howo, f_wo, f_hinwin, f_win;
 };
 
+constexpr float kLeakySlope = 0.2f;   // leaky ReLU of the discriminator
+
 struct ConvArgs {
     const uint16_t* a;       // forward: x; data gradient: dy; weight gradient: dy
     const uint16_t* b;       // forward: W [Co][K]; data gradient: WT [Ci][K]; weight gradient: x
     const float* bias;       // forward, may be null
-    int32_t relu;            // forward
+    int32_t relu;            // forward activation: 0 none, 1 ReLU, 2 leaky ReLU (kLeakySlope)
     const uint16_t* skip;    // forward: second output = out + skip (may be null)
     uint16_t* out2_bf16;
     int32_t ld_out2;         // channels per pixel of out2 (0: Co); out2 may be wider than the conv's output
@@ -116,10 +118,19 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
 bool conv_tile_supported(const ConvGeom& g);
 int wgrad_tile_m(int M);
 hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s);
-// out = bf16(g * [y > 0]) over [rows][C] and bias_grad[c] = sum of out's column c (C <= 256);
-// g has ldg floats per row (0: C)
+// out = bf16(g * (y > 0 ? 1 : slope)) over [rows][C] (y null: out = bf16(g)) and bias_grad[c] = sum of
+// out's column c (C <= 256); g has ldg floats per row (0: C)
 hipError_t mask_colsum(const float* g, int ldg, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
-                       int blocks, float* bias_grad, hipStream_t s);
+                       int blocks, float* bias_grad, hipStream_t s, float slope = 0.f);
+// discriminator input of P real and P fake pixels (see k_disc_input)
+hipError_t disc_input(const uint16_t* x, const float* y_real, const float* y_fake, uint16_t* z, int64_t P,
+                      hipStream_t s);
+// binary cross-entropy on logits (channel 0 of rows of ld floats): rows < P_real label 1, the rest label 0;
+// *loss = sum of w * softplus(-+l), grad = gscale * w * (sigmoid(l) - label)
+hipError_t bce_logits(const float* logits, int ld, int64_t P_real, int64_t P_total, float w_real, float w_fake,
+                      float gscale, float* grad, float* part, int blocks, float* loss, hipStream_t s);
+// gy[p] += dz[p * ld + c]
+hipError_t add_channel(float* gy, const float* dz, int ld, int c, int64_t P, hipStream_t s);
 // depth integral down each column (rows above only), times scale, of the 1x1 map p = w e + b of the bf16
 // tensor e [N][H][W][16] (w bf16 [8][16], b FP32 [8]), into channels [c_off, c_off + 8) of the bf16 tensor
 // out [N][H][W][ld]

@@ -29,7 +29,8 @@ SYMBOLS = (
     "sg_recon_reset", "sg_recon_destroy",
     "sg_conv_forward", "sg_conv_backward_data", "sg_conv_backward_weight",
     "sg_surr_create", "sg_surr_create_ct", "sg_surr_set_ct_reference", "sg_surr_destroy", "sg_surr_num_params",
-    "sg_surr_train_step", "sg_surr_infer",
+    "sg_surr_train_step", "sg_surr_infer", "sg_surr_train_pairs", "sg_surr_gan_losses", "sg_surr_disc_num_params",
+    "sg_surr_disc_get_params", "sg_surr_disc_get_grads", "sg_surr_disc_set_params",
     "sg_audit_decide", "sg_surr_save", "sg_surr_load", "sg_surr_get_params", "sg_surr_get_grads",
     "sg_surr_set_params", "sg_surr_get_batch",
 )
@@ -116,6 +117,12 @@ def load():
         "sg_surr_create_ct": [VP, I32, I32, C.c_uint64, C.c_float, P(I32)],
         "sg_surr_set_ct_reference": [VP, I32, I32, VP, VP, VP, VP],
         "sg_surr_destroy": [VP, I32],
+        "sg_surr_train_pairs": [VP, I32, I32, I32, I32, VP, VP, C.c_float, P(C.c_float)],
+        "sg_surr_gan_losses": [VP, I32, P(C.c_float), P(C.c_float)],
+        "sg_surr_disc_num_params": [VP, I32, P(C.c_int64)],
+        "sg_surr_disc_get_params": [VP, I32, VP],
+        "sg_surr_disc_get_grads": [VP, I32, VP],
+        "sg_surr_disc_set_params": [VP, I32, VP],
         "sg_surr_num_params": [VP, I32, P(C.c_int64)],
         "sg_surr_train_step": [VP, I32, I32, VP, VP, VP, C.c_float, P(C.c_float)],
         "sg_surr_infer": [VP, I32, I32, VP, VP, VP, VP, VP, I32, C.c_float, C.c_float, VP, P(I32)],
@@ -350,6 +357,50 @@ def sg_surr_set_ct_reference(ctx, sid, vol_ids, probes, poses) -> np.ndarray:
     _check(load().sg_surr_set_ct_reference(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p),
                                            ps.ctypes.data, h.ctypes.data), "sg_surr_set_ct_reference")
     return h
+
+
+def sg_surr_train_pairs(ctx, sid, inp, target, lr) -> float:
+    """inp: device bf16 bits (2-byte tensor, n x H x W x 8); target: device float32 (n x H x W)."""
+    if target.dim() != 3 or target.element_size() != 4 or inp.element_size() != 2:
+        raise ValueError("target must be float32 [n, H, W] and inp 2-byte [n, H, W, 8]")
+    n, H, W = (int(v) for v in target.shape)
+    if tuple(inp.shape) != (n, H, W, 8):
+        raise ValueError(f"inp shape {tuple(inp.shape)} != {(n, H, W, 8)}")
+    loss = C.c_float()
+    _check(load().sg_surr_train_pairs(ctx, int(sid), n, H, W, _dptr(inp), _dptr(target), float(lr), C.byref(loss)),
+           "sg_surr_train_pairs")
+    return float(loss.value)
+
+
+def sg_surr_gan_losses(ctx, sid):
+    """(L_D, L_adv) of the last training step."""
+    a, b = C.c_float(), C.c_float()
+    _check(load().sg_surr_gan_losses(ctx, int(sid), C.byref(a), C.byref(b)), "sg_surr_gan_losses")
+    return float(a.value), float(b.value)
+
+
+def sg_surr_disc_num_params(ctx, sid) -> int:
+    n = C.c_int64()
+    _check(load().sg_surr_disc_num_params(ctx, int(sid), C.byref(n)), "sg_surr_disc_num_params")
+    return int(n.value)
+
+
+def sg_surr_disc_get_params(ctx, sid) -> np.ndarray:
+    h = np.zeros(sg_surr_disc_num_params(ctx, sid), dtype=np.float32)
+    _check(load().sg_surr_disc_get_params(ctx, int(sid), h.ctypes.data), "sg_surr_disc_get_params")
+    return h
+
+
+def sg_surr_disc_get_grads(ctx, sid) -> np.ndarray:
+    h = np.zeros(sg_surr_disc_num_params(ctx, sid), dtype=np.float32)
+    _check(load().sg_surr_disc_get_grads(ctx, int(sid), h.ctypes.data), "sg_surr_disc_get_grads")
+    return h
+
+
+def sg_surr_disc_set_params(ctx, sid, host):
+    h = np.ascontiguousarray(host, dtype=np.float32)
+    assert h.size == sg_surr_disc_num_params(ctx, sid)
+    _check(load().sg_surr_disc_set_params(ctx, int(sid), h.ctypes.data), "sg_surr_disc_set_params")
 
 
 def sg_surr_destroy(ctx, sid):
