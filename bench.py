@@ -94,6 +94,60 @@ def ray_traffic_bytes():
     return int(b.group(1))
 
 
+def ct_surrogate_leg(train_steps: int, n_envs: int = 256, batch: int = 32, audit_frac: int = 16,
+                     psnr_min: float = 25.0):
+    """CT-conditioned surrogate with histogram matching and the adversarial
+    term (weight 0.01): train on spine CT phantom pairs, then audited
+    inference of n_envs frames on held-out phantoms beside physics."""
+    import numpy as np
+    import torch
+
+    from paper_2507_01152_amd import sonosim as sg
+    from paper_2507_01152_amd.train_surrogate import CT_FRAME_H, CT_FRAME_W, CtPairSource, train_ct
+
+    sess, sid, _src, step_s, last = train_ct(train_steps, batch, 1e-3, adv_weight=0.01, log=lambda s: None)
+    test_src = CtPairSource(sess, 4, seed0=9000)     # held-out phantoms
+    rng = np.random.default_rng(77)
+    vids, probes, poses = test_src.batch(n_envs, rng)
+    audit = np.sort(np.random.Generator(np.random.Philox(key=9)).choice(n_envs, n_envs // audit_frac,
+                                                                         replace=False)).astype(np.int32)
+    HW = CT_FRAME_W * CT_FRAME_H
+    out = torch.empty(n_envs * HW, dtype=torch.float32, device=sess.device)
+    sg.sg_surr_infer(sess.ctx, sid, vids, probes, poses, out, audit, psnr_min, 0.25)   # warm-up
+    reps = 5
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        psnr, n_fb = sg.sg_surr_infer(sess.ctx, sid, vids, probes, poses, out, audit, psnr_min, 0.25)
+    surr_s = (time.perf_counter() - t) / reps
+    all_psnr, _ = sg.sg_surr_infer(sess.ctx, sid, vids[:64], probes[:64], poses[:64], out, list(range(64)),
+                                   -np.inf, 1.0)
+    offs = np.arange(n_envs, dtype=np.int64) * HW
+    plan = sg.sg_batch_plan_create(sess.ctx, vids, probes, offs)
+    sg.sg_batch_set_poses(sess.ctx, plan, poses)
+    for _ in range(3):
+        sg.sg_batch_step(sess.ctx, plan, out)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(20):
+        sg.sg_batch_step(sess.ctx, plan, out)
+    torch.cuda.synchronize()
+    phys_s = (time.perf_counter() - t) / 20
+    sess.close()
+    return {
+        "workload": f"{n_envs} envs, {CT_FRAME_W}x{CT_FRAME_H} frames at 0.5 mm on held-out 256^3 spine CT "
+                    f"phantoms, histogram-matched CT input, 1/{audit_frac} seeded physics audit at PSNR >= "
+                    f"{psnr_min} dB",
+        "frames_per_s": round(n_envs / surr_s, 1),
+        "physics_frames_per_s_same_workload": round(n_envs / phys_s, 1),
+        "psnr_audit_mean_db": round(float(np.mean(psnr)), 2),
+        "psnr_held_out_64_mean_db": round(float(np.mean(all_psnr)), 2),
+        "frames_from_physics": int(n_fb),
+        "train": {"steps": train_steps, "batch": batch, "pairs": train_steps * batch, "adv_weight": 0.01,
+                  "ms_per_step": round(step_s * 1e3, 2), "pairs_per_s": round(batch / step_s, 1), "last": last},
+    }
+
+
 def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, psnr_min: float = 30.0):
     """Train the surrogate on physics pairs for a fixed budget, then time
     audited inference of n_envs 128 x 256 frames beside the physics path on
@@ -170,6 +224,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--profile-launches", type=int, default=20)
+    ap.add_argument("--ct-surrogate-steps", type=int, default=1500,
+                    help="training steps (batch 32) of the CT-conditioned surrogate with the adversarial term; "
+                         "0 skips it")
     ap.add_argument("--surrogate-steps", type=int, default=3125,
                     help="training steps (batch 64; 3125 = 200k pairs) before timing surrogate inference; "
                          "0 skips the surrogate")
@@ -365,6 +422,10 @@ def main():
     if args.surrogate_steps > 0:
         sess.close()
         res["surrogate"] = surrogate_leg(args.surrogate_steps)
+    if args.ct_surrogate_steps > 0:
+        if sess.ctx is not None:
+            sess.close()
+        res["ct_surrogate"] = ct_surrogate_leg(args.ct_surrogate_steps)
     if args.copy_probe:
         src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=sess.device)
         dst = torch.empty_like(src)

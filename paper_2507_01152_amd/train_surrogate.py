@@ -7,6 +7,10 @@ renders the targets and encodes the inputs on the GPU.  Held-out phantoms
 measure the PSNR of the network against the physics frames (through the
 audited inference path).
 
+The CT-conditioned surrogate (train_ct) learns from 256^3 spine phantoms
+with CT, 128 x 256 frames at 0.5 mm, histogram-matched CT input and the
+adversarial term.
+
     python -m paper_2507_01152_amd.train_surrogate --steps 3000 --batch 64 --ckpt surr.bin
 """
 from __future__ import annotations
@@ -44,6 +48,59 @@ class PairSource:
         vids = self.ids[rng.integers(0, len(self.ids), n)]
         poses = np.stack([s.pose_from(s.random_rotation(rng), rng.uniform(16, 48, 3)) for _ in range(n)])
         return vids, [self.probe] * n, poses
+
+
+CT_FRAME_W, CT_FRAME_H, CT_PIXEL_MM, CT_DIMS = 128, 256, 0.5, (256, 256, 256)
+
+
+class CtPairSource:
+    """Spine phantoms with CT (256^3 labels + int16 HU, 1 mm voxels) on the
+    device and probe poses on the back (the CT workload's pose sampler)."""
+
+    def __init__(self, sess, n_volumes: int, seed0: int):
+        import synth
+        from . import sonosim as sg
+        self.synth = synth
+        self.geoms, ids = [], []
+        for i in range(n_volumes):
+            lab, geom = synth.spine_volume(CT_DIMS, seed0 + i)
+            vol = synth.Volume(labels=lab, ct=synth.ct_from_labels(lab, seed0 + i), seed=0xC7000000 + seed0 + i)
+            ids.append(sess.register(vol))
+            self.geoms.append(geom)
+        self.ids = np.array(ids, dtype=np.int32)
+        sg.sg_tissue_table_set(sess.ctx, synth.default_tissue_table())
+        self.probe = synth.Probe(W=CT_FRAME_W, H=CT_FRAME_H, dx=CT_PIXEL_MM, dy=CT_PIXEL_MM)
+
+    def batch(self, n: int, rng: np.random.Generator):
+        k = rng.integers(0, len(self.ids), n)
+        poses = np.stack([self.synth.spine_pose(self.geoms[i], CT_DIMS[1], rng) for i in k])
+        return self.ids[k], [self.probe] * n, poses
+
+
+def train_ct(steps: int, batch: int, lr: float, adv_weight: float = 0.01, seed: int = 0, n_train_vols: int = 16,
+             n_ref_frames: int = 64, log=print):
+    """CT-conditioned surrogate with the adversarial term: the histogram
+    reference is pooled over n_ref_frames training frames, then every step
+    draws a fresh batch of (phantom, pose) pairs.  Returns (session,
+    surrogate id, training source, per-step wall seconds, last losses)."""
+    from . import sonosim as sg
+    from .session import Session
+    sess = Session(0)
+    src = CtPairSource(sess, n_train_vols, seed0=7000)
+    sid = sg.sg_surr_create_ct(sess.ctx, CT_FRAME_H, CT_FRAME_W, seed=seed, adv_weight=adv_weight)
+    rng = np.random.default_rng(seed + 11)
+    sg.sg_surr_set_ct_reference(sess.ctx, sid, *src.batch(n_ref_frames, rng))
+    t0 = time.time()
+    last = None
+    for step in range(1, steps + 1):
+        cur = lr if step < 0.7 * steps else lr * 0.1
+        loss = sg.sg_surr_train_step(sess.ctx, sid, *src.batch(batch, rng), cur)
+        if step == steps or step % 200 == 0:
+            ld, la = sg.sg_surr_gan_losses(sess.ctx, sid) if adv_weight > 0 else (0.0, 0.0)
+            last = {"step": step, "l1": round(loss, 5), "loss_d": round(ld, 4), "loss_adv": round(la, 4),
+                    "wall_s": round(time.time() - t0, 1)}
+            log(json.dumps(last))
+    return sess, sid, src, (time.time() - t0) / max(1, steps), last
 
 
 def evaluate(sess, sid, src: PairSource, n: int = 64, seed: int = 123):

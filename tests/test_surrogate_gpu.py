@@ -147,23 +147,46 @@ def test_encoder_channels_match_oracle(sess):
     sg.sg_surr_destroy(sess.ctx, sid)
 
 
+def _label_problem(seed, n, H, W):
+    """Seeded parameters and label-mode input pairs (one-hot label, gated
+    scatterer sample, depth) with a target that depends on them."""
+    rng = np.random.default_rng(seed)
+    layout, ng = so.param_layout()
+    g = np.zeros(ng)
+    for name, o, shape in layout:
+        sz = int(np.prod(shape))
+        if name.startswith("w") or name in ("wp", "head_w"):
+            fan = int(np.prod(shape[1:])) if len(shape) > 1 else int(shape[0])
+            g[o:o + sz] = rng.standard_normal(sz) * np.sqrt(2.0 / fan)
+        else:
+            g[o:o + sz] = rng.standard_normal(sz) * 0.02
+    x = np.zeros((n, H, W, 8))
+    lab = rng.integers(0, 4, size=(n, H, W))
+    x[..., :4] = np.eye(4)[lab]
+    x[..., 4] = so.bf16_round(np.where(rng.uniform(size=(n, H, W)) < 0.3, rng.standard_normal((n, H, W)), 0.0))
+    x[..., 5] = so.bf16_round((np.arange(H) + 0.5) / H)[None, :, None]
+    y = np.clip(0.2 * lab + 0.1 * x[..., 4] + 0.05 * rng.standard_normal((n, H, W)), 0, 1).astype(np.float32)
+    return g.astype(np.float32), x, y
+
+
 def test_training_gradients_match_oracle(sess):
     """Every layer's gradient of one training step against the FP64 network
-    oracle on the same bf16 input and target.  bf16 rounding flips of single
+    oracle on the same seeded parameters, bf16 input and target (given to the
+    library through sg_surr_train_pairs).  bf16 rounding flips of single
     activations (FP32 vs FP64 sums) make the layers differ by about 1e-3 to
     1e-2 in norm.  The flips matter most in the deepest levels, which have
     the fewest pixels, so the batch is 4 frames of 128 x 64 (8 x 4 at the
     bottleneck); the noise falls as one over the root of the pixel count."""
     from paper_2507_01152_amd import sonosim as sg
     H, W, n = 128, 64, 4
-    wl = _pairs(n, H, W, seed=5)
-    vids = sess.load(wl)
+    p0, x, y = _label_problem(5, n, H, W)
+    xin = torch.from_numpy(so.f64_to_bf16_bits(x).view(np.int16)).cuda()
+    tgt = torch.from_numpy(y).cuda()
     sid = sg.sg_surr_create(sess.ctx, H, W, seed=11)
-    p0 = sg.sg_surr_get_params(sess.ctx, sid)
-    loss = sg.sg_surr_train_step(sess.ctx, sid, vids, wl.probes, wl.poses, 0.0)
+    sg.sg_surr_set_params(sess.ctx, sid, p0)
+    loss = sg.sg_surr_train_pairs(sess.ctx, sid, xin, tgt, 0.0)
     g = sg.sg_surr_get_grads(sess.ctx, sid).astype(np.float64)
-    xin, tgt = sg.sg_surr_get_batch(sess.ctx, sid, n, H, W)
-    ref_loss, ref_g, _ = so.loss_and_grads(p0.astype(np.float64), so.bf16_bits_to_f64(xin), tgt.astype(np.float64))
+    ref_loss, ref_g, _ = so.loss_and_grads(p0.astype(np.float64), x, y.astype(np.float64))
     assert abs(loss - ref_loss) <= 1e-3 * ref_loss
     layout, _ = so.param_layout()
     report = []
@@ -179,14 +202,35 @@ def test_training_gradients_match_oracle(sess):
     # one Adam step from zero moments moves each weight by lr * g / (|g| + eps)
     lr = 1e-3
     sid2 = sg.sg_surr_create(sess.ctx, H, W, seed=11)
-    sg.sg_surr_train_step(sess.ctx, sid2, vids, wl.probes, wl.poses, lr)
+    sg.sg_surr_set_params(sess.ctx, sid2, p0)
+    sg.sg_surr_train_pairs(sess.ctx, sid2, xin, tgt, lr)
     g2 = sg.sg_surr_get_grads(sess.ctx, sid2).astype(np.float64)
     p1 = sg.sg_surr_get_params(sess.ctx, sid2).astype(np.float64)
+    assert np.array_equal(g2, g)   # the same batch gives the same gradient
     expect = p0 - lr * g2 / (np.abs(g2) + 1e-8)
     # FP32 bias corrections (0.999 is not exact in FP32) allow ~1e-5 relative
     assert np.allclose(p1, expect, rtol=1e-4, atol=1e-6 * lr)
     sg.sg_surr_destroy(sess.ctx, sid)
     sg.sg_surr_destroy(sess.ctx, sid2)
+
+
+def test_encoded_pairs_train_like_given_pairs(sess):
+    """sg_surr_train_step (encoder + physics) and sg_surr_train_pairs on the
+    batch it encoded and rendered give the same step, bit for bit."""
+    from paper_2507_01152_amd import sonosim as sg
+    H, W, n = 64, 32, 2
+    wl = _pairs(n, H, W, seed=5)
+    vids = sess.load(wl)
+    a = sg.sg_surr_create(sess.ctx, H, W, seed=3)
+    b = sg.sg_surr_create(sess.ctx, H, W, seed=3)
+    la = sg.sg_surr_train_step(sess.ctx, a, vids, wl.probes, wl.poses, 1e-3)
+    xin, tgt = sg.sg_surr_get_batch(sess.ctx, a, n, H, W)
+    lb = sg.sg_surr_train_pairs(sess.ctx, b, torch.from_numpy(xin.view(np.int16)).cuda(),
+                                torch.from_numpy(tgt).cuda(), 1e-3)
+    assert la == lb
+    assert np.array_equal(sg.sg_surr_get_params(sess.ctx, a), sg.sg_surr_get_params(sess.ctx, b))
+    for s in (a, b):
+        sg.sg_surr_destroy(sess.ctx, s)
 
 
 def test_checkpoint_resume_is_bit_exact(sess, tmp_path):
