@@ -86,16 +86,24 @@ __device__ __forceinline__ int32_t voxel_at(const EnvDev& e, const VolDev& v, in
     return in ? (iz * v.ny + iy) * v.nx + ix : -1;
 }
 
+// Volume reads through the global address space: the volume pointers are
+// read from memory, so plain dereferences compile to flat loads.
+template <typename T>
+__device__ __forceinline__ T ld_global(const T* p, int64_t i)
+{
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+
 __device__ __forceinline__ int label_of(const VolDev& v, int32_t vox)
 {
-    return vox >= 0 ? (int)v.labels[vox] : 0;
+    return vox >= 0 ? (int)ld_global(v.labels, vox) : 0;
 }
 
 __device__ __forceinline__ double ct_corner(const VolDev& v, int32_t ix, int32_t iy, int32_t iz)
 {
     const bool in = (uint32_t)ix < (uint32_t)v.nx && (uint32_t)iy < (uint32_t)v.ny &&
                     (uint32_t)iz < (uint32_t)v.nz;
-    return in ? (double)v.ct[(iz * v.ny + iy) * v.nx + ix] : -1000.0;
+    return in ? (double)ld_global(v.ct, (iz * v.ny + iy) * v.nx + ix) : -1000.0;
 }
 
 // impedance from CT: max(HU + 1000, 0), HU trilinear in FP64 (successive
@@ -145,7 +153,7 @@ __device__ __forceinline__ int label_at_q(const VolDev& v, int32_t q0, int32_t q
     const int32_t iz = (int32_t)((uint32_t)q2 + 32768u) >> 16;
     const bool in = (uint32_t)ix < (uint32_t)v.nx && (uint32_t)iy < (uint32_t)v.ny &&
                     (uint32_t)iz < (uint32_t)v.nz;
-    return in ? (int)v.labels[(iz * v.ny + iy) * v.nx + ix] : 0;
+    return in ? (int)ld_global(v.labels, (iz * v.ny + iy) * v.nx + ix) : 0;
 }
 
 // cos(theta): Sobel (1,2,1) on [label differs from the centre label] with
@@ -542,13 +550,14 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
     constexpr int kPT = kPW * kWave;     // threads
     extern __shared__ float lds[];
     __shared__ float s_klat[kTaps];
-    __shared__ int s_item;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    for (;;) {
-        const int item = next_item(&q->next_psf, &s_item);
-        if (item >= a.n_psf) break;
+    // tiles are uniform in cost: block b takes tiles b, b + G, b + 2G, ... (G: the
+    // grid).  A shared work counter costs more here than it balances: its
+    // same-address atomics serialise across the XCDs.
+    for (int item = blockIdx.x; item < a.n_psf; item += gridDim.x) {
+        __syncthreads();   // LDS of the previous tile is free
         const ItemPsf it = a.psf_items[item];
         const EnvDev e = a.envs[it.env];
         const int W = e.W, H = e.H, rl = e.rlat;
@@ -713,6 +722,7 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
             if (x < W && yy < H) a.out[e.out_off + (int64_t)yy * W + x] = sY[rr * (TX + 1) + cx];
         }
     }
+    (void)q;   // the queue counter is reset by the step but unused here
 }
 
 // Surrogate input of each pixel: one-hot label (channels 0..3), the
@@ -771,7 +781,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(PhysArgs a, uint16_t* enc)
 __device__ __forceinline__ int ct_bin(const EnvDev& e, const VolDev& v, int x, int y, int32_t& vox)
 {
     vox = voxel_at(e, v, x, y);
-    const int hu = (vox >= 0 && v.ct) ? (int)v.ct[vox] : -1000;
+    const int hu = (vox >= 0 && v.ct) ? (int)ld_global(v.ct, vox) : -1000;
     return min(max(hu + 1024, 0), kCtBins - 1);
 }
 
