@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--launch-shape", default=None, metavar="SPW,TX,CHUNKS",
+                    help="fixed launch shape of the physics step instead of the autotuner's")
     ap.add_argument("--profile-launches", type=int, default=20)
     ap.add_argument("--ct-surrogate-steps", type=int, default=1500,
                     help="training steps (batch 32) of the CT-conditioned surrogate with the adversarial term; "
@@ -261,7 +263,9 @@ def main():
     plan = sg.sg_batch_plan_create(sess.ctx, vids, wl.probes, offs)
     sg.sg_batch_set_poses(sess.ctx, plan, wl.poses)
     out = torch.empty(total, dtype=torch.float32, device=sess.device)
-    if not args.no_tune:
+    if args.launch_shape:
+        sg.sg_batch_set_config(sess.ctx, plan, *(int(v) for v in args.launch_shape.split(",")))
+    elif not args.no_tune:
         sg.sg_autotune(sess.ctx, plan, os.environ.get("SG_TUNE_CACHE", "/tmp/sonosim_tune.jsonl"))
     spw, tx, ty, chunks = sg.sg_batch_config(sess.ctx, plan)
 

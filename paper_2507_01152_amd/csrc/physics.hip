@@ -552,7 +552,7 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
     __shared__ float s_klat[kTaps];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    const int wave = tid / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);   // wave-uniform: scalar column bases
     // tiles are uniform in cost: block b takes tiles b, b + G, b + 2G, ... (G: the
     // grid).  A shared work counter costs more here than it balances: its
     // same-address atomics serialise across the XCDs.
@@ -585,19 +585,20 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
             float vr[NCR], vt[NCR], ve[NCE];
 #pragma unroll
             for (int u = 0; u < NCR; ++u) {
-                const int c = wave + u * kPW;
+                const int c = wave + u * kPW;            // wave-uniform column
                 const int gx = x0 - kRB + c;
-                const bool in = yin && c < CWF && gx >= 0 && gx < W;
-                const int64_t off = in ? (int64_t)gx * H + gy : 0;
-                vr[u] = in ? gR[off] : 0.f;
-                vt[u] = in ? gT[off] : 0.f;
+                const bool col = c < CWF && gx >= 0 && gx < W;
+                const int64_t base = (int64_t)(col ? gx : 0) * H;
+                vr[u] = (col && yin) ? gR[base + gy] : 0.f;
+                vt[u] = (col && yin) ? gT[base + gy] : 0.f;
             }
 #pragma unroll
             for (int u = 0; u < NCE; ++u) {
                 const int c = wave + u * kPW;
                 const int gx = x0 + c;
-                const bool in = yin && c < TX && gx < W;
-                ve[u] = in ? gE[(int64_t)gx * H + gy] : 0.f;
+                const bool col = c < TX && gx < W;
+                const int64_t base = (int64_t)(col ? gx : 0) * H;
+                ve[u] = (col && yin) ? gE[base + gy] : 0.f;
             }
 #pragma unroll
             for (int u = 0; u < NCR; ++u) {
@@ -716,10 +717,13 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
             }
         }
         __syncthreads();
-        for (int idx = tid; idx < TX * kTileRows; idx += kPT) {
-            const int cx = idx % TX, rr = idx / TX;
-            const int x = x0 + cx, yy = y0 + rr;
-            if (x < W && yy < H) a.out[e.out_off + (int64_t)yy * W + x] = sY[rr * (TX + 1) + cx];
+        // whole rows per wave from a scalar row base: row rr = wave + k kPW, lane = column
+        for (int rr = wave; rr < kTileRows; rr += kPW) {
+            const int yy = y0 + rr;
+            if (yy >= H) break;
+            float* orow = a.out + e.out_off + (int64_t)yy * W + x0;
+            for (int cx = lane; cx < TX; cx += kWave)
+                if (x0 + cx < W) orow[cx] = sY[rr * (TX + 1) + cx];
         }
     }
     (void)q;   // the queue counter is reset by the step but unused here
