@@ -156,40 +156,6 @@ __device__ __forceinline__ int label_at_q(const VolDev& v, int32_t q0, int32_t q
     return in ? (int)ld_global(v.labels, (iz * v.ny + iy) * v.nx + ix) : 0;
 }
 
-// cos(theta): Sobel (1,2,1) on [label differs from the centre label] with
-// clamped image coordinates, in physical units (only evaluated at G = 1).
-// q: Q16 position of (x, y); lab_up / lab_dn: labels of (x, y-1) / (x, y+1)
-// (already clamped); side columns are stepped from q by +-DX, +-DY.
-__device__ __forceinline__ float incidence_cos(const EnvDev& e, const VolDev& v, const int32_t q[3], int x, int y,
-                                              int lab, int lab_up, int lab_dn)
-{
-    const int xl = x > 0 ? -1 : 0, xr = x < e.W - 1 ? 1 : 0;
-    const int yu = y > 0 ? -1 : 0, yd = y < e.H - 1 ? 1 : 0;
-    int b[3][3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int yo = j == 0 ? yu : (j == 1 ? 0 : yd);
-#pragma unroll
-        for (int i = 0; i < 3; i += 2) {
-            const int xo = i == 0 ? xl : xr;
-            int32_t p[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                p[c] = (int32_t)((uint32_t)q[c] + (uint32_t)(xo * e.DX[c]) + (uint32_t)(yo * e.DY[c]));
-            b[j][i] = label_at_q(v, p[0], p[1], p[2]) != lab;
-        }
-    }
-    b[0][1] = lab_up != lab;
-    b[1][1] = 0;
-    b[2][1] = lab_dn != lab;
-    float gx = (float)((b[0][2] - b[0][0]) + 2 * (b[1][2] - b[1][0]) + (b[2][2] - b[2][0]));
-    float gy = (float)((b[2][0] - b[0][0]) + 2 * (b[2][1] - b[0][1]) + (b[2][2] - b[0][2]));
-    gx = gx / e.dx;
-    gy = gy / e.dy;
-    const float h = sqrtf(gx * gx + gy * gy);
-    return h == 0.f ? 1.f : fabsf(gy) / h;
-}
-
 __device__ __forceinline__ float uniform24(uint32_t w)
 {
     // (2*(w >> 9) + 1) * 2^-24: odd 24-bit numerator, exact in FP32
@@ -307,6 +273,63 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// cos(theta): Sobel (1,2,1) on [label differs from the centre label] with
+// clamped image coordinates, in physical units, where G is set.  Evaluated
+// by the whole wave (lane = row of a 64-row chunk starting at y0) with one
+// label gather per side column (x -+ 1) per lane: the side labels of rows
+// y - 1 and y + 1 come from the neighbouring lanes, those of the rows just
+// outside the chunk from gathers that run only when an edge lane needs them.
+// q: Q16 position of (x, y); lab_up / lab_dn: labels of (x, y-1) / (x, y+1)
+// (already clamped).  Every lane must call it (uniform control flow).
+__device__ __forceinline__ float incidence_cos_wave(const EnvDev& e, const VolDev& v, const int32_t q[3], int x,
+                                                   int y0, int lane, bool G, int lab, int lab_up, int lab_dn)
+{
+    const int xl = x > 0 ? -1 : 0, xr = x < e.W - 1 ? 1 : 0;
+    uint32_t ol[3], orr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ol[c] = (uint32_t)(xl * e.DX[c]);
+        orr[c] = (uint32_t)(xr * e.DX[c]);
+    }
+    const int sl = label_at_q(v, (int32_t)((uint32_t)q[0] + ol[0]), (int32_t)((uint32_t)q[1] + ol[1]),
+                              (int32_t)((uint32_t)q[2] + ol[2]));
+    const int sr = label_at_q(v, (int32_t)((uint32_t)q[0] + orr[0]), (int32_t)((uint32_t)q[1] + orr[1]),
+                              (int32_t)((uint32_t)q[2] + orr[2]));
+    // rows y - 1 and y + 1 from lanes - 1 and + 1 (lanes 0 and 63 keep their own row: the clamp at the image's
+    // top and bottom rows)
+    int sl_up = dpp_i<kWaveShr1>(sl, sl), sr_up = dpp_i<kWaveShr1>(sr, sr);
+    int sl_dn = dpp_i<kWaveShl1>(sl, sl), sr_dn = dpp_i<kWaveShl1>(sr, sr);
+    const uint64_t gm = __builtin_amdgcn_ballot_w64(G);
+    const bool top = (gm & 1ull) && y0 > 0;             // lane 0 needs row y0 - 1
+    const bool bot = (gm >> (kWave - 1)) & 1ull;       // lane 63 needs row y0 + 64 (G implies it is inside)
+    if (top || bot) {
+        const uint32_t dy = lane == 0 ? (uint32_t)(-e.DY[0]) : (uint32_t)e.DY[0];
+        const uint32_t dy1 = lane == 0 ? (uint32_t)(-e.DY[1]) : (uint32_t)e.DY[1];
+        const uint32_t dy2 = lane == 0 ? (uint32_t)(-e.DY[2]) : (uint32_t)e.DY[2];
+        const int el = label_at_q(v, (int32_t)((uint32_t)q[0] + ol[0] + dy), (int32_t)((uint32_t)q[1] + ol[1] + dy1),
+                                  (int32_t)((uint32_t)q[2] + ol[2] + dy2));
+        const int er = label_at_q(v, (int32_t)((uint32_t)q[0] + orr[0] + dy),
+                                  (int32_t)((uint32_t)q[1] + orr[1] + dy1), (int32_t)((uint32_t)q[2] + orr[2] + dy2));
+        if (lane == 0 && top) {
+            sl_up = el;
+            sr_up = er;
+        }
+        if (lane == kWave - 1 && bot) {
+            sl_dn = el;
+            sr_dn = er;
+        }
+    }
+    const int b00 = sl_up != lab, b02 = sr_up != lab, b10 = sl != lab, b12 = sr != lab;
+    const int b20 = sl_dn != lab, b22 = sr_dn != lab, b01 = lab_up != lab, b21 = lab_dn != lab;
+    const int sx = (b02 - b00) + 2 * (b12 - b10) + (b22 - b20);
+    const int sy = (b20 - b00) + 2 * (b21 - b01) + (b22 - b02);
+    // |gy| / |(gx, gy)| with gx = sx / dx, gy = sy / dy, as |sy dx| / |(sx dy, sy dx)|
+    // with the hardware reciprocal square root (about 1 ulp) instead of three divisions and a square root
+    const float p = (float)sx * (float)e.dy, r = (float)sy * (float)e.dx;
+    const float h2 = p * p + r * r;
+    return h2 == 0.f ? 1.f : fminf(fabsf(r) * __builtin_amdgcn_rsqf(h2), 1.f);
 }
 
 // Axial filter of one chunk from the ring of (R', T) pairs: lane l outputs
@@ -445,7 +468,10 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         }
 
         float cs = 1.f;
-        if (G) cs = incidence_cos(e, v, q, x, y, lab, y > 0 ? lab_pr : lab, lab_nr);
+        if (__builtin_amdgcn_ballot_w64(G)) {   // uniform: the wave-level Sobel reads neighbouring lanes
+            const float c = incidence_cos_wave(e, v, q, x, y0, lane, G, lab, y > 0 ? lab_pr : lab, lab_nr);
+            if (G) cs = c;
+        }
         const float Rp = G ? E * cs * fabsf(r) : 0.f;
 
         // ring slot of this chunk, then the axial filter of the previous chunk
@@ -518,7 +544,7 @@ __global__ __launch_bounds__(kThreads) void k_ray(PhysArgs a, QueueDev* q)
     if (a.pair_rt)
         for (int i = threadIdx.x; i < a.n_labels * a.n_labels; i += kThreads) s_pair[i] = a.pair_rt[i];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform: scalar per-scanline values
     for (;;) {
         const int item = next_item(&q->next_ray, &s_item);
         if (item >= a.n_ray) break;
