@@ -940,9 +940,15 @@ __global__ __launch_bounds__(kThreads) void k_encode_ct(PhysArgs a, const uint16
     }
 }
 
-__global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int n, QueueDev* q)
+// Device geometry of a batched step; its first threads also reset the step's
+// work counters (only the ray kernel, launched after this one, reads them).
+__global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int n, QueueDev* q, int n_queues)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n_queues) {
+        q[e].next_ray = 0;
+        q[e].next_psf = 0;
+    }
     if (e >= n) return;
     EnvDev& d = envs[e];
     const VolDev v = vols[d.vol];
@@ -954,8 +960,7 @@ __global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses
         d.DX[c] = ok ? DX[c] : 0;
         d.DY[c] = ok ? DY[c] : 0;
     }
-    d.valid = ok;
-    if (!ok && d.plane == 0) atomicAdd(&q->n_bad, 1);   // counted once per caller env
+    d.valid = ok;   // sg_batch_status counts the rejected poses from these flags
 }
 
 __global__ void k_queue_reset(QueueDev* q, int n)
@@ -1082,10 +1087,10 @@ hipError_t launch_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, 
 }
 
 hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n, QueueDev* q,
-                           hipStream_t s)
+                           int32_t n_queues, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_geometry, dim3((n + 127) / 128), dim3(128), 0, s, envs, vols, poses, n, q);
+    if (n <= 0 || n_queues < 1 || n_queues > 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_geometry, dim3((n + 127) / 128), dim3(128), 0, s, envs, vols, poses, n, q, n_queues);
     return hipGetLastError();
 }
 

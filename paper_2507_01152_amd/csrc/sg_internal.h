@@ -100,7 +100,7 @@ struct PhysArgs {
 struct QueueDev {
     int32_t next_ray;    // next ray work item
     int32_t next_psf;    // next PSF tile
-    int32_t n_bad;       // envs with rejected poses (device geometry)
+    int32_t n_bad;       // unused (rejected poses are counted from the envs' valid flags)
     int32_t pad;
 };
 
@@ -156,8 +156,8 @@ __host__ __device__ inline int plane_geometry(const double* pose, double sx, dou
 
 // launchers (physics.hip)
 hipError_t launch_queue_reset(QueueDev* q, int n_queues, hipStream_t s);   // resets q[0 .. n_queues)
-hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n_envs,
-                           QueueDev* q, hipStream_t s);
+hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n_envs, QueueDev* q,
+                           int32_t n_queues, hipStream_t s);   // also resets the work counters q[0 .. n_queues)
 hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s);
 hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tile_x, int grid, hipStream_t s);
 hipError_t launch_max_label(const uint8_t* labels, int64_t n, int32_t* d_out, hipStream_t s);

@@ -147,10 +147,8 @@ hipError_t enqueue_step(sg_ctx* c, Plan* p, float* out, hipStream_t s, hipEvent_
 {
     QueueDev* q = (QueueDev*)p->d_queue.p;
     const int K = p->shape.chunks;
-    hipError_t e = launch_queue_reset(q, K, s);
-    if (e == hipSuccess)
-        e = launch_geometry((EnvDev*)p->d_envs.p, (const VolDev*)c->d_vols.p, (const double*)p->d_poses.p,
-                            p->n_envs, q, s);
+    hipError_t e = launch_geometry((EnvDev*)p->d_envs.p, (const VolDev*)c->d_vols.p, (const double*)p->d_poses.p,
+                                   p->n_envs, q, K, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[0], s);
     if (K == 1) {
         const PhysArgs a = plan_args(c, p, out);
@@ -380,11 +378,14 @@ extern "C" sg_status sg_batch_status(sg_ctx* c, int32_t id, int32_t* n_bad)
     Plan* p = c ? find_plan(c, id) : nullptr;
     if (!p || !n_bad) return fail(SG_EINVAL, "sg_batch_status: bad plan id or NULL");
     (void)hipSetDevice(c->device);
-    QueueDev q;
+    // the device geometry flags every plane of a rejected pose; count caller envs (plane 0)
+    std::vector<EnvDev> envs(p->n_envs);
     hipError_t e = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess) e = hipMemcpy(&q, p->d_queue.p, sizeof(QueueDev), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(envs.data(), p->d_envs.p, sizeof(EnvDev) * envs.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "status readback");
-    *n_bad = q.n_bad;
+    int32_t bad = 0;
+    for (const EnvDev& d : envs) bad += (!d.valid && d.plane == 0) ? 1 : 0;
+    *n_bad = bad;
     return SG_OK;
 }
 
