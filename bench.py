@@ -66,6 +66,34 @@ def surrogate_flops_per_frame(H: int, W: int) -> float:
     return f + (2.0 * 16 * 8 + 8) * H * W + 2.0 * 16 * H * W
 
 
+# algorithmic HBM bytes of the inference forward: (channels, level) of every tensor read and written once
+# per consumer in bf16 (2 B), plus the encoder's label gather (1 B/px) and the FP32 head output and clamp
+SURR_FWD_TENSORS = [
+    # (reads, writes): lists of (channels, level)
+    ([], [(8, 0)]),                                   # encoder -> X
+    ([(8, 0)], [(16, 0)]), ([(16, 0)], [(16, 0)]),    # T1, E0
+    ([(16, 0)], [(8, 0)]),                            # depth map + running sum -> A0
+    ([(16, 0)], [(32, 1)]), ([(32, 1)], [(32, 1)]),   # T2, E1
+    ([(32, 1)], [(64, 2)]), ([(64, 2)], [(64, 2)]),   # T3, E2
+    ([(64, 2)], [(128, 3)]), ([(128, 3)], [(128, 3)]),   # T4, E3
+    ([(128, 3)], [(256, 4)]), ([(256, 4)], [(256, 4)]),  # T5, B4
+    ([(256, 4), (128, 3)], [(128, 3)]), ([(128, 3)], [(128, 3)]),   # U3 + E3 -> S3, D3
+    ([(128, 3), (64, 2)], [(64, 2)]), ([(64, 2)], [(64, 2)]),       # U2 + E2 -> S2, D2
+    ([(64, 2), (32, 1)], [(32, 1)]), ([(32, 1)], [(32, 1)]),        # U1 + E1 -> S1, D1
+    ([(32, 1), (16, 0), (8, 0)], [(24, 0)]),          # U0 + E0 + A0 -> S0
+    ([(24, 0)], []),                                  # D0 with the fused head (output below)
+]
+
+
+def surrogate_bytes_per_frame(H: int, W: int) -> float:
+    """Algorithmic HBM bytes of one frame's inference forward."""
+    b = 0.0
+    for reads, writes in SURR_FWD_TENSORS:
+        for c, lv in reads + writes:
+            b += 2.0 * c * (H >> lv) * (W >> lv)
+    return b + (1.0 + 4.0 + 8.0) * H * W   # label gather, FP32 head output, clamp (read + write)
+
+
 RAY_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_ray_hbm_traffic_256env.md")
 RAY_SOURCES = [os.path.join(ROOT, "paper_2507_01152_amd", "csrc", f) for f in ("physics.hip", "sg_internal.h")]
 
@@ -196,6 +224,7 @@ def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, ps
     phys_s = (time.perf_counter() - t) / 20
     mse = 10.0 ** (-np.asarray(psnr, dtype=np.float64) / 10.0)
     flops = surrogate_flops_per_frame(FRAME_H, FRAME_W) * n_envs
+    nbytes = surrogate_bytes_per_frame(FRAME_H, FRAME_W) * n_envs
     res = {
         "workload": f"{n_envs} envs, {FRAME_W}x{FRAME_H} frames on held-out 64^3 ellipsoid phantoms, "
                     f"1/{audit_frac} seeded physics audit at PSNR >= {psnr_min} dB",
@@ -210,7 +239,9 @@ def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, ps
         "roofline": {"bound": "mfma", "kernel": "network forward (encode + 18 convs + depth integral + head)",
                      "achieved": round(flops / net_s / 1e12, 2), "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(flops / net_s / 1e12 / 2500.0, 4), "flops_per_launch": flops,
-                     "ms": round(net_s * 1e3, 3)},
+                     "ms": round(net_s * 1e3, 3),
+                     "hbm_view": {"algorithmic_bytes": nbytes, "achieved_GBps": round(nbytes / net_s / 1e9, 1),
+                                  "frac_of_8TBps": round(nbytes / net_s / 8e12, 4)}},
     }
     sess.close()
     return res

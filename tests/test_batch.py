@@ -75,6 +75,36 @@ def test_batch_256_envs_vs_oracle(sess, uneven):
     assert np.mean(means) > 0.02
 
 
+def test_batch_mixing_window_and_wide_tiles(sess):
+    """One batch whose PSF tiles take both the register-window path (lateral
+    radius <= 8) and the per-pixel tap loop (up to 32 px), in every launch
+    shape: bit-identical to single calls and within the oracle's bars."""
+    from paper_2507_01152_amd import sonosim as sg
+    from paper_2507_01152_amd.session import split_frames
+    from synth import Probe, Workload
+    base = synth.ellipsoid_workload(seed=13, n_envs=6, W=64, H=64)
+    widths = [64, 300, 520, 1024, 90, 700]
+    heights = [96, 64, 40, 33, 128, 70]
+    psfs = [0.01, 0.01, 0.01, 0.0104, 0.01, 0.01]
+    probes = [Probe(W=w, H=h, dx=0.06, dy=0.3, psf=f) for w, h, f in zip(widths, heights, psfs)]
+    wl = Workload(base.volumes, base.vol_ids, probes, base.poses, base.table)
+    vids = sess.load(wl)
+    offs, total = wl.out_offsets()
+    single = torch.zeros(total, dtype=torch.float32, device=sess.device)
+    sg.sg_simulate(sess.ctx, vids, wl.probes, wl.poses, single, offs)
+    plan = sg.sg_batch_plan_create(sess.ctx, vids, wl.probes, offs)
+    for spw, tx in ((4, 16), (8, 32), (16, 64)):
+        sg.sg_batch_set_config(sess.ctx, plan, spw, tx, 1)
+        out, _ = batch_frames(sess, wl, vids, plan=plan)
+        torch.cuda.synchronize()
+        assert torch.equal(out, single), (spw, tx)
+    Y = split_frames(single.cpu().numpy(), wl)
+    for e in range(wl.n_envs):
+        o = oracle.simulate_env(wl.volumes[wl.vol_ids[e]], wl.table, wl.probes[e], wl.poses[e], planes=("I", "A", "Y"))
+        check_env({"Y": Y[e]}, o, wl.probes[e], f"wide batch env {e}")
+    sg.sg_batch_plan_destroy(sess.ctx, plan)
+
+
 def test_env_order_invariance(sess, uneven):
     """Permuting the environments (and their output slots) permutes frames."""
     from paper_2507_01152_amd.session import split_frames

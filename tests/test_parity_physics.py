@@ -61,6 +61,23 @@ def test_ragged_and_degenerate_sizes(sess, W, H):
     check_all(sess, wl, name=f"{W}x{H}")
 
 
+@pytest.mark.parametrize("W,H,psf", [(400, 64, 0.01), (300, 50, 0.0104), (1024, 40, 0.0104)])
+def test_wide_frames_take_the_per_pixel_lateral_taps(sess, W, H, psf):
+    """Lateral PSF radii above 8 px (frames wider than 266 px at 1 % of the
+    width) take the PSF kernel's per-pixel tap loop instead of the register
+    window; 1024 x 40 at 0.0104 gives the 32 px radius limit."""
+    wl = synth.ellipsoid_workload(seed=9, n_envs=1, W=W, H=H, dx=0.06, dy=0.3)
+    for p in wl.probes:
+        p.psf = psf
+    check_all(sess, wl, name=f"{W}x{H} psf {psf}")
+
+
+def test_maximum_frame_1024_square(sess):
+    """The largest frame (1024 x 1024): axial and lateral radii 31 px."""
+    wl = synth.ellipsoid_workload(seed=10, n_envs=1, W=1024, H=1024, dx=0.06, dy=0.06)
+    check_all(sess, wl, name="1024x1024", debug=False)
+
+
 def test_plane_entirely_outside_volume(sess):
     vol = Volume(labels=np.ones((16, 16, 16), dtype=np.uint8), seed=4)
     wl = single_env(vol, Probe(W=20, H=40), axis_pose((-500.0, -500.0, -500.0)))
