@@ -584,8 +584,13 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
     // tiles are uniform in cost: block b takes tiles b, b + G, b + 2G, ... (G: the
     // grid).  A shared work counter costs more here than it balances: its
     // same-address atomics serialise across the XCDs.
+    // LDS: the staged tile, then the output tile in a region of its own, so a
+    // tile needs two barriers (staged -> filter, output written -> stores): the
+    // next tile's staging and taps follow the second one, which every wave
+    // passes only after filtering.
+    const int r_max = a.max_rlat < kRB ? kRB : a.max_rlat;
+    float* sY = lds + kAS * (2 * (TX + 2 * r_max) + TX);   // [kTileRows][TX + 1]
     for (int item = blockIdx.x; item < a.n_psf; item += gridDim.x) {
-        __syncthreads();   // LDS of the previous tile is free
         const ItemPsf it = a.psf_items[item];
         const EnvDev e = a.envs[it.env];
         const int W = e.W, H = e.H, rl = e.rlat;
@@ -724,8 +729,6 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
                 }
             }
         }
-        __syncthreads();   // sR is reused for the output tile
-        float* sY = lds;   // [kTileRows][TX + 1]
 #pragma unroll
         for (int q = 0; q < kSPW; ++q) {
             const int sx = wave + q * kPW;
@@ -1005,7 +1008,8 @@ constexpr int psf_threads(int tx) { return tx / kSx * kWave; }
 size_t psf_lds_bytes(int tx, int max_rlat)
 {
     const int R = max_rlat < kRB ? kRB : max_rlat;
-    return sizeof(float) * (size_t)kAS * (2 * (tx + 2 * R) + tx);
+    // staged tile (R, T with halo, E), then the output tile
+    return sizeof(float) * ((size_t)kAS * (2 * (tx + 2 * R) + tx) + (size_t)kTileRows * (tx + 1));
 }
 
 bool psf_tile_supported(int tx) { return psf_fn(tx) != nullptr; }
