@@ -34,7 +34,7 @@ namespace {
 // beside the ray kernel of the next group (the ray kernel is bound by the
 // VALU, the PSF kernel by memory), each kernel on part of the GPU.
 const LaunchShape kShapes[] = {
-    {1, 32, 1}, {2, 32, 1}, {1, 64, 1}, {2, 64, 1}, {1, 16, 1}, {4, 32, 1},
+    {1, 32, 1}, {2, 32, 1}, {1, 64, 1}, {2, 64, 1}, {1, 16, 1}, {4, 32, 1}, {4, 64, 1},
     {2, 32, 2}, {2, 64, 2}, {2, 32, 4}, {2, 64, 4},
 };
 
