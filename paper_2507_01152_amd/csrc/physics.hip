@@ -358,9 +358,9 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
                              const float2* pair_rt, const float* kax, float2* ring, int x, int lane)
 {
     const int H = e.H;
-    float* fR = a.fR + e.scr_off + (int64_t)x * H;
-    float* fT = a.fT + e.scr_off + (int64_t)x * H;
-    float* fE = a.fE + e.scr_off + (int64_t)x * H;
+    float* fR = a.fR + e.scr_off + (int64_t)x * e.ld;
+    float* fT = a.fT + e.scr_off + (int64_t)x * e.ld;
+    float* fE = a.fE + e.scr_off + (int64_t)x * e.ld;
     if (!e.valid) {
         for (int y = lane; y < H; y += kWave) {
             fR[y] = 0.f;
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
     for (int item = blockIdx.x; item < a.n_psf; item += gridDim.x) {
         const ItemPsf it = a.psf_items[item];
         const EnvDev e = a.envs[it.env];
-        const int W = e.W, H = e.H, rl = e.rlat;
+        const int W = e.W, H = e.H, rl = e.rlat, ld = e.ld;
         const int R = rl <= kRB ? kRB : rl;   // halo of the staged tile
         const int x0 = (it.tile & 0xFFFF) * TX;
         const int y0 = (it.tile >> 16) * kTileRows;
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
                 const int c = wave + u * kPW;            // wave-uniform column
                 const int gx = x0 - kRB + c;
                 const bool col = c < CWF && gx >= 0 && gx < W;
-                const int64_t base = (int64_t)(col ? gx : 0) * H;
+                const int64_t base = (int64_t)(col ? gx : 0) * ld;
                 vr[u] = (col && yin) ? gR[base + gy] : 0.f;
                 vt[u] = (col && yin) ? gT[base + gy] : 0.f;
             }
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
                 const int c = wave + u * kPW;
                 const int gx = x0 + c;
                 const bool col = c < TX && gx < W;
-                const int64_t base = (int64_t)(col ? gx : 0) * H;
+                const int64_t base = (int64_t)(col ? gx : 0) * ld;
                 ve[u] = (col && yin) ? gE[base + gy] : 0.f;
             }
 #pragma unroll
@@ -655,7 +655,7 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
                 const int c = c0 + u * kPW;
                 const int gx = x0 - R + c;
                 const bool in = yin && c < CW && gx >= 0 && gx < W;
-                const int64_t off = in ? (int64_t)gx * H + gy : 0;
+                const int64_t off = in ? (int64_t)gx * ld + gy : 0;
                 vr[u] = in ? gR[off] : 0.f;
                 vt[u] = in ? gT[off] : 0.f;
             }
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
             for (int u = 0; u < kU; ++u) {
                 const int gx = x0 + c0 + u * kPW;
                 const bool in = yin && c0 + u * kPW < TX && gx < W;
-                ve[u] = in ? gE[(int64_t)gx * H + gy] : 0.f;
+                ve[u] = in ? gE[(int64_t)gx * ld + gy] : 0.f;
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u)

@@ -57,6 +57,7 @@ struct Plan {
     std::vector<float> pool;
     std::vector<int> order;            // envs, longest scanlines first
     int64_t n_pixels = 0;
+    int64_t n_scr = 0;                 // field-scratch elements per field (padded scanlines)
     int max_rax = 0, max_rlat = 0;
     int multiscale = 0;                // some env's volume has several noise scales
     LaunchShape shape;

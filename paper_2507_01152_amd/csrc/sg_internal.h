@@ -22,6 +22,8 @@ struct VolDev {
 
 constexpr int kNoiseQ = 4096;   // entries of the quantised normal (w2 >> 20)
 constexpr int kCtBins = 4096;   // HU histogram bins of the CT-conditioned surrogate input (HU + 1024)
+// Field-scratch scanlines start on 128-byte lines, so a 64-row segment is two whole lines
+constexpr int kScrAlign = 32;
 constexpr int kMaxNoiseScales = 4;
 
 struct TissueDev {
@@ -57,6 +59,7 @@ struct EnvDev {
     int32_t plane;                 // plane index within that env
     int64_t out_off;               // frame offset in the output (elements)
     int64_t scr_off;               // offset of this env in the field scratch
+    int32_t ld;                    // scanline stride of the field scratch: H rounded up to kScrAlign
 };
 
 struct ItemRay { int32_t env, x0; };          // x0: first scanline of the group

@@ -175,6 +175,7 @@ sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int plane, in
     e.psf64 = p.psf_frac;
     e.out_off = out_off + (int64_t)plane * p.W * p.H;
     e.scr_off = scr_off;
+    e.ld = (p.H + kScrAlign - 1) / kScrAlign * kScrAlign;
     return SG_OK;
 }
 
@@ -452,7 +453,7 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
             if (!ed.valid)
                 return fail(SG_ERANGE, "env %d plane %d: image plane outside the fixed-point range (|Q16| > 2^30)",
                             i, j);
-            scr += (int64_t)probes[i].W * probes[i].H;
+            scr += (int64_t)probes[i].W * ed.ld;
             max_rlat = std::max(max_rlat, ed.rlat);
             max_px = std::max(max_px, probes[i].W * probes[i].H);
             envs.push_back(ed);

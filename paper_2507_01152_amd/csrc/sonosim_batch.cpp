@@ -129,8 +129,8 @@ PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
     a.psf_items = (const ItemPsf*)p->d_tiles.p;
     a.n_psf = p->n_tiles;
     a.fR = (float*)p->fields.p;
-    a.fT = a.fR + p->n_pixels;
-    a.fE = a.fT + p->n_pixels;
+    a.fT = a.fR + p->n_scr;
+    a.fE = a.fT + p->n_scr;
     a.out = out;
     a.scanlines_per_wave = p->shape.spw;
     a.max_rlat = p->max_rlat;
@@ -269,9 +269,10 @@ extern "C" sg_status sg_batch_plan_create(sg_ctx* c, int32_t n, const int32_t* v
         if (out_offsets[i] < 0) return fail(SG_EINVAL, "env %d: negative output offset", i);
         for (int j = 0; j < probe_planes(probes[i]); ++j) {
             EnvDev ed;
-            s = fill_env_static(probes[i], vol_ids[i], i, j, out_offsets[i], p->n_pixels, p->pool, ed);
+            s = fill_env_static(probes[i], vol_ids[i], i, j, out_offsets[i], p->n_scr, p->pool, ed);
             if (s != SG_OK) return s;
             p->n_pixels += (int64_t)probes[i].W * probes[i].H;
+            p->n_scr += (int64_t)probes[i].W * ed.ld;
             p->max_rax = std::max(p->max_rax, ed.rax);
             p->max_rlat = std::max(p->max_rlat, ed.rlat);
             p->envs.push_back(ed);
@@ -291,7 +292,7 @@ extern "C" sg_status sg_batch_plan_create(sg_ctx* c, int32_t n, const int32_t* v
     if (e == hipSuccess) e = p->d_pool.ensure(sizeof(float) * p->pool.size());
     if (e == hipSuccess) e = p->d_poses.ensure(sizeof(double) * 12 * n);
     if (e == hipSuccess) e = p->d_queue.ensure(sizeof(QueueDev) * kMaxChunks);
-    if (e == hipSuccess) e = p->fields.ensure(sizeof(float) * 3 * (size_t)p->n_pixels);
+    if (e == hipSuccess) e = p->fields.ensure(sizeof(float) * 3 * (size_t)p->n_scr);
     if (e != hipSuccess) return hip_fail(e, "plan allocation");
     e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * ni, hipMemcpyHostToDevice);
     if (e == hipSuccess)
