@@ -26,8 +26,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz non-packed 32-bit VALU lane-ops
-PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X's FP32 vector peak (157.3 TFLOP/s, an FMA counted as 2 flops) is
+# 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz non-packed 32-bit VALU lane-ops:
+# 78.6 T lane-ops/s.  Two-operand encodings approach it, three-operand ones
+# issue at about half of it and the 32x32->64 multiply-add at a quarter
+# (weighted 4 below); the probe's measurements go into the roofline line.
+PEAK_VALU_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 
 
 def psf_radius(size: int, frac: float = 0.01) -> int:
@@ -328,6 +332,10 @@ def main():
     ray_ops = sum(ray_ops_per_pixel(p.W, p.H) * p.W * p.H for p in wl.probes)
     psf_ops = sum(psf_ops_per_pixel(p.W, p.H) * p.W * p.H for p in wl.probes)
     achieved_tops = ray_ops / (ray_ms / 1e3) / 1e12
+    fma_r, int_r, mad_r, fma3_r = sg.sg_valu_probe(sess.ctx)
+    probe = {"what": "measured VALU rates of independent instruction chains, Top/s (sg_valu_probe)",
+             "fma_vop2": round(fma_r / 1e12, 2), "xor_add_vop2": round(int_r / 1e12, 2),
+             "mad_u64": round(mad_r / 1e12, 2), "fma_vop3": round(fma3_r / 1e12, 2)}
     # whole step on algorithmic bytes: 1 B label gather + 4 B FP32 frame per pixel
     alg_bytes = 5 * pixels
     achieved_gbs = alg_bytes / (ms_per_step / 1e3) / 1e9
@@ -357,6 +365,7 @@ def main():
             "kernel": "k_ray (sampling, scans, speckle, axial PSF)",
             "achieved": round(achieved_tops, 3),
             "peak": round(PEAK_VALU_TOPS, 2),
+            "peak_probe": probe,
             "unit": "Top/s",
             "frac": round(achieved_tops / PEAK_VALU_TOPS, 4),
             "ops_per_launch": ray_ops,

@@ -463,6 +463,17 @@ sg_status sg_surr_set_params(sg_ctx* ctx, int32_t surr_id, const float* host);
  * and physics target (FP32, n x H x W). */
 sg_status sg_surr_get_batch(sg_ctx* ctx, int32_t surr_id, uint16_t* input, float* target);
 
+/* VALU throughput probe (measurement support for the rooflines): times
+ * independent instruction chains over a grid of 8 blocks of 256 threads per
+ * compute unit and writes each kind's rate in lane-operations per second to
+ * rates (host, 4 doubles; best of 3 runs):
+ *   [0] FP32 FMA, two-operand encoding (literal operands);
+ *   [1] 32-bit xor + add pairs, two-operand encodings (2 ops per pair);
+ *   [2] 32x32->64 multiply-add (the Philox product);
+ *   [3] FP32 FMA, three-operand encoding (operands from registers).
+ * Synchronises.  Errors: SG_EINVAL (NULL), SG_EHIP. */
+sg_status sg_valu_probe(sg_ctx* ctx, double* rates);
+
 #ifdef __cplusplus
 }
 #endif

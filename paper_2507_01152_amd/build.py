@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, "lib", "libsonosim.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["physics.hip", "conv_mfma.hip", "recon.hip", "sonosim_api.cpp", "sonosim_batch.cpp", "surrogate.cpp"]
+SOURCES = ["physics.hip", "conv_mfma.hip", "recon.hip", "probe.hip", "sonosim_api.cpp", "sonosim_batch.cpp",
+           "surrogate.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           # no packed FP32 instructions in generated code
