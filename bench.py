@@ -110,16 +110,17 @@ def ray_kernel_digest() -> str:
     return h.hexdigest()
 
 
-def ray_traffic_bytes():
-    """HBM bytes per ray-kernel launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or None when
-    the summary is missing or was taken on other kernel sources."""
+def ray_traffic_bytes(key="traffic_bytes_per_launch"):
+    """HBM bytes per ray-kernel (or, with key psf_traffic_bytes_per_launch,
+    PSF-kernel) launch from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy's reading), or None when the summary
+    is missing or was taken on other kernel sources."""
     try:
         with open(RAY_TRAFFIC_SUMMARY) as fh:
             text = fh.read()
     except OSError:
         return None
-    b = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
+    b = re.search(r"^" + key + r":\s*(\d+)", text, re.M)
     d = re.search(r"^kernel_sources_sha256:\s*([0-9a-f]{64})", text, re.M)
     if not b or not d or d.group(1) != ray_kernel_digest():
         return None
@@ -336,6 +337,20 @@ def main():
     probe = {"what": "measured VALU rates of independent instruction chains, Top/s (sg_valu_probe)",
              "fma_vop2": round(fma_r / 1e12, 2), "xor_add_vop2": round(int_r / 1e12, 2),
              "mad_u64": round(mad_r / 1e12, 2), "fma_vop3": round(fma3_r / 1e12, 2)}
+    # achievable HBM bandwidth: a 1 GiB device copy (read + written bytes per second)
+    cp_src = torch.ones(1 << 28, dtype=torch.float32, device=sess.device)
+    cp_dst = torch.empty_like(cp_src)
+    copy_gbs = sg.sg_hbm_probe(sess.ctx, cp_src, cp_dst) / 1e9
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(3):
+        cp_dst.copy_(cp_src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    torch_copy_gbs = 3 * 2 * cp_src.numel() * 4 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    achievable_gbs = max(copy_gbs, torch_copy_gbs)   # the better of the two copies
+    del cp_src, cp_dst
+    psf_traffic = ray_traffic_bytes("psf_traffic_bytes_per_launch")
     # whole step on algorithmic bytes: 1 B label gather + 4 B FP32 frame per pixel
     alg_bytes = 5 * pixels
     achieved_gbs = alg_bytes / (ms_per_step / 1e3) / 1e9
@@ -372,9 +387,17 @@ def main():
             "kernel_ms": round(ray_ms, 4),
             "traffic": ray_traffic_bytes(),
             "psf_kernel": {"kernel_ms": round(psf_ms, 4), "ops_per_launch": psf_ops,
-                           "achieved_Tops": round(psf_ops / (psf_ms / 1e3) / 1e12, 3)},
+                           "achieved_Tops": round(psf_ops / (psf_ms / 1e3) / 1e12, 3),
+                           "traffic": psf_traffic,
+                           "traffic_GBps": (round(psf_traffic / (psf_ms / 1e3) / 1e9, 1)
+                                            if psf_traffic else None),
+                           "traffic_frac_of_achievable": (round(psf_traffic / (psf_ms / 1e3) / 1e9
+                                                                / achievable_gbs, 4) if psf_traffic else None)},
+            "hbm_achievable": {"what": "1 GiB device copies, read + written GB/s; the better one is the achievable",
+                               "sg_hbm_probe": round(copy_gbs, 1), "torch_copy": round(torch_copy_gbs, 1)},
             "hbm_view_whole_step": {"algorithmic_bytes": alg_bytes, "achieved_GBps": round(achieved_gbs, 1),
-                                    "frac_of_8TBps": round(achieved_gbs / PEAK_HBM_GBS, 4)},
+                                    "frac_of_8TBps": round(achieved_gbs / PEAK_HBM_GBS, 4),
+                                    "frac_of_achievable": round(achieved_gbs / achievable_gbs, 4)},
         },
         "wall_s_timed": round(wall, 3),
     }

@@ -474,6 +474,16 @@ sg_status sg_surr_get_batch(sg_ctx* ctx, int32_t surr_id, uint16_t* input, float
  * Synchronises.  Errors: SG_EINVAL (NULL), SG_EHIP. */
 sg_status sg_valu_probe(sg_ctx* ctx, double* rates);
 
+/* HBM bandwidth probe (measurement support for the rooflines): copies bytes
+ * from src to dst (device, 16-byte aligned, not overlapping; bytes a non-zero
+ * multiple of 16; the caller owns both) with 16-byte vector loads and stores
+ * in eight launch shapes (4 or 8 loads in flight per thread, 8 or 16 blocks
+ * of 256 threads per compute unit, cached or non-temporal), four runs each, and writes the best run after
+ * each shape's first as bytes read + written per second to *rate (host).  dst holds a copy of src afterwards.  Use buffers
+ * well beyond the last-level cache (hundreds of MiB).  Synchronises.
+ * Errors: SG_EINVAL (NULL, size, alignment or overlap), SG_EHIP. */
+sg_status sg_hbm_probe(sg_ctx* ctx, const void* src, void* dst, size_t bytes, double* rate);
+
 #ifdef __cplusplus
 }
 #endif

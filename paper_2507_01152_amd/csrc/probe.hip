@@ -4,7 +4,9 @@
 // operands compile to the two-operand (VOP2) encodings, the FMA chain with
 // operands from kernel arguments to the three-operand (VOP3) one; the two
 // issue at different rates.  No chain can be folded at compile time (none
-// is a closed-form recurrence).  Entry point in include/sonosim.h.
+// is a closed-form recurrence).  A 16-byte-vector device copy measures the
+// HBM bandwidth the rooflines' memory side can reach.  Entry points in
+// include/sonosim.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -85,6 +87,37 @@ __global__ __launch_bounds__(256) void k_probe_mad64(uint32_t* out, uint32_t m)
     out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// Grid-stride copy, U 16-byte loads in flight per thread before their
+// stores; NT: non-temporal loads and stores (streamed past the caches).
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void k_probe_copy(const v4f* __restrict__ src, v4f* __restrict__ dst, size_t n4)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += U * stride) {
+        v4f v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (i + j * stride < n4) v[j] = NT ? __builtin_nontemporal_load(src + i + j * stride) : src[i + j * stride];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (i + j * stride < n4) {
+                if (NT)
+                    __builtin_nontemporal_store(v[j], dst + i + j * stride);
+                else
+                    dst[i + j * stride] = v[j];
+            }
+    }
+}
+
+template <int U, bool NT>
+hipError_t launch_copy(int blocks, hipStream_t st, const void* src, void* dst, size_t n4)
+{
+    hipLaunchKernelGGL((k_probe_copy<U, NT>), dim3(blocks), dim3(256), 0, st, (const v4f*)src, (v4f*)dst, n4);
+    return hipGetLastError();
+}
+
 }  // namespace
 }  // namespace sg
 
@@ -125,4 +158,45 @@ extern "C" sg_status sg_valu_probe(sg_ctx* c, double* rates)
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     return e == hipSuccess ? SG_OK : hip_fail(e, "VALU probe");
+}
+
+extern "C" sg_status sg_hbm_probe(sg_ctx* c, const void* src, void* dst, size_t bytes, double* rate)
+{
+    if (!c || !src || !dst || !rate) return fail(SG_EINVAL, "sg_hbm_probe: NULL argument");
+    if (bytes == 0 || bytes % 16 || (uintptr_t)src % 16 || (uintptr_t)dst % 16)
+        return fail(SG_EINVAL, "sg_hbm_probe: bytes and both pointers must be non-zero multiples of 16");
+    const char* s8 = static_cast<const char*>(src);
+    const char* d8 = static_cast<const char*>(dst);
+    if (s8 < d8 + bytes && d8 < s8 + bytes) return fail(SG_EINVAL, "sg_hbm_probe: buffers overlap");
+    (void)hipSetDevice(c->device);
+    const int threads = 256;
+    const size_t n4 = bytes / 16;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = 1e30f;
+    // shapes: {4, 8} loads in flight x {8, 16} blocks per CU x {cached, non-temporal}; the first run of
+    // each warms the TLB and is not kept
+    for (int shape = 0; shape < 8 && e == hipSuccess; ++shape) {
+        const int blocks = (shape & 1 ? 16 : 8) * c->n_cu;
+        const bool u8 = shape & 2, nt = shape & 4;
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess)
+                e = nt ? (u8 ? launch_copy<8, true>(blocks, c->stream, src, dst, n4)
+                             : launch_copy<4, true>(blocks, c->stream, src, dst, n4))
+                       : (u8 ? launch_copy<8, false>(blocks, c->stream, src, dst, n4)
+                             : launch_copy<4, false>(blocks, c->stream, src, dst, n4));
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && rep > 0) best = std::min(best, ms);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "HBM probe");
+    *rate = 2.0 * (double)bytes / (best * 1e-3);
+    return SG_OK;
 }

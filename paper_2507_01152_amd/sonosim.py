@@ -27,7 +27,7 @@ SYMBOLS = (
     "sg_batch_config", "sg_batch_set_config", "sg_batch_plan_destroy",
     "sg_recon_create", "sg_recon_update", "sg_recon_observe", "sg_recon_counts", "sg_recon_points",
     "sg_recon_reset", "sg_recon_destroy",
-    "sg_conv_forward", "sg_conv_backward_data", "sg_conv_backward_weight", "sg_valu_probe",
+    "sg_conv_forward", "sg_conv_backward_data", "sg_conv_backward_weight", "sg_valu_probe", "sg_hbm_probe",
     "sg_surr_create", "sg_surr_create_ct", "sg_surr_set_ct_reference", "sg_surr_destroy", "sg_surr_num_params",
     "sg_surr_train_step", "sg_surr_infer", "sg_surr_train_pairs", "sg_surr_gan_losses", "sg_surr_disc_num_params",
     "sg_surr_disc_get_params", "sg_surr_disc_get_grads", "sg_surr_disc_set_params",
@@ -115,6 +115,7 @@ def load():
         "sg_conv_backward_weight": [VP, P(sg_conv_desc), VP, VP, VP, VP],
         "sg_surr_create": [VP, I32, I32, C.c_uint64, P(I32)],
         "sg_valu_probe": [VP, VP],
+        "sg_hbm_probe": [VP, VP, VP, C.c_size_t, P(C.c_double)],
         "sg_surr_create_ct": [VP, I32, I32, C.c_uint64, C.c_float, P(I32)],
         "sg_surr_set_ct_reference": [VP, I32, I32, VP, VP, VP, VP],
         "sg_surr_destroy": [VP, I32],
@@ -536,3 +537,13 @@ def sg_valu_probe(ctx):
     r = np.zeros(4, dtype=np.float64)
     _check(load().sg_valu_probe(ctx, r.ctypes.data), "sg_valu_probe")
     return tuple(float(v) for v in r)
+
+
+def sg_hbm_probe(ctx, src, dst):
+    """Device copy src -> dst (same byte size); returns bytes read + written per second."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("sg_hbm_probe: src and dst sizes differ")
+    r = C.c_double()
+    _check(load().sg_hbm_probe(ctx, _dptr(src), _dptr(dst), nbytes, C.byref(r)), "sg_hbm_probe")
+    return r.value
