@@ -93,11 +93,17 @@ typedef struct {
 } sg_volume_desc;
 
 /* Register a volume; *vol_id receives its id.  Scans the label map once on
- * the device to record its largest label (synchronises the stream).
- * The volume memory is referenced, not copied.  Errors: SG_EINVAL. */
+ * the device to record its largest label, and copies it into a library-owned
+ * layout of 8 x 4 x 4-voxel bricks (one 128-byte cache line each, so gathers
+ * along a beam touch few lines); synchronises the stream.  The caller's label
+ * buffer may be reused or freed after the call; the CT volume (ct_hu) is
+ * referenced, not copied, and must stay valid while the volume is registered.
+ * Errors: SG_EINVAL (also when the bricked map would need 2^24 bricks or
+ * more), SG_ENOMEM / SG_EHIP. */
 sg_status sg_volume_register(sg_ctx* ctx, const sg_volume_desc* desc, int32_t* vol_id);
 
-/* Forget a registered volume (its memory stays the caller's). */
+/* Forget a registered volume: waits for the context stream, then frees the
+ * library's bricked label map (the CT memory stays the caller's). */
 sg_status sg_volume_release(sg_ctx* ctx, int32_t vol_id);
 
 /* The quantised standard normal of the multi-scale density gate (host, no

@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sg_internal.h"
 
 namespace sg {
@@ -74,8 +76,9 @@ __device__ __forceinline__ int32_t q16(int32_t p0, int32_t dx, int32_t dy, int x
     return (int32_t)((uint32_t)p0 + (uint32_t)x * (uint32_t)dx + (uint32_t)y * (uint32_t)dy);
 }
 
-// nearest voxel of pixel (x, y), -1 outside the grid
-__device__ __forceinline__ int32_t voxel_at(const EnvDev& e, const VolDev& v, int x, int y)
+// nearest voxel of pixel (x, y): its linear index, -1 outside the grid, and
+// (inside) its byte offset in the bricked label map
+__device__ __forceinline__ int32_t voxel_at(const EnvDev& e, const VolDev& v, int x, int y, uint32_t& boff)
 {
     // round half up: floor((q + 2^15) / 2^16) as an arithmetic shift
     const int32_t ix = (int32_t)((uint32_t)q16(e.P0[0], e.DX[0], e.DY[0], x, y) + 32768u) >> 16;
@@ -83,6 +86,7 @@ __device__ __forceinline__ int32_t voxel_at(const EnvDev& e, const VolDev& v, in
     const int32_t iz = (int32_t)((uint32_t)q16(e.P0[2], e.DX[2], e.DY[2], x, y) + 32768u) >> 16;
     const bool in = (uint32_t)ix < (uint32_t)v.nx && (uint32_t)iy < (uint32_t)v.ny &&
                     (uint32_t)iz < (uint32_t)v.nz;
+    boff = in ? brick_offset(v, ix, iy, iz) : 0u;
     return in ? (iz * v.ny + iy) * v.nx + ix : -1;
 }
 
@@ -94,9 +98,10 @@ __device__ __forceinline__ T ld_global(const T* p, int64_t i)
     return ((const __attribute__((address_space(1))) T*)p)[i];
 }
 
-__device__ __forceinline__ int label_of(const VolDev& v, int32_t vox)
+// label of a voxel from voxel_at / voxel_at_q (air outside the grid)
+__device__ __forceinline__ int label_of(const VolDev& v, int32_t vox, uint32_t boff)
 {
-    return vox >= 0 ? (int)ld_global(v.labels, vox) : 0;
+    return vox >= 0 ? (int)ld_global(v.labels, (int64_t)boff) : 0;
 }
 
 __device__ __forceinline__ double ct_corner(const VolDev& v, int32_t ix, int32_t iy, int32_t iz)
@@ -134,14 +139,15 @@ __device__ __forceinline__ double z_from_ct(const EnvDev& e, const VolDev& v, in
     return z > 0.0 ? z : 0.0;
 }
 
-// nearest voxel index at Q16 position q, -1 outside the grid
-__device__ __forceinline__ int32_t voxel_at_q(const VolDev& v, const int32_t q[3])
+// nearest voxel at Q16 position q: linear index (-1 outside the grid) and bricked byte offset
+__device__ __forceinline__ int32_t voxel_at_q(const VolDev& v, const int32_t q[3], uint32_t& boff)
 {
     const int32_t ix = (int32_t)((uint32_t)q[0] + 32768u) >> 16;
     const int32_t iy = (int32_t)((uint32_t)q[1] + 32768u) >> 16;
     const int32_t iz = (int32_t)((uint32_t)q[2] + 32768u) >> 16;
     const bool in = (uint32_t)ix < (uint32_t)v.nx && (uint32_t)iy < (uint32_t)v.ny &&
                     (uint32_t)iz < (uint32_t)v.nz;
+    boff = in ? brick_offset(v, ix, iy, iz) : 0u;
     return in ? (iz * v.ny + iy) * v.nx + ix : -1;
 }
 
@@ -153,7 +159,7 @@ __device__ __forceinline__ int label_at_q(const VolDev& v, int32_t q0, int32_t q
     const int32_t iz = (int32_t)((uint32_t)q2 + 32768u) >> 16;
     const bool in = (uint32_t)ix < (uint32_t)v.nx && (uint32_t)iy < (uint32_t)v.ny &&
                     (uint32_t)iz < (uint32_t)v.nz;
-    return in ? (int)ld_global(v.labels, (iz * v.ny + iy) * v.nx + ix) : 0;
+    return in ? (int)ld_global(v.labels, (int64_t)brick_offset(v, ix, iy, iz)) : 0;
 }
 
 __device__ __forceinline__ float uniform24(uint32_t w)
@@ -382,8 +388,9 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
     const int n_lab = a.n_labels;
     float E_prev = 0.f;      // E of the previous chunk (its axial output is pending)
 
-    int32_t vox = voxel_at(e, v, x, lane);
-    int lab = label_of(v, vox);
+    uint32_t boff;
+    int32_t vox = voxel_at(e, v, x, lane, boff);
+    int lab = label_of(v, vox, boff);
     double Z = ct ? z_from_ct(e, v, x, lane) : 0.0;
     int32_t q[3];    // Q16 position of (x, y0 + lane)
 #pragma unroll
@@ -399,8 +406,9 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         int32_t qn[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) qn[c] = (int32_t)((uint32_t)q[c] + (uint32_t)e.DY[c] * (uint32_t)kWave);
-        const int32_t vox_n = voxel_at_q(v, qn);
-        const int lab_n = label_of(v, vox_n);
+        uint32_t boff_n;
+        const int32_t vox_n = voxel_at_q(v, qn, boff_n);
+        const int lab_n = label_of(v, vox_n, boff_n);
         const double Zct_n = ct ? z_from_ct(e, v, x, y + kWave) : 0.0;
 
         // scatterer of this chunk's voxels (computed for every lane, selected below)
@@ -784,8 +792,9 @@ __global__ __launch_bounds__(kThreads) void k_encode(PhysArgs a, uint16_t* enc)
         int lab = 0;
         float sc = 0.f;
         if (e.valid) {
-            const int32_t vox = voxel_at(e, v, x, y);
-            lab = label_of(v, vox);
+            uint32_t boff;
+            const int32_t vox = voxel_at(e, v, x, y, boff);
+            lab = label_of(v, vox, boff);
             if (vox >= 0) {
                 uint32_t w[4];
                 philox4x32_10((uint32_t)vox, v.key0, v.key1, w);
@@ -815,7 +824,8 @@ __global__ __launch_bounds__(kThreads) void k_encode(PhysArgs a, uint16_t* enc)
 // voxel's HU (-1000 outside the volume) + 1024, clamped to [0, 4095].
 __device__ __forceinline__ int ct_bin(const EnvDev& e, const VolDev& v, int x, int y, int32_t& vox)
 {
-    vox = voxel_at(e, v, x, y);
+    uint32_t boff;
+    vox = voxel_at(e, v, x, y, boff);
     const int hu = (vox >= 0 && v.ct) ? (int)ld_global(v.ct, vox) : -1000;
     return min(max(hu + 1024, 0), kCtBins - 1);
 }
@@ -976,6 +986,23 @@ __global__ void k_queue_reset(QueueDev* q, int n)
     }
 }
 
+// linear [nz][ny][nx] label map -> bricked layout, one thread per destination byte (padding voxels 0)
+__global__ __launch_bounds__(kThreads) void k_brick_labels(const uint8_t* __restrict__ src, int32_t nx, int32_t ny,
+                                                           int32_t nz, int32_t bnx, int32_t bny, int64_t n_bytes,
+                                                           uint8_t* __restrict__ dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n_bytes; i += (int64_t)gridDim.x * kThreads) {
+        const int64_t b = i >> 7;
+        const int w = (int)(i & (kBrickBytes - 1));
+        const int64_t byz = b / bnx;
+        const int32_t ix = (int32_t)(b - byz * bnx) * kBrickX + (w & 7);
+        const int32_t iy = (int32_t)(byz % bny) * kBrickY + ((w >> 3) & 3);
+        const int32_t iz = (int32_t)(byz / bny) * kBrickZ + (w >> 5);
+        const bool in = ix < nx && iy < ny && iz < nz;
+        dst[i] = in ? src[((int64_t)iz * ny + iy) * nx + ix] : (uint8_t)0;
+    }
+}
+
 __global__ void k_max_label(const uint8_t* labels, int64_t n, int32_t* out)
 {
     int m = 0;
@@ -1102,6 +1129,17 @@ hipError_t launch_queue_reset(QueueDev* q, int n, hipStream_t s)
 {
     if (n < 1 || n > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, q, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_brick_labels(const uint8_t* src, int32_t nx, int32_t ny, int32_t nz, uint8_t* dst, hipStream_t s)
+{
+    const int32_t bnx = (nx + kBrickX - 1) / kBrickX, bny = (ny + kBrickY - 1) / kBrickY,
+                  bnz = (nz + kBrickZ - 1) / kBrickZ;
+    const int64_t n_bytes = (int64_t)bnx * bny * bnz * kBrickBytes;
+    const int64_t blocks = std::min<int64_t>((n_bytes + kThreads - 1) / kThreads, 65536);
+    hipLaunchKernelGGL(k_brick_labels, dim3((unsigned)blocks), dim3(kThreads), 0, s, src, nx, ny, nz, bnx, bny, n_bytes,
+                       dst);
     return hipGetLastError();
 }
 

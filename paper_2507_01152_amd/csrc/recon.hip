@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_recon_update(const EnvDev* __restrict__
             const int32_t iz = (int32_t)((uint32_t)q[2] + 32768u) >> 16;
             const bool in =
                 (uint32_t)ix < (uint32_t)v.nx && (uint32_t)iy < (uint32_t)v.ny && (uint32_t)iz < (uint32_t)v.nz;
-            const int lab = in ? (int)v.labels[(iz * v.ny + iy) * v.nx + ix] : 0;
+            const int lab = in ? (int)v.labels[brick_offset(v, ix, iy, iz)] : 0;
             is_bone = s_bone[lab] != 0;
         }
         const unsigned long long b = __ballot(is_bone);

@@ -36,6 +36,7 @@ struct PinnedBuf {
 
 struct HostVolume {
     VolDev dev{};
+    uint8_t* bricks = nullptr;   // library-owned bricked label map (dev.labels); freed on release
     int32_t max_label = 0;
     bool live = false;
 };

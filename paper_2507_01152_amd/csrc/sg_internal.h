@@ -11,11 +11,18 @@ constexpr int kWave = 64;
 constexpr int kRayWaves = 4;        // waves per ray work group (one scanline each)
 #define SG_MAX_LABELS_DEV 256
 
+// Label maps live on the device in bricks of 8 x 4 x 4 voxels (128 bytes, one
+// cache line; x fastest inside a brick, bricks in x, y, z order), so a gather
+// along any direction touches few lines.  The voxel's linear index
+// (iz ny + iy) nx + ix stays its identity (noise counter, debug planes).
+constexpr int kBrickX = 8, kBrickY = 4, kBrickZ = 4, kBrickBytes = kBrickX * kBrickY * kBrickZ;
+
 struct VolDev {
-    const uint8_t* labels;
+    const uint8_t* labels;   // bricked (see kBrickX); library-owned copy
     const int16_t* ct;   // may be null
     double sx, sy, sz;   // voxel spacing, mm
     int32_t nx, ny, nz;
+    int32_t bnx, bny;    // bricks along x and y
     uint32_t key0, key1; // noise-field key (low / high word of the seed)
     int32_t scales;      // noise scales S >= 1
 };
@@ -164,6 +171,19 @@ hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses
 hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s);
 hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tile_x, int grid, hipStream_t s);
 hipError_t launch_max_label(const uint8_t* labels, int64_t n, int32_t* d_out, hipStream_t s);
+// copy a linear [nz][ny][nx] label map into the bricked layout (bricks = bnx * bny * bnz; padding voxels 0)
+hipError_t launch_brick_labels(const uint8_t* src, int32_t nx, int32_t ny, int32_t nz, uint8_t* dst, hipStream_t s);
+
+#if defined(__HIP__)
+// byte offset of voxel (ix, iy, iz), inside the grid, in the bricked label map;
+// brick counts below 2^24 (checked at registration) keep the 24-bit products exact
+__device__ __forceinline__ uint32_t brick_offset(const VolDev& v, int32_t ix, int32_t iy, int32_t iz)
+{
+    const uint32_t b = __umul24(__umul24((uint32_t)iz >> 2, (uint32_t)v.bny) + ((uint32_t)iy >> 2), (uint32_t)v.bnx) +
+                       ((uint32_t)ix >> 3);
+    return (b << 7) | (((uint32_t)iz & 3u) << 5) | (((uint32_t)iy & 3u) << 3) | ((uint32_t)ix & 7u);
+}
+#endif
 // surrogate input encoding of every pixel of n_envs frames (8 bf16 per pixel)
 hipError_t launch_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, uint16_t* enc, hipStream_t s);
 // CT-conditioned input: per-frame HU histograms (hist, n_envs x kCtBins), and when enc is given the

@@ -266,6 +266,7 @@ extern "C" sg_status sg_destroy(sg_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     surrogate_release_all(c);
     recon_release_all(c);
+    for (HostVolume& v : c->vols) (void)hipFree(v.bricks);
     delete c;
     return SG_OK;
 }
@@ -309,8 +310,27 @@ extern "C" sg_status sg_volume_register(sg_ctx* c, const sg_volume_desc* d, int3
     e = hipMemcpyAsync(&mx, c->scan.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "max-label readback");
+    // the library's bricked copy of the label map
+    const int64_t bnx = (d->nx + kBrickX - 1) / kBrickX, bny = (d->ny + kBrickY - 1) / kBrickY,
+                  bnz = (d->nz + kBrickZ - 1) / kBrickZ;
+    const int64_t n_bricks = bnx * bny * bnz;
+    if (n_bricks >= (1ll << 24))
+        return fail(SG_EINVAL, "volume needs %lld label bricks of %dx%dx%d voxels (limit 2^24 - 1)",
+                    (long long)n_bricks, kBrickX, kBrickY, kBrickZ);
+    uint8_t* bricks = nullptr;
+    e = hipMalloc((void**)&bricks, (size_t)n_bricks * kBrickBytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc (label bricks)");
+    e = launch_brick_labels(d->labels, d->nx, d->ny, d->nz, bricks, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(bricks);
+        return hip_fail(e, "label bricking");
+    }
     HostVolume v;
-    v.dev.labels = d->labels;
+    v.bricks = bricks;
+    v.dev.labels = bricks;
+    v.dev.bnx = (int32_t)bnx;
+    v.dev.bny = (int32_t)bny;
     v.dev.ct = d->ct_hu;
     v.dev.sx = d->spacing_mm[0];
     v.dev.sy = d->spacing_mm[1];
@@ -333,7 +353,14 @@ extern "C" sg_status sg_volume_release(sg_ctx* c, int32_t id)
 {
     if (!c || id < 0 || id >= (int32_t)c->vols.size() || !c->vols[id].live)
         return fail(SG_EINVAL, "sg_volume_release: bad volume id %d", id);
+    // work already enqueued may still read the bricked labels
+    (void)hipSetDevice(c->device);
+    const hipError_t e = hipStreamSynchronize(c->stream);
     c->vols[id].live = false;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    (void)hipFree(c->vols[id].bricks);
+    c->vols[id].bricks = nullptr;
+    c->vols[id].dev.labels = nullptr;
     return SG_OK;
 }
 
