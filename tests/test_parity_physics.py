@@ -217,3 +217,48 @@ def test_error_paths(sess):
     sg.sg_tissue_table_set(sess.ctx, wl.table)
     sim()
     torch.cuda.synchronize()
+
+
+def test_odd_volume_dims_random_labels(sess):
+    """A label volume whose sides are not multiples of the 8 x 4 x 4-voxel
+    bricks, with a random label per voxel, cut by an oblique plane that also
+    leaves it: every pixel's label and voxel index (and the frame) against the
+    oracle."""
+    rng = np.random.default_rng(11)
+    vol = Volume(labels=rng.integers(1, 4, size=(29, 13, 37), dtype=np.uint8), seed=5)
+    a, b = 0.6, 0.12
+    Ry = np.array([[np.cos(a), 0, np.sin(a)], [0, 1, 0], [-np.sin(a), 0, np.cos(a)]])
+    Rx = np.array([[1, 0, 0], [0, np.cos(b), -np.sin(b)], [0, np.sin(b), np.cos(b)]])
+    wl = single_env(vol, Probe(W=90, H=100, dx=0.45, dy=0.4), axis_pose((-3.0, 4.0, -2.0), Ry @ Rx))
+    g = check_all(sess, wl, name="odd dims")
+    assert (g[0]["voxel"] == -1).any() and (g[0]["voxel"] >= 0).any()
+    assert len(np.unique(g[0]["label"])) >= 3
+
+
+def test_registration_copies_the_label_map(sess):
+    """The library keeps its own (bricked) copy of a label map: later changes
+    to the caller's buffer do not reach the frames, and a released volume is
+    refused."""
+    from paper_2507_01152_amd import sonosim as sg
+    wl = synth.ellipsoid_workload(seed=3, n_envs=1)
+    v = wl.volumes[0]
+    lab = torch.from_numpy(np.ascontiguousarray(v.labels)).to(sess.device)
+    vid = sg.sg_volume_register(sess.ctx, lab, v.spacing, None, v.seed, 1)
+    sg.sg_tissue_table_set(sess.ctx, wl.table)
+    out, offs = sess.frames(wl)
+    ids = np.asarray([vid], dtype=np.int32)
+    sg.sg_simulate(sess.ctx, ids, wl.probes, wl.poses, out, offs)
+    torch.cuda.synchronize()
+    first = out.clone()
+    assert (first > 0).any()
+    lab.fill_(2)
+    out.zero_()
+    sg.sg_simulate(sess.ctx, ids, wl.probes, wl.poses, out, offs)
+    torch.cuda.synchronize()
+    assert torch.equal(out, first)
+    sg.sg_volume_release(sess.ctx, vid)
+    with pytest.raises(sg.SonosimError) as e:
+        sg.sg_simulate(sess.ctx, ids, wl.probes, wl.poses, out, offs)
+    assert e.value.status == sg.SG_EINVAL
+    with pytest.raises(sg.SonosimError):
+        sg.sg_volume_release(sess.ctx, vid)
