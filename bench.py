@@ -477,6 +477,12 @@ def main():
             _frames, used = oracle.simulate_batch(wl, n_threads=0)
             dt += time.perf_counter() - t
             reps += 1
+        # one core: the first 64 envs once, scaled by their share of the step's pixels
+        sub = list(range(min(64, n)))
+        sub_px = sum(wl.probes[e].W * wl.probes[e].H for e in sub)
+        t = time.perf_counter()
+        _frames, used1 = oracle.simulate_batch(wl, env_ids=sub, n_threads=1)
+        dt1 = time.perf_counter() - t
         res["cpu_baseline"] = {
             "value": round(reps * n / dt, 2),
             "unit": "frames/s",
@@ -484,6 +490,9 @@ def main():
             "kind": "oracle",
             "sample": f"{reps} full steps of the same workload ({n} envs, {pixels} px each), FP64, "
                       f"OpenMP over envs, {dt:.1f} s wall",
+            "single_core": {"value": round(n * sub_px / pixels / dt1, 2), "unit": "frames/s", "cores": used1,
+                            "sample": f"envs 0..{len(sub) - 1} of the step once ({sub_px} px), {dt1:.2f} s, "
+                                      f"as frames of the step's mean size"},
         }
         res["gpu_vs_cpu"] = round(fps / res["cpu_baseline"]["value"], 1)
     if args.surrogate_steps > 0:
