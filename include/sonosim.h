@@ -77,7 +77,8 @@ sg_status sg_synchronize(sg_ctx* ctx);
 typedef struct {
     int32_t nx, ny, nz;        /* voxels; nx*ny*nz < 2^31 */
     double spacing_mm[3];      /* voxel spacing along x, y, z (> 0) */
-    const uint8_t* labels;     /* device, [nz][ny][nx] (x fastest), caller-owned */
+    const uint8_t* labels;     /* device, [nz][ny][nx] (x fastest), caller-owned;
+                                  read during sg_volume_register only */
     const int16_t* ct_hu;      /* device, same layout, HU; or NULL (then Z comes
                                   from the tissue table) */
     uint64_t noise_seed;       /* key of the fixed per-voxel noise fields
