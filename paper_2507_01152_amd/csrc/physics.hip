@@ -340,9 +340,9 @@ __device__ __forceinline__ float incidence_cos_wave(const EnvDev& e, const VolDe
 
 // Axial filter of one chunk from the ring of (R', T) pairs: lane l outputs
 // row y0 + l.  Taps go in groups of four, the next group's ring reads issued
-// before this group's FMAs; kax (16-byte aligned) holds zeros past 2 ra up to
-// the group end, and a zero tap leaves a finite sum unchanged, so the sums are
-// those of the taps 0..2 ra in order.
+// before this group's FMAs; kax (16-byte aligned, kTaps + 7 entries) holds
+// zeros past 2 ra, and a zero tap leaves a finite sum unchanged, so the sums
+// are those of the taps 0..2 ra in order.
 __device__ __forceinline__ void axial_from_ring(const float2* ring, const float* kax, int ra, int y0, int lane,
                                                 float& aR, float& aT)
 {
@@ -354,37 +354,40 @@ __device__ __forceinline__ void axial_from_ring(const float2* ring, const float*
     const float2* p = ring + ((y0 - ra + kRing) & (kRing - 1)) + lane;
     const int ng = (2 * ra + 4) >> 2;   // groups of four taps covering 0..2 ra
     const float4* k4 = reinterpret_cast<const float4*>(kax);
-    // two register sets in turn: a group's taps are read first, then the next
-    // group's ring values, then this group's FMAs
+    // two register sets in turn: the next group's taps and ring values are read
+    // before this group's FMAs (taps up to 2 ra + 7, zero past 2 ra)
+    float4 ka = k4[0], kb;
     float2 a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3], b0, b1, b2, b3;
     for (int g = 0;;) {
-        float4 k = k4[g];
+        kb = k4[g + 1];
         b0 = p[4 * g + 4];   // read past the last group too (unused; in bounds, see above)
         b1 = p[4 * g + 5];
         b2 = p[4 * g + 6];
         b3 = p[4 * g + 7];
-        s1 = fmaf(k.x, a0.x, s1);
-        s2 = fmaf(k.x, a0.y, s2);
-        s1 = fmaf(k.y, a1.x, s1);
-        s2 = fmaf(k.y, a1.y, s2);
-        s1 = fmaf(k.z, a2.x, s1);
-        s2 = fmaf(k.z, a2.y, s2);
-        s1 = fmaf(k.w, a3.x, s1);
-        s2 = fmaf(k.w, a3.y, s2);
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the FMAs
+        s1 = fmaf(ka.x, a0.x, s1);
+        s2 = fmaf(ka.x, a0.y, s2);
+        s1 = fmaf(ka.y, a1.x, s1);
+        s2 = fmaf(ka.y, a1.y, s2);
+        s1 = fmaf(ka.z, a2.x, s1);
+        s2 = fmaf(ka.z, a2.y, s2);
+        s1 = fmaf(ka.w, a3.x, s1);
+        s2 = fmaf(ka.w, a3.y, s2);
         if (++g >= ng) break;
-        k = k4[g];
-        a0 = p[4 * g + 4];   // read past the last group too (unused; in bounds, see above)
+        ka = k4[g + 1];
+        a0 = p[4 * g + 4];
         a1 = p[4 * g + 5];
         a2 = p[4 * g + 6];
         a3 = p[4 * g + 7];
-        s1 = fmaf(k.x, b0.x, s1);
-        s2 = fmaf(k.x, b0.y, s2);
-        s1 = fmaf(k.y, b1.x, s1);
-        s2 = fmaf(k.y, b1.y, s2);
-        s1 = fmaf(k.z, b2.x, s1);
-        s2 = fmaf(k.z, b2.y, s2);
-        s1 = fmaf(k.w, b3.x, s1);
-        s2 = fmaf(k.w, b3.y, s2);
+        __builtin_amdgcn_sched_barrier(0);
+        s1 = fmaf(kb.x, b0.x, s1);
+        s2 = fmaf(kb.x, b0.y, s2);
+        s1 = fmaf(kb.y, b1.x, s1);
+        s2 = fmaf(kb.y, b1.y, s2);
+        s1 = fmaf(kb.z, b2.x, s1);
+        s2 = fmaf(kb.z, b2.y, s2);
+        s1 = fmaf(kb.w, b3.x, s1);
+        s2 = fmaf(kb.w, b3.y, s2);
         if (++g >= ng) break;
     }
     aR = s1;
@@ -582,7 +585,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
 {
     __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
     __shared__ float2 s_pair[kPairLabels * kPairLabels];
-    __shared__ __attribute__((aligned(16))) float s_kax[kTaps + 3];   // zeros past 2 rax up to a group of 4
+    __shared__ __attribute__((aligned(16))) float s_kax[kTaps + 7];   // zeros past 2 rax (read ahead by a group)
     __shared__ float2 s_ring[kWaves][kRingAlloc];
     __shared__ int s_item;
     for (int i = threadIdx.x; i < a.n_labels; i += kThreads) s_tab[i] = a.table[i];
@@ -596,7 +599,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
         const ItemRay it = a.ray_items[item];
         const EnvDev e = a.envs[it.env];
         const VolDev v = a.vols[e.vol];
-        for (int i = threadIdx.x; i < kTaps + 3; i += kThreads) s_kax[i] = i <= 2 * e.rax ? a.coefs[e.kax + i] : 0.f;
+        for (int i = threadIdx.x; i < kTaps + 7; i += kThreads) s_kax[i] = i <= 2 * e.rax ? a.coefs[e.kax + i] : 0.f;
         __syncthreads();
         for (int s = 0; s < a.scanlines_per_wave; ++s) {
             const int x = it.x0 + s * kWaves + wave;
