@@ -395,9 +395,10 @@ __device__ __forceinline__ void axial_from_ring(const float2* ring, const float*
 }
 
 // One scanline of the ray pass, executed by one wave (lane = depth row).
-// MS: the volume may have several noise scales (a separate instantiation, so
-// the single-scale code keeps its registers)
-template <bool MS>
+// MS: the volume may have several noise scales; LAB: label volume whose
+// boundaries take (r, t) from the label-pair table (no CT, no FP64 impedance
+// path).  Separate instantiations, so the common code keeps its registers.
+template <bool MS, bool LAB>
 __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v, const TissueDev* tab,
                              const float2* pair_rt, const float* kax, float2* ring, int x, int lane)
 {
@@ -413,7 +414,7 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         }
         return;
     }
-    const bool ct = v.ct != nullptr;
+    const bool ct = !LAB && v.ct != nullptr;
     const int ra = e.rax;
     // rows -64..-1 of the ring read as zeros (zero padding above the image)
     ring_put(ring, kRing - kWave + lane, make_float2(0.f, 0.f));
@@ -422,7 +423,7 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
     float carry_a = 0.f;     // attenuation integral (sum of alpha) above the chunk,
     float carry_c = 0.f;     // with its Kahan compensation (integral = carry_a - carry_c)
     const float coef2 = (float)e.coef2;
-    const bool pairs = !ct && pair_rt != nullptr;
+    const bool pairs = LAB || (!ct && pair_rt != nullptr);
     const int n_lab = a.n_labels;
     float E_prev = 0.f;      // E of the previous chunk (its axial output is pending)
 
@@ -580,7 +581,7 @@ __device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
 // Ray kernel: items (env, group of kWaves * spw scanlines), longest first.
 // Five waves per SIMD (at most 102 registers, a few spilled) hide more of the
 // gather latency than four; six spill too much.
-template <bool MS>
+template <bool MS, bool LAB>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_ray(PhysArgs a, QueueDev* q)
 {
     __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
@@ -603,7 +604,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
         __syncthreads();
         for (int s = 0; s < a.scanlines_per_wave; ++s) {
             const int x = it.x0 + s * kWaves + wave;
-            if (x < e.W) ray_scanline<MS>(a, e, v, s_tab, a.pair_rt ? s_pair : nullptr, s_kax, s_ring[wave], x, lane);
+            if (x < e.W)
+                ray_scanline<MS, LAB>(a, e, v, s_tab, a.pair_rt ? s_pair : nullptr, s_kax, s_ring[wave], x, lane);
         }
     }
 }
@@ -1079,10 +1081,12 @@ size_t psf_lds_bytes(int tx, int max_rlat)
 
 bool psf_tile_supported(int tx) { return psf_fn(tx) != nullptr; }
 
-int ray_grid(int n_cu, bool multiscale)
+int ray_grid(int n_cu, bool multiscale, bool label_only)
 {
-    const void* fn = multiscale ? reinterpret_cast<const void*>(&k_ray<true>)
-                                : reinterpret_cast<const void*>(&k_ray<false>);
+    const void* fn = multiscale ? (label_only ? reinterpret_cast<const void*>(&k_ray<true, true>)
+                                              : reinterpret_cast<const void*>(&k_ray<true, false>))
+                                : (label_only ? reinterpret_cast<const void*>(&k_ray<false, true>)
+                                              : reinterpret_cast<const void*>(&k_ray<false, false>));
     return blocks_per_cu(fn, kThreads, 0) * n_cu;
 }
 
@@ -1096,10 +1100,15 @@ hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s)
     if (a.n_ray <= 0) return hipSuccess;
     if (grid > a.n_ray) grid = a.n_ray;
     if (grid < 1) return hipErrorInvalidConfiguration;
-    if (a.multiscale)
-        hipLaunchKernelGGL(k_ray<true>, dim3(grid), dim3(kThreads), 0, s, a, q);
+    const bool lab = ray_label_only(a);
+    if (a.multiscale && lab)
+        hipLaunchKernelGGL((k_ray<true, true>), dim3(grid), dim3(kThreads), 0, s, a, q);
+    else if (a.multiscale)
+        hipLaunchKernelGGL((k_ray<true, false>), dim3(grid), dim3(kThreads), 0, s, a, q);
+    else if (lab)
+        hipLaunchKernelGGL((k_ray<false, true>), dim3(grid), dim3(kThreads), 0, s, a, q);
     else
-        hipLaunchKernelGGL(k_ray<false>, dim3(grid), dim3(kThreads), 0, s, a, q);
+        hipLaunchKernelGGL((k_ray<false, false>), dim3(grid), dim3(kThreads), 0, s, a, q);
     return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ struct Plan {
     int64_t n_scr = 0;                 // field-scratch elements per field (padded scanlines)
     int max_rax = 0, max_rlat = 0;
     int multiscale = 0;                // some env's volume has several noise scales
+    int any_ct = 0;                    // some env's volume has a CT
     LaunchShape shape;
     int grid_ray = 0, grid_psf = 0, grid_psf_last = 0;   // (last: the last chunk's PSF kernel runs alone)
     DevBuf d_envs, d_pool, d_rays, d_tiles, d_poses, d_queue, fields;

@@ -92,6 +92,7 @@ struct PhysArgs {
     const float2* pair_rt;    // [n_labels][n_labels] (r, t) of a boundary between two labels, or null
     const float* q_lut;       // [kNoiseQ] quantised normal of the multi-scale gate
     int32_t multiscale;       // some env's volume has more than one noise scale
+    int32_t any_ct;           // some env's volume has a CT (impedance from HU in FP64)
     const float* coefs;       // PSF taps pool
     const ItemRay* ray_items;
     int32_t n_ray;
@@ -195,7 +196,10 @@ hipError_t launch_ct_reference(const uint32_t* hist, int32_t n_envs, long long* 
                                hipStream_t s);
 size_t psf_lds_bytes(int tile_x, int max_rlat);
 bool psf_tile_supported(int tile_x);
-int ray_grid(int n_cu, bool multiscale);                              // resident ray workgroups
+// the ray kernel's label-only instantiation (boundary (r, t) from the label-pair
+// table, no CT volume) serves a launch without FP64 impedance work
+inline bool ray_label_only(const PhysArgs& a) { return a.pair_rt != nullptr && a.any_ct == 0; }
+int ray_grid(int n_cu, bool multiscale, bool label_only);             // resident ray workgroups
 int psf_grid(int tile_x, int max_rlat, int n_cu);    // resident PSF workgroups
 
 }  // namespace sg

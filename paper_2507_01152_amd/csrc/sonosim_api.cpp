@@ -464,13 +464,14 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
     std::vector<EnvDev> envs;
     std::vector<float> pool;
     int64_t scr = 0;
-    int max_rlat = 0, max_px = 0, multiscale = 0;
+    int max_rlat = 0, max_px = 0, multiscale = 0, any_ct = 0;
     for (int i = 0; i < n; ++i) {
         for (int k = 0; k < 12; ++k)
             if (!std::isfinite(poses[12 * i + k])) return fail(SG_EINVAL, "env %d: pose is not finite", i);
         if (out_offsets[i] < 0) return fail(SG_EINVAL, "env %d: negative output offset", i);
         const VolDev& v = c->vols[vol_ids[i]].dev;
         multiscale |= v.scales > 1;
+        any_ct |= v.ct != nullptr;
         for (int j = 0; j < probe_planes(probes[i]); ++j) {
             EnvDev ed;
             s = fill_env_static(probes[i], vol_ids[i], i, j, out_offsets[i], scr, pool, ed);
@@ -550,6 +551,7 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
     a.scanlines_per_wave = spw;
     a.max_rlat = max_rlat;
     a.multiscale = multiscale;
+    a.any_ct = any_ct;
     info.tile_x = tx;
     info.max_pixels = max_px;
     return SG_OK;
@@ -561,7 +563,7 @@ sg_status launch_physics(sg_ctx* c, const PhysArgs& a, const StageInfo& info)
     QueueDev* q = (QueueDev*)c->queue.p;
     hipError_t e;
     if ((e = launch_queue_reset(q, 1, c->stream)) != hipSuccess) return hip_fail(e, "queue reset");
-    if ((e = launch_ray(a, q, ray_grid(c->n_cu, a.multiscale != 0), c->stream)) != hipSuccess)
+    if ((e = launch_ray(a, q, ray_grid(c->n_cu, a.multiscale != 0, ray_label_only(a)), c->stream)) != hipSuccess)
         return hip_fail(e, "ray kernel launch");
     if ((e = launch_psf(a, q, info.tile_x, psf_grid(info.tile_x, a.max_rlat, c->n_cu), c->stream)) != hipSuccess)
         return hip_fail(e, "PSF kernel launch");

@@ -83,7 +83,9 @@ sg_status apply_shape(sg_ctx* c, Plan* p, const LaunchShape& s)
         rays.insert(rays.end(), r.begin(), r.end());
         tiles.insert(tiles.end(), t.begin(), t.end());
     }
-    int gr = ray_grid(c->n_cu, p->multiscale != 0), gp = psf_grid(s.tx, p->max_rlat, c->n_cu);
+    // occupancy only: a persistent grid's surplus blocks find the work counter spent and exit
+    int gr = ray_grid(c->n_cu, p->multiscale != 0, c->n_labels <= kPairLabels && !p->any_ct),
+        gp = psf_grid(s.tx, p->max_rlat, c->n_cu);
     if (gr < 1 || gp < 1) return fail(SG_EINVAL, "launch shape (tile %d) does not fit a compute unit", s.tx);
     p->grid_psf_last = gp;
     if (K > 1) {   // leave room on every CU for one PSF block beside the ray blocks
@@ -135,6 +137,7 @@ PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
     a.scanlines_per_wave = p->shape.spw;
     a.max_rlat = p->max_rlat;
     a.multiscale = p->multiscale;
+    a.any_ct = p->any_ct;
     return a;
 }
 
@@ -278,6 +281,7 @@ extern "C" sg_status sg_batch_plan_create(sg_ctx* c, int32_t n, const int32_t* v
             p->envs.push_back(ed);
         }
         p->multiscale |= c->vols[vol_ids[i]].dev.scales > 1;
+        p->any_ct |= c->vols[vol_ids[i]].dev.ct != nullptr;
     }
     p->n_envs = (int32_t)p->envs.size();
     const int ni = p->n_envs;
