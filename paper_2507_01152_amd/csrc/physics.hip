@@ -397,7 +397,8 @@ __device__ __forceinline__ void axial_from_ring(const float2* ring, const float*
 // One scanline of the ray pass, executed by one wave (lane = depth row).
 // MS: the volume may have several noise scales; LAB: label volume whose
 // boundaries take (r, t) from the label-pair table (no CT, no FP64 impedance
-// path).  Separate instantiations, so the common code keeps its registers.
+// path) and no debug planes.  Separate instantiations, so the common code
+// keeps its registers.
 template <bool MS, bool LAB>
 __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v, const TissueDev* tab,
                              const float2* pair_rt, const float* kax, float2* ring, int x, int lane)
@@ -533,7 +534,7 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
             fE[yp] = E_prev;
         }
         E_prev = E;
-        if (act) {
+        if (!LAB && act) {
             const int64_t kk = e.out_off + (int64_t)y * e.W + x;
             if (a.dbg.label) a.dbg.label[kk] = (uint8_t)lab;
             if (a.dbg.voxel) a.dbg.voxel[kk] = vox;
@@ -582,7 +583,7 @@ __device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
 // Five waves per SIMD (at most 102 registers, a few spilled) hide more of the
 // gather latency than four; six spill too much.
 template <bool MS, bool LAB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_ray(PhysArgs a, QueueDev* q)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB ? 6 : 5))) void k_ray(PhysArgs a, QueueDev* q)
 {
     __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
     __shared__ float2 s_pair[kPairLabels * kPairLabels];

@@ -262,3 +262,19 @@ def test_registration_copies_the_label_map(sess):
     assert e.value.status == sg.SG_EINVAL
     with pytest.raises(sg.SonosimError):
         sg.sg_volume_release(sess.ctx, vid)
+
+
+@pytest.mark.parametrize("scales", [1, 3])
+def test_fast_and_general_ray_paths_agree_bit_for_bit(sess, scales):
+    """Label volumes without debug planes run the ray kernel's label-only
+    instantiation; with debug planes (as in the oracle parity cases) they run
+    the general one.  Both must give the same frames bit for bit."""
+    import dataclasses
+    wl = synth.ellipsoid_workload(seed=5, n_envs=6)
+    wl = dataclasses.replace(wl, volumes=[dataclasses.replace(v, noise_scales=scales) for v in wl.volumes])
+    vids = sess.load(wl)
+    fast, _, _ = sess.simulate(wl, vids, debug=False)
+    general, _, dbg = sess.simulate(wl, vids, debug=True)
+    torch.cuda.synchronize()
+    assert torch.equal(fast, general)
+    assert (fast > 0).any()
