@@ -583,7 +583,7 @@ __device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
 // Five waves per SIMD (at most 102 registers, a few spilled) hide more of the
 // gather latency than four; six spill too much.
 template <bool MS, bool LAB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB ? 6 : 5))) void k_ray(PhysArgs a, QueueDev* q)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB && !MS ? 6 : 5))) void k_ray(PhysArgs a, QueueDev* q)
 {
     __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
     __shared__ float2 s_pair[kPairLabels * kPairLabels];
