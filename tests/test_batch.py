@@ -215,3 +215,58 @@ def test_out_of_range_pose_gives_zero_frame_and_status(sess):
     ref, _, _ = sess.simulate(synth.Workload(wl.volumes[:1], np.zeros(1, np.int32), wl.probes[:1],
                                              wl.poses[:1], wl.table), vids[:1])
     assert torch.equal(ref, out[:n])
+
+
+def _plan_at_timed_shape(sess, wl, vids):
+    """Plan of the workload at the launch shape the benchmark times (16
+    scanlines per ray item, 64-wide PSF tiles, one chunk), stepped once."""
+    from paper_2507_01152_amd import sonosim as sg
+    offs, total = wl.out_offsets()
+    out = torch.full((total,), -7.0, dtype=torch.float32, device=sess.device)
+    plan = sg.sg_batch_plan_create(sess.ctx, vids, wl.probes, offs)
+    sg.sg_batch_set_poses(sess.ctx, plan, wl.poses)
+    sg.sg_batch_set_config(sess.ctx, plan, 16, 64, 1)
+    sg.sg_batch_step(sess.ctx, plan, out)
+    torch.cuda.synchronize()
+    assert sg.sg_batch_status(sess.ctx, plan) == 0
+    return out, plan
+
+
+def _sampled_vs_oracle(wl, out, env_ids, name):
+    from paper_2507_01152_amd.session import split_frames
+    Y = split_frames(out.cpu().numpy(), wl)
+
+    def one(e):
+        o = oracle.simulate_env(wl.volumes[wl.vol_ids[e]], wl.table, wl.probes[e], wl.poses[e],
+                                planes=("I", "A", "Y"))
+        check_env({"Y": Y[e]}, o, wl.probes[e], f"{name} env {e}")
+        return float(o["Y"].mean())
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        return list(ex.map(one, env_ids))
+
+
+def test_multiscale_batch_at_the_timed_shape_vs_oracle(sess, uneven):
+    """The benchmark's multi-scale batch (the 256 uneven envs with S = 3 noise
+    scales) at the timed launch shape: every 16th env against the oracle."""
+    import dataclasses
+    from paper_2507_01152_amd import sonosim as sg
+    ms = dataclasses.replace(uneven, volumes=[dataclasses.replace(v, noise_scales=3) for v in uneven.volumes])
+    vids = sess.load(ms)
+    out, plan = _plan_at_timed_shape(sess, ms, vids)
+    means = _sampled_vs_oracle(ms, out, range(0, ms.n_envs, 16), "S=3 batch")
+    assert np.mean(means) > 0.02
+    sg.sg_batch_plan_destroy(sess.ctx, plan)
+
+
+def test_volumetric_batch_at_the_timed_shape_vs_oracle(sess):
+    """The benchmark's volumetric batch (256 envs of 50 x 37 x 5 at 2 x 2 x 10
+    mm) at the timed launch shape: every plane of every 16th env against the
+    oracle."""
+    from paper_2507_01152_amd import sonosim as sg
+    vw = synth.volumetric_workload(seed=0)
+    vids = sess.load(vw)
+    out, plan = _plan_at_timed_shape(sess, vw, vids)
+    means = _sampled_vs_oracle(vw, out, range(0, vw.n_envs, 16), "volumetric batch")
+    assert np.mean(means) > 0.0
+    sg.sg_batch_plan_destroy(sess.ctx, plan)
