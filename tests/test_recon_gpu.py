@@ -101,3 +101,40 @@ def test_recon_rejects_bad_arguments(sess):
     with pytest.raises(sg.SonosimError):
         sg.sg_recon_update(sess.ctx, rid, 0)
     sg.sg_recon_destroy(sess.ctx, rid)
+
+
+def test_recon_benchmark_batch_sampled_vs_oracle(sess):
+    """The benchmark's reconstruction leg at full size: the 256 envs of the
+    benchmark batch stepped once at the timed launch shape, then 20 updates
+    (capacity 65536 points, 20 % drop, seed 1) and the 40^3 observation: the
+    stored points and the grid of every 16th env against the oracle."""
+    from paper_2507_01152_amd import sonosim as sg
+    wl = synth.batched_workload(seed=0)
+    n = wl.n_envs
+    vids = sess.load(wl)
+    offs, total = wl.out_offsets()
+    plan = sg.sg_batch_plan_create(sess.ctx, vids, wl.probes, offs)
+    sg.sg_batch_set_poses(sess.ctx, plan, wl.poses)
+    sg.sg_batch_set_config(sess.ctx, plan, 16, 64, 1)
+    out = torch.empty(total, dtype=torch.float32, device=sess.device)
+    sg.sg_batch_step(sess.ctx, plan, out)
+    rid = sg.sg_recon_create(sess.ctx, plan, 65536, None, 0.2, seed=1)
+    for st in range(20):
+        sg.sg_recon_update(sess.ctx, rid, st)
+    grids = torch.zeros(n * 40 ** 3, dtype=torch.uint8, device=sess.device)
+    sg.sg_recon_observe(sess.ctx, rid, grids)
+    stored, over = sg.sg_recon_counts(sess.ctx, rid, n)
+    g = grids.cpu().numpy().reshape(n, 40, 40, 40)
+    key = lambda a: a[np.lexsort(a.T[::-1])]
+    total_pts = 0
+    for e in range(0, n, 16):
+        ref = np.concatenate([oracle.recon_points(wl.volumes[wl.vol_ids[e]], wl.probes[e], wl.poses[e], e, st, 1, 0.2)
+                              for st in range(20)])
+        assert stored[e] == ref.shape[0] and over[e] == 0, e
+        got = sg.sg_recon_points(sess.ctx, rid, e, 65536)
+        assert np.array_equal(key(got), key(ref)), e
+        assert np.array_equal(g[e], oracle.recon_observe(ref, wl.poses[e])), e
+        total_pts += ref.shape[0]
+    assert total_pts > 100
+    sg.sg_recon_destroy(sess.ctx, rid)
+    sg.sg_batch_plan_destroy(sess.ctx, plan)
