@@ -320,10 +320,13 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
 // with one output can be fused.
 constexpr int kTileH = 8, kTileW = 32;
 
-template <int C, int CO>
+template <int C, int CO, bool UP>
 __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
 {
-    constexpr int HP = kTileH + 2, WP = kTileW + 2;
+    // UP: the input is read upsampled x2; the tile stages the stored pixels it
+    // covers (fine halo pixel (hy, wx) of the 10 x 34 window is stored pixel
+    // ((hy + 1) / 2, (wx + 1) / 2) of a 6 x 18 window, tile origins being even)
+    constexpr int HP = UP ? kTileH / 2 + 2 : kTileH + 2, WP = UP ? kTileW / 2 + 2 : kTileW + 2;
     constexpr int C8 = C / 8;
     constexpr int PS = (C8 % 2 == 0) ? C + 8 : C;   // LDS pixel stride (bf16)
     constexpr int K8 = 9 * C8;                       // 8-wide K groups
@@ -353,14 +356,20 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     for (int i = tid; i < HP * WP * C8; i += 256) {
         const int c8 = i % C8, pix = i / C8;
         const int hy = pix / WP, wx = pix - hy * WP;
-        int hi = ho0 - 1 + hy, wi = wo0 - 1 + wx;
         u32x4 v = zero;
-        if (hi >= 0 && wi >= 0 && hi < Hin && wi < Win) {
-            if (g.up) {
-                hi >>= 1;
-                wi >>= 1;
+        if constexpr (UP) {   // stored pixels (ho0 / 2 - 1 + hy, wo0 / 2 - 1 + wx), zero outside
+            const int hi = ho0 / 2 - 1 + hy, wi = wo0 / 2 - 1 + wx;
+            if (hi >= 0 && wi >= 0 && hi < g.H && wi < g.W)
+                v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + hi) * g.W + wi) * C + c8 * 8);
+        } else {
+            int hi = ho0 - 1 + hy, wi = wo0 - 1 + wx;
+            if (hi >= 0 && wi >= 0 && hi < Hin && wi < Win) {
+                if (g.up) {
+                    hi >>= 1;
+                    wi >>= 1;
+                }
+                v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + hi) * g.W + wi) * C + c8 * 8);
             }
-            v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + hi) * g.W + wi) * C + c8 * 8);
         }
         *reinterpret_cast<u32x4*>(&sX[pix * PS + c8 * 8]) = v;
     }
@@ -392,7 +401,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
 #pragma unroll
         for (int gi = 0; gi < 4; ++gi) {
             const int rr = 2 * wave + (gi >> 1), cc = (gi & 1) * 16 + lr;
-            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sX[((rr + r) * WP + cc + s) * PS + c0]);
+            const int sy = UP ? (rr + r + 1) >> 1 : rr + r, sx = UP ? (cc + s + 1) >> 1 : cc + s;
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sX[(sy * WP + sx) * PS + c0]);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
                 acc[gi][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[gi][j], 0, 0, 0);
@@ -1094,28 +1104,41 @@ hipError_t launch_gemm(const ConvGeom& g, const ConvArgs& a, int splits, hipStre
 
 bool conv_tile_supported(const ConvGeom& g)
 {
-    return g.kh == 3 && g.kw == 3 && g.stride == 1 && g.pad == 1 && (g.C == 8 || g.C == 16 || g.C == 24 || g.C == 32) &&
-           (g.Co == 16 || g.Co == 32) && g.Ho == (g.up ? 2 * g.H : g.H) && g.Wo == (g.up ? 2 * g.W : g.W);
+    const bool shape = g.kh == 3 && g.kw == 3 && g.stride == 1 && g.pad == 1 && (g.Co == 16 || g.Co == 32) &&
+                       g.Ho == (g.up ? 2 * g.H : g.H) && g.Wo == (g.up ? 2 * g.W : g.W);
+    // 64 input channels only upsampled, where the staged tile is the 6 x 18 stored one
+    return shape && (g.C == 8 || g.C == 16 || g.C == 24 || g.C == 32 || (g.C == 64 && g.up && g.Co == 32));
 }
 
-template <int C, int CO>
+template <int C, int CO, bool UP>
 hipError_t launch_tile(const ConvGeom& g, const ConvArgs& a, hipStream_t s)
 {
     const int64_t tiles = (int64_t)((g.Ho + kTileH - 1) / kTileH) * ((g.Wo + kTileW - 1) / kTileW);
     const int64_t blocks = tiles * (g.Kw / ((int64_t)g.Ho * g.Wo));   // Kw = N * Ho * Wo
     if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_conv3x3_tile<C, CO>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
+    hipLaunchKernelGGL((k_conv3x3_tile<C, CO, UP>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
     return hipGetLastError();
 }
 
 template <int CO>
 hipError_t launch_tile_co(const ConvGeom& g, const ConvArgs& a, hipStream_t s)
 {
+    if (g.up) {
+        switch (g.C) {
+        case 8: return launch_tile<8, CO, true>(g, a, s);
+        case 16: return launch_tile<16, CO, true>(g, a, s);
+        case 24: return launch_tile<24, CO, true>(g, a, s);
+        case 32: return launch_tile<32, CO, true>(g, a, s);
+        default:
+            if constexpr (CO == 32) return launch_tile<64, 32, true>(g, a, s);
+            return hipErrorInvalidValue;
+        }
+    }
     switch (g.C) {
-    case 8: return launch_tile<8, CO>(g, a, s);
-    case 16: return launch_tile<16, CO>(g, a, s);
-    case 24: return launch_tile<24, CO>(g, a, s);
-    default: return launch_tile<32, CO>(g, a, s);
+    case 8: return launch_tile<8, CO, false>(g, a, s);
+    case 16: return launch_tile<16, CO, false>(g, a, s);
+    case 24: return launch_tile<24, CO, false>(g, a, s);
+    default: return launch_tile<32, CO, false>(g, a, s);
     }
 }
 

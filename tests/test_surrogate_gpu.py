@@ -46,6 +46,9 @@ CONV_CASES = [
     (1, 7, 11, 32, 16, 3, 1, 1, 1),      # upsampled to 14 x 22
     (2, 10, 33, 16, 32, 3, 1, 1, 0),     # 32 output channels
     (1, 9, 40, 32, 32, 3, 1, 1, 1),      # upsampled, 32 -> 32
+    # upsampled inputs staged as coarse tiles (6 x 18 stored pixels per 8 x 32 output tile)
+    (2, 6, 20, 64, 32, 3, 1, 1, 1),      # 64 -> 32 (the U1 shape), ragged tiles in both directions
+    (1, 13, 9, 32, 16, 3, 1, 1, 1),      # 32 -> 16 (the U0 shape), odd stored sizes
 ]
 
 
