@@ -620,7 +620,7 @@ constexpr int kRB = 8;
 constexpr int kSx = 8;
 
 template <int TX>
-__global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* q)
+__global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a)
 {
     static_assert(TX % kSx == 0, "strips");
     constexpr int kPW = TX / kSx;        // waves: one 8-column output strip each
@@ -806,7 +806,6 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a, QueueDev* 
                 if (x0 + cx < W) orow[cx] = sY[rr * (TX + 1) + cx];
         }
     }
-    (void)q;   // the queue counter is reset by the step but unused here
 }
 
 // Surrogate input of each pixel: one-hot label (channels 0..3), the
@@ -999,10 +998,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_ct(PhysArgs a, const uint16
 __global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int n, QueueDev* q, int n_queues)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n_queues) {
-        q[e].next_ray = 0;
-        q[e].next_psf = 0;
-    }
+    if (e < n_queues) q[e].next_ray = 0;
     if (e >= n) return;
     EnvDev& d = envs[e];
     const VolDev v = vols[d.vol];
@@ -1019,12 +1015,7 @@ __global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses
 
 __global__ void k_queue_reset(QueueDev* q, int n)
 {
-    if ((int)threadIdx.x < n) {
-        q[threadIdx.x].next_ray = 0;
-        q[threadIdx.x].next_psf = 0;
-        q[threadIdx.x].n_bad = 0;
-        q[threadIdx.x].pad = 0;
-    }
+    if ((int)threadIdx.x < n) q[threadIdx.x].next_ray = 0;
 }
 
 // linear [nz][ny][nx] label map -> bricked layout, one thread per destination byte (padding voxels 0)
@@ -1113,18 +1104,18 @@ hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tx, int grid, hipStream_t s)
+hipError_t launch_psf(const PhysArgs& a, int tx, int grid, hipStream_t s)
 {
     if (a.n_psf <= 0) return hipSuccess;
     if (grid > a.n_psf) grid = a.n_psf;
     if (grid < 1) return hipErrorInvalidConfiguration;
     const size_t lds = psf_lds_bytes(tx, a.max_rlat);
     if (tx == 16)
-        hipLaunchKernelGGL(k_psf<16>, dim3(grid), dim3(psf_threads(16)), lds, s, a, q);
+        hipLaunchKernelGGL(k_psf<16>, dim3(grid), dim3(psf_threads(16)), lds, s, a);
     else if (tx == 32)
-        hipLaunchKernelGGL(k_psf<32>, dim3(grid), dim3(psf_threads(32)), lds, s, a, q);
+        hipLaunchKernelGGL(k_psf<32>, dim3(grid), dim3(psf_threads(32)), lds, s, a);
     else if (tx == 64)
-        hipLaunchKernelGGL(k_psf<64>, dim3(grid), dim3(psf_threads(64)), lds, s, a, q);
+        hipLaunchKernelGGL(k_psf<64>, dim3(grid), dim3(psf_threads(64)), lds, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -169,7 +169,6 @@ extern "C" sg_status sg_hbm_probe(sg_ctx* c, const void* src, void* dst, size_t 
     const char* d8 = static_cast<const char*>(dst);
     if (s8 < d8 + bytes && d8 < s8 + bytes) return fail(SG_EINVAL, "sg_hbm_probe: buffers overlap");
     (void)hipSetDevice(c->device);
-    const int threads = 256;
     const size_t n4 = bytes / 16;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);

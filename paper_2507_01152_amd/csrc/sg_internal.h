@@ -110,9 +110,7 @@ struct PhysArgs {
 // work-queue state of the two persistent kernels (device)
 struct QueueDev {
     int32_t next_ray;    // next ray work item
-    int32_t next_psf;    // next PSF tile
-    int32_t n_bad;       // unused (rejected poses are counted from the envs' valid flags)
-    int32_t pad;
+    int32_t pad[3];
 };
 
 // Plane geometry: the pose [R|t] (probe mm -> volume mm) places pixel (x, y)
@@ -170,7 +168,7 @@ hipError_t launch_queue_reset(QueueDev* q, int n_queues, hipStream_t s);   // re
 hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n_envs, QueueDev* q,
                            int32_t n_queues, hipStream_t s);   // also resets the work counters q[0 .. n_queues)
 hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s);
-hipError_t launch_psf(const PhysArgs& a, QueueDev* q, int tile_x, int grid, hipStream_t s);
+hipError_t launch_psf(const PhysArgs& a, int tile_x, int grid, hipStream_t s);
 hipError_t launch_max_label(const uint8_t* labels, int64_t n, int32_t* d_out, hipStream_t s);
 // copy a linear [nz][ny][nx] label map into the bricked layout (bricks = bnx * bny * bnz; padding voxels 0)
 hipError_t launch_brick_labels(const uint8_t* src, int32_t nx, int32_t ny, int32_t nz, uint8_t* dst, hipStream_t s);

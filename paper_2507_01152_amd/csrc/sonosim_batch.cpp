@@ -157,7 +157,7 @@ hipError_t enqueue_step(sg_ctx* c, Plan* p, float* out, hipStream_t s, hipEvent_
         const PhysArgs a = plan_args(c, p, out);
         if (e == hipSuccess) e = launch_ray(a, q, p->grid_ray, s);
         if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
-        if (e == hipSuccess) e = launch_psf(a, q, p->shape.tx, p->grid_psf, s);
+        if (e == hipSuccess) e = launch_psf(a, p->shape.tx, p->grid_psf, s);
         if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
         return e;
     }
@@ -170,7 +170,7 @@ hipError_t enqueue_step(sg_ctx* c, Plan* p, float* out, hipStream_t s, hipEvent_
         e = launch_ray(a, q + k, p->grid_ray, s);
         if (e == hipSuccess) e = hipEventRecord(p->ev_ray[k], s);
         if (e == hipSuccess) e = hipStreamWaitEvent(p->aux, p->ev_ray[k], 0);
-        if (e == hipSuccess) e = launch_psf(a, q + k, p->shape.tx, k == K - 1 ? p->grid_psf_last : p->grid_psf, p->aux);
+        if (e == hipSuccess) e = launch_psf(a, p->shape.tx, k == K - 1 ? p->grid_psf_last : p->grid_psf, p->aux);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
     if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->aux);
