@@ -64,12 +64,15 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
     constexpr int FM = TM / 16, FN = TN / 16;
     static_assert(WM * WN == 4, "four waves");
     static_assert(FM >= 1 && FN >= 1, "tile");
-    // staged 16-byte chunks per K step: K-contiguous operands are (row, 8 k)
-    // chunks, the weight gradient's are (8 rows, k) chunks
-    constexpr int CA = (MODE == kWgrad) ? (BM / 8) * kBK : BM * (kBK / 8);
-    constexpr int CB = (MODE == kWgrad) ? (BN / 8) * kBK : BN * (kBK / 8);
-    constexpr int PA = (CA + kThreads - 1) / kThreads;
-    constexpr int PB = (CB + kThreads - 1) / kThreads;
+    // staged per K step: K-contiguous operands in (row, 8 k) 16-byte chunks
+    // (one per register); the weight gradient's in tasks of 8 rows x 4 k, four
+    // 16-byte (8 rows, k) chunks per task, transposed in registers into one
+    // 8-byte (row, 4 k) LDS store per row
+    constexpr int CA = (MODE == kWgrad) ? (BM / 8) * (kBK / 4) : BM * (kBK / 8);
+    constexpr int CB = (MODE == kWgrad) ? (BN / 8) * (kBK / 4) : BN * (kBK / 8);
+    constexpr int RPC = (MODE == kWgrad) ? 4 : 1;   // registers per chunk or task
+    constexpr int PA = RPC * ((CA + kThreads - 1) / kThreads);
+    constexpr int PB = RPC * ((CB + kThreads - 1) / kThreads);
     constexpr int AM8 = BM / 8, BN8 = BN / 8;   // weight-gradient row groups
 
     __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * kBKP];
@@ -145,16 +148,16 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
         if constexpr (MODE == kWgrad) {
 #pragma unroll
             for (int i = 0; i < PA; ++i) {
-                const int c = tid + i * kThreads;
-                const int64_t k = k0 + c / AM8;
+                const int c = tid + (i / 4) * kThreads;   // task: rows wg_m0.., k = 4 (c / AM8) + i % 4
+                const int64_t k = k0 + 4 * (c / AM8) + (i & 3);
                 ra[i] = (c < CA && wg_m0 < g.M && k < k_end)
                             ? *reinterpret_cast<const u32x4*>(A + k * g.Co + wg_m0)
                             : zero;
             }
 #pragma unroll
             for (int i = 0; i < PB; ++i) {
-                const int c = tid + i * kThreads;
-                const int64_t k = k0 + c / BN8;
+                const int c = tid + (i / 4) * kThreads;
+                const int64_t k = k0 + 4 * (c / BN8) + (i & 3);
                 rb[i] = zero;
                 if (c < CB && wg_n0 < g.N && k < k_end) {
                     const int p = (int)k;
@@ -214,34 +217,43 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
                         : zero;
         }
     };
+    // four (8 rows, k) chunks of consecutive k -> row j's 4 k as one 8-byte value
+    auto transpose_store = [&](uint16_t* dst, const u32x4* r, int row0, int kk) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int w = j >> 1;
+            const uint32_t lo = (j & 1) ? ((r[0][w] >> 16) | (r[1][w] & 0xFFFF0000u))
+                                        : ((r[0][w] & 0xFFFFu) | (r[1][w] << 16));
+            const uint32_t hi = (j & 1) ? ((r[2][w] >> 16) | (r[3][w] & 0xFFFF0000u))
+                                        : ((r[2][w] & 0xFFFFu) | (r[3][w] << 16));
+            *reinterpret_cast<uint2*>(&dst[(row0 + j) * kBKP + kk]) = make_uint2(lo, hi);
+        }
+    };
     auto store_tiles = [&](int buf) __attribute__((always_inline)) {
+        if constexpr (MODE == kWgrad) {
+#pragma unroll
+            for (int i = 0; i < PA / 4; ++i) {
+                const int c = tid + i * kThreads;
+                if (c < CA) transpose_store(sA[buf], ra + 4 * i, (c % AM8) * 8, 4 * (c / AM8));
+            }
+#pragma unroll
+            for (int i = 0; i < PB / 4; ++i) {
+                const int c = tid + i * kThreads;
+                if (c < CB) transpose_store(sB[buf], rb + 4 * i, (c % BN8) * 8, 4 * (c / BN8));
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < PA; ++i) {
             const int c = tid + i * kThreads;
             if (c >= CA) continue;
-            if constexpr (MODE == kWgrad) {
-                const int m8 = c % AM8, kk = c / AM8;
-                const u32x4 w4 = ra[i];
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    sA[buf][(m8 * 8 + j) * kBKP + kk] = (uint16_t)(w4[j >> 1] >> ((j & 1) * 16));
-            } else {
-                *reinterpret_cast<u32x4*>(&sA[buf][(c >> 2) * kBKP + k8 * 8]) = ra[i];
-            }
+            *reinterpret_cast<u32x4*>(&sA[buf][(c >> 2) * kBKP + k8 * 8]) = ra[i];
         }
 #pragma unroll
         for (int i = 0; i < PB; ++i) {
             const int c = tid + i * kThreads;
             if (c >= CB) continue;
-            if constexpr (MODE == kWgrad) {
-                const int n8 = c % BN8, kk = c / BN8;
-                const u32x4 w4 = rb[i];
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    sB[buf][(n8 * 8 + j) * kBKP + kk] = (uint16_t)(w4[j >> 1] >> ((j & 1) * 16));
-            } else {
-                *reinterpret_cast<u32x4*>(&sB[buf][(c >> 2) * kBKP + k8 * 8]) = rb[i];
-            }
+            *reinterpret_cast<u32x4*>(&sB[buf][(c >> 2) * kBKP + k8 * 8]) = rb[i];
         }
     };
 
