@@ -397,9 +397,9 @@ __device__ __forceinline__ void axial_from_ring(const float2* ring, const float*
 // One scanline of the ray pass, executed by one wave (lane = depth row).
 // MS: the volume may have several noise scales; LAB: label volume whose
 // boundaries take (r, t) from the label-pair table (no CT, no FP64 impedance
-// path) and no debug planes.  Separate instantiations, so the common code
-// keeps its registers.
-template <bool MS, bool LAB>
+// path); DBG: debug planes are written.  Separate instantiations, so the
+// common code keeps its registers.
+template <bool MS, bool LAB, bool DBG>
 __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v, const TissueDev* tab,
                              const float2* pair_rt, const float* kax, float2* ring, int x, int lane)
 {
@@ -534,7 +534,7 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
             fE[yp] = E_prev;
         }
         E_prev = E;
-        if (!LAB && act) {
+        if (DBG && act) {
             const int64_t kk = e.out_off + (int64_t)y * e.W + x;
             if (a.dbg.label) a.dbg.label[kk] = (uint8_t)lab;
             if (a.dbg.voxel) a.dbg.voxel[kk] = vox;
@@ -582,8 +582,9 @@ __device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
 // Ray kernel: items (env, group of kWaves * spw scanlines), longest first.
 // Five waves per SIMD (at most 102 registers, a few spilled) hide more of the
 // gather latency than four; six spill too much.
-template <bool MS, bool LAB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB && !MS ? 6 : 5))) void k_ray(PhysArgs a, QueueDev* q)
+template <bool MS, bool LAB, bool DBG>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB && !DBG && !MS ? 6 : 5))) void k_ray(
+    PhysArgs a, QueueDev* q)
 {
     __shared__ TissueDev s_tab[SG_MAX_LABELS_DEV];
     __shared__ float2 s_pair[kPairLabels * kPairLabels];
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB &&
         for (int s = 0; s < a.scanlines_per_wave; ++s) {
             const int x = it.x0 + s * kWaves + wave;
             if (x < e.W)
-                ray_scanline<MS, LAB>(a, e, v, s_tab, a.pair_rt ? s_pair : nullptr, s_kax, s_ring[wave], x, lane);
+                ray_scanline<MS, LAB, DBG>(a, e, v, s_tab, a.pair_rt ? s_pair : nullptr, s_kax, s_ring[wave], x, lane);
         }
     }
 }
@@ -1073,12 +1074,19 @@ size_t psf_lds_bytes(int tx, int max_rlat)
 
 bool psf_tile_supported(int tx) { return psf_fn(tx) != nullptr; }
 
-int ray_grid(int n_cu, bool multiscale, bool label_only)
+// the instantiation of the ray kernel for a launch
+template <bool MS>
+const void* ray_fn(bool label_only, bool debug)
 {
-    const void* fn = multiscale ? (label_only ? reinterpret_cast<const void*>(&k_ray<true, true>)
-                                              : reinterpret_cast<const void*>(&k_ray<true, false>))
-                                : (label_only ? reinterpret_cast<const void*>(&k_ray<false, true>)
-                                              : reinterpret_cast<const void*>(&k_ray<false, false>));
+    if (label_only) return debug ? reinterpret_cast<const void*>(&k_ray<MS, true, true>)
+                                 : reinterpret_cast<const void*>(&k_ray<MS, true, false>);
+    return debug ? reinterpret_cast<const void*>(&k_ray<MS, false, true>)
+                 : reinterpret_cast<const void*>(&k_ray<MS, false, false>);
+}
+
+int ray_grid(int n_cu, bool multiscale, bool label_only, bool debug)
+{
+    const void* fn = multiscale ? ray_fn<true>(label_only, debug) : ray_fn<false>(label_only, debug);
     return blocks_per_cu(fn, kThreads, 0) * n_cu;
 }
 
@@ -1092,15 +1100,10 @@ hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s)
     if (a.n_ray <= 0) return hipSuccess;
     if (grid > a.n_ray) grid = a.n_ray;
     if (grid < 1) return hipErrorInvalidConfiguration;
-    const bool lab = ray_label_only(a);
-    if (a.multiscale && lab)
-        hipLaunchKernelGGL((k_ray<true, true>), dim3(grid), dim3(kThreads), 0, s, a, q);
-    else if (a.multiscale)
-        hipLaunchKernelGGL((k_ray<true, false>), dim3(grid), dim3(kThreads), 0, s, a, q);
-    else if (lab)
-        hipLaunchKernelGGL((k_ray<false, true>), dim3(grid), dim3(kThreads), 0, s, a, q);
-    else
-        hipLaunchKernelGGL((k_ray<false, false>), dim3(grid), dim3(kThreads), 0, s, a, q);
+    const void* fn = a.multiscale ? ray_fn<true>(ray_label_only(a), ray_debug(a)) : ray_fn<false>(ray_label_only(a), ray_debug(a));
+    void* args[] = {const_cast<PhysArgs*>(&a), &q};
+    const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, 0, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

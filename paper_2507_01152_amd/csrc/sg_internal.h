@@ -194,15 +194,16 @@ hipError_t launch_ct_reference(const uint32_t* hist, int32_t n_envs, long long* 
                                hipStream_t s);
 size_t psf_lds_bytes(int tile_x, int max_rlat);
 bool psf_tile_supported(int tile_x);
-// the ray kernel's label-only instantiation (boundary (r, t) from the label-pair
-// table, no CT volume, no debug planes of the ray pass) serves a launch
-// without FP64 impedance work or debug output
-inline bool ray_label_only(const PhysArgs& a)
+// instantiations of the ray kernel: label-only (boundary (r, t) from the
+// label-pair table, no CT volume, so no FP64 impedance work) and debug (the
+// ray pass writes debug planes); each drops the code and registers the other
+// cases need
+inline bool ray_label_only(const PhysArgs& a) { return a.pair_rt != nullptr && a.any_ct == 0; }
+inline bool ray_debug(const PhysArgs& a)
 {
-    return a.pair_rt != nullptr && a.any_ct == 0 && !a.dbg.label && !a.dbg.voxel && !a.dbg.philox && !a.dbg.energy &&
-           !a.dbg.scatter;
+    return a.dbg.label || a.dbg.voxel || a.dbg.philox || a.dbg.energy || a.dbg.scatter;
 }
-int ray_grid(int n_cu, bool multiscale, bool label_only);             // resident ray workgroups
+int ray_grid(int n_cu, bool multiscale, bool label_only, bool debug);   // resident ray workgroups
 int psf_grid(int tile_x, int max_rlat, int n_cu);    // resident PSF workgroups
 
 }  // namespace sg

@@ -563,7 +563,7 @@ sg_status launch_physics(sg_ctx* c, const PhysArgs& a, const StageInfo& info)
     QueueDev* q = (QueueDev*)c->queue.p;
     hipError_t e;
     if ((e = launch_queue_reset(q, 1, c->stream)) != hipSuccess) return hip_fail(e, "queue reset");
-    if ((e = launch_ray(a, q, ray_grid(c->n_cu, a.multiscale != 0, ray_label_only(a)), c->stream)) != hipSuccess)
+    if ((e = launch_ray(a, q, ray_grid(c->n_cu, a.multiscale != 0, ray_label_only(a), ray_debug(a)), c->stream)) != hipSuccess)
         return hip_fail(e, "ray kernel launch");
     if ((e = launch_psf(a, info.tile_x, psf_grid(info.tile_x, a.max_rlat, c->n_cu), c->stream)) != hipSuccess)
         return hip_fail(e, "PSF kernel launch");

@@ -84,7 +84,7 @@ sg_status apply_shape(sg_ctx* c, Plan* p, const LaunchShape& s)
         tiles.insert(tiles.end(), t.begin(), t.end());
     }
     // occupancy only: a persistent grid's surplus blocks find the work counter spent and exit
-    int gr = ray_grid(c->n_cu, p->multiscale != 0, c->n_labels <= kPairLabels && !p->any_ct),
+    int gr = ray_grid(c->n_cu, p->multiscale != 0, c->n_labels <= kPairLabels && !p->any_ct, false),
         gp = psf_grid(s.tx, p->max_rlat, c->n_cu);
     if (gr < 1 || gp < 1) return fail(SG_EINVAL, "launch shape (tile %d) does not fit a compute unit", s.tx);
     p->grid_psf_last = gp;
