@@ -278,3 +278,19 @@ def test_fast_and_general_ray_paths_agree_bit_for_bit(sess, scales):
     torch.cuda.synchronize()
     assert torch.equal(fast, general)
     assert (fast > 0).any()
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (5, 1, 3), (9, 5, 2)])
+def test_volumes_smaller_than_a_brick(sess, dims):
+    """Label volumes smaller than (or straddling) one 8 x 4 x 4-voxel brick:
+    the padding of the bricked copy must never be read as a voxel.  Labels,
+    voxel indices and the frame against the oracle, with the plane crossing
+    the whole volume and leaving it."""
+    nx, ny, nz = dims
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    vol = Volume(labels=rng.integers(1, 4, size=(nz, ny, nx), dtype=np.uint8), seed=9)
+    # scanlines along x, beam along z, through the middle of y; 0.3 mm pixels reach past every side
+    pose = axis_pose((-0.9, (ny - 1) / 2.0, -0.8))
+    wl = single_env(vol, Probe(W=int(nx / 0.3) + 8, H=int(nz / 0.3) + 8, dx=0.3, dy=0.3), pose)
+    g = check_all(sess, wl, name=f"tiny {dims}")
+    assert (g[0]["voxel"] >= 0).sum() >= nx * nz and (g[0]["voxel"] == -1).any()
