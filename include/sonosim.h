@@ -195,10 +195,10 @@ sg_status sg_simulate(sg_ctx* ctx, int32_t n_envs, const int32_t* vol_ids,
 /* ------------------------------------------------------------------------
  * Batched persistent path (environments stepped in batch mode, Sec. 4):
  * a plan fixes the environments' volumes, probes and output offsets; each
- * step replays one captured HIP graph: device-side plane geometry, then a
- * persistent ray kernel pulling (environment, scanline group) items
- * longest-first from a device queue, then a persistent PSF kernel pulling
- * (environment, tile) items.  Poses
+ * step replays one captured HIP graph: a persistent ray kernel pulling
+ * (environment, scanline group) items longest-first from a device queue,
+ * each item computing its plane from the device pose, then a persistent PSF
+ * kernel striding over (environment, tile) items.  Poses
  * live in a library-owned device buffer that the caller updates between
  * steps (for instance from its own kernels on the same stream).
  */

@@ -579,9 +579,42 @@ __device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
     return *s_item;
 }
 
+// Plane of a batched step's env from its current pose: lane c < 3 computes
+// volume axis c with the host's arithmetic and the wave combines the three
+// (the pose is rejected unless all are in range).  With store, the env's plane
+// and flag are written back for the step's later consumers.
+__device__ __forceinline__ void item_geometry(const PhysArgs& a, EnvDev& e, int env, bool store, int lane)
+{
+    const int c = lane < 3 ? lane : 0;
+    // per-lane voxel size read from the descriptor in global memory (a pick
+    // from the wave's private copy would be indexed scratch)
+    const VolDev* vg = a.vols + e.vol;
+    const double s = c == 0 ? vg->sx : (c == 1 ? vg->sy : vg->sz);
+    int32_t p0 = 0, ddx = 0, ddy = 0;
+    const int ok_c = plane_axis(a.poses + 12 * e.pose_env, c, s, e.W, e.H, e.dx64, e.dy64, e.elev64, p0, ddx, ddy);
+    const bool ok = (__ballot(ok_c != 0) & 7ull) == 7ull;
+    if (!ok) p0 = ddx = ddy = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e.P0[k] = __builtin_amdgcn_readlane(p0, k);
+        e.DX[k] = __builtin_amdgcn_readlane(ddx, k);
+        e.DY[k] = __builtin_amdgcn_readlane(ddy, k);
+    }
+    e.valid = ok ? 1 : 0;
+    if (store && lane < 3) {
+        EnvDev& d = a.geo_out[env];
+        d.P0[lane] = p0;
+        d.DX[lane] = ddx;
+        d.DY[lane] = ddy;
+        if (lane == 0) d.valid = e.valid;   // sg_batch_status counts the rejected poses from these flags
+    }
+}
+
 // Ray kernel: items (env, group of kWaves * spw scanlines), longest first.
 // Five waves per SIMD (at most 102 registers, a few spilled) hide more of the
-// gather latency than four; six spill too much.
+// gather latency than four; the label-pair instantiation without debug planes
+// or noise scales fits six (80 registers), the others spill too much at six.
+// With a.poses (batched steps) every item computes its env's plane itself.
 template <bool MS, bool LAB, bool DBG>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB && !DBG && !MS ? 6 : 5))) void k_ray(
     PhysArgs a, QueueDev* q)
@@ -600,8 +633,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB &&
         const int item = next_item(&q->next_ray, &s_item);
         if (item >= a.n_ray) break;
         const ItemRay it = a.ray_items[item];
-        const EnvDev e = a.envs[it.env];
+        EnvDev e = a.envs[it.env];
         const VolDev v = a.vols[e.vol];
+        if (a.poses) item_geometry(a, e, it.env, it.x0 == 0 && wave == 0, lane);
         for (int i = threadIdx.x; i < kTaps + 7; i += kThreads) s_kax[i] = i <= 2 * e.rax ? a.coefs[e.kax + i] : 0.f;
         __syncthreads();
         for (int s = 0; s < a.scanlines_per_wave; ++s) {
@@ -638,6 +672,7 @@ __global__ __launch_bounds__(TX / kSx * kWave) void k_psf(PhysArgs a)
     // tile needs two barriers (staged -> filter, output written -> stores): the
     // next tile's staging and taps follow the second one, which every wave
     // passes only after filtering.
+    if (a.ray_queue && blockIdx.x == 0 && tid == 0) a.ray_queue->next_ray = 0;   // for the next step's ray kernel
     const int r_max = a.max_rlat < kRB ? kRB : a.max_rlat;
     float* sY = lds + kAS * (2 * (TX + 2 * r_max) + TX);   // [kTileRows][TX + 1]
     for (int item = blockIdx.x; item < a.n_psf; item += gridDim.x) {
@@ -994,26 +1029,6 @@ __global__ __launch_bounds__(kThreads) void k_encode_ct(PhysArgs a, const uint16
     }
 }
 
-// Device geometry of a batched step; its first threads also reset the step's
-// work counters (only the ray kernel, launched after this one, reads them).
-__global__ void k_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int n, QueueDev* q, int n_queues)
-{
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n_queues) q[e].next_ray = 0;
-    if (e >= n) return;
-    EnvDev& d = envs[e];
-    const VolDev v = vols[d.vol];
-    int32_t P0[3], DX[3], DY[3];
-    const int ok = plane_geometry(poses + 12 * d.pose_env, v.sx, v.sy, v.sz, d.W, d.H, d.dx64, d.dy64, d.elev64, P0,
-                                  DX, DY);
-    for (int c = 0; c < 3; ++c) {
-        d.P0[c] = ok ? P0[c] : 0;
-        d.DX[c] = ok ? DX[c] : 0;
-        d.DY[c] = ok ? DY[c] : 0;
-    }
-    d.valid = ok;   // sg_batch_status counts the rejected poses from these flags
-}
-
 __global__ void k_queue_reset(QueueDev* q, int n)
 {
     if ((int)threadIdx.x < n) q[threadIdx.x].next_ray = 0;
@@ -1156,14 +1171,6 @@ hipError_t launch_encode(const PhysArgs& a, int32_t n_envs, int32_t max_pixels, 
         hipLaunchKernelGGL(k_encode<true>, dim3(bx, n_envs), dim3(kThreads), 0, s, a, enc);
     else
         hipLaunchKernelGGL(k_encode<false>, dim3(bx, n_envs), dim3(kThreads), 0, s, a, enc);
-    return hipGetLastError();
-}
-
-hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n, QueueDev* q,
-                           int32_t n_queues, hipStream_t s)
-{
-    if (n <= 0 || n_queues < 1 || n_queues > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_geometry, dim3((n + 127) / 128), dim3(128), 0, s, envs, vols, poses, n, q, n_queues);
     return hipGetLastError();
 }
 

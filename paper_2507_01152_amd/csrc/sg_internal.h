@@ -43,8 +43,8 @@ struct TissueDev {
 };
 
 // Per-environment launch parameters.  The geometry part (P0, DX, DY, valid)
-// is filled either on the host (single call) or by the device geometry
-// kernel (batched plans).
+// is filled either on the host (single call) or by the ray kernel from the
+// current pose (batched plans).
 struct EnvDev {
     int32_t P0[3], DX[3], DY[3];   // Q16 plane origin and per-pixel steps
     int32_t valid;                 // 0: pose rejected, frame is zero
@@ -84,6 +84,12 @@ struct DebugDev {
 // label volumes with at most this many labels take r and t from a pair table
 constexpr int kPairLabels = 16;
 
+// work-queue state of the two persistent kernels (device)
+struct QueueDev {
+    int32_t next_ray;    // next ray work item
+    int32_t pad[3];
+};
+
 struct PhysArgs {
     const EnvDev* envs;
     const VolDev* vols;
@@ -105,68 +111,74 @@ struct PhysArgs {
     DebugDev dbg;
     int32_t scanlines_per_wave;   // ray group = kRayWaves * scanlines_per_wave
     int32_t max_rlat;             // sizing of the PSF tile's LDS
-};
-
-// work-queue state of the two persistent kernels (device)
-struct QueueDev {
-    int32_t next_ray;    // next ray work item
-    int32_t pad[3];
+    // batched steps: the ray kernel computes each item's plane from poses
+    // (12 doubles per caller env) and the group of an env's first scanlines
+    // stores it in geo_out (the envs array) for later consumers; null when the
+    // host staged the geometry in envs
+    const double* poses;
+    EnvDev* geo_out;
+    // the PSF kernel clears this ray-queue counter for the next step (the ray
+    // kernel that consumed it has finished); null: the caller resets it
+    QueueDev* ray_queue;
 };
 
 // Plane geometry: the pose [R|t] (probe mm -> volume mm) places pixel (x, y)
 // at probe point (a + x*dx, 0, y*dy), a = -0.5*(W-1)*dx.  Origin and steps
 // are converted to Q16 voxel units one rounded operation at a time
 // (no contraction) and rounded half-to-even, so host and device agree
-// bit for bit.  Returns 1 if every corner of the plane lies within
-// +-2^30 (Q16), else 0 (outputs then unspecified).
+// bit for bit.  plane_axis computes volume axis c (voxel size s); it returns
+// 1 if the axis is finite and every corner of the plane lies within +-2^30
+// (Q16) on it, else 0 (outputs then unspecified).
+__host__ __device__ inline int plane_axis(const double* pose, int c, double s, int32_t W, int32_t H, double dx,
+                                          double dy, double elev, int32_t& P0, int32_t& DX, int32_t& DY)
+{
+#pragma clang fp contract(off)
+    double a = -0.5 * (double)(W - 1);
+    a = a * dx;
+    const double r0 = pose[4 * c + 0], r1 = pose[4 * c + 1], r2 = pose[4 * c + 2], tc = pose[4 * c + 3];
+    double u = r0 * a;
+    u = tc + u;
+    const double v = r1 * elev;   // elevation offset (exactly 0 for a single plane)
+    u = u + v;
+    u = u / s;
+    u = u * 65536.0;
+    double w = r0 * dx;
+    w = w / s;
+    w = w * 65536.0;
+    double z = r2 * dy;
+    z = z / s;
+    z = z * 65536.0;
+    // non-finite or huge values fail here
+    if (!(u > -1e15 && u < 1e15) || !(w > -1e15 && w < 1e15) || !(z > -1e15 && z < 1e15)) return 0;
+    const long long p0 = (long long)__builtin_rint(u);
+    const long long ddx = (long long)__builtin_rint(w);
+    const long long ddy = (long long)__builtin_rint(z);
+    const long long lim = 1ll << 30;
+    for (int k = 0; k < 4; ++k) {
+        const long long qx = (k & 1) ? (long long)(W - 1) : 0;
+        const long long qy = (k & 2) ? (long long)(H - 1) : 0;
+        const long long q = p0 + qx * ddx + qy * ddy;
+        if (q > lim || q < -lim) return 0;
+    }
+    P0 = (int32_t)p0;
+    DX = (int32_t)ddx;
+    DY = (int32_t)ddy;
+    return 1;
+}
+
+// all three axes; 1 if the pose places the whole plane in range, else 0
 __host__ __device__ inline int plane_geometry(const double* pose, double sx, double sy, double sz,
                                               int32_t W, int32_t H, double dx, double dy, double elev,
                                               int32_t P0[3], int32_t DX[3], int32_t DY[3])
 {
-#pragma clang fp contract(off)
     const double s[3] = {sx, sy, sz};
-    double a = -0.5 * (double)(W - 1);
-    a = a * dx;
-    long long p0[3], ddx[3], ddy[3];
-    for (int c = 0; c < 3; ++c) {
-        const double r0 = pose[4 * c + 0], r1 = pose[4 * c + 1], r2 = pose[4 * c + 2], tc = pose[4 * c + 3];
-        double u = r0 * a;
-        u = tc + u;
-        const double v = r1 * elev;   // elevation offset (exactly 0 for a single plane)
-        u = u + v;
-        u = u / s[c];
-        u = u * 65536.0;
-        double w = r0 * dx;
-        w = w / s[c];
-        w = w * 65536.0;
-        double z = r2 * dy;
-        z = z / s[c];
-        z = z * 65536.0;
-        // non-finite or huge values fail the range test below
-        if (!(u > -1e15 && u < 1e15) || !(w > -1e15 && w < 1e15) || !(z > -1e15 && z < 1e15)) return 0;
-        p0[c] = (long long)__builtin_rint(u);
-        ddx[c] = (long long)__builtin_rint(w);
-        ddy[c] = (long long)__builtin_rint(z);
-    }
-    const long long lim = 1ll << 30;
-    for (int c = 0; c < 3; ++c) {
-        for (int k = 0; k < 4; ++k) {
-            const long long qx = (k & 1) ? (long long)(W - 1) : 0;
-            const long long qy = (k & 2) ? (long long)(H - 1) : 0;
-            const long long q = p0[c] + qx * ddx[c] + qy * ddy[c];
-            if (q > lim || q < -lim) return 0;
-        }
-        P0[c] = (int32_t)p0[c];
-        DX[c] = (int32_t)ddx[c];
-        DY[c] = (int32_t)ddy[c];
-    }
+    for (int c = 0; c < 3; ++c)
+        if (!plane_axis(pose, c, s[c], W, H, dx, dy, elev, P0[c], DX[c], DY[c])) return 0;
     return 1;
 }
 
 // launchers (physics.hip)
 hipError_t launch_queue_reset(QueueDev* q, int n_queues, hipStream_t s);   // resets q[0 .. n_queues)
-hipError_t launch_geometry(EnvDev* envs, const VolDev* vols, const double* poses, int32_t n_envs, QueueDev* q,
-                           int32_t n_queues, hipStream_t s);   // also resets the work counters q[0 .. n_queues)
 hipError_t launch_ray(const PhysArgs& a, QueueDev* q, int grid, hipStream_t s);
 hipError_t launch_psf(const PhysArgs& a, int tile_x, int grid, hipStream_t s);
 hipError_t launch_max_label(const uint8_t* labels, int64_t n, int32_t* d_out, hipStream_t s);

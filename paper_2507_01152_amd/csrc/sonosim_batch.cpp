@@ -138,21 +138,26 @@ PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
     a.max_rlat = p->max_rlat;
     a.multiscale = p->multiscale;
     a.any_ct = p->any_ct;
+    a.poses = (const double*)p->d_poses.p;   // the ray kernel computes the planes of the current poses
+    a.geo_out = (EnvDev*)p->d_envs.p;
+    a.ray_queue = (QueueDev*)p->d_queue.p;
     return a;
 }
 
-// enqueue one step's kernels (queue reset, device geometry, persistent ray
-// kernel, persistent PSF kernel) on stream s; optional events: before the
-// first ray kernel, after the last ray kernel, at the end of the step.  With
-// chunks, chunk k's PSF kernel waits for its ray kernel on the plan's second
-// stream, which the step joins at the end (the same code is captured).
+// enqueue one step's kernels (persistent ray kernel, which also computes the
+// planes of the current poses, then persistent PSF kernel, which clears the
+// ray kernel's work counter for the next step) on stream s; optional events:
+// before the first ray kernel, after the last ray kernel, at the end of the
+// step.  With chunks, chunk k's PSF kernel waits for its ray kernel on the
+// plan's second stream, which the step joins at the end (the same code is
+// captured).  Every chunk holds at least one env, so each ray kernel is
+// followed by a PSF kernel that clears its counter.
 hipError_t enqueue_step(sg_ctx* c, Plan* p, float* out, hipStream_t s, hipEvent_t* ev = nullptr)
 {
     QueueDev* q = (QueueDev*)p->d_queue.p;
     const int K = p->shape.chunks;
-    hipError_t e = launch_geometry((EnvDev*)p->d_envs.p, (const VolDev*)c->d_vols.p, (const double*)p->d_poses.p,
-                                   p->n_envs, q, K, s);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[0], s);
+    hipError_t e = hipSuccess;
+    if (ev) e = hipEventRecord(ev[0], s);
     if (K == 1) {
         const PhysArgs a = plan_args(c, p, out);
         if (e == hipSuccess) e = launch_ray(a, q, p->grid_ray, s);
@@ -167,6 +172,7 @@ hipError_t enqueue_step(sg_ctx* c, Plan* p, float* out, hipStream_t s, hipEvent_
         a.n_ray = p->ray_cnt[k];
         a.psf_items += p->tile_off[k];
         a.n_psf = p->tile_cnt[k];
+        a.ray_queue = q + k;
         e = launch_ray(a, q + k, p->grid_ray, s);
         if (e == hipSuccess) e = hipEventRecord(p->ev_ray[k], s);
         if (e == hipSuccess) e = hipStreamWaitEvent(p->aux, p->ev_ray[k], 0);
@@ -302,6 +308,7 @@ extern "C" sg_status sg_batch_plan_create(sg_ctx* c, int32_t n, const int32_t* v
     if (e == hipSuccess)
         e = hipMemcpy(p->d_pool.p, p->pool.data(), sizeof(float) * p->pool.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->d_poses.p, 0, sizeof(double) * 12 * n);
+    if (e == hipSuccess) e = hipMemset(p->d_queue.p, 0, sizeof(QueueDev) * kMaxChunks);   // steps leave them at 0
     if (e != hipSuccess) return hip_fail(e, "plan upload");
     s = apply_shape(c, p.get(), kShapes[0]);
     if (s != SG_OK) return s;
@@ -354,7 +361,11 @@ extern "C" sg_status sg_batch_step_profiled(sg_ctx* c, int32_t id, float* out, f
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hipError_t e = hipSuccess;
     for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
-    if (e == hipSuccess) e = enqueue_step(c, p, out, c->stream, ev);
+    if (e == hipSuccess) {
+        e = enqueue_step(c, p, out, c->stream, ev);
+        // a step cut short may leave a ray counter that no PSF kernel cleared
+        if (e != hipSuccess) (void)launch_queue_reset((QueueDev*)p->d_queue.p, kMaxChunks, c->stream);
+    }
     if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
     if (e == hipSuccess) e = hipEventElapsedTime(ms_ray, ev[0], ev[1]);
     if (e == hipSuccess) e = hipEventElapsedTime(ms_psf, ev[1], ev[2]);
@@ -383,7 +394,7 @@ extern "C" sg_status sg_batch_status(sg_ctx* c, int32_t id, int32_t* n_bad)
     Plan* p = c ? find_plan(c, id) : nullptr;
     if (!p || !n_bad) return fail(SG_EINVAL, "sg_batch_status: bad plan id or NULL");
     (void)hipSetDevice(c->device);
-    // the device geometry flags every plane of a rejected pose; count caller envs (plane 0)
+    // the step's ray kernel flags every plane of a rejected pose; count caller envs (plane 0)
     std::vector<EnvDev> envs(p->n_envs);
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipMemcpy(envs.data(), p->d_envs.p, sizeof(EnvDev) * envs.size(), hipMemcpyDeviceToHost);
