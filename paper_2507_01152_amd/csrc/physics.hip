@@ -585,7 +585,10 @@ __device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
 // and flag are written back for the step's later consumers.
 __device__ __forceinline__ void item_geometry(const PhysArgs& a, EnvDev& e, int env, bool store, int lane)
 {
-    const int c = lane < 3 ? lane : 0;
+    int c = lane < 3 ? lane : 0;
+    // opaque per item: the lane addresses below are recomputed here instead of
+    // hoisted out of the item loop and held (spilled) across the scanlines
+    asm volatile("" : "+v"(c));
     // per-lane voxel size read from the descriptor in global memory (a pick
     // from the wave's private copy would be indexed scratch)
     const VolDev* vg = a.vols + e.vol;

@@ -1,5 +1,5 @@
-"""Batched persistent path (device geometry, work queue, HIP graph replay,
-autotuner) vs the single-call path and the FP64 oracle (GPU)."""
+"""Batched persistent path (planes from device poses, work queue, HIP graph
+replay, autotuner) vs the single-call path and the FP64 oracle (GPU)."""
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -215,6 +215,48 @@ def test_out_of_range_pose_gives_zero_frame_and_status(sess):
     ref, _, _ = sess.simulate(synth.Workload(wl.volumes[:1], np.zeros(1, np.int32), wl.probes[:1],
                                              wl.poses[:1], wl.table), vids[:1])
     assert torch.equal(ref, out[:n])
+
+
+@pytest.mark.parametrize("chunks", [1, 3])
+def test_poses_changed_between_graph_replays(sess, chunks):
+    """Every replay of one captured plan takes its planes from the poses then
+    in the device buffer, and leaves its work counters ready for the next:
+    poses A, then B (another set, one env out of range), then A again, each
+    step bit-identical to the single-call path on the same poses."""
+    from paper_2507_01152_amd import sonosim as sg
+    wl = synth.ellipsoid_workload(seed=11, n_envs=6)
+    wl_b = synth.ellipsoid_workload(seed=12, n_envs=6)
+    vids = sess.load(wl)
+    offs, total = wl.out_offsets()
+    plan = sg.sg_batch_plan_create(sess.ctx, vids, wl.probes, offs)
+    sg.sg_batch_set_config(sess.ctx, plan, 8, 32, chunks)
+    poses_b = wl_b.poses.copy()
+    poses_b[4, 3] = 1e12
+    out = torch.full((total,), -7.0, dtype=torch.float32, device=sess.device)
+
+    n4 = wl.probes[4].W * wl.probes[4].H
+    lo, hi = int(offs[4]), int(offs[4]) + n4
+
+    def single(poses):
+        # the single call rejects an out-of-range pose outright: env 4 takes
+        # an in-range one there and is compared separately
+        p = poses.copy()
+        p[4] = wl.poses[4]
+        ref, _, _ = sess.simulate(synth.Workload(wl.volumes, wl.vol_ids, wl.probes, p, wl.table), vids)
+        return ref
+
+    for poses, n_bad in ((wl.poses, 0), (poses_b, 1), (wl.poses, 0)):
+        sg.sg_batch_set_poses(sess.ctx, plan, poses)
+        sg.sg_batch_step(sess.ctx, plan, out)
+        assert sg.sg_batch_status(sess.ctx, plan) == n_bad
+        ref = single(poses)
+        torch.cuda.synchronize()
+        assert torch.equal(out[:lo], ref[:lo]) and torch.equal(out[hi:], ref[hi:])
+        if n_bad:
+            assert (out[lo:hi] == 0).all()
+        else:
+            assert torch.equal(out[lo:hi], ref[lo:hi]) and out[lo:hi].max() > 0
+    sg.sg_batch_plan_destroy(sess.ctx, plan)
 
 
 def _plan_at_timed_shape(sess, wl, vids):
