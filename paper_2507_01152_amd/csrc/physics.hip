@@ -627,6 +627,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB &&
     __shared__ __attribute__((aligned(16))) float s_kax[kTaps + 7];   // zeros past 2 rax (read ahead by a group)
     __shared__ float2 s_ring[kWaves][kRingAlloc];
     __shared__ int s_item;
+    __shared__ int32_t s_geo[10];   // an item's plane (P0, DX, DY, valid), computed by wave 0
     for (int i = threadIdx.x; i < a.n_labels; i += kThreads) s_tab[i] = a.table[i];
     if (a.pair_rt)
         for (int i = threadIdx.x; i < a.n_labels * a.n_labels; i += kThreads) s_pair[i] = a.pair_rt[i];
@@ -638,9 +639,31 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB &&
         const ItemRay it = a.ray_items[item];
         EnvDev e = a.envs[it.env];
         const VolDev v = a.vols[e.vol];
-        if (a.poses) item_geometry(a, e, it.env, it.x0 == 0 && wave == 0, lane);
+        // batched step: wave 0 computes the plane and hands it over through LDS
+        // (the other waves last read s_geo before next_item's barriers)
+        if (a.poses && wave == 0) {
+            item_geometry(a, e, it.env, it.x0 == 0, lane);
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    s_geo[k] = e.P0[k];
+                    s_geo[3 + k] = e.DX[k];
+                    s_geo[6 + k] = e.DY[k];
+                }
+                s_geo[9] = e.valid;
+            }
+        }
         for (int i = threadIdx.x; i < kTaps + 7; i += kThreads) s_kax[i] = i <= 2 * e.rax ? a.coefs[e.kax + i] : 0.f;
         __syncthreads();
+        if (a.poses && wave != 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                e.P0[k] = __builtin_amdgcn_readfirstlane(s_geo[k]);
+                e.DX[k] = __builtin_amdgcn_readfirstlane(s_geo[3 + k]);
+                e.DY[k] = __builtin_amdgcn_readfirstlane(s_geo[6 + k]);
+            }
+            e.valid = __builtin_amdgcn_readfirstlane(s_geo[9]);
+        }
         for (int s = 0; s < a.scanlines_per_wave; ++s) {
             const int x = it.x0 + s * kWaves + wave;
             if (x < e.W)
