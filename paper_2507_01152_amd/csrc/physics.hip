@@ -604,6 +604,9 @@ __device__ __forceinline__ void item_geometry(const PhysArgs& a, EnvDev& e, int 
         e.DY[k] = __builtin_amdgcn_readlane(ddy, k);
     }
     e.valid = ok ? 1 : 0;
+    // Other groups of the same env may load the record while it is written
+    // back here; they replace its plane fields before any use (a batched
+    // step never reads them from memory), so the overlap is benign.
     if (store && lane < 3) {
         EnvDev& d = a.geo_out[env];
         d.P0[lane] = p0;
