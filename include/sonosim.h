@@ -88,9 +88,11 @@ typedef struct {
                                   N0 and N1): scale s draws on cells of 2^s voxels
                                   per axis (Philox counter (cell, 0, s, 0)),
                                   N0 = sum_s N0_s / sqrt(S), and the density gate
-                                  tests sum_s Q[w2_s >> 20] <= fl32(sqrt(S) mu1)
-                                  in FP32, Q = the quantised normal of
-                                  sg_noise_quantiles. */
+                                  N1 = sum_s N1_s / sqrt(S) <= mu1 with N1_s =
+                                  Q[w2_s >> 20] 2^-20 is the exact integer test
+                                  sum_s Q[w2_s >> 20] <= floor(sqrt(S) mu1 2^20)
+                                  (threshold rounded in FP64 on the host),
+                                  Q = the table of sg_noise_quantiles. */
 } sg_volume_desc;
 
 /* Register a volume; *vol_id receives its id.  Scans the label map once on
@@ -108,9 +110,10 @@ sg_status sg_volume_register(sg_ctx* ctx, const sg_volume_desc* desc, int32_t* v
 sg_status sg_volume_release(sg_ctx* ctx, int32_t vol_id);
 
 /* The quantised standard normal of the multi-scale density gate (host, no
- * context): out[k] = fl32(Phi^-1((k + 1/2) / 4096)) for k < 4096, with
- * Phi^-1 solved to FP64 precision from erfc.  out: host, 4096 floats. */
-sg_status sg_noise_quantiles(float* out);
+ * context), in units of 2^-20: out[k] = rint(Phi^-1((k + 1/2) / 4096) 2^20)
+ * for k < 4096 (half to even), with Phi^-1 solved to FP64 precision from
+ * erfc.  out: host, 4096 int32.  Errors: SG_EINVAL (NULL). */
+sg_status sg_noise_quantiles(int32_t* out);
 
 /* ------------------------------------------------------------------------
  * Tissue table (App. B.2: per-tissue impedance Z, attenuation alpha and the
@@ -373,7 +376,7 @@ sg_status sg_surr_destroy(sg_ctx* ctx, int32_t surr_id);
  *      the frame, compared exactly in 64-bit integers), as (r - 1024) / 1000;
  *   1  N0 of the voxel's noise draw (not gated), 0 outside;
  *   2  N1 of the draw as the quantised normal of sg_noise_quantiles
- *      (entry w2 >> 20), 0 outside;
+ *      (entry w2 >> 20, times 2^-20), 0 outside;
  *   3  depth (y + 0.5) / H;  4..7 zero.
  * Every volume it reads must carry a CT (SG_EINVAL otherwise), and the
  * reference must be set (SG_ESTATE otherwise).

@@ -83,8 +83,10 @@ def lib():
         L.or_simulate_env.argtypes = [C.POINTER(_Volume), C.c_void_p, C.c_int32, C.POINTER(_Probe),
                                       C.c_void_p, C.POINTER(_Planes)]
         L.or_simulate_env.restype = C.c_int
+        L.or_multiscale_threshold.argtypes = [C.c_int32, C.c_float]
+        L.or_multiscale_threshold.restype = C.c_int64
         L.or_scatter_voxel.argtypes = [C.POINTER(_Volume), C.c_float, C.c_int64, C.c_int64, C.c_int64,
-                                       C.POINTER(C.c_double), C.POINTER(C.c_float), C.c_void_p]
+                                       C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_void_p]
         L.or_scatter_voxel.restype = C.c_int
         L.or_scatter_grid.argtypes = [C.POINTER(_Volume), C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_recon_points.argtypes = [C.POINTER(_Volume), C.c_void_p, C.POINTER(_Probe), C.c_void_p, C.c_int32,
@@ -107,13 +109,21 @@ _Q_LUT = None
 
 
 def quantised_normal_table() -> np.ndarray:
-    """Q[k] = fl32(Phi^-1((k + 1/2) / 4096)), k < 4096: the quantised standard
-    normal of the multi-scale gate (scipy's ndtri in FP64, rounded once)."""
+    """Q[k] = rint(Phi^-1((k + 1/2) / 4096) * 2^20) (int32), k < 4096: the
+    quantised standard normal of the multi-scale gate in units of 2^-20
+    (scipy's ndtri in FP64, scaled exactly, rounded half to even once)."""
     global _Q_LUT
     if _Q_LUT is None:
         from scipy.special import ndtri
-        _Q_LUT = np.ascontiguousarray(ndtri((np.arange(4096) + 0.5) / 4096.0).astype(np.float32))
+        q = np.rint(ndtri((np.arange(4096) + 0.5) / 4096.0) * 1048576.0)
+        _Q_LUT = np.ascontiguousarray(q.astype(np.int32))
     return _Q_LUT
+
+
+def multiscale_threshold(scales: int, mu1: float) -> int:
+    """Integer threshold of the multi-scale gate: floor(sqrt(S) * mu1 * 2^20)
+    in FP64, clamped to the int32 range (mu1 is taken as an FP32 value)."""
+    return int(lib().or_multiscale_threshold(int(scales), float(mu1)))
 
 
 def _volume_struct(vol):
@@ -153,22 +163,24 @@ def _probe_struct(p, plane: int = 0):
 # ---------------------------------------------------------------------------
 
 def scatter_voxel(vol, mu1: float, ix: int, iy: int, iz: int):
-    """Scattering draw of one voxel: (N0 (FP64), N1 (FP32 sum of quantised
-    normals, 0 with one scale), gate (bool), scale-0 Philox words)."""
+    """Scattering draw of one voxel: (N0 (FP64), N1 (integer sum of the
+    quantised normals, units of 2^-20; 0 with one scale), gate (bool), scale-0
+    Philox words)."""
     vs, keep = _volume_struct(vol)
-    n0, n1 = C.c_double(), C.c_float()
+    n0, n1 = C.c_double(), C.c_int64()
     w = np.zeros(4, dtype=np.uint32)
     g = lib().or_scatter_voxel(C.byref(vs), float(mu1), int(ix), int(iy), int(iz), C.byref(n0), C.byref(n1),
                                w.ctypes.data)
-    return float(n0.value), float(n1.value), bool(g), w
+    return float(n0.value), int(n1.value), bool(g), w
 
 
 def scatter_grid(vol, mu1: float):
-    """(N0, N1, gate) of every voxel of vol, each [nz][ny][nx]."""
+    """(N0, N1, gate) of every voxel of vol, each [nz][ny][nx]; N1 is the
+    integer sum of the quantised normals (units of 2^-20)."""
     vs, keep = _volume_struct(vol)
     shape = np.asarray(vol.labels).shape
     n0 = np.zeros(shape, dtype=np.float64)
-    n1 = np.zeros(shape, dtype=np.float32)
+    n1 = np.zeros(shape, dtype=np.int64)
     g = np.zeros(shape, dtype=np.uint8)
     lib().or_scatter_grid(C.byref(vs), float(mu1), n0.ctypes.data, n1.ctypes.data, g.ctypes.data)
     return n0, n1, g.astype(bool)

@@ -38,10 +38,11 @@
  *      of 2^s voxels per axis (counter = (cell index, 0, s, 0); s = 0 is the
  *      voxel stream above) and
  *        N0 = (1/sqrt(S)) * sum_s BoxMuller(w0_s, w1_s)       (FP64),
- *        N1 = sum_s Q[w2_s >> 20] <= fl32(sqrt(S) * mu1)      (FP32 sum, s ascending),
- *      with Q[k] = fl32(Phi^-1((k + 1/2) / 4096)), a quantised standard
- *      normal: the gate is decided in FP32 from exactly representable steps,
- *      as the GPU decides it.
+ *        gate: N1 = (1/sqrt(S)) * sum_s N1_s <= mu1, with N1_s the quantised
+ *        standard normal Q[w2_s >> 20] * 2^-20, Q[k] = rint(Phi^-1((k + 1/2)
+ *        / 4096) * 2^20) (int32).  The sum of the Q is an exact integer, so
+ *        the gate is the integer test sum_s Q[w2_s >> 20] <= floor(sqrt(S) *
+ *        mu1 * 2^20), the threshold rounded once in FP64 in that order.
  *   O8 R' = G * E * cos(theta) * |r|.
  *   O9 separable Gaussian PSF with std c_psf * (image size) per axis, radius
  *      max(1, ceil(3 sigma)), normalised, zero padding (App. B.2).
@@ -69,7 +70,7 @@ typedef struct {
     const int16_t* ct;        /* [nz][ny][nx] or NULL */
     uint64_t seed;            /* noise-field key */
     int32_t scales;           /* noise scales S (<= 1: one) */
-    const float* q_lut;       /* [4096] quantised normal Q (used when S > 1) */
+    const int32_t* q_lut;     /* [4096] quantised normal Q in units of 2^-20 (used when S > 1) */
 } or_volume;
 
 typedef struct {
@@ -218,16 +219,31 @@ int32_t or_psf_kernel(double sigma, double* K, int32_t cap)
     return r;
 }
 
+/* O7 multi-scale gate threshold: floor(sqrt(S) * mu1 * 2^20), one FP64
+ * rounding per operation in that order, clamped to the int32 range (sums of
+ * at most four quantised normals stay far inside it; mu1 = -inf never
+ * passes, +inf always). */
+int64_t or_multiscale_threshold(int32_t S, float mu1)
+{
+    double x = sqrt((double)S);
+    x = x * (double)mu1;
+    x = x * 1048576.0;
+    x = floor(x);
+    if (!(x > -2147483648.0)) return -2147483648ll;
+    if (x > 2147483647.0) return 2147483647ll;
+    return (int64_t)x;
+}
+
 /* O7 for one voxel (ix, iy, iz) inside the grid: N0 and, with S > 1, the
- * FP32 sum N1 of the quantised normals and its threshold test; words of
- * scale 0 in w[4].  Returns the gate (1: scatter). */
-int or_scatter_voxel(const or_volume* v, float mu1, int64_t ix, int64_t iy, int64_t iz, double* n0, float* n1,
+ * integer sum N1 of the quantised normals (units of 2^-20) and its threshold
+ * test; words of scale 0 in w[4].  Returns the gate (1: scatter). */
+int or_scatter_voxel(const or_volume* v, float mu1, int64_t ix, int64_t iy, int64_t iz, double* n0, int64_t* n1,
                      uint32_t w[4])
 {
     const uint32_t key[2] = {(uint32_t)v->seed, (uint32_t)(v->seed >> 32)};
     const int S = v->scales > 1 ? v->scales : 1;
     double sum0 = 0.0;
-    float sum1 = 0.0f;
+    int64_t sum1 = 0;
     int gate = 0;
     for (int s = 0; s < S; ++s) {
         const int64_t mx = ((int64_t)v->nx + ((int64_t)1 << s) - 1) >> s;
@@ -240,23 +256,22 @@ int or_scatter_voxel(const or_volume* v, float mu1, int64_t ix, int64_t iy, int6
         double u0 = (2.0 * (double)(ws[0] >> 9) + 1.0) / 16777216.0;
         double u1 = (2.0 * (double)(ws[1] >> 9) + 1.0) / 16777216.0;
         sum0 += sqrt(-2.0 * log(u0)) * cos(2.0 * M_PI * u1);
-        if (S > 1) sum1 = sum1 + v->q_lut[ws[2] >> 20];
+        if (S > 1) sum1 += v->q_lut[ws[2] >> 20];
     }
     if (S == 1) {
         *n0 = sum0;
-        *n1 = 0.0f;
+        *n1 = 0;
         gate = (uint64_t)w[2] < or_gate_threshold(mu1);
     } else {
         *n0 = sum0 / sqrt((double)S);
         *n1 = sum1;
-        const float thr = (float)(sqrt((double)S) * (double)mu1);
-        gate = sum1 <= thr;
+        gate = sum1 <= or_multiscale_threshold(S, mu1);
     }
     return gate;
 }
 
 /* O7 over the whole grid: N0, N1 and the gate of every voxel, [nz][ny][nx]. */
-void or_scatter_grid(const or_volume* v, float mu1, double* n0, float* n1, uint8_t* gate)
+void or_scatter_grid(const or_volume* v, float mu1, double* n0, int64_t* n1, uint8_t* gate)
 {
     const int64_t n = (int64_t)v->nx * v->ny * v->nz;
 #pragma omp parallel for schedule(static)
@@ -421,7 +436,7 @@ int or_simulate_env(const or_volume* v, const or_tissue* table, int32_t n_labels
             const int64_t ix = vox[k] % v->nx, iy = (vox[k] / v->nx) % v->ny, iz = vox[k] / ((int64_t)v->nx * v->ny);
             const or_tissue* tt = &table[lab[k]];
             double n0;
-            float n1;
+            int64_t n1;
             if (or_scatter_voxel(v, tt->mu1, ix, iy, iz, &n0, &n1, &ph[4 * k]))
                 T[k] = n0 * (double)tt->sigma0 + (double)tt->mu0;
         }

@@ -276,7 +276,7 @@ def adam_update(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 #              cumulative counts; exact integers), value (r - 1024) / 1000
 #   channel 1  N0 of the voxel's noise draw (Box-Muller of its Philox words,
 #              not gated); 0 outside
-#   channel 2  N1 as the quantised normal Q[w2 >> 20]; 0 outside
+#   channel 2  N1 as the quantised normal Q[w2 >> 20] * 2^-20; 0 outside
 #   channel 3  depth (y + 0.5) / H
 # all bf16; channels 4..7 zero.
 
@@ -329,7 +329,7 @@ def ct_input(vol, probe, pose, ref_hist) -> np.ndarray:
     u1 = (2.0 * (w[..., 1] >> 9).astype(np.float64) + 1.0) / 16777216.0
     n0 = np.sqrt(-2.0 * np.log(u0)) * np.cos(2.0 * np.pi * u1)
     q = _or.quantised_normal_table()
-    n1 = q[(w[..., 2] >> 20).astype(np.int64)].astype(np.float64)
+    n1 = q[(w[..., 2] >> 20).astype(np.int64)].astype(np.float64) * 2.0 ** -20
     x[..., 1] = np.where(inside, bf16_round(n0), 0.0)
     x[..., 2] = np.where(inside, bf16_round(n1), 0.0)
     H = probe.H

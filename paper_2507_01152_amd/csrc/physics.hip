@@ -178,14 +178,14 @@ __device__ __forceinline__ float box_muller(uint32_t w0, uint32_t w1)
 // Scatterer draw of voxel (ix, iy, iz) -- index vox, scale-0 words in w --
 // for a volume with S > 1 noise scales: scale s draws on cells of 2^s voxels
 // (counter (cell, 0, s, 0)); n0 = sum_s N0_s / sqrt(S); the gate sums the
-// quantised normals Q[w2_s >> 20] in FP32 (s ascending) against
-// fl32(sqrt(S) mu1), exactly as the oracle decides it.
-__device__ __forceinline__ void scatter_multiscale(const VolDev& v, const float* __restrict__ q_lut, float mu1,
+// integer quantised normals Q[w2_s >> 20] (units of 2^-20) exactly and tests
+// the sum against the label's integer threshold floor(sqrt(S) mu1 2^20).
+__device__ __forceinline__ void scatter_multiscale(const VolDev& v, const int32_t* __restrict__ q_lut, int32_t thr,
                                                 int32_t ix, int32_t iy, int32_t iz, const uint32_t w[4],
                                                 float& n0, bool& gate)
 {
     float s0 = box_muller(w[0], w[1]);
-    float s1 = q_lut[w[2] >> 20];
+    int32_t s1 = q_lut[w[2] >> 20];
     for (int s = 1; s < v.scales; ++s) {
         const uint32_t mx = ((uint32_t)v.nx + (1u << s) - 1u) >> s;
         const uint32_t my = ((uint32_t)v.ny + (1u << s) - 1u) >> s;
@@ -193,11 +193,10 @@ __device__ __forceinline__ void scatter_multiscale(const VolDev& v, const float*
         uint32_t ws[4];
         philox4x32_10(cell, v.key0, v.key1, ws, (uint32_t)s);
         s0 += box_muller(ws[0], ws[1]);
-        s1 = s1 + q_lut[ws[2] >> 20];
+        s1 += q_lut[ws[2] >> 20];
     }
-    const double rs = sqrt((double)v.scales);
-    n0 = s0 * (float)(1.0 / rs);
-    gate = s1 <= (float)(rs * (double)mu1);
+    n0 = s0 * (float)(1.0 / sqrt((double)v.scales));
+    gate = s1 <= thr;
 }
 
 // ---- wave64 data movement on DPP (GFX9 controls) -----------------------
@@ -463,7 +462,8 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         } else {
             float n0;
             bool gate;
-            scatter_multiscale(v, a.q_lut, tt.mu1, (int32_t)((uint32_t)q[0] + 32768u) >> 16,
+            scatter_multiscale(v, a.q_lut, a.ms_thr[lab * kMaxNoiseScales + v.scales - 1],
+                               (int32_t)((uint32_t)q[0] + 32768u) >> 16,
                                (int32_t)((uint32_t)q[1] + 32768u) >> 16, (int32_t)((uint32_t)q[2] + 32768u) >> 16, w,
                                n0, gate);
             T = (inside && gate) ? n0 * tt.sigma0 + tt.mu0 : 0.f;
@@ -910,7 +910,8 @@ __global__ __launch_bounds__(kThreads) void k_encode(PhysArgs a, uint16_t* enc)
                     const int32_t ix = vox % v.nx, iy = (vox / v.nx) % v.ny, iz = vox / (v.nx * v.ny);
                     float n0;
                     bool gate;
-                    scatter_multiscale(v, a.q_lut, tt.mu1, ix, iy, iz, w, n0, gate);
+                    scatter_multiscale(v, a.q_lut, a.ms_thr[lab * kMaxNoiseScales + v.scales - 1], ix, iy, iz, w,
+                                       n0, gate);
                     if (gate) sc = n0;
                 }
             }
@@ -1047,7 +1048,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_ct(PhysArgs a, const uint16
             uint32_t w[4];
             philox4x32_10((uint32_t)vox, v.key0, v.key1, w);
             n0 = box_muller(w[0], w[1]);
-            n1 = a.q_lut[w[2] >> 20];
+            n1 = (float)a.q_lut[w[2] >> 20] * 0x1p-20f;   // exact: |Q| < 2^24
         }
         uint4 o;
         o.x = (uint32_t)f2bf16(ct) | ((uint32_t)f2bf16(n0) << 16);

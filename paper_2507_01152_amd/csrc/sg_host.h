@@ -101,7 +101,8 @@ struct sg_ctx {
     sg::DevBuf d_vols;
     sg::DevBuf table;
     sg::DevBuf pair_rt;   // (r, t) per label pair, when n_labels <= kPairLabels
-    sg::DevBuf q_lut;     // quantised normal of the multi-scale gate (kNoiseQ floats)
+    sg::DevBuf q_lut;     // quantised normal of the multi-scale gate (kNoiseQ int32, units of 2^-20)
+    sg::DevBuf ms_thr;    // multi-scale gate thresholds, [SG_MAX_LABELS_DEV][kMaxNoiseScales] int32
     int32_t n_labels = 0;
     sg::DevBuf scan, params, fields, queue;
     sg::PinnedBuf staging;

@@ -38,7 +38,7 @@ struct TissueDev {
     float alpha;
     float mu0;
     float sigma0;
-    float mu1;                // density parameter (multi-scale gate)
+    float mu1;                // density parameter
     unsigned long long thr;   // scatter gate: word2 < thr (thr may be 2^32)
 };
 
@@ -96,7 +96,8 @@ struct PhysArgs {
     const TissueDev* table;
     int32_t n_labels;
     const float2* pair_rt;    // [n_labels][n_labels] (r, t) of a boundary between two labels, or null
-    const float* q_lut;       // [kNoiseQ] quantised normal of the multi-scale gate
+    const int32_t* q_lut;     // [kNoiseQ] quantised normal of the multi-scale gate, units of 2^-20
+    const int32_t* ms_thr;    // [label][kMaxNoiseScales]: entry S - 1 is the gate threshold of S scales
     int32_t multiscale;       // some env's volume has more than one noise scale
     int32_t any_ct;           // some env's volume has a CT (impedance from HU in FP64)
     const float* coefs;       // PSF taps pool

@@ -125,6 +125,21 @@ unsigned long long gate_threshold(float mu1)
     return (unsigned long long)x;
 }
 
+int32_t multiscale_threshold(int S, float mu1)
+{
+    // multi-scale gate: (1 / sqrt S) sum_s Q_s 2^-20 <= mu1 with integer Q_s,
+    // i.e. sum_s Q_s <= floor(sqrt(S) mu1 2^20), one FP64 rounding per step
+    // in this order; clamped to int32 (sums of at most four quantised normals
+    // stay far inside it)
+    double x = std::sqrt((double)S);
+    x = x * (double)mu1;
+    x = x * 1048576.0;
+    x = std::floor(x);
+    if (!(x > -2147483648.0)) return INT32_MIN;
+    if (x > 2147483647.0) return INT32_MAX;
+    return (int32_t)x;
+}
+
 sg_status check_probe(const sg_probe& p, int idx)
 {
     if (p.W < 1 || p.W > SG_MAX_IMAGE || p.H < 1 || p.H > SG_MAX_IMAGE)
@@ -205,7 +220,7 @@ extern "C" const char* sg_last_error(void) { return g_err.c_str(); }
 
 extern "C" int32_t sg_version(void) { return 100; }
 
-extern "C" sg_status sg_noise_quantiles(float* out)
+extern "C" sg_status sg_noise_quantiles(int32_t* out)
 {
     if (!out) return fail(SG_EINVAL, "sg_noise_quantiles: NULL argument");
     // Phi(x) = erfc(-x / sqrt 2) / 2 is increasing: bisect to adjacent doubles
@@ -220,10 +235,11 @@ extern "C" sg_status sg_noise_quantiles(float* out)
             else
                 hi = mid;
         }
-        // the double nearer the root of the computed Phi
+        // the double nearer the root of the computed Phi, in units of 2^-20
+        // (an exact scaling), rounded half to even
         const double flo = std::fabs(0.5 * std::erfc(-lo / std::sqrt(2.0)) - p);
         const double fhi = std::fabs(0.5 * std::erfc(-hi / std::sqrt(2.0)) - p);
-        out[k] = (float)(flo < fhi ? lo : hi);
+        out[k] = (int32_t)std::nearbyint((flo < fhi ? lo : hi) * 1048576.0);
     }
     return SG_OK;
 }
@@ -247,10 +263,10 @@ extern "C" sg_status sg_create(sg_ctx** out, int32_t device, void* stream)
         c->n_cu = prop.multiProcessorCount;
         c->arch = prop.gcnArchName;
     }
-    std::vector<float> q(kNoiseQ);
+    std::vector<int32_t> q(kNoiseQ);
     (void)sg_noise_quantiles(q.data());
-    e = c->q_lut.ensure(sizeof(float) * kNoiseQ);
-    if (e == hipSuccess) e = hipMemcpy(c->q_lut.p, q.data(), sizeof(float) * kNoiseQ, hipMemcpyHostToDevice);
+    e = c->q_lut.ensure(sizeof(int32_t) * kNoiseQ);
+    if (e == hipSuccess) e = hipMemcpy(c->q_lut.p, q.data(), sizeof(int32_t) * kNoiseQ, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "noise table upload");
@@ -369,6 +385,7 @@ extern "C" sg_status sg_tissue_table_set(sg_ctx* c, const sg_tissue* rows, int32
     if (!c || !rows) return fail(SG_EINVAL, "sg_tissue_table_set: NULL argument");
     if (n < 1 || n > SG_MAX_LABELS) return fail(SG_EINVAL, "table size %d outside [1, %d]", n, SG_MAX_LABELS);
     std::vector<TissueDev> t(n);
+    std::vector<int32_t> ms((size_t)n * kMaxNoiseScales, 0);
     for (int i = 0; i < n; ++i) {
         const sg_tissue& r = rows[i];
         if (std::isnan(r.Z_mrayl) || r.Z_mrayl < 0.f || !std::isfinite(r.alpha_np_cm_mhz) ||
@@ -380,6 +397,7 @@ extern "C" sg_status sg_tissue_table_set(sg_ctx* c, const sg_tissue* rows, int32
         t[i].sigma0 = r.sigma0;
         t[i].mu1 = r.mu1;
         t[i].thr = gate_threshold(r.mu1);
+        for (int s = 2; s <= kMaxNoiseScales; ++s) ms[(size_t)i * kMaxNoiseScales + s - 1] = multiscale_threshold(s, r.mu1);
     }
     // reflection and transmission of a boundary between labels i (above) and j
     // (below), for label volumes: the ray kernel's FP64 expressions, evaluated
@@ -408,6 +426,8 @@ extern "C" sg_status sg_tissue_table_set(sg_ctx* c, const sg_tissue* rows, int32
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = c->table.ensure(sizeof(TissueDev) * SG_MAX_LABELS_DEV);
     if (e == hipSuccess) e = c->pair_rt.ensure(sizeof(float2) * rt.size());
+    if (e == hipSuccess) e = c->ms_thr.ensure(sizeof(int32_t) * SG_MAX_LABELS_DEV * kMaxNoiseScales);
+    if (e == hipSuccess) e = hipMemcpy(c->ms_thr.p, ms.data(), sizeof(int32_t) * ms.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->table.p, t.data(), sizeof(TissueDev) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->pair_rt.p, rt.data(), sizeof(float2) * rt.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "tissue table upload");
@@ -530,7 +550,8 @@ sg_status stage_physics(sg_ctx* c, int32_t n, const int32_t* vol_ids, const sg_p
     a.table = (const TissueDev*)c->table.p;
     a.n_labels = c->n_labels;
     a.pair_rt = c->n_labels <= kPairLabels ? (const float2*)c->pair_rt.p : nullptr;
-    a.q_lut = (const float*)c->q_lut.p;
+    a.q_lut = (const int32_t*)c->q_lut.p;
+    a.ms_thr = (const int32_t*)c->ms_thr.p;
     a.coefs = (const float*)(d + o_pool);
     a.ray_items = (const ItemRay*)(d + o_ray);
     a.n_ray = (int32_t)rays.size();

@@ -124,7 +124,8 @@ PhysArgs plan_args(sg_ctx* c, Plan* p, float* out)
     a.table = (const TissueDev*)c->table.p;
     a.n_labels = c->n_labels;
     a.pair_rt = c->n_labels <= kPairLabels ? (const float2*)c->pair_rt.p : nullptr;
-    a.q_lut = (const float*)c->q_lut.p;
+    a.q_lut = (const int32_t*)c->q_lut.p;
+    a.ms_thr = (const int32_t*)c->ms_thr.p;
     a.coefs = (const float*)p->d_pool.p;
     a.ray_items = (const ItemRay*)p->d_rays.p;
     a.n_ray = p->n_rays;

@@ -209,8 +209,9 @@ def sg_volume_release(ctx, vol_id: int):
 
 
 def sg_noise_quantiles() -> np.ndarray:
-    """The quantised standard normal of the multi-scale gate (4096 floats, host)."""
-    out = np.zeros(4096, dtype=np.float32)
+    """The quantised standard normal of the multi-scale gate (4096 int32 in
+    units of 2^-20, host)."""
+    out = np.zeros(4096, dtype=np.int32)
     _check(load().sg_noise_quantiles(out.ctypes.data), "sg_noise_quantiles")
     return out
 

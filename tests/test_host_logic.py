@@ -36,7 +36,7 @@ def test_audit_rule_rejects_bad_arguments(sg):
 def test_noise_quantiles_of_the_library_match_the_oracle():
     """The library's host-side quantised normal of the multi-scale gate
     (bisection on erfc, C++) equals the oracle's (scipy's ndtri), entry for
-    entry: both sides then decide the gate on identical FP32 steps."""
+    entry: both sides then sum identical integers."""
     import oracle
     from paper_2507_01152_amd import sonosim as sg
     assert np.array_equal(sg.sg_noise_quantiles(), oracle.quantised_normal_table())

@@ -342,6 +342,33 @@ def test_cos_theta_45_degree_staircase():
     assert np.allclose(o["cos_theta"][ys[interior], xs[interior]], 1 / sqrt(2), rtol=1e-15)
 
 
+@pytest.mark.parametrize("dx,dy", [(1.0, 0.5), (0.5, 1.0), (0.37, 0.29)])
+def test_cos_theta_pixel_diagonal_with_anisotropic_pixels(dx, dy):
+    """Labels split on ix + iz, imaged by an axis-aligned plane whose pixels
+    are the voxels (pitch dx laterally, dy axially): the interface runs along
+    the pixel diagonals, i.e. along the physical direction (dx, -dy), so its
+    normal is (dy, dx) / |(dx, dy)| and the beam (axial) meets it at
+    cos(theta) = dx / sqrt(dx^2 + dy^2).  Swapping the physical scaling of
+    the two Sobel sums would give dy / sqrt(dx^2 + dy^2) instead."""
+    n = 40
+    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    lab = np.where(xx + zz < 40, 1, 3).astype(np.uint8)
+    vol = Volume(labels=lab, spacing=(dx, 1.0, dy), seed=2)
+    probe = Probe(W=21, H=30, dx=dx, dy=dy)
+    # pixel (x, y) -> probe point ((x - 10) dx, 0, y dy) -> voxel (10 + x, 20, y)
+    pose = axis_pose((20.0 * dx, 20.0, 0.0))
+    g = oracle.geometry(vol, probe, pose)
+    assert [int(v) for v in g[0]] == [10 << 16, 20 << 16, 0] and [int(v) for v in g[1]] == [1 << 16, 0, 0]
+    assert [int(v) for v in g[2]] == [0, 0, 1 << 16]
+    o = oracle.simulate_env(vol, synth.default_tissue_table(), probe, pose, planes=("G", "cos_theta", "label"))
+    assert np.array_equal(o["label"], np.where(10 + np.arange(21)[None, :] + np.arange(30)[:, None] < 40, 1, 3))
+    ys, xs = np.nonzero(o["G"])
+    interior = (xs > 0) & (xs < probe.W - 1) & (ys > 0)
+    assert interior.sum() > 10
+    want = dx / sqrt(dx * dx + dy * dy)
+    assert np.allclose(o["cos_theta"][ys[interior], xs[interior]], want, rtol=1e-15, atol=0)
+
+
 # ---------------------------------------------------------------------------
 # O9 .. O11
 
@@ -452,16 +479,74 @@ def test_rejects_label_outside_table():
 # multi-scale noise (reading of the last sentence on the scattering pattern)
 
 def test_quantised_normal_table_inverts_the_normal_cdf():
-    """Q[k] is the FP32 quantile of (k + 1/2)/4096: pinned by the forward CDF
-    (a different library routine), odd symmetry and monotonicity."""
+    """Q[k] is the quantile of (k + 1/2)/4096 rounded to a multiple of 2^-20:
+    pinned by the forward CDF (a different library routine) bracketing the
+    probability between the half-steps around Q, odd symmetry and
+    monotonicity."""
     from scipy.stats import norm
     q = oracle.quantised_normal_table()
+    assert q.dtype == np.int32 and q.shape == (4096,)
     p = (np.arange(4096) + 0.5) / 4096.0
-    back = norm.cdf(q.astype(np.float64))
-    # one FP32 rounding of the quantile moves the CDF by at most pdf(Q) * ulp(Q) / 2
-    bound = norm.pdf(q) * np.spacing(np.abs(q).astype(np.float32)).astype(np.float64) + 1e-15
-    assert np.all(np.abs(back - p) <= bound)
+    lo = norm.cdf((q.astype(np.float64) - 0.5) * 2.0 ** -20)
+    hi = norm.cdf((q.astype(np.float64) + 0.5) * 2.0 ** -20)
+    assert np.all(lo <= p) and np.all(p <= hi)
     assert np.array_equal(q, -q[::-1]) and np.all(np.diff(q) > 0)
+    # next to the median Phi^-1(1/2 + e) = sqrt(2 pi) e + O(e^3): the entry
+    # above the median is rint(sqrt(2 pi) 2^-13 2^20)
+    assert q[2048] == round(sqrt(2 * np.pi) * 2.0 ** -13 * 2.0 ** 20) == 321
+
+
+def test_multiscale_threshold_is_the_exact_floor():
+    """floor(sqrt(S) mu1 2^20) against exact rational arithmetic: n <= sqrt(S)
+    mu1 2^20 is decided on squares of exact rationals (mu1 as its FP32 value),
+    and the threshold is the largest such integer n."""
+    def exact_floor(S, mu1):
+        m = Fraction(float(np.float32(mu1))) * (1 << 20)
+        # largest integer n with n <= sqrt(S) * m
+        if m >= 0:
+            n = isqrt(int(S * m * m))          # candidate for sqrt(S m^2)
+            while (n + 1) ** 2 <= S * m * m:
+                n += 1
+            while n * n > S * m * m:
+                n -= 1
+            return n
+        # m < 0: n <= -sqrt(S m^2)  <=>  n <= -ceil(sqrt(S m^2))
+        c = isqrt(int(S * m * m))
+        while c * c < S * m * m:
+            c += 1
+        return -c
+    rng = np.random.default_rng(12)
+    mus = [0.0, 0.5, -0.5, 1e-6, -1e-6, 0.3, 2.9, -2.9] + list(rng.normal(0, 1.5, 200))
+    for S in (2, 3, 4):
+        for mu in mus:
+            assert oracle.multiscale_threshold(S, mu) == exact_floor(S, mu), (S, mu)
+    assert oracle.multiscale_threshold(3, float("-inf")) == -(1 << 31)
+    assert oracle.multiscale_threshold(3, float("inf")) == (1 << 31) - 1
+
+
+def test_multiscale_gate_brute_force():
+    """The gate of every voxel of a small multi-scale grid, recomputed from
+    the generator's words (pinned against numpy's Philox above), the table and
+    the exact-rational threshold: sum_s Q[w2_s >> 20] <= sqrt(S) mu1 2^20."""
+    vol = _ms_volume(6, 3)
+    q = oracle.quantised_normal_table()
+    key = [41, 0]
+    for mu1 in (0.4, -0.7):
+        _, n1, g = oracle.scatter_grid(vol, mu1)
+        m = Fraction(float(np.float32(mu1))) * (1 << 20)
+        for iz in range(6):
+            for iy in range(6):
+                for ix in range(6):
+                    tot = 0
+                    for s in range(3):
+                        mx = (6 + (1 << s) - 1) >> s
+                        cell = ((iz >> s) * mx + (iy >> s)) * mx + (ix >> s)
+                        tot += int(q[int(oracle.philox4x32([cell, 0, s, 0], key)[2]) >> 20])
+                    assert int(n1[iz, iy, ix]) == tot
+                    # tot <= sqrt(3) m, decided on exact squares
+                    want = (tot <= 0 and (m >= 0 or tot * tot >= 3 * m * m)) or (tot > 0 and m > 0 and
+                                                                                 tot * tot <= 3 * m * m)
+                    assert bool(g[iz, iy, ix]) == want, (ix, iy, iz, tot)
 
 
 def _ms_volume(n, scales, seed=41):
@@ -503,6 +588,7 @@ def test_multiscale_noise_statistics(scales):
         shared = sum(1 for s in range(scales) if (j >> s) == ((j + 1) >> s))
         assert abs(np.corrcoef(a, b)[0, 1] - shared / scales) < 0.03, (j, shared)
     # N1 sums S unit-variance quantised normals: mean 0, variance S
+    n1 = n1 * 2.0 ** -20
     assert abs(n1.mean()) < 0.05 * np.sqrt(scales) and abs(n1.var() / scales - 1.0) < 0.05
 
 

@@ -109,8 +109,9 @@ def test_deep_attenuation_down_to_the_energy_floor(sess):
 
 @pytest.mark.parametrize("scales", [2, 3, 4])
 def test_multiscale_noise_parity(sess, scales):
-    """Multi-scale N0 and N1: the gate pattern bit for bit (FP32 sums of the
-    quantised normal on both sides), T, E, I and Y within the bars; odd
+    """Multi-scale N0 and N1: the gate pattern bit for bit (exact integer sums
+    of the quantised normal against the integer threshold on both sides), T,
+    E, I and Y within the bars; odd
     volume sizes exercise the coarse cells' partial edges."""
     wl = synth.ellipsoid_workload(seed=20 + scales, n_envs=2)
     for v in wl.volumes:
