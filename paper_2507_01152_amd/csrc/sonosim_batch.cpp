@@ -223,9 +223,12 @@ std::string tune_key(sg_ctx* c, Plan* p)
         maxW = std::max(maxW, pr.W);
         maxH = std::max(maxH, pr.H);
     }
+    // the ray kernel's instantiation (noise scales, CT, label-pair table)
+    // changes its occupancy, so it is part of the key
+    const int pairs = c->n_labels <= kPairLabels ? 1 : 0;
     std::ostringstream k;
     k << c->arch << "|n" << p->n_envs << "|px" << p->n_pixels << "|W" << maxW << "|H" << maxH << "|ra"
-      << p->max_rax << "|rl" << p->max_rlat;
+      << p->max_rax << "|rl" << p->max_rlat << "|ms" << p->multiscale << "|ct" << p->any_ct << "|lp" << pairs;
     return k.str();
 }
 
@@ -450,15 +453,24 @@ extern "C" sg_status sg_autotune(sg_ctx* c, int32_t id, const char* cache_path)
     hipError_t e = scratch_out.ensure(sizeof(float) * (size_t)p->n_pixels);
     if (e != hipSuccess) return hip_fail(e, "autotune output");
     // the plan's offsets may address a larger caller buffer: time into a
-    // private buffer laid out densely with the same sizes
-    std::vector<EnvDev> saved = p->envs;
+    // private buffer laid out densely with the same sizes.  The plan's own
+    // records (p->envs) are never changed; the device copy is restored from
+    // them on every exit after the dense upload.
+    std::vector<EnvDev> dense = p->envs;
     int64_t off = 0;
     for (int i = 0; i < p->n_envs; ++i) {
-        p->envs[i].out_off = off;
-        off += (int64_t)p->envs[i].W * p->envs[i].H;
+        dense[i].out_off = off;
+        off += (int64_t)dense[i].W * dense[i].H;
     }
-    e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * p->n_envs, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "autotune env upload");
+    auto restore = [&]() -> hipError_t {
+        drop_graph(p);   // captured with the dense offsets and the private buffer
+        return hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * p->n_envs, hipMemcpyHostToDevice);
+    };
+    e = hipMemcpy(p->d_envs.p, dense.data(), sizeof(EnvDev) * p->n_envs, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)restore();
+        return hip_fail(e, "autotune env upload");
+    }
     hipEvent_t t0 = nullptr, t1 = nullptr;
     (void)hipEventCreate(&t0);
     (void)hipEventCreate(&t1);
@@ -483,9 +495,7 @@ extern "C" sg_status sg_autotune(sg_ctx* c, int32_t id, const char* cache_path)
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
-    drop_graph(p);
-    p->envs = saved;
-    e = hipMemcpy(p->d_envs.p, p->envs.data(), sizeof(EnvDev) * p->n_envs, hipMemcpyHostToDevice);
+    e = restore();
     if (e != hipSuccess) return hip_fail(e, "autotune env restore");
     s = apply_shape(c, p, best);
     if (s != SG_OK) return s;

@@ -168,6 +168,31 @@ def _dptr(t):
     return t.data_ptr()
 
 
+def _out(t, what: str, elem_size: int, need: int, float32: bool = False):
+    """Device pointer of an output tensor the library writes `need` elements
+    of `elem_size` bytes into; refuses tensors that are too small, of the
+    wrong element size (or not float32 where float32 is written)."""
+    if t is None:
+        raise ValueError(f"{what}: output tensor is None")
+    if t.element_size() != elem_size or (float32 and not t.is_floating_point()):
+        raise ValueError(f"{what}: expected {'float32' if float32 else f'{elem_size}-byte'} elements, got {t.dtype}")
+    if t.numel() < need:
+        raise ValueError(f"{what}: {t.numel()} elements, the call writes {need}")
+    return _dptr(t)
+
+
+def _frames_extent(probes, offs) -> int:
+    """Elements of a packed output the frames of `probes` at offsets `offs`
+    reach: max(offset + planes * W * H)."""
+    if len(probes) == 0:
+        return 0
+    return int(max(int(o) + max(1, int(getattr(p, "n_elev", 1))) * int(p.W) * int(p.H)
+                   for o, p in zip(offs, probes)))
+
+
+_PLAN_EXTENT = {}   # (context address, plan id) -> output elements a step writes
+
+
 # ---------------------------------------------------------------------------
 
 def sg_version() -> int:
@@ -182,6 +207,8 @@ def sg_create(device: int = 0, stream=None):
 
 def sg_destroy(ctx):
     _check(load().sg_destroy(ctx), "sg_destroy")
+    for k in [k for k in _PLAN_EXTENT if k[0] == ctx.value]:
+        del _PLAN_EXTENT[k]
 
 
 def sg_set_stream(ctx, stream=None):
@@ -241,12 +268,22 @@ def sg_simulate(ctx, vol_ids, probes, poses, out, out_offsets, debug: dict | Non
     offs = np.ascontiguousarray(out_offsets, dtype=np.int64)
     if len(vids) != n or len(offs) != n:
         raise ValueError("vol_ids, probes and out_offsets must have one entry per env")
+    if (offs < 0).any():
+        raise ValueError("out_offsets must be >= 0")
+    need = _frames_extent(probes, offs)
     dbg = None
     if debug:
-        dbg = sg_debug_planes(*[_dptr(debug.get(k)) for k in ("label", "voxel", "philox", "energy",
-                                                               "intensity", "scatter")])
-    _check(load().sg_simulate(ctx, n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data, _dptr(out),
-                              offs.ctypes.data, C.byref(dbg) if dbg is not None else None), "sg_simulate")
+        spec = {"label": (1, 1, False), "voxel": (4, 1, False), "philox": (4, 4, False), "energy": (4, 1, True),
+                "intensity": (4, 1, True), "scatter": (4, 1, True)}
+        ptrs = []
+        for k in ("label", "voxel", "philox", "energy", "intensity", "scatter"):
+            t = debug.get(k)
+            size, per, f32 = spec[k]
+            ptrs.append(None if t is None else _out(t, f"sg_simulate debug {k}", size, per * need, f32))
+        dbg = sg_debug_planes(*ptrs)
+    _check(load().sg_simulate(ctx, n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data,
+                              _out(out, "sg_simulate", 4, need, True), offs.ctypes.data,
+                              C.byref(dbg) if dbg is not None else None), "sg_simulate")
 
 
 def sg_batch_plan_create(ctx, vol_ids, probes, out_offsets) -> int:
@@ -255,9 +292,19 @@ def sg_batch_plan_create(ctx, vol_ids, probes, out_offsets) -> int:
     offs = np.ascontiguousarray(out_offsets, dtype=np.int64)
     pa = probes_array(probes)
     pid = C.c_int32()
+    if len(vids) != n or len(offs) != n:
+        raise ValueError("vol_ids, probes and out_offsets must have one entry per env")
     _check(load().sg_batch_plan_create(ctx, n, vids.ctypes.data, C.cast(pa, C.c_void_p), offs.ctypes.data,
                                        C.byref(pid)), "sg_batch_plan_create")
+    _PLAN_EXTENT[(ctx.value, int(pid.value))] = _frames_extent(probes, offs)
     return int(pid.value)
+
+
+def _plan_out(ctx, plan_id: int, out, what: str):
+    need = _PLAN_EXTENT.get((ctx.value, int(plan_id)))
+    if need is None:
+        return _dptr(out)   # unknown plan: the library reports it
+    return _out(out, what, 4, need, True)
 
 
 def sg_batch_poses(ctx, plan_id: int) -> int:
@@ -276,13 +323,13 @@ def sg_batch_set_poses(ctx, plan_id: int, poses):
 def sg_batch_step_profiled(ctx, plan_id: int, out):
     """One eager step; returns (ray kernel ms, PSF kernel ms)."""
     a, b = C.c_float(), C.c_float()
-    _check(load().sg_batch_step_profiled(ctx, int(plan_id), _dptr(out), C.byref(a), C.byref(b)),
-           "sg_batch_step_profiled")
+    _check(load().sg_batch_step_profiled(ctx, int(plan_id), _plan_out(ctx, plan_id, out, "sg_batch_step_profiled"),
+                                         C.byref(a), C.byref(b)), "sg_batch_step_profiled")
     return float(a.value), float(b.value)
 
 
 def sg_batch_step(ctx, plan_id: int, out):
-    _check(load().sg_batch_step(ctx, int(plan_id), _dptr(out)), "sg_batch_step")
+    _check(load().sg_batch_step(ctx, int(plan_id), _plan_out(ctx, plan_id, out, "sg_batch_step")), "sg_batch_step")
 
 
 def sg_batch_status(ctx, plan_id: int) -> int:
@@ -311,6 +358,7 @@ def sg_batch_set_config(ctx, plan_id: int, scanlines_per_item: int, tile_x: int,
 
 def sg_batch_plan_destroy(ctx, plan_id: int):
     _check(load().sg_batch_plan_destroy(ctx, int(plan_id)), "sg_batch_plan_destroy")
+    _PLAN_EXTENT.pop((ctx.value, int(plan_id)), None)
 
 
 # ---------------------------------------------------------------------------
@@ -434,9 +482,13 @@ def sg_surr_infer(ctx, sid, vol_ids, probes, poses, out, audit_envs=(), psnr_min
     pa = probes_array(probes)
     ps = np.ascontiguousarray(poses, dtype=np.float64).reshape(n, 12)
     au = np.ascontiguousarray(audit_envs, dtype=np.int32)
+    if len(vids) != n:
+        raise ValueError("vol_ids and probes must have one entry per env")
+    need = sum(int(p.W) * int(p.H) for p in probes)
     psnr = np.zeros(max(1, len(au)), dtype=np.float32)
     nf = C.c_int32()
-    _check(load().sg_surr_infer(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data, _dptr(out),
+    _check(load().sg_surr_infer(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data,
+                                _out(out, "sg_surr_infer", 4, need, True),
                                 au.ctypes.data if len(au) else None, len(au), float(psnr_min), float(max_fail_frac),
                                 psnr.ctypes.data if len(au) else None, C.byref(nf)), "sg_surr_infer")
     return psnr[:len(au)], int(nf.value)

@@ -8,6 +8,7 @@ import synth
 from cases import axis_pose
 from oracle import surrogate as so
 from synth import Probe, Volume, Workload
+from tolerance import check_env
 
 pytestmark = pytest.mark.gpu
 
@@ -70,8 +71,15 @@ def test_ct_reference_and_input_parity(sess):
     assert hist.sum() == len(ref_envs) * H * W and hist[0] > 0 and hist[-1] > 0   # both clamps are hit
     envs = [3, 4, 5, 7]
     sg.sg_surr_train_step(sess.ctx, sid, vids[envs], [wl.probes[e] for e in envs], wl.poses[envs], 0.0)
-    xin, _ = sg.sg_surr_get_batch(sess.ctx, sid, len(envs), H, W)
+    xin, tgt = sg.sg_surr_get_batch(sess.ctx, sid, len(envs), H, W)
     _check_inputs(so.bf16_bits_to_f64(xin), wl, envs, ref)
+    # the physics targets (rendered by the CT ray instantiation without debug
+    # planes) against the oracle's frames
+    import oracle
+    for i, e in enumerate(envs):
+        o = oracle.simulate_env(wl.volumes[wl.vol_ids[e]], wl.table, wl.probes[e], wl.poses[e],
+                                planes=("I", "A", "Y"))
+        check_env({"Y": tgt[i]}, o, wl.probes[e], f"CT target env {e}")
     sg.sg_surr_destroy(sess.ctx, sid)
 
 

@@ -295,3 +295,58 @@ def test_volumes_smaller_than_a_brick(sess, dims):
     wl = single_env(vol, Probe(W=int(nx / 0.3) + 8, H=int(nz / 0.3) + 8, dx=0.3, dy=0.3), pose)
     g = check_all(sess, wl, name=f"tiny {dims}")
     assert (g[0]["voxel"] >= 0).sum() >= nx * nz and (g[0]["voxel"] == -1).any()
+
+
+def _many_label_workload(n_labels, scales, seed=31):
+    """A 40^3 volume of random labels 0..n_labels-1 in blocks of 3 voxels
+    (boundaries along every axis) under a random table, imaged by an oblique
+    plane: more than 16 labels leave the label-pair table unused, so the ray
+    kernel takes the FP64 impedance path."""
+    rng = np.random.default_rng(seed)
+    blocks = rng.integers(0, n_labels, size=(14, 14, 14)).astype(np.uint8)
+    lab = np.ascontiguousarray(blocks.repeat(3, 0).repeat(3, 1).repeat(3, 2)[:40, :40, :40])
+    lab[0, 0, 0] = n_labels - 1
+    t = np.zeros((n_labels, 5), dtype=np.float32)
+    t[:, 0] = rng.uniform(0.5, 8.0, n_labels)
+    t[0, 0] = 0.0
+    t[1, 0] = np.inf
+    t[:, 1] = rng.uniform(0.0, 0.8, n_labels)
+    t[:, 2] = rng.uniform(0.0, 0.1, n_labels)
+    t[:, 3] = rng.uniform(0.0, 0.05, n_labels)
+    t[:, 4] = rng.uniform(-1, 1, n_labels)
+    vol = Volume(labels=lab, spacing=(0.9, 1.0, 1.1), seed=78, noise_scales=scales)
+    poses = np.stack([synth.pose_from(synth.random_rotation(rng), (18.0 + i, 20.0, 17.0 - i)) for i in range(3)])
+    probes = [Probe(W=70, H=150, dx=0.3, dy=0.25), Probe(W=33, H=64, dx=0.4, dy=0.5),
+              Probe(W=129, H=97, dx=0.2, dy=0.3)]
+    return Workload([vol], np.zeros(3, dtype=np.int32), probes, poses, t)
+
+
+@pytest.mark.parametrize("scales", [1, 3])
+def test_many_labels_without_debug_planes(sess, scales):
+    """20 labels (no label-pair table) launched without debug planes: the
+    ray kernel's non-label-only, non-debug instantiation.  Frames against the
+    oracle, and bit for bit against the debug instantiation (itself checked
+    against the oracle plane by plane)."""
+    wl = _many_label_workload(20, scales)
+    g = check_all(sess, wl, name=f"20 labels S={scales} fast", debug=False)
+    assert any(len(np.unique(np.round(x["Y"], 3))) > 50 for x in g)
+    check_all(sess, wl, name=f"20 labels S={scales} debug")
+    vids = sess.load(wl)
+    fast, _, _ = sess.simulate(wl, vids, debug=False)
+    general, _, _ = sess.simulate(wl, vids, debug=True)
+    torch.cuda.synchronize()
+    assert torch.equal(fast, general)
+
+
+def test_spine_ct_full_size_without_debug_planes(sess):
+    """The full-size CT workload (64 envs, 256^3 labels + int16 HU, 128 x 256)
+    without debug planes: the CT instantiation the batched CT physics and the
+    CT surrogate's targets run on.  Every env's frame against the oracle, and
+    bit for bit against the debug instantiation."""
+    wl = synth.spine_ct_workload(seed=0)
+    check_all(sess, wl, name="c2 fast", debug=False)
+    vids = sess.load(wl)
+    fast, _, _ = sess.simulate(wl, vids, debug=False)
+    general, _, _ = sess.simulate(wl, vids, debug=True)
+    torch.cuda.synchronize()
+    assert torch.equal(fast, general) and (fast > 0).any()
