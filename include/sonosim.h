@@ -195,6 +195,26 @@ sg_status sg_simulate(sg_ctx* ctx, int32_t n_envs, const int32_t* vol_ids,
                       const sg_probe* probes, const double* poses, float* out,
                       const int64_t* out_offsets, const sg_debug_planes* debug);
 
+/* sg_simulate for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and frames (bit for bit), without debug planes, but it allocates
+ * nothing -- no hipMalloc / hipFree / pinned or other allocating call.  The
+ * per-plane records, PSF taps, work lists, work counter and the FP32 field
+ * planes between the two kernels live in a file-scope device array of
+ * SG_NOALLOC_SCRATCH_BYTES on each GPU, set up by sg_create and held until
+ * the process ends; the records are staged in a static host array.  Each
+ * call reuses its GPU's array, which keeps the last call's contents: calls
+ * that overlap on one GPU (e.g. on two streams) race; on one stream they are
+ * ordered.  A call waits (host) until the previous call's record upload has
+ * been read.  Limits: at most SG_NOALLOC_MAX_PLANES image planes (envs times
+ * their planes) and 12 bytes per field pixel (scanlines padded to 32 rows)
+ * within the array, e.g. 64 envs of 256 x 256.  Arguments as sg_simulate.
+ * Errors: as sg_simulate; SG_ERANGE beyond the limits (nothing is enqueued). */
+#define SG_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define SG_NOALLOC_MAX_PLANES 256
+sg_status sg_simulate_noalloc(sg_ctx* ctx, int32_t n_envs, const int32_t* vol_ids, const sg_probe* probes,
+                              const double* poses, float* out, const int64_t* out_offsets);
+
 /* ------------------------------------------------------------------------
  * Batched persistent path (environments stepped in batch mode, Sec. 4):
  * a plan fixes the environments' volumes, probes and output offsets; each

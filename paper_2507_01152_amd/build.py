@@ -15,8 +15,8 @@ LIB = os.path.join(HERE, "lib", "libsonosim.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["physics.hip", "conv_mfma.hip", "recon.hip", "probe.hip", "sonosim_api.cpp", "sonosim_batch.cpp",
-           "surrogate.cpp"]
+SOURCES = ["physics.hip", "conv_mfma.hip", "recon.hip", "probe.hip", "noalloc.hip", "sonosim_api.cpp",
+           "sonosim_batch.cpp", "surrogate.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           # no packed FP32 instructions in generated code
@@ -27,7 +27,7 @@ HOST_EXTRA = ["-ffp-contract=off"]
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    flags = COMMON + (HOST_EXTRA if src.endswith(".cpp") else [])
+    flags = COMMON + (HOST_EXTRA if src.endswith(".cpp") or src == "noalloc.hip" else [])
     cmd = [HIPCC] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -119,16 +119,25 @@ namespace sg {
 
 sg_status fail(sg_status code, const char* fmt, ...);
 sg_status hip_fail(hipError_t e, const char* what);
-int psf_taps(double sigma, std::vector<float>& pool, int32_t* offset);
+constexpr int kPsfTapsMax = 2 * kMaxPsfRadius + 1;
+int psf_taps_into(double sigma, float* out);   // no allocation
 sg_status check_probe(const sg_probe& p, int idx);
 // static parameters of plane `plane` of caller env idx (frame at out_off + plane * W * H)
 sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int plane, int64_t out_off, int64_t scr_off,
                           std::vector<float>& pool, EnvDev& e);
+// the same without allocation: taps appended to pool[*pool_used ..) within pool_cap floats
+// (SG_ERANGE when full), e.kax / e.klat as offsets into pool
+sg_status fill_env_static_into(const sg_probe& p, int32_t vol, int idx, int plane, int64_t out_off, int64_t scr_off,
+                               float* pool, int64_t pool_cap, int64_t* pool_used, EnvDev& e);
 int probe_planes(const sg_probe& p);                 // image planes of a probe (>= 1)
 double plane_elevation(const sg_probe& p, int j);   // elevation b of plane j, mm
 void build_items(const std::vector<EnvDev>& envs, const std::vector<int>& order, int spw, int tx,
                  std::vector<ItemRay>& rays, std::vector<ItemPsf>& tiles);
 sg_status sync_volumes(sg_ctx* c);
+// entry point without allocation (noalloc.hip): its device scratch and limits
+constexpr size_t kNoAllocBytes = SG_NOALLOC_SCRATCH_BYTES;
+constexpr int kNoAllocMaxPlanes = SG_NOALLOC_MAX_PLANES;
+hipError_t noalloc_init(int device);   // with `device` current; once per device (later calls return at once)
 
 struct StageInfo {
     int tile_x = 32;

@@ -96,20 +96,20 @@ hipError_t PinnedBuf::acquire(size_t bytes)
     return e;
 }
 
-// normalised sampled Gaussian of std sigma; radius max(1, ceil(3 sigma))
-int psf_taps(double sigma, std::vector<float>& pool, int32_t* offset)
+// normalised sampled Gaussian of std sigma; radius max(1, ceil(3 sigma));
+// taps 0 .. 2r into out (room for kPsfTapsMax); returns r, or -1 beyond kMaxPsfRadius
+int psf_taps_into(double sigma, float* out)
 {
     int r = (int)std::ceil(3.0 * sigma);
     if (r < 1) r = 1;
     if (r > kMaxPsfRadius) return -1;
-    std::vector<double> k(2 * r + 1);
+    double k[kPsfTapsMax];
     double sum = 0.0;
     for (int i = -r; i <= r; ++i) {
         k[i + r] = std::exp(-((double)i * (double)i) / (2.0 * sigma * sigma));
         sum += k[i + r];
     }
-    *offset = (int32_t)pool.size();
-    for (double v : k) pool.push_back((float)(v / sum));
+    for (int i = 0; i <= 2 * r; ++i) out[i] = (float)(k[i] / sum);
     return r;
 }
 
@@ -165,6 +165,19 @@ double plane_elevation(const sg_probe& p, int j)
 sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int plane, int64_t out_off, int64_t scr_off,
                           std::vector<float>& pool, EnvDev& e)
 {
+    float taps[2 * kPsfTapsMax];
+    int64_t used = 0;
+    const sg_status s = fill_env_static_into(p, vol, idx, plane, out_off, scr_off, taps, 2 * kPsfTapsMax, &used, e);
+    if (s != SG_OK) return s;
+    e.kax += (int32_t)pool.size();
+    e.klat += (int32_t)pool.size();
+    pool.insert(pool.end(), taps, taps + used);
+    return SG_OK;
+}
+
+sg_status fill_env_static_into(const sg_probe& p, int32_t vol, int idx, int plane, int64_t out_off, int64_t scr_off,
+                               float* pool, int64_t pool_cap, int64_t* pool_used, EnvDev& e)
+{
     std::memset(&e, 0, sizeof(e));
     e.pose_env = idx;
     e.plane = plane;
@@ -172,10 +185,18 @@ sg_status fill_env_static(const sg_probe& p, int32_t vol, int idx, int plane, in
     e.W = p.W;
     e.H = p.H;
     e.vol = vol;
-    e.rax = psf_taps(p.psf_frac * (double)p.H, pool, &e.kax);
-    e.rlat = psf_taps(p.psf_frac * (double)p.W, pool, &e.klat);
+    float kax[kPsfTapsMax], klat[kPsfTapsMax];
+    e.rax = psf_taps_into(p.psf_frac * (double)p.H, kax);
+    e.rlat = psf_taps_into(p.psf_frac * (double)p.W, klat);
     if (e.rax < 0 || e.rlat < 0)
         return fail(SG_EINVAL, "env %d: PSF radius exceeds %d pixels", idx, kMaxPsfRadius);
+    const int64_t nax = 2 * e.rax + 1, nlat = 2 * e.rlat + 1;
+    if (*pool_used + nax + nlat > pool_cap) return fail(SG_ERANGE, "env %d: PSF tap pool full", idx);
+    e.kax = (int32_t)*pool_used;
+    std::memcpy(pool + *pool_used, kax, sizeof(float) * nax);
+    e.klat = (int32_t)(*pool_used + nax);
+    std::memcpy(pool + *pool_used + nax, klat, sizeof(float) * nlat);
+    *pool_used += nax + nlat;
     e.E0 = (float)p.E0;
     e.inv_E0 = (float)(1.0 / p.E0);
     e.dx = (float)p.dx_mm;
@@ -258,6 +279,11 @@ extern "C" sg_status sg_create(sg_ctx** out, int32_t device, void* stream)
     if (!c) return fail(SG_ENOMEM, "sg_create: out of host memory");
     c->device = device;
     c->stream = (hipStream_t)stream;
+    e = noalloc_init(device);   // the no-allocation entry point's scratch on this device
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "scratch symbol");
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
         c->n_cu = prop.multiProcessorCount;
@@ -362,7 +388,9 @@ extern "C" sg_status sg_volume_register(sg_ctx* c, const sg_volume_desc* d, int3
     c->vols.push_back(v);
     c->vols_dirty = true;
     *vol_id = (int32_t)c->vols.size() - 1;
-    return SG_OK;
+    // the device table is brought up to date here, where allocating is
+    // allowed (the entry point without allocation relies on it)
+    return sync_volumes(c);
 }
 
 extern "C" sg_status sg_volume_release(sg_ctx* c, int32_t id)

@@ -22,6 +22,7 @@ SG_MAX_IMAGE = 1024
 SYMBOLS = (
     "sg_last_error", "sg_version", "sg_create", "sg_destroy", "sg_set_stream", "sg_synchronize",
     "sg_volume_register", "sg_volume_release", "sg_noise_quantiles", "sg_tissue_table_set", "sg_simulate",
+    "sg_simulate_noalloc",
     "sg_batch_plan_create", "sg_batch_poses", "sg_batch_set_poses", "sg_batch_step",
     "sg_batch_step_profiled", "sg_batch_status", "sg_autotune",
     "sg_batch_config", "sg_batch_set_config", "sg_batch_plan_destroy",
@@ -93,6 +94,7 @@ def load():
         "sg_noise_quantiles": [VP],
         "sg_tissue_table_set": [VP, VP, I32],
         "sg_simulate": [VP, I32, VP, VP, VP, VP, VP, P(sg_debug_planes)],
+        "sg_simulate_noalloc": [VP, I32, VP, VP, VP, VP, VP],
         "sg_batch_plan_create": [VP, I32, VP, VP, VP, P(I32)],
         "sg_batch_poses": [VP, I32, P(VP)],
         "sg_batch_set_poses": [VP, I32, VP],
@@ -284,6 +286,22 @@ def sg_simulate(ctx, vol_ids, probes, poses, out, out_offsets, debug: dict | Non
     _check(load().sg_simulate(ctx, n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data,
                               _out(out, "sg_simulate", 4, need, True), offs.ctypes.data,
                               C.byref(dbg) if dbg is not None else None), "sg_simulate")
+
+
+def sg_simulate_noalloc(ctx, vol_ids, probes, poses, out, out_offsets):
+    """sg_simulate without allocation (no debug planes); out: device float32 tensor."""
+    n = len(probes)
+    vids = np.ascontiguousarray(vol_ids, dtype=np.int32)
+    pa = probes_array(probes)
+    ps = np.ascontiguousarray(poses, dtype=np.float64).reshape(n, 12)
+    offs = np.ascontiguousarray(out_offsets, dtype=np.int64)
+    if len(vids) != n or len(offs) != n:
+        raise ValueError("vol_ids, probes and out_offsets must have one entry per env")
+    if (offs < 0).any():
+        raise ValueError("out_offsets must be >= 0")
+    _check(load().sg_simulate_noalloc(ctx, n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data,
+                                      _out(out, "sg_simulate_noalloc", 4, _frames_extent(probes, offs), True),
+                                      offs.ctypes.data), "sg_simulate_noalloc")
 
 
 def sg_batch_plan_create(ctx, vol_ids, probes, out_offsets) -> int:
