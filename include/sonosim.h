@@ -493,6 +493,51 @@ sg_status sg_surr_set_params(sg_ctx* ctx, int32_t surr_id, const float* host);
  * and physics target (FP32, n x H x W). */
 sg_status sg_surr_get_batch(sg_ctx* ctx, int32_t surr_id, uint16_t* input, float* target);
 
+/* Host copy of a tensor the last training step left on the device (support
+ * for element-wise checking of each layer; valid until the next training or
+ * inference call of this surrogate).  With host == NULL, *n receives the
+ * element count; otherwise *n must equal it and the elements are copied
+ * (synchronises).  n frames of the last step, NHWC, H x W at level 0 and
+ * (H >> l) x (W >> l) at level l:
+ *   SG_SURR_T_ACT    bf16 tensor `index` (uint16 bits): 0 X (8 ch, input),
+ *       1 T1 (16), 2 E0 (16), 3 T2 (32, l1), 4 E1 (32), 5 T3 (64, l2),
+ *       6 E2 (64), 7 T4 (128, l3), 8 E3 (128), 9 T5 (256, l4), 10 B4 (256),
+ *       11 U3 (128, l3), 12 S3 = U3 + E3, 13 D3 (128), 14 U2 (64, l2),
+ *       15 S2 = U2 + E2, 16 D2, 17 U1 (32, l1), 18 S1 = U1 + E1, 19 D1,
+ *       20 U0 (16, l0), 21 S0 = [U0 + E0, depth integral] (24), 22 D0 (16),
+ *       23 A0 (8, the depth integral before its copy into S0)
+ *   SG_SURR_T_GRAD   FP32 gradient of the loss at tensor `index` (>= 1)
+ *   SG_SURR_T_YHAT, _TARGET, _GY   FP32 n x H x W: network output, physics
+ *       target, gradient at the output (L1 plus the adversarial part)
+ *   SG_SURR_T_MOM1, _MOM2   FP32 Adam moments (sg_surr_num_params)
+ *   SG_SURR_T_DSCAN  bf16 gradient at the depth map p (n x H x W x 8): the
+ *       backward of the depth integral, scale * sum of the rows below
+ * With a discriminator (frames [0, 2n): the step's first pass on the real
+ * then the fake pairs; frames [2n, 3n): its second pass on the fake pairs
+ * through the updated discriminator; level l = 1, 2, 3, 3, 3 for k = 1..5):
+ *   SG_SURR_T_DISC_ACT   bf16 input of layer `index` (0: z, 8 ch, frames
+ *       [0, 2n) only; 1..4: 32, 64, 128, 128 ch after leaky ReLU)
+ *   SG_SURR_T_DISC_GRAD  FP32 gradient at that tensor (index 0: second pass only)
+ *   SG_SURR_T_DISC_LOGITS, _GLOG   FP32 last-layer outputs (8 ch, channel 0
+ *       the logit) and their gradient, (H >> 3) x (W >> 3)
+ *   SG_SURR_T_DISC_MOM1, _MOM2   FP32 Adam moments (sg_surr_disc_num_params)
+ * Errors: SG_EINVAL (id, kind, index, count), SG_ESTATE (no step yet). */
+#define SG_SURR_T_ACT 0
+#define SG_SURR_T_GRAD 1
+#define SG_SURR_T_YHAT 2
+#define SG_SURR_T_TARGET 3
+#define SG_SURR_T_GY 4
+#define SG_SURR_T_MOM1 5
+#define SG_SURR_T_MOM2 6
+#define SG_SURR_T_DISC_ACT 7
+#define SG_SURR_T_DISC_GRAD 8
+#define SG_SURR_T_DISC_LOGITS 9
+#define SG_SURR_T_DISC_GLOG 10
+#define SG_SURR_T_DISC_MOM1 11
+#define SG_SURR_T_DISC_MOM2 12
+#define SG_SURR_T_DSCAN 13
+sg_status sg_surr_tensor(sg_ctx* ctx, int32_t surr_id, int32_t kind, int32_t index, void* host, int64_t* n);
+
 /* VALU throughput probe (measurement support for the rooflines): times
  * independent instruction chains over a grid of 8 blocks of 256 threads per
  * compute unit and writes each kind's rate in lane-operations per second to

@@ -78,6 +78,7 @@ struct Surrogate {
     int cap = 0, cap_grad = 0, last_n = 0;
     DevBuf act[kNumT], gact[kNumT];
     DevBuf dpre, fine, parts, yhat, target, gy, loss, psnr, idx;
+    DevBuf dscan;   // bf16 gradient at the depth map's output (the integral's backward), n x H x W x kScanC
     // CT-conditioned input: per-frame histograms and matching maps, the reference
     // (kCtBins int64 counts, then their inclusive cumulative counts) and its total
     bool ct = false;
@@ -85,7 +86,9 @@ struct Surrogate {
     DevBuf ct_hist, ct_lut, ct_ref;
     long long ct_n_ref = 0;
     // discriminator (adv_weight > 0): FP32 masters, Adam moments, gradient, bf16 copies; tensors for up to
-    // d_cap frames (d_act[k]: bf16, tensor k; d_g[k]: FP32 gradient at tensor k; logits FP32)
+    // d_cap frames (d_act[k]: bf16, tensor k; d_g[k]: FP32 gradient at tensor k; logits FP32).  A step's
+    // first pass (real and fake pairs, 2n frames) uses frames [0, 2n), its second pass (the generator's
+    // adversarial gradient, n frames) frames [2n, 3n), so both stay readable after the step
     int64_t dn_params = 0;
     int64_t dw_off[kNumD] = {}, db_off[kNumD] = {}, dw_n[kNumD] = {};
     DevBuf d_master, d_mom1, d_mom2, d_grad, d_wb, d_wt;
@@ -234,6 +237,7 @@ sg_status ensure_capacity(Surrogate& s, int n, bool grads)
         int64_t mx = 0;
         for (int t = 1; t < kNumT; ++t) mx = std::max(mx, tensor_elems(s, t, n));
         SG_TRY(check(s.dpre.ensure(sizeof(uint16_t) * mx), "dpre buffer"));
+        SG_TRY(check(s.dscan.ensure(sizeof(uint16_t) * (size_t)n * s.H * s.W * kScanC), "depth map gradient"));
         SG_TRY(check(s.gy.ensure(sizeof(float) * (int64_t)n * s.H * s.W), "output grad"));
         s.cap_grad = n;
     }
@@ -342,18 +346,18 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
         const int64_t n_out = tensor_elems(s, d.out, n);
         const int64_t rows = n_out / d.Co;
         if (go == kScanDst) {
-            // depth integral: dp (bf16, in dpre), its bias gradient, and the skip copy of
+            // depth integral: dp (bf16, in dscan), its bias gradient, and the skip copy of
             // S0's first channels into E0's gradient; then the 1x1 map's two products
             const int sb = depth_scan_blocks(n, s.W);
             SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)sb * kScanC), "depth integral workspace"));
             SG_TRY(check(depth_scan_bwd((const float*)s.gact[kScanDst].p, kTC[kScanDst], kScanOff,
-                                        (float*)s.gact[kScanSrc].p, (uint16_t*)s.dpre.p, (float*)s.parts.p,
+                                        (float*)s.gact[kScanSrc].p, (uint16_t*)s.dscan.p, (float*)s.parts.p,
                                         grad + s.proj_b, n, s.H, s.W, kScanScale, c->stream),
                          "depth integral backward"));
             const ConvShape ps = proj_shape(s, n);
-            SG_TRY(wgrad(c, ps, (const uint16_t*)s.act[kScanSrc].p, (const uint16_t*)s.dpre.p, grad + s.proj_w,
+            SG_TRY(wgrad(c, ps, (const uint16_t*)s.act[kScanSrc].p, (const uint16_t*)s.dscan.p, grad + s.proj_w,
                          nullptr, s.parts));
-            SG_TRY(dgrad(c, ps, (const uint16_t*)s.dpre.p, (const uint16_t*)s.wt.p + s.proj_w,
+            SG_TRY(dgrad(c, ps, (const uint16_t*)s.dscan.p, (const uint16_t*)s.wt.p + s.proj_w,
                          (float*)s.gact[kScanSrc].p, 1, s.fine));
             written[kScanSrc] = true;
         }
@@ -443,7 +447,7 @@ sg_status disc_capacity(Surrogate& s, int frames)
 {
     if (frames <= s.d_cap) return SG_OK;
     int64_t mx = 0;
-    for (int k = 0; k < kNumD; ++k) {
+    for (int k = 0; k < kNumD; ++k) {   // (k = 0: the input z; its gradient only in the second pass)
         SG_TRY(check(s.d_act[k].ensure(sizeof(uint16_t) * disc_elems(s, k, frames)), "discriminator activations"));
         SG_TRY(check(s.d_g[k].ensure(sizeof(float) * disc_elems(s, k, frames)), "discriminator gradients"));
         mx = std::max(mx, disc_elems(s, k + 1, frames));
@@ -500,49 +504,55 @@ sg_status disc_create(sg_ctx* c, Surrogate& s, uint64_t seed)
     return disc_refresh_bf16(c, s);
 }
 
-// forward over `frames` frames of input z (bf16, [frames][H][W][8]): d_act[1..], logits
-sg_status disc_forward(sg_ctx* c, Surrogate& s, const uint16_t* z, int frames)
+// element offset of frame `off` in the discriminator's tensor k
+int64_t disc_at(const Surrogate& s, int k, int off) { return disc_elems(s, k, off); }
+
+// forward over `frames` frames of input z (bf16, [frames][H][W][8]): d_act[1..], logits, written from
+// frame `off` on
+sg_status disc_forward(sg_ctx* c, Surrogate& s, const uint16_t* z, int frames, int off)
 {
     for (int L = 0; L < kNumD; ++L) {
         const bool last = L == kNumD - 1;
         ConvArgs a;
         std::memset(&a, 0, sizeof(a));
-        a.a = L == 0 ? z : (const uint16_t*)s.d_act[L].p;
+        a.a = L == 0 ? z : (const uint16_t*)s.d_act[L].p + disc_at(s, L, off);
         a.b = (const uint16_t*)s.d_wb.p + s.dw_off[L];
         a.bias = (const float*)s.d_master.p + s.db_off[L];
         a.relu = last ? 0 : 2;
         if (last)
-            a.out_f32 = (float*)s.d_logits.p;
+            a.out_f32 = (float*)s.d_logits.p + disc_at(s, kNumD, off);
         else
-            a.out_bf16 = (uint16_t*)s.d_act[L + 1].p;
+            a.out_bf16 = (uint16_t*)s.d_act[L + 1].p + disc_at(s, L + 1, off);
         SG_TRY(check(conv_gemm(0, geom_of(disc_shape(s, L, frames), 0), a, 1, c->stream), "discriminator conv"));
     }
     return SG_OK;
 }
 
 // backward from the logit gradient in d_glog: parameter gradients into d_grad (weights) and the input
-// gradient into d_g[0] (input_grad)
-sg_status disc_backward(sg_ctx* c, Surrogate& s, const uint16_t* z, int frames, bool weights, bool input_grad)
+// gradient into d_g[0] (input_grad); tensors from frame `off` on
+sg_status disc_backward(sg_ctx* c, Surrogate& s, const uint16_t* z, int frames, bool weights, bool input_grad,
+                        int off)
 {
     float* grad = (float*)s.d_grad.p;
     for (int L = kNumD - 1; L >= 0; --L) {
         const bool last = L == kNumD - 1;
         const ConvShape sh = disc_shape(s, L, frames);
         const int64_t rows = disc_elems(s, L + 1, frames) / kDisc[L].Co;
-        const float* g_out = last ? (const float*)s.d_glog.p : (const float*)s.d_g[L + 1].p;
+        const float* g_out = last ? (const float*)s.d_glog.p + disc_at(s, kNumD, off)
+                                  : (const float*)s.d_g[L + 1].p + disc_at(s, L + 1, off);
         const int mb = blocks_for(rows * 16, 1024);
         SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)mb * kDisc[L].Co), "bias workspace"));
-        SG_TRY(check(mask_colsum(g_out, 0, last ? nullptr : (const uint16_t*)s.d_act[L + 1].p, (uint16_t*)s.d_dpre.p,
-                                 rows, kDisc[L].Co, (float*)s.parts.p, mb,
+        SG_TRY(check(mask_colsum(g_out, 0, last ? nullptr : (const uint16_t*)s.d_act[L + 1].p + disc_at(s, L + 1, off),
+                                 (uint16_t*)s.d_dpre.p, rows, kDisc[L].Co, (float*)s.parts.p, mb,
                                  weights ? grad + s.db_off[L] : (float*)s.d_bias_scratch.p, c->stream,
                                  last ? 0.f : kLeakySlope),
                      "discriminator mask"));
-        const uint16_t* x = L == 0 ? z : (const uint16_t*)s.d_act[L].p;
+        const uint16_t* x = L == 0 ? z : (const uint16_t*)s.d_act[L].p + disc_at(s, L, off);
         if (weights)
             SG_TRY(wgrad(c, sh, x, (const uint16_t*)s.d_dpre.p, grad + s.dw_off[L], nullptr, s.parts));
         if (L > 0 || input_grad)
             SG_TRY(dgrad(c, sh, (const uint16_t*)s.d_dpre.p, (const uint16_t*)s.d_wt.p + s.dw_off[L],
-                         (float*)s.d_g[L].p, 0, s.fine));
+                         (float*)s.d_g[L].p + disc_at(s, L, off), 0, s.fine));
     }
     return SG_OK;
 }
@@ -574,29 +584,33 @@ sg_status disc_adam(sg_ctx* c, Surrogate& s, float lr)
 // gradient through the updated discriminator, added into gy.  Losses: loss[1] = L_D, loss[2] = L_adv.
 sg_status adversarial_step(sg_ctx* c, Surrogate& s, int n, float lr)
 {
-    SG_TRY(disc_capacity(s, 2 * n));
+    SG_TRY(disc_capacity(s, 3 * n));
     const int64_t P = (int64_t)n * s.H * s.W;
     const int64_t Pp = (int64_t)n * (s.H >> 3) * (s.W >> 3);   // patches per set
     uint16_t* z = (uint16_t*)s.d_act[0].p;
     SG_TRY(check(disc_input((const uint16_t*)s.act[X].p, (const float*)s.target.p, (const float*)s.yhat.p, z, P,
                             c->stream),
                  "discriminator input"));
-    SG_TRY(disc_forward(c, s, z, 2 * n));
+    SG_TRY(disc_forward(c, s, z, 2 * n, 0));
     const int bb = blocks_for(2 * Pp, 256);
     SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)bb), "bce workspace"));
     const float wd = 0.5f / (float)Pp;
     SG_TRY(check(bce_logits((const float*)s.d_logits.p, kDiscLogitC, Pp, 2 * Pp, wd, wd, 1.f, (float*)s.d_glog.p,
                             (float*)s.parts.p, bb, (float*)s.loss.p + 1, c->stream),
                  "discriminator loss"));
-    SG_TRY(disc_backward(c, s, z, 2 * n, true, false));
+    SG_TRY(disc_backward(c, s, z, 2 * n, true, false, 0));
     SG_TRY(disc_adam(c, s, lr));
-    const uint16_t* zf = z + P * 8;   // the fake half
-    SG_TRY(disc_forward(c, s, zf, n));
-    SG_TRY(check(bce_logits((const float*)s.d_logits.p, kDiscLogitC, Pp, Pp, 1.f / (float)Pp, 0.f, s.adv_weight,
-                            (float*)s.d_glog.p, (float*)s.parts.p, bb, (float*)s.loss.p + 2, c->stream),
+    // second pass on the fake half through the updated discriminator, tensors at frames [2n, 3n)
+    const uint16_t* zf = z + P * 8;
+    const int off = 2 * n;
+    SG_TRY(disc_forward(c, s, zf, n, off));
+    SG_TRY(check(bce_logits((const float*)s.d_logits.p + disc_at(s, kNumD, off), kDiscLogitC, Pp, Pp,
+                            1.f / (float)Pp, 0.f, s.adv_weight, (float*)s.d_glog.p + disc_at(s, kNumD, off),
+                            (float*)s.parts.p, bb, (float*)s.loss.p + 2, c->stream),
                  "adversarial loss"));
-    SG_TRY(disc_backward(c, s, zf, n, false, true));
-    return check(add_channel((float*)s.gy.p, (const float*)s.d_g[0].p, 8, kDiscImageC, P, c->stream),
+    SG_TRY(disc_backward(c, s, zf, n, false, true, off));
+    return check(add_channel((float*)s.gy.p, (const float*)s.d_g[0].p + disc_at(s, 0, off), 8, kDiscImageC, P,
+                             c->stream),
                  "adversarial gradient");
 }
 
@@ -1114,6 +1128,58 @@ extern "C" sg_status sg_surr_get_batch(sg_ctx* c, int32_t id, uint16_t* input, f
     if (e == hipSuccess && input) e = hipMemcpy(input, s->act[X].p, sizeof(uint16_t) * 8 * P, hipMemcpyDeviceToHost);
     if (e == hipSuccess && target) e = hipMemcpy(target, s->target.p, sizeof(float) * P, hipMemcpyDeviceToHost);
     return check(e, "batch readback");
+}
+
+extern "C" sg_status sg_surr_tensor(sg_ctx* c, int32_t id, int32_t kind, int32_t index, void* host, int64_t* n)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !n) return fail(SG_EINVAL, "sg_surr_tensor: bad id or NULL");
+    if (s->last_n < 1) return fail(SG_ESTATE, "sg_surr_tensor: no training step yet");
+    const int ln = s->last_n;
+    const int64_t P = (int64_t)ln * s->H * s->W;
+    const bool disc = kind >= SG_SURR_T_DISC_ACT && kind <= SG_SURR_T_DISC_MOM2;
+    if (disc && s->adv_weight <= 0.f) return fail(SG_EINVAL, "sg_surr_tensor: the surrogate has no discriminator");
+    const void* src = nullptr;
+    int64_t count = 0;
+    size_t esz = sizeof(float);
+    switch (kind) {
+    case SG_SURR_T_ACT:
+    case SG_SURR_T_GRAD:
+        if (index < (kind == SG_SURR_T_GRAD ? 1 : 0) || index >= kNumT)
+            return fail(SG_EINVAL, "sg_surr_tensor: tensor index %d", index);
+        src = kind == SG_SURR_T_ACT ? s->act[index].p : s->gact[index].p;
+        count = tensor_elems(*s, index, ln);
+        if (kind == SG_SURR_T_ACT) esz = sizeof(uint16_t);
+        break;
+    case SG_SURR_T_YHAT: src = s->yhat.p; count = P; break;
+    case SG_SURR_T_TARGET: src = s->target.p; count = P; break;
+    case SG_SURR_T_GY: src = s->gy.p; count = P; break;
+    case SG_SURR_T_MOM1: src = s->mom1.p; count = s->n_params; break;
+    case SG_SURR_T_MOM2: src = s->mom2.p; count = s->n_params; break;
+    case SG_SURR_T_DSCAN: src = s->dscan.p; count = P * kScanC; esz = sizeof(uint16_t); break;
+    case SG_SURR_T_DISC_ACT:
+    case SG_SURR_T_DISC_GRAD:
+        if (index < 0 || index >= kNumD) return fail(SG_EINVAL, "sg_surr_tensor: discriminator tensor %d", index);
+        src = kind == SG_SURR_T_DISC_ACT ? s->d_act[index].p : s->d_g[index].p;
+        count = disc_elems(*s, index, 3 * ln);
+        if (kind == SG_SURR_T_DISC_ACT) esz = sizeof(uint16_t);
+        break;
+    case SG_SURR_T_DISC_LOGITS: src = s->d_logits.p; count = disc_elems(*s, kNumD, 3 * ln); break;
+    case SG_SURR_T_DISC_GLOG: src = s->d_glog.p; count = disc_elems(*s, kNumD, 3 * ln); break;
+    case SG_SURR_T_DISC_MOM1: src = s->d_mom1.p; count = s->dn_params; break;
+    case SG_SURR_T_DISC_MOM2: src = s->d_mom2.p; count = s->dn_params; break;
+    default: return fail(SG_EINVAL, "sg_surr_tensor: kind %d", kind);
+    }
+    if (!host) {
+        *n = count;
+        return SG_OK;
+    }
+    if (*n != count) return fail(SG_EINVAL, "sg_surr_tensor: %lld elements asked, the tensor has %lld",
+                                 (long long)*n, (long long)count);
+    (void)hipSetDevice(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(host, src, esz * (size_t)count, hipMemcpyDeviceToHost);
+    return check(e, "tensor readback");
 }
 
 extern "C" sg_status sg_surr_gan_losses(sg_ctx* c, int32_t id, float* loss_d, float* loss_adv)

@@ -33,7 +33,7 @@ SYMBOLS = (
     "sg_surr_train_step", "sg_surr_infer", "sg_surr_train_pairs", "sg_surr_gan_losses", "sg_surr_disc_num_params",
     "sg_surr_disc_get_params", "sg_surr_disc_get_grads", "sg_surr_disc_set_params",
     "sg_audit_decide", "sg_surr_save", "sg_surr_load", "sg_surr_get_params", "sg_surr_get_grads",
-    "sg_surr_set_params", "sg_surr_get_batch",
+    "sg_surr_set_params", "sg_surr_get_batch", "sg_surr_tensor",
 )
 
 
@@ -137,6 +137,7 @@ def load():
         "sg_surr_get_grads": [VP, I32, VP],
         "sg_surr_set_params": [VP, I32, VP],
         "sg_surr_get_batch": [VP, I32, VP, VP],
+        "sg_surr_tensor": [VP, I32, I32, I32, VP, P(C.c_int64)],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -546,6 +547,23 @@ def sg_surr_set_params(ctx, sid, params):
     if h.size != sg_surr_num_params(ctx, sid):
         raise ValueError("wrong parameter count")
     _check(load().sg_surr_set_params(ctx, int(sid), h.ctypes.data), "sg_surr_set_params")
+
+
+(SURR_T_ACT, SURR_T_GRAD, SURR_T_YHAT, SURR_T_TARGET, SURR_T_GY, SURR_T_MOM1, SURR_T_MOM2, SURR_T_DISC_ACT,
+ SURR_T_DISC_GRAD, SURR_T_DISC_LOGITS, SURR_T_DISC_GLOG, SURR_T_DISC_MOM1, SURR_T_DISC_MOM2, SURR_T_DSCAN) = range(14)
+SURR_TENSORS = ("X", "T1", "E0", "T2", "E1", "T3", "E2", "T4", "E3", "T5", "B4", "U3", "S3", "D3", "U2", "S2",
+                "D2", "U1", "S1", "D1", "U0", "S0", "D0", "A0")
+
+
+def sg_surr_tensor(ctx, sid, kind: int, index: int = 0) -> np.ndarray:
+    """Flat host copy of a tensor of the last training step (uint16 bf16 bits
+    for the activation kinds, float32 otherwise)."""
+    n = C.c_int64()
+    _check(load().sg_surr_tensor(ctx, int(sid), int(kind), int(index), None, C.byref(n)), "sg_surr_tensor")
+    bf = kind in (SURR_T_ACT, SURR_T_DISC_ACT, SURR_T_DSCAN)
+    h = np.zeros(int(n.value), dtype=np.uint16 if bf else np.float32)
+    _check(load().sg_surr_tensor(ctx, int(sid), int(kind), int(index), h.ctypes.data, C.byref(n)), "sg_surr_tensor")
+    return h
 
 
 def sg_surr_get_batch(ctx, sid, n, H, W):
