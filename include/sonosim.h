@@ -448,6 +448,17 @@ sg_status sg_surr_infer(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, const int3
                         int32_t n_audit, float psnr_min, float max_fail_frac, float* psnr_out,
                         int32_t* n_fallback);
 
+/* sg_surr_infer with BF16 frames: out_bf16 (device, n_envs x H x W bf16
+ * bits, caller-owned) receives bf16(round to nearest even) of the frames
+ * sg_surr_infer would write, network and fallback alike; the audit judges
+ * the FP32 frames (the bf16 rounding of values in [0, 1] adds at most 2^-9
+ * relative error, below -60 dB).  The library keeps an FP32 staging buffer
+ * of the frames.  Errors as sg_surr_infer. */
+sg_status sg_surr_infer_bf16(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, const int32_t* vol_ids,
+                             const sg_probe* probes, const double* poses, uint16_t* out_bf16,
+                             const int32_t* audit_envs, int32_t n_audit, float psnr_min, float max_fail_frac,
+                             float* psnr_out, int32_t* n_fallback);
+
 /* Decision rule of sg_surr_infer on host data (no device work): fallback[i]
  * (host, n_audit) = psnr[i] < psnr_min (NaN counts as failing); *whole = 1
  * if the failing fraction exceeds max_fail_frac. */

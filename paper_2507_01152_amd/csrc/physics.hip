@@ -501,7 +501,8 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         // order within the chunk and a compensated sum of the chunk totals, so
         // the integral's relative error stays near 9 u), shifted by one lane
         // for the exclusive prefix
-        const float tp = wave_scan_mul(act ? t : 1.f);
+        const uint64_t gmask = __builtin_amdgcn_ballot_w64(G);
+        const float tp = gmask ? wave_scan_mul(act ? t : 1.f) : 1.f;
         const float as = wave_scan_add(act ? tt.alpha : 0.f);
         const float t_ex = dpp_f<kWaveShr1>(1.f, tp);
         const float a_ex = dpp_f<kWaveShr1>(0.f, as);
@@ -516,7 +517,7 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
         }
 
         float cs = 1.f;
-        if (__builtin_amdgcn_ballot_w64(G)) {   // uniform: the wave-level Sobel reads neighbouring lanes
+        if (gmask) {   // uniform: the wave-level Sobel reads neighbouring lanes
             const float c = incidence_cos_wave(e, v, q, x, y0, lane, G, lab, y > 0 ? lab_pr : lab, lab_nr);
             if (G) cs = c;
         }
@@ -571,10 +572,13 @@ __device__ void ray_scanline(const PhysArgs& a, const EnvDev& e, const VolDev& v
     wave_sync_lds();
 }
 
+// Work items of the ray kernel: block b takes item b first (no atomic: the
+// blocks of a launch would otherwise all meet on the counter at once), then
+// items gridDim.x + the counter's successive values.
 __device__ __forceinline__ int next_item(int32_t* counter, int* s_item)
 {
     __syncthreads();
-    if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) *s_item = (int)gridDim.x + atomicAdd(counter, 1);
     __syncthreads();
     return *s_item;
 }
@@ -636,8 +640,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LAB &&
         for (int i = threadIdx.x; i < a.n_labels * a.n_labels; i += kThreads) s_pair[i] = a.pair_rt[i];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform: scalar per-scanline values
-    for (;;) {
-        const int item = next_item(&q->next_ray, &s_item);
+    for (int item = (int)blockIdx.x;; item = next_item(&q->next_ray, &s_item)) {
         if (item >= a.n_ray) break;
         const ItemRay it = a.ray_items[item];
         EnvDev e = a.envs[it.env];

@@ -79,6 +79,7 @@ struct Surrogate {
     DevBuf act[kNumT], gact[kNumT];
     DevBuf dpre, fine, parts, yhat, target, gy, loss, psnr, idx;
     DevBuf dscan;   // bf16 gradient at the depth map's output (the integral's backward), n x H x W x kScanC
+    DevBuf out32;   // FP32 frames of bf16 inference
     // CT-conditioned input: per-frame histograms and matching maps, the reference
     // (kCtBins int64 counts, then their inclusive cumulative counts) and its total
     bool ct = false;
@@ -914,13 +915,13 @@ extern "C" sg_status sg_audit_decide(int32_t n_audit, const float* psnr, float p
     return SG_OK;
 }
 
-extern "C" sg_status sg_surr_infer(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
-                                   const double* poses, float* out, const int32_t* audit_envs, int32_t n_audit,
-                                   float psnr_min, float max_fail_frac, float* psnr_out, int32_t* n_fallback)
+namespace sg {
+namespace {
+// audited inference into FP32 frames `out` (device, n x H x W); synchronises
+sg_status infer_impl(sg_ctx* c, Surrogate* s, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
+                     const double* poses, float* out, const int32_t* audit_envs, int32_t n_audit, float psnr_min,
+                     float max_fail_frac, float* psnr_out, int32_t* n_fallback)
 {
-    Surrogate* s = find_surr(c, id);
-    if (!s || !vol_ids || !probes || !poses || !out || !n_fallback)
-        return fail(SG_EINVAL, "sg_surr_infer: bad id or NULL");
     if (n < 1 || n_audit < 0 || n_audit > n || (n_audit > 0 && (!audit_envs || !psnr_out)))
         return fail(SG_EINVAL, "sg_surr_infer: bad sizes");
     std::vector<char> seen(n, 0);
@@ -985,6 +986,38 @@ extern "C" sg_status sg_surr_infer(sg_ctx* c, int32_t id, int32_t n, const int32
         }
         *n_fallback = nf;
     }
+    return check(hipStreamSynchronize(c->stream), "infer");
+}
+}  // namespace
+}  // namespace sg
+
+extern "C" sg_status sg_surr_infer(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
+                                   const double* poses, float* out, const int32_t* audit_envs, int32_t n_audit,
+                                   float psnr_min, float max_fail_frac, float* psnr_out, int32_t* n_fallback)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !vol_ids || !probes || !poses || !out || !n_fallback)
+        return fail(SG_EINVAL, "sg_surr_infer: bad id or NULL");
+    return infer_impl(c, s, n, vol_ids, probes, poses, out, audit_envs, n_audit, psnr_min, max_fail_frac, psnr_out,
+                      n_fallback);
+}
+
+extern "C" sg_status sg_surr_infer_bf16(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids,
+                                        const sg_probe* probes, const double* poses, uint16_t* out_bf16,
+                                        const int32_t* audit_envs, int32_t n_audit, float psnr_min,
+                                        float max_fail_frac, float* psnr_out, int32_t* n_fallback)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !vol_ids || !probes || !poses || !out_bf16 || !n_fallback)
+        return fail(SG_EINVAL, "sg_surr_infer_bf16: bad id or NULL");
+    if (n < 1) return fail(SG_EINVAL, "sg_surr_infer_bf16: bad sizes");
+    (void)hipSetDevice(c->device);
+    SG_TRY(check_frames(*s, n, probes));
+    const int64_t P = (int64_t)n * s->H * s->W;
+    SG_TRY(check(s->out32.ensure(sizeof(float) * (size_t)P), "FP32 frames"));
+    SG_TRY(infer_impl(c, s, n, vol_ids, probes, poses, (float*)s->out32.p, audit_envs, n_audit, psnr_min,
+                      max_fail_frac, psnr_out, n_fallback));
+    SG_TRY(check(mask_to_bf16((const float*)s->out32.p, nullptr, out_bf16, P, c->stream), "bf16 frames"));
     return check(hipStreamSynchronize(c->stream), "infer");
 }
 

@@ -30,7 +30,7 @@ SYMBOLS = (
     "sg_recon_reset", "sg_recon_destroy",
     "sg_conv_forward", "sg_conv_backward_data", "sg_conv_backward_weight", "sg_valu_probe", "sg_hbm_probe",
     "sg_surr_create", "sg_surr_create_ct", "sg_surr_set_ct_reference", "sg_surr_destroy", "sg_surr_num_params",
-    "sg_surr_train_step", "sg_surr_infer", "sg_surr_train_pairs", "sg_surr_gan_losses", "sg_surr_disc_num_params",
+    "sg_surr_train_step", "sg_surr_infer", "sg_surr_infer_bf16", "sg_surr_train_pairs", "sg_surr_gan_losses", "sg_surr_disc_num_params",
     "sg_surr_disc_get_params", "sg_surr_disc_get_grads", "sg_surr_disc_set_params",
     "sg_audit_decide", "sg_surr_save", "sg_surr_load", "sg_surr_get_params", "sg_surr_get_grads",
     "sg_surr_set_params", "sg_surr_get_batch", "sg_surr_tensor",
@@ -130,6 +130,7 @@ def load():
         "sg_surr_num_params": [VP, I32, P(C.c_int64)],
         "sg_surr_train_step": [VP, I32, I32, VP, VP, VP, C.c_float, P(C.c_float)],
         "sg_surr_infer": [VP, I32, I32, VP, VP, VP, VP, VP, I32, C.c_float, C.c_float, VP, P(I32)],
+        "sg_surr_infer_bf16": [VP, I32, I32, VP, VP, VP, VP, VP, I32, C.c_float, C.c_float, VP, P(I32)],
         "sg_audit_decide": [I32, VP, C.c_float, C.c_float, VP, P(I32)],
         "sg_surr_save": [VP, I32, C.c_char_p],
         "sg_surr_load": [VP, I32, C.c_char_p],
@@ -510,6 +511,26 @@ def sg_surr_infer(ctx, sid, vol_ids, probes, poses, out, audit_envs=(), psnr_min
                                 _out(out, "sg_surr_infer", 4, need, True),
                                 au.ctypes.data if len(au) else None, len(au), float(psnr_min), float(max_fail_frac),
                                 psnr.ctypes.data if len(au) else None, C.byref(nf)), "sg_surr_infer")
+    return psnr[:len(au)], int(nf.value)
+
+
+def sg_surr_infer_bf16(ctx, sid, vol_ids, probes, poses, out, audit_envs=(), psnr_min=30.0, max_fail_frac=0.25):
+    """sg_surr_infer with bf16 frames: out is a 2-byte device tensor (bfloat16
+    or int16 storage) of n x H x W elements."""
+    n = len(probes)
+    vids = np.ascontiguousarray(vol_ids, dtype=np.int32)
+    pa = probes_array(probes)
+    ps = np.ascontiguousarray(poses, dtype=np.float64).reshape(n, 12)
+    au = np.ascontiguousarray(audit_envs, dtype=np.int32)
+    if len(vids) != n:
+        raise ValueError("vol_ids and probes must have one entry per env")
+    need = sum(int(p.W) * int(p.H) for p in probes)
+    psnr = np.zeros(max(1, len(au)), dtype=np.float32)
+    nf = C.c_int32()
+    _check(load().sg_surr_infer_bf16(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data,
+                                     _out(out, "sg_surr_infer_bf16", 2, need), au.ctypes.data if len(au) else None,
+                                     len(au), float(psnr_min), float(max_fail_frac),
+                                     psnr.ctypes.data if len(au) else None, C.byref(nf)), "sg_surr_infer_bf16")
     return psnr[:len(au)], int(nf.value)
 
 

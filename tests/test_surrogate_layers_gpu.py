@@ -434,3 +434,31 @@ def test_discriminator_second_pass_and_adversarial_gradient(gan):
     assert np.array_equal(gan["gy"], want.astype(np.float64)), "adversarial gradient add"
     assert np.abs(gan["DG"][0][f][..., 4]).max() > 0
     print([round(v, 3) for v in worst])
+
+
+def test_inference_runs_the_checked_forward_and_bf16_frames(sess):
+    """sg_surr_infer's frames are clamp(yhat) of the forward the layer-local
+    checks above cover: bit for bit against a training step's forward (rate
+    0) on the same envs.  sg_surr_infer_bf16 writes bf16 of the same frames
+    bit for bit, with the same audit decisions, including physics fallback."""
+    from paper_2507_01152_amd import sonosim as sg
+    from test_surrogate_gpu import _pairs
+    n, h, w = 6, 64, 48
+    wl = _pairs(n, h, w, seed=19)
+    vids = sess.load(wl)
+    sid = sg.sg_surr_create(sess.ctx, h, w, seed=7)
+    sg.sg_surr_train_step(sess.ctx, sid, vids, wl.probes, wl.poses, 0.0)
+    yhat = sg.sg_surr_tensor(sess.ctx, sid, sg.SURR_T_YHAT).reshape(n, h, w)
+    out = torch.empty(n * h * w, dtype=torch.float32, device="cuda")
+    sg.sg_surr_infer(sess.ctx, sid, vids, wl.probes, wl.poses, out, [], 30.0)
+    net = out.cpu().numpy().reshape(n, h, w)
+    assert np.array_equal(net, np.clip(yhat, 0.0, 1.0))
+    ob = torch.empty(n * h * w, dtype=torch.int16, device="cuda")
+    for audit, thr in (([], 30.0), ([1, 4], -np.inf), ([0, 2, 5], np.inf)):
+        p32, nf32 = sg.sg_surr_infer(sess.ctx, sid, vids, wl.probes, wl.poses, out, audit, thr, 0.5)
+        p16, nf16 = sg.sg_surr_infer_bf16(sess.ctx, sid, vids, wl.probes, wl.poses, ob, audit, thr, 0.5)
+        assert nf16 == nf32 and np.array_equal(p16, p32)
+        want = so.f64_to_bf16_bits(out.cpu().numpy().astype(np.float64))
+        assert np.array_equal(ob.cpu().numpy().view(np.uint16), want)
+    assert nf32 == n   # the last case fell back to physics entirely
+    sg.sg_surr_destroy(sess.ctx, sid)
