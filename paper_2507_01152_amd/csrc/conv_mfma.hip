@@ -486,6 +486,273 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     }
 }
 
+// Direct 3x3 weight gradient (stride 1, pad 1) for few channels (CI in
+// {8, 16, 24, 32}, CO in {16, 32}): dW[co][r][s][ci] = sum over output pixels
+// p of dy[p][co] x[p + (r - 1, s - 1)][ci].  A block stages, per tile of
+// 8 x 32 output pixels, the 10 x 34 halo of x and the tile of dy once in LDS,
+// both transposed to channel planes (pixels contiguous; a thread packs two
+// neighbouring pixels per 4-byte LDS store), so the MFMA operands of one
+// output row are 32 consecutive pixels of a channel: A = dy (m = co), B = x
+// shifted by the tap's column (n = ci), built from one aligned 16-byte and
+// one 4-byte LDS read by byte alignment in registers.  A wave takes one 16-channel group of co and
+// 8 CO / 64 consecutive output rows with all nine taps (every offset a
+// compile-time constant, each staged x row read once per column shift for
+// all its output rows) and keeps its accumulators in registers across the
+// block's tiles; the next tile's chunks are loaded into
+// registers while the current one is multiplied.  Tiles are dealt out with a
+// static stride; at the end the four waves are summed in LDS in a fixed order
+// and the block writes one partial dW, which a fixed-order reduction sums.
+// UP: x is read upsampled x2 (fine pixel (h, w) is stored pixel (h/2, w/2)).
+constexpr int kWgH = 8, kWgW = 32;
+constexpr int kWgXR = kWgH + 2, kWgXC = kWgW + 2;   // staged halo rows and columns
+constexpr int kWgPitch = 40;                        // LDS row pitch (bf16)
+constexpr int kWgXPlane = kWgXR * kWgPitch + 8;     // 204 dwords per channel: banks 12 apart
+constexpr int kWgDPlane = kWgH * kWgPitch + 8;      // 164 dwords per channel: banks 4 apart
+
+template <int CI, int CO, bool UP>
+__global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_t* __restrict__ x,
+                                                       const uint16_t* __restrict__ dy, float* __restrict__ part)
+{
+    constexpr int NB = (CI + 15) / 16, CB = CO / 16, CIP = NB * 16;
+    constexpr int CI8 = CI / 8, CO8 = CO / 8;
+    constexpr int RW = kWgH * CB / 4;   // output rows per wave (the waves split co groups x row groups)
+    // items (8 channels of two neighbouring pixels) of one tile's operands, and each thread's share
+    constexpr int XN = kWgXR * (kWgXC / 2) * CI8, DN = kWgH * (kWgW / 2) * CO8;
+    constexpr int XI = (XN + 255) / 256, DI = (DN + 255) / 256;
+    constexpr int SX = CIP * kWgXPlane, SD = CO * kWgDPlane, NW = CO * 9 * CI;
+    static_assert(NW * 4 <= (SX + SD) * 2, "the cross-wave sum reuses the operand planes");
+    __shared__ __attribute__((aligned(16))) uint16_t smem[SX + SD];
+    uint16_t* sX = smem;
+    uint16_t* sD = smem + SX;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int Hin = UP ? 2 * g.H : g.H, Win = UP ? 2 * g.W : g.W;
+    const int tiles_x = (g.Wo + kWgW - 1) / kWgW, tiles_y = (g.Ho + kWgH - 1) / kWgH;
+    const int64_t per_img = (int64_t)tiles_x * tiles_y;
+    const int64_t total = (g.Kw / ((int64_t)g.Ho * g.Wo)) * per_img;   // Kw = N * Ho * Wo
+    if constexpr (CIP != CI) {   // channels CI .. CIP - 1 stay zero
+        for (int i = tid; i < (CIP - CI) * kWgXPlane; i += 256) sX[CI * kWgXPlane + i] = 0;
+    }
+    const int cbw = wave % CB, r0 = (wave / CB) * RW;   // the wave's co group and first output row
+    f32x4 acc[9][NB];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[t][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    u32x4 xv[XI][2], dv[DI][2];
+    auto load = [&](int64_t t) {
+        const int64_t n = t / per_img;
+        const int t_in = (int)(t - n * per_img);
+        const int ty = t_in / tiles_x, tx = t_in - ty * tiles_x;
+        const int ho0 = ty * kWgH, wo0 = tx * kWgW;
+#pragma unroll
+        for (int k = 0; k < XI; ++k) {
+            const int i = tid + 256 * k;
+            const int c8 = i % CI8, pr = i / CI8;
+            const int hy = pr / (kWgXC / 2), wx = 2 * (pr - hy * (kWgXC / 2));
+            const int hi = ho0 - 1 + hy;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int wi = wo0 - 1 + wx + e;
+                xv[k][e] = zero;
+                if (i < XN && hi >= 0 && wi >= 0 && hi < Hin && wi < Win) {
+                    const int hs = UP ? hi >> 1 : hi, ws = UP ? wi >> 1 : wi;
+                    xv[k][e] = *reinterpret_cast<const u32x4*>(x + ((n * g.H + hs) * g.W + ws) * CI + c8 * 8);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < DI; ++k) {
+            const int i = tid + 256 * k;
+            const int c8 = i % CO8, pr = i / CO8;
+            const int r = pr / (kWgW / 2), c = 2 * (pr - r * (kWgW / 2));
+            const int ho = ho0 + r;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int wo = wo0 + c + e;
+                dv[k][e] = zero;
+                if (i < DN && ho < g.Ho && wo < g.Wo)
+                    dv[k][e] = *reinterpret_cast<const u32x4*>(dy + ((n * g.Ho + ho) * g.Wo + wo) * CO + c8 * 8);
+            }
+        }
+    };
+    // transpose into the channel planes: channel 2j of the pair is the low halves of dword j,
+    // channel 2j + 1 the high halves (LDS positions do not depend on the tile)
+    auto store = [&]() {
+#pragma unroll
+        for (int k = 0; k < XI; ++k) {
+            const int i = tid + 256 * k;
+            if (i < XN) {
+                const int c8 = i % CI8, pr = i / CI8;
+                const int hy = pr / (kWgXC / 2), wx = 2 * (pr - hy * (kWgXC / 2));
+                uint32_t* d = reinterpret_cast<uint32_t*>(&sX[(c8 * 8) * kWgXPlane + hy * kWgPitch + wx]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    d[(2 * j) * (kWgXPlane / 2)] = __builtin_amdgcn_perm(xv[k][1][j], xv[k][0][j], 0x05040100u);
+                    d[(2 * j + 1) * (kWgXPlane / 2)] = __builtin_amdgcn_perm(xv[k][1][j], xv[k][0][j], 0x07060302u);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < DI; ++k) {
+            const int i = tid + 256 * k;
+            if (i < DN) {
+                const int c8 = i % CO8, pr = i / CO8;
+                const int r = pr / (kWgW / 2), c = 2 * (pr - r * (kWgW / 2));
+                uint32_t* d = reinterpret_cast<uint32_t*>(&sD[(c8 * 8) * kWgDPlane + r * kWgPitch + c]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    d[(2 * j) * (kWgDPlane / 2)] = __builtin_amdgcn_perm(dv[k][1][j], dv[k][0][j], 0x05040100u);
+                    d[(2 * j + 1) * (kWgDPlane / 2)] = __builtin_amdgcn_perm(dv[k][1][j], dv[k][0][j], 0x07060302u);
+                }
+            }
+        }
+    };
+    const uint16_t* pa = &sD[(cbw * 16 + lr) * kWgDPlane + r0 * kWgPitch + 8 * lk];   // A: output row r0
+    const uint16_t* pbx = &sX[lr * kWgXPlane + r0 * kWgPitch + 8 * lk];                // B: staged row r0
+    if ((int64_t)blockIdx.x < total) load(blockIdx.x);
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        __syncthreads();   // the previous tile's operands have been read
+        store();
+        __syncthreads();
+        if (t + gridDim.x < total) load(t + gridDim.x);
+        bf16x8 fa[RW];
+#pragma unroll
+        for (int rs = 0; rs < RW; ++rs) fa[rs] = *reinterpret_cast<const bf16x8*>(pa + rs * kWgPitch);
+        // staged row r0 + xr feeds output row r0 + rs through tap row xr - rs
+#pragma unroll
+        for (int xr = 0; xr < RW + 2; ++xr)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                // staged columns 8 lk .. 8 lk + 9 of the row: the operands of the three column shifts
+                const uint16_t* src = pbx + nb * 16 * kWgXPlane + xr * kWgPitch;
+                const u32x4 lo = *reinterpret_cast<const u32x4*>(src);
+                const uint32_t ex = *reinterpret_cast<const uint32_t*>(src + 8);
+                u32x4 sh[3];
+                sh[0] = lo;
+                sh[1] = u32x4{__builtin_amdgcn_alignbyte(lo[1], lo[0], 2u), __builtin_amdgcn_alignbyte(lo[2], lo[1], 2u),
+                              __builtin_amdgcn_alignbyte(lo[3], lo[2], 2u), __builtin_amdgcn_alignbyte(ex, lo[3], 2u)};
+                sh[2] = u32x4{lo[1], lo[2], lo[3], ex};
+#pragma unroll
+                for (int dc = 0; dc < 3; ++dc) {
+                    const bf16x8 fb = __builtin_bit_cast(bf16x8, sh[dc]);
+#pragma unroll
+                    for (int rs = 0; rs < RW; ++rs) {
+                        const int dr = xr - rs;
+                        if (dr < 0 || dr > 2) continue;
+                        acc[3 * dr + dc][nb] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[rs], fb, acc[3 * dr + dc][nb], 0, 0, 0);
+                    }
+                }
+            }
+    }
+    // sum over the row groups, in wave order, in the [Co][3][3][Ci] layout: lane (lr, lk),
+    // element q is co = 16 cbw + 4 lk + q, ci = 16 nb + lr (waves below CB start their co group)
+    float* red = reinterpret_cast<float*>(smem);
+    for (int w = 0; w < 4; ++w) {
+        __syncthreads();
+        if (wave == w) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int ci = nb * 16 + lr;
+                    if (ci >= CI) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float& r = red[((cbw * 16 + 4 * lk + q) * 9 + tap) * CI + ci];
+                        r = (w < CB ? 0.f : r) + acc[tap][nb][q];
+                    }
+                }
+        }
+    }
+    __syncthreads();
+    float* pb = part + (int64_t)blockIdx.x * NW;
+    for (int i = tid; i < NW; i += 256) pb[i] = red[i];
+}
+
+// Backward of the 1x1 map p = W x (W: KC x C, bf16) feeding the depth
+// integral: g[pixel][c] += sum_k dp[pixel][k] W[k][c] (written once, after
+// the FP32 sum over k) and the per-block partials of dW[k][c] = sum over
+// pixels of dp[pixel][k] x[pixel][c].  Four threads share a pixel, each
+// owning C / 4 channels, so a thread keeps KC x C / 4 accumulators; the
+// pixels are dealt out in a fixed order and reduced in a fixed order.
+constexpr int kProjBlocks = 1024;
+template <int KC, int C>
+__global__ __launch_bounds__(256) void k_proj_bwd(const uint16_t* __restrict__ dp, const uint16_t* __restrict__ x,
+                                                  const uint16_t* __restrict__ w, float* __restrict__ g, int64_t P,
+                                                  float* __restrict__ part)
+{
+    constexpr int CQ = C / 4;
+    static_assert(C % 16 == 0 && KC == 8, "four 4-channel groups per thread quad; 8 map channels");
+    __shared__ float red[4][KC * C];
+    const int q = threadIdx.x & 3, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float wr[KC][CQ], acc[KC][CQ];
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+#pragma unroll
+        for (int j = 0; j < CQ; ++j) {
+            wr[k][j] = bf2f(w[k * C + q * CQ + j]);
+            acc[k][j] = 0.f;
+        }
+    const int64_t stride = (int64_t)gridDim.x * 64;
+    for (int64_t p = (int64_t)blockIdx.x * 64 + (threadIdx.x >> 2); p < P; p += stride) {
+        const u32x4 dv = *reinterpret_cast<const u32x4*>(dp + p * KC);
+        float d[KC];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            d[2 * j] = __uint_as_float(dv[j] << 16);
+            d[2 * j + 1] = __uint_as_float(dv[j] & 0xFFFF0000u);
+        }
+        float xs[CQ];
+        const uint16_t* xp = x + p * C + q * CQ;
+#pragma unroll
+        for (int j = 0; j < CQ; j += 4) {
+            const uint2 v = *reinterpret_cast<const uint2*>(xp + j);
+            xs[j] = __uint_as_float(v.x << 16);
+            xs[j + 1] = __uint_as_float(v.x & 0xFFFF0000u);
+            xs[j + 2] = __uint_as_float(v.y << 16);
+            xs[j + 3] = __uint_as_float(v.y & 0xFFFF0000u);
+        }
+        float* gp = g + p * C + q * CQ;
+#pragma unroll
+        for (int j = 0; j < CQ; j += 4) {
+            float4 gv = *reinterpret_cast<const float4*>(gp + j);
+            float s[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float t = 0.f;
+#pragma unroll
+                for (int k = 0; k < KC; ++k) t = fmaf(d[k], wr[k][j + e], t);
+                s[e] = t;
+            }
+            gv.x += s[0];
+            gv.y += s[1];
+            gv.z += s[2];
+            gv.w += s[3];
+            *reinterpret_cast<float4*>(gp + j) = gv;
+        }
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+            for (int j = 0; j < CQ; ++j) acc[k][j] = fmaf(d[k], xs[j], acc[k][j]);
+    }
+    // the 16 threads of a wave with the same channel group, then the four waves
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+#pragma unroll
+        for (int j = 0; j < CQ; ++j) {
+            float v = acc[k][j];
+#pragma unroll
+            for (int m = 4; m < 64; m <<= 1) v += __shfl_xor(v, m);
+            if (lane < 4) red[wave][k * C + q * CQ + j] = v;
+        }
+    __syncthreads();
+    for (int i = threadIdx.x; i < KC * C; i += 256)
+        part[(int64_t)blockIdx.x * (KC * C) + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+}
+
 // ---------------------------------------------------------------------------
 // element-wise / reduction kernels
 
@@ -1180,6 +1447,54 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
     return launch_gemm<kDgrad, 128, 128, 2, 2>(g, a, 1, s);
 }
 
+bool wgrad_tile_supported(const ConvGeom& g)
+{
+    return g.kh == 3 && g.kw == 3 && g.stride == 1 && g.pad == 1 && (g.Co == 16 || g.Co == 32) &&
+           (g.C == 8 || g.C == 16 || g.C == 24 || g.C == 32) && g.Ho == (g.up ? 2 * g.H : g.H) &&
+           g.Wo == (g.up ? 2 * g.W : g.W);
+}
+
+int wgrad_tile_blocks(const ConvGeom& g)
+{
+    const int64_t tiles = (g.Kw / ((int64_t)g.Ho * g.Wo)) * (int64_t)((g.Ho + kWgH - 1) / kWgH) *
+                          ((g.Wo + kWgW - 1) / kWgW);
+    return (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), 512);
+}
+
+namespace {
+template <int CI, int CO, bool UP>
+hipError_t launch_wgrad_tile3(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, int blocks,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL((k_wgrad3x3_tile<CI, CO, UP>), dim3(blocks), dim3(256), 0, s, g, x, dy, part);
+    return hipGetLastError();
+}
+
+template <int CO, bool UP>
+hipError_t launch_wgrad_tile2(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, int blocks,
+                              hipStream_t s)
+{
+    switch (g.C) {
+    case 8: return launch_wgrad_tile3<8, CO, UP>(g, x, dy, part, blocks, s);
+    case 16: return launch_wgrad_tile3<16, CO, UP>(g, x, dy, part, blocks, s);
+    case 24: return launch_wgrad_tile3<24, CO, UP>(g, x, dy, part, blocks, s);
+    case 32: return launch_wgrad_tile3<32, CO, UP>(g, x, dy, part, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t wgrad_tile(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, int blocks,
+                      hipStream_t s)
+{
+    if (!wgrad_tile_supported(g) || blocks < 1) return hipErrorInvalidValue;
+    if (g.Co == 16)
+        return g.up ? launch_wgrad_tile2<16, true>(g, x, dy, part, blocks, s)
+                    : launch_wgrad_tile2<16, false>(g, x, dy, part, blocks, s);
+    return g.up ? launch_wgrad_tile2<32, true>(g, x, dy, part, blocks, s)
+                : launch_wgrad_tile2<32, false>(g, x, dy, part, blocks, s);
+}
+
 int wgrad_tile_m(int M) { return M <= 16 ? 16 : (M <= 32 ? 32 : 64); }
 
 hipError_t mask_colsum(const float* g, int ldg, const uint16_t* y, uint16_t* out, int64_t rows, int C, float* part,
@@ -1219,6 +1534,18 @@ hipError_t depth_scan_bwd(const float* g, int ld, int c_off, float* g_skip, uint
     if (e != hipSuccess) return e;
     return reduce_parts(part, kScanC, blocks, bias_grad, s);
 }
+
+hipError_t proj_bwd(const uint16_t* dp, const uint16_t* x, const uint16_t* w, float* g, int64_t P, int KC, int C,
+                    float* part, float* dw, hipStream_t s)
+{
+    if (KC != 8 || C != 16 || P < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_proj_bwd<8, 16>), dim3(kProjBlocks), dim3(256), 0, s, dp, x, w, g, P, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_parts(part, KC * C, kProjBlocks, dw, s);
+}
+
+int proj_bwd_blocks() { return kProjBlocks; }
 
 hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s)
 {

@@ -155,6 +155,16 @@ sg_status wgrad(sg_ctx* c, const ConvShape& sh, const uint16_t* x, const uint16_
                 DevBuf& parts)
 {
     ConvGeom g = geom_of(sh, 2);
+    const int cs_blocks0 = blocks_for(g.Kw, 512);
+    if (wgrad_tile_supported(g)) {   // few channels: direct tiled kernel, one partial per block
+        const int blocks = wgrad_tile_blocks(g);
+        const size_t need = sizeof(float) * std::max<int64_t>((int64_t)blocks * g.M * g.N, (int64_t)cs_blocks0 * sh.Co);
+        SG_TRY(check(parts.ensure(need), "wgrad workspace"));
+        SG_TRY(check(wgrad_tile(g, x, dy, (float*)parts.p, blocks, c->stream), "wgrad launch"));
+        SG_TRY(check(sum_parts((float*)parts.p, g.M * g.N, blocks, dw, c->stream), "wgrad reduce"));
+        if (db) SG_TRY(check(colsum_bf16(dy, g.Kw, sh.Co, (float*)parts.p, cs_blocks0, db, c->stream), "bias grad"));
+        return SG_OK;
+    }
     const int bm = wgrad_tile_m((int)g.M);
     const int64_t tiles = ((g.M + bm - 1) / bm) * ((g.N + 127) / 128);
     const int64_t nkt = (g.Kw + 31) / 32;
@@ -262,21 +272,6 @@ sg_status refresh_bf16(sg_ctx* c, Surrogate& s)
                  "bf16 head");
 }
 
-ConvShape proj_shape(const Surrogate& s, int n)
-{
-    ConvShape sh;
-    sh.N = n;
-    sh.H = s.H;
-    sh.W = s.W;
-    sh.C = kTC[kScanSrc];
-    sh.Co = kScanC;
-    sh.k = 1;
-    sh.stride = 1;
-    sh.pad = 0;
-    sh.up = 0;
-    return sh;
-}
-
 // train: also keep the pre-skip outputs of the decoder layers (ReLU masks of the backward)
 sg_status forward(sg_ctx* c, Surrogate& s, int n, bool train)
 {
@@ -355,11 +350,13 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
                                         (float*)s.gact[kScanSrc].p, (uint16_t*)s.dscan.p, (float*)s.parts.p,
                                         grad + s.proj_b, n, s.H, s.W, kScanScale, c->stream),
                          "depth integral backward"));
-            const ConvShape ps = proj_shape(s, n);
-            SG_TRY(wgrad(c, ps, (const uint16_t*)s.act[kScanSrc].p, (const uint16_t*)s.dscan.p, grad + s.proj_w,
-                         nullptr, s.parts));
-            SG_TRY(dgrad(c, ps, (const uint16_t*)s.dscan.p, (const uint16_t*)s.wt.p + s.proj_w,
-                         (float*)s.gact[kScanSrc].p, 1, s.fine));
+            SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)proj_bwd_blocks() * kScanC * kTC[kScanSrc]),
+                         "depth map workspace"));
+            SG_TRY(check(proj_bwd((const uint16_t*)s.dscan.p, (const uint16_t*)s.act[kScanSrc].p,
+                                  (const uint16_t*)s.wb.p + s.proj_w, (float*)s.gact[kScanSrc].p,
+                                  (int64_t)n * s.H * s.W, kScanC, kTC[kScanSrc], (float*)s.parts.p, grad + s.proj_w,
+                                  c->stream),
+                         "depth map backward"));
             written[kScanSrc] = true;
         }
         const int mb = blocks_for(rows * 16, 1024);

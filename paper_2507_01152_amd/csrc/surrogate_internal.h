@@ -117,6 +117,12 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
 // Co in {16, 32}); the fused head needs Co = 16
 bool conv_tile_supported(const ConvGeom& g);
 int wgrad_tile_m(int M);
+// direct 3x3 weight gradient (stride 1, pad 1, C in {8, 16, 24, 32}, Co in {16, 32}): each of `blocks`
+// blocks writes its partial dW (Co x 9 C floats, the [Co][3][3][C] layout) to part; sum_parts adds them
+bool wgrad_tile_supported(const ConvGeom& g);
+int wgrad_tile_blocks(const ConvGeom& g);
+hipError_t wgrad_tile(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, int blocks,
+                      hipStream_t s);
 hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s);
 // out = bf16(g * (y > 0 ? 1 : slope)) over [rows][C] (y null: out = bf16(g)) and bias_grad[c] = sum of
 // out's column c (C <= 256); g has ldg floats per row (0: C)
@@ -139,6 +145,12 @@ hipError_t depth_map_scan_fwd(const uint16_t* e, const uint16_t* w, const float*
 // its backward from g [N][H][W][ld] (FP32): dp (bf16, [N][H][W][8]), the channels [0, c_off) copied to
 // g_skip [N][H][W][c_off], bias_grad[8] = column sums of dp; part holds depth_scan_blocks(N, W) * 8 floats
 int depth_scan_blocks(int N, int W);
+// backward of the 1x1 map p = W x (KC = 8 map channels, C = 16 input channels, W bf16 [KC][C]) over
+// P pixels: g [P][C] += dp W (FP32) and dw [KC][C] = sum of dp^T x (FP32, fixed order); part holds
+// proj_bwd_blocks() * KC * C floats
+int proj_bwd_blocks();
+hipError_t proj_bwd(const uint16_t* dp, const uint16_t* x, const uint16_t* w, float* g, int64_t P, int KC, int C,
+                    float* part, float* dw, hipStream_t s);
 hipError_t depth_scan_bwd(const float* g, int ld, int c_off, float* g_skip, uint16_t* dp, float* part,
                           float* bias_grad, int N, int H, int W, float scale, hipStream_t s);
 hipError_t pool2x2_sum(const float* fine, float* coarse, int N, int H, int W, int C, int accumulate, hipStream_t s);

@@ -49,6 +49,9 @@ CONV_CASES = [
     # upsampled inputs staged as coarse tiles (6 x 18 stored pixels per 8 x 32 output tile)
     (2, 6, 20, 64, 32, 3, 1, 1, 1),      # 64 -> 32 (the U1 shape), ragged tiles in both directions
     (1, 13, 9, 32, 16, 3, 1, 1, 1),      # 32 -> 16 (the U0 shape), odd stored sizes
+    # more 8 x 32 tiles than the weight gradient's 512 blocks: blocks accumulate several tiles
+    (20, 48, 130, 8, 16, 3, 1, 1, 0),    # 600 tiles, ragged last column tile
+    (8, 40, 100, 32, 32, 3, 1, 1, 1),    # upsampled to 80 x 200: 560 tiles
 ]
 
 
