@@ -214,6 +214,42 @@ def ct_surrogate_leg(train_steps: int, n_envs: int = 256, batch: int = 32, audit
     }
 
 
+def train_step_timing(sess, sid_src, n: int = 64, steps: int = 40):
+    """Wall and device time per training step on a fixed batch of n pairs
+    (the last batch sid_src trained on), enqueued without loss readbacks, with
+    the step replayed from its HIP graph and kernel by kernel; a fresh network
+    of the same shape, so the trained one is left as it is."""
+    import torch
+
+    from paper_2507_01152_amd import sonosim as sg
+    from paper_2507_01152_amd.train_surrogate import FRAME_H, FRAME_W
+    xin, tgt = sg.sg_surr_get_batch(sess.ctx, sid_src, n, FRAME_H, FRAME_W)
+    xin = torch.from_numpy(xin.view("int16")).to(sess.device)
+    tgt = torch.from_numpy(tgt).to(sess.device)
+    res = {"pairs": n, "steps": steps}
+    for mode in ("graph", "eager"):
+        sid = sg.sg_surr_create(sess.ctx, FRAME_H, FRAME_W, seed=1)
+        sg.sg_surr_set_graph(sess.ctx, sid, mode == "graph")
+        for _ in range(3):   # eager sizing step, capture, one replay
+            sg.sg_surr_train_pairs(sess.ctx, sid, xin, tgt, 1e-3)
+        st = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        a.record(st)
+        for _ in range(steps):
+            sg.sg_surr_train_pairs_async(sess.ctx, sid, xin, tgt, 1e-3)
+        b.record(st)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / steps
+        first = sg.sg_surr_step_count(sess.ctx, sid) - steps + 1
+        last = sg.sg_surr_loss_history(sess.ctx, sid, first, steps)[-1, 0]
+        res[mode] = {"wall_ms": round(wall * 1e3, 3), "device_ms": round(a.elapsed_time(b) / steps, 3),
+                     "last_loss": round(float(last), 5)}
+        sg.sg_surr_destroy(sess.ctx, sid)
+    return res
+
+
 def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, psnr_min: float = 30.0):
     """Train the surrogate on physics pairs for a fixed budget, then time
     audited inference of n_envs 128 x 256 frames beside the physics path on
@@ -229,6 +265,7 @@ def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, ps
     sess, sid, _train_src, _ev, hist = train(train_steps, 64, 1e-3, seed=0, eval_every=max(1, train_steps),
                                              log=lambda s: None)
     train_s = time.perf_counter() - t0
+    step_timing = train_step_timing(sess, sid)
     test_src = PairSource(sess, 64, seed0=200000)     # held-out phantoms
     rng = np.random.default_rng(2024)
     vids, probes, poses = test_src.batch(n_envs, rng)
@@ -275,7 +312,7 @@ def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, ps
         "psnr_audit_pooled_db": round(float(-10 * np.log10(mse.mean())), 2),
         "frames_from_physics": int(n_fb),
         "train": {"steps": train_steps, "pairs": train_steps * 64, "seconds": round(train_s, 1),
-                  "last_eval": hist[-1] if hist else None},
+                  "last_eval": hist[-1] if hist else None, "step_timing": step_timing},
         "roofline": {"bound": "mfma", "kernel": "network forward (encode + 18 convs + depth integral + head)",
                      "achieved": round(flops / net_s / 1e12, 2), "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(flops / net_s / 1e12 / 2500.0, 4), "flops_per_launch": flops,

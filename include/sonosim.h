@@ -431,9 +431,36 @@ sg_status sg_surr_num_params(sg_ctx* ctx, int32_t surr_id, int64_t* n);
  * renders the targets, the encoder builds the inputs, then forward, L1 loss
  * (mean |Yhat - Y|), backward and one Adam step (beta1 0.9, beta2 0.999,
  * eps 1e-8) with learning rate lr.  Every probe must be H x W.  *loss (host)
- * receives the batch loss before the update (synchronises). */
+ * receives the batch loss before the update (synchronises).
+ * The step's network part (forward, losses, backward, Adam) is replayed from
+ * a HIP graph captured for the batch size: the first step of a new batch
+ * size runs kernel by kernel (sizing the workspaces), the next one is
+ * captured, later ones replay it; results are bit-identical either way.
+ * Adam's step count and bias corrections are kept on the device. */
 sg_status sg_surr_train_step(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, const int32_t* vol_ids,
                              const sg_probe* probes, const double* poses, float lr, float* loss);
+
+/* sg_surr_train_step without the loss readback: the step is enqueued on the
+ * context's stream and the call returns without waiting for the device
+ * (host staging of the physics render aside).  The losses of each step stay
+ * on the device for sg_surr_loss_history. */
+sg_status sg_surr_train_step_async(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, const int32_t* vol_ids,
+                                   const sg_probe* probes, const double* poses, float lr);
+
+/* Losses of training steps first_step .. first_step + count - 1 (steps are
+ * counted from 1 since creation or as restored by sg_surr_load): out (host,
+ * count x 3 floats) receives per step the L1 loss, L_D and L_adv (both 0
+ * without an adversarial term).  The device keeps the last 4096 steps.
+ * Waits for the context's stream; copies through a pinned buffer.  Errors:
+ * SG_ERANGE (steps not yet enqueued or older than the last 4096). */
+sg_status sg_surr_loss_history(sg_ctx* ctx, int32_t surr_id, int64_t first_step, int32_t count, float* out);
+
+/* Training steps done (enqueued) so far, *steps (host). */
+sg_status sg_surr_step_count(sg_ctx* ctx, int32_t surr_id, int64_t* steps);
+
+/* enable = 0: train kernel by kernel (no graph); 1 (default): replay the
+ * captured step.  For timing comparisons and tests; results are identical. */
+sg_status sg_surr_set_graph(sg_ctx* ctx, int32_t surr_id, int32_t enable);
 
 /* Inference with an audit (the physics path judges the network on a subset
  * and replaces failing frames).  out: device FP32, n_envs frames of H x W,
@@ -474,6 +501,11 @@ sg_status sg_audit_decide(int32_t n_audit, const float* psnr, float psnr_min, fl
  * Synchronises. */
 sg_status sg_surr_train_pairs(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, int32_t H, int32_t W,
                               const uint16_t* input, const float* target, float lr, float* loss);
+
+/* sg_surr_train_pairs without the loss readback (see sg_surr_train_step_async):
+ * the two copies and the step are enqueued; returns without waiting. */
+sg_status sg_surr_train_pairs_async(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, int32_t H, int32_t W,
+                                    const uint16_t* input, const float* target, float lr);
 
 /* Adversarial losses of the last training step (host): L_D before the
  * discriminator's update and L_adv (without its weight) after it.

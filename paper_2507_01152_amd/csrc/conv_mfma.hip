@@ -1239,10 +1239,48 @@ __global__ void k_l1(const float* yhat, const float* y, int64_t n, float scale, 
 
 // Adam on FP32 masters; writes the bf16 weights [Co][K] and their transpose
 // WT [Ci][taps][Co] (data gradient operand)
-__global__ void k_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
-                       float eps, float c1, float c2, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci)
+// Adam's per-step scalars on the device, so a captured step reads them at
+// replay: steps[0] (and steps[1], the discriminator's, when disc) count the
+// updates; coef = {lr, 1 - b1^t, 1 - b2^t, 1 - b1^td, 1 - b2^td}
+__global__ void k_adam_coef(int64_t* steps, float* coef, float lr, float b1, float b2, int disc)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t t = steps[0] + 1;
+    steps[0] = t;
+    coef[0] = lr;
+    coef[1] = 1.f - powf(b1, (float)t);
+    coef[2] = 1.f - powf(b2, (float)t);
+    if (disc) {
+        const int64_t td = steps[1] + 1;
+        steps[1] = td;
+        coef[3] = 1.f - powf(b1, (float)td);
+        coef[4] = 1.f - powf(b2, (float)td);
+    }
+}
+
+// Adam over a parameter vector made of segments (one launch for all of a
+// network's tensors): block b works on kAdamChunk elements of the segment
+// whose block0 <= b; a weight segment also refreshes its bf16 copy and,
+// with a transpose, the [Ci][taps][Co] copy of the data gradient
+constexpr int kAdamChunk = 2048;
+__global__ __launch_bounds__(256) void k_adam_multi(const AdamSeg* __restrict__ segs, int nseg, float* w, float* m,
+                                                    float* v, const float* __restrict__ g, uint16_t* wb, uint16_t* wt,
+                                                    const float* __restrict__ coef, int ci, float b1, float b2,
+                                                    float eps)
+{
+    __shared__ int s_seg;
+    if (threadIdx.x == 0) {
+        int k = 0;
+        while (k + 1 < nseg && segs[k + 1].block0 <= (int)blockIdx.x) ++k;
+        s_seg = k;
+    }
+    __syncthreads();
+    const AdamSeg sg = segs[s_seg];
+    const float lr = coef[0], c1 = coef[ci], c2 = coef[ci + 1];
+    const int64_t base = (int64_t)((int)blockIdx.x - sg.block0) * kAdamChunk;
+    const int64_t end = min(base + (int64_t)kAdamChunk, sg.n);
+    for (int64_t j = base + threadIdx.x; j < end; j += 256) {
+        const int64_t i = sg.off + j;
         const float gi = g[i];
         const float mi = b1 * m[i] + (1.f - b1) * gi;
         const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
@@ -1250,18 +1288,27 @@ __global__ void k_adam(float* w, float* m, float* v, const float* g, int64_t n, 
         v[i] = vi;
         const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
         w[i] = wi;
-        if (wb) {
-            const uint16_t b = f2bf(wi);
-            wb[i] = b;
-            if (wt) {
-                // i = (co * taps + t) * Ci + ci  ->  (ci * taps + t) * Co + co
-                const int ci = (int)(i % Ci);
-                const int64_t q = i / Ci;
-                const int t = (int)(q % taps);
-                const int co = (int)(q / taps);
-                wt[((int64_t)ci * taps + t) * Co + co] = b;
+        if (sg.bf16) {
+            const uint16_t bb = f2bf(wi);
+            wb[i] = bb;
+            if (sg.transpose) {
+                // j = (co * taps + t) * Ci + ci  ->  (ci * taps + t) * Co + co
+                const int cc = (int)(j % sg.Ci);
+                const int64_t q = j / sg.Ci;
+                const int t = (int)(q % sg.taps);
+                const int co = (int)(q / sg.taps);
+                wt[sg.off + ((int64_t)cc * sg.taps + t) * sg.Co + co] = bb;
             }
         }
+    }
+}
+
+// the step's losses into a ring of R steps: hist[(t - 1) mod R] = loss[0..2], t = steps[0]
+__global__ void k_loss_log(const float* loss, const int64_t* steps, float* hist, int R)
+{
+    if (threadIdx.x < 3 && blockIdx.x == 0) {
+        const int64_t slot = (steps[0] - 1) % R;
+        hist[slot * 3 + threadIdx.x] = loss[threadIdx.x];
     }
 }
 
@@ -1628,11 +1675,27 @@ hipError_t add_channel(float* gy, const float* dz, int ld, int c, int64_t P, hip
     return hipGetLastError();
 }
 
-hipError_t adam_step(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
-                     float c1, float c2, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci, hipStream_t s)
+int adam_blocks(int64_t n) { return (int)((n + kAdamChunk - 1) / kAdamChunk); }
+
+hipError_t adam_coef(int64_t* steps, float* coef, float lr, float b1, float b2, int disc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)grid_for(n)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, c1, c2,
-                       wb, wt, Co, taps, Ci);
+    hipLaunchKernelGGL(k_adam_coef, dim3(1), dim3(64), 0, s, steps, coef, lr, b1, b2, disc);
+    return hipGetLastError();
+}
+
+hipError_t adam_multi(const AdamSeg* segs, int nseg, int blocks, float* w, float* m, float* v, const float* g,
+                      uint16_t* wb, uint16_t* wt, const float* coef, int ci, float b1, float b2, float eps,
+                      hipStream_t s)
+{
+    if (nseg < 1 || blocks < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adam_multi, dim3((unsigned)blocks), dim3(256), 0, s, segs, nseg, w, m, v, g, wb, wt, coef, ci,
+                       b1, b2, eps);
+    return hipGetLastError();
+}
+
+hipError_t loss_log(const float* loss, const int64_t* steps, float* hist, int R, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loss_log, dim3(1), dim3(64), 0, s, loss, steps, hist, R);
     return hipGetLastError();
 }
 

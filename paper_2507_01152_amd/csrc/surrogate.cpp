@@ -48,6 +48,7 @@ constexpr int kHeadC = 16;
 constexpr int kScanSrc = E0, kScanDst = S0, kScanTmp = A0, kScanC = 8, kScanOff = 16;
 constexpr float kScanScale = 1.f / 16.f;
 constexpr float kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
+constexpr int kLossRing = 4096;   // training steps whose losses stay readable on the device
 
 // conditional patch discriminator of the adversarial term (pix2pix: the
 // discriminator judges patches of an image together with the network's
@@ -96,8 +97,27 @@ struct Surrogate {
     int64_t d_step = 0;
     int d_cap = 0;
     DevBuf d_act[kNumD], d_g[kNumD], d_logits, d_glog, d_dpre, d_bias_scratch;
-    float last_loss[3] = {0.f, 0.f, 0.f};   // L1, L_D, L_adv of the last training step
+    // training state on the device: update counters {generator, discriminator}, Adam's per-step
+    // scalars, the fused Adam's segment tables, and the losses of the last kLossRing steps
+    DevBuf steps, coef, segs, d_segs, hist;
+    int nseg = 0, adam_nb = 0, d_nseg = 0, d_adam_nb = 0;
+    // the captured training step (forward, losses, backward, Adam) for batches of g_n pairs, valid while
+    // the buffers it was captured on stay in place; warm_n: shape of the last eager step
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t g_exec = nullptr;
+    int g_n = 0, warm_n = 0, g_failed_n = 0;
+    std::vector<const void*> g_ptrs, warm_ptrs;
+    float* pinned = nullptr;   // host-pinned loss readback (3 * kLossRing floats)
+    ~Surrogate();
 };
+
+Surrogate::~Surrogate()
+{
+    if (g_exec) (void)hipGraphExecDestroy(g_exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (pinned) (void)hipHostFree(pinned);
+}
 
 void SurrogateDeleter::operator()(Surrogate* p) const { delete p; }
 
@@ -382,39 +402,37 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
     return SG_OK;
 }
 
-sg_status adam(sg_ctx* c, Surrogate& s, float lr)
+// Adam on every generator tensor, one launch (scalars from the device, counted by adam_coef)
+sg_status adam(sg_ctx* c, Surrogate& s)
 {
-    s.step += 1;
-    const float c1 = 1.f - std::pow(kBeta1, (float)s.step);
-    const float c2 = 1.f - std::pow(kBeta2, (float)s.step);
-    float* w = (float*)s.master.p;
-    float* m = (float*)s.mom1.p;
-    float* v = (float*)s.mom2.p;
-    const float* g = (const float*)s.grad.p;
-    for (int L = 0; L < kNumL; ++L) {
-        const LayerDef& d = kLayers[L];
-        const int64_t o = s.w_off[L];
-        SG_TRY(check(adam_step(w + o, m + o, v + o, g + o, s.w_n[L], lr, kBeta1, kBeta2, kEps, c1, c2,
-                               (uint16_t*)s.wb.p + o, (uint16_t*)s.wt.p + o, d.Co, 9, d.Ci, c->stream),
-                     "adam"));
-        const int64_t b = s.b_off[L];
-        SG_TRY(check(adam_step(w + b, m + b, v + b, g + b, d.Co, lr, kBeta1, kBeta2, kEps, c1, c2, nullptr, nullptr,
-                               1, 1, 1, c->stream),
-                     "adam bias"));
-    }
-    const int cs = kTC[kScanSrc];
-    SG_TRY(check(adam_step(w + s.proj_w, m + s.proj_w, v + s.proj_w, g + s.proj_w, kScanC * cs, lr, kBeta1, kBeta2, kEps,
-                           c1, c2, (uint16_t*)s.wb.p + s.proj_w, (uint16_t*)s.wt.p + s.proj_w, kScanC, 1, cs, c->stream),
-                 "adam depth map"));
-    SG_TRY(check(adam_step(w + s.proj_b, m + s.proj_b, v + s.proj_b, g + s.proj_b, kScanC, lr, kBeta1, kBeta2, kEps, c1,
-                           c2, nullptr, nullptr, 1, 1, 1, c->stream),
-                 "adam depth map bias"));
-    SG_TRY(check(adam_step(w + s.head_w, m + s.head_w, v + s.head_w, g + s.head_w, kHeadC, lr, kBeta1, kBeta2, kEps, c1,
-                           c2, (uint16_t*)s.wb.p + s.head_w, nullptr, 1, 1, kHeadC, c->stream),
-                 "adam head"));
-    return check(adam_step(w + s.head_b, m + s.head_b, v + s.head_b, g + s.head_b, 1, lr, kBeta1, kBeta2, kEps, c1, c2,
-                           nullptr, nullptr, 1, 1, 1, c->stream),
-                 "adam head bias");
+    return check(adam_multi((const AdamSeg*)s.segs.p, s.nseg, s.adam_nb, (float*)s.master.p, (float*)s.mom1.p,
+                            (float*)s.mom2.p, (const float*)s.grad.p, (uint16_t*)s.wb.p, (uint16_t*)s.wt.p,
+                            (const float*)s.coef.p, 1, kBeta1, kBeta2, kEps, c->stream),
+                 "adam");
+}
+
+// segment table of the fused Adam: off, n, layout and copies of each tensor, with each segment's first block
+void add_seg(std::vector<AdamSeg>& t, int& blocks, int64_t off, int64_t n, int Co, int taps, int Ci, bool bf16,
+             bool transpose)
+{
+    AdamSeg a;
+    a.off = off;
+    a.n = n;
+    a.block0 = blocks;
+    a.Co = Co;
+    a.taps = taps;
+    a.Ci = Ci;
+    a.bf16 = bf16 ? 1 : 0;
+    a.transpose = transpose ? 1 : 0;
+    t.push_back(a);
+    blocks += adam_blocks(n);
+}
+
+hipError_t upload_segs(DevBuf& d, const std::vector<AdamSeg>& t)
+{
+    hipError_t e = d.ensure(sizeof(AdamSeg) * t.size());
+    if (e == hipSuccess) e = hipMemcpy(d.p, t.data(), sizeof(AdamSeg) * t.size(), hipMemcpyHostToDevice);
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -498,6 +516,15 @@ sg_status disc_create(sg_ctx* c, Surrogate& s, uint64_t seed)
     if (e == hipSuccess) e = hipMemset(s.d_mom1.p, 0, bytes);
     if (e == hipSuccess) e = hipMemset(s.d_mom2.p, 0, bytes);
     if (e == hipSuccess) e = hipMemset(s.d_grad.p, 0, bytes);
+    std::vector<AdamSeg> t;
+    int nb = 0;
+    for (int L = 0; L < kNumD; ++L) {
+        add_seg(t, nb, s.dw_off[L], s.dw_n[L], kDisc[L].Co, 9, kDisc[L].Ci, true, true);
+        add_seg(t, nb, s.db_off[L], kDisc[L].Co, 1, 1, 1, false, false);
+    }
+    if (e == hipSuccess) e = upload_segs(s.d_segs, t);
+    s.d_nseg = (int)t.size();
+    s.d_adam_nb = nb;
     if (e != hipSuccess) return hip_fail(e, "discriminator allocation");
     return disc_refresh_bf16(c, s);
 }
@@ -555,32 +582,18 @@ sg_status disc_backward(sg_ctx* c, Surrogate& s, const uint16_t* z, int frames, 
     return SG_OK;
 }
 
-sg_status disc_adam(sg_ctx* c, Surrogate& s, float lr)
+sg_status disc_adam(sg_ctx* c, Surrogate& s)
 {
-    s.d_step += 1;
-    const float c1 = 1.f - std::pow(kBeta1, (float)s.d_step);
-    const float c2 = 1.f - std::pow(kBeta2, (float)s.d_step);
-    float* w = (float*)s.d_master.p;
-    float* m = (float*)s.d_mom1.p;
-    float* v = (float*)s.d_mom2.p;
-    const float* g = (const float*)s.d_grad.p;
-    for (int L = 0; L < kNumD; ++L) {
-        const int64_t o = s.dw_off[L], b = s.db_off[L];
-        SG_TRY(check(adam_step(w + o, m + o, v + o, g + o, s.dw_n[L], lr, kBeta1, kBeta2, kEps, c1, c2,
-                               (uint16_t*)s.d_wb.p + o, (uint16_t*)s.d_wt.p + o, kDisc[L].Co, 9, kDisc[L].Ci,
-                               c->stream),
-                     "discriminator adam"));
-        SG_TRY(check(adam_step(w + b, m + b, v + b, g + b, kDisc[L].Co, lr, kBeta1, kBeta2, kEps, c1, c2, nullptr,
-                               nullptr, 1, 1, 1, c->stream),
-                     "discriminator adam bias"));
-    }
-    return SG_OK;
+    return check(adam_multi((const AdamSeg*)s.d_segs.p, s.d_nseg, s.d_adam_nb, (float*)s.d_master.p,
+                            (float*)s.d_mom1.p, (float*)s.d_mom2.p, (const float*)s.d_grad.p, (uint16_t*)s.d_wb.p,
+                            (uint16_t*)s.d_wt.p, (const float*)s.coef.p, 3, kBeta1, kBeta2, kEps, c->stream),
+                 "discriminator adam");
 }
 
 // The adversarial part of one training step (pix2pix order), after the generator's forward and L1 loss:
 // discriminator step on (x, target) as real and (x, yhat) as fake, then the generator's adversarial
 // gradient through the updated discriminator, added into gy.  Losses: loss[1] = L_D, loss[2] = L_adv.
-sg_status adversarial_step(sg_ctx* c, Surrogate& s, int n, float lr)
+sg_status adversarial_step(sg_ctx* c, Surrogate& s, int n)
 {
     SG_TRY(disc_capacity(s, 3 * n));
     const int64_t P = (int64_t)n * s.H * s.W;
@@ -597,7 +610,7 @@ sg_status adversarial_step(sg_ctx* c, Surrogate& s, int n, float lr)
                             (float*)s.parts.p, bb, (float*)s.loss.p + 1, c->stream),
                  "discriminator loss"));
     SG_TRY(disc_backward(c, s, z, 2 * n, true, false, 0));
-    SG_TRY(disc_adam(c, s, lr));
+    SG_TRY(disc_adam(c, s));
     // second pass on the fake half through the updated discriminator, tensors at frames [2n, 3n)
     const uint16_t* zf = z + P * 8;
     const int off = 2 * n;
@@ -765,6 +778,26 @@ extern "C" sg_status sg_surr_create(sg_ctx* c, int32_t H, int32_t W, uint64_t se
     if (e == hipSuccess) e = hipMemset(s->mom1.p, 0, bytes);
     if (e == hipSuccess) e = hipMemset(s->mom2.p, 0, bytes);
     if (e == hipSuccess) e = hipMemset(s->grad.p, 0, bytes);
+    std::vector<AdamSeg> t;
+    int nb = 0;
+    for (int L = 0; L < kNumL; ++L) {
+        add_seg(t, nb, s->w_off[L], s->w_n[L], kLayers[L].Co, 9, kLayers[L].Ci, true, true);
+        add_seg(t, nb, s->b_off[L], kLayers[L].Co, 1, 1, 1, false, false);
+    }
+    add_seg(t, nb, s->proj_w, kScanC * kTC[kScanSrc], kScanC, 1, kTC[kScanSrc], true, true);
+    add_seg(t, nb, s->proj_b, kScanC, 1, 1, 1, false, false);
+    add_seg(t, nb, s->head_w, kHeadC, 1, 1, kHeadC, true, false);
+    add_seg(t, nb, s->head_b, 1, 1, 1, 1, false, false);
+    if (e == hipSuccess) e = upload_segs(s->segs, t);
+    s->nseg = (int)t.size();
+    s->adam_nb = nb;
+    if (e == hipSuccess) e = s->steps.ensure(sizeof(int64_t) * 2);
+    if (e == hipSuccess) e = hipMemset(s->steps.p, 0, sizeof(int64_t) * 2);
+    if (e == hipSuccess) e = s->coef.ensure(sizeof(float) * 8);
+    if (e == hipSuccess) e = hipMemset(s->coef.p, 0, sizeof(float) * 8);
+    if (e == hipSuccess) e = s->hist.ensure(sizeof(float) * 3 * kLossRing);
+    if (e == hipSuccess) e = hipMemset(s->hist.p, 0, sizeof(float) * 3 * kLossRing);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->pinned, sizeof(float) * 3 * kLossRing, hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e, "surrogate allocation");
     SG_TRY(refresh_bf16(c, *s));
     const int32_t sid = c->next_surr++;
@@ -842,8 +875,34 @@ extern "C" sg_status sg_surr_num_params(sg_ctx* c, int32_t id, int64_t* n)
 
 namespace sg {
 namespace {
-// forward, L1 (and adversarial) loss, backward and Adam on the batch in act[X] / target
-sg_status train_on_batch(sg_ctx* c, Surrogate& s, int32_t n, float lr, float* loss)
+// every buffer a training step touches: a captured step stays valid while none of them moved
+std::vector<const void*> buffer_ptrs(const Surrogate& s)
+{
+    std::vector<const void*> v = {s.master.p, s.mom1.p, s.mom2.p, s.grad.p, s.wb.p, s.wt.p, s.dpre.p, s.fine.p,
+                                  s.parts.p, s.yhat.p, s.target.p, s.gy.p, s.loss.p, s.dscan.p, s.steps.p, s.coef.p,
+                                  s.segs.p, s.hist.p, s.d_master.p, s.d_mom1.p, s.d_mom2.p, s.d_grad.p, s.d_wb.p,
+                                  s.d_wt.p, s.d_logits.p, s.d_glog.p, s.d_dpre.p, s.d_bias_scratch.p, s.d_segs.p};
+    for (int t = 0; t < kNumT; ++t) {
+        v.push_back(s.act[t].p);
+        v.push_back(s.gact[t].p);
+    }
+    for (int k = 0; k < kNumD; ++k) {
+        v.push_back(s.d_act[k].p);
+        v.push_back(s.d_g[k].p);
+    }
+    return v;
+}
+
+void drop_graph(Surrogate& s)
+{
+    if (s.g_exec) (void)hipGraphExecDestroy(s.g_exec);
+    s.g_exec = nullptr;
+    s.g_n = 0;
+    s.g_ptrs.clear();
+}
+
+// forward, L1 (and adversarial) loss, backward, Adam and the loss log on the batch in act[X] / target
+sg_status train_body(sg_ctx* c, Surrogate& s, int32_t n)
 {
     SG_TRY(forward(c, s, n, true));
     const int64_t P = (int64_t)n * s.H * s.W;
@@ -852,37 +911,83 @@ sg_status train_on_batch(sg_ctx* c, Surrogate& s, int32_t n, float lr, float* lo
     SG_TRY(check(l1_loss((const float*)s.yhat.p, (const float*)s.target.p, P, (float*)s.gy.p, (float*)s.parts.p, lb,
                          (float*)s.loss.p, c->stream),
                  "loss"));
-    if (s.adv_weight > 0.f) SG_TRY(adversarial_step(c, s, n, lr));
+    if (s.adv_weight > 0.f) SG_TRY(adversarial_step(c, s, n));
     SG_TRY(backward(c, s, n));
-    SG_TRY(adam(c, s, lr));
+    SG_TRY(adam(c, s));
+    return check(loss_log((const float*)s.loss.p, (const int64_t*)s.steps.p, (float*)s.hist.p, kLossRing, c->stream),
+                 "loss log");
+}
+
+// capture train_body on a private stream (the caller's stream may be the legacy default stream)
+hipError_t capture_step(sg_ctx* c, Surrogate& s, int32_t n)
+{
+    hipError_t e = hipSuccess;
+    if (!s.cap_stream) e = hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipStream_t user = c->stream;
+    c->stream = s.cap_stream;
+    const sg_status st = train_body(c, s, n);
+    c->stream = user;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s.cap_stream, &g);
+    if (st != SG_OK && e == hipSuccess) e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipGraphInstantiate(&s.g_exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) drop_graph(s);
+    return e;
+}
+
+// Enqueue one training step on the batch in act[X] / target: the Adam scalars (counted on the device)
+// first, then the step, replayed from its graph when one was captured for this shape and buffers.  A new
+// shape runs eagerly once (sizing the workspaces), then is captured.  Nothing waits for the device.
+sg_status enqueue_step(sg_ctx* c, Surrogate& s, int32_t n, float lr)
+{
+    const bool disc = s.adv_weight > 0.f;
+    SG_TRY(check(adam_coef((int64_t*)s.steps.p, (float*)s.coef.p, lr, kBeta1, kBeta2, disc ? 1 : 0, c->stream),
+                 "adam scalars"));
+    s.step += 1;
+    if (disc) s.d_step += 1;
     s.last_n = n;
-    hipError_t e = hipMemcpyAsync(s.last_loss, s.loss.p, sizeof(float) * 3, hipMemcpyDeviceToHost, c->stream);
+    if (!s.use_graph) return train_body(c, s, n);
+    const std::vector<const void*> ptrs = buffer_ptrs(s);
+    if (s.g_exec && s.g_n == n && ptrs == s.g_ptrs)
+        return check(hipGraphLaunch(s.g_exec, c->stream), "training graph launch");
+    drop_graph(s);
+    if (s.warm_n != n || ptrs != s.warm_ptrs || s.g_failed_n == n) {
+        SG_TRY(train_body(c, s, n));
+        s.warm_n = n;
+        s.warm_ptrs = buffer_ptrs(s);
+        return SG_OK;
+    }
+    hipError_t e = capture_step(c, s, n);
+    if (e == hipSuccess && buffer_ptrs(s) != ptrs) e = hipErrorInvalidValue;   // a workspace moved during capture
+    if (e != hipSuccess) {   // run this shape eagerly from now on
+        drop_graph(s);
+        (void)hipGetLastError();
+        s.g_failed_n = n;
+        return train_body(c, s, n);
+    }
+    s.g_n = n;
+    s.g_ptrs = ptrs;
+    return check(hipGraphLaunch(s.g_exec, c->stream), "training graph launch");
+}
+
+// wait for the stream, then the losses of the last step
+sg_status read_last_losses(sg_ctx* c, Surrogate& s, float* out3)
+{
+    hipError_t e = hipMemcpyAsync(s.pinned, s.loss.p, sizeof(float) * 3, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    *loss = s.last_loss[0];
-    return check(e, "loss readback");
-}
-}  // namespace
-}  // namespace sg
-
-extern "C" sg_status sg_surr_train_step(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids,
-                                        const sg_probe* probes, const double* poses, float lr, float* loss)
-{
-    Surrogate* s = find_surr(c, id);
-    if (!s || !vol_ids || !probes || !poses || !loss) return fail(SG_EINVAL, "sg_surr_train_step: bad id or NULL");
-    if (n < 1) return fail(SG_EINVAL, "sg_surr_train_step: n_envs must be >= 1");
-    if (!(lr >= 0.f) || !std::isfinite(lr)) return fail(SG_EINVAL, "sg_surr_train_step: bad learning rate");
-    (void)hipSetDevice(c->device);
-    SG_TRY(check_frames(*s, n, probes));
-    SG_TRY(ensure_capacity(*s, n, true));
-    SG_TRY(encode_and_render(c, *s, n, vol_ids, probes, poses, (float*)s->target.p));
-    return train_on_batch(c, *s, n, lr, loss);
+    if (e != hipSuccess) return hip_fail(e, "loss readback");
+    for (int j = 0; j < 3; ++j) out3[j] = s.pinned[j];
+    return SG_OK;
 }
 
-extern "C" sg_status sg_surr_train_pairs(sg_ctx* c, int32_t id, int32_t n, int32_t H, int32_t W,
-                                         const uint16_t* input, const float* target, float lr, float* loss)
+sg_status train_pairs_impl(sg_ctx* c, int32_t id, int32_t n, int32_t H, int32_t W, const uint16_t* input,
+                           const float* target, float lr, Surrogate** out)
 {
     Surrogate* s = find_surr(c, id);
-    if (!s || !input || !target || !loss) return fail(SG_EINVAL, "sg_surr_train_pairs: bad id or NULL");
+    if (!s || !input || !target) return fail(SG_EINVAL, "sg_surr_train_pairs: bad id or NULL");
     if (n < 1 || n > 65535) return fail(SG_EINVAL, "sg_surr_train_pairs: n in [1, 65535]");
     if (H != s->H || W != s->W)
         return fail(SG_EINVAL, "sg_surr_train_pairs: %dx%d frames, the surrogate takes %dx%d", W, H, s->W, s->H);
@@ -894,7 +999,108 @@ extern "C" sg_status sg_surr_train_pairs(sg_ctx* c, int32_t id, int32_t n, int32
                  "input copy"));
     SG_TRY(check(hipMemcpyAsync(s->target.p, target, sizeof(float) * P, hipMemcpyDeviceToDevice, c->stream),
                  "target copy"));
-    return train_on_batch(c, *s, n, lr, loss);
+    *out = s;
+    return enqueue_step(c, *s, n, lr);
+}
+
+sg_status train_step_impl(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids, const sg_probe* probes,
+                          const double* poses, float lr, Surrogate** out)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !vol_ids || !probes || !poses) return fail(SG_EINVAL, "sg_surr_train_step: bad id or NULL");
+    if (n < 1) return fail(SG_EINVAL, "sg_surr_train_step: n_envs must be >= 1");
+    if (!(lr >= 0.f) || !std::isfinite(lr)) return fail(SG_EINVAL, "sg_surr_train_step: bad learning rate");
+    (void)hipSetDevice(c->device);
+    SG_TRY(check_frames(*s, n, probes));
+    SG_TRY(ensure_capacity(*s, n, true));
+    SG_TRY(encode_and_render(c, *s, n, vol_ids, probes, poses, (float*)s->target.p));
+    *out = s;
+    return enqueue_step(c, *s, n, lr);
+}
+}  // namespace
+}  // namespace sg
+
+extern "C" sg_status sg_surr_train_step(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids,
+                                        const sg_probe* probes, const double* poses, float lr, float* loss)
+{
+    if (!loss) return fail(SG_EINVAL, "sg_surr_train_step: NULL loss");
+    Surrogate* s = nullptr;
+    SG_TRY(train_step_impl(c, id, n, vol_ids, probes, poses, lr, &s));
+    float l[3];
+    SG_TRY(read_last_losses(c, *s, l));
+    *loss = l[0];
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_train_step_async(sg_ctx* c, int32_t id, int32_t n, const int32_t* vol_ids,
+                                              const sg_probe* probes, const double* poses, float lr)
+{
+    Surrogate* s = nullptr;
+    return train_step_impl(c, id, n, vol_ids, probes, poses, lr, &s);
+}
+
+extern "C" sg_status sg_surr_train_pairs(sg_ctx* c, int32_t id, int32_t n, int32_t H, int32_t W,
+                                         const uint16_t* input, const float* target, float lr, float* loss)
+{
+    if (!loss) return fail(SG_EINVAL, "sg_surr_train_pairs: NULL loss");
+    Surrogate* s = nullptr;
+    SG_TRY(train_pairs_impl(c, id, n, H, W, input, target, lr, &s));
+    float l[3];
+    SG_TRY(read_last_losses(c, *s, l));
+    *loss = l[0];
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_train_pairs_async(sg_ctx* c, int32_t id, int32_t n, int32_t H, int32_t W,
+                                               const uint16_t* input, const float* target, float lr)
+{
+    Surrogate* s = nullptr;
+    return train_pairs_impl(c, id, n, H, W, input, target, lr, &s);
+}
+
+extern "C" sg_status sg_surr_loss_history(sg_ctx* c, int32_t id, int64_t first_step, int32_t count, float* out)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !out || count < 0) return fail(SG_EINVAL, "sg_surr_loss_history: bad id, NULL or negative count");
+    if (count == 0) return SG_OK;
+    const int64_t last = first_step + count - 1;
+    if (first_step < 1 || last > s->step || s->step - first_step >= kLossRing)
+        return fail(SG_ERANGE, "sg_surr_loss_history: steps %lld..%lld not held (done: %lld, ring of %d)",
+                    (long long)first_step, (long long)last, (long long)s->step, kLossRing);
+    (void)hipSetDevice(c->device);
+    const int64_t a = (first_step - 1) % kLossRing;
+    const int64_t n1 = std::min<int64_t>(count, kLossRing - a);   // up to the ring's end, then from its start
+    hipError_t e = hipMemcpyAsync(s->pinned, (const float*)s->hist.p + 3 * a, sizeof(float) * 3 * n1,
+                                  hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && count > n1)
+        e = hipMemcpyAsync(s->pinned + 3 * n1, s->hist.p, sizeof(float) * 3 * (count - n1), hipMemcpyDeviceToHost,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "loss history readback");
+    std::memcpy(out, s->pinned, sizeof(float) * 3 * count);
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_set_graph(sg_ctx* c, int32_t id, int32_t enable)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s) return fail(SG_EINVAL, "sg_surr_set_graph: bad id");
+    s->use_graph = enable != 0;
+    if (!s->use_graph) {
+        (void)hipSetDevice(c->device);
+        drop_graph(*s);
+        s->warm_n = 0;
+        s->g_failed_n = 0;
+    }
+    return SG_OK;
+}
+
+extern "C" sg_status sg_surr_step_count(sg_ctx* c, int32_t id, int64_t* steps)
+{
+    Surrogate* s = find_surr(c, id);
+    if (!s || !steps) return fail(SG_EINVAL, "sg_surr_step_count: bad id or NULL");
+    *steps = s->step;
+    return SG_OK;
 }
 
 extern "C" sg_status sg_audit_decide(int32_t n_audit, const float* psnr, float psnr_min, float max_fail_frac,
@@ -1113,6 +1319,9 @@ extern "C" sg_status sg_surr_load(sg_ctx* c, int32_t id, const char* path)
         s->d_step = dmeta[1];
         SG_TRY(disc_refresh_bf16(c, *s));
     }
+    const int64_t st[2] = {s->step, s->d_step};   // the device's update counters (Adam's bias correction)
+    e = hipMemcpy(s->steps.p, st, sizeof(st), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint upload");
     return refresh_bf16(c, *s);
 }
 
@@ -1218,8 +1427,11 @@ extern "C" sg_status sg_surr_gan_losses(sg_ctx* c, int32_t id, float* loss_d, fl
     if (!s || !loss_d || !loss_adv) return fail(SG_EINVAL, "sg_surr_gan_losses: bad id or NULL");
     if (s->adv_weight <= 0.f) return fail(SG_EINVAL, "sg_surr_gan_losses: the surrogate has no adversarial term");
     if (s->last_n < 1) return fail(SG_ESTATE, "sg_surr_gan_losses: no training step yet");
-    *loss_d = s->last_loss[1];
-    *loss_adv = s->last_loss[2];
+    (void)hipSetDevice(c->device);
+    float l[3];
+    SG_TRY(read_last_losses(c, *s, l));
+    *loss_d = l[1];
+    *loss_adv = l[2];
     return SG_OK;
 }
 

@@ -162,8 +162,21 @@ hipError_t head_bwd(const uint16_t* x, const uint16_t* w, const float* g, float*
                     int blocks, float* dwb, hipStream_t s);
 hipError_t l1_loss(const float* yhat, const float* y, int64_t n, float* grad, float* part, int blocks, float* loss,
                    hipStream_t s);
-hipError_t adam_step(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
-                     float c1, float c2, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci, hipStream_t s);
+// Adam: the step counters and per-step scalars live on the device (coef = {lr, c1, c2, disc c1, disc c2});
+// one launch updates all segments of a parameter vector (blocks = sum of adam_blocks(n) over segments)
+struct AdamSeg {
+    int64_t off, n;          // element range of the segment in the parameter vector
+    int32_t block0;          // first block of the segment
+    int32_t Co, taps, Ci;    // weight layout [Co][taps][Ci] (transpose only)
+    int32_t bf16, transpose; // refresh the bf16 copy; also its [Ci][taps][Co] transpose
+};
+int adam_blocks(int64_t n);
+hipError_t adam_coef(int64_t* steps, float* coef, float lr, float b1, float b2, int disc, hipStream_t s);
+hipError_t adam_multi(const AdamSeg* segs, int nseg, int blocks, float* w, float* m, float* v, const float* g,
+                      uint16_t* wb, uint16_t* wt, const float* coef, int ci, float b1, float b2, float eps,
+                      hipStream_t s);
+// losses of the step counted in steps[0] into a ring of R steps (3 floats each)
+hipError_t loss_log(const float* loss, const int64_t* steps, float* hist, int R, hipStream_t s);
 hipError_t weights_to_bf16(const float* w, int64_t n, uint16_t* wb, uint16_t* wt, int Co, int taps, int Ci,
                            hipStream_t s);
 hipError_t psnr_frames(const float* yhat, const float* y, int n_frames, int64_t frame, float* psnr, hipStream_t s);

@@ -33,7 +33,8 @@ SYMBOLS = (
     "sg_surr_train_step", "sg_surr_infer", "sg_surr_infer_bf16", "sg_surr_train_pairs", "sg_surr_gan_losses", "sg_surr_disc_num_params",
     "sg_surr_disc_get_params", "sg_surr_disc_get_grads", "sg_surr_disc_set_params",
     "sg_audit_decide", "sg_surr_save", "sg_surr_load", "sg_surr_get_params", "sg_surr_get_grads",
-    "sg_surr_set_params", "sg_surr_get_batch", "sg_surr_tensor",
+    "sg_surr_set_params", "sg_surr_get_batch", "sg_surr_tensor", "sg_surr_train_step_async",
+    "sg_surr_train_pairs_async", "sg_surr_loss_history", "sg_surr_step_count", "sg_surr_set_graph",
 )
 
 
@@ -122,6 +123,11 @@ def load():
         "sg_surr_set_ct_reference": [VP, I32, I32, VP, VP, VP, VP],
         "sg_surr_destroy": [VP, I32],
         "sg_surr_train_pairs": [VP, I32, I32, I32, I32, VP, VP, C.c_float, P(C.c_float)],
+        "sg_surr_train_pairs_async": [VP, I32, I32, I32, I32, VP, VP, C.c_float],
+        "sg_surr_train_step_async": [VP, I32, I32, VP, VP, VP, C.c_float],
+        "sg_surr_loss_history": [VP, I32, C.c_int64, I32, VP],
+        "sg_surr_step_count": [VP, I32, P(C.c_int64)],
+        "sg_surr_set_graph": [VP, I32, I32],
         "sg_surr_gan_losses": [VP, I32, P(C.c_float), P(C.c_float)],
         "sg_surr_disc_num_params": [VP, I32, P(C.c_int64)],
         "sg_surr_disc_get_params": [VP, I32, VP],
@@ -430,17 +436,47 @@ def sg_surr_set_ct_reference(ctx, sid, vol_ids, probes, poses) -> np.ndarray:
     return h
 
 
-def sg_surr_train_pairs(ctx, sid, inp, target, lr) -> float:
-    """inp: device bf16 bits (2-byte tensor, n x H x W x 8); target: device float32 (n x H x W)."""
+def _pairs_shape(inp, target):
     if target.dim() != 3 or target.element_size() != 4 or inp.element_size() != 2:
         raise ValueError("target must be float32 [n, H, W] and inp 2-byte [n, H, W, 8]")
     n, H, W = (int(v) for v in target.shape)
     if tuple(inp.shape) != (n, H, W, 8):
         raise ValueError(f"inp shape {tuple(inp.shape)} != {(n, H, W, 8)}")
+    return n, H, W
+
+
+def sg_surr_train_pairs(ctx, sid, inp, target, lr) -> float:
+    """inp: device bf16 bits (2-byte tensor, n x H x W x 8); target: device float32 (n x H x W)."""
+    n, H, W = _pairs_shape(inp, target)
     loss = C.c_float()
     _check(load().sg_surr_train_pairs(ctx, int(sid), n, H, W, _dptr(inp), _dptr(target), float(lr), C.byref(loss)),
            "sg_surr_train_pairs")
     return float(loss.value)
+
+
+def sg_surr_train_pairs_async(ctx, sid, inp, target, lr) -> None:
+    """As sg_surr_train_pairs, enqueued without reading the loss back."""
+    n, H, W = _pairs_shape(inp, target)
+    _check(load().sg_surr_train_pairs_async(ctx, int(sid), n, H, W, _dptr(inp), _dptr(target), float(lr)),
+           "sg_surr_train_pairs_async")
+
+
+def sg_surr_loss_history(ctx, sid, first_step, count) -> np.ndarray:
+    """(count, 3) float32: L1, L_D, L_adv of steps first_step .. first_step + count - 1 (1-based)."""
+    out = np.zeros((int(count), 3), dtype=np.float32)
+    _check(load().sg_surr_loss_history(ctx, int(sid), int(first_step), int(count), out.ctypes.data),
+           "sg_surr_loss_history")
+    return out
+
+
+def sg_surr_step_count(ctx, sid) -> int:
+    n = C.c_int64()
+    _check(load().sg_surr_step_count(ctx, int(sid), C.byref(n)), "sg_surr_step_count")
+    return int(n.value)
+
+
+def sg_surr_set_graph(ctx, sid, enable: bool) -> None:
+    _check(load().sg_surr_set_graph(ctx, int(sid), 1 if enable else 0), "sg_surr_set_graph")
 
 
 def sg_surr_gan_losses(ctx, sid):
@@ -493,6 +529,16 @@ def sg_surr_train_step(ctx, sid, vol_ids, probes, poses, lr) -> float:
     _check(load().sg_surr_train_step(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data,
                                      float(lr), C.byref(loss)), "sg_surr_train_step")
     return float(loss.value)
+
+
+def sg_surr_train_step_async(ctx, sid, vol_ids, probes, poses, lr) -> None:
+    """As sg_surr_train_step, enqueued without reading the loss back."""
+    n = len(probes)
+    vids = np.ascontiguousarray(vol_ids, dtype=np.int32)
+    pa = probes_array(probes)
+    ps = np.ascontiguousarray(poses, dtype=np.float64).reshape(n, 12)
+    _check(load().sg_surr_train_step_async(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p),
+                                           ps.ctypes.data, float(lr)), "sg_surr_train_step_async")
 
 
 def sg_surr_infer(ctx, sid, vol_ids, probes, poses, out, audit_envs=(), psnr_min=30.0, max_fail_frac=0.25):

@@ -92,12 +92,14 @@ def train_ct(steps: int, batch: int, lr: float, adv_weight: float = 0.01, seed: 
     sg.sg_surr_set_ct_reference(sess.ctx, sid, *src.batch(n_ref_frames, rng))
     t0 = time.time()
     last = None
+    first = sg.sg_surr_step_count(sess.ctx, sid)
     for step in range(1, steps + 1):
         cur = lr if step < 0.7 * steps else lr * 0.1
-        loss = sg.sg_surr_train_step(sess.ctx, sid, *src.batch(batch, rng), cur)
+        # enqueued without a loss readback; the losses are read from the device's log when reported
+        sg.sg_surr_train_step_async(sess.ctx, sid, *src.batch(batch, rng), cur)
         if step == steps or step % 200 == 0:
-            ld, la = sg.sg_surr_gan_losses(sess.ctx, sid) if adv_weight > 0 else (0.0, 0.0)
-            last = {"step": step, "l1": round(loss, 5), "loss_d": round(ld, 4), "loss_adv": round(la, 4),
+            l1, ld, la = (float(v) for v in sg.sg_surr_loss_history(sess.ctx, sid, first + step, 1)[0])
+            last = {"step": step, "l1": round(l1, 5), "loss_d": round(ld, 4), "loss_adv": round(la, 4),
                     "wall_s": round(time.time() - t0, 1)}
             log(json.dumps(last))
     return sess, sid, src, (time.time() - t0) / max(1, steps), last
@@ -128,12 +130,15 @@ def train(steps: int, batch: int, lr: float, seed: int = 0, eval_every: int = 50
     rng = np.random.default_rng(seed + 1)
     history = []
     t0 = time.time()
+    first = sg.sg_surr_step_count(sess.ctx, sid)
     for step in range(1, steps + 1):
         # constant rate, then a tenfold decay over the last 30 %
         cur = lr if step < 0.7 * steps else lr * 0.1
         vids, probes, poses = train_src.batch(batch, rng)
-        loss = sg.sg_surr_train_step(sess.ctx, sid, vids, probes, poses, cur)
+        # enqueued without a loss readback (the host draws the next batch meanwhile)
+        sg.sg_surr_train_step_async(sess.ctx, sid, vids, probes, poses, cur)
         if step % eval_every == 0 or step == steps:
+            loss = float(sg.sg_surr_loss_history(sess.ctx, sid, first + step, 1)[0, 0])
             mean_db, pooled_db = evaluate(sess, sid, eval_src)
             rec = {"step": step, "pairs": step * batch, "loss": round(loss, 5), "psnr_mean_db": round(mean_db, 2),
                    "psnr_pooled_db": round(pooled_db, 2), "wall_s": round(time.time() - t0, 1)}

@@ -239,6 +239,72 @@ def test_encoded_pairs_train_like_given_pairs(sess):
         sg.sg_surr_destroy(sess.ctx, s)
 
 
+def _random_pairs(n, H, W, seed):
+    rng = np.random.default_rng(seed)
+    xin = torch.from_numpy(so.bf16_round(rng.random((n, H, W, 8))).astype(np.float32)).to(torch.bfloat16)
+    tgt = torch.from_numpy(rng.random((n, H, W)).astype(np.float32))
+    return xin.view(torch.int16).cuda(), tgt.cuda()
+
+
+@pytest.mark.parametrize("adv", [0.0, 0.01])
+def test_graph_replay_matches_eager_bit_for_bit(sess, adv):
+    """The captured training step (first step of a batch size eager, the
+    second captured, later ones replayed) gives the same losses, parameters
+    and discriminator state as kernel-by-kernel steps, also when the batch
+    size changes and the graph is captured again."""
+    from paper_2507_01152_amd import sonosim as sg
+    H, W = 32, 48
+    mk = (lambda: sg.sg_surr_create_ct(sess.ctx, H, W, seed=4, adv_weight=adv)) if adv else \
+        (lambda: sg.sg_surr_create(sess.ctx, H, W, seed=4))
+    eager, graph = mk(), mk()
+    sg.sg_surr_set_graph(sess.ctx, eager, False)
+    batches = [_random_pairs(n, H, W, 60 + i) for i, n in enumerate([3, 3, 3, 3, 2, 2, 2, 3, 3])]
+    for xin, tgt in batches:
+        la = sg.sg_surr_train_pairs(sess.ctx, eager, xin, tgt, 2e-3)
+        lb = sg.sg_surr_train_pairs(sess.ctx, graph, xin, tgt, 2e-3)
+        assert la == lb
+        if adv:
+            assert sg.sg_surr_gan_losses(sess.ctx, eager) == sg.sg_surr_gan_losses(sess.ctx, graph)
+    assert np.array_equal(sg.sg_surr_get_params(sess.ctx, eager), sg.sg_surr_get_params(sess.ctx, graph))
+    if adv:
+        assert np.array_equal(sg.sg_surr_disc_get_params(sess.ctx, eager), sg.sg_surr_disc_get_params(sess.ctx, graph))
+    for s in (eager, graph):
+        sg.sg_surr_destroy(sess.ctx, s)
+
+
+def test_async_steps_keep_their_losses_on_the_device(sess):
+    """Enqueued steps (no readback) give the steps and losses of synchronous
+    ones; the device keeps the last 4096 steps' losses, read across the
+    ring's wrap."""
+    from paper_2507_01152_amd import sonosim as sg
+    H, W = 32, 48
+    a = sg.sg_surr_create(sess.ctx, H, W, seed=8)
+    b = sg.sg_surr_create(sess.ctx, H, W, seed=8)
+    batches = [_random_pairs(2, H, W, 70 + i) for i in range(6)]
+    want = [sg.sg_surr_train_pairs(sess.ctx, a, xin, tgt, 1e-3) for xin, tgt in batches]
+    for xin, tgt in batches:
+        sg.sg_surr_train_pairs_async(sess.ctx, b, xin, tgt, 1e-3)
+    assert sg.sg_surr_step_count(sess.ctx, b) == 6
+    hist = sg.sg_surr_loss_history(sess.ctx, b, 1, 6)
+    assert list(hist[:, 0]) == want and not hist[:, 1:].any()
+    assert np.array_equal(sg.sg_surr_get_params(sess.ctx, a), sg.sg_surr_get_params(sess.ctx, b))
+    with pytest.raises(sg.SonosimError):
+        sg.sg_surr_loss_history(sess.ctx, b, 6, 2)   # step 7 not enqueued
+    # across the ring's end: 4098 steps of a tiny network
+    c = sg.sg_surr_create(sess.ctx, 16, 16, seed=9)
+    xin, tgt = _random_pairs(1, 16, 16, 80)
+    for _ in range(4097):
+        sg.sg_surr_train_pairs_async(sess.ctx, c, xin, tgt, 1e-4)
+    last = sg.sg_surr_train_pairs(sess.ctx, c, xin, tgt, 1e-4)
+    h = sg.sg_surr_loss_history(sess.ctx, c, 4094, 5)
+    assert h[-1, 0] == last and np.all(np.isfinite(h))
+    assert np.array_equal(h[:, 0], sg.sg_surr_loss_history(sess.ctx, c, 4094, 5)[:, 0])
+    with pytest.raises(sg.SonosimError):
+        sg.sg_surr_loss_history(sess.ctx, c, 2, 1)   # older than the last 4096 steps
+    for s in (a, b, c):
+        sg.sg_surr_destroy(sess.ctx, s)
+
+
 def test_checkpoint_resume_is_bit_exact(sess, tmp_path):
     from paper_2507_01152_amd import sonosim as sg
     H, W = 32, 48
