@@ -19,17 +19,22 @@ _SRC = os.path.join(_HERE, "sonosim_oracle.c")
 _LIB = os.path.join(_HERE, "_build", "libsonooracle.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, -ffp-contract=off, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        os.makedirs(os.path.dirname(_LIB), exist_ok=True)
-        tmp = _LIB + ".tmp%d" % os.getpid()
+def build(force: bool = True, sanitize: bool = False, out: str | None = None) -> str:
+    """Compile the oracle with gcc (FP64, -ffp-contract=off, OpenMP).  sanitize: an
+    AddressSanitizer + UndefinedBehaviorSanitizer build (any finding aborts) into `out`,
+    for the sanitizer test; a process loads it through SONO_ORACLE_LIB."""
+    path = out or _LIB
+    if force or not os.path.exists(path):
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        extra = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                 "-fno-sanitize-recover=undefined"] if sanitize else []
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off", "-fPIC",
-             "-shared", "-o", tmp, _SRC, "-lm"]
+            ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off", "-fPIC"] + extra +
+            ["-shared", "-o", tmp, _SRC, "-lm"]
         )
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, path)
+    return path
 
 
 class _Volume(C.Structure):
@@ -67,9 +72,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = os.environ.get("SONO_ORACLE_LIB") or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             build(force=False)
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
         L.or_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_philox4x64_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_philox4x32_rounds.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
