@@ -161,7 +161,7 @@ def ray_traffic_bytes(key="traffic_bytes_per_launch"):
 
 
 def ct_surrogate_leg(train_steps: int, n_envs: int = 256, batch: int = 32, audit_frac: int = 16,
-                     psnr_min: float = 25.0):
+                     psnr_min: float = 30.0):
     """CT-conditioned surrogate with histogram matching and the adversarial
     term (weight 0.01): train on spine CT phantom pairs, then audited
     inference of n_envs frames on held-out phantoms beside physics."""
@@ -179,12 +179,13 @@ def ct_surrogate_leg(train_steps: int, n_envs: int = 256, batch: int = 32, audit
                                                                          replace=False)).astype(np.int32)
     HW = CT_FRAME_W * CT_FRAME_H
     out = torch.empty(n_envs * HW, dtype=torch.float32, device=sess.device)
-    sg.sg_surr_infer(sess.ctx, sid, vids, probes, poses, out, audit, psnr_min, 0.25)   # warm-up
+    out16 = torch.empty(n_envs * HW, dtype=torch.bfloat16, device=sess.device)   # the served BF16 frames
+    sg.sg_surr_infer_bf16(sess.ctx, sid, vids, probes, poses, out16, audit, psnr_min, 0.25)   # warm-up
     reps = 5
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(reps):
-        psnr, n_fb = sg.sg_surr_infer(sess.ctx, sid, vids, probes, poses, out, audit, psnr_min, 0.25)
+        psnr, n_fb = sg.sg_surr_infer_bf16(sess.ctx, sid, vids, probes, poses, out16, audit, psnr_min, 0.25)
     surr_s = (time.perf_counter() - t) / reps
     all_psnr, _ = sg.sg_surr_infer(sess.ctx, sid, vids[:64], probes[:64], poses[:64], out, list(range(64)),
                                    -np.inf, 1.0)
@@ -202,8 +203,9 @@ def ct_surrogate_leg(train_steps: int, n_envs: int = 256, batch: int = 32, audit
     sess.close()
     return {
         "workload": f"{n_envs} envs, {CT_FRAME_W}x{CT_FRAME_H} frames at 0.5 mm on held-out 256^3 spine CT "
-                    f"phantoms, histogram-matched CT input, 1/{audit_frac} seeded physics audit at PSNR >= "
-                    f"{psnr_min} dB",
+                    f"phantoms, histogram-matched CT input, BF16 frames, 1/{audit_frac} seeded physics audit at "
+                    f"PSNR >= {psnr_min} dB",
+        "frame_dtype": "bf16",
         "frames_per_s": round(n_envs / surr_s, 1),
         "physics_frames_per_s_same_workload": round(n_envs / phys_s, 1),
         "psnr_audit_mean_db": round(float(np.mean(psnr)), 2),
@@ -334,7 +336,7 @@ def main():
     ap.add_argument("--launch-shape", default=None, metavar="SPW,TX,CHUNKS",
                     help="fixed launch shape of the physics step instead of the autotuner's")
     ap.add_argument("--profile-launches", type=int, default=20)
-    ap.add_argument("--ct-surrogate-steps", type=int, default=1500,
+    ap.add_argument("--ct-surrogate-steps", type=int, default=4500,
                     help="training steps (batch 32) of the CT-conditioned surrogate with the adversarial term; "
                          "0 skips it")
     ap.add_argument("--surrogate-steps", type=int, default=3125,
