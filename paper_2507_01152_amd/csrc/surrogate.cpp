@@ -272,7 +272,6 @@ sg_status ensure_capacity(Surrogate& s, int n, bool grads)
         SG_TRY(check(s.gy.ensure(sizeof(float) * (int64_t)n * s.H * s.W), "output grad"));
         s.cap_grad = n;
     }
-    SG_TRY(check(s.loss.ensure(sizeof(float) * 8), "loss"));
     return SG_OK;
 }
 
@@ -795,6 +794,9 @@ extern "C" sg_status sg_surr_create(sg_ctx* c, int32_t H, int32_t W, uint64_t se
     if (e == hipSuccess) e = hipMemset(s->steps.p, 0, sizeof(int64_t) * 2);
     if (e == hipSuccess) e = s->coef.ensure(sizeof(float) * 8);
     if (e == hipSuccess) e = hipMemset(s->coef.p, 0, sizeof(float) * 8);
+    // losses {L1, L_D, L_adv}: without an adversarial term the last two stay 0
+    if (e == hipSuccess) e = s->loss.ensure(sizeof(float) * 8);
+    if (e == hipSuccess) e = hipMemset(s->loss.p, 0, sizeof(float) * 8);
     if (e == hipSuccess) e = s->hist.ensure(sizeof(float) * 3 * kLossRing);
     if (e == hipSuccess) e = hipMemset(s->hist.p, 0, sizeof(float) * 3 * kLossRing);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->pinned, sizeof(float) * 3 * kLossRing, hipHostMallocDefault);
