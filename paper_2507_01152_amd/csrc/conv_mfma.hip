@@ -486,9 +486,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     }
 }
 
-// Direct 3x3 weight gradient (stride 1, pad 1) for few channels (CI in
-// {8, 16, 24, 32}, CO in {16, 32}): dW[co][r][s][ci] = sum over output pixels
-// p of dy[p][co] x[p + (r - 1, s - 1)][ci].  A block stages, per tile of
+// Direct 3x3 weight gradient (stride 1, pad 1): dW[co][r][s][ci] = sum over
+// output pixels p of dy[p][co] x[p + (r - 1, s - 1)][ci], for a group of CI in
+// {8, 16, 24, 32} input and CO in {16, 32} output channels (block y: input
+// group, block z: output group, of a layer with g.C and g.Co channels).  A block stages, per tile of
 // 8 x 32 output pixels, the 10 x 34 halo of x and the tile of dy once in LDS,
 // both transposed to channel planes (pixels contiguous; a thread packs two
 // neighbouring pixels per 4-byte LDS store), so the MFMA operands of one
@@ -530,6 +531,8 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
     const int tiles_x = (g.Wo + kWgW - 1) / kWgW, tiles_y = (g.Ho + kWgH - 1) / kWgH;
     const int64_t per_img = (int64_t)tiles_x * tiles_y;
     const int64_t total = (g.Kw / ((int64_t)g.Ho * g.Wo)) * per_img;   // Kw = N * Ho * Wo
+    const uint16_t* xg = x + blockIdx.y * CI;    // the block's input channel group
+    const uint16_t* dyg = dy + blockIdx.z * CO;  // and output channel group
     if constexpr (CIP != CI) {   // channels CI .. CIP - 1 stay zero
         for (int i = tid; i < (CIP - CI) * kWgXPlane; i += 256) sX[CI * kWgXPlane + i] = 0;
     }
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
                 xv[k][e] = zero;
                 if (i < XN && hi >= 0 && wi >= 0 && hi < Hin && wi < Win) {
                     const int hs = UP ? hi >> 1 : hi, ws = UP ? wi >> 1 : wi;
-                    xv[k][e] = *reinterpret_cast<const u32x4*>(x + ((n * g.H + hs) * g.W + ws) * CI + c8 * 8);
+                    xv[k][e] = *reinterpret_cast<const u32x4*>(xg + ((n * g.H + hs) * g.W + ws) * g.C + c8 * 8);
                 }
             }
         }
@@ -573,7 +576,7 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
                 const int wo = wo0 + c + e;
                 dv[k][e] = zero;
                 if (i < DN && ho < g.Ho && wo < g.Wo)
-                    dv[k][e] = *reinterpret_cast<const u32x4*>(dy + ((n * g.Ho + ho) * g.Wo + wo) * CO + c8 * 8);
+                    dv[k][e] = *reinterpret_cast<const u32x4*>(dyg + ((n * g.Ho + ho) * g.Wo + wo) * g.Co + c8 * 8);
             }
         }
     };
@@ -668,8 +671,12 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
         }
     }
     __syncthreads();
-    float* pb = part + (int64_t)blockIdx.x * NW;
-    for (int i = tid; i < NW; i += 256) pb[i] = red[i];
+    // the blocks with this blockIdx.x (one per channel-group pair) fill partial blockIdx.x of the whole dW
+    float* pb = part + (int64_t)blockIdx.x * ((int64_t)g.Co * 9 * g.C);
+    for (int i = tid; i < NW; i += 256) {
+        const int ci = i % CI, q = i / CI;   // q = co * 9 + tap
+        pb[((int64_t)(blockIdx.z * CO) * 9 + q) * g.C + blockIdx.y * CI + ci] = red[i];
+    }
 }
 
 // Backward of the 1x1 map p = W x (W: KC x C, bf16) feeding the depth
@@ -1494,52 +1501,77 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
     return launch_gemm<kDgrad, 128, 128, 2, 2>(g, a, 1, s);
 }
 
-bool wgrad_tile_supported(const ConvGeom& g)
+bool wgrad_tile_plan(const ConvGeom& g, WgradTilePlan* plan)
 {
-    return g.kh == 3 && g.kw == 3 && g.stride == 1 && g.pad == 1 && (g.Co == 16 || g.Co == 32) &&
-           (g.C == 8 || g.C == 16 || g.C == 24 || g.C == 32) && g.Ho == (g.up ? 2 * g.H : g.H) &&
-           g.Wo == (g.up ? 2 * g.W : g.W);
+    if (!(g.kh == 3 && g.kw == 3 && g.stride == 1 && g.pad == 1 && g.Ho == (g.up ? 2 * g.H : g.H) &&
+          g.Wo == (g.up ? 2 * g.W : g.W)))
+        return false;
+    int ci_g = 0, co_g = 0;
+    if (g.C == 8 || g.C == 16 || g.C == 24 || g.C == 32)
+        ci_g = g.C;
+    else if (g.C % 32 == 0 && g.Wo >= 16)   // wider layers in groups of 32 (tiles at least half full)
+        ci_g = 32;
+    if (g.Co == 16 || g.Co == 32)
+        co_g = g.Co;
+    else if (g.Co % 32 == 0 && g.Wo >= 16)
+        co_g = 32;
+    if (!ci_g || !co_g) return false;
+    if (plan) {
+        const int gy = g.C / ci_g, gz = g.Co / co_g;
+        const int64_t tiles = (g.Kw / ((int64_t)g.Ho * g.Wo)) * (int64_t)((g.Ho + kWgH - 1) / kWgH) *
+                              ((g.Wo + kWgW - 1) / kWgW);
+        const int64_t want = std::max<int64_t>(1, (512 + gy * gz - 1) / (gy * gz));   // about 512 blocks
+        plan->gx = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), want);
+        plan->gy = gy;
+        plan->gz = gz;
+        plan->ci_g = ci_g;
+        plan->co_g = co_g;
+    }
+    return true;
 }
 
-int wgrad_tile_blocks(const ConvGeom& g)
+int64_t wgrad_tile_part_floats(const WgradTilePlan& p)
 {
-    const int64_t tiles = (g.Kw / ((int64_t)g.Ho * g.Wo)) * (int64_t)((g.Ho + kWgH - 1) / kWgH) *
-                          ((g.Wo + kWgW - 1) / kWgW);
-    return (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), 512);
+    return (int64_t)p.gx * p.gy * p.gz * p.co_g * 9 * p.ci_g;   // gx partials of the whole dW
 }
 
 namespace {
 template <int CI, int CO, bool UP>
-hipError_t launch_wgrad_tile3(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, int blocks,
-                              hipStream_t s)
+hipError_t launch_wgrad_tile3(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part,
+                              const WgradTilePlan& p, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_wgrad3x3_tile<CI, CO, UP>), dim3(blocks), dim3(256), 0, s, g, x, dy, part);
+    hipLaunchKernelGGL((k_wgrad3x3_tile<CI, CO, UP>), dim3(p.gx, p.gy, p.gz), dim3(256), 0, s, g, x, dy, part);
     return hipGetLastError();
 }
 
 template <int CO, bool UP>
-hipError_t launch_wgrad_tile2(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, int blocks,
-                              hipStream_t s)
+hipError_t launch_wgrad_tile2(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part,
+                              const WgradTilePlan& p, hipStream_t s)
 {
-    switch (g.C) {
-    case 8: return launch_wgrad_tile3<8, CO, UP>(g, x, dy, part, blocks, s);
-    case 16: return launch_wgrad_tile3<16, CO, UP>(g, x, dy, part, blocks, s);
-    case 24: return launch_wgrad_tile3<24, CO, UP>(g, x, dy, part, blocks, s);
-    case 32: return launch_wgrad_tile3<32, CO, UP>(g, x, dy, part, blocks, s);
+    switch (p.ci_g) {
+    case 8: return launch_wgrad_tile3<8, CO, UP>(g, x, dy, part, p, s);
+    case 16: return launch_wgrad_tile3<16, CO, UP>(g, x, dy, part, p, s);
+    case 24: return launch_wgrad_tile3<24, CO, UP>(g, x, dy, part, p, s);
+    case 32: return launch_wgrad_tile3<32, CO, UP>(g, x, dy, part, p, s);
     default: return hipErrorInvalidValue;
     }
 }
 }  // namespace
 
-hipError_t wgrad_tile(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, int blocks,
-                      hipStream_t s)
+hipError_t wgrad_tile(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, const WgradTilePlan& p,
+                      float* dw, hipStream_t s)
 {
-    if (!wgrad_tile_supported(g) || blocks < 1) return hipErrorInvalidValue;
-    if (g.Co == 16)
-        return g.up ? launch_wgrad_tile2<16, true>(g, x, dy, part, blocks, s)
-                    : launch_wgrad_tile2<16, false>(g, x, dy, part, blocks, s);
-    return g.up ? launch_wgrad_tile2<32, true>(g, x, dy, part, blocks, s)
-                : launch_wgrad_tile2<32, false>(g, x, dy, part, blocks, s);
+    WgradTilePlan q;
+    if (!wgrad_tile_plan(g, &q) || q.gx != p.gx || q.gy != p.gy || q.gz != p.gz || q.ci_g != p.ci_g ||
+        q.co_g != p.co_g)
+        return hipErrorInvalidValue;
+    hipError_t e;
+    if (p.co_g == 16)
+        e = g.up ? launch_wgrad_tile2<16, true>(g, x, dy, part, p, s) : launch_wgrad_tile2<16, false>(g, x, dy, part, p, s);
+    else
+        e = g.up ? launch_wgrad_tile2<32, true>(g, x, dy, part, p, s) : launch_wgrad_tile2<32, false>(g, x, dy, part, p, s);
+    if (e != hipSuccess) return e;
+    return reduce_parts(part, (int64_t)g.Co * 9 * g.C, p.gx, dw, s);
 }
 
 int wgrad_tile_m(int M) { return M <= 16 ? 16 : (M <= 32 ? 32 : 64); }

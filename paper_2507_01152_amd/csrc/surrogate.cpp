@@ -176,12 +176,11 @@ sg_status wgrad(sg_ctx* c, const ConvShape& sh, const uint16_t* x, const uint16_
 {
     ConvGeom g = geom_of(sh, 2);
     const int cs_blocks0 = blocks_for(g.Kw, 512);
-    if (wgrad_tile_supported(g)) {   // few channels: direct tiled kernel, one partial per block
-        const int blocks = wgrad_tile_blocks(g);
-        const size_t need = sizeof(float) * std::max<int64_t>((int64_t)blocks * g.M * g.N, (int64_t)cs_blocks0 * sh.Co);
+    WgradTilePlan tp;
+    if (wgrad_tile_plan(g, &tp)) {   // stride 1: direct tiled kernel, one partial per block and channel group
+        const size_t need = sizeof(float) * std::max<int64_t>(wgrad_tile_part_floats(tp), (int64_t)cs_blocks0 * sh.Co);
         SG_TRY(check(parts.ensure(need), "wgrad workspace"));
-        SG_TRY(check(wgrad_tile(g, x, dy, (float*)parts.p, blocks, c->stream), "wgrad launch"));
-        SG_TRY(check(sum_parts((float*)parts.p, g.M * g.N, blocks, dw, c->stream), "wgrad reduce"));
+        SG_TRY(check(wgrad_tile(g, x, dy, (float*)parts.p, tp, dw, c->stream), "wgrad launch"));
         if (db) SG_TRY(check(colsum_bf16(dy, g.Kw, sh.Co, (float*)parts.p, cs_blocks0, db, c->stream), "bias grad"));
         return SG_OK;
     }

@@ -117,12 +117,17 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
 // Co in {16, 32}); the fused head needs Co = 16
 bool conv_tile_supported(const ConvGeom& g);
 int wgrad_tile_m(int M);
-// direct 3x3 weight gradient (stride 1, pad 1, C in {8, 16, 24, 32}, Co in {16, 32}): each of `blocks`
-// blocks writes its partial dW (Co x 9 C floats, the [Co][3][3][C] layout) to part; sum_parts adds them
-bool wgrad_tile_supported(const ConvGeom& g);
-int wgrad_tile_blocks(const ConvGeom& g);
-hipError_t wgrad_tile(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, int blocks,
-                      hipStream_t s);
+// direct 3x3 weight gradient (stride 1, pad 1; C in {8, 16, 24, 32} or a multiple of 32, Co in {16, 32}
+// or a multiple of 32, the wider ones for outputs at least 16 wide): gx x gy x gz blocks (gy input and gz
+// output channel groups of ci_g and co_g) write gx partials of the whole dW (the gy x gz blocks with one
+// block x index fill one partial), then a fixed-order reduction over the gx partials writes dw ([Co][3][3][C])
+struct WgradTilePlan {
+    int gx = 0, gy = 0, gz = 0, ci_g = 0, co_g = 0;
+};
+bool wgrad_tile_plan(const ConvGeom& g, WgradTilePlan* plan);
+int64_t wgrad_tile_part_floats(const WgradTilePlan& p);
+hipError_t wgrad_tile(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part, const WgradTilePlan& p,
+                      float* dw, hipStream_t s);
 hipError_t mask_to_bf16(const float* g, const uint16_t* y, uint16_t* out, int64_t n, hipStream_t s);
 // out = bf16(g * (y > 0 ? 1 : slope)) over [rows][C] (y null: out = bf16(g)) and bias_grad[c] = sum of
 // out's column c (C <= 256); g has ldg floats per row (0: C)

@@ -52,6 +52,12 @@ CONV_CASES = [
     # more 8 x 32 tiles than the weight gradient's 512 blocks: blocks accumulate several tiles
     (20, 48, 130, 8, 16, 3, 1, 1, 0),    # 600 tiles, ragged last column tile
     (8, 40, 100, 32, 32, 3, 1, 1, 1),    # upsampled to 80 x 200: 560 tiles
+    # wider layers: the direct weight gradient in groups of 32 input x 32 output channels
+    (2, 10, 20, 64, 32, 3, 1, 1, 1),     # 2 input groups, upsampled (the U1 shape)
+    (1, 12, 33, 64, 64, 3, 1, 1, 0),     # 2 x 2 groups, ragged tiles
+    (1, 6, 10, 128, 64, 3, 1, 1, 1),     # 4 x 2 groups, upsampled to 12 x 20 (the U2 shape)
+    (2, 9, 16, 96, 96, 3, 1, 1, 0),      # 3 x 3 groups, outputs exactly 16 wide
+    (8, 48, 96, 64, 64, 3, 1, 1, 0),     # 144 tiles over 128 blocks per group pair
 ]
 
 
