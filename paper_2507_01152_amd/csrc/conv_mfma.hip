@@ -20,6 +20,7 @@
 // (decoder layers): the gather maps (h, w) to (h / 2, w / 2).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <cstring>
 
 #include "surrogate_internal.h"
 
@@ -332,9 +333,11 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
 // with one output can be fused.
 constexpr int kTileH = 8, kTileW = 32;
 
-template <int C, int CO, bool UP>
+template <int C, int CO, bool UP, bool DIL = false>
 __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
 {
+    // DIL: the input is dy of a stride-2 conv dilated by zeros: virtual pixel (h, w) is stored pixel
+    // (h / 2, w / 2) when both are even, else 0 (the data gradient of that conv as a stride-1 conv)
     // UP: the input is read upsampled x2; the tile stages the stored pixels it
     // covers (fine halo pixel (hy, wx) of the 10 x 34 window is stored pixel
     // ((hy + 1) / 2, (wx + 1) / 2) of a 6 x 18 window, tile origins being even)
@@ -373,6 +376,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
             const int hi = ho0 / 2 - 1 + hy, wi = wo0 / 2 - 1 + wx;
             if (hi >= 0 && wi >= 0 && hi < g.H && wi < g.W)
                 v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + hi) * g.W + wi) * C + c8 * 8);
+        } else if constexpr (DIL) {
+            const int hi = ho0 - 1 + hy, wi = wo0 - 1 + wx;
+            if (hi >= 0 && wi >= 0 && !(hi & 1) && !(wi & 1) && (hi >> 1) < g.H && (wi >> 1) < g.W)
+                v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + (hi >> 1)) * g.W + (wi >> 1)) * C + c8 * 8);
         } else {
             int hi = ho0 - 1 + hy, wi = wo0 - 1 + wx;
             if (hi >= 0 && wi >= 0 && hi < Hin && wi < Win) {
@@ -387,7 +394,9 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     }
     for (int i = tid; i < CO * NKS * 4; i += 256) {
         const int co = i / (NKS * 4), k8 = i - co * (NKS * 4);
-        const u32x4 v = k8 < K8 ? *reinterpret_cast<const u32x4*>(a.b + (int64_t)co * (9 * C) + k8 * 8) : zero;
+        // k8 = tap * C8 + channel group; mirrored: tap 8 - tap of the transposed copy
+        const int ks = a.flip ? (8 - k8 / C8) * C8 + k8 % C8 : k8;
+        const u32x4 v = k8 < K8 ? *reinterpret_cast<const u32x4*>(a.b + (int64_t)co * (9 * C) + ks * 8) : zero;
         *reinterpret_cast<u32x4*>(&sW[co * KP + k8 * 8]) = v;
     }
     __syncthreads();
@@ -436,7 +445,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
                 const float y = activate(acc[gi][j][q] + bias, a.relu);
                 sO[(rr * kTileW + cc) * CO + co] = f2bf(y);
                 const int ho = ho0 + rr, wo = wo0 + cc;
-                if (a.out_f32 && ho < g.Ho && wo < g.Wo) a.out_f32[((n * g.Ho + ho) * g.Wo + wo) * CO + co] = y;
+                if (a.out_f32 && ho < g.Ho && wo < g.Wo) {
+                    float* o = a.out_f32 + ((n * g.Ho + ho) * g.Wo + wo) * CO + co;
+                    *o = a.accumulate ? *o + y : y;
+                }
             }
         }
     }
@@ -1443,13 +1455,13 @@ bool conv_tile_supported(const ConvGeom& g)
     return shape && (g.C == 8 || g.C == 16 || g.C == 24 || g.C == 32 || (g.C == 64 && g.up && g.Co == 32));
 }
 
-template <int C, int CO, bool UP>
+template <int C, int CO, bool UP, bool DIL = false>
 hipError_t launch_tile(const ConvGeom& g, const ConvArgs& a, hipStream_t s)
 {
     const int64_t tiles = (int64_t)((g.Ho + kTileH - 1) / kTileH) * ((g.Wo + kTileW - 1) / kTileW);
     const int64_t blocks = tiles * (g.Kw / ((int64_t)g.Ho * g.Wo));   // Kw = N * Ho * Wo
     if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_conv3x3_tile<C, CO, UP>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
+    hipLaunchKernelGGL((k_conv3x3_tile<C, CO, UP, DIL>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
     return hipGetLastError();
 }
 
@@ -1473,6 +1485,56 @@ hipError_t launch_tile_co(const ConvGeom& g, const ConvArgs& a, hipStream_t s)
     case 24: return launch_tile<24, CO, false>(g, a, s);
     default: return launch_tile<32, CO, false>(g, a, s);
     }
+}
+
+bool dgrad_tile_supported(const ConvGeom& g)
+{
+    const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
+    const bool geom = g.kh == 3 && g.kw == 3 && g.pad == 1 &&
+                      ((g.stride == 1 && g.Ho == Hin && g.Wo == Win) ||
+                       (g.stride == 2 && !g.up && Hin == 2 * g.Ho && Win == 2 * g.Wo));
+    // the forward tile conv's channels: dy's Co in, the layer's C out
+    return geom && (g.Co == 8 || g.Co == 16 || g.Co == 24 || g.Co == 32) && (g.C == 16 || g.C == 32);
+}
+
+namespace {
+template <int CO, bool DIL>
+hipError_t launch_dgrad_tile(const ConvGeom& f, const ConvArgs& a, hipStream_t s)
+{
+    switch (f.C) {
+    case 8: return launch_tile<8, CO, false, DIL>(f, a, s);
+    case 16: return launch_tile<16, CO, false, DIL>(f, a, s);
+    case 24: return launch_tile<24, CO, false, DIL>(f, a, s);
+    default: return launch_tile<32, CO, false, DIL>(f, a, s);
+    }
+}
+}  // namespace
+
+hipError_t dgrad_tile(const ConvGeom& g, const uint16_t* dy, const uint16_t* wt, float* dx, int accumulate,
+                      hipStream_t s)
+{
+    if (!dgrad_tile_supported(g)) return hipErrorInvalidValue;
+    const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
+    ConvGeom f = g;   // forward conv: dy (Ho x Wo, Co channels) -> dx (Hin x Win, C channels)
+    f.C = g.Co;
+    f.Co = g.C;
+    f.H = g.Ho;
+    f.W = g.Wo;
+    f.Ho = Hin;
+    f.Wo = Win;
+    f.stride = 1;
+    f.up = 0;
+    f.Kw = (g.Kw / ((int64_t)g.Ho * g.Wo)) * Hin * Win;   // N * Hin * Win
+    ConvArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.a = dy;
+    a.b = wt;
+    a.flip = 1;
+    a.out_f32 = dx;
+    a.accumulate = accumulate;
+    const bool dil = g.stride == 2;
+    if (f.Co == 16) return dil ? launch_dgrad_tile<16, true>(f, a, s) : launch_dgrad_tile<16, false>(f, a, s);
+    return dil ? launch_dgrad_tile<32, true>(f, a, s) : launch_dgrad_tile<32, false>(f, a, s);
 }
 
 hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s)

@@ -63,6 +63,9 @@ struct ConvArgs {
     // [pixel][extra_c] (extra_c multiple of 8, Co + extra_c <= ld_out2), so out2 is written whole
     const uint16_t* extra;
     int32_t extra_c;
+    // tiled 3x3 path only: b is the transposed copy [C][9][Co] of a layer's weights and the taps are
+    // read mirrored (the data gradient as a forward conv of dy)
+    int32_t flip;
 };
 
 // convolution shape of one layer (per batch)
@@ -116,6 +119,12 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
 // forward shapes served by the LDS-tiled direct 3x3 kernel (stride 1, pad 1, C in {8, 16, 24, 32},
 // Co in {16, 32}); the fused head needs Co = 16
 bool conv_tile_supported(const ConvGeom& g);
+// data gradient of a 3x3 pad-1 conv (g: the layer's mode-1 geometry; stride 1, or stride 2 with even input
+// sizes) as a forward tiled conv of dy with mirrored taps, over dy dilated by zeros for stride 2: dx
+// [N][Hin][Win][C] FP32 (the fine-resolution gradient of an upsampled layer), written or accumulated
+bool dgrad_tile_supported(const ConvGeom& g);
+hipError_t dgrad_tile(const ConvGeom& g, const uint16_t* dy, const uint16_t* wt, float* dx, int accumulate,
+                      hipStream_t s);
 int wgrad_tile_m(int M);
 // direct 3x3 weight gradient (stride 1, pad 1; C in {8, 16, 24, 32} or a multiple of 32, Co in {16, 32}
 // or a multiple of 32, the wider ones for outputs at least 16 wide): gx x gy x gz blocks (gy input and gz

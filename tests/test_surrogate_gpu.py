@@ -58,6 +58,10 @@ CONV_CASES = [
     (1, 6, 10, 128, 64, 3, 1, 1, 1),     # 4 x 2 groups, upsampled to 12 x 20 (the U2 shape)
     (2, 9, 16, 96, 96, 3, 1, 1, 0),      # 3 x 3 groups, outputs exactly 16 wide
     (8, 48, 96, 64, 64, 3, 1, 1, 0),     # 144 tiles over 128 blocks per group pair
+    # stride 2 with even input sizes: the data gradient as a tiled conv over dy dilated by zeros
+    (2, 16, 40, 16, 32, 3, 2, 1, 0),     # the T2 shape
+    (1, 22, 70, 16, 32, 3, 2, 1, 0),     # ragged tiles of the 22 x 70 input gradient
+    (1, 12, 36, 32, 16, 3, 2, 1, 0),     # 32 input channels, 16 output
 ]
 
 
