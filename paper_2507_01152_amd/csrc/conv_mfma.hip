@@ -1111,6 +1111,30 @@ __global__ __launch_bounds__(256) void k_sum_parts_grouped(const float* part, in
     }
 }
 
+// Several reductions of per-block partials in one launch: block b computes output i of the segment
+// holding it, out[out_off + i] = sum over z < splits of part[part_off + z n + i], added as
+// k_sum_parts_grouped adds one output (thread t sums z = t, t + 256, ... in order, then the 256
+// thread sums in order), so the results equal separate reduce_parts calls
+__global__ __launch_bounds__(256) void k_reduce_segments(const float* __restrict__ part, float* __restrict__ out,
+                                                         ReduceSegs t)
+{
+    __shared__ float red[256];
+    int k = 0;
+    while (k + 1 < t.count && t.s[k + 1].first <= (int)blockIdx.x) ++k;
+    const ReduceSeg sg = t.s[k];
+    const int64_t i = (int64_t)blockIdx.x - sg.first;
+    const float* p = part + sg.part_off + i;
+    float v = 0.f;
+    for (int z = threadIdx.x; z < sg.splits; z += 256) v += p[(int64_t)z * sg.n];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float a = 0.f;
+        for (int j = 0; j < 256; ++j) a += red[j];
+        out[sg.out_off + i] = a;
+    }
+}
+
 // 1x1 head with one output channel: y[p] = sum_c w[c] x[p][c] + b (C = 16)
 __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t* x, const uint16_t* w, const float* b, float* y,
                                                   int64_t P, int C)
@@ -1646,8 +1670,16 @@ hipError_t mask_colsum(const float* g, int ldg, const uint16_t* y, uint16_t* out
     hipLaunchKernelGGL(k_mask_colsum, dim3(blocks), dim3(256), 0, s, g, ldg ? ldg : C, nullptr, y, out, rows, C, per,
                        part, slope);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !bias_grad) return e;
     return reduce_parts(part, C, blocks, bias_grad, s);
+}
+
+hipError_t reduce_segments(const float* part, float* out, const ReduceSegs& t, hipStream_t s)
+{
+    if (t.count < 1 || t.count > kMaxReduceSegs) return hipErrorInvalidValue;
+    const ReduceSeg& last = t.s[t.count - 1];
+    hipLaunchKernelGGL(k_reduce_segments, dim3((unsigned)(last.first + last.n)), dim3(256), 0, s, part, out, t);
+    return hipGetLastError();
 }
 
 int depth_scan_blocks(int N, int W)

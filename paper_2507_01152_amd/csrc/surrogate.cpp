@@ -79,6 +79,7 @@ struct Surrogate {
     int cap = 0, cap_grad = 0, last_n = 0;
     DevBuf act[kNumT], gact[kNumT];
     DevBuf dpre, fine, parts, yhat, target, gy, loss, psnr, idx;
+    DevBuf bias_parts;   // per-block bias-gradient partials of every layer of a backward pass, reduced at its end
     DevBuf dscan;   // bf16 gradient at the depth map's output (the integral's backward), n x H x W x kScanC
     DevBuf out32;   // FP32 frames of bf16 inference
     // CT-conditioned input: per-frame histograms and matching maps, the reference
@@ -130,6 +131,14 @@ Surrogate* find_surr(sg_ctx* c, int32_t id)
     if (!c) return nullptr;
     auto it = c->surrogates.find(id);
     return it == c->surrogates.end() ? nullptr : it->second.get();
+}
+
+// output channels of all generator layers (the bias-gradient outputs of a backward pass)
+int bias_count()
+{
+    int n = 0;
+    for (int L = 0; L < kNumL; ++L) n += kLayers[L].Co;
+    return n;
 }
 
 ConvShape layer_shape(const Surrogate& s, int L, int n)
@@ -362,6 +371,12 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
                           (float*)s.gact[D0].p, P, kHeadC, (float*)s.parts.p, hb, grad + s.head_w, c->stream),
                  "head backward"));
     written[D0] = true;
+    static_assert(kNumL <= kMaxReduceSegs, "one bias segment per layer");
+    ReduceSegs bseg;
+    bseg.count = 0;
+    int64_t boff = 0;
+    int bfirst = 0;
+    SG_TRY(check(s.bias_parts.ensure(sizeof(float) * 1024 * (size_t)bias_count()), "bias partials"));
     for (int L = kNumL - 1; L >= 0; --L) {
         const LayerDef& d = kLayers[L];
         const ConvShape sh = layer_shape(s, L, n);
@@ -386,11 +401,20 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
                          "depth map backward"));
             written[kScanSrc] = true;
         }
+        // ReLU mask; the bias gradient's per-block partials are reduced with the other layers' after the loop
         const int mb = blocks_for(rows * 16, 1024);
-        SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)mb * d.Co), "bias workspace"));
+        ReduceSeg& rs = bseg.s[bseg.count++];
+        rs.part_off = boff;
+        rs.out_off = s.b_off[L];
+        rs.n = d.Co;
+        rs.splits = mb;
+        rs.first = bfirst;
+        boff += (int64_t)mb * d.Co;
+        bfirst += d.Co;
         SG_TRY(check(mask_colsum((const float*)s.gact[go].p, kTC[go], (const uint16_t*)s.act[d.out].p,
-                                 (uint16_t*)s.dpre.p, rows, d.Co, (float*)s.parts.p, mb, grad + s.b_off[L], c->stream),
-                     "relu mask and bias gradient"));
+                                 (uint16_t*)s.dpre.p, rows, d.Co, (float*)s.bias_parts.p + rs.part_off, mb, nullptr,
+                                 c->stream),
+                     "relu mask and bias partials"));
         if (d.skip >= 0 && go != kScanDst) {   // (S0's skip copy is done by the depth integral's backward)
             // out2 = out + skip: the skip tensor receives the same gradient
             SG_TRY(check(hipMemcpyAsync(s.gact[d.skip].p, s.gact[go].p, sizeof(float) * n_out,
@@ -406,7 +430,7 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
             written[d.in] = true;
         }
     }
-    return SG_OK;
+    return check(reduce_segments((const float*)s.bias_parts.p, grad, bseg, c->stream), "bias gradients");
 }
 
 // Adam on every generator tensor, one launch (scalars from the device, counted by adam_coef)
@@ -890,7 +914,7 @@ std::vector<const void*> buffer_ptrs(const Surrogate& s)
 {
     std::vector<const void*> v = {s.master.p, s.mom1.p, s.mom2.p, s.grad.p, s.wb.p, s.wt.p, s.dpre.p, s.fine.p,
                                   s.parts.p, s.yhat.p, s.target.p, s.gy.p, s.loss.p, s.dscan.p, s.steps.p, s.coef.p,
-                                  s.segs.p, s.hist.p, s.d_master.p, s.d_mom1.p, s.d_mom2.p, s.d_grad.p, s.d_wb.p,
+                                  s.segs.p, s.hist.p, s.bias_parts.p, s.d_master.p, s.d_mom1.p, s.d_mom2.p, s.d_grad.p, s.d_wb.p,
                                   s.d_wt.p, s.d_logits.p, s.d_glog.p, s.d_dpre.p, s.d_bias_scratch.p, s.d_segs.p};
     for (int t = 0; t < kNumT; ++t) {
         v.push_back(s.act[t].p);

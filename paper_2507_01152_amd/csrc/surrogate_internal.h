@@ -171,6 +171,19 @@ hipError_t pool2x2_sum(const float* fine, float* coarse, int N, int H, int W, in
 hipError_t colsum_bf16(const uint16_t* x, int64_t rows, int cols, float* part, int blocks, float* out,
                        hipStream_t s);
 hipError_t sum_parts(const float* part, int64_t n, int splits, float* out, hipStream_t s);
+// several reductions of per-block partials ([splits][n] at part_off) into out + out_off, in one launch,
+// each bit-identical to sum_parts of the same partials (n <= 65535 per segment)
+constexpr int kMaxReduceSegs = 24;
+struct ReduceSeg {
+    int64_t part_off, out_off;
+    int32_t n, splits;
+    int32_t first;   // first block (output) of the segment: the sum of n over the earlier segments
+};
+struct ReduceSegs {
+    ReduceSeg s[kMaxReduceSegs];
+    int32_t count;
+};
+hipError_t reduce_segments(const float* part, float* out, const ReduceSegs& t, hipStream_t s);
 hipError_t head_fwd(const uint16_t* x, const uint16_t* w, const float* b, float* y, int64_t P, int C, hipStream_t s);
 hipError_t head_bwd(const uint16_t* x, const uint16_t* w, const float* g, float* dx, int64_t P, int C, float* part,
                     int blocks, float* dwb, hipStream_t s);
