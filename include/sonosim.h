@@ -503,7 +503,10 @@ sg_status sg_surr_train_pairs(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, int3
                               const uint16_t* input, const float* target, float lr, float* loss);
 
 /* sg_surr_train_pairs without the loss readback (see sg_surr_train_step_async):
- * the two copies and the step are enqueued; returns without waiting. */
+ * the two copies and the step are enqueued; returns without waiting, so
+ * input and target must stay valid until the copies have run on the
+ * context's stream (work ordered after the call on that stream may reuse
+ * them). */
 sg_status sg_surr_train_pairs_async(sg_ctx* ctx, int32_t surr_id, int32_t n_envs, int32_t H, int32_t W,
                                     const uint16_t* input, const float* target, float lr);
 
