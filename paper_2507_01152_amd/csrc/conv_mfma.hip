@@ -59,8 +59,20 @@ __device__ __forceinline__ float bf2f(uint16_t b)
 enum Mode { kFwd = 0, kDgrad = 1, kWgrad = 2 };
 
 template <int MODE, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
+__global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
 {
+    ConvGeom g = g0;
+    if (MODE == kDgrad && g0.par == 4) {   // parity class blockIdx.z of a stride-2 data gradient
+        const int par = blockIdx.z, pa = par >> 1, pb = par & 1;
+        g.par = par;
+        g.Hc = g0.hc4[par];
+        g.Wc = g0.wc4[par];
+        g.f_hinwin = g0.f_hw4[par];
+        g.f_win = g0.f_w4[par];
+        g.M = (g0.Kw / ((int64_t)g0.Ho * g0.Wo)) * g.Hc * g.Wc;
+        g.K = (pa + 1) * (pb + 1) * g0.Co;
+        if ((int64_t)blockIdx.x * BM >= g.M) return;   // this class has fewer row tiles
+    }
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 16, FN = TN / 16;
     static_assert(WM * WN == 4, "four waves");
@@ -131,10 +143,13 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
                     a_wb[i] = wo * g.stride - g.pad;
                     a_base[i] = (int64_t)n * g.H * g.W * g.C;
                 } else {
+                    // pixel (h, w) of image n; a parity class counts only its own pixels
+                    const bool pc = g.par >= 0;
                     const int n = (int)fdiv((uint32_t)m, g.f_hinwin);
-                    const int rem = m - n * Hin * Win;
-                    const int h = (int)fdiv((uint32_t)rem, g.f_win);
-                    const int w = rem - h * Win;
+                    const int rem = m - n * (pc ? g.Hc * g.Wc : Hin * Win);
+                    const int qh = (int)fdiv((uint32_t)rem, g.f_win);
+                    const int qw = rem - qh * (pc ? g.Wc : Win);
+                    const int h = pc ? 2 * qh + (g.par >> 1) : qh, w = pc ? 2 * qw + (g.par & 1) : qw;
                     a_hb[i] = h + g.pad;
                     a_wb[i] = w + g.pad;
                     a_base[i] = (int64_t)n * g.Ho * g.Wo * g.Co;
@@ -181,14 +196,23 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
         // K-contiguous: one tap / channel split per K step (k8 fixed per thread)
         const int k = (int)k0 + k8 * 8;
         const bool kin = k < g.K;
-        int r = 0, s = 0, c0 = 0;
+        int r = 0, s = 0, c0 = 0, kf = k;   // kf: the column of B (all taps)
         if (kin) {
             const FastDiv fc = (MODE == kFwd) ? g.f_c : g.f_co;
             const int cc = (MODE == kFwd) ? g.C : g.Co;
             const int t = (int)fdiv((uint32_t)k, fc);
             c0 = k - t * cc;
-            r = (int)fdiv((uint32_t)t, g.f_kw);
-            s = t - r * g.kw;
+            if (MODE == kDgrad && g.par >= 0) {
+                // class taps: rows r in {1} (even h) or {0, 2} (odd h), columns s likewise, row-major
+                const int pa = g.par >> 1, pb = g.par & 1;
+                const int tr = pb ? t >> 1 : t, ts = pb ? t & 1 : 0;
+                r = pa ? 2 * tr : 1;
+                s = pb ? 2 * ts : 1;
+                kf = (r * 3 + s) * cc + c0;
+            } else {
+                r = (int)fdiv((uint32_t)t, g.f_kw);
+                s = t - r * g.kw;
+            }
         }
 #pragma unroll
         for (int i = 0; i < PA; ++i) {
@@ -214,7 +238,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
         for (int i = 0; i < PB; ++i) {
             const int col = n_base + (tid >> 2) + i * (kThreads / 4);
             rb[i] = (kin && (tid >> 2) + i * (kThreads / 4) < BN && col < g.N)
-                        ? *reinterpret_cast<const u32x4*>(B + (int64_t)col * g.K + k)
+                        ? *reinterpret_cast<const u32x4*>(B + (int64_t)col * g.kb + kf)
                         : zero;
         }
     };
@@ -310,7 +334,15 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g, ConvArgs a)
                     if (a.skip && a.out2_bf16)
                         a.out2_bf16[row * (a.ld_out2 ? a.ld_out2 : g.Co) + col] = f2bf(bf2f(yb) + bf2f(a.skip[o]));
                 } else if constexpr (MODE == kDgrad) {
-                    const int64_t o = row * g.C + col;
+                    int64_t px = row;   // pixel of the row (a parity class's rows are a quarter of them)
+                    if (g.par >= 0) {
+                        const int n = (int)fdiv((uint32_t)row, g.f_hinwin);
+                        const int rem = (int)row - n * g.Hc * g.Wc;
+                        const int qh = (int)fdiv((uint32_t)rem, g.f_win);
+                        const int qw = rem - qh * g.Wc;
+                        px = ((int64_t)n * g.H + 2 * qh + (g.par >> 1)) * g.W + 2 * qw + (g.par & 1);
+                    }
+                    const int64_t o = px * g.C + col;
                     a.out_f32[o] = a.accumulate ? a.out_f32[o] + v : v;
                 } else {
                     a.out_f32[(int64_t)blockIdx.z * g.M * g.N + row * g.N + col] = v;
@@ -1561,6 +1593,39 @@ hipError_t dgrad_tile(const ConvGeom& g, const uint16_t* dy, const uint16_t* wt,
     return dil ? launch_dgrad_tile<32, true>(f, a, s) : launch_dgrad_tile<32, false>(f, a, s);
 }
 
+bool dgrad_parity_supported(const ConvGeom& g)
+{
+    return g.kh == 3 && g.kw == 3 && g.stride == 2 && g.pad == 1 && !g.up && g.Co % 8 == 0 && g.C % 8 == 0 &&
+           g.H >= 2 && g.W >= 2;
+}
+
+hipError_t dgrad_parity(const ConvGeom& g, const uint16_t* dy, const uint16_t* wt, float* dx, int accumulate,
+                        hipStream_t s)
+{
+    if (!dgrad_parity_supported(g)) return hipErrorInvalidValue;
+    if (g.H < 2 || g.W < 2) return hipErrorInvalidValue;   // every class has pixels
+    // one launch: class blockIdx.z; the grid covers class 0's rows, the largest class
+    const int64_t N = g.Kw / ((int64_t)g.Ho * g.Wo);
+    ConvGeom c = g;
+    c.par = 4;
+    for (int par = 0; par < 4; ++par) {
+        c.hc4[par] = (g.H - (par >> 1) + 1) / 2;
+        c.wc4[par] = (g.W - (par & 1) + 1) / 2;
+        c.f_hw4[par] = make_fastdiv((uint32_t)(c.hc4[par] * c.wc4[par]));
+        c.f_w4[par] = make_fastdiv((uint32_t)c.wc4[par]);
+    }
+    c.M = N * c.hc4[0] * c.wc4[0];
+    c.K = 4 * g.Co;   // the largest class's (for the launch shape only)
+    c.kb = 9 * g.Co;
+    ConvArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.a = dy;
+    a.b = wt;
+    a.out_f32 = dx;
+    a.accumulate = accumulate;
+    return conv_gemm(kDgrad, c, a, 1, s);
+}
+
 hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits, hipStream_t s)
 {
     if (a.head_out && (mode != kFwd || !conv_tile_supported(g) || g.Co != 16 || !a.head_w || !a.head_b))
@@ -1581,10 +1646,12 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
         if (g.N <= 64) return launch_gemm<kFwd, 128, 64, 2, 2>(g, a, 1, s);
         return launch_gemm<kFwd, 128, 128, 2, 2>(g, a, 1, s);
     }
-    if (g.N <= 16) return launch_gemm<kDgrad, 256, 16, 4, 1>(g, a, 1, s);
-    if (g.N <= 32) return launch_gemm<kDgrad, 128, 32, 4, 1>(g, a, 1, s);
-    if (g.N <= 64) return launch_gemm<kDgrad, 128, 64, 2, 2>(g, a, 1, s);
-    return launch_gemm<kDgrad, 128, 128, 2, 2>(g, a, 1, s);
+    // data gradient: splits = 4 only for the parity classes (g.par == 4), one per grid z
+    const int nz = g.par == 4 ? 4 : 1;
+    if (g.N <= 16) return launch_gemm<kDgrad, 256, 16, 4, 1>(g, a, nz, s);
+    if (g.N <= 32) return launch_gemm<kDgrad, 128, 32, 4, 1>(g, a, nz, s);
+    if (g.N <= 64) return launch_gemm<kDgrad, 128, 64, 2, 2>(g, a, nz, s);
+    return launch_gemm<kDgrad, 128, 128, 2, 2>(g, a, nz, s);
 }
 
 bool wgrad_tile_plan(const ConvGeom& g, WgradTilePlan* plan)

@@ -231,6 +231,8 @@ sg_status dgrad(sg_ctx* c, const ConvShape& sh, const uint16_t* dy, const uint16
         }
         return check(dgrad_tile(g, dy, wt, dx, accumulate, c->stream), "dgrad launch");
     }
+    if (dgrad_parity_supported(g))   // stride 2, wider: one GEMM per output parity class, one launch
+        return check(dgrad_parity(g, dy, wt, dx, accumulate, c->stream), "dgrad launch");
     ConvArgs a;
     std::memset(&a, 0, sizeof(a));
     a.a = dy;

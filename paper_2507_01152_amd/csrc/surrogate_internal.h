@@ -38,6 +38,14 @@ struct ConvGeom {
     int32_t Ho, Wo; // output size
     int32_t kh, kw, stride, pad, up;
     FastDiv f_c, f_co, f_kw, f_stride, f_howo, f_wo, f_hinwin, f_win;
+    int32_t kb;     // elements per row of the GEMM's B operand (forward W, data gradient WT): K, or 9 Co
+    // data gradient of a stride-2, pad-1 3x3 conv split by output parity (par = 2 (h % 2) + (w % 2), or
+    // -1): rows are the Hc x Wc pixels (2 i + h % 2, 2 j + w % 2) of each image, K the Co x taps that
+    // reach them (f_hinwin and f_win then divide by Hc Wc and Wc).  par = 4: all four classes in one
+    // launch, class blockIdx.z, with its sizes and divisors in the arrays below
+    int32_t par, Hc, Wc;
+    int32_t hc4[4], wc4[4];
+    FastDiv f_hw4[4], f_w4[4];
 };
 
 constexpr float kLeakySlope = 0.2f;   // leaky ReLU of the discriminator
@@ -112,6 +120,9 @@ inline ConvGeom geom_of(const ConvShape& s, int mode)
         g.N = s.k * s.k * s.C;
         g.K = 0;
     }
+    g.kb = g.K;
+    g.par = -1;
+    g.Hc = g.Wc = 0;
     return g;
 }
 
@@ -123,6 +134,11 @@ bool conv_tile_supported(const ConvGeom& g);
 // sizes) as a forward tiled conv of dy with mirrored taps, over dy dilated by zeros for stride 2: dx
 // [N][Hin][Win][C] FP32 (the fine-resolution gradient of an upsampled layer), written or accumulated
 bool dgrad_tile_supported(const ConvGeom& g);
+// data gradient of a stride-2, pad-1 3x3 conv (g: mode-1 geometry) as four implicit GEMMs, one per output
+// parity class, each over only the taps that reach it (a quarter of the full gather's products)
+bool dgrad_parity_supported(const ConvGeom& g);
+hipError_t dgrad_parity(const ConvGeom& g, const uint16_t* dy, const uint16_t* wt, float* dx, int accumulate,
+                        hipStream_t s);
 hipError_t dgrad_tile(const ConvGeom& g, const uint16_t* dy, const uint16_t* wt, float* dx, int accumulate,
                       hipStream_t s);
 int wgrad_tile_m(int M);

@@ -62,6 +62,8 @@ CONV_CASES = [
     (2, 16, 40, 16, 32, 3, 2, 1, 0),     # the T2 shape
     (1, 22, 70, 16, 32, 3, 2, 1, 0),     # ragged tiles of the 22 x 70 input gradient
     (1, 12, 36, 32, 16, 3, 2, 1, 0),     # 32 input channels, 16 output
+    # wider stride-2 layers: the data gradient as one GEMM per output parity class (odd sizes above)
+    (2, 16, 24, 32, 64, 3, 2, 1, 0),     # the T3 shape
 ]
 
 
