@@ -530,7 +530,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     }
 }
 
-// Direct 3x3 weight gradient (stride 1, pad 1): dW[co][r][s][ci] = sum over
+// Direct 3x3 weight gradient (pad 1; stride 1, or 2 with S2): dW[co][r][s][ci] = sum over
 // output pixels p of dy[p][co] x[p + (r - 1, s - 1)][ci], for a group of CI in
 // {8, 16, 24, 32} input and CO in {16, 32} output channels (block y: input
 // group, block z: output group, of a layer with g.C and g.Co channels).  A block stages, per tile of
@@ -548,23 +548,37 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
 // static stride; at the end the four waves are summed in LDS in a fixed order
 // and the block writes one partial dW, which a fixed-order reduction sums.
 // UP: x is read upsampled x2 (fine pixel (h, w) is stored pixel (h/2, w/2)).
+// S2: stride 2 (x pixel (2 h + r - 1, 2 w + s - 1) meets output pixel (h, w)).
 constexpr int kWgH = 8, kWgW = 32;
 constexpr int kWgXR = kWgH + 2, kWgXC = kWgW + 2;   // staged halo rows and columns
 constexpr int kWgPitch = 40;                        // LDS row pitch (bf16)
 constexpr int kWgXPlane = kWgXR * kWgPitch + 8;     // 204 dwords per channel: banks 12 apart
 constexpr int kWgDPlane = kWgH * kWgPitch + 8;      // 164 dwords per channel: banks 4 apart
+// stride 2: tiles of 4 x 32 outputs; their 9 x 65 input window is staged with the even and the odd
+// columns in separate halves of an 80-element row, so the operands of all three column taps are
+// aligned reads again (tap 0: even half; tap 1: odd half; tap 2: even half one column on)
+constexpr int kWgH2 = 4;
+constexpr int kWgXR2 = 2 * kWgH2 + 1, kWgRow2 = 80, kWgQ2 = 17;   // rows, row length, 4-column items
+constexpr int kWgXPlane2 = kWgXR2 * kWgRow2 + 8;                  // 364 dwords: banks 44 apart
+constexpr int kWgDPlane2 = kWgH2 * kWgPitch + 8;                  // 84 dwords: banks 20 apart
 
-template <int CI, int CO, bool UP>
+template <int CI, int CO, bool UP, bool S2>
 __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_t* __restrict__ x,
                                                        const uint16_t* __restrict__ dy, float* __restrict__ part)
 {
+    static_assert(!(UP && S2), "stride 2 reads its input directly");
     constexpr int NB = (CI + 15) / 16, CB = CO / 16, CIP = NB * 16;
     constexpr int CI8 = CI / 8, CO8 = CO / 8;
-    constexpr int RW = kWgH * CB / 4;   // output rows per wave (the waves split co groups x row groups)
-    // items (8 channels of two neighbouring pixels) of one tile's operands, and each thread's share
-    constexpr int XN = kWgXR * (kWgXC / 2) * CI8, DN = kWgH * (kWgW / 2) * CO8;
+    constexpr int TH = S2 ? kWgH2 : kWgH;               // output rows per tile
+    constexpr int XROW = S2 ? kWgRow2 : kWgPitch;       // LDS elements per staged input row
+    constexpr int XPL = S2 ? kWgXPlane2 : kWgXPlane, DPL = S2 ? kWgDPlane2 : kWgDPlane;
+    constexpr int RW = TH * CB / 4;   // output rows per wave (the waves split co groups x row groups)
+    // items of one tile's operands and each thread's share: stride 1, 8 channels of two neighbouring
+    // pixels; stride 2 input, 8 channels of four neighbouring pixels
+    constexpr int XN = S2 ? kWgXR2 * kWgQ2 * CI8 : kWgXR * (kWgXC / 2) * CI8, DN = TH * (kWgW / 2) * CO8;
+    constexpr int XE = S2 ? 4 : 2;    // pixels per input item
     constexpr int XI = (XN + 255) / 256, DI = (DN + 255) / 256;
-    constexpr int SX = CIP * kWgXPlane, SD = CO * kWgDPlane, NW = CO * 9 * CI;
+    constexpr int SX = CIP * XPL, SD = CO * DPL, NW = CO * 9 * CI;
     static_assert(NW * 4 <= (SX + SD) * 2, "the cross-wave sum reuses the operand planes");
     __shared__ __attribute__((aligned(16))) uint16_t smem[SX + SD];
     uint16_t* sX = smem;
@@ -572,13 +586,13 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int Hin = UP ? 2 * g.H : g.H, Win = UP ? 2 * g.W : g.W;
-    const int tiles_x = (g.Wo + kWgW - 1) / kWgW, tiles_y = (g.Ho + kWgH - 1) / kWgH;
+    const int tiles_x = (g.Wo + kWgW - 1) / kWgW, tiles_y = (g.Ho + TH - 1) / TH;
     const int64_t per_img = (int64_t)tiles_x * tiles_y;
     const int64_t total = (g.Kw / ((int64_t)g.Ho * g.Wo)) * per_img;   // Kw = N * Ho * Wo
     const uint16_t* xg = x + blockIdx.y * CI;    // the block's input channel group
     const uint16_t* dyg = dy + blockIdx.z * CO;  // and output channel group
     if constexpr (CIP != CI) {   // channels CI .. CIP - 1 stay zero
-        for (int i = tid; i < (CIP - CI) * kWgXPlane; i += 256) sX[CI * kWgXPlane + i] = 0;
+        for (int i = tid; i < (CIP - CI) * XPL; i += 256) sX[CI * XPL + i] = 0;
     }
     const int cbw = wave % CB, r0 = (wave / CB) * RW;   // the wave's co group and first output row
     f32x4 acc[9][NB];
@@ -587,21 +601,22 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[t][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     const u32x4 zero = {0u, 0u, 0u, 0u};
-    u32x4 xv[XI][2], dv[DI][2];
+    u32x4 xv[XI][XE], dv[DI][2];
     auto load = [&](int64_t t) {
         const int64_t n = t / per_img;
         const int t_in = (int)(t - n * per_img);
         const int ty = t_in / tiles_x, tx = t_in - ty * tiles_x;
-        const int ho0 = ty * kWgH, wo0 = tx * kWgW;
+        const int ho0 = ty * TH, wo0 = tx * kWgW;
 #pragma unroll
         for (int k = 0; k < XI; ++k) {
             const int i = tid + 256 * k;
             const int c8 = i % CI8, pr = i / CI8;
-            const int hy = pr / (kWgXC / 2), wx = 2 * (pr - hy * (kWgXC / 2));
-            const int hi = ho0 - 1 + hy;
+            constexpr int XQ = S2 ? kWgQ2 : kWgXC / 2;
+            const int hy = pr / XQ, wx = XE * (pr - hy * XQ);
+            const int hi = (S2 ? 2 * ho0 : ho0) - 1 + hy;
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int wi = wo0 - 1 + wx + e;
+            for (int e = 0; e < XE; ++e) {
+                const int wi = (S2 ? 2 * wo0 : wo0) - 1 + wx + e;
                 xv[k][e] = zero;
                 if (i < XN && hi >= 0 && wi >= 0 && hi < Hin && wi < Win) {
                     const int hs = UP ? hi >> 1 : hi, ws = UP ? wi >> 1 : wi;
@@ -624,7 +639,7 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
             }
         }
     };
-    // transpose into the channel planes: channel 2j of the pair is the low halves of dword j,
+    // transpose into the channel planes: channel 2j of a pixel pair is the low halves of dword j,
     // channel 2j + 1 the high halves (LDS positions do not depend on the tile)
     auto store = [&]() {
 #pragma unroll
@@ -632,12 +647,27 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
             const int i = tid + 256 * k;
             if (i < XN) {
                 const int c8 = i % CI8, pr = i / CI8;
-                const int hy = pr / (kWgXC / 2), wx = 2 * (pr - hy * (kWgXC / 2));
-                uint32_t* d = reinterpret_cast<uint32_t*>(&sX[(c8 * 8) * kWgXPlane + hy * kWgPitch + wx]);
+                constexpr int XQ = S2 ? kWgQ2 : kWgXC / 2;
+                const int hy = pr / XQ, q = pr - hy * XQ;
+                if constexpr (S2) {
+                    // columns 4q .. 4q + 3: even ones to half 0 at 2q, 2q + 1; odd ones to half 1
+                    uint32_t* d = reinterpret_cast<uint32_t*>(&sX[(c8 * 8) * XPL + hy * XROW + 2 * q]);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    d[(2 * j) * (kWgXPlane / 2)] = __builtin_amdgcn_perm(xv[k][1][j], xv[k][0][j], 0x05040100u);
-                    d[(2 * j + 1) * (kWgXPlane / 2)] = __builtin_amdgcn_perm(xv[k][1][j], xv[k][0][j], 0x07060302u);
+                    for (int j = 0; j < 4; ++j) {
+                        d[(2 * j) * (XPL / 2)] = __builtin_amdgcn_perm(xv[k][2][j], xv[k][0][j], 0x05040100u);
+                        d[(2 * j + 1) * (XPL / 2)] = __builtin_amdgcn_perm(xv[k][2][j], xv[k][0][j], 0x07060302u);
+                        d[(2 * j) * (XPL / 2) + kWgPitch / 2] =
+                            __builtin_amdgcn_perm(xv[k][3][j], xv[k][1][j], 0x05040100u);
+                        d[(2 * j + 1) * (XPL / 2) + kWgPitch / 2] =
+                            __builtin_amdgcn_perm(xv[k][3][j], xv[k][1][j], 0x07060302u);
+                    }
+                } else {
+                    uint32_t* d = reinterpret_cast<uint32_t*>(&sX[(c8 * 8) * XPL + hy * XROW + 2 * q]);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        d[(2 * j) * (XPL / 2)] = __builtin_amdgcn_perm(xv[k][1][j], xv[k][0][j], 0x05040100u);
+                        d[(2 * j + 1) * (XPL / 2)] = __builtin_amdgcn_perm(xv[k][1][j], xv[k][0][j], 0x07060302u);
+                    }
                 }
             }
         }
@@ -647,17 +677,17 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
             if (i < DN) {
                 const int c8 = i % CO8, pr = i / CO8;
                 const int r = pr / (kWgW / 2), c = 2 * (pr - r * (kWgW / 2));
-                uint32_t* d = reinterpret_cast<uint32_t*>(&sD[(c8 * 8) * kWgDPlane + r * kWgPitch + c]);
+                uint32_t* d = reinterpret_cast<uint32_t*>(&sD[(c8 * 8) * DPL + r * kWgPitch + c]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    d[(2 * j) * (kWgDPlane / 2)] = __builtin_amdgcn_perm(dv[k][1][j], dv[k][0][j], 0x05040100u);
-                    d[(2 * j + 1) * (kWgDPlane / 2)] = __builtin_amdgcn_perm(dv[k][1][j], dv[k][0][j], 0x07060302u);
+                    d[(2 * j) * (DPL / 2)] = __builtin_amdgcn_perm(dv[k][1][j], dv[k][0][j], 0x05040100u);
+                    d[(2 * j + 1) * (DPL / 2)] = __builtin_amdgcn_perm(dv[k][1][j], dv[k][0][j], 0x07060302u);
                 }
             }
         }
     };
-    const uint16_t* pa = &sD[(cbw * 16 + lr) * kWgDPlane + r0 * kWgPitch + 8 * lk];   // A: output row r0
-    const uint16_t* pbx = &sX[lr * kWgXPlane + r0 * kWgPitch + 8 * lk];                // B: staged row r0
+    const uint16_t* pa = &sD[(cbw * 16 + lr) * DPL + r0 * kWgPitch + 8 * lk];                // A: output row r0
+    const uint16_t* pbx = &sX[lr * XPL + (S2 ? 2 * r0 : r0) * XROW + 8 * lk];              // B: its first input row
     if ((int64_t)blockIdx.x < total) load(blockIdx.x);
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         __syncthreads();   // the previous tile's operands have been read
@@ -667,26 +697,35 @@ __global__ __launch_bounds__(256) void k_wgrad3x3_tile(ConvGeom g, const uint16_
         bf16x8 fa[RW];
 #pragma unroll
         for (int rs = 0; rs < RW; ++rs) fa[rs] = *reinterpret_cast<const bf16x8*>(pa + rs * kWgPitch);
-        // staged row r0 + xr feeds output row r0 + rs through tap row xr - rs
+        // staged row xr feeds output row r0 + rs through tap row xr - rs (stride 2: xr - 2 rs)
+        constexpr int NXR = S2 ? 2 * RW + 1 : RW + 2;
 #pragma unroll
-        for (int xr = 0; xr < RW + 2; ++xr)
+        for (int xr = 0; xr < NXR; ++xr)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                // staged columns 8 lk .. 8 lk + 9 of the row: the operands of the three column shifts
-                const uint16_t* src = pbx + nb * 16 * kWgXPlane + xr * kWgPitch;
+                // stride 1: staged columns 8 lk .. 8 lk + 9 of the row give the three column shifts;
+                // stride 2: even columns 8 lk .. 8 lk + 8 and odd columns 8 lk .. 8 lk + 7
+                const uint16_t* src = pbx + nb * 16 * XPL + xr * XROW;
                 const u32x4 lo = *reinterpret_cast<const u32x4*>(src);
                 const uint32_t ex = *reinterpret_cast<const uint32_t*>(src + 8);
+                const u32x4 sft = {__builtin_amdgcn_alignbyte(lo[1], lo[0], 2u), __builtin_amdgcn_alignbyte(lo[2], lo[1], 2u),
+                                   __builtin_amdgcn_alignbyte(lo[3], lo[2], 2u), __builtin_amdgcn_alignbyte(ex, lo[3], 2u)};
                 u32x4 sh[3];
-                sh[0] = lo;
-                sh[1] = u32x4{__builtin_amdgcn_alignbyte(lo[1], lo[0], 2u), __builtin_amdgcn_alignbyte(lo[2], lo[1], 2u),
-                              __builtin_amdgcn_alignbyte(lo[3], lo[2], 2u), __builtin_amdgcn_alignbyte(ex, lo[3], 2u)};
-                sh[2] = u32x4{lo[1], lo[2], lo[3], ex};
+                if constexpr (S2) {
+                    sh[0] = lo;
+                    sh[1] = *reinterpret_cast<const u32x4*>(src + kWgPitch);
+                    sh[2] = sft;
+                } else {
+                    sh[0] = lo;
+                    sh[1] = sft;
+                    sh[2] = u32x4{lo[1], lo[2], lo[3], ex};
+                }
 #pragma unroll
                 for (int dc = 0; dc < 3; ++dc) {
                     const bf16x8 fb = __builtin_bit_cast(bf16x8, sh[dc]);
 #pragma unroll
                     for (int rs = 0; rs < RW; ++rs) {
-                        const int dr = xr - rs;
+                        const int dr = xr - (S2 ? 2 : 1) * rs;
                         if (dr < 0 || dr > 2) continue;
                         acc[3 * dr + dc][nb] =
                             __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[rs], fb, acc[3 * dr + dc][nb], 0, 0, 0);
@@ -1656,9 +1695,9 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
 
 bool wgrad_tile_plan(const ConvGeom& g, WgradTilePlan* plan)
 {
-    if (!(g.kh == 3 && g.kw == 3 && g.stride == 1 && g.pad == 1 && g.Ho == (g.up ? 2 * g.H : g.H) &&
-          g.Wo == (g.up ? 2 * g.W : g.W)))
-        return false;
+    const bool s1 = g.stride == 1 && g.Ho == (g.up ? 2 * g.H : g.H) && g.Wo == (g.up ? 2 * g.W : g.W);
+    const bool s2 = g.stride == 2 && !g.up && g.Ho == (g.H - 1) / 2 + 1 && g.Wo == (g.W - 1) / 2 + 1;
+    if (!(g.kh == 3 && g.kw == 3 && g.pad == 1 && (s1 || s2))) return false;
     int ci_g = 0, co_g = 0;
     if (g.C == 8 || g.C == 16 || g.C == 24 || g.C == 32)
         ci_g = g.C;
@@ -1671,7 +1710,8 @@ bool wgrad_tile_plan(const ConvGeom& g, WgradTilePlan* plan)
     if (!ci_g || !co_g) return false;
     if (plan) {
         const int gy = g.C / ci_g, gz = g.Co / co_g;
-        const int64_t tiles = (g.Kw / ((int64_t)g.Ho * g.Wo)) * (int64_t)((g.Ho + kWgH - 1) / kWgH) *
+        const int th = g.stride == 2 ? kWgH2 : kWgH;
+        const int64_t tiles = (g.Kw / ((int64_t)g.Ho * g.Wo)) * (int64_t)((g.Ho + th - 1) / th) *
                               ((g.Wo + kWgW - 1) / kWgW);
         const int64_t want = std::max<int64_t>(1, (512 + gy * gz - 1) / (gy * gz));   // about 512 blocks
         plan->gx = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), want);
@@ -1693,7 +1733,15 @@ template <int CI, int CO, bool UP>
 hipError_t launch_wgrad_tile3(const ConvGeom& g, const uint16_t* x, const uint16_t* dy, float* part,
                               const WgradTilePlan& p, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_wgrad3x3_tile<CI, CO, UP>), dim3(p.gx, p.gy, p.gz), dim3(256), 0, s, g, x, dy, part);
+    if (g.stride == 2) {
+        if constexpr (UP) return hipErrorInvalidValue;
+        else
+            hipLaunchKernelGGL((k_wgrad3x3_tile<CI, CO, false, true>), dim3(p.gx, p.gy, p.gz), dim3(256), 0, s, g,
+                               x, dy, part);
+    } else {
+        hipLaunchKernelGGL((k_wgrad3x3_tile<CI, CO, UP, false>), dim3(p.gx, p.gy, p.gz), dim3(256), 0, s, g, x, dy,
+                           part);
+    }
     return hipGetLastError();
 }
 

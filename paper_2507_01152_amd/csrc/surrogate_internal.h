@@ -142,7 +142,7 @@ hipError_t dgrad_parity(const ConvGeom& g, const uint16_t* dy, const uint16_t* w
 hipError_t dgrad_tile(const ConvGeom& g, const uint16_t* dy, const uint16_t* wt, float* dx, int accumulate,
                       hipStream_t s);
 int wgrad_tile_m(int M);
-// direct 3x3 weight gradient (stride 1, pad 1; C in {8, 16, 24, 32} or a multiple of 32, Co in {16, 32}
+// direct 3x3 weight gradient (stride 1 or 2, pad 1; C in {8, 16, 24, 32} or a multiple of 32, Co in {16, 32}
 // or a multiple of 32, the wider ones for outputs at least 16 wide): gx x gy x gz blocks (gy input and gz
 // output channel groups of ci_g and co_g) write gx partials of the whole dW (the gy x gz blocks with one
 // block x index fill one partial), then a fixed-order reduction over the gx partials writes dw ([Co][3][3][C])

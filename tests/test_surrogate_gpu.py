@@ -64,6 +64,9 @@ CONV_CASES = [
     (1, 12, 36, 32, 16, 3, 2, 1, 0),     # 32 input channels, 16 output
     # wider stride-2 layers: the data gradient as one GEMM per output parity class (odd sizes above)
     (2, 16, 24, 32, 64, 3, 2, 1, 0),     # the T3 shape
+    # stride-2 weight gradients on the direct kernel (4 x 32 output tiles, even and odd input columns)
+    (1, 10, 40, 64, 64, 3, 2, 1, 0),     # 2 x 2 channel groups
+    (64, 40, 96, 16, 32, 3, 2, 1, 0),    # 640 tiles over 512 blocks
 ]
 
 
