@@ -180,6 +180,9 @@ def ct_surrogate_leg(train_steps: int, n_envs: int = 256, batch: int = 32, audit
     HW = CT_FRAME_W * CT_FRAME_H
     out = torch.empty(n_envs * HW, dtype=torch.float32, device=sess.device)
     out16 = torch.empty(n_envs * HW, dtype=torch.bfloat16, device=sess.device)   # the served BF16 frames
+    # a serving loop's probes are fixed per env: marshalled once, as the physics plan takes them once
+    vids = np.ascontiguousarray(vids, dtype=np.int32)
+    probes = sg.probes_array(probes)
     sg.sg_surr_infer_bf16(sess.ctx, sid, vids, probes, poses, out16, audit, psnr_min, 0.25)   # warm-up
     reps = 5
     torch.cuda.synchronize()
@@ -276,6 +279,9 @@ def surrogate_leg(train_steps: int, n_envs: int = 1024, audit_frac: int = 16, ps
     HW = FRAME_W * FRAME_H
     out = torch.empty(n_envs * HW, dtype=torch.float32, device=sess.device)
     out16 = torch.empty(n_envs * HW, dtype=torch.bfloat16, device=sess.device)   # the served BF16 frames
+    # a serving loop's probes are fixed per env: marshalled once, as the physics plan takes them once
+    vids = np.ascontiguousarray(vids, dtype=np.int32)
+    probes = sg.probes_array(probes)
     sg.sg_surr_infer_bf16(sess.ctx, sid, vids, probes, poses, out16, audit, psnr_min, 0.25)   # warm-up
     reps = 5
     torch.cuda.synchronize()

@@ -260,12 +260,31 @@ def sg_tissue_table_set(ctx, table):
 
 
 def probes_array(probes):
-    """Host array of sg_probe from objects with W, H, dx, dy, f, E0, psf, dr."""
+    """Host array of sg_probe from objects with W, H, dx, dy, f, E0, psf, dr.
+    An sg_probe array (what this returns) passes through unchanged, so a
+    caller that serves the same probes every step marshals them once."""
+    if _is_probe_array(probes):
+        return probes
     arr = (sg_probe * len(probes))()
     for i, p in enumerate(probes):
-        arr[i] = sg_probe(int(p.W), int(p.H), float(p.dx), float(p.dy), float(p.f), float(p.E0),
-                          float(p.psf), float(p.dr), int(getattr(p, "n_elev", 1)), float(getattr(p, "elev", 0.0)))
+        arr[i] = p if isinstance(p, sg_probe) else sg_probe(
+            int(p.W), int(p.H), float(p.dx), float(p.dy), float(p.f), float(p.E0), float(p.psf), float(p.dr),
+            int(getattr(p, "n_elev", 1)), float(getattr(p, "elev", 0.0)))
     return arr
+
+
+def _is_probe_array(probes):
+    return isinstance(probes, C.Array) and probes._type_ is sg_probe
+
+
+def _pixels(probes):
+    """Sum of W * H over the probes (one plane each)."""
+    if _is_probe_array(probes):
+        dt = np.dtype({"names": ["W", "H"], "formats": [np.int32, np.int32],
+                       "offsets": [sg_probe.W.offset, sg_probe.H.offset], "itemsize": C.sizeof(sg_probe)})
+        a = np.frombuffer((C.c_char * C.sizeof(probes)).from_buffer(probes), dtype=dt)
+        return int((a["W"].astype(np.int64) * a["H"]).sum())
+    return sum(int(p.W) * int(p.H) for p in probes)
 
 
 def sg_simulate(ctx, vol_ids, probes, poses, out, out_offsets, debug: dict | None = None):
@@ -550,7 +569,7 @@ def sg_surr_infer(ctx, sid, vol_ids, probes, poses, out, audit_envs=(), psnr_min
     au = np.ascontiguousarray(audit_envs, dtype=np.int32)
     if len(vids) != n:
         raise ValueError("vol_ids and probes must have one entry per env")
-    need = sum(int(p.W) * int(p.H) for p in probes)
+    need = _pixels(probes)
     psnr = np.zeros(max(1, len(au)), dtype=np.float32)
     nf = C.c_int32()
     _check(load().sg_surr_infer(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data,
@@ -570,7 +589,7 @@ def sg_surr_infer_bf16(ctx, sid, vol_ids, probes, poses, out, audit_envs=(), psn
     au = np.ascontiguousarray(audit_envs, dtype=np.int32)
     if len(vids) != n:
         raise ValueError("vol_ids and probes must have one entry per env")
-    need = sum(int(p.W) * int(p.H) for p in probes)
+    need = _pixels(probes)
     psnr = np.zeros(max(1, len(au)), dtype=np.float32)
     nf = C.c_int32()
     _check(load().sg_surr_infer_bf16(ctx, int(sid), n, vids.ctypes.data, C.cast(pa, C.c_void_p), ps.ctypes.data,

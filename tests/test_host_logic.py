@@ -1,6 +1,6 @@
 """Host-side logic of the library that runs without a device: the audit
-decision rule of surrogate inference and the quantised normal of the
-multi-scale density gate."""
+decision rule of surrogate inference, the quantised normal of the
+multi-scale density gate, and the binding's probe marshalling."""
 import numpy as np
 import pytest
 
@@ -40,3 +40,19 @@ def test_noise_quantiles_of_the_library_match_the_oracle():
     import oracle
     from paper_2507_01152_amd import sonosim as sg
     assert np.array_equal(sg.sg_noise_quantiles(), oracle.quantised_normal_table())
+
+
+def test_probe_arrays_are_marshalled_once(sg):
+    """probes_array builds the C array from probe objects; an array it built
+    (or a list of its elements) passes through unchanged, and the binding's
+    pixel count agrees for both forms."""
+    from types import SimpleNamespace
+    objs = [SimpleNamespace(W=32 + 16 * (i % 3), H=64 + 8 * i, dx=0.25, dy=0.5, f=5.0, E0=1.0, psf=0.01, dr=60.0)
+            for i in range(5)]
+    arr = sg.probes_array(objs)
+    assert sg.probes_array(arr) is arr
+    again = sg.probes_array(list(arr))
+    assert bytes(again) == bytes(arr)
+    assert [(p.W, p.H, p.dx_mm, p.dy_mm) for p in arr] == [(o.W, o.H, o.dx, o.dy) for o in objs]
+    want = sum(o.W * o.H for o in objs)
+    assert sg._pixels(arr) == want and sg._pixels(objs) == want
