@@ -88,8 +88,10 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
     constexpr int PB = RPC * ((CB + kThreads - 1) / kThreads);
     constexpr int AM8 = BM / 8, BN8 = BN / 8;   // weight-gradient row groups
 
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * kBKP];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * kBKP];
+    // double-buffered operand tiles; the forward epilogue reuses the space for its output tile
+    __shared__ __attribute__((aligned(16))) uint16_t smem[2 * (BM + BN) * kBKP];
+    uint16_t (*sA)[BM * kBKP] = reinterpret_cast<uint16_t (*)[BM * kBKP]>(smem);
+    uint16_t (*sB)[BN * kBKP] = reinterpret_cast<uint16_t (*)[BN * kBKP]>(smem + 2 * BM * kBKP);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -287,6 +289,14 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the forward epilogue's bias, read once here (in the epilogue a load after a possibly
+    // aliasing store would be repeated, each waiting for memory)
+    float bias_r[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int col = n_base + wn * TN + j * 16 + (lane & 15);
+        bias_r[j] = (MODE == kFwd && a.bias && col < g.N) ? a.bias[col] : 0.f;
+    }
 
     if (nk > 0) {
         load_tiles(k_begin);
@@ -314,39 +324,131 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
     }
 
     // epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each tile
+    if constexpr (MODE == kFwd) {
+        // the bf16 outputs go through an LDS tile [BM][BN + 8] to 16-byte stores; the skip tensor's
+        // chunks are all loaded before the first store (a load issued after a store waits for it:
+        // one memory round trip per element otherwise)
+        constexpr int TP = BN + 8;
+        static_assert(BM * TP <= 2 * (BM + BN) * kBKP, "output tile fits the operand buffers");
+        uint16_t* sT = smem;
+        __syncthreads();   // every wave is done with the operand tiles
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int cl = wn * TN + j * 16 + (lane & 15), col = n_base + cl;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rl = wm * TM + i * 16 + (lane >> 4) * 4 + r;
+                    const int64_t row = (int64_t)m_base + rl;
+                    const float y = activate(acc[i][j][r] + bias_r[j], a.relu);
+                    sT[rl * TP + cl] = f2bf(y);
+                    if (a.out_f32 && row < g.M && col < g.N) a.out_f32[row * g.Co + col] = y;
+                }
+            }
+        __syncthreads();
+        constexpr int CH = BM * BN / 8, CPT = (CH + kThreads - 1) / kThreads;   // 16-byte chunks
+        const int ld2 = a.ld_out2 ? a.ld_out2 : g.Co;
+        // chunk u of this thread: tile row rl, columns 8 c8.. (Co is a multiple of 8, so a chunk is
+        // wholly inside or past column N); separate loops with and without the skip tensor, so the
+        // stores of the plain one wait for no load
+        if (a.skip && a.out2_bf16) {
+            u32x4 kv[CPT];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = tid + u * kThreads, rl = c / (BN / 8), c8 = c % (BN / 8);
+                const int64_t row = (int64_t)m_base + rl;
+                const int col = n_base + c8 * 8;
+                kv[u] = (c < CH && row < g.M && col < g.N)
+                            ? *reinterpret_cast<const u32x4*>(a.skip + row * g.Co + col)
+                            : zero;
+            }
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = tid + u * kThreads, rl = c / (BN / 8), c8 = c % (BN / 8);
+                const int64_t row = (int64_t)m_base + rl;
+                const int col = n_base + c8 * 8;
+                if (c >= CH || row >= g.M || col >= g.N) continue;
+                const u32x4 v = *reinterpret_cast<const u32x4*>(&sT[rl * TP + c8 * 8]);
+                if (a.out_bf16) *reinterpret_cast<u32x4*>(a.out_bf16 + row * g.Co + col) = v;
+                u32x4 o;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint16_t lo = f2bf(bf2f((uint16_t)(v[q] & 0xFFFFu)) + bf2f((uint16_t)(kv[u][q] & 0xFFFFu)));
+                    const uint16_t hi = f2bf(bf2f((uint16_t)(v[q] >> 16)) + bf2f((uint16_t)(kv[u][q] >> 16)));
+                    o[q] = (uint32_t)lo | ((uint32_t)hi << 16);
+                }
+                *reinterpret_cast<u32x4*>(a.out2_bf16 + row * ld2 + col) = o;
+            }
+        } else if (a.out_bf16) {
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = tid + u * kThreads, rl = c / (BN / 8), c8 = c % (BN / 8);
+                const int64_t row = (int64_t)m_base + rl;
+                const int col = n_base + c8 * 8;
+                if (c >= CH || row >= g.M || col >= g.N) continue;
+                *reinterpret_cast<u32x4*>(a.out_bf16 + row * g.Co + col) =
+                    *reinterpret_cast<const u32x4*>(&sT[rl * TP + c8 * 8]);
+            }
+        }
+        return;
+    }
+    // data and weight gradients: FP32 straight from the accumulators.  Output pixel of row r of row
+    // tile i (a parity class's rows are a quarter of the pixels), -1 past the last row:
+    auto pixel = [&](int i, int r) __attribute__((always_inline)) -> int64_t {
+        const int64_t row = (int64_t)m_base + wm * TM + i * 16 + (lane >> 4) * 4 + r;
+        if (row >= g.M) return -1;
+        if constexpr (MODE == kDgrad) {
+            if (g.par >= 0) {
+                const int n = (int)fdiv((uint32_t)row, g.f_hinwin);
+                const int rem = (int)row - n * g.Hc * g.Wc;
+                const int qh = (int)fdiv((uint32_t)rem, g.f_win);
+                const int qw = rem - qh * g.Wc;
+                return ((int64_t)n * g.H + 2 * qh + (g.par >> 1)) * g.W + 2 * qw + (g.par & 1);
+            }
+        }
+        return row;
+    };
+    if (MODE == kDgrad && a.accumulate) {
+        // per row tile, the old values are all loaded before the tile's first store (a load issued
+        // after a store waits for it)
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            int64_t px[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) px[r] = pixel(i, r);
+            float pre[FN][4];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int col = n_base + wn * TN + j * 16 + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    pre[j][r] = (col < g.N && px[r] >= 0) ? a.out_f32[px[r] * g.C + col] : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int col = n_base + wn * TN + j * 16 + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (col < g.N && px[r] >= 0) a.out_f32[px[r] * g.C + col] = pre[j][r] + acc[i][j][r];
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int col = n_base + wn * TN + j * 16 + (lane & 15);
-            if (col >= g.N) continue;
+        for (int r = 0; r < 4; ++r) {
+            const int64_t px = pixel(i, r);
+            if (px < 0) continue;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = (int64_t)m_base + wm * TM + i * 16 + (lane >> 4) * 4 + r;
-                if (row >= g.M) continue;
-                const float v = acc[i][j][r];
-                if constexpr (MODE == kFwd) {
-                    float y = activate(v + (a.bias ? a.bias[col] : 0.f), a.relu);
-                    const int64_t o = row * g.Co + col;
-                    const uint16_t yb = f2bf(y);
-                    if (a.out_bf16) a.out_bf16[o] = yb;
-                    if (a.out_f32) a.out_f32[o] = y;
-                    if (a.skip && a.out2_bf16)
-                        a.out2_bf16[row * (a.ld_out2 ? a.ld_out2 : g.Co) + col] = f2bf(bf2f(yb) + bf2f(a.skip[o]));
-                } else if constexpr (MODE == kDgrad) {
-                    int64_t px = row;   // pixel of the row (a parity class's rows are a quarter of them)
-                    if (g.par >= 0) {
-                        const int n = (int)fdiv((uint32_t)row, g.f_hinwin);
-                        const int rem = (int)row - n * g.Hc * g.Wc;
-                        const int qh = (int)fdiv((uint32_t)rem, g.f_win);
-                        const int qw = rem - qh * g.Wc;
-                        px = ((int64_t)n * g.H + 2 * qh + (g.par >> 1)) * g.W + 2 * qw + (g.par & 1);
-                    }
-                    const int64_t o = px * g.C + col;
-                    a.out_f32[o] = a.accumulate ? a.out_f32[o] + v : v;
-                } else {
-                    a.out_f32[(int64_t)blockIdx.z * g.M * g.N + row * g.N + col] = v;
-                }
+            for (int j = 0; j < FN; ++j) {
+                const int col = n_base + wn * TN + j * 16 + (lane & 15);
+                if (col >= g.N) continue;
+                if constexpr (MODE == kDgrad)
+                    a.out_f32[px * g.C + col] = acc[i][j][r];
+                else
+                    a.out_f32[(int64_t)blockIdx.z * g.M * g.N + px * g.N + col] = acc[i][j][r];
             }
         }
     }
@@ -365,7 +467,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
 // with one output can be fused.
 constexpr int kTileH = 8, kTileW = 32;
 
-template <int C, int CO, bool UP, bool DIL = false>
+template <int C, int CO, bool UP, bool DIL = false, bool ACC = false>
 __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
 {
     // DIL: the input is dy of a stride-2 conv dilated by zeros: virtual pixel (h, w) is stored pixel
@@ -399,6 +501,11 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     const int ho0 = ty * kTileH, wo0 = tx * kTileW;
     const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
     const u32x4 zero = {0u, 0u, 0u, 0u};
+    // the epilogue's bias, read here, where its latency overlaps the staging (in the epilogue a
+    // load after a possibly aliasing store would be repeated, each waiting for memory)
+    float bias_r[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) bias_r[j] = a.bias ? a.bias[16 * j + lr] : 0.f;
 
     for (int i = tid; i < HP * WP * C8; i += 256) {
         const int c8 = i % C8, pix = i / C8;
@@ -466,28 +573,56 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     uint16_t* sO = sX;   // [kTileH * kTileW][CO]
 #pragma unroll
     for (int gi = 0; gi < 4; ++gi) {
-        const int rr = 2 * wave + (gi >> 1);
+        const int rr = 2 * wave + (gi >> 1), ho = ho0 + rr;
+        // ACC (an FP32 output accumulated into, a.accumulate): the old values of this row group,
+        // all loaded before its stores (a load issued after a store waits for it)
+        float prev[ACC ? FN : 1][4];
+        if constexpr (ACC) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int wo = wo0 + (gi & 1) * 16 + 4 * lk + q;
+                    prev[j][q] = (ho < g.Ho && wo < g.Wo)
+                                     ? a.out_f32[((n * g.Ho + ho) * g.Wo + wo) * CO + 16 * j + lr]
+                                     : 0.f;
+                }
+        }
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             const int co = 16 * j + lr;
-            const float bias = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int cc = (gi & 1) * 16 + 4 * lk + q;
-                const float y = activate(acc[gi][j][q] + bias, a.relu);
+                const float y = activate(acc[gi][j][q] + bias_r[j], a.relu);
                 sO[(rr * kTileW + cc) * CO + co] = f2bf(y);
-                const int ho = ho0 + rr, wo = wo0 + cc;
+                const int wo = wo0 + cc;
                 if (a.out_f32 && ho < g.Ho && wo < g.Wo) {
-                    float* o = a.out_f32 + ((n * g.Ho + ho) * g.Wo + wo) * CO + co;
-                    *o = a.accumulate ? *o + y : y;
+                    float yo = y;
+                    if constexpr (ACC) yo = prev[j][q] + y;
+                    a.out_f32[((n * g.Ho + ho) * g.Wo + wo) * CO + co] = yo;
                 }
             }
         }
     }
     __syncthreads();
     const int ld2 = a.ld_out2 ? a.ld_out2 : CO;
-    for (int i = tid; i < kTileH * kTileW * CO8; i += 256) {
-        const int c8 = i % CO8, pix = i / CO8;
+    // 16-byte output chunks: thread tid takes chunks tid + 256 u; the skip tensor's chunks are all
+    // loaded before the first store
+    static_assert(kTileH * kTileW == 256, "one output pixel per thread and channel group");
+    u32x4 kv[CO8];
+#pragma unroll
+    for (int u = 0; u < CO8; ++u) {
+        const int i = tid + 256 * u, c8 = i % CO8, pix = i / CO8;
+        const int rr = pix / kTileW, cc = pix - rr * kTileW;
+        const int ho = ho0 + rr, wo = wo0 + cc;
+        kv[u] = (a.skip && a.out2_bf16 && ho < g.Ho && wo < g.Wo)
+                    ? *reinterpret_cast<const u32x4*>(a.skip + ((n * g.Ho + ho) * g.Wo + wo) * CO + c8 * 8)
+                    : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < CO8; ++u) {
+        const int i = tid + 256 * u, c8 = i % CO8, pix = i / CO8;
         const int rr = pix / kTileW, cc = pix - rr * kTileW;
         const int ho = ho0 + rr, wo = wo0 + cc;
         if (ho >= g.Ho || wo >= g.Wo) continue;
@@ -495,7 +630,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
         const u32x4 v = *reinterpret_cast<const u32x4*>(&sO[pix * CO + c8 * 8]);
         if (a.out_bf16) *reinterpret_cast<u32x4*>(a.out_bf16 + op * CO + c8 * 8) = v;
         if (a.skip && a.out2_bf16) {
-            const u32x4 k = *reinterpret_cast<const u32x4*>(a.skip + op * CO + c8 * 8);
+            const u32x4 k = kv[u];
             u32x4 o;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -1556,7 +1691,12 @@ hipError_t launch_tile(const ConvGeom& g, const ConvArgs& a, hipStream_t s)
     const int64_t tiles = (int64_t)((g.Ho + kTileH - 1) / kTileH) * ((g.Wo + kTileW - 1) / kTileW);
     const int64_t blocks = tiles * (g.Kw / ((int64_t)g.Ho * g.Wo));   // Kw = N * Ho * Wo
     if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_conv3x3_tile<C, CO, UP, DIL>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
+    if (a.out_f32 && a.accumulate) {   // data gradients accumulated into (never upsampled)
+        if constexpr (UP) return hipErrorInvalidValue;
+        else hipLaunchKernelGGL((k_conv3x3_tile<C, CO, false, DIL, true>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
+    } else {
+        hipLaunchKernelGGL((k_conv3x3_tile<C, CO, UP, DIL>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
+    }
     return hipGetLastError();
 }
 
