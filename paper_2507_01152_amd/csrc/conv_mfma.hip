@@ -466,6 +466,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
 // tile is staged through LDS for 16-byte stores; the skip sum and a 1x1 head
 // with one output can be fused.
 constexpr int kTileH = 8, kTileW = 32;
+constexpr int kStageG = 4;   // staging loads in flight per thread
 
 template <int C, int CO, bool UP, bool DIL = false, bool ACC = false>
 __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
@@ -507,7 +508,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
 #pragma unroll
     for (int j = 0; j < FN; ++j) bias_r[j] = a.bias ? a.bias[16 * j + lr] : 0.f;
 
-    for (int i = tid; i < HP * WP * C8; i += 256) {
+    // staging: halo item i (pixel i / C8, channel group i % C8) and weight item i (row i / (4 NKS),
+    // k group i % (4 NKS)); a thread takes items tid + 256 u, loading kStageG of them before it
+    // stores them to LDS, so that many global round trips overlap instead of one per item
+    auto load_x = [&](int i) __attribute__((always_inline)) -> u32x4 {
         const int c8 = i % C8, pix = i / C8;
         const int hy = pix / WP, wx = pix - hy * WP;
         u32x4 v = zero;
@@ -529,14 +533,46 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
                 v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + hi) * g.W + wi) * C + c8 * 8);
             }
         }
-        *reinterpret_cast<u32x4*>(&sX[pix * PS + c8 * 8]) = v;
-    }
-    for (int i = tid; i < CO * NKS * 4; i += 256) {
+        return v;
+    };
+    auto load_w = [&](int i) __attribute__((always_inline)) -> u32x4 {
         const int co = i / (NKS * 4), k8 = i - co * (NKS * 4);
         // k8 = tap * C8 + channel group; mirrored: tap 8 - tap of the transposed copy
         const int ks = a.flip ? (8 - k8 / C8) * C8 + k8 % C8 : k8;
-        const u32x4 v = k8 < K8 ? *reinterpret_cast<const u32x4*>(a.b + (int64_t)co * (9 * C) + ks * 8) : zero;
-        *reinterpret_cast<u32x4*>(&sW[co * KP + k8 * 8]) = v;
+        return k8 < K8 ? *reinterpret_cast<const u32x4*>(a.b + (int64_t)co * (9 * C) + ks * 8) : zero;
+    };
+    constexpr int NX = HP * WP * C8, NW = CO * NKS * 4;
+    constexpr int UX = (NX + 255) / 256, UW = (NW + 255) / 256;
+#pragma unroll
+    for (int u0 = 0; u0 < UX; u0 += kStageG) {
+        u32x4 v[kStageG];
+#pragma unroll
+        for (int k = 0; k < kStageG; ++k) {
+            const int i = tid + 256 * (u0 + k);
+            v[k] = (u0 + k < UX && i < NX) ? load_x(i) : zero;
+        }
+#pragma unroll
+        for (int k = 0; k < kStageG; ++k) {
+            const int i = tid + 256 * (u0 + k);
+            if (u0 + k < UX && i < NX) *reinterpret_cast<u32x4*>(&sX[(i / C8) * PS + (i % C8) * 8]) = v[k];
+        }
+    }
+#pragma unroll
+    for (int u0 = 0; u0 < UW; u0 += kStageG) {
+        u32x4 v[kStageG];
+#pragma unroll
+        for (int k = 0; k < kStageG; ++k) {
+            const int i = tid + 256 * (u0 + k);
+            v[k] = (u0 + k < UW && i < NW) ? load_w(i) : zero;
+        }
+#pragma unroll
+        for (int k = 0; k < kStageG; ++k) {
+            const int i = tid + 256 * (u0 + k);
+            if (u0 + k < UW && i < NW) {
+                const int co = i / (NKS * 4), k8 = i - co * (NKS * 4);
+                *reinterpret_cast<u32x4*>(&sW[co * KP + k8 * 8]) = v[k];
+            }
+        }
     }
     __syncthreads();
 
