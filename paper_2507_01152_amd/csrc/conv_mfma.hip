@@ -1065,31 +1065,57 @@ __global__ __launch_bounds__(256) void k_mask_colsum(const float* g, int ldg, co
 #pragma unroll
     for (int j = 0; j < 8; ++j) sum[j] = 0.f;
     if (r_off < RP) {
-        for (int64_t r = r0 + r_off; r < r1; r += RP) {
-            const int64_t i = r * C + c8 * 8;
-            u32x4 b;
+        // kMaskRows rows per thread at a time, all their loads issued before their stores (a load
+        // issued after a store waits for it); the sums take the rows in order
+        constexpr int kMaskRows = 4;
+        for (int64_t rb = r0 + r_off; rb < r1; rb += kMaskRows * RP) {
+            u32x4 b[kMaskRows];
             if (gb) {
-                b = *reinterpret_cast<const u32x4*>(gb + i);
-            } else {
-                const float4 g0 = *reinterpret_cast<const float4*>(g + r * ldg + c8 * 8);
-                const float4 g1 = *reinterpret_cast<const float4*>(g + r * ldg + c8 * 8 + 4);
-                const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
-                u32x4 yv = {0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u};   // no mask: bf16 1.0
-                if (y) yv = *reinterpret_cast<const u32x4*>(y + i);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float ylo = __uint_as_float(yv[j] << 16), yhi = __uint_as_float(yv[j] & 0xFFFF0000u);
-                    const uint16_t lo = f2bf(ylo > 0.f ? gv[2 * j] : (slope != 0.f ? slope * gv[2 * j] : 0.f));
-                    const uint16_t hi =
-                        f2bf(yhi > 0.f ? gv[2 * j + 1] : (slope != 0.f ? slope * gv[2 * j + 1] : 0.f));
-                    b[j] = (uint32_t)lo | ((uint32_t)hi << 16);
+                for (int k = 0; k < kMaskRows; ++k) {
+                    const int64_t r = rb + k * RP;
+                    b[k] = r < r1 ? *reinterpret_cast<const u32x4*>(gb + r * C + c8 * 8) : u32x4{0u, 0u, 0u, 0u};
                 }
-                if (out) *reinterpret_cast<u32x4*>(out + i) = b;
+            } else {
+                float4 g0[kMaskRows], g1[kMaskRows];
+                u32x4 yv[kMaskRows];
+#pragma unroll
+                for (int k = 0; k < kMaskRows; ++k) {
+                    const int64_t r = rb + k * RP;
+                    yv[k] = u32x4{0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u};   // no mask: bf16 1.0
+                    g0[k] = g1[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (r < r1) {
+                        g0[k] = *reinterpret_cast<const float4*>(g + r * ldg + c8 * 8);
+                        g1[k] = *reinterpret_cast<const float4*>(g + r * ldg + c8 * 8 + 4);
+                        if (y) yv[k] = *reinterpret_cast<const u32x4*>(y + r * C + c8 * 8);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kMaskRows; ++k) {
+                    const float gv[8] = {g0[k].x, g0[k].y, g0[k].z, g0[k].w, g1[k].x, g1[k].y, g1[k].z, g1[k].w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float ylo = __uint_as_float(yv[k][j] << 16), yhi = __uint_as_float(yv[k][j] & 0xFFFF0000u);
+                        const uint16_t lo = f2bf(ylo > 0.f ? gv[2 * j] : (slope != 0.f ? slope * gv[2 * j] : 0.f));
+                        const uint16_t hi =
+                            f2bf(yhi > 0.f ? gv[2 * j + 1] : (slope != 0.f ? slope * gv[2 * j + 1] : 0.f));
+                        b[k][j] = (uint32_t)lo | ((uint32_t)hi << 16);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kMaskRows; ++k) {
+                    const int64_t r = rb + k * RP;
+                    if (out && r < r1) *reinterpret_cast<u32x4*>(out + r * C + c8 * 8) = b[k];
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                sum[2 * j] += __uint_as_float(b[j] << 16);
-                sum[2 * j + 1] += __uint_as_float(b[j] & 0xFFFF0000u);
+            for (int k = 0; k < kMaskRows; ++k) {
+                if (rb + k * RP >= r1) break;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    sum[2 * j] += __uint_as_float(b[k][j] << 16);
+                    sum[2 * j + 1] += __uint_as_float(b[k][j] & 0xFFFF0000u);
+                }
             }
         }
     }

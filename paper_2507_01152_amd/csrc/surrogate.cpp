@@ -404,7 +404,7 @@ sg_status backward(sg_ctx* c, Surrogate& s, int n)
             written[kScanSrc] = true;
         }
         // ReLU mask; the bias gradient's per-block partials are reduced with the other layers' after the loop
-        const int mb = blocks_for(rows * 16, 1024);
+        const int mb = blocks_for(rows * d.Co / 2, 1024);   // about four rows per thread
         ReduceSeg& rs = bseg.s[bseg.count++];
         rs.part_off = boff;
         rs.out_off = s.b_off[L];
@@ -598,7 +598,7 @@ sg_status disc_backward(sg_ctx* c, Surrogate& s, const uint16_t* z, int frames, 
         const int64_t rows = disc_elems(s, L + 1, frames) / kDisc[L].Co;
         const float* g_out = last ? (const float*)s.d_glog.p + disc_at(s, kNumD, off)
                                   : (const float*)s.d_g[L + 1].p + disc_at(s, L + 1, off);
-        const int mb = blocks_for(rows * 16, 1024);
+        const int mb = blocks_for(rows * kDisc[L].Co / 2, 1024);   // about four rows per thread
         SG_TRY(check(s.parts.ensure(sizeof(float) * (size_t)mb * kDisc[L].Co), "bias workspace"));
         SG_TRY(check(mask_colsum(g_out, 0, last ? nullptr : (const uint16_t*)s.d_act[L + 1].p + disc_at(s, L + 1, off),
                                  (uint16_t*)s.d_dpre.p, rows, kDisc[L].Co, (float*)s.parts.p, mb,
