@@ -607,6 +607,41 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     __syncthreads();   // sX is reused for the output tile
 
     uint16_t* sO = sX;   // [kTileH * kTileW][CO]
+    const bool pool = a.out_f32 && a.pool2;
+    if (pool) {
+        // data gradient of an upsampled input: each 2 x 2 output block summed into one pixel of the
+        // half-size out_f32, as (top pair) + (bottom pair).  Wave w holds output rows 2 w (row tile
+        // gi = h) and 2 w + 1 (gi = h + 2) of column half h; a lane the column pairs (q, q + 1), q = 0, 2.
+        const int Hc = g.Ho >> 1, Wc = g.Wo >> 1, hc = (ho0 >> 1) + wave;
+        float pv[ACC ? FN : 1][2][2];   // ACC: the old values, all loaded before the stores
+        if constexpr (ACC) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int pr = 0; pr < 2; ++pr) {
+                        const int wc = ((wo0 + h * 16 + 4 * lk) >> 1) + pr;
+                        pv[j][h][pr] = (hc < Hc && wc < Wc) ? a.out_f32[((n * Hc + hc) * Wc + wc) * CO + 16 * j + lr]
+                                                            : 0.f;
+                    }
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int pr = 0; pr < 2; ++pr) {
+                    const int wc = ((wo0 + h * 16 + 4 * lk) >> 1) + pr;
+                    const float y00 = activate(acc[h][j][2 * pr] + bias_r[j], a.relu);
+                    const float y01 = activate(acc[h][j][2 * pr + 1] + bias_r[j], a.relu);
+                    const float y10 = activate(acc[h + 2][j][2 * pr] + bias_r[j], a.relu);
+                    const float y11 = activate(acc[h + 2][j][2 * pr + 1] + bias_r[j], a.relu);
+                    float sum = (y00 + y01) + (y10 + y11);
+                    if constexpr (ACC) sum = pv[j][h][pr] + sum;
+                    if (hc < Hc && wc < Wc) a.out_f32[((n * Hc + hc) * Wc + wc) * CO + 16 * j + lr] = sum;
+                }
+    }
 #pragma unroll
     for (int gi = 0; gi < 4; ++gi) {
         const int rr = 2 * wave + (gi >> 1), ho = ho0 + rr;
@@ -619,7 +654,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int wo = wo0 + (gi & 1) * 16 + 4 * lk + q;
-                    prev[j][q] = (ho < g.Ho && wo < g.Wo)
+                    prev[j][q] = (!pool && ho < g.Ho && wo < g.Wo)
                                      ? a.out_f32[((n * g.Ho + ho) * g.Wo + wo) * CO + 16 * j + lr]
                                      : 0.f;
                 }
@@ -633,7 +668,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
                 const float y = activate(acc[gi][j][q] + bias_r[j], a.relu);
                 sO[(rr * kTileW + cc) * CO + co] = f2bf(y);
                 const int wo = wo0 + cc;
-                if (a.out_f32 && ho < g.Ho && wo < g.Wo) {
+                if (a.out_f32 && !pool && ho < g.Ho && wo < g.Wo) {
                     float yo = y;
                     if constexpr (ACC) yo = prev[j][q] + y;
                     a.out_f32[((n * g.Ho + ho) * g.Wo + wo) * CO + co] = yo;
@@ -1829,6 +1864,7 @@ hipError_t dgrad_tile(const ConvGeom& g, const uint16_t* dy, const uint16_t* wt,
     a.flip = 1;
     a.out_f32 = dx;
     a.accumulate = accumulate;
+    a.pool2 = g.up;   // an upsampled layer's gradient at its stored input resolution
     const bool dil = g.stride == 2;
     if (f.Co == 16) return dil ? launch_dgrad_tile<16, true>(f, a, s) : launch_dgrad_tile<16, false>(f, a, s);
     return dil ? launch_dgrad_tile<32, true>(f, a, s) : launch_dgrad_tile<32, false>(f, a, s);

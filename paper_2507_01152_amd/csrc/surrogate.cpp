@@ -222,15 +222,9 @@ sg_status dgrad(sg_ctx* c, const ConvShape& sh, const uint16_t* dy, const uint16
                 DevBuf& fine)
 {
     ConvGeom g = geom_of(sh, 1);
-    if (dgrad_tile_supported(g)) {   // few channels: the tiled forward conv of dy with mirrored taps
-        if (sh.up) {
-            SG_TRY(check(fine.ensure(sizeof(float) * (size_t)g.M * sh.C), "dgrad workspace"));
-            SG_TRY(check(dgrad_tile(g, dy, wt, (float*)fine.p, 0, c->stream), "dgrad launch"));
-            return check(pool2x2_sum((float*)fine.p, dx, sh.N, sh.H, sh.W, sh.C, accumulate, c->stream),
-                         "upsample grad");
-        }
-        return check(dgrad_tile(g, dy, wt, dx, accumulate, c->stream), "dgrad launch");
-    }
+    // few channels: the tiled forward conv of dy with mirrored taps (an upsampled layer's 2 x 2 sums in
+    // its epilogue)
+    if (dgrad_tile_supported(g)) return check(dgrad_tile(g, dy, wt, dx, accumulate, c->stream), "dgrad launch");
     if (dgrad_parity_supported(g))   // stride 2, wider: one GEMM per output parity class, one launch
         return check(dgrad_parity(g, dy, wt, dx, accumulate, c->stream), "dgrad launch");
     ConvArgs a;

@@ -74,6 +74,9 @@ struct ConvArgs {
     // tiled 3x3 path only: b is the transposed copy [C][9][Co] of a layer's weights and the taps are
     // read mirrored (the data gradient as a forward conv of dy)
     int32_t flip;
+    // tiled 3x3 path only, with out_f32: the output's 2 x 2 blocks summed into one pixel of a half-size
+    // out_f32 (the data gradient of an upsampled input); Ho and Wo even
+    int32_t pool2;
 };
 
 // convolution shape of one layer (per batch)
@@ -132,7 +135,8 @@ hipError_t conv_gemm(int mode, const ConvGeom& g, const ConvArgs& a, int splits,
 bool conv_tile_supported(const ConvGeom& g);
 // data gradient of a 3x3 pad-1 conv (g: the layer's mode-1 geometry; stride 1, or stride 2 with even input
 // sizes) as a forward tiled conv of dy with mirrored taps, over dy dilated by zeros for stride 2: dx
-// [N][Hin][Win][C] FP32 (the fine-resolution gradient of an upsampled layer), written or accumulated
+// [N][H][W][C] FP32 at the stored input resolution (an upsampled layer's fine-resolution gradient summed
+// over 2 x 2 blocks in the epilogue), written or accumulated
 bool dgrad_tile_supported(const ConvGeom& g);
 // data gradient of a stride-2, pad-1 3x3 conv (g: mode-1 geometry) as four implicit GEMMs, one per output
 // parity class, each over only the taps that reach it (a quarter of the full gather's products)
