@@ -455,9 +455,10 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Direct 3x3 convolution (stride 1, pad 1) for few channels.  A block computes
-// an 8 x 32 pixel output tile of one image for all CO output channels.  The
-// input tile with its one-pixel halo (10 x 34 pixels, zero outside the image;
+// Direct 3x3 convolution (stride 1, pad 1) for few channels.  A block of TH / 2
+// waves computes a TH x 32 pixel output tile of one image for all CO output
+// channels.  The
+// input tile with its one-pixel halo ((TH + 2) x 34 pixels, zero outside the image;
 // with upsampling, fine pixel (h, w) reads stored pixel (h / 2, w / 2)) and
 // all weights are staged in LDS once, and the MFMA operands are read from
 // there, so each input pixel leaves global memory once per tile instead of
@@ -465,18 +466,23 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
 // the 16-byte operand reads of a wave are free of bank conflicts.  The output
 // tile is staged through LDS for 16-byte stores; the skip sum and a 1x1 head
 // with one output can be fused.
-constexpr int kTileH = 8, kTileW = 32;
+// 16 x 32 tiles (eight waves): against 8 x 32 ones, the weights staged per
+// block serve twice the pixels and the halo adds 1/8 instead of 1/4 of the
+// input rows (the 1024-frame forward's tiled layers took 3.3 instead of
+// 3.6 ms; 32-row tiles were slower again)
+constexpr int kTileH = 16, kTileW = 32;
 constexpr int kStageG = 4;   // staging loads in flight per thread
 
-template <int C, int CO, bool UP, bool DIL = false, bool ACC = false>
-__global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
+template <int C, int CO, bool UP, bool DIL = false, bool ACC = false, int TH = kTileH>
+__global__ __launch_bounds__(32 * TH) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
 {
     // DIL: the input is dy of a stride-2 conv dilated by zeros: virtual pixel (h, w) is stored pixel
     // (h / 2, w / 2) when both are even, else 0 (the data gradient of that conv as a stride-1 conv)
     // UP: the input is read upsampled x2; the tile stages the stored pixels it
-    // covers (fine halo pixel (hy, wx) of the 10 x 34 window is stored pixel
-    // ((hy + 1) / 2, (wx + 1) / 2) of a 6 x 18 window, tile origins being even)
-    constexpr int HP = UP ? kTileH / 2 + 2 : kTileH + 2, WP = UP ? kTileW / 2 + 2 : kTileW + 2;
+    // covers (fine halo pixel (hy, wx) of the (TH + 2) x 34 window is stored pixel
+    // ((hy + 1) / 2, (wx + 1) / 2) of a (TH / 2 + 2) x 18 window, tile origins being even)
+    constexpr int NT = 32 * TH;   // threads: TH / 2 waves of two output rows each
+    constexpr int HP = UP ? TH / 2 + 2 : TH + 2, WP = UP ? kTileW / 2 + 2 : kTileW + 2;
     constexpr int C8 = C / 8;
     constexpr int PS = (C8 % 2 == 0) ? C + 8 : C;   // LDS pixel stride (bf16)
     constexpr int K8 = 9 * C8;                       // 8-wide K groups
@@ -484,13 +490,13 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     constexpr int KP = NKS * 32 + 8;                 // LDS weight row (bf16), zero beyond K
     constexpr int FN = CO / 16;
     constexpr int CO8 = CO / 8;
-    constexpr int XS = HP * WP * PS, OS = kTileH * kTileW * CO;
+    constexpr int XS = HP * WP * PS, OS = TH * kTileW * CO;
     __shared__ __attribute__((aligned(16))) uint16_t sX[XS > OS ? XS : OS];
     __shared__ __attribute__((aligned(16))) uint16_t sW[CO * KP];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int tiles_x = (g.Wo + kTileW - 1) / kTileW, tiles_y = (g.Ho + kTileH - 1) / kTileH;
+    const int tiles_x = (g.Wo + kTileW - 1) / kTileW, tiles_y = (g.Ho + TH - 1) / TH;
     // neighbouring tiles on the same XCD (blocks are dealt round-robin over 8)
     int64_t b = blockIdx.x;
     const int64_t nb = gridDim.x;
@@ -499,7 +505,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     const int64_t n = b / per_img;
     const int t_in = (int)(b - n * per_img);
     const int ty = t_in / tiles_x, tx = t_in - ty * tiles_x;
-    const int ho0 = ty * kTileH, wo0 = tx * kTileW;
+    const int ho0 = ty * TH, wo0 = tx * kTileW;
     const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
     const u32x4 zero = {0u, 0u, 0u, 0u};
     // the epilogue's bias, read here, where its latency overlaps the staging (in the epilogue a
@@ -509,7 +515,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     for (int j = 0; j < FN; ++j) bias_r[j] = a.bias ? a.bias[16 * j + lr] : 0.f;
 
     // staging: halo item i (pixel i / C8, channel group i % C8) and weight item i (row i / (4 NKS),
-    // k group i % (4 NKS)); a thread takes items tid + 256 u, loading kStageG of them before it
+    // k group i % (4 NKS)); a thread takes items tid + NT u, loading kStageG of them before it
     // stores them to LDS, so that many global round trips overlap instead of one per item
     auto load_x = [&](int i) __attribute__((always_inline)) -> u32x4 {
         const int c8 = i % C8, pix = i / C8;
@@ -542,18 +548,18 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
         return k8 < K8 ? *reinterpret_cast<const u32x4*>(a.b + (int64_t)co * (9 * C) + ks * 8) : zero;
     };
     constexpr int NX = HP * WP * C8, NW = CO * NKS * 4;
-    constexpr int UX = (NX + 255) / 256, UW = (NW + 255) / 256;
+    constexpr int UX = (NX + NT - 1) / NT, UW = (NW + NT - 1) / NT;
 #pragma unroll
     for (int u0 = 0; u0 < UX; u0 += kStageG) {
         u32x4 v[kStageG];
 #pragma unroll
         for (int k = 0; k < kStageG; ++k) {
-            const int i = tid + 256 * (u0 + k);
+            const int i = tid + NT * (u0 + k);
             v[k] = (u0 + k < UX && i < NX) ? load_x(i) : zero;
         }
 #pragma unroll
         for (int k = 0; k < kStageG; ++k) {
-            const int i = tid + 256 * (u0 + k);
+            const int i = tid + NT * (u0 + k);
             if (u0 + k < UX && i < NX) *reinterpret_cast<u32x4*>(&sX[(i / C8) * PS + (i % C8) * 8]) = v[k];
         }
     }
@@ -562,12 +568,12 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
         u32x4 v[kStageG];
 #pragma unroll
         for (int k = 0; k < kStageG; ++k) {
-            const int i = tid + 256 * (u0 + k);
+            const int i = tid + NT * (u0 + k);
             v[k] = (u0 + k < UW && i < NW) ? load_w(i) : zero;
         }
 #pragma unroll
         for (int k = 0; k < kStageG; ++k) {
-            const int i = tid + 256 * (u0 + k);
+            const int i = tid + NT * (u0 + k);
             if (u0 + k < UW && i < NW) {
                 const int co = i / (NKS * 4), k8 = i - co * (NKS * 4);
                 *reinterpret_cast<u32x4*>(&sW[co * KP + k8 * 8]) = v[k];
@@ -606,7 +612,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     }
     __syncthreads();   // sX is reused for the output tile
 
-    uint16_t* sO = sX;   // [kTileH * kTileW][CO]
+    uint16_t* sO = sX;   // [TH * kTileW][CO]
     const bool pool = a.out_f32 && a.pool2;
     if (pool) {
         // data gradient of an upsampled input: each 2 x 2 output block summed into one pixel of the
@@ -678,13 +684,13 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     }
     __syncthreads();
     const int ld2 = a.ld_out2 ? a.ld_out2 : CO;
-    // 16-byte output chunks: thread tid takes chunks tid + 256 u; the skip tensor's chunks are all
+    // 16-byte output chunks: thread tid takes chunks tid + NT u; the skip tensor's chunks are all
     // loaded before the first store
-    static_assert(kTileH * kTileW == 256, "one output pixel per thread and channel group");
+    static_assert(TH * kTileW == NT, "one output pixel per thread and channel group");
     u32x4 kv[CO8];
 #pragma unroll
     for (int u = 0; u < CO8; ++u) {
-        const int i = tid + 256 * u, c8 = i % CO8, pix = i / CO8;
+        const int i = tid + NT * u, c8 = i % CO8, pix = i / CO8;
         const int rr = pix / kTileW, cc = pix - rr * kTileW;
         const int ho = ho0 + rr, wo = wo0 + cc;
         kv[u] = (a.skip && a.out2_bf16 && ho < g.Ho && wo < g.Wo)
@@ -693,7 +699,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     }
 #pragma unroll
     for (int u = 0; u < CO8; ++u) {
-        const int i = tid + 256 * u, c8 = i % CO8, pix = i / CO8;
+        const int i = tid + NT * u, c8 = i % CO8, pix = i / CO8;
         const int rr = pix / kTileW, cc = pix - rr * kTileW;
         const int ho = ho0 + rr, wo = wo0 + cc;
         if (ho >= g.Ho || wo >= g.Wo) continue;
@@ -714,7 +720,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
     }
     if (a.extra && a.out2_bf16) {
         const int E8 = a.extra_c / 8;
-        for (int i = tid; i < kTileH * kTileW * E8; i += 256) {
+        for (int i = tid; i < TH * kTileW * E8; i += NT) {
             const int e8 = i % E8, pix = i / E8;
             const int rr = pix / kTileW, cc = pix - rr * kTileW;
             const int ho = ho0 + rr, wo = wo0 + cc;
@@ -724,7 +730,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
                 *reinterpret_cast<const u32x4*>(a.extra + op * a.extra_c + e8 * 8);
         }
     }
-    if (a.head_out && tid < kTileH * kTileW) {
+    if (a.head_out && tid < TH * kTileW) {
         const int rr = tid / kTileW, cc = tid - rr * kTileW;
         const int ho = ho0 + rr, wo = wo0 + cc;
         if (ho < g.Ho && wo < g.Wo) {
@@ -1778,21 +1784,23 @@ bool conv_tile_supported(const ConvGeom& g)
 {
     const bool shape = g.kh == 3 && g.kw == 3 && g.stride == 1 && g.pad == 1 && (g.Co == 16 || g.Co == 32) &&
                        g.Ho == (g.up ? 2 * g.H : g.H) && g.Wo == (g.up ? 2 * g.W : g.W);
-    // 64 input channels only upsampled, where the staged tile is the 6 x 18 stored one
+    // 64 input channels only upsampled, where the staged tile is the 10 x 18 stored one
     return shape && (g.C == 8 || g.C == 16 || g.C == 24 || g.C == 32 || (g.C == 64 && g.up && g.Co == 32));
 }
 
 template <int C, int CO, bool UP, bool DIL = false>
 hipError_t launch_tile(const ConvGeom& g, const ConvArgs& a, hipStream_t s)
 {
-    const int64_t tiles = (int64_t)((g.Ho + kTileH - 1) / kTileH) * ((g.Wo + kTileW - 1) / kTileW);
+    constexpr int TH = kTileH;
+    const int64_t tiles = (int64_t)((g.Ho + TH - 1) / TH) * ((g.Wo + kTileW - 1) / kTileW);
     const int64_t blocks = tiles * (g.Kw / ((int64_t)g.Ho * g.Wo));   // Kw = N * Ho * Wo
     if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
     if (a.out_f32 && a.accumulate) {   // data gradients accumulated into (never upsampled)
         if constexpr (UP) return hipErrorInvalidValue;
-        else hipLaunchKernelGGL((k_conv3x3_tile<C, CO, false, DIL, true>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
+        else hipLaunchKernelGGL((k_conv3x3_tile<C, CO, false, DIL, true, TH>), dim3((unsigned)blocks), dim3(32 * TH), 0, s,
+                                g, a);
     } else {
-        hipLaunchKernelGGL((k_conv3x3_tile<C, CO, UP, DIL>), dim3((unsigned)blocks), dim3(256), 0, s, g, a);
+        hipLaunchKernelGGL((k_conv3x3_tile<C, CO, UP, DIL, false, TH>), dim3((unsigned)blocks), dim3(32 * TH), 0, s, g, a);
     }
     return hipGetLastError();
 }

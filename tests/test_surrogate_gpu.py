@@ -41,15 +41,15 @@ CONV_CASES = [
     (3, 11, 5, 24, 40, 1, 1, 0, 0),      # 1x1, channel counts not powers of two
     (2, 9, 70, 16, 8, 1, 1, 0, 0),       # 1x1 to 8 channels (the depth map), K below one MFMA step
     (1, 12, 10, 24, 16, 3, 1, 1, 0),     # 24 input channels (the last decoder conv)
-    # LDS-tiled direct 3x3 path (stride 1, pad 1, C <= 32, Co 16 or 32): 8 x 32 tiles
+    # LDS-tiled direct 3x3 path (stride 1, pad 1, C <= 32, Co 16 or 32): 16 x 32 tiles
     (2, 19, 70, 16, 16, 3, 1, 1, 0),     # ragged tiles in both directions
     (1, 7, 11, 32, 16, 3, 1, 1, 1),      # upsampled to 14 x 22
     (2, 10, 33, 16, 32, 3, 1, 1, 0),     # 32 output channels
     (1, 9, 40, 32, 32, 3, 1, 1, 1),      # upsampled, 32 -> 32
-    # upsampled inputs staged as coarse tiles (6 x 18 stored pixels per 8 x 32 output tile)
+    # upsampled inputs staged as coarse tiles (10 x 18 stored pixels per 16 x 32 output tile)
     (2, 6, 20, 64, 32, 3, 1, 1, 1),      # 64 -> 32 (the U1 shape), ragged tiles in both directions
     (1, 13, 9, 32, 16, 3, 1, 1, 1),      # 32 -> 16 (the U0 shape), odd stored sizes
-    # more 8 x 32 tiles than the weight gradient's 512 blocks: blocks accumulate several tiles
+    # more 8 x 32 weight-gradient tiles than its 512 blocks: blocks accumulate several tiles
     (20, 48, 130, 8, 16, 3, 1, 1, 0),    # 600 tiles, ragged last column tile
     (8, 40, 100, 32, 32, 3, 1, 1, 1),    # upsampled to 80 x 200: 560 tiles
     # wider layers: the direct weight gradient in groups of 32 input x 32 output channels
