@@ -1282,6 +1282,73 @@ __global__ __launch_bounds__(256) void k_depth_map_scan_fwd(const uint16_t* __re
     }
 }
 
+// k_depth_map_scan_fwd for columns of at most kScan1Seg * kScan1Rows rows, reading e once: a block
+// owns kScan1Cols neighbouring columns split into kScan1Seg segments of at most kScan1Rows rows, one
+// thread per (segment, column), which keeps its rows' maps p in registers between the segment sum
+// and the running sums (the two-pass kernel reads e again for those).
+constexpr int kScan1Cols = 8, kScan1Seg = 32, kScan1Rows = 8;
+__global__ __launch_bounds__(256) void k_depth_map_scan_fwd1(const uint16_t* __restrict__ e,
+                                                             const uint16_t* __restrict__ w,
+                                                             const float* __restrict__ b, uint16_t* __restrict__ out,
+                                                             int N, int H, int W, float scale, int ld, int c_off)
+{
+    static_assert(kScan1Cols * kScan1Seg == 256, "one thread per (segment, column)");
+    __shared__ float sw[kScanC * 16];
+    __shared__ float sb[kScanC];
+    __shared__ float tot[kScan1Seg][kScanC][kScan1Cols + 1];
+    if (threadIdx.x < kScanC * 16) sw[threadIdx.x] = bf2f(w[threadIdx.x]);
+    if (threadIdx.x < kScanC) sb[threadIdx.x] = b[threadIdx.x];
+    __syncthreads();
+    const int c = threadIdx.x % kScan1Cols, sg = threadIdx.x / kScan1Cols;
+    const int64_t col = (int64_t)blockIdx.x * kScan1Cols + c;
+    const bool live = col < (int64_t)N * W;
+    const int64_t n = live ? col / W : 0;
+    const int x = live ? (int)(col - n * W) : 0;
+    const int seg = (H + kScan1Seg - 1) / kScan1Seg;   // <= kScan1Rows (host check)
+    const int ya = live ? min(sg * seg, H) : 0, yb = live ? min(ya + seg, H) : 0;
+    const uint16_t* ec = e + (n * H * W + x) * 16;   // column base; row stride W * 16
+    u32x4 a0[kScan1Rows], a1[kScan1Rows];
+#pragma unroll
+    for (int q = 0; q < kScan1Rows; ++q) {   // every row's loads before any use
+        const int64_t o = (int64_t)min(ya + q, max(yb - 1, 0)) * W * 16;
+        a0[q] = *reinterpret_cast<const u32x4*>(ec + o);
+        a1[q] = *reinterpret_cast<const u32x4*>(ec + o + 8);
+    }
+    float pr[kScan1Rows][kScanC], sum[kScanC];
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) sum[k] = 0.f;
+#pragma unroll
+    for (int q = 0; q < kScan1Rows; ++q) {
+        depth_map(a0[q], a1[q], sw, sb, pr[q]);
+        if (ya + q < yb) {
+#pragma unroll
+            for (int k = 0; k < kScanC; ++k) sum[k] += pr[q][k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) tot[sg][k][c] = sum[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanC; ++k) {
+        float o = 0.f;
+        for (int q = 0; q < sg; ++q) o += tot[q][k][c];
+        sum[k] = o;   // running sum over the rows above this segment
+    }
+    uint16_t* oc = out + (n * H * W + x) * ld + c_off;
+#pragma unroll
+    for (int q = 0; q < kScan1Rows; ++q) {
+        const int y = ya + q;
+        if (y >= yb) break;
+        u32x4 ov;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            ov[j] = (uint32_t)f2bf(scale * sum[2 * j]) | ((uint32_t)f2bf(scale * sum[2 * j + 1]) << 16);
+        *reinterpret_cast<u32x4*>(oc + (int64_t)y * W * ld) = ov;
+#pragma unroll
+        for (int k = 0; k < kScanC; ++k) sum[k] += pr[q][k];
+    }
+}
+
 // Backward of k_depth_map_scan_fwd after the 1x1 map, through a tensor g
 // [pixel][ld] (FP32) whose channels [c_off, c_off + 8) are the integral's
 // gradient:  dp[n][v][x][k] = bf16(scale * sum_{y > v} g[n][y][x][c_off + k]),
@@ -2052,6 +2119,12 @@ hipError_t depth_map_scan_fwd(const uint16_t* e, const uint16_t* w, const float*
                               int W, float scale, int ld, int c_off, hipStream_t s)
 {
     if (ld % 8 || c_off % 8 || c_off + kScanC > ld) return hipErrorInvalidValue;
+    if (H <= kScan1Seg * kScan1Rows) {   // one read of e
+        const int64_t blocks = ((int64_t)N * W + kScan1Cols - 1) / kScan1Cols;
+        hipLaunchKernelGGL(k_depth_map_scan_fwd1, dim3((unsigned)blocks), dim3(256), 0, s, e, w, b, out, N, H, W, scale,
+                           ld, c_off);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_depth_map_scan_fwd, dim3((unsigned)depth_scan_blocks(N, W)), dim3(256), 0, s, e, w, b, out, N,
                        H, W, scale, ld, c_off);
     return hipGetLastError();
