@@ -10,12 +10,17 @@
 //                                  (k = (r, s, co); WT = [Ci][kh][kw][Co])
 //   weight gr C[co][(r, s, ci)]  = sum_pixels dy[pixel][co] * x(shifted)[pixel][ci]
 // A block tile (BM x BN) is built from 4 waves, each owning FM x FN tiles of
-// v_mfma_f32_16x16x32_bf16; operands are staged through double-buffered LDS
-// (rows padded to 80 bytes).  The forward / data-gradient operands are
-// contiguous along K and are written to LDS with 16-byte stores; the
-// weight-gradient operands are contiguous along the channel (M / N) axis and
-// are transposed into LDS.  The weight gradient splits K (pixels) over
-// blocks and sums the partial tiles in a fixed order (deterministic).
+// v_mfma_f32_16x16x32_bf16.  The forward / data-gradient operands are
+// contiguous along K: they go from global memory straight into a three-stage
+// LDS ring by DMA (global_load_lds, 16 bytes a lane, two K steps ahead; no
+// staging registers), in unpadded 64-byte rows whose 16-byte chunks are
+// XOR-swizzled so the MFMA operand reads are free of bank conflicts.  Where the
+// channel count is a multiple of 32 each K step is one tap's 32 channels, and
+// the gather addresses are set once per tap.  The weight-gradient operands are
+// contiguous along the channel (M / N) axis and are transposed into
+// double-buffered LDS (rows padded to 80 bytes) through registers.  The weight
+// gradient splits K (pixels) over blocks and sums the partial tiles in a fixed
+// order (deterministic).
 // A conv may read its input through a nearest-neighbour x2 upsampling
 // (decoder layers): the gather maps (h, w) to (h / 2, w / 2).
 #include <hip/hip_runtime.h>
@@ -58,6 +63,24 @@ __device__ __forceinline__ float bf2f(uint16_t b)
 
 enum Mode { kFwd = 0, kDgrad = 1, kWgrad = 2 };
 
+// LDS DMA operand rows are 64 bytes (four 16-byte K chunks) with no padding; K chunk q of row
+// r sits in slot q ^ swz(r).  The 16 rows read by one MFMA operand load then put their chunks
+// in 16 distinct 16-byte bank groups of 256 bytes (and any 8 consecutive rows in 8 of 128).
+__device__ __forceinline__ int swz(int r) { return ((r >> 2) ^ (r >> 1)) & 3; }
+// source of the DMA loads of padding and out-of-tile chunks (the DMA writes what it reads):
+// 4096 bf16, so that a padding chunk can be advanced by any channel offset below C (C <= 4096)
+__device__ __attribute__((aligned(16))) uint16_t g_zero_buf[4096];
+// one 16-byte global -> LDS DMA load per lane: lane i of the wave writes dst_wave + 16 i, where
+// dst_wave must be the same for the whole wave (it goes through M0).  A function of its own: the
+// builtin called straight from a lambda inside a kernel template leaves that kernel without a
+// host launch stub, with no diagnostic.
+__device__ __forceinline__ void dma16(const uint16_t* src, uint16_t* dst_wave)
+{
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst_wave, 16, 0, 0);
+}
+// s_waitcnt immediate with expcnt and lgkmcnt at their maxima: OR in a vmcnt below 16
+constexpr int kWaitVm0 = 0x0F70;
+
 template <int MODE, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
 {
@@ -88,10 +111,15 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
     constexpr int PB = RPC * ((CB + kThreads - 1) / kThreads);
     constexpr int AM8 = BM / 8, BN8 = BN / 8;   // weight-gradient row groups
 
-    // double-buffered operand tiles; the forward epilogue reuses the space for its output tile
-    __shared__ __attribute__((aligned(16))) uint16_t smem[2 * (BM + BN) * kBKP];
-    uint16_t (*sA)[BM * kBKP] = reinterpret_cast<uint16_t (*)[BM * kBKP]>(smem);
-    uint16_t (*sB)[BN * kBKP] = reinterpret_cast<uint16_t (*)[BN * kBKP]>(smem + 2 * BM * kBKP);
+    // operand tiles: the K-contiguous products fill a three-stage ring of unpadded 64-byte rows
+    // straight from global memory (LDS DMA); the weight gradient double-buffers padded rows
+    // through registers.  The forward epilogue reuses the space for its output tile.
+    constexpr bool DMA = MODE != kWgrad;
+    constexpr int NS = DMA ? 3 : 2, RL = DMA ? kBK : kBKP;   // stages, LDS row length
+    constexpr int SMEM_OPS = NS * (BM + BN) * RL, SMEM_OUT = (MODE == kFwd) ? BM * (BN + 8) : 0;
+    __shared__ __attribute__((aligned(16))) uint16_t smem[SMEM_OPS > SMEM_OUT ? SMEM_OPS : SMEM_OUT];
+    uint16_t (*sA)[BM * RL] = reinterpret_cast<uint16_t (*)[BM * RL]>(smem);
+    uint16_t (*sB)[BN * RL] = reinterpret_cast<uint16_t (*)[BN * RL]>(smem + NS * BM * RL);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -113,8 +141,9 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
     const int Hin = g.up ? 2 * g.H : g.H, Win = g.up ? 2 * g.W : g.W;
 
     // ---- per-thread chunk bookkeeping, fixed over the K loop ----
-    // K-contiguous modes: chunk c = tid + i * 256 -> (row c / 4, k8 = tid % 4)
-    const int k8 = tid & 3;
+    // K-contiguous modes: chunk c = tid + i * 256 -> LDS row c / 4, 16-byte slot c % 4, which holds
+    // K chunk k8 = slot ^ swz(row); swz depends on row bits 1..3 only, so k8 is fixed per thread
+    const int k8 = DMA ? (tid & 3) ^ swz(tid >> 2) : tid & 3;
     int a_hb[PA], a_wb[PA];       // forward: ho*s - pad, wo*s - pad; data grad: h + pad, w + pad
     int64_t a_base[PA];           // element offset of the row's image (or -1: row outside M)
     // weight gradient: fixed channel group of A (dy) and of B (x)
@@ -244,6 +273,116 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
                         : zero;
         }
     };
+    // one stage of the LDS-DMA ring: each lane fetches its 16-byte chunk (a zero chunk where the
+    // operand is padding or past the tile) into slot c of the stage; the 64 lanes of a wave fill
+    // 64 consecutive slots, so the LDS address passed is the wave's first slot, a scalar.
+    // The zero buffer's address is taken once (readfirstlane returns int: each half goes through
+    // uint32_t, or the low half sign-extends).
+    const uint64_t zp = reinterpret_cast<uint64_t>(g_zero_buf);
+    const uint32_t zhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(zp >> 32));
+    const uint32_t zlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)zp);
+    const uint16_t* zsrc = reinterpret_cast<const uint16_t*>(((uint64_t)zhi << 32) | zlo);
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const FastDiv fcc = (MODE == kFwd) ? g.f_c : g.f_co;
+    const int cc = (MODE == kFwd) ? g.C : g.Co;   // channels of one tap along K
+    // tap (r, s) of tap index t, and the column of B where the tap's channels start
+    auto tap_of = [&](int t, int& r, int& s, int& kfb) __attribute__((always_inline)) {
+        if (MODE == kDgrad && g.par >= 0) {
+            // class taps: rows r in {1} (even h) or {0, 2} (odd h), columns s likewise, row-major
+            const int pa = g.par >> 1, pb = g.par & 1;
+            const int tr = pb ? t >> 1 : t, ts = pb ? t & 1 : 0;
+            r = pa ? 2 * tr : 1;
+            s = pb ? 2 * ts : 1;
+            kfb = (r * 3 + s) * cc;
+        } else {
+            r = (int)fdiv((uint32_t)t, g.f_kw);
+            s = t - r * g.kw;
+            kfb = t * cc;
+        }
+    };
+    // element offset of tap (r, s), channel c0, inside row i's image; false where it is padding
+    auto a_tap = [&](int i, int r, int s, int c0, int& off) __attribute__((always_inline)) -> bool {
+        if constexpr (MODE == kFwd) {
+            const int hi = a_hb[i] + r, wi = a_wb[i] + s;
+            off = ((hi >> g.up) * g.W + (wi >> g.up)) * g.C + c0;
+            return a_base[i] >= 0 && (unsigned)hi < (unsigned)Hin && (unsigned)wi < (unsigned)Win;
+        } else {
+            const int hh = a_hb[i] - r, ww = a_wb[i] - s;
+            const int ho = (int)fdiv((uint32_t)hh, g.f_stride), wo = (int)fdiv((uint32_t)ww, g.f_stride);
+            off = (ho * g.Wo + wo) * g.Co + c0;
+            return a_base[i] >= 0 && hh >= 0 && ww >= 0 && ho * g.stride == hh && wo * g.stride == ww &&
+                   ho < g.Ho && wo < g.Wo;
+        }
+    };
+    // general K steps (C not a multiple of 32: a step's chunks may fall in different taps, or past K)
+    auto issue_stage = [&](int64_t k0, int st) __attribute__((always_inline)) {
+        const int k = (int)k0 + k8 * 8;
+        const bool kin = k < g.K;
+        int r = 0, s = 0, c0 = 0, kf = k;
+        if (kin) {
+            const int t = (int)fdiv((uint32_t)k, fcc);
+            c0 = k - t * cc;
+            int kfb;
+            tap_of(t, r, s, kfb);
+            kf = kfb + c0;
+        }
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            if (wv * 64 + i * kThreads >= CA) continue;   // CA is a multiple of 64
+            int off;
+            const bool ok = a_tap(i, r, s, c0, off) && kin;
+            dma16(ok ? A + a_base[i] + off : zsrc, &sA[st][(wv * 64 + i * kThreads) * 8]);
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            if (wv * 64 + i * kThreads >= CB) continue;
+            const int col = n_base + ((tid + i * kThreads) >> 2);
+            dma16((kin && col < g.N) ? B + (int64_t)col * g.kb + kf : zsrc, &sB[st][(wv * 64 + i * kThreads) * 8]);
+        }
+    };
+    // tap steps (C a multiple of 32: each K step is 32 channels of one tap, and K = nk * 32): the
+    // chunk pointers are set once per tap (pointing at channel 0 plus this lane's 8 k, or into the
+    // zero buffer) and a step adds its channel offset
+    const uint16_t* tpa[PA];
+    const uint16_t* tpb[PB];
+    int cur_t = -1;
+    auto issue_tap = [&](int64_t k0, int st) __attribute__((always_inline)) {
+        const int t = (int)fdiv((uint32_t)k0, fcc);
+        const int c0 = (int)k0 - t * cc;
+        if (t != cur_t) {
+            cur_t = t;
+            int r, s, kfb;
+            tap_of(t, r, s, kfb);
+#pragma unroll
+            for (int i = 0; i < PA; ++i) {
+                if (wv * 64 + i * kThreads >= CA) continue;
+                int off;
+                const bool ok = a_tap(i, r, s, 0, off);
+                tpa[i] = (ok ? A + a_base[i] + off : zsrc) + k8 * 8;
+            }
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                if (wv * 64 + i * kThreads >= CB) continue;
+                const int col = n_base + ((tid + i * kThreads) >> 2);
+                tpb[i] = (col < g.N ? B + (int64_t)col * g.kb + kfb : zsrc) + k8 * 8;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PA; ++i) {
+            if (wv * 64 + i * kThreads >= CA) continue;
+            dma16(tpa[i] + c0, &sA[st][(wv * 64 + i * kThreads) * 8]);
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            if (wv * 64 + i * kThreads >= CB) continue;
+            dma16(tpb[i] + c0, &sB[st][(wv * 64 + i * kThreads) * 8]);
+        }
+    };
+    const bool tap_steps = cc % kBK == 0;
+    auto issue = [&](int64_t k0, int st) __attribute__((always_inline)) {
+        if (tap_steps) issue_tap(k0, st);
+        else issue_stage(k0, st);
+    };
     // four (8 rows, k) chunks of consecutive k -> row j's 4 k as one 8-byte value
     auto transpose_store = [&](uint16_t* dst, const u32x4* r, int row0, int kk) __attribute__((always_inline)) {
 #pragma unroll
@@ -298,22 +437,54 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
         bias_r[j] = (MODE == kFwd && a.bias && col < g.N) ? a.bias[col] : 0.f;
     }
 
+    const int frow = lane & 15, fk = (lane >> 4) * 8;
+    if constexpr (DMA) {
+        // a wave waits for its own DMA of stage kt (vmcnt counts in issue order: at most the next
+        // stage's loads may remain), then the barrier makes every wave's chunks visible and
+        // retires the reads of the stage the next issue overwrites.  LW is the fewest DMA loads
+        // any wave issues per stage; a wave with more waits for part of the next stage too.
+        constexpr int LW = ((CA - 192 + kThreads - 1) / kThreads) + (CB > 192 ? (CB - 192 + kThreads - 1) / kThreads : 0);
+        static_assert(LW >= 1 && LW < 16, "per-wave DMA loads per stage");
+        const int rd = frow * kBK + (((lane >> 4) ^ swz(frow)) * 8);
+        if (nk > 0) issue(k_begin, 0);
+        if (nk > 1) issue(k_begin + kBK, 1);
+        for (int kt = 0; kt < nk; ++kt) {
+            const int st = kt % 3;
+            if (kt + 1 < nk) __builtin_amdgcn_s_waitcnt(kWaitVm0 | LW);
+            else __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (kt + 2 < nk) issue(k_begin + (int64_t)(kt + 2) * kBK, (kt + 2) % 3);
+            bf16x8 fa[FM], fb[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                fa[i] = *reinterpret_cast<const bf16x8*>(&sA[st][(wm * TM + i * 16) * kBK + rd]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                fb[j] = *reinterpret_cast<const bf16x8*>(&sB[st][(wn * TN + j * 16) * kBK + rd]);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+    } else {
     if (nk > 0) {
         load_tiles(k_begin);
         store_tiles(0);
     }
     __syncthreads();
-    const int frow = lane & 15, fk = (lane >> 4) * 8;
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) load_tiles(k_begin + (int64_t)(kt + 1) * kBK);
         bf16x8 fa[FM], fb[FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
-            fa[i] = *reinterpret_cast<const bf16x8*>(&sA[buf][(wm * TM + i * 16 + frow) * kBKP + fk]);
+            fa[i] = *reinterpret_cast<const bf16x8*>(&sA[buf][(wm * TM + i * 16 + frow) * RL + fk]);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-            fb[j] = *reinterpret_cast<const bf16x8*>(&sB[buf][(wn * TN + j * 16 + frow) * kBKP + fk]);
+            fb[j] = *reinterpret_cast<const bf16x8*>(&sB[buf][(wn * TN + j * 16 + frow) * RL + fk]);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -322,6 +493,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
         if (kt + 1 < nk) store_tiles(buf ^ 1);
         __syncthreads();
     }
+    }
 
     // epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each tile
     if constexpr (MODE == kFwd) {
@@ -329,7 +501,6 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
         // chunks are all loaded before the first store (a load issued after a store waits for it:
         // one memory round trip per element otherwise)
         constexpr int TP = BN + 8;
-        static_assert(BM * TP <= 2 * (BM + BN) * kBKP, "output tile fits the operand buffers");
         uint16_t* sT = smem;
         __syncthreads();   // every wave is done with the operand tiles
 #pragma unroll
