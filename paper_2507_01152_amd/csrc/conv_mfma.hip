@@ -631,9 +631,9 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
 // channels.  The
 // input tile with its one-pixel halo ((TH + 2) x 34 pixels, zero outside the image;
 // with upsampling, fine pixel (h, w) reads stored pixel (h / 2, w / 2)) and
-// all weights are staged in LDS once, and the MFMA operands are read from
-// there, so each input pixel leaves global memory once per tile instead of
-// once per tap.  LDS pixel and weight rows are odd multiples of 16 bytes, so
+// all weights are staged in LDS once (by DMA, every chunk in flight at once),
+// and the MFMA operands are read from there, so each input pixel leaves global
+// memory once per tile instead of once per tap.  LDS pixel and weight rows are odd multiples of 16 bytes, so
 // the 16-byte operand reads of a wave are free of bank conflicts.  The output
 // tile is staged through LDS for 16-byte stores; the skip sum and a 1x1 head
 // with one output can be fused.
@@ -642,7 +642,6 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
 // input rows (the 1024-frame forward's tiled layers took 3.3 instead of
 // 3.6 ms; 32-row tiles were slower again)
 constexpr int kTileH = 16, kTileW = 32;
-constexpr int kStageG = 4;   // staging loads in flight per thread
 
 template <int C, int CO, bool UP, bool DIL = false, bool ACC = false, int TH = kTileH>
 __global__ __launch_bounds__(32 * TH) void k_conv3x3_tile(ConvGeom g, ConvArgs a)
@@ -661,9 +660,14 @@ __global__ __launch_bounds__(32 * TH) void k_conv3x3_tile(ConvGeom g, ConvArgs a
     constexpr int KP = NKS * 32 + 8;                 // LDS weight row (bf16), zero beyond K
     constexpr int FN = CO / 16;
     constexpr int CO8 = CO / 8;
-    constexpr int XS = HP * WP * PS, OS = TH * kTileW * CO;
+    // staged by LDS DMA in 16-byte slots, whole waves at a time: the regions are rounded up to
+    // 64 slots (512 bf16), the slots past the data (and the pad slot of each pixel and weight
+    // row) filled from the zero buffer
+    constexpr int SPP = PS / 8, KPS = KP / 8;        // slots per staged pixel, per weight row
+    constexpr int NXS = HP * WP * SPP, NWS = CO * KPS;
+    constexpr int XS = (NXS + 63) / 64 * 512, OS = TH * kTileW * CO;
     __shared__ __attribute__((aligned(16))) uint16_t sX[XS > OS ? XS : OS];
-    __shared__ __attribute__((aligned(16))) uint16_t sW[CO * KP];
+    __shared__ __attribute__((aligned(16))) uint16_t sW[(NWS + 63) / 64 * 512];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -685,72 +689,57 @@ __global__ __launch_bounds__(32 * TH) void k_conv3x3_tile(ConvGeom g, ConvArgs a
 #pragma unroll
     for (int j = 0; j < FN; ++j) bias_r[j] = a.bias ? a.bias[16 * j + lr] : 0.f;
 
-    // staging: halo item i (pixel i / C8, channel group i % C8) and weight item i (row i / (4 NKS),
-    // k group i % (4 NKS)); a thread takes items tid + NT u, loading kStageG of them before it
-    // stores them to LDS, so that many global round trips overlap instead of one per item
-    auto load_x = [&](int i) __attribute__((always_inline)) -> u32x4 {
-        const int c8 = i % C8, pix = i / C8;
+    // staging: every slot of the halo tile and of the weights is one DMA load, all in flight
+    // together (no staging registers); halo slot j is pixel j / SPP, channel group j % SPP (the
+    // pad group where that is C8), weight slot j is row j / KPS, K group j % KPS
+    const uint64_t zp = reinterpret_cast<uint64_t>(g_zero_buf);
+    const uint32_t zhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(zp >> 32));
+    const uint32_t zlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)zp);
+    const uint16_t* zsrc = reinterpret_cast<const uint16_t*>(((uint64_t)zhi << 32) | zlo);
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    // (each source is one select between the operand and the zero buffer, computed without early
+    // returns: with divergent returns the compiler reused the zero pointer's register on the
+    // padding lanes' path and those lanes loaded from a garbage address)
+    auto x_src = [&](int j) __attribute__((always_inline)) -> const uint16_t* {
+        const int pix = j / SPP, c8 = j - pix * SPP;
         const int hy = pix / WP, wx = pix - hy * WP;
-        u32x4 v = zero;
+        bool ok = j < NXS && c8 < C8;
+        int hi, wi;
         if constexpr (UP) {   // stored pixels (ho0 / 2 - 1 + hy, wo0 / 2 - 1 + wx), zero outside
-            const int hi = ho0 / 2 - 1 + hy, wi = wo0 / 2 - 1 + wx;
-            if (hi >= 0 && wi >= 0 && hi < g.H && wi < g.W)
-                v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + hi) * g.W + wi) * C + c8 * 8);
+            hi = ho0 / 2 - 1 + hy;
+            wi = wo0 / 2 - 1 + wx;
+            ok = ok && (unsigned)hi < (unsigned)g.H && (unsigned)wi < (unsigned)g.W;
         } else if constexpr (DIL) {
-            const int hi = ho0 - 1 + hy, wi = wo0 - 1 + wx;
-            if (hi >= 0 && wi >= 0 && !(hi & 1) && !(wi & 1) && (hi >> 1) < g.H && (wi >> 1) < g.W)
-                v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + (hi >> 1)) * g.W + (wi >> 1)) * C + c8 * 8);
+            const int h2 = ho0 - 1 + hy, w2 = wo0 - 1 + wx;
+            ok = ok && h2 >= 0 && w2 >= 0 && !(h2 & 1) && !(w2 & 1) && (h2 >> 1) < g.H && (w2 >> 1) < g.W;
+            hi = h2 >> 1;
+            wi = w2 >> 1;
         } else {
-            int hi = ho0 - 1 + hy, wi = wo0 - 1 + wx;
-            if (hi >= 0 && wi >= 0 && hi < Hin && wi < Win) {
-                if (g.up) {
-                    hi >>= 1;
-                    wi >>= 1;
-                }
-                v = *reinterpret_cast<const u32x4*>(a.a + ((n * g.H + hi) * g.W + wi) * C + c8 * 8);
-            }
+            const int h2 = ho0 - 1 + hy, w2 = wo0 - 1 + wx;
+            ok = ok && (unsigned)h2 < (unsigned)Hin && (unsigned)w2 < (unsigned)Win;
+            hi = h2 >> g.up;
+            wi = w2 >> g.up;
         }
-        return v;
+        const int64_t off = ((n * g.H + hi) * g.W + wi) * C + c8 * 8;
+        return ok ? a.a + off : zsrc;
     };
-    auto load_w = [&](int i) __attribute__((always_inline)) -> u32x4 {
-        const int co = i / (NKS * 4), k8 = i - co * (NKS * 4);
+    auto w_src = [&](int j) __attribute__((always_inline)) -> const uint16_t* {
+        const int co = j / KPS, k8 = j - co * KPS;
         // k8 = tap * C8 + channel group; mirrored: tap 8 - tap of the transposed copy
         const int ks = a.flip ? (8 - k8 / C8) * C8 + k8 % C8 : k8;
-        return k8 < K8 ? *reinterpret_cast<const u32x4*>(a.b + (int64_t)co * (9 * C) + ks * 8) : zero;
+        return (j < NWS && k8 < K8) ? a.b + (int64_t)co * (9 * C) + ks * 8 : zsrc;
     };
-    constexpr int NX = HP * WP * C8, NW = CO * NKS * 4;
-    constexpr int UX = (NX + NT - 1) / NT, UW = (NW + NT - 1) / NT;
 #pragma unroll
-    for (int u0 = 0; u0 < UX; u0 += kStageG) {
-        u32x4 v[kStageG];
-#pragma unroll
-        for (int k = 0; k < kStageG; ++k) {
-            const int i = tid + NT * (u0 + k);
-            v[k] = (u0 + k < UX && i < NX) ? load_x(i) : zero;
-        }
-#pragma unroll
-        for (int k = 0; k < kStageG; ++k) {
-            const int i = tid + NT * (u0 + k);
-            if (u0 + k < UX && i < NX) *reinterpret_cast<u32x4*>(&sX[(i / C8) * PS + (i % C8) * 8]) = v[k];
-        }
+    for (int u = 0; u < (NWS + NT - 1) / NT; ++u) {
+        const int base = wv * 64 + NT * u;   // first slot of this wave's load
+        if (base < NWS) dma16(w_src(base + lane), &sW[base * 8]);
     }
 #pragma unroll
-    for (int u0 = 0; u0 < UW; u0 += kStageG) {
-        u32x4 v[kStageG];
-#pragma unroll
-        for (int k = 0; k < kStageG; ++k) {
-            const int i = tid + NT * (u0 + k);
-            v[k] = (u0 + k < UW && i < NW) ? load_w(i) : zero;
-        }
-#pragma unroll
-        for (int k = 0; k < kStageG; ++k) {
-            const int i = tid + NT * (u0 + k);
-            if (u0 + k < UW && i < NW) {
-                const int co = i / (NKS * 4), k8 = i - co * (NKS * 4);
-                *reinterpret_cast<u32x4*>(&sW[co * KP + k8 * 8]) = v[k];
-            }
-        }
+    for (int u = 0; u < (NXS + NT - 1) / NT; ++u) {
+        const int base = wv * 64 + NT * u;
+        if (base < NXS) dma16(x_src(base + lane), &sX[base * 8]);
     }
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
 
     f32x4 acc[4][FN];
