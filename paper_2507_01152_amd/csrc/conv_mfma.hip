@@ -442,7 +442,10 @@ __global__ __launch_bounds__(kThreads) void k_conv_gemm(ConvGeom g0, ConvArgs a)
         // a wave waits for its own DMA of stage kt (vmcnt counts in issue order: at most the next
         // stage's loads may remain), then the barrier makes every wave's chunks visible and
         // retires the reads of the stage the next issue overwrites.  LW is the fewest DMA loads
-        // any wave issues per stage; a wave with more waits for part of the next stage too.
+        // any wave issues per stage (wave 3's, whose first chunk is 192); a wave with more waits
+        // for part of the next stage too.  The barrier is the bare s_barrier: __syncthreads()
+        // would add a wait for every outstanding load (vmcnt(0)) and drain the ring; the empty
+        // asm statements keep the compiler from moving LDS accesses across it.
         constexpr int LW = ((CA - 192 + kThreads - 1) / kThreads) + (CB > 192 ? (CB - 192 + kThreads - 1) / kThreads : 0);
         static_assert(LW >= 1 && LW < 16, "per-wave DMA loads per stage");
         const int rd = frow * kBK + (((lane >> 4) ^ swz(frow)) * 8);
