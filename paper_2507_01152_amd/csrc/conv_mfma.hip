@@ -850,6 +850,12 @@ __global__ __launch_bounds__(32 * TH) void k_conv3x3_tile(ConvGeom g, ConvArgs a
     // 16-byte output chunks: thread tid takes chunks tid + NT u; the skip tensor's chunks are all
     // loaded before the first store
     static_assert(TH * kTileW == NT, "one output pixel per thread and channel group");
+    // one extra chunk per pixel (the depth integral into S0): pixel tid's, loaded with the skip
+    // chunks before the first store
+    const bool extra1 = a.extra && a.out2_bf16 && a.extra_c == 8;
+    const int64_t op_t = (n * g.Ho + ho0 + tid / kTileW) * g.Wo + wo0 + tid % kTileW;
+    const bool in_t = ho0 + tid / kTileW < g.Ho && wo0 + tid % kTileW < g.Wo;
+    const u32x4 ev = (extra1 && in_t) ? *reinterpret_cast<const u32x4*>(a.extra + op_t * 8) : zero;
     u32x4 kv[CO8];
 #pragma unroll
     for (int u = 0; u < CO8; ++u) {
@@ -881,7 +887,9 @@ __global__ __launch_bounds__(32 * TH) void k_conv3x3_tile(ConvGeom g, ConvArgs a
             *reinterpret_cast<u32x4*>(a.out2_bf16 + op * ld2 + c8 * 8) = o;
         }
     }
-    if (a.extra && a.out2_bf16) {
+    if (extra1) {
+        if (in_t) *reinterpret_cast<u32x4*>(a.out2_bf16 + op_t * ld2 + CO) = ev;
+    } else if (a.extra && a.out2_bf16) {
         const int E8 = a.extra_c / 8;
         for (int i = tid; i < TH * kTileW * E8; i += NT) {
             const int e8 = i % E8, pix = i / E8;
