@@ -40,6 +40,8 @@ CONV_CASES = [
     (1, 4, 3, 128, 64, 3, 1, 1, 1),
     (3, 11, 5, 24, 40, 1, 1, 0, 0),      # 1x1, channel counts not powers of two
     (2, 9, 70, 16, 8, 1, 1, 0, 0),       # 1x1 to 8 channels (the depth map), K below one MFMA step
+    (2, 7, 9, 64, 32, 1, 1, 0, 0),       # 1x1, two K steps of one tap's 32 channels each
+    (2, 7, 9, 48, 24, 1, 1, 0, 0),       # 1x1, two K steps, the second half past K
     (1, 12, 10, 24, 16, 3, 1, 1, 0),     # 24 input channels (the last decoder conv)
     # LDS-tiled direct 3x3 path (stride 1, pad 1, C <= 32, Co 16 or 32): 16 x 32 tiles
     (2, 19, 70, 16, 16, 3, 1, 1, 0),     # ragged tiles in both directions
