@@ -786,6 +786,16 @@ __global__ __launch_bounds__(32 * TH) void k_conv3x3_tile(ConvGeom g, ConvArgs a
     for (int gi = 0; gi < 4; ++gi)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[gi][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // operand of row group gi (output rows rr = 2 wave + gi / 2, columns cc = 16 (gi % 2) + lr) at
+    // tap (r, s): staged pixel (sy, sx) = (rr + r, cc + s), or with UP ((rr + r + 1) / 2,
+    // (cc + s + 1) / 2) = (wave + (gi / 2 + r + 1) / 2, 8 (gi % 2) + lr / 2 + (lr % 2 + s + 1) / 2).
+    // Either way the LDS offset is a per-lane part fixed over the K loop plus a per-step part that
+    // depends on gi only through gi / 2.
+    int gofs[4];
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi)
+        gofs[gi] = UP ? (wave * WP + (gi & 1) * 8 + (lr >> 1)) * PS
+                      : ((2 * wave + (gi >> 1)) * WP + (gi & 1) * 16 + lr) * PS;
 #pragma unroll 3
     for (int ks = 0; ks < NKS; ++ks) {
         const int k8 = ks * 4 + lk;
@@ -796,14 +806,20 @@ __global__ __launch_bounds__(32 * TH) void k_conv3x3_tile(ConvGeom g, ConvArgs a
             r = tap / 3;
             s = tap - r * 3;
         }
+        int tofs[2];
+        if constexpr (UP) {
+            const int sxo = ((lr & 1) + s + 1) >> 1;
+            tofs[0] = (((r + 1) >> 1) * WP + sxo) * PS + c0;
+            tofs[1] = (((r + 2) >> 1) * WP + sxo) * PS + c0;
+        } else {
+            tofs[0] = tofs[1] = (r * WP + s) * PS + c0;
+        }
         bf16x8 fb[FN];
 #pragma unroll
         for (int j = 0; j < FN; ++j) fb[j] = *reinterpret_cast<const bf16x8*>(&sW[(16 * j + lr) * KP + k8 * 8]);
 #pragma unroll
         for (int gi = 0; gi < 4; ++gi) {
-            const int rr = 2 * wave + (gi >> 1), cc = (gi & 1) * 16 + lr;
-            const int sy = UP ? (rr + r + 1) >> 1 : rr + r, sx = UP ? (cc + s + 1) >> 1 : cc + s;
-            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sX[(sy * WP + sx) * PS + c0]);
+            const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sX[gofs[gi] + tofs[gi >> 1]]);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
                 acc[gi][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[j], acc[gi][j], 0, 0, 0);
